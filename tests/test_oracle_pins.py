@@ -1,0 +1,365 @@
+"""Pins for the FP64 oracle: exact arithmetic, an independent library, closed
+forms, decision special cases, order invariance, statistics invariants and the
+paper's printed policy vectors.  CPU only."""
+import itertools
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import hydro_synth as hs
+import oracle
+from oracle import hydro_oracle as ho
+from tests import bruteforce as bf
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+def tiny_mlp(seed, d, h):
+    return hs.make_model(hs.ModelDesc(arch="mlp", seed=seed, d_in=d, hidden=h))
+
+
+def tiny_cnn(seed, hw, widths):
+    return hs.make_model(hs.ModelDesc(arch="cnn", seed=seed, in_hw=hw, widths=tuple(widths)))
+
+
+def bf16_frames(rng, n, hw):
+    return hs.f64_to_bf16_bits(rng.random((n, hw, hw, 3)))
+
+
+def exact_frame(fr64):
+    return [[[Fraction(float(fr64[y, x, c])) for c in range(3)] for x in range(fr64.shape[1])]
+            for y in range(fr64.shape[0])]
+
+
+# ---------------------------------------------------------------- O1-O4: exact brute force
+def test_mlp_matches_exact_rationals():
+    rng = np.random.default_rng(11)
+    m = tiny_mlp(7, 48, 8)
+    fr = bf16_frames(rng, 64, 4)
+    z = ho.model_logits(m, fr, "bf16")
+    x64 = ho.frames_to_f64(fr, "bf16")
+    t = m.tensors
+    for i in range(64):
+        ze = bf.mlp_exact(exact_frame(x64[i]), t["W1"], t["b1"], t["W2"], t["b2"])
+        for c in range(10):
+            assert abs(float(Fraction(z[i, c]) - ze[c])) <= 1e-12 * (1 + abs(float(ze[c])))
+
+
+def test_cnn_matches_exact_rationals():
+    rng = np.random.default_rng(12)
+    m = tiny_cnn(8, 8, [4, 8])
+    fr = bf16_frames(rng, 64, 8)
+    z = ho.model_logits(m, fr, "bf16")
+    x64 = ho.frames_to_f64(fr, "bf16")
+    t = m.tensors
+    for i in range(64):
+        ze = bf.cnn_exact(exact_frame(x64[i]), t["convs"], t["Wfc"], t["bfc"])
+        for c in range(10):
+            assert abs(float(Fraction(z[i, c]) - ze[c])) <= 1e-12 * (1 + abs(float(ze[c])))
+
+
+def test_u8_frames_exact_rationals():
+    """uint8 v means v/255: compare with the exact rational v/255."""
+    rng = np.random.default_rng(13)
+    m = tiny_cnn(9, 8, [4, 8])
+    fr = rng.integers(0, 256, size=(16, 8, 8, 3), dtype=np.uint8)
+    z = ho.model_logits(m, fr, "u8")
+    t = m.tensors
+    for i in range(16):
+        fe = [[[Fraction(int(fr[i, y, x, c]), 255) for c in range(3)] for x in range(8)] for y in range(8)]
+        ze = bf.cnn_exact(fe, t["convs"], t["Wfc"], t["bfc"])
+        for c in range(10):
+            assert abs(float(Fraction(z[i, c]) - ze[c])) <= 1e-12 * (1 + abs(float(ze[c])))
+
+
+def test_decisions_match_exact_margins():
+    """Margins and strict decisions agree with exact rationals (thresholds off-tie)."""
+    rng = np.random.default_rng(14)
+    m = tiny_cnn(10, 8, [4, 8])
+    fr = bf16_frames(rng, 48, 8)
+    z = ho.model_logits(m, fr, "bf16")
+    x64 = ho.frames_to_f64(fr, "bf16")
+    for mask in (0b1, 0b1000000001, 0b0011110000):
+        d = ho.predicate_margin(z, mask)
+        theta = float(np.float32(np.median(d)))
+        got = ho.decide(d, theta)
+        for i in range(48):
+            ze = bf.cnn_exact(exact_frame(x64[i]), m.tensors["convs"], m.tensors["Wfc"], m.tensors["bfc"])
+            de, kind = bf.margin_exact(ze, mask)
+            assert kind == "finite"
+            assert abs(float(de) - d[i]) <= 1e-12
+            if abs(float(de - Fraction(theta))) > 1e-9:
+                assert got[i] == (de > Fraction(theta))
+
+
+# ---------------------------------------------------------------- O3/O4: independent library
+def test_mlp_vs_torch_linear_on_small_workload():
+    cfg = hs.workload(1)
+    fr = hs.make_frames(cfg, 0, 512)
+    for desc in cfg.models:
+        m = hs.make_model(desc)
+        z = ho.model_logits(m, fr, cfg.dtype)
+        x = (torch.from_numpy(fr.astype(np.float64)).reshape(512, -1) - 0.5) * 4
+        t = {k: torch.from_numpy(v.astype(np.float64)) for k, v in m.tensors.items()}
+        h = torch.relu(torch.nn.functional.linear(x, t["W1"].T, t["b1"]))
+        zt = torch.nn.functional.linear(h, t["W2"].T, t["b2"]).numpy()
+        assert np.abs(z - zt).max() <= 1e-12 * max(1.0, np.abs(zt).max())
+
+
+def _torch_cnn(m, x64):
+    x = torch.from_numpy(x64).permute(0, 3, 1, 2)
+    x = (x - 0.5) * 4
+    for w, b in m.tensors["convs"]:
+        x = torch.relu(torch.nn.functional.conv2d(x, torch.from_numpy(w.astype(np.float64)),
+                                                  torch.from_numpy(b.astype(np.float64)),
+                                                  stride=2, padding=1))
+    g = x.mean(dim=(2, 3))
+    return (g @ torch.from_numpy(m.tensors["Wfc"].astype(np.float64))
+            + torch.from_numpy(m.tensors["bfc"].astype(np.float64))).numpy()
+
+
+@pytest.mark.parametrize("wl,n", [(2, 64), (5, 8)])
+def test_cnn_vs_torch_conv2d_on_workload_prefix(wl, n):
+    cfg = hs.workload(wl)
+    fr = hs.make_frames(cfg, 0, n)
+    x64 = ho.frames_to_f64(fr, cfg.dtype)
+    for desc in cfg.models[:2]:
+        m = hs.make_model(desc)
+        z = ho.model_logits(m, fr, cfg.dtype)
+        zt = _torch_cnn(m, x64)
+        assert np.abs(z - zt).max() <= 1e-12 * max(1.0, np.abs(zt).max())
+
+
+# ---------------------------------------------------------------- closed forms
+def test_zero_weights_give_bias():
+    m = tiny_cnn(3, 8, [4, 8])
+    for w, b in m.tensors["convs"]:
+        w[...] = 0
+    m.tensors["Wfc"][...] = 0
+    fr = bf16_frames(np.random.default_rng(1), 5, 8)
+    z = ho.model_logits(m, fr, "bf16")
+    assert np.array_equal(z, np.tile(m.tensors["bfc"].astype(np.float64), (5, 1)))
+    mm = tiny_mlp(4, 48, 8)
+    mm.tensors["W1"][...] = 0
+    mm.tensors["W2"][...] = 0
+    z = ho.model_logits(mm, bf16_frames(np.random.default_rng(2), 3, 4), "bf16")
+    assert np.array_equal(z, np.tile(mm.tensors["b2"].astype(np.float64), (3, 1)))
+
+
+def test_delta_kernel_subsamples_even_pixels():
+    """Centre tap 1 on one channel, zero bias: output = normalised input at (2i, 2j), clipped at 0."""
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((2, 8, 8, 3))
+    w = np.zeros((3, 3, 3, 3))
+    for c in range(3):
+        w[c, c, 1, 1] = 1.0
+    y = ho.conv3x3_s2_relu(a, w, np.zeros(3))
+    assert np.array_equal(y, np.maximum(a[:, ::2, ::2, :], 0))
+
+
+def test_corner_taps_read_the_zero_border():
+    """Tap (0,0) reads input (2i-1, 2j-1): zero for i=0 or j=0, else the odd pixel."""
+    a = np.arange(1, 2 * 6 * 6 + 1, dtype=np.float64).reshape(1, 6, 6, 2)
+    w = np.zeros((2, 2, 3, 3))
+    w[0, 0, 0, 0] = 1.0
+    w[1, 1, 2, 2] = 1.0           # tap (2,2) reads (2i+1, 2j+1)
+    y = ho.conv3x3_s2_relu(a, w, np.zeros(2))
+    exp0 = np.zeros((3, 3))
+    exp0[1:, 1:] = a[0, 1:4:2, 1:4:2, 0]
+    assert np.array_equal(y[0, :, :, 0], exp0)
+    assert np.array_equal(y[0, :, :, 1], a[0, 1::2, 1::2, 1])
+
+
+def test_constant_image_constant_pool():
+    """A frame of raw value 0.5 normalises to exactly zero (so does the padding):
+    every conv output is ReLU(bias), the pool is ReLU(bias), z = ReLU(b) Wfc + bfc."""
+    m = tiny_cnn(5, 8, [4])
+    fr = np.full((1, 8, 8, 3), 0.5, dtype=np.float32)           # normalises to exactly 0
+    z = ho.model_logits(m, fr, "f32")
+    b0 = np.maximum(m.tensors["convs"][0][1].astype(np.float64), 0)
+    exp = b0 @ m.tensors["Wfc"].astype(np.float64) + m.tensors["bfc"]
+    assert np.allclose(z[0], exp, rtol=0, atol=1e-15)
+
+
+def test_block_selector_mlp_gives_block_sums():
+    """W1 selects pixel blocks, W2 = identity on the first 8 hidden units."""
+    d, h = 48, 10
+    m = tiny_mlp(6, d, h)
+    W1 = np.zeros((d, h), dtype=np.float32)
+    for j in range(h):
+        W1[(j * 4):(j * 4 + 4), j] = 1.0 if j < 10 else 0.0
+    m.tensors["W1"][...] = W1
+    m.tensors["b1"][...] = 100.0                    # keeps ReLU inactive
+    m.tensors["W2"][...] = np.eye(h, 10, dtype=np.float32)
+    m.tensors["b2"][...] = -100.0
+    fr = np.random.default_rng(4).random((3, 4, 4, 3)).astype(np.float32)
+    z = ho.model_logits(m, fr, "f32")
+    xn = (fr.astype(np.float64).reshape(3, -1) - 0.5) * 4
+    exp = np.stack([xn[:, j * 4:j * 4 + 4].sum(axis=1) for j in range(10)], axis=1)
+    assert np.allclose(z, exp, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- O5 decision special cases
+def test_decision_special_cases():
+    z = np.random.default_rng(5).standard_normal((100, 10))
+    d = ho.predicate_margin(z, 0b101)
+    assert not ho.decide(d, np.inf).any()
+    assert ho.decide(d, -np.inf).all()
+    assert ho.decide(ho.predicate_margin(z, 0x3FF), 1e30).all()       # S = all classes
+    assert not ho.decide(ho.predicate_margin(z, 0), -1e30).any()      # S = empty
+    for mask in (0b1, 0b110, 0b1111100000):
+        inside = np.array([(mask >> c) & 1 for c in range(10)], dtype=bool)
+        assert np.array_equal(ho.decide(ho.predicate_margin(z, mask), 0.0), inside[np.argmax(z, axis=1)])
+
+
+def test_tie_is_rejected():
+    z = np.zeros((1, 10))
+    z[0, 3] = z[0, 4] = 1.0
+    assert not ho.decide(ho.predicate_margin(z, 1 << 3), 0.0)[0]
+
+
+# ---------------------------------------------------------------- O6/O7 order invariance, stats
+@pytest.fixture(scope="module")
+def small_truth():
+    cfg = hs.workload(1)
+    fr = hs.make_frames(cfg)
+    pt = hs.load_predicates(cfg)
+    models = [hs.make_model(d) for d in cfg.models]
+    P, D = ho.truth_table(fr, cfg.dtype, models, pt.class_masks, pt.thresholds, cfg.n // cfg.n_seg)
+    return cfg, P, D, pt
+
+
+def test_every_order_gives_the_same_result(small_truth):
+    cfg, P, D, pt = small_truth
+    R = ho.result_ids(P)
+    for order in itertools.permutations(range(P.shape[1])):
+        r, ev, ps = ho.short_circuit_eval(P, order)
+        assert np.array_equal(r, R)
+
+
+def test_every_order_random_truth_tables():
+    rng = np.random.default_rng(6)
+    for k in range(1, 7):
+        P = rng.random((500, k)) < rng.uniform(0.2, 0.9, size=k)
+        R = ho.result_ids(P)
+        brute = np.array([t for t in range(500) if all(P[t, j] for j in range(k))], dtype=np.int64)
+        assert np.array_equal(R, brute)
+        for order in itertools.permutations(range(k)):
+            r, ev, ps = ho.short_circuit_eval(P, order)
+            assert np.array_equal(r, R)
+            assert ho.stats_invariants(ev, ps, 500, R.size) == []
+            assert ev[order[0]] == 500
+            for a, b in zip(order[:-1], order[1:]):
+                assert ev[b] == ps[a]
+
+
+def test_small_workload_selectivities_near_targets(small_truth):
+    cfg, P, D, pt = small_truth
+    sel = P.mean(axis=0)
+    assert np.all(np.abs(sel - np.array(cfg.targets[0])) < 0.06), sel
+
+
+def test_small_workload_no_near_ties(small_truth):
+    cfg, P, D, pt = small_truth
+    assert ho.near_tie_gap(D, pt.thresholds, cfg.n // cfg.n_seg) > 1e-9
+
+
+def test_replay_route_accepts_valid_and_flags_invalid():
+    P = np.array([[1, 1, 0], [1, 1, 1], [0, 1, 1]], dtype=bool)
+    ok, ev, ps, out, msg = ho.replay_route(P, [[0, 2], [2, 1, 0], [0]])
+    assert ok and list(out) == [1]
+    assert list(ev) == [3, 1, 2] and list(ps) == [2, 1, 1]
+    assert not ho.replay_route(P, [[2, 0], [0, 1, 2], [0]])[0]          # continues after a fail
+    assert not ho.replay_route(P, [[0, 1, 2], [0, 1], [0]])[0]          # stops after a pass
+    assert not ho.replay_route(P, [[0, 0], [0, 1, 2], [0]])[0]          # revisits
+
+
+def test_stats_invariants_catch_bad_counts():
+    assert ho.stats_invariants([10, 6], [6, 3], 10, 3) == []
+    assert ho.stats_invariants([10, 6], [6, 4], 10, 3) != []
+
+
+# ---------------------------------------------------------------- paper policy vectors
+@pytest.mark.parametrize("case", ["uc1_profile", "table1_case1", "table1_case2", "worked_example"])
+def test_policy_first_choice_matches_paper(case):
+    with open(os.path.join(GOLD, "paper_policy_vectors.json")) as f:
+        v = json.load(f)[case]
+    cost = v.get("cost_ms", v.get("cost"))
+    sel = v["selectivity"]
+    for pol, name in ((ho.POLICY_COST, "cost"), (ho.POLICY_SCORE, "score"), (ho.POLICY_SEL, "selectivity")):
+        assert ho.policy_order(pol, cost, sel)[0] == v["first"][name], (case, name)
+    if "score" in v:
+        assert np.allclose(ho.policy_keys(ho.POLICY_SCORE, cost, sel), v["score"], rtol=1e-12)
+
+
+def test_uc1_scores_match_printed_statistics():
+    k = ho.policy_keys(ho.POLICY_SCORE, [35.11, 1.98], [0.254, 0.633])
+    assert round(k[0], 2) == 47.06 and round(k[1], 2) == 5.40
+
+
+def test_score_key_edge_cases():
+    k = ho.policy_keys(ho.POLICY_SCORE, [1.0, 1.0, 5.0], [1.0, 0.0, 0.5])
+    assert k[0] == np.inf and k[1] == 1.0 and k[2] == 10.0
+    assert ho.policy_order(ho.POLICY_COST, [2.0, 2.0, 1.0], [0, 0, 0]) == [2, 0, 1]   # ties -> lower index
+    assert np.allclose(ho.smoothed_selectivity([0, 5], [0, 8]), [0.5, 0.6])
+
+
+# ---------------------------------------------------------------- planted mistakes are caught
+def _mutant_results(monkeypatch, mutate):
+    rng = np.random.default_rng(21)
+    m = tiny_cnn(22, 8, [4, 8])
+    fr = bf16_frames(rng, 4, 8)
+    x64 = ho.frames_to_f64(fr, "bf16")
+    exact = [bf.cnn_exact(exact_frame(x64[i]), m.tensors["convs"], m.tensors["Wfc"], m.tensors["bfc"])
+             for i in range(4)]
+    mutate(monkeypatch)
+    z = ho.model_logits(m, fr, "bf16")
+    return max(abs(float(Fraction(z[i, c]) - exact[i][c])) for i in range(4) for c in range(10))
+
+
+@pytest.mark.parametrize("name", ["no_bias", "pad_offset", "kernel_transposed", "no_normalise", "sum_pool"])
+def test_brute_force_catches_planted_oracle_mistakes(monkeypatch, name):
+    orig_conv = ho.conv3x3_s2_relu
+
+    def mutate(mp):
+        if name == "no_bias":
+            mp.setattr(ho, "conv3x3_s2_relu", lambda a, w, b: orig_conv(a, w, 0 * b))
+        elif name == "pad_offset":
+            def conv(a, w, b):
+                a2 = np.zeros_like(a)
+                a2[:, :-1, :-1] = a[:, 1:, 1:]
+                return orig_conv(a2, w, b)
+            mp.setattr(ho, "conv3x3_s2_relu", conv)
+        elif name == "kernel_transposed":
+            mp.setattr(ho, "conv3x3_s2_relu", lambda a, w, b: orig_conv(a, np.swapaxes(w, 2, 3), b))
+        elif name == "no_normalise":
+            mp.setattr(ho, "normalize", lambda x: x)
+        elif name == "sum_pool":
+            def cnn(t, xn):
+                a = xn
+                for w, b in t["convs"]:
+                    a = ho.conv3x3_s2_relu(a, w, b)
+                return a.sum(axis=(1, 2)) @ t["Wfc"] + t["bfc"]
+            mp.setattr(ho, "cnn_logits", cnn)
+
+    assert _mutant_results(monkeypatch, mutate) > 1e-6
+
+
+# ---------------------------------------------------------------- input generator sanity
+def test_bf16_rounding_is_nearest_even():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, 0.0], dtype=np.float64)
+    bits = hs.f64_to_bf16_bits(vals)
+    back = ho.frames_to_f64(bits, "bf16")
+    assert list(back) == [1.0, 1.0, 1.0 + 2 ** -6, 1.0, 0.0]
+
+
+def test_frame_chunks_regenerate_independently():
+    cfg = hs.workload(2)
+    a = hs.make_frames(cfg, 1000, 100)
+    b = hs.make_frames(cfg, 0, 1100)[1000:]
+    assert np.array_equal(a, b)
