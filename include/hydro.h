@@ -1,0 +1,225 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) engine for conjunctive ML-UDF queries.
+ *
+ * The engine evaluates  SELECT id FROM frames WHERE P_0(frame) AND ... AND P_{K-1}(frame)
+ * where every P_k is a classifier (an MLP or a small CNN) followed by a class-subset
+ * threshold test, and routes tuples through the predicates adaptively, batch by batch,
+ * in the order that running cost and selectivity statistics favour.
+ *
+ * Paper: Hydro, "Adaptive Query Processing of ML Queries" (arXiv 2403.14902).
+ *   - The conjunction and its answer: section 1 (motivating query) and section 4.1 (UC1 query).
+ *   - Eddy routing, visited-predicate metadata, completion: section 3.2 ("Data Flow and
+ *     Routing") and section 3.3 ("Metadata for Data Routing").
+ *   - Eager dropping of failing tuples: section 3.3 ("Eager Materialization").
+ *   - Routing batches: section 3.3 ("Batch Evaluation").
+ *   - Policies: section 4.1 ("Cost-Driven Routing Policy": score = cost / (1 - selectivity),
+ *     lowest first; "System Variants": no reordering, cost-, score- and selectivity-driven;
+ *     selectivity from counts of filtered rows).
+ *   - Warmup: section 4.1 ("Warmup Phase").
+ *   - Content-based routing (the idea behind the learned router): section 2.2.
+ *
+ * Conventions
+ *   - Every function returns an int status (hydro_status); nothing is thrown across the ABI.
+ *     On error, output pointers are set to NULL / 0 and caller-owned outputs are left untouched;
+ *     hydro_last_error() returns a thread-local message describing the last failure.
+ *   - Pointers are borrowed for the duration of a call unless stated otherwise.
+ *   - Device pointers are HIP device addresses on the current device; "host" pointers are
+ *     ordinary process memory (pinned memory is copied asynchronously, pageable memory is
+ *     staged through a pinned buffer).
+ *   - Frames are NHWC with 3 channels, row-major, tightly packed.
+ *   - Result ids are unique and sorted ascending (the query's answer is a set).
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRO_MAX_PREDICATES 8
+#define HYDRO_MAX_LAYERS 4
+#define HYDRO_N_CLASSES 10
+
+typedef enum {
+  HYDRO_OK = 0,
+  HYDRO_EINVAL = -1,        /* bad argument (NULL pointer, size, shape mismatch, bad order)      */
+  HYDRO_ENOMEM = -2,        /* device or pinned-host allocation failed                           */
+  HYDRO_EDEVICE = -3,       /* a HIP call failed; the message carries HIP's error string         */
+  HYDRO_EUNSUPPORTED = -4,  /* valid but not supported (K > 8, channels != 3, model shape, ...)  */
+  HYDRO_ECAPACITY = -5,     /* more tuples than the session was created for                      */
+  HYDRO_ESTATE = -6         /* call out of order (push after finish, finish without push, ...)   */
+} hydro_status;
+
+typedef enum { HYDRO_DTYPE_F32 = 0, HYDRO_DTYPE_BF16 = 1, HYDRO_DTYPE_U8 = 2 } hydro_dtype;
+typedef enum { HYDRO_MEM_DEVICE = 0, HYDRO_MEM_HOST = 1 } hydro_mem;
+
+/* A block of tuples.  Tuple i of the block has global id id_base + i.
+ * data: n * h * w * 3 elements of dtype (F32: float; BF16: bfloat16 bit patterns; U8: uint8,
+ * whose value is v / 255).  Ownership stays with the caller.  For where == HOST the caller keeps
+ * the memory valid until hydro_session_finish returns. */
+typedef struct {
+  const void* data;
+  int32_t dtype;
+  int32_t where;
+  int64_t n;
+  int32_t h, w;
+  int64_t id_base;
+} hydro_frames;
+
+typedef enum { HYDRO_ARCH_MLP = 0, HYDRO_ARCH_CNN = 1 } hydro_arch;
+
+/* One predicate: a classifier with 10 logits z and a class subset S (class_mask bit c <=> c in S).
+ * Its margin is d = max_{c in S} z_c - max_{c not in S} z_c and it holds iff d > theta (strict),
+ * theta taken from the threshold table for the tuple's segment.  Every model first normalises
+ * its input: x' = (x - 0.5) * 4, with x in [0,1] (u8: x = v / 255).
+ *
+ * MLP (arch = MLP): x' flattened in NHWC order (d_in = in_h * in_w * 3);
+ *   h = ReLU(x' W1 + b1), z = h W2 + b2.  w1: [d_in][hidden], b1: [hidden], w2: [hidden][10],
+ *   b2: [10], all fp32, row-major.
+ * CNN (arch = CNN): n_layers conv3x3 layers, stride 2, zero padding 1 (in normalised space),
+ *   each followed by ReLU; then the mean over all final positions; then z = g Wfc + bfc.
+ *   conv_w[l]: [widths[l]][c_in][3][3] (c_in = 3 for l = 0, else widths[l-1]), conv_b[l]:
+ *   [widths[l]]; fc_w: [widths[n_layers-1]][10], fc_b: [10]; all fp32, row-major.
+ * Weights are copied (and re-packed per precision) when a session is created. */
+typedef struct {
+  int32_t arch;
+  int32_t in_h, in_w;
+  int32_t hidden;
+  const float *w1, *b1, *w2, *b2;
+  int32_t n_layers;
+  int32_t widths[HYDRO_MAX_LAYERS];
+  const float* conv_w[HYDRO_MAX_LAYERS];
+  const float* conv_b[HYDRO_MAX_LAYERS];
+  const float *fc_w, *fc_b;
+  uint32_t class_mask;
+} hydro_model;
+
+typedef enum {
+  HYDRO_ROUTE_FIXED = 0,    /* the written order in policy.order (no reordering)                 */
+  HYDRO_ROUTE_SEL = 1,      /* lowest estimated selectivity first                                */
+  HYDRO_ROUTE_SCORE = 2,    /* lowest cost / (1 - selectivity) first                             */
+  HYDRO_ROUTE_COST = 3,     /* lowest estimated cost first                                       */
+  HYDRO_ROUTE_LEARNED = 4   /* per-tuple keys from an online-trained router MLP, judged against
+                               SCORE and falling back to it                                       */
+} hydro_route;
+
+typedef enum { HYDRO_PREC_FP32 = 0, HYDRO_PREC_BF16 = 1 } hydro_precision;
+typedef enum { HYDRO_COST_MEASURED = 0, HYDRO_COST_STATIC = 1 } hydro_cost_source;
+
+/* Execution policy.  Fill with hydro_policy_default() and override fields. */
+typedef struct {
+  int32_t route;                         /* hydro_route                                          */
+  int32_t order[HYDRO_MAX_PREDICATES];   /* FIXED: a permutation of 0..K-1                       */
+  int32_t routing_batch;                 /* tuples per routing batch (default 64)                */
+  int32_t wave;                          /* tuples admitted per round (default 8192)             */
+  int32_t warmup_batches;                /* routing batches per predicate in the warmup round
+                                            (default 1; adaptive policies only)                  */
+  float ewma_alpha;                      /* weight of the newest round in the running
+                                            selectivity / cost estimates (default 0.5)           */
+  int32_t cost_source;                   /* MEASURED: device time per evaluated tuple;
+                                            STATIC: the model's FLOPs (deterministic routes)     */
+  int32_t precision;                     /* first-pass arithmetic; see tau                       */
+  float tau;                             /* BF16 first pass: |d - theta| < tau is re-scored in
+                                            FP32 (<= 0: default 0.05)                            */
+  float tau32;                           /* FP32 pass: |d - theta| < tau32 is re-scored in FP64
+                                            (<= 0: default 1e-4)                                 */
+  int32_t grouped;                       /* 1: one persistent launch per round and tier for all
+                                            predicates (default 1)                               */
+  int32_t use_graph;                     /* 1: replay the round sequence from a HIP graph        */
+  int32_t log_routes;                    /* 1: record every tuple's visit sequence (debug)       */
+  float explore;                         /* LEARNED: fraction of routing batches kept on SCORE
+                                            as the judge's control arm (default 0.05)            */
+  uint64_t seed;                         /* LEARNED: router init / exploration seed              */
+  void* stream;                          /* hipStream_t to run on; NULL: the session's own       */
+} hydro_policy;
+
+/* Per-predicate statistics of one query. */
+typedef struct {
+  uint64_t evaluated;          /* tuples this predicate was evaluated on                        */
+  uint64_t passed;             /* of those, tuples that passed                                  */
+  uint64_t rescored;           /* first-pass decisions deferred to the FP32 pass                */
+  uint64_t escalated;          /* FP32 decisions deferred to the FP64 pass                      */
+  double device_us;            /* summed device time of this predicate's first-pass tiles       */
+  double cost_us_per_tuple;    /* final running cost estimate                                   */
+  double selectivity;          /* passed / evaluated: conditional on the tuples it saw          */
+} hydro_pred_stats;
+
+/* Whole-query counters. */
+typedef struct {
+  uint64_t n_tuples, n_result;
+  uint32_t rounds, k;
+  uint64_t learned_routed, stats_routed;   /* LEARNED: tuples routed by each arm                 */
+  uint32_t learned_active;                 /* LEARNED: 1 if the judge kept the learned router    */
+  uint32_t train_steps;                    /* LEARNED: optimiser steps taken                      */
+  double elapsed_us;                       /* host time from first push to results on the host  */
+} hydro_query_info;
+
+typedef struct hydro_session hydro_session;
+
+/* Fill *p with defaults (SCORE, batch 64, wave 8192, BF16, grouped, no graph). */
+void hydro_policy_default(hydro_policy* p);
+
+/* One-shot query: create a session, push all frames, finish, destroy.
+ * thresholds: fp32 [n_seg][K]; tuple id t uses row min(t / seg_len, n_seg - 1).
+ * *out_ids: library-allocated int64[*out_n], sorted ascending; release with hydro_free.
+ * out_stats: caller-allocated [K] (may be NULL). */
+int hydro_query(const hydro_frames* frames, const hydro_model* models, int32_t k,
+                const float* thresholds, int32_t n_seg, int64_t seg_len,
+                const hydro_policy* policy, int64_t** out_ids, int64_t* out_n,
+                hydro_pred_stats* out_stats);
+
+/* Create a session: validates and uploads the K models (1 <= K <= 8), allocates device state
+ * for pushes of at most max_push tuples of frame_h x frame_w x 3 frames.  The policy is copied.
+ * Setup cost (weight upload and packing, buffer allocation) is paid here. */
+int hydro_session_create(const hydro_model* models, int32_t k, const hydro_policy* policy,
+                         int32_t frame_h, int32_t frame_w, int64_t max_push,
+                         hydro_session** out);
+
+/* Start a new query on an existing session: clears statistics, results and learned-router
+ * state; keeps weights and buffers. */
+int hydro_session_reset(hydro_session* s);
+
+/* Evaluate one block of tuples: admit them in waves, route, evaluate and forward survivors
+ * until every tuple of the block has completed or been dropped.  Enqueued on the policy's
+ * stream; returns before the work finishes.  thresholds / n_seg / seg_len as in hydro_query
+ * (copied).  Ids of different pushes must not overlap. */
+int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float* thresholds,
+                       int32_t n_seg, int64_t seg_len);
+
+/* Wait for all pushed work; return the sorted result ids (library-allocated, hydro_free) and
+ * the statistics (out_stats: caller-allocated [K], may be NULL). */
+int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n,
+                         hydro_pred_stats* out_stats);
+
+/* Whole-query counters of the last finished query. */
+int hydro_session_info(const hydro_session* s, hydro_query_info* out);
+
+/* Debug: the visit sequence of the last finished query's tuples (policy.log_routes = 1).
+ * out[i] describes tuple first_id + i: nibble j (bits 4j..4j+3) = 1 + the j-th predicate
+ * evaluated, 0 after the last one.  n must not exceed the tuples of the last push. */
+int hydro_session_routes(const hydro_session* s, int64_t first_id, int64_t n, uint32_t* out);
+
+/* Evaluate predicate `pred`'s model on every given tuple at one arithmetic tier
+ * (0 = the first-pass precision of the session, 1 = FP32, 2 = FP64) and return its logits as
+ * fp64 [n][10] in host memory.  Used for logit-error reports and kernel parity tests. */
+int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hydro_frames* frames,
+                         double* out_logits);
+
+int hydro_session_destroy(hydro_session* s);
+
+/* Release memory returned by the library. */
+void hydro_free(void* p);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* hydro_last_error(void);
+
+/* Library version string. */
+const char* hydro_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYDRO_H */

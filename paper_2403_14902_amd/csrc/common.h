@@ -1,0 +1,183 @@
+// Shared device/host definitions of the gfx950 engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hydro.h"
+
+namespace hydro {
+
+constexpr int kMaxK = HYDRO_MAX_PREDICATES;
+constexpr int kClasses = HYDRO_N_CLASSES;
+constexpr int kWave = 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A queue entry packs a tuple's local index (within its push) and the set of predicates
+// already evaluated on it (the per-tuple analogue of the visited table of section 3.3).
+constexpr int kIdxBits = 24;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1;
+__host__ __device__ inline uint32_t entry_idx(uint32_t e) { return e & kIdxMask; }
+__host__ __device__ inline uint32_t entry_mask(uint32_t e) { return e >> kIdxBits; }
+__host__ __device__ inline uint32_t make_entry(uint32_t idx, uint32_t mask) { return (mask << kIdxBits) | idx; }
+
+// Kernel variants of the fused CNN (widths (16m, 32m, 64m) on 64x64x3 frames).
+enum CnnVariant { CNN_W1 = 0, CNN_W2 = 1, CNN_W4 = 2, CNN_NONE = -1 };
+
+// Per-predicate device descriptor (lives in device memory, built at session creation).
+struct PredDesc {
+  int arch;            // HYDRO_ARCH_*
+  int variant;         // CnnVariant for CNNs
+  int d_in, hidden;    // MLP
+  int n_layers;
+  int widths[HYDRO_MAX_LAYERS];
+  int in_hw;
+  uint32_t class_mask;
+  float flops;
+  // first-pass / FP32 weights, normalisation folded into layer 1 (see the packing code)
+  const __bf16* w1_bf;     // MLP: [hidden][d_in] (n-major, k contiguous), bf16
+  const float* w1_f32;     // MLP: [hidden][d_in], fp32
+  const float* b1_fold;    // MLP: folded layer-1 bias, fp32
+  const float* w2;         // MLP: [hidden][10] fp32 (canonical)
+  const float* b2;         // MLP: [10]
+  // CNN packed weights: per layer, MFMA-fragment order (see cnn.hip)
+  const __bf16* cw_bf[HYDRO_MAX_LAYERS];
+  const float* cw_f32[HYDRO_MAX_LAYERS];
+  const float* cb_fold[HYDRO_MAX_LAYERS];   // bias (layer 1 folded), fp32
+  const float* fc_w;       // [c_last][10] canonical fp32
+  const float* fc_b;       // [10]
+  // canonical fp32 weights for the FP64 tier (unfolded)
+  const float* w1_canon;   // MLP [d_in][hidden]
+  const float* b1_canon;
+  const float* cw_canon[HYDRO_MAX_LAYERS];  // [co][ci][3][3]
+  const float* cb_canon[HYDRO_MAX_LAYERS];
+};
+
+// Device-resident routing state and statistics (one per session).
+struct DevState {
+  // per-round accumulators (cleared by the fold kernel at the start of every round)
+  unsigned long long r_eval[kMaxK], r_pass[kMaxK], r_ticks[kMaxK], r_rescored[kMaxK], r_esc[kMaxK];
+  // query totals
+  unsigned long long t_eval[kMaxK], t_pass[kMaxK], t_ticks[kMaxK], t_rescored[kMaxK], t_esc[kMaxK];
+  double sel_est[kMaxK], cost_est[kMaxK];
+  int seen[kMaxK];
+  int order[kMaxK];            // predicate ranking used by this round's router
+  int rounds;
+  // queue counters
+  int pend_count[2];
+  int qcount[kMaxK];           // first-pass queues
+  int bcount[kMaxK];           // FP32 re-score queues
+  int ecount[kMaxK];           // FP64 escalation queues
+  int n_result;
+  // learned router
+  unsigned long long learned_routed, stats_routed;
+  double arm_cost[2], arm_tuples[2];   // judge: realised UDF cost and tuples completed per arm
+  int learned_active;
+  int train_steps;
+  int ring_count;
+  int pad_;
+};
+
+// Where the frames of the current push live.
+struct FrameSrc {
+  const void* base;     // device pointer to tuple 0 of the push
+  int dtype;            // hydro_dtype
+  int hw;               // frame side
+  int64_t elems;        // elements per frame (hw*hw*3)
+};
+
+// Queues of one tier: entries[k * cap + i], i < counts[k].
+struct Queues {
+  uint32_t* entries;
+  int* counts;
+  int64_t cap;
+};
+
+// Where deciding kernels send their decisions.
+struct Forward {
+  DevState* st;
+  uint32_t* pend_out;        // survivors with predicates left
+  int* pend_out_count;
+  uint32_t* result_bits;     // completed tuples (bit per local index)
+  uint32_t* route_log;       // optional
+  Queues defer;              // next tier (band) queues; entries == nullptr for the last tier
+  unsigned long long* defer_stat;   // per-predicate counter of deferred decisions
+  float tau;                 // |d - theta| < tau defers to the next tier
+  const float* theta;        // [n_seg][K]
+  int n_seg;
+  int64_t seg_len;
+  int64_t id_base;
+  uint32_t full_mask;        // (1 << K) - 1
+  int k_total;
+  int count_eval;            // 1 in the first pass (counts evaluated tuples)
+  double* logits;            // if set: write fp64 logits [idx][10] instead of deciding
+};
+
+__device__ inline float theta_of(const Forward& f, int k, uint32_t idx) {
+  int64_t g = f.id_base + (int64_t)idx;
+  int64_t s = g / f.seg_len;
+  if (s >= f.n_seg) s = f.n_seg - 1;
+  return f.theta[s * f.k_total + k];
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Wave-aggregated append: every active lane with `want` set gets a unique slot in *counter.
+__device__ inline int wave_append(int* counter, bool want) {
+  unsigned long long m = __ballot(want);
+  if (m == 0) return -1;
+  int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader);
+  unsigned long long below = m & ((1ull << lane_id()) - 1ull);
+  return want ? base + __popcll(below) : -1;
+}
+
+__device__ inline void wave_add_u64(unsigned long long* counter, bool pred) {
+  unsigned long long m = __ballot(pred);
+  if (m != 0 && lane_id() == __ffsll((long long)m) - 1) atomicAdd(counter, (unsigned long long)__popcll(m));
+}
+
+// Margin d = max_{c in S} z_c - max_{c not in S} z_c (a max over no classes is -inf).
+template <typename T>
+__device__ inline T class_margin(const T* z, uint32_t mask) {
+  T in = -__builtin_inf(), out = -__builtin_inf();
+  for (int c = 0; c < kClasses; ++c) {
+    if ((mask >> c) & 1u) in = z[c] > in ? z[c] : in;
+    else out = z[c] > out ? z[c] : out;
+  }
+  return in - out;
+}
+
+// Record the decision on one (tuple, predicate) evaluation.  Called by every lane of a wave
+// (lanes with active == false take part in the ballots only).
+//   decided: pass / fail known at this tier;  pass: the decision;  defer: send to next tier.
+__device__ inline void forward_decision(const Forward& f, int k, uint32_t e, bool active, bool defer, bool pass) {
+  bool decided = active && !defer;
+  if (f.count_eval) wave_add_u64(&f.st->r_eval[k], active);
+  // next tier
+  if (f.defer.entries != nullptr) {
+    wave_add_u64(&f.defer_stat[k], active && defer);
+    int slot = wave_append(&f.defer.counts[k], active && defer);
+    if (active && defer) f.defer.entries[(int64_t)k * f.defer.cap + slot] = e;
+  }
+  bool ok = decided && pass;
+  wave_add_u64(&f.st->r_pass[k], ok);
+  uint32_t idx = entry_idx(e);
+  uint32_t mask = entry_mask(e) | (1u << k);
+  if (decided && f.route_log != nullptr) {
+    int step = __popc(entry_mask(e));
+    f.route_log[idx] |= (uint32_t)(k + 1) << (4 * step);
+  }
+  bool done = ok && mask == f.full_mask;
+  bool more = ok && mask != f.full_mask;
+  if (done) atomicOr(&f.result_bits[idx >> 5], 1u << (idx & 31));
+  int slot = wave_append(f.pend_out_count, more);
+  if (more) f.pend_out[slot] = make_entry(idx, mask);
+}
+
+}  // namespace hydro

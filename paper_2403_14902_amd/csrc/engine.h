@@ -1,0 +1,62 @@
+// Internal interfaces between the round driver (engine.hip) and the predicate kernels.
+#pragma once
+
+#include "common.h"
+
+namespace hydro {
+
+enum Tier { TIER_FIRST = 0, TIER_F32 = 1, TIER_F64 = 2 };
+
+// Grouped launch over the MLP predicates of one tier.
+struct MlpArgs {
+  int n_preds;
+  int pred[kMaxK];                  // predicate index of each slot
+  int d_in[kMaxK], hidden[kMaxK];
+  uint32_t class_mask[kMaxK];
+  const __bf16* w1_bf[kMaxK];       // [hidden][d_in], folded
+  const float* w1_f32[kMaxK];       // [hidden][d_in], folded
+  const float* b1_fold[kMaxK];
+  const float* w2[kMaxK];           // [hidden][10]
+  const float* b2[kMaxK];
+  const float* w1_canon[kMaxK];     // [d_in][hidden]
+  const float* b1_canon[kMaxK];
+  float* partial[kMaxK];            // [hidden/64][part_cap][10]
+  int64_t part_cap;
+  Queues q;
+  FrameSrc fr;
+  DevState* st;
+  int count_ticks;
+  int prec;
+};
+
+// Grouped launch over the CNN predicates of one tier.
+struct CnnArgs {
+  int n_preds;
+  int pred[kMaxK];
+  int variant[kMaxK];
+  uint32_t class_mask[kMaxK];
+  const __bf16* w_bf[kMaxK][3];     // packed per layer (bf16 fragments)
+  const float* w_f32[kMaxK][3];     // packed per layer (fp32 fragments)
+  const float* bias[kMaxK][3];      // fp32, layer 1 folded
+  const float* fc_w[kMaxK];         // [c_last][10]
+  const float* fc_b[kMaxK];
+  const float* w_canon[kMaxK][3];   // [co][ci][3][3]
+  const float* b_canon[kMaxK][3];
+  float pad_raw;                    // raw frame value that normalises to 0
+  double* scratch64;                // FP64 tier: per-block activation scratch
+  int64_t scratch64_per_block;      // doubles
+  Queues q;
+  FrameSrc fr;
+  DevState* st;
+  int count_ticks;
+  int prec;
+};
+
+void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
+void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
+size_t cnn_packed_elems(int variant, int layer);
+void cnn_pack_layer(int variant, int layer, const float* w_canon, float scale, float* out_f32);
+int cnn_variant_of(int in_hw, int n_layers, const int* widths);
+int cnn_grid_hint(int variant, int tier);
+
+}  // namespace hydro

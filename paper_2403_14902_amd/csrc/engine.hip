@@ -1,0 +1,1067 @@
+// Round driver of the gfx950 engine: sessions, weight packing, the adaptive router, queue
+// multi-split, result materialisation, and the C ABI declared in include/hydro.h.
+//
+// A push of n tuples is evaluated in rounds.  Every round:
+//   1. fold: the previous round's per-predicate counts and device time are folded into
+//      running selectivity / cost estimates and the predicates are ranked by the policy
+//      (section 4.1: score = cost / (1 - selectivity); cost alone; selectivity alone; or the
+//      written order);
+//   2. route: every live tuple (survivors of earlier rounds plus a newly admitted wave) goes to
+//      the first predicate in that ranking it has not visited yet (the visited table of
+//      section 3.3 is a per-tuple bit mask) and is appended to that predicate's queue with
+//      one atomic per wave per predicate;
+//   3. evaluate: one grouped launch per arithmetic tier evaluates every queue; a tuple whose
+//      margin lies within tau of its threshold is deferred to the next tier (BF16 -> FP32 ->
+//      FP64); decided tuples are forwarded: failures are dropped at once (section 3.3, eager
+//      materialisation), survivors join the next round's live list, and tuples that passed
+//      every predicate set their bit in the result bitmap.
+// The number of rounds of a push is fixed by n alone (every live tuple is evaluated once per
+// round, so a tuple admitted in round r is done by round r + K - 1); the host therefore
+// enqueues the whole push without waiting on the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "router_nn.h"
+
+using namespace hydro;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(_e == hipErrorOutOfMemory ? HYDRO_ENOMEM : HYDRO_EDEVICE,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                        \
+  } while (0)
+
+// Optional allocation-failure injection for tests of the error paths: the n-th device
+// allocation after session start fails when HYDRO_FAULT_ALLOC_AFTER=n is set.
+static int g_alloc_counter = 0;
+static hipError_t dev_alloc(void** p, size_t bytes) {
+  const char* s = getenv("HYDRO_FAULT_ALLOC_AFTER");
+  if (s != nullptr && *s) {
+    int lim = atoi(s);
+    if (g_alloc_counter++ >= lim) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  if (bytes == 0) bytes = 16;
+  return hipMalloc(p, bytes);
+}
+
+// ---------------------------------------------------------------- round kernels
+struct FoldArgs {
+  DevState* st;
+  int k;
+  int route;
+  int order[kMaxK];
+  double alpha;
+  int static_cost;
+  double flops[kMaxK];
+  int out_slot;         // pend_count slot that receives this round's survivors
+  int final_fold;       // 1: only fold counts (after the last round)
+};
+
+__global__ void k_fold(FoldArgs a) {
+  DevState* st = a.st;
+  const int k = threadIdx.x;
+  if (k < a.k) {
+    unsigned long long e = st->r_eval[k], p = st->r_pass[k], tk = st->r_ticks[k];
+    st->t_eval[k] += e;
+    st->t_pass[k] += p;
+    st->t_ticks[k] += tk;
+    st->t_rescored[k] += st->r_rescored[k];
+    st->t_esc[k] += st->r_esc[k];
+    if (e > 0) {
+      // running estimates; the +1/+2 prior keeps the selectivity off 0 and 1
+      double s_obs = ((double)p + 1.0) / ((double)e + 2.0);
+      double c_obs = a.static_cost ? a.flops[k] : (double)tk / (double)e;
+      if (!st->seen[k]) {
+        st->sel_est[k] = s_obs;
+        st->cost_est[k] = c_obs;
+        st->seen[k] = 1;
+      } else {
+        st->sel_est[k] = (1.0 - a.alpha) * st->sel_est[k] + a.alpha * s_obs;
+        st->cost_est[k] = (1.0 - a.alpha) * st->cost_est[k] + a.alpha * c_obs;
+      }
+    }
+    st->r_eval[k] = st->r_pass[k] = st->r_ticks[k] = st->r_rescored[k] = st->r_esc[k] = 0;
+    st->qcount[k] = st->bcount[k] = st->ecount[k] = 0;
+  }
+  __syncthreads();
+  if (k == 0 && !a.final_fold) {
+    st->pend_count[a.out_slot] = 0;
+    st->rounds += 1;
+    double key[kMaxK];
+    for (int j = 0; j < a.k; ++j) {
+      double s = st->sel_est[j], c = st->cost_est[j];
+      if (!st->seen[j]) key[j] = -1.0;  // unseen predicates first (gathers statistics)
+      else if (a.route == HYDRO_ROUTE_SEL) key[j] = s;
+      else if (a.route == HYDRO_ROUTE_COST) key[j] = c;
+      else key[j] = c / (1.0 - s);      // SCORE (and the LEARNED router's fallback)
+    }
+    if (a.route == HYDRO_ROUTE_FIXED) {
+      for (int j = 0; j < a.k; ++j) st->order[j] = a.order[j];
+    } else {
+      bool used[kMaxK] = {false};
+      for (int r = 0; r < a.k; ++r) {
+        int best = -1;
+        for (int j = 0; j < a.k; ++j)
+          if (!used[j] && (best < 0 || key[j] < key[best])) best = j;
+        used[best] = true;
+        st->order[r] = best;
+      }
+    }
+  }
+}
+
+struct RouteArgs {
+  DevState* st;
+  const uint32_t* pend_in;
+  int in_slot;
+  uint32_t adm_lo, adm_hi;
+  int warmup;
+  int routing_batch;
+  int k;
+  Queues q;
+  const float* learned_keys;   // LEARNED: per-tuple keys [idx][K] (nullptr otherwise)
+  const uint8_t* arm;          // LEARNED: per routing batch, 1 = learned arm
+};
+
+__device__ inline int choose_pred(const RouteArgs& a, uint32_t e, const int* order) {
+  uint32_t mask = entry_mask(e);
+  uint32_t idx = entry_idx(e);
+  if (a.warmup && mask == 0) return (int)((idx / (uint32_t)a.routing_batch) % (uint32_t)a.k);
+  if (a.learned_keys != nullptr && a.arm[idx / (uint32_t)a.routing_batch]) {
+    const float* kk = a.learned_keys + (int64_t)idx * a.k;
+    int best = -1;
+    float bk = 0.f;
+    for (int j = 0; j < a.k; ++j)
+      if (!((mask >> j) & 1u) && (best < 0 || kk[j] < bk)) { best = j; bk = kk[j]; }
+    return best;
+  }
+  for (int r = 0; r < a.k; ++r) {
+    int j = order[r];
+    if (!((mask >> j) & 1u)) return j;
+  }
+  return 0;
+}
+
+__global__ __launch_bounds__(256) void k_route(RouteArgs a) {
+  __shared__ int order[kMaxK];
+  if (threadIdx.x < a.k) order[threadIdx.x] = a.st->order[threadIdx.x];
+  __syncthreads();
+  const int n_in = a.st->pend_count[a.in_slot];
+  const int total = n_in + (int)(a.adm_hi - a.adm_lo);
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
+    int i = base + threadIdx.x;
+    bool active = i < total;
+    uint32_t e = 0;
+    int k = -1;
+    if (active) {
+      e = i < n_in ? a.pend_in[i] : make_entry(a.adm_lo + (uint32_t)(i - n_in), 0u);
+      k = choose_pred(a, e, order);
+    }
+    if (a.learned_keys != nullptr) {
+      bool learned = active && a.arm[entry_idx(e) / (uint32_t)a.routing_batch] && !(a.warmup && entry_mask(e) == 0);
+      wave_add_u64(&a.st->learned_routed, learned && entry_mask(e) == 0);
+      wave_add_u64(&a.st->stats_routed, active && !learned && entry_mask(e) == 0);
+    }
+    for (int j = 0; j < a.k; ++j) {
+      bool mine = active && k == j;
+      if (__ballot(mine) == 0) continue;
+      int slot = wave_append(&a.q.counts[j], mine);
+      if (mine) a.q.entries[(int64_t)j * a.q.cap + slot] = e;
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Result bitmap -> ascending int64 ids (ordered compaction, three passes).
+__global__ __launch_bounds__(256) void k_res_count(const uint32_t* bits, int64_t nwords, int* block_counts) {
+  __shared__ int red[256];
+  int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  red[threadIdx.x] = w < nwords ? __popc(bits[w]) : 0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_res_scan(int* block_counts, int nblocks, DevState* st, int* base_out) {
+  __shared__ int sums[1024];
+  const int t = threadIdx.x;
+  const int per = (nblocks + 1023) / 1024;
+  int lo = t * per, hi = min(nblocks, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += block_counts[i];
+  sums[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = t >= o ? sums[t - o] : 0;
+    __syncthreads();
+    sums[t] += v;
+    __syncthreads();
+  }
+  int base = st->n_result;
+  int run = base + (t > 0 ? sums[t - 1] : 0);
+  for (int i = lo; i < hi; ++i) {
+    int c = block_counts[i];
+    block_counts[i] = run;
+    run += c;
+  }
+  __syncthreads();
+  if (t == 0) {
+    *base_out = base;
+    st->n_result = base + sums[1023];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_res_write(const uint32_t* bits, int64_t nwords, const int* block_offsets,
+                                                   int64_t id_base, int64_t* out) {
+  __shared__ int pre[256];
+  int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  uint32_t b = w < nwords ? bits[w] : 0u;
+  pre[threadIdx.x] = __popc(b);
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int v = threadIdx.x >= o ? pre[threadIdx.x - o] : 0;
+    __syncthreads();
+    pre[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = block_offsets[blockIdx.x] + pre[threadIdx.x] - __popc(b);
+  while (b) {
+    int bit = __ffs(b) - 1;
+    out[pos++] = id_base + w * 32 + bit;
+    b &= b - 1;
+  }
+}
+
+// ---------------------------------------------------------------- session
+struct HostModel {
+  hydro_model m;
+  std::vector<float> w1, b1, w2, b2, fcw, fcb;
+  std::vector<float> cw[HYDRO_MAX_LAYERS], cb[HYDRO_MAX_LAYERS];
+  double flops = 0;
+  int variant = CNN_NONE;
+};
+
+struct PushRec {
+  int64_t id_base, n;
+};
+
+struct hydro_session {
+  int device = 0;
+  int n_cu = 256;
+  hipStream_t stream = nullptr, copy_stream = nullptr;
+  bool own_stream = false;
+  hydro_policy pol{};
+  int K = 0, fh = 0, fw = 0, fdtype = 0;
+  int64_t max_push = 0, cap = 0;
+  std::vector<HostModel> models;
+  std::vector<void*> allocs;
+  // device state
+  DevState* st = nullptr;
+  uint32_t* pend[2] = {nullptr, nullptr};
+  uint32_t *q1 = nullptr, *q2 = nullptr, *q3 = nullptr;
+  uint32_t* result_bits = nullptr;
+  uint32_t* route_log = nullptr;
+  int* res_blocks = nullptr;
+  int* res_base = nullptr;
+  int64_t* out_ids = nullptr;
+  int64_t out_cap = 0;
+  float* theta = nullptr;
+  int theta_cap = 0;
+  void* stage[2] = {nullptr, nullptr};
+  hipEvent_t stage_free[2] = {nullptr, nullptr}, stage_ready[2] = {nullptr, nullptr};
+  int stage_next = 0;
+  MlpArgs mlp{};
+  CnnArgs cnn{};
+  RouterNN* rnn = nullptr;
+  // query progress
+  int rounds_done = 0;
+  bool warmed = false;
+  int parity = 0;
+  int pushes = 0;
+  bool ids_sorted = true;
+  int64_t last_id_end = INT64_MIN;
+  int64_t last_push_n = 0;
+  std::deque<std::vector<float>> theta_host;
+  std::chrono::steady_clock::time_point t_start;
+  hydro_query_info info{};
+  double tick_us = 0.01;   // device wall clock period in microseconds
+};
+
+static int sess_alloc(hydro_session* s, void** p, size_t bytes) {
+  hipError_t e = dev_alloc(p, bytes);
+  if (e != hipSuccess) return fail(HYDRO_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes failed");
+  s->allocs.push_back(*p);
+  return HYDRO_OK;
+}
+
+template <typename T>
+static int upload(hydro_session* s, const T* host, size_t n, T** dev) {
+  int rc = sess_alloc(s, (void**)dev, n * sizeof(T));
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(*dev, host, n * sizeof(T), hipMemcpyHostToDevice));
+  return HYDRO_OK;
+}
+
+static uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+static double model_flops(const hydro_model& m) {
+  if (m.arch == HYDRO_ARCH_MLP) {
+    double d = (double)m.in_h * m.in_w * 3;
+    return 2.0 * (d * m.hidden + (double)m.hidden * kClasses);
+  }
+  double f = 0;
+  int hw = m.in_h, cin = 3;
+  for (int l = 0; l < m.n_layers; ++l) {
+    hw /= 2;
+    f += 2.0 * hw * hw * m.widths[l] * cin * 9;
+    cin = m.widths[l];
+  }
+  return f + 2.0 * cin * kClasses;
+}
+
+static int validate_model(const hydro_model& m, int fh, int fw) {
+  if (m.in_h != fh || m.in_w != fw) return fail(HYDRO_EINVAL, "model input shape differs from the session's frame shape");
+  if (m.class_mask >= (1u << kClasses)) return fail(HYDRO_EINVAL, "class_mask has bits above class 9");
+  if (m.arch == HYDRO_ARCH_MLP) {
+    if (!m.w1 || !m.b1 || !m.w2 || !m.b2) return fail(HYDRO_EINVAL, "MLP weight pointer is NULL");
+    if (m.hidden <= 0 || m.hidden % 128 != 0 || m.hidden > 2048)
+      return fail(HYDRO_EUNSUPPORTED, "MLP hidden width must be a multiple of 128 and at most 2048");
+    int64_t d = (int64_t)fh * fw * 3;
+    if (d % 32 != 0) return fail(HYDRO_EUNSUPPORTED, "MLP input size must be a multiple of 32");
+    return HYDRO_OK;
+  }
+  if (m.arch != HYDRO_ARCH_CNN) return fail(HYDRO_EINVAL, "unknown model arch");
+  if (m.n_layers < 1 || m.n_layers > HYDRO_MAX_LAYERS) return fail(HYDRO_EINVAL, "CNN n_layers out of range");
+  for (int l = 0; l < m.n_layers; ++l)
+    if (!m.conv_w[l] || !m.conv_b[l]) return fail(HYDRO_EINVAL, "CNN conv weight pointer is NULL");
+  if (!m.fc_w || !m.fc_b) return fail(HYDRO_EINVAL, "CNN fc weight pointer is NULL");
+  if (cnn_variant_of(m.in_h, m.n_layers, m.widths) == CNN_NONE || m.in_w != m.in_h)
+    return fail(HYDRO_EUNSUPPORTED, "CNN shape not supported (64x64 frames, 3 layers of widths (16m, 32m, 64m), m in {1,2,4})");
+  return HYDRO_OK;
+}
+
+static int pack_models(hydro_session* s) {
+  const double scale = s->fdtype == HYDRO_DTYPE_U8 ? 4.0 / 255.0 : 4.0;
+  const float pad_raw = s->fdtype == HYDRO_DTYPE_U8 ? 127.5f : 0.5f;
+  MlpArgs& ma = s->mlp;
+  CnnArgs& ca = s->cnn;
+  ma = MlpArgs{};
+  ca = CnnArgs{};
+  ca.pad_raw = pad_raw;
+  for (int k = 0; k < s->K; ++k) {
+    HostModel& hm = s->models[k];
+    const hydro_model& m = hm.m;
+    if (m.arch == HYDRO_ARCH_MLP) {
+      const int D = m.in_h * m.in_w * 3, H = m.hidden;
+      std::vector<float> wt((size_t)H * D), b1f(H);
+      std::vector<uint16_t> wb((size_t)H * D);
+      for (int j = 0; j < H; ++j) {
+        double colsum = 0;
+        for (int d = 0; d < D; ++d) {
+          double w = hm.w1[(size_t)d * H + j];
+          colsum += w;
+          float v = (float)(w * scale);
+          wt[(size_t)j * D + d] = v;
+          wb[(size_t)j * D + d] = f32_to_bf16_bits(v);
+        }
+        b1f[j] = (float)((double)hm.b1[j] - 2.0 * colsum);
+      }
+      int i = ma.n_preds++;
+      ma.pred[i] = k;
+      ma.d_in[i] = D;
+      ma.hidden[i] = H;
+      ma.class_mask[i] = m.class_mask;
+      int rc;
+      float* dp;
+      uint16_t* bp;
+      if ((rc = upload(s, wt.data(), wt.size(), &dp))) return rc;
+      ma.w1_f32[i] = dp;
+      if ((rc = upload(s, wb.data(), wb.size(), &bp))) return rc;
+      ma.w1_bf[i] = reinterpret_cast<const __bf16*>(bp);
+      if ((rc = upload(s, b1f.data(), b1f.size(), &dp))) return rc;
+      ma.b1_fold[i] = dp;
+      if ((rc = upload(s, hm.w2.data(), hm.w2.size(), &dp))) return rc;
+      ma.w2[i] = dp;
+      if ((rc = upload(s, hm.b2.data(), hm.b2.size(), &dp))) return rc;
+      ma.b2[i] = dp;
+      if ((rc = upload(s, hm.w1.data(), hm.w1.size(), &dp))) return rc;
+      ma.w1_canon[i] = dp;
+      if ((rc = upload(s, hm.b1.data(), hm.b1.size(), &dp))) return rc;
+      ma.b1_canon[i] = dp;
+      if ((rc = sess_alloc(s, (void**)&ma.partial[i], (size_t)(H / 64) * s->cap * kClasses * sizeof(float)))) return rc;
+    } else {
+      int i = ca.n_preds++;
+      ca.pred[i] = k;
+      ca.variant[i] = hm.variant;
+      ca.class_mask[i] = m.class_mask;
+      int cin = 3;
+      for (int l = 0; l < m.n_layers; ++l) {
+        const int co = m.widths[l];
+        const double sc = l == 0 ? scale : 1.0;
+        std::vector<float> bias(co);
+        for (int o = 0; o < co; ++o) {
+          double b = hm.cb[l][o];
+          if (l == 0) {
+            double sum = 0;
+            for (int t = 0; t < cin * 9; ++t) sum += hm.cw[l][(size_t)o * cin * 9 + t];
+            b -= 2.0 * sum;
+          }
+          bias[o] = (float)b;
+        }
+        size_t n = cnn_packed_elems(hm.variant, l);
+        std::vector<float> pf(n);
+        cnn_pack_layer(hm.variant, l, hm.cw[l].data(), (float)sc, pf.data());
+        std::vector<uint16_t> pb(n);
+        for (size_t t = 0; t < n; ++t) pb[t] = f32_to_bf16_bits(pf[t]);
+        int rc;
+        float* dp;
+        uint16_t* bp;
+        if ((rc = upload(s, pf.data(), n, &dp))) return rc;
+        ca.w_f32[i][l] = dp;
+        if ((rc = upload(s, pb.data(), n, &bp))) return rc;
+        ca.w_bf[i][l] = reinterpret_cast<const __bf16*>(bp);
+        if ((rc = upload(s, bias.data(), bias.size(), &dp))) return rc;
+        ca.bias[i][l] = dp;
+        if ((rc = upload(s, hm.cw[l].data(), hm.cw[l].size(), &dp))) return rc;
+        ca.w_canon[i][l] = dp;
+        if ((rc = upload(s, hm.cb[l].data(), hm.cb[l].size(), &dp))) return rc;
+        ca.b_canon[i][l] = dp;
+        cin = co;
+      }
+      int rc;
+      float* dp;
+      if ((rc = upload(s, hm.fcw.data(), hm.fcw.size(), &dp))) return rc;
+      ca.fc_w[i] = dp;
+      if ((rc = upload(s, hm.fcb.data(), hm.fcb.size(), &dp))) return rc;
+      ca.fc_b[i] = dp;
+    }
+  }
+  if (ca.n_preds > 0) {
+    // FP64 tier scratch: two activation buffers per block (largest layer output)
+    int64_t per = 0;
+    for (int i = 0; i < ca.n_preds; ++i) {
+      const hydro_model& m = s->models[ca.pred[i]].m;
+      int hw = m.in_h;
+      for (int l = 0; l < m.n_layers; ++l) {
+        hw /= 2;
+        per = std::max<int64_t>(per, (int64_t)hw * hw * m.widths[l]);
+      }
+    }
+    ca.scratch64_per_block = 2 * per;
+    int rc = sess_alloc(s, (void**)&ca.scratch64, (size_t)ca.scratch64_per_block * s->n_cu * sizeof(double));
+    if (rc) return rc;
+  }
+  return HYDRO_OK;
+}
+
+static void free_session(hydro_session* s) {
+  if (!s) return;
+  if (s->stream) hipStreamSynchronize(s->stream);
+  if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
+  if (s->rnn) router_nn_destroy(s->rnn);
+  for (void* p : s->allocs) hipFree(p);
+  for (int i = 0; i < 2; ++i) {
+    if (s->stage[i]) hipFree(s->stage[i]);
+    if (s->stage_free[i]) hipEventDestroy(s->stage_free[i]);
+    if (s->stage_ready[i]) hipEventDestroy(s->stage_ready[i]);
+  }
+  if (s->out_ids) hipFree(s->out_ids);
+  if (s->copy_stream) hipStreamDestroy(s->copy_stream);
+  if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+  delete s;
+}
+
+extern "C" {
+
+const char* hydro_last_error(void) { return g_err.c_str(); }
+const char* hydro_version(void) { return "hydro-gfx950 0.1"; }
+void hydro_free(void* p) { free(p); }
+
+void hydro_policy_default(hydro_policy* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->route = HYDRO_ROUTE_SCORE;
+  for (int i = 0; i < HYDRO_MAX_PREDICATES; ++i) p->order[i] = i;
+  p->routing_batch = 64;
+  p->wave = 8192;
+  p->warmup_batches = 1;
+  p->ewma_alpha = 0.5f;
+  p->cost_source = HYDRO_COST_MEASURED;
+  p->precision = HYDRO_PREC_BF16;
+  p->tau = 0.05f;
+  p->tau32 = 1e-4f;
+  p->grouped = 1;
+  p->use_graph = 0;
+  p->log_routes = 0;
+  p->explore = 0.05f;
+  p->seed = 4242;
+  p->stream = nullptr;
+}
+
+static int validate_policy(const hydro_policy* p, int K) {
+  if (!p) return fail(HYDRO_EINVAL, "policy is NULL");
+  if (p->route < HYDRO_ROUTE_FIXED || p->route > HYDRO_ROUTE_LEARNED) return fail(HYDRO_EINVAL, "unknown route policy");
+  if (p->route == HYDRO_ROUTE_FIXED) {
+    unsigned seen = 0;
+    for (int i = 0; i < K; ++i) {
+      int o = p->order[i];
+      if (o < 0 || o >= K || (seen >> o) & 1u) return fail(HYDRO_EINVAL, "FIXED order is not a permutation of 0..K-1");
+      seen |= 1u << o;
+    }
+  }
+  if (p->routing_batch <= 0) return fail(HYDRO_EINVAL, "routing_batch must be positive");
+  if (p->wave <= 0) return fail(HYDRO_EINVAL, "wave must be positive");
+  if (p->warmup_batches < 0) return fail(HYDRO_EINVAL, "warmup_batches must be >= 0");
+  if (!(p->ewma_alpha > 0.f && p->ewma_alpha <= 1.f)) return fail(HYDRO_EINVAL, "ewma_alpha must be in (0, 1]");
+  if (p->precision != HYDRO_PREC_FP32 && p->precision != HYDRO_PREC_BF16) return fail(HYDRO_EUNSUPPORTED, "precision not supported");
+  if (p->cost_source != HYDRO_COST_MEASURED && p->cost_source != HYDRO_COST_STATIC) return fail(HYDRO_EINVAL, "unknown cost_source");
+  if (p->explore < 0.f || p->explore > 1.f) return fail(HYDRO_EINVAL, "explore must be in [0, 1]");
+  return HYDRO_OK;
+}
+
+int hydro_session_create(const hydro_model* models, int32_t k, const hydro_policy* policy, int32_t frame_h,
+                         int32_t frame_w, int64_t max_push, hydro_session** out) {
+  g_err.clear();
+  if (!out) return fail(HYDRO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!models) return fail(HYDRO_EINVAL, "models is NULL");
+  if (k < 1) return fail(HYDRO_EINVAL, "K must be at least 1");
+  if (k > HYDRO_MAX_PREDICATES) return fail(HYDRO_EUNSUPPORTED, "K above 8 is not supported");
+  if (frame_h <= 0 || frame_w <= 0) return fail(HYDRO_EINVAL, "frame shape must be positive");
+  if (max_push <= 0) return fail(HYDRO_EINVAL, "max_push must be positive");
+  if (max_push > (int64_t)kIdxMask) return fail(HYDRO_EUNSUPPORTED, "max_push above 2^24 - 1 tuples");
+  int rc = validate_policy(policy, k);
+  if (rc) return rc;
+  for (int i = 0; i < k; ++i)
+    if ((rc = validate_model(models[i], frame_h, frame_w))) return rc;
+
+  g_alloc_counter = 0;
+  hydro_session* s = new hydro_session();
+  s->pol = *policy;
+  if (s->pol.tau <= 0.f) s->pol.tau = 0.05f;
+  if (s->pol.tau32 <= 0.f) s->pol.tau32 = 1e-4f;
+  s->K = k;
+  s->fh = frame_h;
+  s->fw = frame_w;
+  s->max_push = max_push;
+  s->cap = max_push;
+  // the session's frame dtype is fixed by the first push; weights are packed then
+  s->fdtype = -1;
+  s->models.resize(k);
+  for (int i = 0; i < k; ++i) {
+    HostModel& hm = s->models[i];
+    hm.m = models[i];
+    const hydro_model& m = models[i];
+    hm.flops = model_flops(m);
+    if (m.arch == HYDRO_ARCH_MLP) {
+      size_t D = (size_t)m.in_h * m.in_w * 3;
+      hm.w1.assign(m.w1, m.w1 + D * m.hidden);
+      hm.b1.assign(m.b1, m.b1 + m.hidden);
+      hm.w2.assign(m.w2, m.w2 + (size_t)m.hidden * kClasses);
+      hm.b2.assign(m.b2, m.b2 + kClasses);
+    } else {
+      int cin = 3;
+      for (int l = 0; l < m.n_layers; ++l) {
+        hm.cw[l].assign(m.conv_w[l], m.conv_w[l] + (size_t)m.widths[l] * cin * 9);
+        hm.cb[l].assign(m.conv_b[l], m.conv_b[l] + m.widths[l]);
+        cin = m.widths[l];
+      }
+      hm.fcw.assign(m.fc_w, m.fc_w + (size_t)cin * kClasses);
+      hm.fcb.assign(m.fc_b, m.fc_b + kClasses);
+      hm.variant = cnn_variant_of(m.in_h, m.n_layers, m.widths);
+    }
+  }
+  auto bail = [&](int code) {
+    free_session(s);
+    return code;
+  };
+  hipError_t he = hipGetDevice(&s->device);
+  if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he)));
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, s->device);
+  if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he)));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return bail(fail(HYDRO_EUNSUPPORTED, std::string("this library is built for gfx950, device is ") + prop.gcnArchName));
+  s->n_cu = prop.multiProcessorCount;
+  int clk_khz = 0;
+  if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, s->device) == hipSuccess && clk_khz > 0)
+    s->tick_us = 1000.0 / clk_khz;
+  if (s->pol.stream) {
+    s->stream = (hipStream_t)s->pol.stream;
+  } else {
+    he = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(he)));
+    s->own_stream = true;
+  }
+  he = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+  if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(he)));
+  for (int i = 0; i < 2; ++i) {
+    hipEventCreateWithFlags(&s->stage_free[i], hipEventDisableTiming);
+    hipEventCreateWithFlags(&s->stage_ready[i], hipEventDisableTiming);
+  }
+  const int64_t cap = s->cap;
+  if ((rc = sess_alloc(s, (void**)&s->st, sizeof(DevState)))) return bail(rc);
+  for (int i = 0; i < 2; ++i)
+    if ((rc = sess_alloc(s, (void**)&s->pend[i], cap * 4))) return bail(rc);
+  if ((rc = sess_alloc(s, (void**)&s->q1, cap * 4 * k))) return bail(rc);
+  if ((rc = sess_alloc(s, (void**)&s->q2, cap * 4 * k))) return bail(rc);
+  if ((rc = sess_alloc(s, (void**)&s->q3, cap * 4 * k))) return bail(rc);
+  const int64_t nwords = (cap + 31) / 32;
+  if ((rc = sess_alloc(s, (void**)&s->result_bits, nwords * 4 + 1024))) return bail(rc);
+  if ((rc = sess_alloc(s, (void**)&s->res_blocks, ((nwords + 255) / 256 + 1) * 4))) return bail(rc);
+  if ((rc = sess_alloc(s, (void**)&s->res_base, 16))) return bail(rc);
+  if (s->pol.log_routes && (rc = sess_alloc(s, (void**)&s->route_log, cap * 4))) return bail(rc);
+  if ((rc = sess_alloc(s, (void**)&s->theta, 4096 * sizeof(float)))) return bail(rc);
+  s->theta_cap = 4096;
+  he = dev_alloc((void**)&s->out_ids, cap * sizeof(int64_t));
+  if (he != hipSuccess) return bail(fail(HYDRO_ENOMEM, "result buffer allocation failed"));
+  s->out_cap = cap;
+  if (s->pol.route == HYDRO_ROUTE_LEARNED) {
+    rc = router_nn_create(&s->rnn, s->K, frame_h, frame_w, cap, s->pol.seed, s->pol.routing_batch);
+    if (rc) return bail(rc);
+  }
+  rc = hydro_session_reset(s);
+  if (rc) return bail(rc);
+  *out = s;
+  return HYDRO_OK;
+}
+
+int hydro_session_reset(hydro_session* s) {
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->rounds_done = 0;
+  s->warmed = false;
+  s->parity = 0;
+  s->pushes = 0;
+  s->ids_sorted = true;
+  s->last_id_end = INT64_MIN;
+  s->theta_host.clear();
+  s->info = hydro_query_info{};
+  if (s->rnn) router_nn_reset(s->rnn, s->stream);
+  return HYDRO_OK;
+}
+
+static Forward make_forward(hydro_session* s, int tier, int out_slot, const FrameSrc& fr, int n_seg, int64_t seg_len,
+                            int64_t id_base) {
+  Forward f{};
+  f.st = s->st;
+  f.pend_out = s->pend[out_slot];
+  f.pend_out_count = &s->st->pend_count[out_slot];
+  f.result_bits = s->result_bits;
+  f.route_log = s->route_log;
+  f.theta = s->theta;
+  f.n_seg = n_seg;
+  f.seg_len = seg_len;
+  f.id_base = id_base;
+  f.full_mask = (1u << s->K) - 1u;
+  f.k_total = s->K;
+  f.logits = nullptr;
+  const bool bf = s->pol.precision == HYDRO_PREC_BF16;
+  if (tier == TIER_FIRST) {
+    f.count_eval = 1;
+    f.defer = Queues{bf ? s->q2 : s->q3, bf ? s->st->bcount : s->st->ecount, s->cap};
+    f.defer_stat = bf ? s->st->r_rescored : s->st->r_esc;
+    f.tau = bf ? s->pol.tau : s->pol.tau32;
+  } else if (tier == TIER_F32) {
+    f.count_eval = 0;
+    f.defer = Queues{s->q3, s->st->ecount, s->cap};
+    f.defer_stat = s->st->r_esc;
+    f.tau = s->pol.tau32;
+  } else {
+    f.count_eval = 0;
+    f.defer = Queues{nullptr, nullptr, 0};
+    f.defer_stat = nullptr;
+    f.tau = 0.f;
+  }
+  (void)fr;
+  return f;
+}
+
+static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const Forward& f, hipStream_t st) {
+  Queues q;
+  if (tier == TIER_FIRST) q = Queues{s->q1, s->st->qcount, s->cap};
+  else if (tier == TIER_F32) q = Queues{s->q2, s->st->bcount, s->cap};
+  else q = Queues{s->q3, s->st->ecount, s->cap};
+  if (s->mlp.n_preds) {
+    MlpArgs a = s->mlp;
+    a.q = q;
+    a.fr = fr;
+    a.st = s->st;
+    a.part_cap = s->cap;
+    a.count_ticks = 1;
+    a.prec = s->pol.precision;
+    launch_mlp_pass(a, f, tier, tier == TIER_F64 ? s->n_cu : s->n_cu * 4, st);
+  }
+  if (s->cnn.n_preds) {
+    CnnArgs a = s->cnn;
+    a.q = q;
+    a.fr = fr;
+    a.st = s->st;
+    a.count_ticks = 1;
+    a.prec = s->pol.precision;
+    launch_cnn_pass(a, f, tier, s->n_cu, st);
+  }
+}
+
+static int ensure_dtype(hydro_session* s, int dtype) {
+  if (s->fdtype == dtype) return HYDRO_OK;
+  if (s->fdtype != -1) return fail(HYDRO_EINVAL, "frame dtype differs from the session's first push");
+  if (dtype != HYDRO_DTYPE_F32 && dtype != HYDRO_DTYPE_BF16 && dtype != HYDRO_DTYPE_U8)
+    return fail(HYDRO_EINVAL, "unknown frame dtype");
+  for (auto& hm : s->models)
+    if (hm.m.arch == HYDRO_ARCH_CNN && dtype == HYDRO_DTYPE_F32)
+      return fail(HYDRO_EUNSUPPORTED, "CNN predicates take bf16 or uint8 frames");
+  s->fdtype = dtype;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int rc = pack_models(s);
+  if (rc) {
+    s->fdtype = -1;
+    return rc;
+  }
+  return HYDRO_OK;
+}
+
+static size_t dtype_size(int dt) { return dt == HYDRO_DTYPE_F32 ? 4 : dt == HYDRO_DTYPE_BF16 ? 2 : 1; }
+
+int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float* thresholds, int32_t n_seg,
+                       int64_t seg_len) {
+  g_err.clear();
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  if (!frames) return fail(HYDRO_EINVAL, "frames is NULL");
+  if (!thresholds) return fail(HYDRO_EINVAL, "thresholds is NULL");
+  if (n_seg < 1 || seg_len < 1) return fail(HYDRO_EINVAL, "n_seg and seg_len must be positive");
+  if ((int64_t)n_seg * s->K > 1 << 20) return fail(HYDRO_EUNSUPPORTED, "threshold table too large");
+  const hydro_frames& fr = *frames;
+  if (fr.n < 0) return fail(HYDRO_EINVAL, "negative tuple count");
+  if (fr.n > s->max_push) return fail(HYDRO_ECAPACITY, "push larger than the session's max_push");
+  if (fr.h != s->fh || fr.w != s->fw) return fail(HYDRO_EINVAL, "frame shape differs from the session's");
+  if (fr.where != HYDRO_MEM_DEVICE && fr.where != HYDRO_MEM_HOST) return fail(HYDRO_EINVAL, "unknown frame location");
+  if (fr.n > 0 && !fr.data) return fail(HYDRO_EINVAL, "frame data is NULL");
+  if (fr.id_base < 0) return fail(HYDRO_EINVAL, "negative id_base");
+  int rc = ensure_dtype(s, fr.dtype);
+  if (rc) return rc;
+  for (int64_t i = 0; i < (int64_t)n_seg * s->K; ++i)
+    if (std::isnan(thresholds[i])) return fail(HYDRO_EINVAL, "threshold is NaN");
+
+  if (s->pushes == 0) s->t_start = std::chrono::steady_clock::now();
+  s->pushes++;
+  if (fr.id_base < s->last_id_end) s->ids_sorted = false;
+  s->last_id_end = fr.id_base + fr.n;
+  s->last_push_n = fr.n;
+  hipStream_t st = s->stream;
+  const int64_t n = fr.n;
+
+  // thresholds (the host copy lives until finish: the async copy may still read it)
+  if ((int64_t)n_seg * s->K > s->theta_cap) {
+    HIP_TRY(hipStreamSynchronize(st));
+    void* p;
+    if ((rc = sess_alloc(s, &p, (size_t)n_seg * s->K * sizeof(float)))) return rc;
+    s->theta = (float*)p;
+    s->theta_cap = n_seg * s->K;
+  }
+  s->theta_host.emplace_back(thresholds, thresholds + (size_t)n_seg * s->K);
+  HIP_TRY(hipMemcpyAsync(s->theta, s->theta_host.back().data(), (size_t)n_seg * s->K * sizeof(float),
+                         hipMemcpyHostToDevice, st));
+
+  // frames
+  const size_t fbytes = (size_t)fr.h * fr.w * 3 * dtype_size(fr.dtype);
+  FrameSrc src{};
+  src.dtype = fr.dtype;
+  src.hw = fr.h;
+  src.elems = (int64_t)fr.h * fr.w * 3;
+  if (fr.where == HYDRO_MEM_DEVICE) {
+    src.base = fr.data;
+  } else {
+    int slot = s->stage_next;
+    s->stage_next ^= 1;
+    if (!s->stage[slot]) {
+      HIP_TRY(hipStreamSynchronize(st));
+      hipError_t he = dev_alloc(&s->stage[slot], fbytes * s->max_push);
+      if (he != hipSuccess) return fail(HYDRO_ENOMEM, "frame staging allocation failed");
+    }
+    // the copy waits until the last push that used this slot has finished computing
+    HIP_TRY(hipStreamWaitEvent(s->copy_stream, s->stage_free[slot], 0));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(s->stage[slot], fr.data, fbytes * n, hipMemcpyHostToDevice, s->copy_stream));
+    HIP_TRY(hipEventRecord(s->stage_ready[slot], s->copy_stream));
+    HIP_TRY(hipStreamWaitEvent(st, s->stage_ready[slot], 0));
+    src.base = s->stage[slot];
+  }
+
+  // result capacity
+  if (s->info.n_tuples + n > (uint64_t)s->out_cap) {
+    HIP_TRY(hipStreamSynchronize(st));
+    int64_t ncap = std::max<int64_t>(s->out_cap * 2, s->info.n_tuples + n);
+    int64_t* p;
+    hipError_t he = dev_alloc((void**)&p, ncap * sizeof(int64_t));
+    if (he != hipSuccess) return fail(HYDRO_ENOMEM, "result buffer allocation failed");
+    HIP_TRY(hipMemcpy(p, s->out_ids, s->out_cap * sizeof(int64_t), hipMemcpyDeviceToDevice));
+    hipFree(s->out_ids);
+    s->out_ids = p;
+    s->out_cap = ncap;
+  }
+  s->info.n_tuples += n;
+
+  const int64_t nwords = (n + 31) / 32;
+  if (nwords > 0) hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (nwords + 255) / 256)), dim3(256), 0, st,
+                                     s->result_bits, 0u, nwords);
+  if (s->route_log && n > 0)
+    hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, s->route_log, 0u, n);
+
+  if (s->rnn && n > 0) {
+    rc = router_nn_admit(s->rnn, src, n, st);
+    if (rc) return rc;
+  }
+
+  // admission schedule: optional warmup round, then waves
+  const bool adaptive = s->pol.route != HYDRO_ROUTE_FIXED;
+  std::vector<std::pair<int64_t, int64_t>> adm;
+  std::vector<int> warm;
+  int64_t pos = 0;
+  if (adaptive && !s->warmed && n > 0 && s->pol.warmup_batches > 0) {
+    int64_t w0 = std::min<int64_t>(n, (int64_t)s->pol.warmup_batches * s->K * s->pol.routing_batch);
+    adm.push_back({0, w0});
+    warm.push_back(1);
+    pos = w0;
+    s->warmed = true;
+  }
+  while (pos < n) {
+    int64_t w = std::min<int64_t>(n - pos, s->pol.wave);
+    adm.push_back({pos, pos + w});
+    warm.push_back(0);
+    pos += w;
+  }
+  const int n_rounds = adm.empty() ? 0 : (int)adm.size() + s->K - 1;
+
+  for (int r = 0; r < n_rounds; ++r) {
+    const int in_slot = s->parity, out_slot = s->parity ^ 1;
+    FoldArgs fa{};
+    fa.st = s->st;
+    fa.k = s->K;
+    fa.route = s->pol.route;
+    for (int j = 0; j < s->K; ++j) {
+      fa.order[j] = s->pol.order[j];
+      fa.flops[j] = s->models[j].flops;
+    }
+    fa.alpha = s->pol.ewma_alpha;
+    fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
+    fa.out_slot = out_slot;
+    fa.final_fold = 0;
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
+
+    if (s->rnn) router_nn_round(s->rnn, s->st, st);
+
+    RouteArgs ra{};
+    ra.st = s->st;
+    ra.pend_in = s->pend[in_slot];
+    ra.in_slot = in_slot;
+    if (r < (int)adm.size()) {
+      ra.adm_lo = (uint32_t)adm[r].first;
+      ra.adm_hi = (uint32_t)adm[r].second;
+      ra.warmup = warm[r];
+    } else {
+      ra.adm_lo = ra.adm_hi = 0;
+      ra.warmup = 0;
+    }
+    ra.routing_batch = s->pol.routing_batch;
+    ra.k = s->K;
+    ra.q = Queues{s->q1, s->st->qcount, s->cap};
+    ra.learned_keys = s->rnn ? router_nn_keys(s->rnn) : nullptr;
+    ra.arm = s->rnn ? router_nn_arms(s->rnn) : nullptr;
+    hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
+
+    for (int tier = TIER_FIRST; tier <= TIER_F64; ++tier) {
+      if (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_BF16) continue;
+      Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
+      enqueue_tier(s, tier, src, f, st);
+    }
+    if (s->rnn) router_nn_learn(s->rnn, s->st, src, s->route_log, st);
+    s->parity ^= 1;
+    s->rounds_done++;
+  }
+  {
+    FoldArgs fa{};
+    fa.st = s->st;
+    fa.k = s->K;
+    fa.final_fold = 1;
+    fa.alpha = s->pol.ewma_alpha;
+    fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
+    for (int j = 0; j < s->K; ++j) fa.flops[j] = s->models[j].flops;
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
+  }
+  // ordered result materialisation for this push
+  if (nwords > 0) {
+    const int nb = (int)((nwords + 255) / 256);
+    hipLaunchKernelGGL(k_res_count, dim3(nb), dim3(256), 0, st, s->result_bits, nwords, s->res_blocks);
+    hipLaunchKernelGGL(k_res_scan, dim3(1), dim3(1024), 0, st, s->res_blocks, nb, s->st, s->res_base);
+    hipLaunchKernelGGL(k_res_write, dim3(nb), dim3(256), 0, st, s->result_bits, nwords, s->res_blocks, fr.id_base,
+                       s->out_ids);
+  }
+  if (fr.where == HYDRO_MEM_HOST) HIP_TRY(hipEventRecord(s->stage_free[s->stage_next ^ 1], st));
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
+int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hydro_pred_stats* out_stats) {
+  g_err.clear();
+  if (out_ids) *out_ids = nullptr;
+  if (out_n) *out_n = 0;
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  if (!out_ids || !out_n) return fail(HYDRO_EINVAL, "out_ids / out_n is NULL");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipGetLastError());
+  DevState h;
+  HIP_TRY(hipMemcpy(&h, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  const int64_t nres = h.n_result;
+  int64_t* ids = (int64_t*)malloc(std::max<int64_t>(1, nres) * sizeof(int64_t));
+  if (!ids) return fail(HYDRO_ENOMEM, "host allocation of the result failed");
+  if (nres > 0) {
+    hipError_t he = hipMemcpy(ids, s->out_ids, nres * sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) {
+      free(ids);
+      return fail(HYDRO_EDEVICE, std::string("result copy: ") + hipGetErrorString(he));
+    }
+  }
+  if (!s->ids_sorted) std::sort(ids, ids + nres);
+  auto t1 = std::chrono::steady_clock::now();
+  s->info.n_result = nres;
+  s->info.rounds = h.rounds;
+  s->info.k = s->K;
+  s->info.learned_routed = h.learned_routed;
+  s->info.stats_routed = h.stats_routed;
+  s->info.learned_active = h.learned_active;
+  s->info.train_steps = h.train_steps;
+  s->info.elapsed_us = s->pushes ? std::chrono::duration<double, std::micro>(t1 - s->t_start).count() : 0.0;
+  if (out_stats) {
+    for (int k = 0; k < s->K; ++k) {
+      hydro_pred_stats& o = out_stats[k];
+      o.evaluated = h.t_eval[k];
+      o.passed = h.t_pass[k];
+      o.rescored = h.t_rescored[k];
+      o.escalated = h.t_esc[k];
+      o.device_us = (double)h.t_ticks[k] * s->tick_us;
+      o.cost_us_per_tuple = s->pol.cost_source == HYDRO_COST_STATIC ? h.cost_est[k] : h.cost_est[k] * s->tick_us;
+      o.selectivity = h.t_eval[k] ? (double)h.t_pass[k] / (double)h.t_eval[k] : 0.0;
+    }
+  }
+  *out_ids = ids;
+  *out_n = nres;
+  s->theta_host.clear();
+  return HYDRO_OK;
+}
+
+int hydro_session_info(const hydro_session* s, hydro_query_info* out) {
+  if (!s || !out) return fail(HYDRO_EINVAL, "NULL argument");
+  *out = s->info;
+  return HYDRO_OK;
+}
+
+int hydro_session_routes(const hydro_session* s, int64_t first_id, int64_t n, uint32_t* out) {
+  if (!s || !out) return fail(HYDRO_EINVAL, "NULL argument");
+  if (!s->route_log) return fail(HYDRO_ESTATE, "session was created without log_routes");
+  if (first_id < 0 || n < 0 || first_id + n > s->last_push_n) return fail(HYDRO_EINVAL, "range outside the last push");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy(out, s->route_log + first_id, n * 4, hipMemcpyDeviceToHost));
+  return HYDRO_OK;
+}
+
+int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hydro_frames* frames, double* out_logits) {
+  g_err.clear();
+  if (!s || !frames || !out_logits) return fail(HYDRO_EINVAL, "NULL argument");
+  if (pred < 0 || pred >= s->K) return fail(HYDRO_EINVAL, "predicate index out of range");
+  if (tier < 0 || tier > 2) return fail(HYDRO_EINVAL, "tier must be 0, 1 or 2");
+  const hydro_frames& fr = *frames;
+  if (fr.where != HYDRO_MEM_DEVICE) return fail(HYDRO_EUNSUPPORTED, "logits take device frames");
+  if (fr.n <= 0 || fr.n > s->max_push) return fail(HYDRO_ECAPACITY, "tuple count outside 1..max_push");
+  if (fr.h != s->fh || fr.w != s->fw || !fr.data) return fail(HYDRO_EINVAL, "frame shape or data");
+  int rc = ensure_dtype(s, fr.dtype);
+  if (rc) return rc;
+  hipStream_t st = s->stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  const int t = tier == 0 ? TIER_FIRST : tier == 1 ? TIER_F32 : TIER_F64;
+  // queue of every tuple for this predicate at the chosen tier
+  std::vector<uint32_t> ent(fr.n);
+  for (int64_t i = 0; i < fr.n; ++i) ent[i] = make_entry((uint32_t)i, 0u);
+  uint32_t* qbase = t == TIER_FIRST ? s->q1 : t == TIER_F32 ? s->q2 : s->q3;
+  HIP_TRY(hipMemcpy(qbase + (int64_t)pred * s->cap, ent.data(), fr.n * 4, hipMemcpyHostToDevice));
+  DevState zero{};
+  HIP_TRY(hipMemcpy(s->st, &zero, sizeof(DevState), hipMemcpyHostToDevice));
+  int cnt[kMaxK] = {0};
+  cnt[pred] = (int)fr.n;
+  int* cptr = t == TIER_FIRST ? s->st->qcount : t == TIER_F32 ? s->st->bcount : s->st->ecount;
+  HIP_TRY(hipMemcpy(cptr, cnt, sizeof(cnt), hipMemcpyHostToDevice));
+  double* dlog;
+  HIP_TRY(hipMalloc(&dlog, fr.n * kClasses * sizeof(double)));
+  FrameSrc src{fr.data, fr.dtype, fr.h, (int64_t)fr.h * fr.w * 3};
+  Forward f = make_forward(s, t, 0, src, 1, 1, 0);
+  f.logits = dlog;
+  f.defer = Queues{nullptr, nullptr, 0};
+  enqueue_tier(s, t, src, f, st);
+  hipError_t he = hipStreamSynchronize(st);
+  if (he == hipSuccess) he = hipMemcpy(out_logits, dlog, fr.n * kClasses * sizeof(double), hipMemcpyDeviceToHost);
+  hipFree(dlog);
+  if (he != hipSuccess) return fail(HYDRO_EDEVICE, std::string("logits: ") + hipGetErrorString(he));
+  // leave the session ready for a new query
+  return hydro_session_reset(s);
+}
+
+int hydro_session_destroy(hydro_session* s) {
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  free_session(s);
+  return HYDRO_OK;
+}
+
+int hydro_query(const hydro_frames* frames, const hydro_model* models, int32_t k, const float* thresholds,
+                int32_t n_seg, int64_t seg_len, const hydro_policy* policy, int64_t** out_ids, int64_t* out_n,
+                hydro_pred_stats* out_stats) {
+  if (out_ids) *out_ids = nullptr;
+  if (out_n) *out_n = 0;
+  if (!frames) return fail(HYDRO_EINVAL, "frames is NULL");
+  if (!out_ids || !out_n) return fail(HYDRO_EINVAL, "out_ids / out_n is NULL");
+  hydro_session* s = nullptr;
+  int rc = hydro_session_create(models, k, policy, frames->h, frames->w, std::max<int64_t>(1, frames->n), &s);
+  if (rc) return rc;
+  rc = hydro_session_push(s, frames, thresholds, n_seg, seg_len);
+  if (!rc) rc = hydro_session_finish(s, out_ids, out_n, out_stats);
+  std::string err = g_err;
+  hydro_session_destroy(s);
+  g_err = err;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,407 @@
+// MLP predicates on gfx950: gathered-row GEMM1 on MFMA (bf16 or fp32 operands, fp32
+// accumulation) with ReLU and a partial GEMM2 in the epilogue; a head kernel that finishes the
+// logits, takes the class-subset margin and forwards the decision; and an FP64 tier.
+//
+// The model (one synthetic UDF predicate): h = ReLU(x' W1 + b1), z = h W2 + b2 with
+// x' = (x - 0.5) * 4 flattened NHWC.  The first two passes use the folded form
+// h = ReLU((s W1)^T raw + (b1 - 2 colsum(W1))) with s = 4 (or 4/255 for uint8 frames), which is
+// the same function of the stored frame without a separate normalisation step.
+#include "engine.h"
+
+namespace hydro {
+
+constexpr int MLP_BM = 128, MLP_BN = 128;
+
+template <typename T> struct MlpTile;
+template <> struct MlpTile<__bf16> { static constexpr int BK = 32, LD = 40; };   // LDS row stride (elements)
+template <> struct MlpTile<float> { static constexpr int BK = 16, LD = 20; };
+
+// Load `N` consecutive frame elements starting at element `off` of frame `idx`, converted to T.
+template <typename T, int N>
+__device__ inline void load_frame_run(const FrameSrc& fr, uint32_t idx, int64_t off, T* out) {
+  const int64_t base = (int64_t)idx * fr.elems + off;
+  if (fr.dtype == HYDRO_DTYPE_BF16) {
+    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const __bf16*>(fr.base) + base);
+#pragma unroll
+    for (int v = 0; v < N / 8; ++v) {
+      uint4 u = p[v];
+      const __bf16* b = reinterpret_cast<const __bf16*>(&u);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) out[v * 8 + j] = static_cast<T>(b[j]);
+    }
+  } else if (fr.dtype == HYDRO_DTYPE_U8) {
+    const uint8_t* p = static_cast<const uint8_t*>(fr.base) + base;
+    if constexpr (N == 16) {
+      uint4 u = *reinterpret_cast<const uint4*>(p);
+      const uint8_t* b = reinterpret_cast<const uint8_t*>(&u);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) out[j] = static_cast<T>((float)b[j]);
+    } else {
+      uint2 u = *reinterpret_cast<const uint2*>(p);
+      const uint8_t* b = reinterpret_cast<const uint8_t*>(&u);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) out[j] = static_cast<T>((float)b[j]);
+    }
+  } else {
+    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(fr.base) + base);
+#pragma unroll
+    for (int v = 0; v < N / 4; ++v) {
+      float4 f = p[v];
+      out[v * 4 + 0] = static_cast<T>(f.x);
+      out[v * 4 + 1] = static_cast<T>(f.y);
+      out[v * 4 + 2] = static_cast<T>(f.z);
+      out[v * 4 + 3] = static_cast<T>(f.w);
+    }
+  }
+}
+
+// Decode a persistent-loop tile index into (predicate slot, m tile, n tile).
+__device__ inline bool mlp_decode_tile(const MlpArgs& a, int t, int& slot, int& mt, int& nt) {
+  int acc = 0;
+  for (int i = 0; i < a.n_preds; ++i) {
+    int k = a.pred[i];
+    int cnt = a.q.counts[k];
+    int n_mt = (cnt + MLP_BM - 1) / MLP_BM;
+    int n_nt = a.hidden[i] / MLP_BN;
+    int tiles = n_mt * n_nt;
+    if (t < acc + tiles) {
+      int local = t - acc;
+      slot = i;
+      mt = local / n_nt;
+      nt = local % n_nt;
+      return true;
+    }
+    acc += tiles;
+  }
+  return false;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
+  constexpr int BK = MlpTile<T>::BK, LD = MlpTile<T>::LD;
+  constexpr int PER = BK / 2;                     // elements each thread loads per row and k-tile
+  __shared__ __attribute__((aligned(16))) T As[2][MLP_BM * LD];
+  __shared__ __attribute__((aligned(16))) T Bs[2][MLP_BN * LD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = tid >> 1, lk = (tid & 1) * PER;  // this thread's load row and k offset
+
+  // total tiles of this launch
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) {
+    int cnt = a.q.counts[a.pred[i]];
+    total += ((cnt + MLP_BM - 1) / MLP_BM) * (a.hidden[i] / MLP_BN);
+  }
+
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot, mt, nt;
+    mlp_decode_tile(a, t, slot, mt, nt);
+    const int k = a.pred[slot];
+    const int cnt = a.q.counts[k];
+    const int D = a.d_in[slot];
+    const uint32_t* qe = a.q.entries + (int64_t)k * a.q.cap;
+    unsigned long long t0 = wall_clock64();
+
+    int row = mt * MLP_BM + lr;
+    uint32_t idx = entry_idx(qe[row < cnt ? row : cnt - 1]);
+    const T* wrow;
+    if constexpr (sizeof(T) == 2) wrow = reinterpret_cast<const T*>(a.w1_bf[slot]) + (int64_t)(nt * MLP_BN + lr) * D;
+    else wrow = reinterpret_cast<const T*>(a.w1_f32[slot]) + (int64_t)(nt * MLP_BN + lr) * D;
+
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+
+    alignas(16) T ra[PER];
+    alignas(16) T rb[PER];
+    auto gload = [&](int kt) {
+      load_frame_run<T, PER>(a.fr, idx, (int64_t)kt * BK + lk, ra);
+      const uint4* pb = reinterpret_cast<const uint4*>(wrow + (int64_t)kt * BK + lk);
+#pragma unroll
+      for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb)[v] = pb[v];
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) {
+        reinterpret_cast<uint4*>(&As[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(ra)[v];
+        reinterpret_cast<uint4*>(&Bs[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(rb)[v];
+      }
+    };
+
+    const int nk = D / BK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload(kt + 1);
+      if constexpr (sizeof(T) == 2) {
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm * 64 + i * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+          bfr[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn * 64 + i * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+          float af[4], bfr[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            af[i] = As[buf][(wm * 64 + i * 16 + (lane & 15)) * LD + ks * 4 + (lane >> 4)];
+            bfr[i] = Bs[buf][(wn * 64 + i * 16 + (lane & 15)) * LD + ks * 4 + (lane >> 4)];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      if (kt + 1 < nk) {
+        __syncthreads();
+        lstore(buf ^ 1);
+        __syncthreads();
+      }
+    }
+
+    // epilogue: H = ReLU(acc + b1'), partial logits over this wave's 64 hidden columns
+    const float* b1 = a.b1_fold[slot];
+    const float* w2 = a.w2[slot];
+    const int col0 = nt * MLP_BN + wn * 64 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float bb = b1[col0 + j * 16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = fmaxf(acc[i][j][r] + bb, 0.f);
+    }
+    float* part = a.partial[slot] + ((int64_t)(nt * 2 + wn) * a.part_cap) * kClasses;
+    for (int c = 0; c < kClasses; ++c) {
+      float w2v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w2v[j] = w2[(col0 + j * 16) * kClasses + c];
+      float v[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float s = 0.f;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) s += acc[i][j][r] * w2v[j];
+          v[i][r] = s;
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float s = v[i][r];
+          s += __shfl_xor(s, 1);
+          s += __shfl_xor(s, 2);
+          s += __shfl_xor(s, 4);
+          s += __shfl_xor(s, 8);
+          v[i][r] = s;
+        }
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int rr = mt * MLP_BM + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+            if (rr < cnt) part[(int64_t)rr * kClasses + c] = v[i][r];
+          }
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
+  }
+}
+
+// Head: z = b2 + sum of partial logits; margin; decision / deferral; forwarding.
+__global__ __launch_bounds__(256) void mlp_head_kernel(MlpArgs a, Forward f) {
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
+    int g = base + threadIdx.x;
+    bool active = g < total;
+    // find predicate slot (uniform work per lane; K <= 8)
+    int slot = 0, off = g;
+    for (int i = 0; i < a.n_preds; ++i) {
+      int c = a.q.counts[a.pred[i]];
+      if (off < c || i == a.n_preds - 1) { slot = i; break; }
+      off -= c;
+    }
+    int k = a.pred[slot];
+    uint32_t e = 0;
+    bool pass = false, defer = false;
+    if (active) {
+      e = a.q.entries[(int64_t)k * a.q.cap + off];
+      float z[kClasses];
+      const float* b2 = a.b2[slot];
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) z[c] = b2[c];
+      const int parts = a.hidden[slot] / 64;
+      const float* part = a.partial[slot];
+      for (int p = 0; p < parts; ++p) {
+        const float* pp = part + ((int64_t)p * a.part_cap + off) * kClasses;
+#pragma unroll
+        for (int c = 0; c < kClasses; ++c) z[c] += pp[c];
+      }
+      if (f.logits != nullptr) {
+        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)entry_idx(e) * kClasses + c] = (double)z[c];
+        continue;
+      }
+      float d = class_margin(z, a.class_mask[slot]);
+      float th = theta_of(f, k, entry_idx(e));
+      float gap = d - th;
+      defer = f.defer.entries != nullptr && fabsf(gap) < f.tau;
+      pass = d > th;
+    }
+    if (f.logits != nullptr) continue;
+    // all lanes of every wave reach this point; k differs per lane only at predicate seams,
+    // so forward per distinct k present in the wave
+    for (int i = 0; i < a.n_preds; ++i) {
+      int kk = a.pred[i];
+      if (__ballot(active && k == kk) == 0) continue;
+      forward_decision(f, kk, e, active && k == kk, defer, pass);
+    }
+  }
+}
+
+// FP64 tier: up to 8 entries of one predicate per work item; frames normalised in fp64
+// exactly as the definition states; canonical fp32 weights widened to fp64.
+constexpr int F64_B = 4;
+constexpr int F64_DCH = 256;
+
+__global__ __launch_bounds__(256) void mlp_f64_kernel(MlpArgs a, Forward f) {
+  __shared__ double xs[F64_B][F64_DCH];
+  __shared__ double zred[4][F64_B][kClasses];
+  __shared__ uint32_t ents[F64_B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += (a.q.counts[a.pred[i]] + F64_B - 1) / F64_B;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      int c = (a.q.counts[a.pred[i]] + F64_B - 1) / F64_B;
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    const int k = a.pred[slot];
+    const int cnt = a.q.counts[k];
+    const int D = a.d_in[slot], H = a.hidden[slot];
+    const int nb = min(F64_B, cnt - off * F64_B);
+    if (tid < F64_B) ents[tid] = tid < nb ? a.q.entries[(int64_t)k * a.q.cap + off * F64_B + tid] : 0u;
+    __syncthreads();
+    constexpr int JMAX = 8;            // hidden units per thread (H <= 2048)
+    double s[JMAX][F64_B];
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j)
+#pragma unroll
+      for (int b = 0; b < F64_B; ++b) s[j][b] = 0.0;
+    const float* W1 = a.w1_canon[slot];
+    for (int d0 = 0; d0 < D; d0 += F64_DCH) {
+      for (int q = tid; q < F64_B * F64_DCH; q += blockDim.x) {
+        int b = q / F64_DCH, dd = q % F64_DCH;
+        double x = 0.0;
+        if (b < nb && d0 + dd < D) {
+          int64_t o = (int64_t)entry_idx(ents[b]) * a.fr.elems + d0 + dd;
+          if (a.fr.dtype == HYDRO_DTYPE_BF16) x = (double)(float)static_cast<const __bf16*>(a.fr.base)[o];
+          else if (a.fr.dtype == HYDRO_DTYPE_U8) x = (double)static_cast<const uint8_t*>(a.fr.base)[o] / 255.0;
+          else x = (double)static_cast<const float*>(a.fr.base)[o];
+          x = (x - 0.5) * 4.0;
+        }
+        xs[b][dd] = x;
+      }
+      __syncthreads();
+      const int dlim = min(F64_DCH, D - d0);
+      for (int dd = 0; dd < dlim; ++dd) {
+        const float* wr = W1 + (int64_t)(d0 + dd) * H;
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j) {
+          int col = tid + j * 256;
+          if (col < H) {
+            double w = (double)wr[col];
+#pragma unroll
+            for (int b = 0; b < F64_B; ++b) s[j][b] = fma(w, xs[b][dd], s[j][b]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // h = ReLU(s + b1); z partial = h W2
+    double zp[F64_B][kClasses];
+#pragma unroll
+    for (int b = 0; b < F64_B; ++b)
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) zp[b][c] = 0.0;
+    const float* b1 = a.b1_canon[slot];
+    const float* w2 = a.w2[slot];
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+      int col = tid + j * 256;
+      if (col < H) {
+        double bb = (double)b1[col];
+#pragma unroll
+        for (int b = 0; b < F64_B; ++b) {
+          double h = s[j][b] + bb;
+          h = h > 0.0 ? h : 0.0;
+#pragma unroll
+          for (int c = 0; c < kClasses; ++c) zp[b][c] = fma(h, (double)w2[col * kClasses + c], zp[b][c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < F64_B; ++b)
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) {
+        double v = zp[b][c];
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) zred[wave][b][c] = v;
+      }
+    __syncthreads();
+    if (wave == 0) {
+      bool active = lane < nb;
+      bool pass = false;
+      uint32_t e = active ? ents[lane] : 0u;
+      if (active) {
+        double z[kClasses];
+        const float* b2 = a.b2[slot];
+        for (int c = 0; c < kClasses; ++c)
+          z[c] = (double)b2[c] + ((zred[0][lane][c] + zred[1][lane][c]) + (zred[2][lane][c] + zred[3][lane][c]));
+        if (f.logits != nullptr)
+          for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)entry_idx(e) * kClasses + c] = z[c];
+        double d = class_margin(z, a.class_mask[slot]);
+        pass = d > (double)theta_of(f, k, entry_idx(e));
+      }
+      if (f.logits == nullptr) forward_decision(f, k, e, active, false, pass);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
+  if (a.n_preds == 0) return;
+  if (tier == TIER_F64) {
+    hipLaunchKernelGGL(mlp_f64_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    return;
+  }
+  if (a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)
+    hipLaunchKernelGGL(mlp_gemm_kernel<__bf16>, dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(mlp_gemm_kernel<float>, dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(mlp_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
+}
+
+}  // namespace hydro

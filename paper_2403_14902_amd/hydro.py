@@ -1,0 +1,302 @@
+"""ctypes binding of libhydro.so (the gfx950 engine declared in include/hydro.h).
+
+Argument marshalling only: every step of the query runs in the library's HIP kernels.
+torch is used for device memory (frames may be CUDA/HIP tensors) and streams.  The binding
+raises if the library has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+
+MAX_PREDICATES = 8
+MAX_LAYERS = 4
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ECAPACITY, ESTATE = 0, -1, -2, -3, -4, -5, -6
+DTYPE_F32, DTYPE_BF16, DTYPE_U8 = 0, 1, 2
+MEM_DEVICE, MEM_HOST = 0, 1
+ARCH_MLP, ARCH_CNN = 0, 1
+ROUTE_FIXED, ROUTE_SEL, ROUTE_SCORE, ROUTE_COST, ROUTE_LEARNED = 0, 1, 2, 3, 4
+PREC_FP32, PREC_BF16 = 0, 1
+COST_MEASURED, COST_STATIC = 0, 1
+
+ROUTES = {"fixed": ROUTE_FIXED, "selectivity": ROUTE_SEL, "score": ROUTE_SCORE, "cost": ROUTE_COST,
+          "learned": ROUTE_LEARNED}
+PRECISIONS = {"fp32": PREC_FP32, "bf16": PREC_BF16}
+DTYPES = {"f32": DTYPE_F32, "bf16": DTYPE_BF16, "u8": DTYPE_U8}
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hydro status {code}: {msg}")
+        self.code = code
+
+
+class Frames(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("where", C.c_int32), ("n", C.c_int64),
+                ("h", C.c_int32), ("w", C.c_int32), ("id_base", C.c_int64)]
+
+
+FP = C.POINTER(C.c_float)
+
+
+class Model(C.Structure):
+    _fields_ = [("arch", C.c_int32), ("in_h", C.c_int32), ("in_w", C.c_int32), ("hidden", C.c_int32),
+                ("w1", FP), ("b1", FP), ("w2", FP), ("b2", FP),
+                ("n_layers", C.c_int32), ("widths", C.c_int32 * MAX_LAYERS),
+                ("conv_w", FP * MAX_LAYERS), ("conv_b", FP * MAX_LAYERS),
+                ("fc_w", FP), ("fc_b", FP), ("class_mask", C.c_uint32)]
+
+
+class Policy(C.Structure):
+    _fields_ = [("route", C.c_int32), ("order", C.c_int32 * MAX_PREDICATES), ("routing_batch", C.c_int32),
+                ("wave", C.c_int32), ("warmup_batches", C.c_int32), ("ewma_alpha", C.c_float),
+                ("cost_source", C.c_int32), ("precision", C.c_int32), ("tau", C.c_float), ("tau32", C.c_float),
+                ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
+                ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class PredStats(C.Structure):
+    _fields_ = [("evaluated", C.c_uint64), ("passed", C.c_uint64), ("rescored", C.c_uint64),
+                ("escalated", C.c_uint64), ("device_us", C.c_double), ("cost_us_per_tuple", C.c_double),
+                ("selectivity", C.c_double)]
+
+
+class QueryInfo(C.Structure):
+    _fields_ = [("n_tuples", C.c_uint64), ("n_result", C.c_uint64), ("rounds", C.c_uint32), ("k", C.c_uint32),
+                ("learned_routed", C.c_uint64), ("stats_routed", C.c_uint64), ("learned_active", C.c_uint32),
+                ("train_steps", C.c_uint32), ("elapsed_us", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhydro.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2403_14902_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.hydro_policy_default.argtypes = [C.POINTER(Policy)]
+        L.hydro_policy_default.restype = None
+        L.hydro_query.argtypes = [C.POINTER(Frames), C.POINTER(Model), i32, FP, i32, i64, C.POINTER(Policy),
+                                  C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.c_int64), C.POINTER(PredStats)]
+        L.hydro_session_create.argtypes = [C.POINTER(Model), i32, C.POINTER(Policy), i32, i32, i64, C.POINTER(vp)]
+        L.hydro_session_reset.argtypes = [vp]
+        L.hydro_session_push.argtypes = [vp, C.POINTER(Frames), FP, i32, i64]
+        L.hydro_session_finish.argtypes = [vp, C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.c_int64),
+                                           C.POINTER(PredStats)]
+        L.hydro_session_info.argtypes = [vp, C.POINTER(QueryInfo)]
+        L.hydro_session_routes.argtypes = [vp, i64, i64, C.POINTER(C.c_uint32)]
+        L.hydro_session_logits.argtypes = [vp, i32, i32, C.POINTER(Frames), C.POINTER(C.c_double)]
+        L.hydro_session_destroy.argtypes = [vp]
+        L.hydro_free.argtypes = [vp]
+        L.hydro_free.restype = None
+        L.hydro_last_error.restype = C.c_char_p
+        L.hydro_version.restype = C.c_char_p
+        for name in ("hydro_query", "hydro_session_create", "hydro_session_reset", "hydro_session_push",
+                     "hydro_session_finish", "hydro_session_info", "hydro_session_routes", "hydro_session_logits",
+                     "hydro_session_destroy"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_session_create", "hydro_session_reset",
+            "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
+            "hydro_session_logits", "hydro_session_destroy", "hydro_free", "hydro_last_error", "hydro_version")
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise HydroError(rc, lib().hydro_last_error().decode())
+
+
+def _fp(a: Optional[np.ndarray]):
+    if a is None:
+        return FP()
+    return a.ctypes.data_as(FP)
+
+
+class ModelSpec:
+    """A predicate model held as contiguous fp32 numpy arrays (kept alive by this object)."""
+
+    def __init__(self, arch: str, in_hw: int, class_mask: int, tensors: dict, hidden: int = 0,
+                 widths: Sequence[int] = ()):
+        self.arch, self.in_hw, self.class_mask = arch, in_hw, int(class_mask)
+        self.hidden, self.widths = hidden, tuple(widths)
+        f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+        if arch == "mlp":
+            self.t = {k: f32(tensors[k]) for k in ("W1", "b1", "W2", "b2")}
+        else:
+            self.t = {"convs": [(f32(w), f32(b)) for w, b in tensors["convs"]],
+                      "Wfc": f32(tensors["Wfc"]), "bfc": f32(tensors["bfc"])}
+
+    @classmethod
+    def from_weights(cls, weights, class_mask: int) -> "ModelSpec":
+        """From a ``hydro_synth.ModelWeights``."""
+        d = weights.desc
+        if d.arch == "mlp":
+            hw = int(round((d.d_in / 3) ** 0.5))
+            return cls("mlp", hw, class_mask, weights.tensors, hidden=d.hidden)
+        return cls("cnn", d.in_hw, class_mask, weights.tensors, widths=d.widths)
+
+    def to_c(self) -> Model:
+        m = Model()
+        m.in_h = m.in_w = self.in_hw
+        m.class_mask = self.class_mask
+        if self.arch == "mlp":
+            m.arch = ARCH_MLP
+            m.hidden = self.hidden
+            m.w1, m.b1, m.w2, m.b2 = (_fp(self.t[k]) for k in ("W1", "b1", "W2", "b2"))
+        else:
+            m.arch = ARCH_CNN
+            m.n_layers = len(self.widths)
+            for i, w in enumerate(self.widths):
+                m.widths[i] = w
+                m.conv_w[i] = _fp(self.t["convs"][i][0])
+                m.conv_b[i] = _fp(self.t["convs"][i][1])
+            m.fc_w, m.fc_b = _fp(self.t["Wfc"]), _fp(self.t["bfc"])
+        return m
+
+
+def make_policy(route: str = "score", order: Optional[Sequence[int]] = None, precision: str = "bf16",
+                **kw) -> Policy:
+    p = Policy()
+    lib().hydro_policy_default(C.byref(p))
+    p.route = ROUTES[route] if isinstance(route, str) else int(route)
+    if order is not None:
+        for i, o in enumerate(order):
+            p.order[i] = int(o)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for k, v in kw.items():
+        if k == "cost_source" and isinstance(v, str):
+            v = COST_STATIC if v == "static" else COST_MEASURED
+        setattr(p, k, v)
+    return p
+
+
+def _frames_struct(frames, dtype: str, id_base: int) -> Frames:
+    fr = Frames()
+    fr.dtype = DTYPES[dtype]
+    fr.id_base = int(id_base)
+    if hasattr(frames, "data_ptr"):          # torch tensor
+        assert frames.is_contiguous(), "frames must be contiguous"
+        fr.data = frames.data_ptr()
+        fr.where = MEM_DEVICE if frames.is_cuda else MEM_HOST
+        shape = tuple(frames.shape)
+    else:
+        assert frames.flags["C_CONTIGUOUS"], "frames must be contiguous"
+        fr.data = frames.ctypes.data
+        fr.where = MEM_HOST
+        shape = frames.shape
+    if len(shape) != 4 or shape[3] != 3:
+        raise HydroError(EINVAL, f"frames must be [n, h, w, 3], got {shape}")
+    fr.n, fr.h, fr.w = shape[0], shape[1], shape[2]
+    return fr
+
+
+def _stats_list(st, k) -> List[Dict]:
+    return [{f: getattr(st[i], f) for f, _ in PredStats._fields_} for i in range(k)]
+
+
+class Session:
+    """A query session: models are uploaded once; each query is pushes + finish."""
+
+    def __init__(self, models: Sequence[ModelSpec], policy: Policy, frame_hw: int, max_push: int):
+        self.models = list(models)
+        self.k = len(self.models)
+        self._cm = (Model * self.k)(*[m.to_c() for m in self.models])
+        self.policy = policy
+        self._h = C.c_void_p()
+        self._keep = []
+        _check(lib().hydro_session_create(self._cm, self.k, C.byref(policy), frame_hw, frame_hw, int(max_push),
+                                          C.byref(self._h)))
+
+    def reset(self):
+        self._keep = []
+        _check(lib().hydro_session_reset(self._h))
+
+    def push(self, frames, dtype: str, thresholds: np.ndarray, seg_len: int, id_base: int = 0):
+        th = np.ascontiguousarray(thresholds, dtype=np.float32)
+        if th.ndim == 1:
+            th = th[None, :]
+        fr = _frames_struct(frames, dtype, id_base)
+        self._keep.append((frames, th))
+        _check(lib().hydro_session_push(self._h, C.byref(fr), _fp(th), th.shape[0], int(seg_len)))
+
+    def finish(self):
+        ptr = C.POINTER(C.c_int64)()
+        n = C.c_int64()
+        st = (PredStats * self.k)()
+        _check(lib().hydro_session_finish(self._h, C.byref(ptr), C.byref(n), st))
+        ids = np.ctypeslib.as_array(ptr, shape=(n.value,)).copy() if n.value > 0 else np.zeros(0, np.int64)
+        lib().hydro_free(ptr)
+        self._keep = []
+        return ids, _stats_list(st, self.k)
+
+    def info(self) -> Dict:
+        q = QueryInfo()
+        _check(lib().hydro_session_info(self._h, C.byref(q)))
+        return {f: getattr(q, f) for f, _ in QueryInfo._fields_}
+
+    def routes(self, first: int, n: int) -> np.ndarray:
+        out = np.zeros(n, dtype=np.uint32)
+        _check(lib().hydro_session_routes(self._h, first, n, out.ctypes.data_as(C.POINTER(C.c_uint32))))
+        return out
+
+    def logits(self, pred: int, tier: int, frames, dtype: str) -> np.ndarray:
+        fr = _frames_struct(frames, dtype, 0)
+        out = np.zeros((fr.n, 10), dtype=np.float64)
+        _check(lib().hydro_session_logits(self._h, pred, tier, C.byref(fr),
+                                          out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().hydro_session_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def query(frames, dtype: str, models: Sequence[ModelSpec], thresholds: np.ndarray, seg_len: int,
+          policy: Policy, id_base: int = 0):
+    """One-shot query through hydro_query."""
+    cm = (Model * len(models))(*[m.to_c() for m in models])
+    th = np.ascontiguousarray(thresholds, dtype=np.float32)
+    if th.ndim == 1:
+        th = th[None, :]
+    fr = _frames_struct(frames, dtype, id_base)
+    ptr = C.POINTER(C.c_int64)()
+    n = C.c_int64()
+    st = (PredStats * len(models))()
+    _check(lib().hydro_query(C.byref(fr), cm, len(models), _fp(th), th.shape[0], int(seg_len), C.byref(policy),
+                             C.byref(ptr), C.byref(n), st))
+    ids = np.ctypeslib.as_array(ptr, shape=(n.value,)).copy() if n.value > 0 else np.zeros(0, np.int64)
+    lib().hydro_free(ptr)
+    return ids, _stats_list(st, len(models))
+
+
+def decode_routes(codes: np.ndarray) -> List[List[int]]:
+    """Per-tuple visit sequences from the packed route log."""
+    out = []
+    for c in codes.tolist():
+        seq = []
+        while c:
+            seq.append((c & 15) - 1)
+            c >>= 4
+        out.append(seq)
+    return out

@@ -1,0 +1,131 @@
+"""GPU parity of the MLP path (small MLP workload: 2,048 frames 32x32x3 fp32, two MLP
+3072-256-10 predicates) against the FP64 oracle, through the C ABI."""
+import itertools
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import case, check_stats, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2403_14902_amd import hydro  # noqa: E402
+from oracle import hydro_oracle as ho  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return case(1, 2048, logits=True)
+
+
+def _session(c, policy, max_push=None):
+    return hydro.Session(c.specs(), policy, c.cfg.hw, max_push or c.n)
+
+
+@pytest.mark.parametrize("prec,tier,tol", [("fp32", 0, 2e-4), ("bf16", 0, 0.08), ("bf16", 1, 2e-4), ("fp32", 2, 1e-10)])
+def test_logits_each_tier_vs_oracle(c1, prec, tier, tol):
+    log(f"[gpu] logits prec={prec} tier={tier}")
+    s = _session(c1, hydro.make_policy("score", precision=prec))
+    dev = c1.device_frames()
+    for k in range(c1.cfg.k):
+        z = s.logits(k, tier, dev, c1.cfg.dtype)
+        err = np.abs(z - c1.Z[k]).max()
+        log(f"  predicate {k}: max |z - z64| = {err:.3e}")
+        assert err <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("order", list(itertools.permutations(range(2))))
+def test_fixed_order_ids_and_exact_counts(c1, prec, order):
+    log(f"[gpu] fixed order {order} prec={prec}")
+    pol = hydro.make_policy("fixed", order=order, precision=prec, wave=512, log_routes=1)
+    s = _session(c1, pol)
+    s.push(c1.device_frames(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c1.expect)
+    _, ev, ps = ho.short_circuit_eval(c1.P, order)
+    assert [st["evaluated"] for st in stats] == list(ev)
+    assert [st["passed"] for st in stats] == list(ps)
+    routes = hydro.decode_routes(s.routes(0, c1.n))
+    ok, rev, rps, out, msg = ho.replay_route(c1.P, routes)
+    assert ok, msg
+    assert np.array_equal(out, c1.expect)
+    s.close()
+
+
+@pytest.mark.parametrize("route", ["score", "selectivity", "cost"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_adaptive_policies_ids_stats_and_replay(c1, route, prec):
+    log(f"[gpu] route={route} prec={prec}")
+    pol = hydro.make_policy(route, precision=prec, wave=256, log_routes=1)
+    s = _session(c1, pol)
+    s.push(c1.device_frames(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c1.expect)
+    check_stats(stats, c1.n, ids.size)
+    routes = hydro.decode_routes(s.routes(0, c1.n))
+    ok, rev, rps, out, msg = ho.replay_route(c1.P, routes)
+    assert ok, msg
+    assert [st["evaluated"] for st in stats] == list(rev)
+    assert [st["passed"] for st in stats] == list(rps)
+    info = s.info()
+    assert info["n_result"] == ids.size and info["rounds"] > 0
+    s.close()
+
+
+def test_one_shot_query_and_host_frames(c1):
+    pol = hydro.make_policy("score", precision="bf16", wave=1000)
+    ids, stats = hydro.query(c1.device_frames(), c1.cfg.dtype, c1.specs(), c1.pt.thresholds, c1.seg_len, pol)
+    assert np.array_equal(ids, c1.expect)
+    ids2, _ = hydro.query(c1.frames, c1.cfg.dtype, c1.specs(), c1.pt.thresholds, c1.seg_len, pol)
+    assert np.array_equal(ids2, c1.expect)
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 1000])
+def test_ragged_and_empty_pushes(c1, n):
+    pol = hydro.make_policy("score", precision="bf16", wave=100)
+    s = _session(c1, pol, max_push=2048)
+    if n > 0:
+        s.push(c1.device_frames()[:n].contiguous(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    else:
+        s.push(c1.device_frames()[:0], c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c1.expect[c1.expect < n])
+    s.close()
+
+
+def test_several_pushes_one_query(c1):
+    pol = hydro.make_policy("score", precision="bf16", wave=300)
+    s = _session(c1, pol, max_push=700)
+    dev = c1.device_frames()
+    for lo in range(0, c1.n, 700):
+        hi = min(c1.n, lo + 700)
+        s.push(dev[lo:hi].contiguous(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len, id_base=lo)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c1.expect)
+    check_stats(stats, c1.n, ids.size)
+    # the session can run a second query after reset
+    s.reset()
+    s.push(dev[:700].contiguous(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, _ = s.finish()
+    assert np.array_equal(ids, c1.expect[c1.expect < 700])
+    s.close()
+
+
+def test_threshold_extremes(c1):
+    pol = hydro.make_policy("score", precision="bf16", wave=512)
+    inf = np.full_like(c1.pt.thresholds, np.inf)
+    ids, stats = hydro.query(c1.device_frames(), c1.cfg.dtype, c1.specs(), inf, c1.seg_len, pol)
+    assert ids.size == 0
+    ids, stats = hydro.query(c1.device_frames(), c1.cfg.dtype, c1.specs(), -inf, c1.seg_len, pol)
+    assert np.array_equal(ids, np.arange(c1.n))
+
+
+def test_capacity_error(c1):
+    s = _session(c1, hydro.make_policy(), max_push=100)
+    with pytest.raises(hydro.HydroError) as e:
+        s.push(c1.device_frames()[:200].contiguous(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    assert e.value.code == hydro.ECAPACITY
+    s.close()
