@@ -1,17 +1,551 @@
-// CNN predicates (placeholder until the fused kernels land).
+// CNN predicates on gfx950: one fused kernel evaluates conv3x3/s2 x3 + ReLU, global average
+// pooling, FC and the class-subset decision for a frame entirely in LDS and registers.
+//
+// Model (synthetic UDF): 64x64x3 frame -> conv(16m) -> conv(32m) -> conv(64m) -> mean over 8x8 ->
+// FC 10, m in {1, 2, 4}; every conv has stride 2, zero padding 1 (in normalised space), ReLU.
+//
+// Per frame, one workgroup (4 wave64s):
+//   FR   the raw frame in LDS as bf16 (exact for bf16 and uint8 inputs), 4 channels (the 4th is 0),
+//        with a one-pixel top/left border holding the raw value that normalises to zero.
+//        Layer 1 uses the folded form sW * raw + (b - 2 sum W), so no normalisation pass runs.
+//   S1   one 16-channel slab of layer-1 output (all 32x32 positions);
+//   ACC2 layer-2 accumulators for all 16x16 positions and all 32m channels stay in registers while
+//        the m slabs of layer 1 stream through S1 (layer 2's K loop runs slab by slab), so
+//        layer 1's full output never needs to fit in LDS and every layer-2 weight is read once
+//        per frame;
+//   L2   layer-2 output (bias + ReLU) written over FR/S1 once all slabs are consumed;
+//   ACC3 layer-3 accumulators (64 positions x 64m channels) in registers; their ReLU is summed
+//        straight into the pooled vector, then FC, margin and decision.
+// Convolutions are implicit GEMMs on MFMA: M = output positions, N = output channels,
+// K = (tap, input channel).  Weights are pre-packed in MFMA-fragment order so each lane reads
+// one contiguous run per fragment.
 #include "engine.h"
 
 namespace hydro {
 
+template <typename T> struct Mf;
+template <> struct Mf<__bf16> {
+  static constexpr int KSTEP = 32, KPL = 8;
+  typedef bf16x8 frag;
+};
+template <> struct Mf<float> {
+  static constexpr int KSTEP = 4, KPL = 1;
+  typedef float frag;
+};
+
+__device__ inline floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx4 mfma(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline typename Mf<T>::frag ld_frag(const T* p) {
+  if constexpr (sizeof(T) == 2) return *reinterpret_cast<const bf16x8*>(p);
+  else return *p;
+}
+
+// geometry
+constexpr int H0 = 64, H1 = 32, H2 = 16, H3 = 8;
+constexpr int FR_W = H0 + 1;        // frame row stride in pixels (top/left border)
+constexpr int S1_W = H1 + 1;
+constexpr int L2_W = H2 + 1;
+constexpr int CB1 = 16;             // layer-1 channels per slab
+
+template <typename T> struct CnnLds {
+  static constexpr int FR_BYTES = FR_W * FR_W * 4 * 2;
+  static constexpr int S1_OFF = (FR_BYTES + 15) / 16 * 16;
+  static constexpr int S1_BYTES = S1_W * S1_W * CB1 * (int)sizeof(T);
+  static constexpr int L2_BYTES_MAX = L2_W * L2_W * 128 * (int)sizeof(T);
+  static constexpr int REGION = (S1_OFF + S1_BYTES) > L2_BYTES_MAX ? (S1_OFF + S1_BYTES) : L2_BYTES_MAX;
+};
+
+constexpr int DBUF = 64;
+
+// packed-layer geometry: [slab][kstep][ntile][64][KPL]
+template <typename T>
+__host__ __device__ constexpr int cnn_ksteps(int layer, int m) {
+  return layer == 0 ? (36 + Mf<T>::KSTEP - 1) / Mf<T>::KSTEP
+       : layer == 1 ? (9 * CB1 + Mf<T>::KSTEP - 1) / Mf<T>::KSTEP
+                    : 9 * 32 * m / Mf<T>::KSTEP;
+}
+__host__ __device__ constexpr int cnn_slabs(int layer, int m) { return layer == 2 ? 1 : m; }
+__host__ __device__ constexpr int cnn_ntiles(int layer, int m) { return layer == 0 ? 1 : layer == 1 ? 2 * m : 4 * m; }
+
+struct CnnShared {
+  float gbuf[256];
+  float z[kClasses];
+  uint32_t d_e[DBUF];
+  uint8_t d_k[DBUF];
+  uint8_t d_f[DBUF];
+  int d_n;
+  unsigned long long ticks[kMaxK];
+};
+
+template <typename T>
+__device__ void flush_decisions(const Forward& f, CnnShared& sh, int k_total_slots, const int* pred) {
+  // called by all threads; wave 0 forwards
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int n = sh.d_n;
+    bool active = lane < n;
+    uint32_t e = active ? sh.d_e[lane] : 0u;
+    int k = active ? (int)sh.d_k[lane] : -1;
+    uint8_t fl = active ? sh.d_f[lane] : 0;
+    for (int i = 0; i < k_total_slots; ++i) {
+      int kk = pred[i];
+      if (__ballot(active && k == kk) == 0) continue;
+      forward_decision(f, kk, e, active && k == kk, (fl & 2) != 0, (fl & 1) != 0);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sh.d_n = 0;
+  __syncthreads();
+}
+
+// One frame through the network.  Returns (in sh.z, valid after the final barrier) the logits.
+template <typename T, int M>
+__device__ void cnn_frame(const CnnArgs& a, int slot, uint32_t idx, unsigned char* region, CnnShared& sh) {
+  constexpr int C1 = 16 * M, C2 = 32 * M, C3 = 64 * M;
+  constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
+  typedef typename Mf<T>::frag frag;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+
+  __bf16* FR = reinterpret_cast<__bf16*>(region);
+  T* S1 = reinterpret_cast<T*>(region + CnnLds<T>::S1_OFF);
+  T* L2 = reinterpret_cast<T*>(region);
+
+  // ---- frame -> FR (raw values, 4th channel 0, border = pad_raw)
+  {
+    const __bf16 padv = static_cast<__bf16>(a.pad_raw);
+    const __bf16 zero = static_cast<__bf16>(0.f);
+    const int64_t base = (int64_t)idx * a.fr.elems;
+    for (int p = tid; p < H0 * H0; p += 256) {
+      const int y = p >> 6, x = p & 63;
+      __bf16 c0, c1, c2;
+      if (a.fr.dtype == HYDRO_DTYPE_BF16) {
+        const __bf16* src = static_cast<const __bf16*>(a.fr.base) + base + p * 3;
+        c0 = src[0]; c1 = src[1]; c2 = src[2];
+      } else {
+        const uint8_t* src = static_cast<const uint8_t*>(a.fr.base) + base + p * 3;
+        c0 = static_cast<__bf16>((float)src[0]);
+        c1 = static_cast<__bf16>((float)src[1]);
+        c2 = static_cast<__bf16>((float)src[2]);
+      }
+      __bf16* d = FR + ((y + 1) * FR_W + (x + 1)) * 4;
+      d[0] = c0; d[1] = c1; d[2] = c2; d[3] = zero;
+    }
+    for (int p = tid; p < 2 * FR_W - 1; p += 256) {
+      const int y = p < FR_W ? 0 : p - FR_W + 1, x = p < FR_W ? p : 0;
+      __bf16* d = FR + (y * FR_W + x) * 4;
+      d[0] = padv; d[1] = padv; d[2] = padv; d[3] = zero;
+    }
+    // S1 border (top row, left column) is zero in normalised space
+    for (int p = tid; p < (2 * S1_W - 1) * CB1; p += 256) {
+      const int q = p / CB1, c = p % CB1;
+      const int y = q < S1_W ? 0 : q - S1_W + 1, x = q < S1_W ? q : 0;
+      S1[(y * S1_W + x) * CB1 + c] = static_cast<T>(0.f);
+    }
+  }
+  __syncthreads();
+
+  const T* const* wpk;
+  if constexpr (sizeof(T) == 2) wpk = reinterpret_cast<const T* const*>(a.w_bf[slot]);
+  else wpk = reinterpret_cast<const T* const*>(a.w_f32[slot]);
+  const float* b1 = a.bias[slot][0];
+  const float* b2 = a.bias[slot][1];
+  const float* b3 = a.bias[slot][2];
+
+  // ---- layer 1 (slab by slab) interleaved with layer-2 accumulation
+  constexpr int NT2 = 2 * M;
+  floatx4 acc2[4][NT2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < NT2; ++j) acc2[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+
+  constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
+  for (int slab = 0; slab < M; ++slab) {
+    // layer 1: 64 m-tiles of 16 positions, one 16-channel n-tile; wave w owns m-tiles 16w..16w+15
+    const frag* w1p = reinterpret_cast<const frag*>(wpk[0]) + (size_t)slab * KS1 * 64;
+    for (int chunk = 0; chunk < 4; ++chunk) {
+      floatx4 acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) {
+        frag bw = w1p[ks * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int mt = wave * 16 + chunk * 4 + q;
+          const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
+          frag av;
+          if constexpr (sizeof(T) == 2) {
+            // 8 k values = taps (k0/4, k0/4 + 1), 4 channels each
+            const int k0 = ks * 32 + 8 * g;
+            const int t0 = k0 >> 2, t1 = t0 + 1;
+            uint2 v0 = {0u, 0u}, v1 = {0u, 0u};
+            if (t0 < 9) v0 = *reinterpret_cast<const uint2*>(FR + ((2 * i + t0 / 3) * FR_W + 2 * j + t0 % 3) * 4);
+            if (t1 < 9) v1 = *reinterpret_cast<const uint2*>(FR + ((2 * i + t1 / 3) * FR_W + 2 * j + t1 % 3) * 4);
+            uint4 u = {v0.x, v0.y, v1.x, v1.y};
+            av = *reinterpret_cast<const bf16x8*>(&u);
+          } else {
+            const int k = ks * 4 + g;          // tap = ks, channel = g
+            const int t = k >> 2, c = k & 3;
+            av = (float)FR[((2 * i + t / 3) * FR_W + 2 * j + t % 3) * 4 + c];
+          }
+          acc[q] = mfma(av, bw, acc[q]);
+        }
+      }
+      const float bb = b1[slab * CB1 + l16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int mt = wave * 16 + chunk * 4 + q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int px = mt * 16 + 4 * g + r, i = px >> 5, j = px & 31;
+          S1[((i + 1) * S1_W + (j + 1)) * CB1 + l16] = static_cast<T>(fmaxf(acc[q][r] + bb, 0.f));
+        }
+      }
+    }
+    __syncthreads();
+    // layer 2 partial: K = 9 taps x 16 channels of this slab; wave w owns m-tiles 4w..4w+3
+    const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64;
+#pragma unroll 1
+    for (int ks = 0; ks < KS2; ++ks) {
+      const int k0 = ks * KSTEP + KPL * g;
+      int t = k0 / CB1;
+      const int c0 = k0 % CB1;
+      if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
+      const int u = t / 3, v = t % 3;
+      frag av[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int px = (wave * 4 + q) * 16 + l16, i = px >> 4, j = px & 15;
+        av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * CB1 + c0);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT2; ++nt) {
+        frag bw = w2p[(ks * NT2 + nt) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc2[q][nt] = mfma(av[q], bw, acc2[q][nt]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- layer-2 epilogue into L2 (overwrites FR / S1)
+#pragma unroll
+  for (int nt = 0; nt < NT2; ++nt) {
+    const int ch = nt * 16 + l16;
+    const float bb = b2[ch];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int px = (wave * 4 + q) * 16 + 4 * g + r, i = px >> 4, j = px & 15;
+        L2[((i + 1) * L2_W + (j + 1)) * C2 + ch] = static_cast<T>(fmaxf(acc2[q][nt][r] + bb, 0.f));
+      }
+  }
+  for (int p = tid; p < (2 * L2_W - 1) * C2; p += 256) {
+    const int qq = p / C2, c = p % C2;
+    const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
+    L2[(y * L2_W + x) * C2 + c] = static_cast<T>(0.f);
+  }
+  __syncthreads();
+
+  // ---- layer 3: 4 m-tiles (64 positions) x 4m n-tiles; wave w owns n-tiles M*w .. M*w+M-1
+  constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
+  floatx4 acc3[4][M];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < M; ++j) acc3[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  const frag* w3p = reinterpret_cast<const frag*>(wpk[2]);
+#pragma unroll 1
+  for (int ks = 0; ks < KS3; ++ks) {
+    const int k0 = ks * KSTEP + KPL * g;
+    const int t = k0 / C2, c0 = k0 % C2;
+    const int u = t / 3, v = t % 3;
+    frag av[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int px = q * 16 + l16, i = px >> 3, j = px & 7;
+      av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2 + c0);
+    }
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      frag bw = w3p[(ks * NT3 + wave * M + n) * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc3[q][n] = mfma(av[q], bw, acc3[q][n]);
+    }
+  }
+  // ReLU + pooled sum over the 64 positions
+#pragma unroll
+  for (int n = 0; n < M; ++n) {
+    const int ch = (wave * M + n) * 16 + l16;
+    const float bb = b3[ch];
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s += fmaxf(acc3[q][n][r] + bb, 0.f);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (g == 0) sh.gbuf[ch] = s * (1.0f / 64.0f);
+  }
+  __syncthreads();
+  // FC: z[c] = fc_b[c] + sum_ch g[ch] Wfc[ch][c]
+  if (tid < kClasses) {
+    const float* fw = a.fc_w[slot];
+    float z = a.fc_b[slot][tid];
+    for (int ch = 0; ch < C3; ++ch) z += sh.gbuf[ch] * fw[ch * kClasses + tid];
+    sh.z[tid] = z;
+  }
+  __syncthreads();
+}
+
+template <typename T, int M>
+__device__ void cnn_frame_dispatch(const CnnArgs& a, int slot, uint32_t idx, unsigned char* region, CnnShared& sh);
+
+template <typename T>
+__global__ __launch_bounds__(256) void cnn_fused_kernel(CnnArgs a, Forward f) {
+  __shared__ __attribute__((aligned(16))) unsigned char region[CnnLds<T>::REGION];
+  __shared__ CnnShared sh;
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.d_n = 0;
+  if (tid < kMaxK) sh.ticks[tid] = 0;
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  __syncthreads();
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      int c = a.q.counts[a.pred[i]];
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    const int k = a.pred[slot];
+    const uint32_t e = a.q.entries[(int64_t)k * a.q.cap + off];
+    const uint32_t idx = entry_idx(e);
+    unsigned long long t0 = wall_clock64();
+    switch (a.variant[slot]) {
+      case CNN_W1: cnn_frame<T, 1>(a, slot, idx, region, sh); break;
+      case CNN_W2: cnn_frame<T, 2>(a, slot, idx, region, sh); break;
+      default: cnn_frame<T, 4>(a, slot, idx, region, sh); break;
+    }
+    if (tid == 0) {
+      if (f.logits != nullptr) {
+        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)sh.z[c];
+      } else {
+        float d = class_margin(sh.z, a.class_mask[slot]);
+        float th = theta_of(f, k, idx);
+        bool defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau;
+        int n = sh.d_n;
+        sh.d_e[n] = e;
+        sh.d_k[n] = (uint8_t)k;
+        sh.d_f[n] = (uint8_t)((d > th ? 1 : 0) | (defer ? 2 : 0));
+        sh.d_n = n + 1;
+      }
+      sh.ticks[k] += wall_clock64() - t0;
+    }
+    __syncthreads();
+    if (sh.d_n == DBUF) flush_decisions<T>(f, sh, a.n_preds, a.pred);
+  }
+  if (f.logits == nullptr) flush_decisions<T>(f, sh, a.n_preds, a.pred);
+  __syncthreads();
+  if (tid < kMaxK && sh.ticks[tid] && a.count_ticks) atomicAdd(&a.st->r_ticks[tid], sh.ticks[tid]);
+}
+
+// ---------------------------------------------------------------- FP64 tier
+// One workgroup per escalated entry; activations in a per-block global scratch; the canonical
+// (unfolded) fp32 weights widened to fp64; the frame normalised in fp64 as defined.
+__device__ inline double frame_norm64(const FrameSrc& fr, uint32_t idx, int y, int x, int c) {
+  const int64_t o = (int64_t)idx * fr.elems + ((int64_t)y * fr.hw + x) * 3 + c;
+  double v;
+  if (fr.dtype == HYDRO_DTYPE_BF16) v = (double)(float)static_cast<const __bf16*>(fr.base)[o];
+  else v = (double)static_cast<const uint8_t*>(fr.base)[o] / 255.0;
+  return (v - 0.5) * 4.0;
+}
+
+__global__ __launch_bounds__(256) void cnn_f64_kernel(CnnArgs a, Forward f) {
+  __shared__ double gsh[256];
+  __shared__ double zsh[kClasses];
+  const int tid = threadIdx.x;
+  double* A = a.scratch64 + (int64_t)blockIdx.x * a.scratch64_per_block;
+  double* B = A + a.scratch64_per_block / 2;
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      int c = a.q.counts[a.pred[i]];
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    const int k = a.pred[slot];
+    const uint32_t e = a.q.entries[(int64_t)k * a.q.cap + off];
+    const uint32_t idx = entry_idx(e);
+    const int m = a.variant[slot] == CNN_W1 ? 1 : a.variant[slot] == CNN_W2 ? 2 : 4;
+    const int C1 = 16 * m, C2 = 32 * m, C3 = 64 * m;
+    // layer 1 -> A [32][32][C1]
+    {
+      const float* W = a.w_canon[slot][0];
+      const float* b = a.b_canon[slot][0];
+      for (int q = tid; q < H1 * H1 * C1; q += 256) {
+        const int o = q % C1, p = q / C1, i = p / H1, j = p % H1;
+        double s = (double)b[o];
+        for (int c = 0; c < 3; ++c)
+          for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) {
+              const int y = 2 * i + u - 1, x = 2 * j + v - 1;
+              if (y < 0 || x < 0 || y >= H0 || x >= H0) continue;
+              s = fma((double)W[((o * 3 + c) * 3 + u) * 3 + v], frame_norm64(a.fr, idx, y, x, c), s);
+            }
+        A[q] = s > 0.0 ? s : 0.0;
+      }
+    }
+    __syncthreads();
+    // layer 2 -> B [16][16][C2]
+    {
+      const float* W = a.w_canon[slot][1];
+      const float* b = a.b_canon[slot][1];
+      for (int q = tid; q < H2 * H2 * C2; q += 256) {
+        const int o = q % C2, p = q / C2, i = p / H2, j = p % H2;
+        double s = (double)b[o];
+        for (int u = 0; u < 3; ++u)
+          for (int v = 0; v < 3; ++v) {
+            const int y = 2 * i + u - 1, x = 2 * j + v - 1;
+            if (y < 0 || x < 0 || y >= H1 || x >= H1) continue;
+            const double* in = A + (y * H1 + x) * C1;
+            for (int c = 0; c < C1; ++c) s = fma((double)W[((o * C1 + c) * 3 + u) * 3 + v], in[c], s);
+          }
+        B[q] = s > 0.0 ? s : 0.0;
+      }
+    }
+    __syncthreads();
+    // layer 3 -> A [8][8][C3]
+    {
+      const float* W = a.w_canon[slot][2];
+      const float* b = a.b_canon[slot][2];
+      for (int q = tid; q < H3 * H3 * C3; q += 256) {
+        const int o = q % C3, p = q / C3, i = p / H3, j = p % H3;
+        double s = (double)b[o];
+        for (int u = 0; u < 3; ++u)
+          for (int v = 0; v < 3; ++v) {
+            const int y = 2 * i + u - 1, x = 2 * j + v - 1;
+            if (y < 0 || x < 0 || y >= H2 || x >= H2) continue;
+            const double* in = B + (y * H2 + x) * C2;
+            for (int c = 0; c < C2; ++c) s = fma((double)W[((o * C2 + c) * 3 + u) * 3 + v], in[c], s);
+          }
+        A[q] = s > 0.0 ? s : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int o = tid; o < C3; o += 256) {
+      double s = 0.0;
+      for (int p = 0; p < H3 * H3; ++p) s += A[p * C3 + o];
+      gsh[o] = s / 64.0;
+    }
+    __syncthreads();
+    if (tid < kClasses) {
+      const float* fw = a.fc_w[slot];
+      double z = (double)a.fc_b[slot][tid];
+      for (int ch = 0; ch < C3; ++ch) z = fma(gsh[ch], (double)fw[ch * kClasses + tid], z);
+      zsh[tid] = z;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      bool active = tid == 0;
+      bool pass = false;
+      if (active) {
+        if (f.logits != nullptr) {
+          for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = zsh[c];
+        }
+        double d = class_margin(zsh, a.class_mask[slot]);
+        pass = d > (double)theta_of(f, k, idx);
+      }
+      if (f.logits == nullptr) forward_decision(f, k, e, active, false, pass);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- host helpers
 int cnn_variant_of(int in_hw, int n_layers, const int* widths) {
   if (in_hw != 64 || n_layers != 3) return CNN_NONE;
   for (int v = 0, m = 1; v < 3; ++v, m *= 2)
     if (widths[0] == 16 * m && widths[1] == 32 * m && widths[2] == 64 * m) return v;
   return CNN_NONE;
 }
-size_t cnn_packed_elems(int, int) { return 1; }
-void cnn_pack_layer(int, int, const float*, float, float* out) { out[0] = 0.f; }
-int cnn_grid_hint(int, int) { return 256; }
-void launch_cnn_pass(const CnnArgs&, const Forward&, int, int, hipStream_t) {}
+
+static int mult_of(int variant) { return variant == CNN_W1 ? 1 : variant == CNN_W2 ? 2 : 4; }
+
+template <typename T>
+static size_t packed_elems_t(int variant, int layer) {
+  const int m = mult_of(variant);
+  return (size_t)cnn_slabs(layer, m) * cnn_ksteps<T>(layer, m) * cnn_ntiles(layer, m) * 64 * Mf<T>::KPL;
+}
+
+size_t cnn_packed_elems(int variant, int layer, int prec) {
+  return prec == HYDRO_PREC_BF16 ? packed_elems_t<__bf16>(variant, layer) : packed_elems_t<float>(variant, layer);
+}
+
+// Pack one conv layer ([co][ci][3][3] fp32, scaled by `scale`) into fragment order.
+template <typename T>
+static void pack_t(int variant, int layer, const float* w, float scale, float* out) {
+  const int m = mult_of(variant);
+  const int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
+  const int slabs = cnn_slabs(layer, m), ks_n = cnn_ksteps<T>(layer, m), nt_n = cnn_ntiles(layer, m);
+  const int C2 = 32 * m;
+  const int cin = layer == 0 ? 3 : layer == 1 ? 16 * m : C2;
+  size_t o = 0;
+  for (int sl = 0; sl < slabs; ++sl)
+    for (int ks = 0; ks < ks_n; ++ks)
+      for (int nt = 0; nt < nt_n; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < KPL; ++e) {
+            const int k = ks * KSTEP + KPL * (lane >> 4) + e;
+            const int n = nt * 16 + (lane & 15);
+            int oc, ic, tap;
+            bool valid;
+            if (layer == 0) {
+              tap = k >> 2;
+              ic = k & 3;
+              oc = sl * CB1 + n;
+              valid = tap < 9 && ic < 3;
+            } else if (layer == 1) {
+              tap = k / CB1;
+              ic = sl * CB1 + k % CB1;
+              oc = n;
+              valid = tap < 9;
+            } else {
+              tap = k / C2;
+              ic = k % C2;
+              oc = n;
+              valid = tap < 9;
+            }
+            out[o++] = valid ? scale * w[((size_t)(oc * cin + ic) * 3 + tap / 3) * 3 + tap % 3] : 0.f;
+          }
+}
+
+void cnn_pack_layer(int variant, int layer, int prec, const float* w_canon, float scale, float* out) {
+  if (prec == HYDRO_PREC_BF16) pack_t<__bf16>(variant, layer, w_canon, scale, out);
+  else pack_t<float>(variant, layer, w_canon, scale, out);
+}
+
+void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
+  if (a.n_preds == 0) return;
+  if (tier == TIER_F64) {
+    hipLaunchKernelGGL(cnn_f64_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    return;
+  }
+  if (a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)
+    hipLaunchKernelGGL(cnn_fused_kernel<__bf16>, dim3(grid), dim3(256), 0, s, a, f);
+  else
+    hipLaunchKernelGGL(cnn_fused_kernel<float>, dim3(grid), dim3(256), 0, s, a, f);
+}
 
 }  // namespace hydro

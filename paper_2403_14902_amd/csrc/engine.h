@@ -54,8 +54,8 @@ struct CnnArgs {
 
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
-size_t cnn_packed_elems(int variant, int layer);
-void cnn_pack_layer(int variant, int layer, const float* w_canon, float scale, float* out_f32);
+size_t cnn_packed_elems(int variant, int layer, int prec);
+void cnn_pack_layer(int variant, int layer, int prec, const float* w_canon, float scale, float* out);
 int cnn_variant_of(int in_hw, int n_layers, const int* widths);
 int cnn_grid_hint(int variant, int tier);
 

@@ -442,18 +442,25 @@ static int pack_models(hydro_session* s) {
           }
           bias[o] = (float)b;
         }
-        size_t n = cnn_packed_elems(hm.variant, l);
-        std::vector<float> pf(n);
-        cnn_pack_layer(hm.variant, l, hm.cw[l].data(), (float)sc, pf.data());
-        std::vector<uint16_t> pb(n);
-        for (size_t t = 0; t < n; ++t) pb[t] = f32_to_bf16_bits(pf[t]);
         int rc;
         float* dp;
         uint16_t* bp;
-        if ((rc = upload(s, pf.data(), n, &dp))) return rc;
-        ca.w_f32[i][l] = dp;
-        if ((rc = upload(s, pb.data(), n, &bp))) return rc;
-        ca.w_bf[i][l] = reinterpret_cast<const __bf16*>(bp);
+        {
+          size_t n = cnn_packed_elems(hm.variant, l, HYDRO_PREC_FP32);
+          std::vector<float> pf(n);
+          cnn_pack_layer(hm.variant, l, HYDRO_PREC_FP32, hm.cw[l].data(), (float)sc, pf.data());
+          if ((rc = upload(s, pf.data(), n, &dp))) return rc;
+          ca.w_f32[i][l] = dp;
+        }
+        {
+          size_t n = cnn_packed_elems(hm.variant, l, HYDRO_PREC_BF16);
+          std::vector<float> pf(n);
+          cnn_pack_layer(hm.variant, l, HYDRO_PREC_BF16, hm.cw[l].data(), (float)sc, pf.data());
+          std::vector<uint16_t> pb(n);
+          for (size_t t = 0; t < n; ++t) pb[t] = f32_to_bf16_bits(pf[t]);
+          if ((rc = upload(s, pb.data(), n, &bp))) return rc;
+          ca.w_bf[i][l] = reinterpret_cast<const __bf16*>(bp);
+        }
         if ((rc = upload(s, bias.data(), bias.size(), &dp))) return rc;
         ca.bias[i][l] = dp;
         if ((rc = upload(s, hm.cw[l].data(), hm.cw[l].size(), &dp))) return rc;

@@ -1,0 +1,108 @@
+"""GPU parity of the fused CNN path (64x64x3 frames, CNN predicates of widths (16m, 32m, 64m),
+m = 1, 2, 4, drifting thresholds over 8 segments) against the FP64 oracle, through the C ABI."""
+import itertools
+
+import numpy as np
+import pytest
+
+import hydro_synth as hs
+from oracle import hydro_oracle as ho
+from tests.gpu_util import case, check_stats, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2403_14902_amd import hydro  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c2small():
+    return case(2, 256, logits=True)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    # two drift segments (8192 tuples each)
+    return case(2, 16384)
+
+
+@pytest.mark.parametrize("prec,tier,tol", [("bf16", 0, 0.1), ("bf16", 1, 1e-4), ("fp32", 0, 1e-4), ("bf16", 2, 1e-10)])
+def test_cnn_logits_each_tier_vs_oracle(c2small, prec, tier, tol):
+    c = c2small
+    s = hydro.Session(c.specs(), hydro.make_policy("score", precision=prec), 64, c.n)
+    dev = c.device_frames()
+    for k in range(c.cfg.k):
+        z = s.logits(k, tier, dev, c.cfg.dtype)
+        err = np.abs(z - c.Z[k]).max()
+        log(f"[gpu] cnn logits prec={prec} tier={tier} predicate {k}: max |z - z64| = {err:.3e}")
+        assert err <= tol
+    s.close()
+
+
+def test_cnn_uint8_frames_logits_and_ids():
+    """uint8 frames (value v/255) through the same CNN predicates."""
+    cfg = hs.workload(2)
+    fr = hs.make_frames(cfg, 0, 512)
+    x = ho.frames_to_f64(fr, "bf16")
+    u8 = np.rint(255.0 * x).astype(np.uint8)
+    pt = hs.load_predicates(cfg)
+    weights = [hs.make_model(d) for d in cfg.models]
+    P, D, Z = ho.truth_table(u8, "u8", weights, pt.class_masks, pt.thresholds, cfg.n // cfg.n_seg,
+                             return_logits=True)
+    specs = [hydro.ModelSpec.from_weights(w, m) for w, m in zip(weights, pt.class_masks)]
+    dev = torch.from_numpy(u8).cuda()
+    s = hydro.Session(specs, hydro.make_policy("score", precision="bf16"), 64, 512)
+    for k in range(3):
+        for tier, tol in ((0, 0.1), (1, 1e-4), (2, 1e-10)):
+            err = np.abs(s.logits(k, tier, dev, "u8") - Z[k]).max()
+            log(f"[gpu] u8 logits tier {tier} predicate {k}: {err:.3e}")
+            assert err <= tol
+    s.push(dev, "u8", pt.thresholds, cfg.n // cfg.n_seg)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, ho.result_ids(P))
+    s.close()
+
+
+@pytest.mark.parametrize("route,prec", [("score", "bf16"), ("score", "fp32"), ("selectivity", "bf16"),
+                                        ("cost", "bf16")])
+def test_cnn_adaptive_ids_stats_replay(c2, route, prec):
+    log(f"[gpu] cnn route={route} prec={prec}")
+    pol = hydro.make_policy(route, precision=prec, wave=4096, log_routes=1)
+    s = hydro.Session(c2.specs(), pol, 64, c2.n)
+    s.push(c2.device_frames(), c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c2.expect)
+    check_stats(stats, c2.n, ids.size)
+    ok, rev, rps, out, msg = ho.replay_route(c2.P, hydro.decode_routes(s.routes(0, c2.n)))
+    assert ok, msg
+    assert [st["evaluated"] for st in stats] == list(rev)
+    assert [st["passed"] for st in stats] == list(rps)
+    log(f"  |R|={ids.size} rescored={[st['rescored'] for st in stats]} escalated={[st['escalated'] for st in stats]}")
+    s.close()
+
+
+@pytest.mark.parametrize("order", [(0, 1, 2), (2, 1, 0), (1, 2, 0)])
+def test_cnn_fixed_orders_exact_counts(c2, order):
+    pol = hydro.make_policy("fixed", order=order, precision="bf16", wave=8192)
+    s = hydro.Session(c2.specs(), pol, 64, c2.n)
+    s.push(c2.device_frames(), c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c2.expect)
+    _, ev, ps = ho.short_circuit_eval(c2.P, order)
+    assert [st["evaluated"] for st in stats] == list(ev)
+    assert [st["passed"] for st in stats] == list(ps)
+    s.close()
+
+
+def test_cnn_static_cost_routes_are_reproducible(c2):
+    pol = hydro.make_policy("score", precision="bf16", wave=2048, cost_source="static", log_routes=1)
+    runs = []
+    for _ in range(2):
+        s = hydro.Session(c2.specs(), pol, 64, c2.n)
+        s.push(c2.device_frames(), c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+        ids, stats = s.finish()
+        assert np.array_equal(ids, c2.expect)
+        runs.append(([st["evaluated"] for st in stats], s.routes(0, c2.n)))
+        s.close()
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
