@@ -1,0 +1,202 @@
+"""Throughput of the conjunctive ML-UDF query on one MI355X.
+
+Workload (default): 65,536 synthetic frames 64x64x3 bf16, three CNN predicates of widths
+(16m, 32m, 64m), m = 1, 2, 4, class-subset thresholds that drift over 8 segments of 8,192
+tuples.  Frames are resident in HBM before timing starts; models are uploaded at session
+creation (setup, not timed).
+
+A step is one whole query: reset, push every tuple (route, multi-split, evaluate, forward
+survivors, materialise the sorted ids) and copy ids and statistics to the host.
+
+Forms:
+  full   first pass in BF16 on MFMA (fp32 accumulate), margins within tau re-scored in FP32,
+         within tau32 in FP64; score-driven routing; grouped persistent launches per round.
+  plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate.
+
+Prints one JSON line (the full form's throughput as `value`, the plain form beside it, the
+dominant kernel's roofline from HIP events recorded by the library on its stream, and the FP64
+oracle timed on the host cores on a bounded sample).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs plain; MFMA util"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--wave", type=int, default=8192)
+    ap.add_argument("--tau", type=float, default=0.0)
+    ap.add_argument("--route", default="score")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--check-sample", type=int, default=2048)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps, warmup, n):
+    sess = hydro.Session(specs, policy, frames_dev.shape[1], n)
+    res = None
+    for _ in range(warmup):
+        sess.reset()
+        sess.push(frames_dev, dtype, pt.thresholds, seg_len)
+        res = sess.finish()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, stats_all = [], []
+    for _ in range(steps):
+        sess.reset()
+        sess.push(frames_dev, dtype, pt.thresholds, seg_len)
+        res = sess.finish()
+        infos.append(sess.info())
+        stats_all.append(res[1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sess.close()
+    return res[0], stats_all, infos, t1 - t0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU sharding design is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    import hydro_synth as hs
+    from paper_2403_14902_amd import hydro
+
+    torch.cuda.set_device(0)
+    hydro.lib()
+    cfg = hs.workload(args.workload)
+    n = cfg.n
+    log(f"[bench] generating {n} frames of workload {cfg.name}")
+    frames = hs.make_frames_parallel(cfg, 0, n)
+    pt = hs.load_predicates(cfg)
+    weights = [hs.make_model(d) for d in cfg.models]
+    specs = [hydro.ModelSpec.from_weights(w, m) for w, m in zip(weights, pt.class_masks)]
+    seg_len = cfg.n // cfg.n_seg
+    frames_dev = torch.from_numpy(frames).cuda()
+    flops = np.array([d.flops() for d in cfg.models])
+
+    extra = {}
+    if args.tau > 0:
+        extra["tau"] = args.tau
+    full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
+    log("[bench] full form")
+    ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
+                                         args.steps, args.warmup, n)
+    value = n * args.steps / dt
+    ms_per_step = dt * 1e3 / args.steps
+
+    # dominant kernel: the first-pass launch of every round (grouped bf16 MFMA kernel)
+    ev = np.array([[s["evaluated"] for s in st] for st in stats_all], dtype=np.float64)
+    first_flops = float((ev * flops).sum())
+    first_ms = sum(i["first_pass_ms"] for i in infos)
+    launches = sum(i["timed_rounds"] for i in infos)
+    achieved = first_flops / (first_ms * 1e-3) / 1e12 if first_ms > 0 else 0.0
+    resc = np.array([[s["rescored"] for s in st] for st in stats_all], dtype=np.float64)
+    f32_flops = float((resc * flops).sum())
+    f32_ms = sum(i["f32_pass_ms"] for i in infos)
+    last = stats_all[-1]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {n} frames {cfg.hw}x{cfg.hw}x3 {cfg.dtype}, "
+                               f"{cfg.k} predicates, {cfg.n_seg} threshold segments",
+                   "form": "full: bf16 first pass + fp32/fp64 re-score, " + args.route + " routing, grouped",
+                   "wave": args.wave, "tuples_per_step": n},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "cnn_fused_kernel<bf16> (first pass, one grouped launch per round)",
+            "achieved": achieved,
+            "peak": PEAK_BF16_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": first_flops / max(1, launches),
+            "avg_launch_ms": first_ms / max(1, launches),
+        },
+        "phases_ms_per_step": {
+            "route": sum(i["route_ms"] for i in infos) / args.steps,
+            "first_pass": first_ms / args.steps,
+            "fp32_rescore": f32_ms / args.steps,
+            "fp64_escalate": sum(i["f64_pass_ms"] for i in infos) / args.steps,
+        },
+        "fp32_rescore_tflops": f32_flops / (f32_ms * 1e-3) / 1e12 if f32_ms > 0 else 0.0,
+        "per_predicate": [{"evaluated": s["evaluated"], "passed": s["passed"], "rescored": s["rescored"],
+                           "escalated": s["escalated"], "selectivity": round(s["selectivity"], 4)} for s in last],
+        "n_result": int(ids.size),
+        "rounds": infos[-1]["rounds"],
+    }
+
+    if not args.no_plain:
+        log("[bench] plain form")
+        plain_pol = hydro.make_policy(args.route, precision="fp32", wave=args.wave, grouped=0, time_kernels=0)
+        ids_p, _, _, dtp = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, plain_pol,
+                                    max(1, args.steps // 2), 1, n)
+        assert np.array_equal(ids_p, ids), "plain and full forms disagree"
+        vp = n * max(1, args.steps // 2) / dtp
+        out["plain"] = {"value": vp, "unit": "tuples/s", "form": "fp32 first pass, per-predicate launches"}
+        out["speedup_vs_plain"] = value / vp
+
+    if not args.no_cpu:
+        # FP64 oracle on a bounded, evenly spread sample of the same workload
+        from threadpoolctl import threadpool_info
+        from oracle import hydro_oracle as ho
+        m = min(args.cpu_sample, n)
+        sel = np.linspace(0, n - 1, m).astype(np.int64)
+        fr_s = np.ascontiguousarray(frames[sel])
+        cores = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu oracle on {m} sampled tuples, {cores} threads")
+        t0 = time.perf_counter()
+        P = np.zeros((m, cfg.k), dtype=bool)
+        th = ho.tuple_thresholds(pt.thresholds, seg_len, sel)
+        for j, w in enumerate(weights):
+            z = ho.model_logits(w, fr_s, cfg.dtype, workers=cores)
+            P[:, j] = ho.decide(ho.predicate_margin(z, pt.class_masks[j]), th[:, j])
+        tc = time.perf_counter() - t0
+        exp_in = P.all(axis=1)
+        got_in = np.isin(sel, ids)
+        out["cpu_baseline"] = {"value": m / tc, "unit": "tuples/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{m} tuples evenly spaced over the {n}-tuple workload, every predicate "
+                                         f"evaluated in fp64 (numpy, BLAS 1 thread per worker)",
+                               "os_cpu_count": os.cpu_count(),
+                               "blas": [d.get("internal_api") for d in threadpool_info()]}
+        out["sample_check"] = {"tuples": m, "mismatches": int((exp_in != got_in).sum())}
+        if (exp_in != got_in).any():
+            log("[bench] WARNING: GPU ids differ from the oracle on the sample")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,8 @@ typedef struct {
                                             predicates (default 1)                               */
   int32_t use_graph;                     /* 1: replay the round sequence from a HIP graph        */
   int32_t log_routes;                    /* 1: record every tuple's visit sequence (debug)       */
+  int32_t time_kernels;                  /* 1: bracket each round's phases with HIP events and
+                                            report their summed durations in hydro_query_info    */
   float explore;                         /* LEARNED: fraction of routing batches kept on SCORE
                                             as the judge's control arm (default 0.05)            */
   uint64_t seed;                         /* LEARNED: router init / exploration seed              */
@@ -155,6 +157,13 @@ typedef struct {
   uint32_t learned_active;                 /* LEARNED: 1 if the judge kept the learned router    */
   uint32_t train_steps;                    /* LEARNED: optimiser steps taken                      */
   double elapsed_us;                       /* host time from first push to results on the host  */
+  /* policy.time_kernels = 1: summed device durations (HIP events on the session's stream) */
+  double route_ms;                         /* fold + router + learned-router work                */
+  double first_pass_ms;                    /* first-pass inference launches (one per round)      */
+  double f32_pass_ms;                      /* FP32 re-score launches                              */
+  double f64_pass_ms;                      /* FP64 escalation launches                            */
+  uint32_t timed_rounds;                   /* rounds bracketed                                    */
+  uint32_t pad_;
 } hydro_query_info;
 
 typedef struct hydro_session hydro_session;

@@ -314,7 +314,18 @@ struct hydro_session {
   std::chrono::steady_clock::time_point t_start;
   hydro_query_info info{};
   double tick_us = 0.01;   // device wall clock period in microseconds
+  std::vector<hipEvent_t> evpool;   // time_kernels: 5 events per round
+  int ev_used = 0;
 };
+
+static hipEvent_t next_event(hydro_session* s) {
+  if (s->ev_used == (int)s->evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->evpool.push_back(e);
+  }
+  return s->evpool[s->ev_used++];
+}
 
 static int sess_alloc(hydro_session* s, void** p, size_t bytes) {
   hipError_t e = dev_alloc(p, bytes);
@@ -382,7 +393,13 @@ static int pack_models(hydro_session* s) {
   ma = MlpArgs{};
   ca = CnnArgs{};
   ca.pad_raw = pad_raw;
-  for (int k = 0; k < s->K; ++k) {
+  // grouped launches walk their slots in order: most expensive predicates first, so the
+  // longest work items start early (longest-processing-time-first)
+  std::vector<int> slots_order(s->K);
+  for (int k = 0; k < s->K; ++k) slots_order[k] = k;
+  std::stable_sort(slots_order.begin(), slots_order.end(),
+                   [&](int x, int y) { return s->models[x].flops > s->models[y].flops; });
+  for (int k : slots_order) {
     HostModel& hm = s->models[k];
     const hydro_model& m = hm.m;
     if (m.arch == HYDRO_ARCH_MLP) {
@@ -507,6 +524,7 @@ static void free_session(hydro_session* s) {
     if (s->stage_ready[i]) hipEventDestroy(s->stage_ready[i]);
   }
   if (s->out_ids) hipFree(s->out_ids);
+  for (hipEvent_t e : s->evpool) hipEventDestroy(e);
   if (s->copy_stream) hipStreamDestroy(s->copy_stream);
   if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
   delete s;
@@ -680,6 +698,7 @@ int hydro_session_reset(hydro_session* s) {
   s->last_id_end = INT64_MIN;
   s->theta_host.clear();
   s->info = hydro_query_info{};
+  s->ev_used = 0;
   if (s->rnn) router_nn_reset(s->rnn, s->stream);
   return HYDRO_OK;
 }
@@ -725,6 +744,8 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
   if (tier == TIER_FIRST) q = Queues{s->q1, s->st->qcount, s->cap};
   else if (tier == TIER_F32) q = Queues{s->q2, s->st->bcount, s->cap};
   else q = Queues{s->q3, s->st->ecount, s->cap};
+  // grouped: one launch covers every predicate of an architecture; otherwise one launch per
+  // predicate (the plain form)
   if (s->mlp.n_preds) {
     MlpArgs a = s->mlp;
     a.q = q;
@@ -733,7 +754,19 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
     a.part_cap = s->cap;
     a.count_ticks = 1;
     a.prec = s->pol.precision;
-    launch_mlp_pass(a, f, tier, tier == TIER_F64 ? s->n_cu : s->n_cu * 4, st);
+    const int grid = tier == TIER_F64 ? s->n_cu : s->n_cu * 4;
+    if (s->pol.grouped || a.n_preds == 1) {
+      launch_mlp_pass(a, f, tier, grid, st);
+    } else {
+      for (int i = 0; i < s->mlp.n_preds; ++i) {
+        MlpArgs b = a;
+        b.n_preds = 1;
+        b.pred[0] = a.pred[i]; b.d_in[0] = a.d_in[i]; b.hidden[0] = a.hidden[i]; b.class_mask[0] = a.class_mask[i];
+        b.w1_bf[0] = a.w1_bf[i]; b.w1_f32[0] = a.w1_f32[i]; b.b1_fold[0] = a.b1_fold[i]; b.w2[0] = a.w2[i];
+        b.b2[0] = a.b2[i]; b.w1_canon[0] = a.w1_canon[i]; b.b1_canon[0] = a.b1_canon[i]; b.partial[0] = a.partial[i];
+        launch_mlp_pass(b, f, tier, grid, st);
+      }
+    }
   }
   if (s->cnn.n_preds) {
     CnnArgs a = s->cnn;
@@ -742,7 +775,21 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
     a.st = s->st;
     a.count_ticks = 1;
     a.prec = s->pol.precision;
-    launch_cnn_pass(a, f, tier, s->n_cu, st);
+    if (s->pol.grouped || a.n_preds == 1) {
+      launch_cnn_pass(a, f, tier, s->n_cu, st);
+    } else {
+      for (int i = 0; i < s->cnn.n_preds; ++i) {
+        CnnArgs b = a;
+        b.n_preds = 1;
+        b.pred[0] = a.pred[i]; b.variant[0] = a.variant[i]; b.class_mask[0] = a.class_mask[i];
+        for (int l = 0; l < 3; ++l) {
+          b.w_bf[0][l] = a.w_bf[i][l]; b.w_f32[0][l] = a.w_f32[i][l]; b.bias[0][l] = a.bias[i][l];
+          b.w_canon[0][l] = a.w_canon[i][l]; b.b_canon[0][l] = a.b_canon[i][l];
+        }
+        b.fc_w[0] = a.fc_w[i]; b.fc_b[0] = a.fc_b[i];
+        launch_cnn_pass(b, f, tier, s->n_cu, st);
+      }
+    }
   }
 }
 
@@ -875,8 +922,14 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   }
   const int n_rounds = adm.empty() ? 0 : (int)adm.size() + s->K - 1;
 
+  const bool timing = s->pol.time_kernels != 0;
   for (int r = 0; r < n_rounds; ++r) {
     const int in_slot = s->parity, out_slot = s->parity ^ 1;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (timing) {
+      for (int i = 0; i < 5; ++i) ev[i] = next_event(s);
+      if (ev[0]) hipEventRecord(ev[0], st);
+    }
     FoldArgs fa{};
     fa.st = s->st;
     fa.k = s->K;
@@ -911,12 +964,15 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
     ra.learned_keys = s->rnn ? router_nn_keys(s->rnn) : nullptr;
     ra.arm = s->rnn ? router_nn_arms(s->rnn) : nullptr;
     hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
+    if (timing && ev[1]) hipEventRecord(ev[1], st);
 
     for (int tier = TIER_FIRST; tier <= TIER_F64; ++tier) {
       if (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_BF16) continue;
       Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
       enqueue_tier(s, tier, src, f, st);
+      if (timing && ev[2 + tier]) hipEventRecord(ev[2 + tier], st);
     }
+    if (timing && s->pol.precision != HYDRO_PREC_BF16 && ev[3]) hipEventRecord(ev[3], st);
     if (s->rnn) router_nn_learn(s->rnn, s->st, src, s->route_log, st);
     s->parity ^= 1;
     s->rounds_done++;
@@ -965,6 +1021,25 @@ int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hy
     }
   }
   if (!s->ids_sorted) std::sort(ids, ids + nres);
+  if (s->pol.time_kernels) {
+    // events were recorded in groups of 5 per round: start, routed, first, f32, f64
+    double tr = 0, t1 = 0, t2 = 0, t3 = 0;
+    int nr = 0;
+    for (int i = 0; i + 4 < s->ev_used; i += 5) {
+      float a = 0, b = 0, c = 0, d = 0;
+      if (hipEventElapsedTime(&a, s->evpool[i], s->evpool[i + 1]) != hipSuccess) continue;
+      hipEventElapsedTime(&b, s->evpool[i + 1], s->evpool[i + 2]);
+      hipEventElapsedTime(&c, s->evpool[i + 2], s->evpool[i + 3]);
+      hipEventElapsedTime(&d, s->evpool[i + 3], s->evpool[i + 4]);
+      tr += a; t1 += b; t2 += c; t3 += d;
+      ++nr;
+    }
+    s->info.route_ms = tr;
+    s->info.first_pass_ms = t1;
+    s->info.f32_pass_ms = t2;
+    s->info.f64_pass_ms = t3;
+    s->info.timed_rounds = nr;
+  }
   auto t1 = std::chrono::steady_clock::now();
   s->info.n_result = nres;
   s->info.rounds = h.rounds;

@@ -59,6 +59,7 @@ class Policy(C.Structure):
                 ("wave", C.c_int32), ("warmup_batches", C.c_int32), ("ewma_alpha", C.c_float),
                 ("cost_source", C.c_int32), ("precision", C.c_int32), ("tau", C.c_float), ("tau32", C.c_float),
                 ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
+                ("time_kernels", C.c_int32),
                 ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p)]
 
 
@@ -71,7 +72,9 @@ class PredStats(C.Structure):
 class QueryInfo(C.Structure):
     _fields_ = [("n_tuples", C.c_uint64), ("n_result", C.c_uint64), ("rounds", C.c_uint32), ("k", C.c_uint32),
                 ("learned_routed", C.c_uint64), ("stats_routed", C.c_uint64), ("learned_active", C.c_uint32),
-                ("train_steps", C.c_uint32), ("elapsed_us", C.c_double)]
+                ("train_steps", C.c_uint32), ("elapsed_us", C.c_double), ("route_ms", C.c_double),
+                ("first_pass_ms", C.c_double), ("f32_pass_ms", C.c_double), ("f64_pass_ms", C.c_double),
+                ("timed_rounds", C.c_uint32), ("pad_", C.c_uint32)]
 
 
 _lib = None
