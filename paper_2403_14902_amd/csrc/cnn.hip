@@ -360,8 +360,11 @@ __global__ __launch_bounds__(256) void cnn_fused_kernel(CnnArgs a, Forward f) {
 }
 
 // ---------------------------------------------------------------- FP64 tier
-// One workgroup per escalated entry; activations in a per-block global scratch; the canonical
-// (unfolded) fp32 weights widened to fp64; the frame normalised in fp64 as defined.
+// The frame normalised in fp64 exactly as defined, the canonical (unfolded) fp32 weights
+// widened to fp64, fp64 accumulation.  The first esc_cap escalated entries of each predicate are
+// evaluated layer-parallel across the whole GPU (one thread per output activation, weights laid
+// out [ci][3][3][co] so consecutive threads read consecutive weights); any beyond that run one
+// entry per workgroup.
 __device__ inline double frame_norm64(const FrameSrc& fr, uint32_t idx, int y, int x, int c) {
   const int64_t o = (int64_t)idx * fr.elems + ((int64_t)y * fr.hw + x) * 3 + c;
   double v;
@@ -370,105 +373,159 @@ __device__ inline double frame_norm64(const FrameSrc& fr, uint32_t idx, int y, i
   return (v - 0.5) * 4.0;
 }
 
-__global__ __launch_bounds__(256) void cnn_f64_kernel(CnnArgs a, Forward f) {
-  __shared__ double gsh[256];
-  __shared__ double zsh[kClasses];
+__device__ inline int mult_dev(int variant) { return variant == CNN_W1 ? 1 : variant == CNN_W2 ? 2 : 4; }
+
+// Activation (after ReLU) of output (p, o) of `layer` for one entry.  `in` is the previous layer's
+// output ([H][H][Cin] fp64) for layers 1 and 2.
+__device__ inline double conv64_at(const CnnArgs& a, int slot, int layer, uint32_t idx, const double* in, int p, int o) {
+  const int m = mult_dev(a.variant[slot]);
+  const int cin = layer == 0 ? 3 : layer == 1 ? 16 * m : 32 * m;
+  const int cout = layer == 0 ? 16 * m : layer == 1 ? 32 * m : 64 * m;
+  const int hin = layer == 0 ? H0 : layer == 1 ? H1 : H2;
+  const int hout = hin / 2;
+  const int i = p / hout, j = p % hout;
+  const float* W = a.wt_canon[slot][layer];
+  double s = (double)a.b_canon[slot][layer][o];
+  for (int u = 0; u < 3; ++u) {
+    const int y = 2 * i + u - 1;
+    if (y < 0 || y >= hin) continue;
+    for (int v = 0; v < 3; ++v) {
+      const int x = 2 * j + v - 1;
+      if (x < 0 || x >= hin) continue;
+      const float* w = W + (u * 3 + v) * cout + o;
+      if (layer == 0) {
+        for (int c = 0; c < 3; ++c) s = fma((double)w[c * 9 * cout], frame_norm64(a.fr, idx, y, x, c), s);
+      } else {
+        const double* xin = in + (y * hin + x) * cin;
+        for (int c = 0; c < cin; ++c) s = fma((double)w[c * 9 * cout], xin[c], s);
+      }
+    }
+  }
+  return s > 0.0 ? s : 0.0;
+}
+
+__device__ inline int64_t act_off(int layer, int m) {
+  // per entry: [layer-1 output | layer-2 output]; layer 3 reuses the layer-1 region
+  return layer == 1 ? (int64_t)H1 * H1 * 16 * m : 0;
+}
+
+__global__ __launch_bounds__(256) void cnn_f64_layer_kernel(CnnArgs a, int layer) {
+  int64_t total = 0;
+  int64_t outs[kMaxK];
+  int ne[kMaxK];
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int m = mult_dev(a.variant[i]);
+    const int hout = layer == 0 ? H1 : layer == 1 ? H2 : H3;
+    const int cout = layer == 0 ? 16 * m : layer == 1 ? 32 * m : 64 * m;
+    ne[i] = min(a.q.counts[a.pred[i]], a.esc_cap);
+    outs[i] = (int64_t)hout * hout * cout;
+    total += ne[i] * outs[i];
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
+    int slot = 0;
+    int64_t rem = gi;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int64_t c = ne[i] * outs[i];
+      if (rem < c) { slot = i; break; }
+      rem -= c;
+    }
+    const int e = (int)(rem / outs[slot]);
+    const int oi = (int)(rem % outs[slot]);
+    const int m = mult_dev(a.variant[slot]);
+    const int cout = layer == 0 ? 16 * m : layer == 1 ? 32 * m : 64 * m;
+    const int p = oi / cout, o = oi % cout;
+    const uint32_t idx = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + e]);
+    double* act = a.esc_act[slot] + (int64_t)e * a.esc_stride;
+    const double* in = layer == 0 ? nullptr : layer == 1 ? act + act_off(0, m) : act + act_off(1, m);
+    double* out = layer == 1 ? act + act_off(1, m) : act;   // layers 1 and 3 share a region
+    out[oi] = conv64_at(a, slot, layer, idx, in, p, o);
+  }
+}
+
+// Pool, FC, margin and decision: one wave per escalated entry.
+__device__ inline void cnn_head64(const CnnArgs& a, const Forward& f, int slot, uint32_t e, const double* act3,
+                                  bool active) {
+  const int lane = threadIdx.x & 63;
+  const int m = mult_dev(a.variant[slot]);
+  const int C3 = 64 * m;
+  double zp[kClasses];
+#pragma unroll
+  for (int c = 0; c < kClasses; ++c) zp[c] = 0.0;
+  if (active) {
+    const float* fw = a.fc_w[slot];
+    for (int ch = lane; ch < C3; ch += 64) {
+      double sum = 0.0;
+      for (int p = 0; p < H3 * H3; ++p) sum += act3[p * C3 + ch];
+      const double gch = sum / 64.0;
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) zp[c] = fma(gch, (double)fw[ch * kClasses + c], zp[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kClasses; ++c)
+    for (int o = 32; o >= 1; o >>= 1) zp[c] += __shfl_xor(zp[c], o);
+  const int k = a.pred[slot];
+  const uint32_t idx = entry_idx(e);
+  bool lead = active && lane == 0;
+  bool pass = false;
+  if (lead) {
+    double z[kClasses];
+    for (int c = 0; c < kClasses; ++c) z[c] = (double)a.fc_b[slot][c] + zp[c];
+    if (f.logits != nullptr)
+      for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = z[c];
+    pass = class_margin(z, a.class_mask[slot]) > (double)theta_of(f, k, idx);
+  }
+  if (f.logits == nullptr) forward_decision(f, k, e, lead, false, pass);
+}
+
+__global__ __launch_bounds__(256) void cnn_f64_head_kernel(CnnArgs a, Forward f) {
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += min(a.q.counts[a.pred[i]], a.esc_cap);
+  const int wave = threadIdx.x >> 6;
+  const int nw = gridDim.x * 4;
+  for (int base = blockIdx.x * 4; base < total; base += nw) {
+    const int t = base + wave;
+    const bool active = t < total;
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = min(a.q.counts[a.pred[i]], a.esc_cap);
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    if (!active) { slot = 0; off = 0; }
+    const uint32_t e = active ? a.q.entries[(int64_t)a.pred[slot] * a.q.cap + off] : 0u;
+    const double* act3 = a.esc_act[slot] + (int64_t)off * a.esc_stride;
+    cnn_head64(a, f, slot, e, act3, active);
+  }
+}
+
+// Entries beyond esc_cap: one workgroup per entry, per-block scratch.
+__global__ __launch_bounds__(256) void cnn_f64_rest_kernel(CnnArgs a, Forward f) {
   const int tid = threadIdx.x;
   double* A = a.scratch64 + (int64_t)blockIdx.x * a.scratch64_per_block;
   double* B = A + a.scratch64_per_block / 2;
   int total = 0;
-  for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  for (int i = 0; i < a.n_preds; ++i) total += max(0, a.q.counts[a.pred[i]] - a.esc_cap);
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int slot = 0, off = t;
     for (int i = 0; i < a.n_preds; ++i) {
-      int c = a.q.counts[a.pred[i]];
+      const int c = max(0, a.q.counts[a.pred[i]] - a.esc_cap);
       if (off < c) { slot = i; break; }
       off -= c;
     }
+    off += a.esc_cap;
     const int k = a.pred[slot];
     const uint32_t e = a.q.entries[(int64_t)k * a.q.cap + off];
     const uint32_t idx = entry_idx(e);
-    const int m = a.variant[slot] == CNN_W1 ? 1 : a.variant[slot] == CNN_W2 ? 2 : 4;
-    const int C1 = 16 * m, C2 = 32 * m, C3 = 64 * m;
-    // layer 1 -> A [32][32][C1]
-    {
-      const float* W = a.w_canon[slot][0];
-      const float* b = a.b_canon[slot][0];
-      for (int q = tid; q < H1 * H1 * C1; q += 256) {
-        const int o = q % C1, p = q / C1, i = p / H1, j = p % H1;
-        double s = (double)b[o];
-        for (int c = 0; c < 3; ++c)
-          for (int u = 0; u < 3; ++u)
-            for (int v = 0; v < 3; ++v) {
-              const int y = 2 * i + u - 1, x = 2 * j + v - 1;
-              if (y < 0 || x < 0 || y >= H0 || x >= H0) continue;
-              s = fma((double)W[((o * 3 + c) * 3 + u) * 3 + v], frame_norm64(a.fr, idx, y, x, c), s);
-            }
-        A[q] = s > 0.0 ? s : 0.0;
-      }
-    }
+    const int m = mult_dev(a.variant[slot]);
+    for (int q = tid; q < H1 * H1 * 16 * m; q += 256) A[q] = conv64_at(a, slot, 0, idx, nullptr, q / (16 * m), q % (16 * m));
     __syncthreads();
-    // layer 2 -> B [16][16][C2]
-    {
-      const float* W = a.w_canon[slot][1];
-      const float* b = a.b_canon[slot][1];
-      for (int q = tid; q < H2 * H2 * C2; q += 256) {
-        const int o = q % C2, p = q / C2, i = p / H2, j = p % H2;
-        double s = (double)b[o];
-        for (int u = 0; u < 3; ++u)
-          for (int v = 0; v < 3; ++v) {
-            const int y = 2 * i + u - 1, x = 2 * j + v - 1;
-            if (y < 0 || x < 0 || y >= H1 || x >= H1) continue;
-            const double* in = A + (y * H1 + x) * C1;
-            for (int c = 0; c < C1; ++c) s = fma((double)W[((o * C1 + c) * 3 + u) * 3 + v], in[c], s);
-          }
-        B[q] = s > 0.0 ? s : 0.0;
-      }
-    }
+    for (int q = tid; q < H2 * H2 * 32 * m; q += 256) B[q] = conv64_at(a, slot, 1, idx, A, q / (32 * m), q % (32 * m));
     __syncthreads();
-    // layer 3 -> A [8][8][C3]
-    {
-      const float* W = a.w_canon[slot][2];
-      const float* b = a.b_canon[slot][2];
-      for (int q = tid; q < H3 * H3 * C3; q += 256) {
-        const int o = q % C3, p = q / C3, i = p / H3, j = p % H3;
-        double s = (double)b[o];
-        for (int u = 0; u < 3; ++u)
-          for (int v = 0; v < 3; ++v) {
-            const int y = 2 * i + u - 1, x = 2 * j + v - 1;
-            if (y < 0 || x < 0 || y >= H2 || x >= H2) continue;
-            const double* in = B + (y * H2 + x) * C2;
-            for (int c = 0; c < C2; ++c) s = fma((double)W[((o * C2 + c) * 3 + u) * 3 + v], in[c], s);
-          }
-        A[q] = s > 0.0 ? s : 0.0;
-      }
-    }
+    for (int q = tid; q < H3 * H3 * 64 * m; q += 256) A[q] = conv64_at(a, slot, 2, idx, B, q / (64 * m), q % (64 * m));
     __syncthreads();
-    for (int o = tid; o < C3; o += 256) {
-      double s = 0.0;
-      for (int p = 0; p < H3 * H3; ++p) s += A[p * C3 + o];
-      gsh[o] = s / 64.0;
-    }
-    __syncthreads();
-    if (tid < kClasses) {
-      const float* fw = a.fc_w[slot];
-      double z = (double)a.fc_b[slot][tid];
-      for (int ch = 0; ch < C3; ++ch) z = fma(gsh[ch], (double)fw[ch * kClasses + tid], z);
-      zsh[tid] = z;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      bool active = tid == 0;
-      bool pass = false;
-      if (active) {
-        if (f.logits != nullptr) {
-          for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = zsh[c];
-        }
-        double d = class_margin(zsh, a.class_mask[slot]);
-        pass = d > (double)theta_of(f, k, idx);
-      }
-      if (f.logits == nullptr) forward_decision(f, k, e, active, false, pass);
-    }
+    if (tid < 64) cnn_head64(a, f, slot, e, A, true);
     __syncthreads();
   }
 }
@@ -539,7 +596,10 @@ void cnn_pack_layer(int variant, int layer, int prec, const float* w_canon, floa
 void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
   if (a.n_preds == 0) return;
   if (tier == TIER_F64) {
-    hipLaunchKernelGGL(cnn_f64_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    for (int layer = 0; layer < 3; ++layer)
+      hipLaunchKernelGGL(cnn_f64_layer_kernel, dim3(grid * 4), dim3(256), 0, s, a, layer);
+    hipLaunchKernelGGL(cnn_f64_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    hipLaunchKernelGGL(cnn_f64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f);
     return;
   }
   if (a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)

@@ -22,6 +22,8 @@ struct MlpArgs {
   const float* b1_canon[kMaxK];
   float* partial[kMaxK];            // [hidden/64][part_cap][10]
   int64_t part_cap;
+  double* esc_h[kMaxK];             // FP64 tier: partial hidden sums [chunk][esc_cap][hidden]
+  int esc_cap;
   Queues q;
   FrameSrc fr;
   DevState* st;
@@ -43,7 +45,11 @@ struct CnnArgs {
   const float* w_canon[kMaxK][3];   // [co][ci][3][3]
   const float* b_canon[kMaxK][3];
   float pad_raw;                    // raw frame value that normalises to 0
-  double* scratch64;                // FP64 tier: per-block activation scratch
+  const float* wt_canon[kMaxK][3];  // FP64 tier: canonical weights as [ci][3][3][co]
+  double* esc_act[kMaxK];           // FP64 tier: per-entry activations (esc_cap entries per slot)
+  int64_t esc_stride;               // doubles per entry
+  int esc_cap;                      // entries handled layer-parallel; the rest run one per block
+  double* scratch64;                // FP64 tier fallback: per-block activation scratch
   int64_t scratch64_per_block;      // doubles
   Queues q;
   FrameSrc fr;

@@ -262,6 +262,14 @@ __global__ __launch_bounds__(256) void k_res_write(const uint32_t* bits, int64_t
 }
 
 // ---------------------------------------------------------------- session
+// Escalated (FP64) entries per predicate and round evaluated layer-parallel; more run one per
+// block.  HYDRO_ESC_CAP overrides the default (tests use it to exercise the per-block path).
+static int esc_cap_setting() {
+  const char* e = getenv("HYDRO_ESC_CAP");
+  int v = (e && *e) ? atoi(e) : 128;
+  return v < 1 ? 1 : v > 4096 ? 4096 : v;
+}
+
 struct HostModel {
   hydro_model m;
   std::vector<float> w1, b1, w2, b2, fcw, fcb;
@@ -393,6 +401,7 @@ static int pack_models(hydro_session* s) {
   ma = MlpArgs{};
   ca = CnnArgs{};
   ca.pad_raw = pad_raw;
+  const int esc_cap = esc_cap_setting();
   // grouped launches walk their slots in order: most expensive predicates first, so the
   // longest work items start early (longest-processing-time-first)
   std::vector<int> slots_order(s->K);
@@ -440,6 +449,10 @@ static int pack_models(hydro_session* s) {
       if ((rc = upload(s, hm.b1.data(), hm.b1.size(), &dp))) return rc;
       ma.b1_canon[i] = dp;
       if ((rc = sess_alloc(s, (void**)&ma.partial[i], (size_t)(H / 64) * s->cap * kClasses * sizeof(float)))) return rc;
+      {
+        const int nch = (D + 1535) / 1536;   // chunking of the FP64 tier's hidden pass
+        if ((rc = sess_alloc(s, (void**)&ma.esc_h[i], (size_t)nch * esc_cap * H * sizeof(double)))) return rc;
+      }
     } else {
       int i = ca.n_preds++;
       ca.pred[i] = k;
@@ -482,6 +495,14 @@ static int pack_models(hydro_session* s) {
         ca.bias[i][l] = dp;
         if ((rc = upload(s, hm.cw[l].data(), hm.cw[l].size(), &dp))) return rc;
         ca.w_canon[i][l] = dp;
+        {
+          std::vector<float> wt(hm.cw[l].size());
+          for (int o = 0; o < co; ++o)
+            for (int c = 0; c < cin; ++c)
+              for (int t = 0; t < 9; ++t) wt[((size_t)c * 9 + t) * co + o] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
+          if ((rc = upload(s, wt.data(), wt.size(), &dp))) return rc;
+          ca.wt_canon[i][l] = dp;
+        }
         if ((rc = upload(s, hm.cb[l].data(), hm.cb[l].size(), &dp))) return rc;
         ca.b_canon[i][l] = dp;
         cin = co;
@@ -494,6 +515,7 @@ static int pack_models(hydro_session* s) {
       ca.fc_b[i] = dp;
     }
   }
+  ma.esc_cap = esc_cap;
   if (ca.n_preds > 0) {
     // FP64 tier scratch: two activation buffers per block (largest layer output)
     int64_t per = 0;
@@ -508,6 +530,15 @@ static int pack_models(hydro_session* s) {
     ca.scratch64_per_block = 2 * per;
     int rc = sess_alloc(s, (void**)&ca.scratch64, (size_t)ca.scratch64_per_block * s->n_cu * sizeof(double));
     if (rc) return rc;
+    // layer-parallel FP64 tier: per entry, layer-1 output then layer-2 output
+    ca.esc_stride = 0;
+    for (int i = 0; i < ca.n_preds; ++i) {
+      const int m = ca.variant[i] == CNN_W1 ? 1 : ca.variant[i] == CNN_W2 ? 2 : 4;
+      ca.esc_stride = std::max<int64_t>(ca.esc_stride, (int64_t)32 * 32 * 16 * m + 16 * 16 * 32 * m);
+    }
+    ca.esc_cap = esc_cap;
+    for (int i = 0; i < ca.n_preds; ++i)
+      if ((rc = sess_alloc(s, (void**)&ca.esc_act[i], (size_t)esc_cap * ca.esc_stride * sizeof(double)))) return rc;
   }
   return HYDRO_OK;
 }
@@ -764,6 +795,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
         b.pred[0] = a.pred[i]; b.d_in[0] = a.d_in[i]; b.hidden[0] = a.hidden[i]; b.class_mask[0] = a.class_mask[i];
         b.w1_bf[0] = a.w1_bf[i]; b.w1_f32[0] = a.w1_f32[i]; b.b1_fold[0] = a.b1_fold[i]; b.w2[0] = a.w2[i];
         b.b2[0] = a.b2[i]; b.w1_canon[0] = a.w1_canon[i]; b.b1_canon[0] = a.b1_canon[i]; b.partial[0] = a.partial[i];
+        b.esc_h[0] = a.esc_h[i];
         launch_mlp_pass(b, f, tier, grid, st);
       }
     }
@@ -787,6 +819,8 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
           b.w_canon[0][l] = a.w_canon[i][l]; b.b_canon[0][l] = a.b_canon[i][l];
         }
         b.fc_w[0] = a.fc_w[i]; b.fc_b[0] = a.fc_b[i];
+        b.esc_act[0] = a.esc_act[i];
+        for (int l = 0; l < 3; ++l) b.wt_canon[0][l] = a.wt_canon[i][l];
         launch_cnn_pass(b, f, tier, s->n_cu, st);
       }
     }

@@ -278,82 +278,203 @@ __global__ __launch_bounds__(256) void mlp_head_kernel(MlpArgs a, Forward f) {
   }
 }
 
-// FP64 tier: up to 8 entries of one predicate per work item; frames normalised in fp64
-// exactly as the definition states; canonical fp32 weights widened to fp64.
-constexpr int F64_B = 4;
-constexpr int F64_DCH = 256;
+// FP64 tier: frames normalised in fp64 exactly as defined; canonical fp32 weights widened to
+// fp64.  The first esc_cap escalated entries of each predicate are evaluated across many
+// workgroups: work item = (predicate, group of 8 entries, 256 hidden units, 1536-long chunk of
+// the input) -> partial hidden sums; a head (one wave per entry) adds the chunks, applies
+// ReLU, GEMM2, the margin and the decision.  Entries beyond esc_cap run one group per block.
+constexpr int F64_B = 8;
+constexpr int F64_DCH = 1536;
 
-__global__ __launch_bounds__(256) void mlp_f64_kernel(MlpArgs a, Forward f) {
-  __shared__ double xs[F64_B][F64_DCH];
-  __shared__ double zred[4][F64_B][kClasses];
+__device__ inline double frame_norm64_flat(const FrameSrc& fr, uint32_t idx, int64_t d) {
+  const int64_t o = (int64_t)idx * fr.elems + d;
+  double x;
+  if (fr.dtype == HYDRO_DTYPE_BF16) x = (double)(float)static_cast<const __bf16*>(fr.base)[o];
+  else if (fr.dtype == HYDRO_DTYPE_U8) x = (double)static_cast<const uint8_t*>(fr.base)[o] / 255.0;
+  else x = (double)static_cast<const float*>(fr.base)[o];
+  return (x - 0.5) * 4.0;
+}
+
+__global__ __launch_bounds__(256) void mlp_f64_hidden_kernel(MlpArgs a) {
+  __shared__ double xs[F64_B][256];
   __shared__ uint32_t ents[F64_B];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   int total = 0;
-  for (int i = 0; i < a.n_preds; ++i) total += (a.q.counts[a.pred[i]] + F64_B - 1) / F64_B;
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int ne = min(a.q.counts[a.pred[i]], a.esc_cap);
+    total += (ne + F64_B - 1) / F64_B * (a.hidden[i] / 256 + (a.hidden[i] % 256 ? 1 : 0)) *
+             ((a.d_in[i] + F64_DCH - 1) / F64_DCH);
+  }
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int slot = 0, off = t;
     for (int i = 0; i < a.n_preds; ++i) {
-      int c = (a.q.counts[a.pred[i]] + F64_B - 1) / F64_B;
+      const int ne = min(a.q.counts[a.pred[i]], a.esc_cap);
+      const int c = (ne + F64_B - 1) / F64_B * (a.hidden[i] / 256 + (a.hidden[i] % 256 ? 1 : 0)) *
+                    ((a.d_in[i] + F64_DCH - 1) / F64_DCH);
       if (off < c) { slot = i; break; }
       off -= c;
     }
     const int k = a.pred[slot];
-    const int cnt = a.q.counts[k];
     const int D = a.d_in[slot], H = a.hidden[slot];
-    const int nb = min(F64_B, cnt - off * F64_B);
-    if (tid < F64_B) ents[tid] = tid < nb ? a.q.entries[(int64_t)k * a.q.cap + off * F64_B + tid] : 0u;
+    const int ne = min(a.q.counts[k], a.esc_cap);
+    const int nch = (D + F64_DCH - 1) / F64_DCH;
+    const int nhb = H / 256 + (H % 256 ? 1 : 0);
+    const int ch = off % nch;
+    const int hb = (off / nch) % nhb;
+    const int grp = off / (nch * nhb);
+    const int nb = min(F64_B, ne - grp * F64_B);
+    if (tid < F64_B) ents[tid] = tid < nb ? a.q.entries[(int64_t)k * a.q.cap + grp * F64_B + tid] : 0u;
+    __syncthreads();
+    const int j = hb * 256 + tid;
+    double s[F64_B];
+#pragma unroll
+    for (int b = 0; b < F64_B; ++b) s[b] = 0.0;
+    const float* W1 = a.w1_canon[slot];
+    const int d_lo = ch * F64_DCH, d_hi = min(D, d_lo + F64_DCH);
+    for (int d0 = d_lo; d0 < d_hi; d0 += 256) {
+      const int dl = min(256, d_hi - d0);
+      for (int q = tid; q < F64_B * 256; q += 256) {
+        const int b = q >> 8, dd = q & 255;
+        xs[b][dd] = (b < nb && dd < dl) ? frame_norm64_flat(a.fr, entry_idx(ents[b]), d0 + dd) : 0.0;
+      }
+      __syncthreads();
+      if (j < H) {
+        for (int dd = 0; dd < dl; ++dd) {
+          const double w = (double)W1[(int64_t)(d0 + dd) * H + j];
+#pragma unroll
+          for (int b = 0; b < F64_B; ++b) s[b] = fma(w, xs[b][dd], s[b]);
+        }
+      }
+      __syncthreads();
+    }
+    if (j < H) {
+      double* hp = a.esc_h[slot] + ((int64_t)ch * a.esc_cap) * H;
+      for (int b = 0; b < nb; ++b) hp[(int64_t)(grp * F64_B + b) * H + j] = s[b];
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline void mlp_head64(const MlpArgs& a, const Forward& f, int slot, uint32_t e, int ei, bool active) {
+  const int lane = threadIdx.x & 63;
+  const int k = a.pred[slot];
+  const int D = a.d_in[slot], H = a.hidden[slot];
+  const int nch = (D + F64_DCH - 1) / F64_DCH;
+  double zp[kClasses];
+#pragma unroll
+  for (int c = 0; c < kClasses; ++c) zp[c] = 0.0;
+  if (active) {
+    const float* b1 = a.b1_canon[slot];
+    const float* w2 = a.w2[slot];
+    for (int j = lane; j < H; j += 64) {
+      double h = (double)b1[j];
+      for (int c = 0; c < nch; ++c) h += a.esc_h[slot][((int64_t)c * a.esc_cap + ei) * H + j];
+      h = h > 0.0 ? h : 0.0;
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) zp[c] = fma(h, (double)w2[j * kClasses + c], zp[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kClasses; ++c)
+    for (int o = 32; o >= 1; o >>= 1) zp[c] += __shfl_xor(zp[c], o);
+  const uint32_t idx = entry_idx(e);
+  const bool lead = active && lane == 0;
+  bool pass = false;
+  if (lead) {
+    double z[kClasses];
+    for (int c = 0; c < kClasses; ++c) z[c] = (double)a.b2[slot][c] + zp[c];
+    if (f.logits != nullptr)
+      for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = z[c];
+    pass = class_margin(z, a.class_mask[slot]) > (double)theta_of(f, k, idx);
+  }
+  if (f.logits == nullptr) forward_decision(f, k, e, lead, false, pass);
+}
+
+__global__ __launch_bounds__(256) void mlp_f64_head_kernel(MlpArgs a, Forward f) {
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += min(a.q.counts[a.pred[i]], a.esc_cap);
+  const int wave = threadIdx.x >> 6;
+  for (int base = blockIdx.x * 4; base < total; base += gridDim.x * 4) {
+    const int t = base + wave;
+    const bool active = t < total;
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = min(a.q.counts[a.pred[i]], a.esc_cap);
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    if (!active) { slot = 0; off = 0; }
+    const uint32_t e = active ? a.q.entries[(int64_t)a.pred[slot] * a.q.cap + off] : 0u;
+    mlp_head64(a, f, slot, e, off, active);
+  }
+}
+
+// Entries beyond esc_cap: groups of 4 per block, the whole input and hidden width in one block.
+constexpr int R64_B = 4;
+constexpr int R64_DCH = 256;
+
+__global__ __launch_bounds__(256) void mlp_f64_rest_kernel(MlpArgs a, Forward f) {
+  __shared__ double xs[R64_B][R64_DCH];
+  __shared__ double zred[4][R64_B][kClasses];
+  __shared__ uint32_t ents[R64_B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += (max(0, a.q.counts[a.pred[i]] - a.esc_cap) + R64_B - 1) / R64_B;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = (max(0, a.q.counts[a.pred[i]] - a.esc_cap) + R64_B - 1) / R64_B;
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    const int k = a.pred[slot];
+    const int rest = a.q.counts[k] - a.esc_cap;
+    const int D = a.d_in[slot], H = a.hidden[slot];
+    const int nb = min(R64_B, rest - off * R64_B);
+    if (tid < R64_B) ents[tid] = tid < nb ? a.q.entries[(int64_t)k * a.q.cap + a.esc_cap + off * R64_B + tid] : 0u;
     __syncthreads();
     constexpr int JMAX = 8;            // hidden units per thread (H <= 2048)
-    double s[JMAX][F64_B];
+    double s[JMAX][R64_B];
 #pragma unroll
     for (int j = 0; j < JMAX; ++j)
 #pragma unroll
-      for (int b = 0; b < F64_B; ++b) s[j][b] = 0.0;
+      for (int b = 0; b < R64_B; ++b) s[j][b] = 0.0;
     const float* W1 = a.w1_canon[slot];
-    for (int d0 = 0; d0 < D; d0 += F64_DCH) {
-      for (int q = tid; q < F64_B * F64_DCH; q += blockDim.x) {
-        int b = q / F64_DCH, dd = q % F64_DCH;
-        double x = 0.0;
-        if (b < nb && d0 + dd < D) {
-          int64_t o = (int64_t)entry_idx(ents[b]) * a.fr.elems + d0 + dd;
-          if (a.fr.dtype == HYDRO_DTYPE_BF16) x = (double)(float)static_cast<const __bf16*>(a.fr.base)[o];
-          else if (a.fr.dtype == HYDRO_DTYPE_U8) x = (double)static_cast<const uint8_t*>(a.fr.base)[o] / 255.0;
-          else x = (double)static_cast<const float*>(a.fr.base)[o];
-          x = (x - 0.5) * 4.0;
-        }
-        xs[b][dd] = x;
+    for (int d0 = 0; d0 < D; d0 += R64_DCH) {
+      for (int q = tid; q < R64_B * R64_DCH; q += blockDim.x) {
+        const int b = q / R64_DCH, dd = q % R64_DCH;
+        xs[b][dd] = (b < nb && d0 + dd < D) ? frame_norm64_flat(a.fr, entry_idx(ents[b]), d0 + dd) : 0.0;
       }
       __syncthreads();
-      const int dlim = min(F64_DCH, D - d0);
+      const int dlim = min(R64_DCH, D - d0);
       for (int dd = 0; dd < dlim; ++dd) {
         const float* wr = W1 + (int64_t)(d0 + dd) * H;
 #pragma unroll
         for (int j = 0; j < JMAX; ++j) {
-          int col = tid + j * 256;
+          const int col = tid + j * 256;
           if (col < H) {
-            double w = (double)wr[col];
+            const double w = (double)wr[col];
 #pragma unroll
-            for (int b = 0; b < F64_B; ++b) s[j][b] = fma(w, xs[b][dd], s[j][b]);
+            for (int b = 0; b < R64_B; ++b) s[j][b] = fma(w, xs[b][dd], s[j][b]);
           }
         }
       }
       __syncthreads();
     }
-    // h = ReLU(s + b1); z partial = h W2
-    double zp[F64_B][kClasses];
+    double zp[R64_B][kClasses];
 #pragma unroll
-    for (int b = 0; b < F64_B; ++b)
+    for (int b = 0; b < R64_B; ++b)
 #pragma unroll
       for (int c = 0; c < kClasses; ++c) zp[b][c] = 0.0;
     const float* b1 = a.b1_canon[slot];
     const float* w2 = a.w2[slot];
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
-      int col = tid + j * 256;
+      const int col = tid + j * 256;
       if (col < H) {
-        double bb = (double)b1[col];
+        const double bb = (double)b1[col];
 #pragma unroll
-        for (int b = 0; b < F64_B; ++b) {
+        for (int b = 0; b < R64_B; ++b) {
           double h = s[j][b] + bb;
           h = h > 0.0 ? h : 0.0;
 #pragma unroll
@@ -362,7 +483,7 @@ __global__ __launch_bounds__(256) void mlp_f64_kernel(MlpArgs a, Forward f) {
       }
     }
 #pragma unroll
-    for (int b = 0; b < F64_B; ++b)
+    for (int b = 0; b < R64_B; ++b)
 #pragma unroll
       for (int c = 0; c < kClasses; ++c) {
         double v = zp[b][c];
@@ -371,9 +492,9 @@ __global__ __launch_bounds__(256) void mlp_f64_kernel(MlpArgs a, Forward f) {
       }
     __syncthreads();
     if (wave == 0) {
-      bool active = lane < nb;
+      const bool active = lane < nb;
       bool pass = false;
-      uint32_t e = active ? ents[lane] : 0u;
+      const uint32_t e = active ? ents[lane] : 0u;
       if (active) {
         double z[kClasses];
         const float* b2 = a.b2[slot];
@@ -381,8 +502,7 @@ __global__ __launch_bounds__(256) void mlp_f64_kernel(MlpArgs a, Forward f) {
           z[c] = (double)b2[c] + ((zred[0][lane][c] + zred[1][lane][c]) + (zred[2][lane][c] + zred[3][lane][c]));
         if (f.logits != nullptr)
           for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)entry_idx(e) * kClasses + c] = z[c];
-        double d = class_margin(z, a.class_mask[slot]);
-        pass = d > (double)theta_of(f, k, entry_idx(e));
+        pass = class_margin(z, a.class_mask[slot]) > (double)theta_of(f, k, entry_idx(e));
       }
       if (f.logits == nullptr) forward_decision(f, k, e, active, false, pass);
     }
@@ -394,7 +514,9 @@ __global__ __launch_bounds__(256) void mlp_f64_kernel(MlpArgs a, Forward f) {
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
   if (a.n_preds == 0) return;
   if (tier == TIER_F64) {
-    hipLaunchKernelGGL(mlp_f64_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    hipLaunchKernelGGL(mlp_f64_hidden_kernel, dim3(grid * 2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mlp_f64_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    hipLaunchKernelGGL(mlp_f64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f);
     return;
   }
   if (a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)

@@ -106,3 +106,22 @@ def test_cnn_static_cost_routes_are_reproducible(c2):
         s.close()
     assert runs[0][0] == runs[1][0]
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("esc_cap", [None, "3"])
+def test_cnn_fp64_tier_heavy(monkeypatch, esc_cap):
+    """A huge FP32 band sends most decisions to the FP64 tier (layer-parallel path, and with a
+    tiny cap the one-entry-per-block path too); ids must still equal the oracle's."""
+    if esc_cap:
+        monkeypatch.setenv("HYDRO_ESC_CAP", esc_cap)
+    c = case(2, 1024)
+    pol = hydro.make_policy("score", precision="fp32", tau32=0.5, wave=512)
+    s = hydro.Session(c.specs(), pol, 64, c.n)
+    s.push(c.device_frames(), c.cfg.dtype, c.pt.thresholds, c.seg_len)
+    ids, stats = s.finish()
+    esc = [st["escalated"] for st in stats]
+    log(f"[gpu] fp64-heavy cap={esc_cap}: escalated={esc}")
+    assert sum(esc) > 100
+    assert np.array_equal(ids, c.expect)
+    check_stats(stats, c.n, ids.size)
+    s.close()

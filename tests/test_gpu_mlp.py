@@ -129,3 +129,18 @@ def test_capacity_error(c1):
         s.push(c1.device_frames()[:200].contiguous(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
     assert e.value.code == hydro.ECAPACITY
     s.close()
+
+
+@pytest.mark.parametrize("esc_cap", [None, "5"])
+def test_mlp_fp64_tier_heavy(c1, monkeypatch, esc_cap):
+    if esc_cap:
+        monkeypatch.setenv("HYDRO_ESC_CAP", esc_cap)
+    pol = hydro.make_policy("score", precision="bf16", tau=1.0, tau32=0.5, wave=512)
+    s = _session(c1, pol)
+    s.push(c1.device_frames(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, stats = s.finish()
+    esc = [st["escalated"] for st in stats]
+    log(f"[gpu] mlp fp64-heavy cap={esc_cap}: escalated={esc}")
+    assert sum(esc) > 100
+    assert np.array_equal(ids, c1.expect)
+    s.close()
