@@ -48,13 +48,15 @@ __device__ inline typename Mf<T>::frag ld_frag(const T* p) {
 
 // geometry
 constexpr int H0 = 64, H1 = 32, H2 = 16, H3 = 8;
-constexpr int FR_W = H0 + 1;        // frame row stride in pixels (top/left border)
-constexpr int S1_W = H1 + 1;
+constexpr int NTHR = 512;           // 8 wave64s per workgroup
+constexpr int FRS = 200;            // FR row stride (bf16 elements): 5 unused, border pixel, 64 pixels
+constexpr int FR_X0 = 8;            // element offset of pixel 0 in an FR row (16-byte aligned)
+constexpr int S1_W = H1 + 1;        // layer-1 slab row stride in pixels (top/left border)
 constexpr int L2_W = H2 + 1;
 constexpr int CB1 = 16;             // layer-1 channels per slab
 
 template <typename T> struct CnnLds {
-  static constexpr int FR_BYTES = FR_W * FR_W * 4 * 2;
+  static constexpr int FR_BYTES = (H0 + 1) * FRS * 2;
   static constexpr int S1_OFF = (FR_BYTES + 15) / 16 * 16;
   static constexpr int S1_BYTES = S1_W * S1_W * CB1 * (int)sizeof(T);
   static constexpr int L2_BYTES_MAX = L2_W * L2_W * 128 * (int)sizeof(T);
@@ -64,9 +66,10 @@ template <typename T> struct CnnLds {
 constexpr int DBUF = 64;
 
 // packed-layer geometry: [slab][kstep][ntile][64][KPL]
+// layer 1: K = 27 in (row u, column v, channel c) order, k = 9u + 3v + c, padded to KSTEP
 template <typename T>
 __host__ __device__ constexpr int cnn_ksteps(int layer, int m) {
-  return layer == 0 ? (36 + Mf<T>::KSTEP - 1) / Mf<T>::KSTEP
+  return layer == 0 ? (27 + Mf<T>::KSTEP - 1) / Mf<T>::KSTEP
        : layer == 1 ? (9 * CB1 + Mf<T>::KSTEP - 1) / Mf<T>::KSTEP
                     : 9 * 32 * m / Mf<T>::KSTEP;
 }
@@ -74,7 +77,7 @@ __host__ __device__ constexpr int cnn_slabs(int layer, int m) { return layer == 
 __host__ __device__ constexpr int cnn_ntiles(int layer, int m) { return layer == 0 ? 1 : layer == 1 ? 2 * m : 4 * m; }
 
 struct CnnShared {
-  float gbuf[256];
+  float gpart[2][256];
   float z[kClasses];
   uint32_t d_e[DBUF];
   uint8_t d_k[DBUF];
@@ -83,9 +86,7 @@ struct CnnShared {
   unsigned long long ticks[kMaxK];
 };
 
-template <typename T>
-__device__ void flush_decisions(const Forward& f, CnnShared& sh, int k_total_slots, const int* pred) {
-  // called by all threads; wave 0 forwards
+__device__ void flush_decisions(const Forward& f, CnnShared& sh, int n_slots, const int* pred) {
   __syncthreads();
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
@@ -94,7 +95,7 @@ __device__ void flush_decisions(const Forward& f, CnnShared& sh, int k_total_slo
     uint32_t e = active ? sh.d_e[lane] : 0u;
     int k = active ? (int)sh.d_k[lane] : -1;
     uint8_t fl = active ? sh.d_f[lane] : 0;
-    for (int i = 0; i < k_total_slots; ++i) {
+    for (int i = 0; i < n_slots; ++i) {
       int kk = pred[i];
       if (__ballot(active && k == kk) == 0) continue;
       forward_decision(f, kk, e, active && k == kk, (fl & 2) != 0, (fl & 1) != 0);
@@ -105,51 +106,76 @@ __device__ void flush_decisions(const Forward& f, CnnShared& sh, int k_total_slo
   __syncthreads();
 }
 
-// One frame through the network.  Returns (in sh.z, valid after the final barrier) the logits.
+// Raw frame bytes held in registers between the issue of their loads and their LDS store
+// (the next frame is fetched while the current one is in layer 3).
+struct FramePrefetch {
+  uint4 v[3];
+};
+
+__device__ inline void frame_issue(const CnnArgs& a, uint32_t idx, FramePrefetch& pf) {
+  const int tid = threadIdx.x;
+  if (a.fr.dtype == HYDRO_DTYPE_BF16) {
+    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const __bf16*>(a.fr.base) + (int64_t)idx * a.fr.elems);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) pf.v[r] = src[tid + r * NTHR];      // 1536 chunks of 8 elements
+  } else {
+    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(a.fr.base) + (int64_t)idx * a.fr.elems);
+    pf.v[0] = src[tid];                                              // 768 chunks of 16 elements
+    if (tid + NTHR < 768) pf.v[1] = src[tid + NTHR];
+  }
+}
+
+// Store a prefetched frame into FR and (re)write the borders of FR and the layer-1 slab.
+template <typename T>
+__device__ inline void frame_store(const CnnArgs& a, const FramePrefetch& pf, unsigned char* region) {
+  const int tid = threadIdx.x;
+  __bf16* FR = reinterpret_cast<__bf16*>(region);
+  if (a.fr.dtype == HYDRO_DTYPE_BF16) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int q = tid + r * NTHR, y = q / 24, c = q % 24;
+      *reinterpret_cast<uint4*>(FR + (y + 1) * FRS + FR_X0 + c * 8) = pf.v[r];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = tid + r * NTHR;
+      if (q < 768) {
+        const int y = q / 12, c = q % 12;
+        const uint8_t* b = reinterpret_cast<const uint8_t*>(&pf.v[r]);
+        alignas(16) __bf16 o[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) o[j] = static_cast<__bf16>((float)b[j]);
+        uint4* d = reinterpret_cast<uint4*>(FR + (y + 1) * FRS + FR_X0 + c * 16);
+        d[0] = reinterpret_cast<const uint4*>(o)[0];
+        d[1] = reinterpret_cast<const uint4*>(o)[1];
+      }
+    }
+  }
+  const __bf16 padv = static_cast<__bf16>(a.pad_raw);
+  for (int e = tid; e < FRS; e += NTHR) FR[e] = padv;                              // top border row
+  for (int e = tid; e < H0 * 3; e += NTHR) FR[(e / 3 + 1) * FRS + FR_X0 - 3 + e % 3] = padv;  // left border
+  T* S1 = reinterpret_cast<T*>(region + CnnLds<T>::S1_OFF);
+  for (int p = tid; p < (2 * S1_W - 1) * CB1; p += NTHR) {
+    const int q = p / CB1, c = p % CB1;
+    const int y = q < S1_W ? 0 : q - S1_W + 1, x = q < S1_W ? q : 0;
+    S1[(y * S1_W + x) * CB1 + c] = static_cast<T>(0.f);
+  }
+}
+
+// One frame through the network (FR already holds it).  Writes the logits to sh.z; if
+// next_valid, fetches the next frame into FR (valid after the final barrier).
 template <typename T, int M>
-__device__ void cnn_frame(const CnnArgs& a, int slot, uint32_t idx, unsigned char* region, CnnShared& sh) {
-  constexpr int C1 = 16 * M, C2 = 32 * M, C3 = 64 * M;
+__device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, bool next_valid,
+                          uint32_t next_idx) {
+  constexpr int C2 = 32 * M, C3 = 64 * M;
   constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
   typedef typename Mf<T>::frag frag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
 
-  __bf16* FR = reinterpret_cast<__bf16*>(region);
+  const __bf16* FR = reinterpret_cast<const __bf16*>(region);
   T* S1 = reinterpret_cast<T*>(region + CnnLds<T>::S1_OFF);
   T* L2 = reinterpret_cast<T*>(region);
-
-  // ---- frame -> FR (raw values, 4th channel 0, border = pad_raw)
-  {
-    const __bf16 padv = static_cast<__bf16>(a.pad_raw);
-    const __bf16 zero = static_cast<__bf16>(0.f);
-    const int64_t base = (int64_t)idx * a.fr.elems;
-    for (int p = tid; p < H0 * H0; p += 256) {
-      const int y = p >> 6, x = p & 63;
-      __bf16 c0, c1, c2;
-      if (a.fr.dtype == HYDRO_DTYPE_BF16) {
-        const __bf16* src = static_cast<const __bf16*>(a.fr.base) + base + p * 3;
-        c0 = src[0]; c1 = src[1]; c2 = src[2];
-      } else {
-        const uint8_t* src = static_cast<const uint8_t*>(a.fr.base) + base + p * 3;
-        c0 = static_cast<__bf16>((float)src[0]);
-        c1 = static_cast<__bf16>((float)src[1]);
-        c2 = static_cast<__bf16>((float)src[2]);
-      }
-      __bf16* d = FR + ((y + 1) * FR_W + (x + 1)) * 4;
-      d[0] = c0; d[1] = c1; d[2] = c2; d[3] = zero;
-    }
-    for (int p = tid; p < 2 * FR_W - 1; p += 256) {
-      const int y = p < FR_W ? 0 : p - FR_W + 1, x = p < FR_W ? p : 0;
-      __bf16* d = FR + (y * FR_W + x) * 4;
-      d[0] = padv; d[1] = padv; d[2] = padv; d[3] = zero;
-    }
-    // S1 border (top row, left column) is zero in normalised space
-    for (int p = tid; p < (2 * S1_W - 1) * CB1; p += 256) {
-      const int q = p / CB1, c = p % CB1;
-      const int y = q < S1_W ? 0 : q - S1_W + 1, x = q < S1_W ? q : 0;
-      S1[(y * S1_W + x) * CB1 + c] = static_cast<T>(0.f);
-    }
-  }
-  __syncthreads();
 
   const T* const* wpk;
   if constexpr (sizeof(T) == 2) wpk = reinterpret_cast<const T* const*>(a.w_bf[slot]);
@@ -160,77 +186,90 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, uint32_t idx, unsigned cha
 
   // ---- layer 1 (slab by slab) interleaved with layer-2 accumulation
   constexpr int NT2 = 2 * M;
-  floatx4 acc2[4][NT2];
+  floatx4 acc2[2][NT2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int j = 0; j < NT2; ++j) acc2[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
 
   constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
   for (int slab = 0; slab < M; ++slab) {
-    // layer 1: 64 m-tiles of 16 positions, one 16-channel n-tile; wave w owns m-tiles 16w..16w+15
+    // layer 1: 64 m-tiles (16 positions each), one 16-channel n-tile; wave w owns 8w..8w+7
     const frag* w1p = reinterpret_cast<const frag*>(wpk[0]) + (size_t)slab * KS1 * 64;
-    for (int chunk = 0; chunk < 4; ++chunk) {
+    frag w1f[KS1];
+#pragma unroll
+    for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1p[ks * 64 + lane];
+    const float bb1 = b1[slab * CB1 + l16];
+#pragma unroll
+    for (int chunk = 0; chunk < 2; ++chunk) {
       floatx4 acc[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = (floatx4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ks = 0; ks < KS1; ++ks) {
-        frag bw = w1p[ks * 64 + lane];
+      for (int q = 0; q < 4; ++q) {
+        const int mt = wave * 8 + chunk * 4 + q;
+        const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
+        // im2col row of output (i, j): FR row 2i+u, elements 5 + 6j + (3v + c)
+        const __bf16* rowp = FR + 5 + 6 * j;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int mt = wave * 16 + chunk * 4 + q;
-          const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
+        for (int ks = 0; ks < KS1; ++ks) {
           frag av;
           if constexpr (sizeof(T) == 2) {
-            // 8 k values = taps (k0/4, k0/4 + 1), 4 channels each
-            const int k0 = ks * 32 + 8 * g;
-            const int t0 = k0 >> 2, t1 = t0 + 1;
-            uint2 v0 = {0u, 0u}, v1 = {0u, 0u};
-            if (t0 < 9) v0 = *reinterpret_cast<const uint2*>(FR + ((2 * i + t0 / 3) * FR_W + 2 * j + t0 % 3) * 4);
-            if (t1 < 9) v1 = *reinterpret_cast<const uint2*>(FR + ((2 * i + t1 / 3) * FR_W + 2 * j + t1 % 3) * 4);
-            uint4 u = {v0.x, v0.y, v1.x, v1.y};
-            av = *reinterpret_cast<const bf16x8*>(&u);
+            alignas(16) __bf16 t8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int k = ks * 32 + 8 * g + e;
+              t8[e] = k < 27 ? rowp[(2 * i + k / 9) * FRS + k % 9] : static_cast<__bf16>(0.f);
+            }
+            av = *reinterpret_cast<const bf16x8*>(t8);
           } else {
-            const int k = ks * 4 + g;          // tap = ks, channel = g
-            const int t = k >> 2, c = k & 3;
-            av = (float)FR[((2 * i + t / 3) * FR_W + 2 * j + t % 3) * 4 + c];
+            const int k = ks * 4 + g;
+            av = k < 27 ? (float)rowp[(2 * i + k / 9) * FRS + k % 9] : 0.f;
           }
-          acc[q] = mfma(av, bw, acc[q]);
+          acc[q] = mfma(av, w1f[ks], acc[q]);
         }
       }
-      const float bb = b1[slab * CB1 + l16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int mt = wave * 16 + chunk * 4 + q;
+        const int mt = wave * 8 + chunk * 4 + q;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int px = mt * 16 + 4 * g + r, i = px >> 5, j = px & 31;
-          S1[((i + 1) * S1_W + (j + 1)) * CB1 + l16] = static_cast<T>(fmaxf(acc[q][r] + bb, 0.f));
+          S1[((i + 1) * S1_W + (j + 1)) * CB1 + l16] = static_cast<T>(fmaxf(acc[q][r] + bb1, 0.f));
         }
       }
     }
     __syncthreads();
-    // layer 2 partial: K = 9 taps x 16 channels of this slab; wave w owns m-tiles 4w..4w+3
+    // layer 2 partial: K = 9 taps x 16 channels of this slab; wave w owns m-tiles 2w, 2w+1
     const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64;
+    frag bcur[NT2];
+#pragma unroll
+    for (int nt = 0; nt < NT2; ++nt) bcur[nt] = w2p[nt * 64 + lane];
 #pragma unroll 1
     for (int ks = 0; ks < KS2; ++ks) {
+      frag bnext[NT2];
+      if (ks + 1 < KS2) {
+#pragma unroll
+        for (int nt = 0; nt < NT2; ++nt) bnext[nt] = w2p[((ks + 1) * NT2 + nt) * 64 + lane];
+      }
       const int k0 = ks * KSTEP + KPL * g;
       int t = k0 / CB1;
       const int c0 = k0 % CB1;
       if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
       const int u = t / 3, v = t % 3;
-      frag av[4];
+      frag av[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int px = (wave * 4 + q) * 16 + l16, i = px >> 4, j = px & 15;
+      for (int q = 0; q < 2; ++q) {
+        const int px = (wave * 2 + q) * 16 + l16, i = px >> 4, j = px & 15;
         av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * CB1 + c0);
       }
 #pragma unroll
-      for (int nt = 0; nt < NT2; ++nt) {
-        frag bw = w2p[(ks * NT2 + nt) * 64 + lane];
+      for (int nt = 0; nt < NT2; ++nt)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc2[q][nt] = mfma(av[q], bw, acc2[q][nt]);
+        for (int q = 0; q < 2; ++q) acc2[q][nt] = mfma(av[q], bcur[nt], acc2[q][nt]);
+      if (ks + 1 < KS2) {
+#pragma unroll
+        for (int nt = 0; nt < NT2; ++nt) bcur[nt] = bnext[nt];
       }
     }
     __syncthreads();
@@ -242,76 +281,98 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, uint32_t idx, unsigned cha
     const int ch = nt * 16 + l16;
     const float bb = b2[ch];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int px = (wave * 4 + q) * 16 + 4 * g + r, i = px >> 4, j = px & 15;
+        const int px = (wave * 2 + q) * 16 + 4 * g + r, i = px >> 4, j = px & 15;
         L2[((i + 1) * L2_W + (j + 1)) * C2 + ch] = static_cast<T>(fmaxf(acc2[q][nt][r] + bb, 0.f));
       }
   }
-  for (int p = tid; p < (2 * L2_W - 1) * C2; p += 256) {
+  for (int p = tid; p < (2 * L2_W - 1) * C2; p += NTHR) {
     const int qq = p / C2, c = p % C2;
     const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
     L2[(y * L2_W + x) * C2 + c] = static_cast<T>(0.f);
   }
+  FramePrefetch pf;
+  if (next_valid) frame_issue(a, next_idx, pf);
   __syncthreads();
 
-  // ---- layer 3: 4 m-tiles (64 positions) x 4m n-tiles; wave w owns n-tiles M*w .. M*w+M-1
+  // ---- layer 3: 4 m-tiles (64 positions) x 4M n-tiles; wave w: m-tiles 2(w&1), 2(w&1)+1,
+  //      n-tiles (w>>1)*M .. (w>>1)*M + M - 1
   constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
-  floatx4 acc3[4][M];
+  const int mh = wave & 1, ng = wave >> 1;
+  floatx4 acc3[2][M];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int j = 0; j < M; ++j) acc3[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-  const frag* w3p = reinterpret_cast<const frag*>(wpk[2]);
+  const frag* w3p = reinterpret_cast<const frag*>(wpk[2]) + (size_t)(ng * M) * 64 + lane;
+  frag b3cur[M];
+#pragma unroll
+  for (int n = 0; n < M; ++n) b3cur[n] = w3p[n * 64];
 #pragma unroll 1
   for (int ks = 0; ks < KS3; ++ks) {
+    frag b3next[M];
+    if (ks + 1 < KS3) {
+#pragma unroll
+      for (int n = 0; n < M; ++n) b3next[n] = w3p[((ks + 1) * NT3 + n) * 64];
+    }
     const int k0 = ks * KSTEP + KPL * g;
     const int t = k0 / C2, c0 = k0 % C2;
     const int u = t / 3, v = t % 3;
-    frag av[4];
+    frag av[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int px = q * 16 + l16, i = px >> 3, j = px & 7;
+    for (int q = 0; q < 2; ++q) {
+      const int px = (mh * 2 + q) * 16 + l16, i = px >> 3, j = px & 7;
       av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2 + c0);
     }
 #pragma unroll
-    for (int n = 0; n < M; ++n) {
-      frag bw = w3p[(ks * NT3 + wave * M + n) * 64 + lane];
+    for (int n = 0; n < M; ++n)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc3[q][n] = mfma(av[q], bw, acc3[q][n]);
+      for (int q = 0; q < 2; ++q) acc3[q][n] = mfma(av[q], b3cur[n], acc3[q][n]);
+    if (ks + 1 < KS3) {
+#pragma unroll
+      for (int n = 0; n < M; ++n) b3cur[n] = b3next[n];
     }
   }
-  // ReLU + pooled sum over the 64 positions
+  // ReLU + pooled partial sums over this wave's 32 positions
 #pragma unroll
   for (int n = 0; n < M; ++n) {
-    const int ch = (wave * M + n) * 16 + l16;
+    const int ch = (ng * M + n) * 16 + l16;
     const float bb = b3[ch];
     float s = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) s += fmaxf(acc3[q][n][r] + bb, 0.f);
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
-    if (g == 0) sh.gbuf[ch] = s * (1.0f / 64.0f);
+    if (g == 0) sh.gpart[mh][ch] = s;
   }
   __syncthreads();
-  // FC: z[c] = fc_b[c] + sum_ch g[ch] Wfc[ch][c]
+  // FC on the pooled vector; meanwhile the next frame goes into FR
   if (tid < kClasses) {
     const float* fw = a.fc_w[slot];
     float z = a.fc_b[slot][tid];
-    for (int ch = 0; ch < C3; ++ch) z += sh.gbuf[ch] * fw[ch * kClasses + tid];
+    for (int ch = 0; ch < C3; ++ch) z += (sh.gpart[0][ch] + sh.gpart[1][ch]) * (1.0f / 64.0f) * fw[ch * kClasses + tid];
     sh.z[tid] = z;
   }
+  if (next_valid) frame_store<T>(a, pf, region);
   __syncthreads();
 }
 
-template <typename T, int M>
-__device__ void cnn_frame_dispatch(const CnnArgs& a, int slot, uint32_t idx, unsigned char* region, CnnShared& sh);
+__device__ inline void decode_entry(const CnnArgs& a, int t, int& slot, int& off) {
+  slot = 0;
+  off = t;
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int c = a.q.counts[a.pred[i]];
+    if (off < c) { slot = i; return; }
+    off -= c;
+  }
+}
 
-template <typename T>
-__global__ __launch_bounds__(256) void cnn_fused_kernel(CnnArgs a, Forward f) {
+template <typename T, int M>
+__global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
   __shared__ __attribute__((aligned(16))) unsigned char region[CnnLds<T>::REGION];
   __shared__ CnnShared sh;
   const int tid = threadIdx.x;
@@ -319,23 +380,30 @@ __global__ __launch_bounds__(256) void cnn_fused_kernel(CnnArgs a, Forward f) {
   if (tid < kMaxK) sh.ticks[tid] = 0;
   int total = 0;
   for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  if ((int)blockIdx.x < total) {
+    int slot, off;
+    decode_entry(a, blockIdx.x, slot, off);
+    FramePrefetch pf;
+    frame_issue(a, entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + off]), pf);
+    frame_store<T>(a, pf, region);
+  }
   __syncthreads();
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    int slot = 0, off = t;
-    for (int i = 0; i < a.n_preds; ++i) {
-      int c = a.q.counts[a.pred[i]];
-      if (off < c) { slot = i; break; }
-      off -= c;
-    }
+    int slot, off;
+    decode_entry(a, t, slot, off);
     const int k = a.pred[slot];
     const uint32_t e = a.q.entries[(int64_t)k * a.q.cap + off];
     const uint32_t idx = entry_idx(e);
-    unsigned long long t0 = wall_clock64();
-    switch (a.variant[slot]) {
-      case CNN_W1: cnn_frame<T, 1>(a, slot, idx, region, sh); break;
-      case CNN_W2: cnn_frame<T, 2>(a, slot, idx, region, sh); break;
-      default: cnn_frame<T, 4>(a, slot, idx, region, sh); break;
+    const int tn = t + gridDim.x;
+    bool next_valid = tn < total;
+    uint32_t next_idx = 0;
+    if (next_valid) {
+      int s2, o2;
+      decode_entry(a, tn, s2, o2);
+      next_idx = entry_idx(a.q.entries[(int64_t)a.pred[s2] * a.q.cap + o2]);
     }
+    unsigned long long t0 = wall_clock64();
+    cnn_frame<T, M>(a, slot, region, sh, next_valid, next_idx);
     if (tid == 0) {
       if (f.logits != nullptr) {
         for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)sh.z[c];
@@ -352,9 +420,9 @@ __global__ __launch_bounds__(256) void cnn_fused_kernel(CnnArgs a, Forward f) {
       sh.ticks[k] += wall_clock64() - t0;
     }
     __syncthreads();
-    if (sh.d_n == DBUF) flush_decisions<T>(f, sh, a.n_preds, a.pred);
+    if (sh.d_n == DBUF) flush_decisions(f, sh, a.n_preds, a.pred);
   }
-  if (f.logits == nullptr) flush_decisions<T>(f, sh, a.n_preds, a.pred);
+  if (f.logits == nullptr) flush_decisions(f, sh, a.n_preds, a.pred);
   __syncthreads();
   if (tid < kMaxK && sh.ticks[tid] && a.count_ticks) atomicAdd(&a.st->r_ticks[tid], sh.ticks[tid]);
 }
@@ -569,10 +637,11 @@ static void pack_t(int variant, int layer, const float* w, float scale, float* o
             int oc, ic, tap;
             bool valid;
             if (layer == 0) {
-              tap = k >> 2;
-              ic = k & 3;
+              // k = 9u + 3v + c
+              tap = (k / 9) * 3 + (k % 9) / 3;
+              ic = k % 3;
               oc = sl * CB1 + n;
-              valid = tap < 9 && ic < 3;
+              valid = k < 27;
             } else if (layer == 1) {
               tap = k / CB1;
               ic = sl * CB1 + k % CB1;
@@ -602,10 +671,33 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
     hipLaunchKernelGGL(cnn_f64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f);
     return;
   }
-  if (a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)
-    hipLaunchKernelGGL(cnn_fused_kernel<__bf16>, dim3(grid), dim3(256), 0, s, a, f);
-  else
-    hipLaunchKernelGGL(cnn_fused_kernel<float>, dim3(grid), dim3(256), 0, s, a, f);
+  // one launch per width class (each instantiation gets its own register allocation); every
+  // launch is persistent over all queues of its class
+  const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;
+  for (int v = CNN_W4; v >= CNN_W1; --v) {
+    CnnArgs b = a;
+    b.n_preds = 0;
+    for (int i = 0; i < a.n_preds; ++i) {
+      if (a.variant[i] != v) continue;
+      const int j = b.n_preds++;
+      b.pred[j] = a.pred[i]; b.variant[j] = a.variant[i]; b.class_mask[j] = a.class_mask[i];
+      for (int l = 0; l < 3; ++l) {
+        b.w_bf[j][l] = a.w_bf[i][l]; b.w_f32[j][l] = a.w_f32[i][l]; b.bias[j][l] = a.bias[i][l];
+        b.w_canon[j][l] = a.w_canon[i][l]; b.b_canon[j][l] = a.b_canon[i][l]; b.wt_canon[j][l] = a.wt_canon[i][l];
+      }
+      b.fc_w[j] = a.fc_w[i]; b.fc_b[j] = a.fc_b[i]; b.esc_act[j] = a.esc_act[i];
+    }
+    if (b.n_preds == 0) continue;
+    if (bf) {
+      if (v == CNN_W1) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 1>), dim3(grid), dim3(NTHR), 0, s, b, f);
+      else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 2>), dim3(grid), dim3(NTHR), 0, s, b, f);
+      else hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 4>), dim3(grid), dim3(NTHR), 0, s, b, f);
+    } else {
+      if (v == CNN_W1) hipLaunchKernelGGL((cnn_fused_kernel<float, 1>), dim3(grid), dim3(NTHR), 0, s, b, f);
+      else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<float, 2>), dim3(grid), dim3(NTHR), 0, s, b, f);
+      else hipLaunchKernelGGL((cnn_fused_kernel<float, 4>), dim3(grid), dim3(NTHR), 0, s, b, f);
+    }
+  }
 }
 
 }  // namespace hydro
