@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--check-sample", type=int, default=2048)
+    ap.add_argument("--errors", type=int, default=4096,
+                    help="frames on which bf16 / fp32 logits and margins are compared with fp64 (0: skip)")
     return ap.parse_args()
 
 
@@ -168,6 +170,28 @@ def main():
         vp = n * max(1, args.steps // 2) / dtp
         out["plain"] = {"value": vp, "unit": "tuples/s", "form": "fp32 first pass, per-predicate launches"}
         out["speedup_vs_plain"] = value / vp
+
+    if args.errors > 0:
+        from oracle import hydro_oracle as ho
+        m = min(args.errors, n)
+        log(f"[bench] logit / margin error on {m} frames")
+        fr_e = frames[:m]
+        _, _, Z = ho.truth_table(fr_e, cfg.dtype, weights, pt.class_masks, pt.thresholds, seg_len,
+                                 return_logits=True)
+        es = hydro.Session(specs, hydro.make_policy(args.route, precision="bf16"), cfg.hw, m)
+        rep = {"frames": m, "tau": float(full_pol.tau), "tau32": float(full_pol.tau32)}
+        for tier, name in ((0, "bf16"), (1, "fp32")):
+            ml, mm, pm = [], [], []
+            for j in range(cfg.k):
+                z = es.logits(j, tier, frames_dev[:m], cfg.dtype)
+                dz = np.abs(z - Z[j])
+                dd = np.abs(ho.predicate_margin(z, pt.class_masks[j]) - ho.predicate_margin(Z[j], pt.class_masks[j]))
+                ml.append(float(dz.max()))
+                mm.append(float(dd.max()))
+                pm.append(float(np.quantile(dd, 0.999)))
+            rep[name] = {"max_logit_err": ml, "max_margin_err": mm, "p999_margin_err": pm}
+        es.close()
+        out["logit_error"] = rep
 
     if not args.no_cpu:
         # FP64 oracle on a bounded, evenly spread sample of the same workload

@@ -55,11 +55,18 @@ constexpr int S1_W = H1 + 1;        // layer-1 slab row stride in pixels (top/le
 constexpr int L2_W = H2 + 1;
 constexpr int CB1 = 16;             // layer-1 channels per slab
 
+// Pixel strides (elements) of the layer-1 slab and the layer-2 output are padded so that the 16
+// lanes of an MFMA row group, which read 16 different pixels, spread over the LDS banks.
+template <typename T> struct Pad {
+  static constexpr int S1P = CB1 + (sizeof(T) == 4 ? 1 : 0);
+  static constexpr int L2E = 16 / (int)sizeof(T);      // extra elements per layer-2 pixel
+};
+
 template <typename T> struct CnnLds {
   static constexpr int FR_BYTES = (H0 + 1) * FRS * 2;
   static constexpr int S1_OFF = (FR_BYTES + 15) / 16 * 16;
-  static constexpr int S1_BYTES = S1_W * S1_W * CB1 * (int)sizeof(T);
-  static constexpr int L2_BYTES_MAX = L2_W * L2_W * 128 * (int)sizeof(T);
+  static constexpr int S1_BYTES = S1_W * S1_W * Pad<T>::S1P * (int)sizeof(T);
+  static constexpr int L2_BYTES_MAX = L2_W * L2_W * (128 + Pad<T>::L2E) * (int)sizeof(T);
   static constexpr int REGION = (S1_OFF + S1_BYTES) > L2_BYTES_MAX ? (S1_OFF + S1_BYTES) : L2_BYTES_MAX;
 };
 
@@ -159,7 +166,7 @@ __device__ inline void frame_store(const CnnArgs& a, const FramePrefetch& pf, un
   for (int p = tid; p < (2 * S1_W - 1) * CB1; p += NTHR) {
     const int q = p / CB1, c = p % CB1;
     const int y = q < S1_W ? 0 : q - S1_W + 1, x = q < S1_W ? q : 0;
-    S1[(y * S1_W + x) * CB1 + c] = static_cast<T>(0.f);
+    S1[(y * S1_W + x) * Pad<T>::S1P + c] = static_cast<T>(0.f);
   }
 }
 
@@ -169,6 +176,7 @@ template <typename T, int M>
 __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, bool next_valid,
                           uint32_t next_idx) {
   constexpr int C2 = 32 * M, C3 = 64 * M;
+  constexpr int S1P = Pad<T>::S1P, C2P = C2 + Pad<T>::L2E;
   constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
   typedef typename Mf<T>::frag frag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
@@ -235,7 +243,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int px = mt * 16 + 4 * g + r, i = px >> 5, j = px & 31;
-          S1[((i + 1) * S1_W + (j + 1)) * CB1 + l16] = static_cast<T>(fmaxf(acc[q][r] + bb1, 0.f));
+          S1[((i + 1) * S1_W + (j + 1)) * S1P + l16] = static_cast<T>(fmaxf(acc[q][r] + bb1, 0.f));
         }
       }
     }
@@ -261,7 +269,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int px = (wave * 2 + q) * 16 + l16, i = px >> 4, j = px & 15;
-        av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * CB1 + c0);
+        av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
       }
 #pragma unroll
       for (int nt = 0; nt < NT2; ++nt)
@@ -285,13 +293,13 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int px = (wave * 2 + q) * 16 + 4 * g + r, i = px >> 4, j = px & 15;
-        L2[((i + 1) * L2_W + (j + 1)) * C2 + ch] = static_cast<T>(fmaxf(acc2[q][nt][r] + bb, 0.f));
+        L2[((i + 1) * L2_W + (j + 1)) * C2P + ch] = static_cast<T>(fmaxf(acc2[q][nt][r] + bb, 0.f));
       }
   }
   for (int p = tid; p < (2 * L2_W - 1) * C2; p += NTHR) {
     const int qq = p / C2, c = p % C2;
     const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
-    L2[(y * L2_W + x) * C2 + c] = static_cast<T>(0.f);
+    L2[(y * L2_W + x) * C2P + c] = static_cast<T>(0.f);
   }
   FramePrefetch pf;
   if (next_valid) frame_issue(a, next_idx, pf);
@@ -324,7 +332,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int px = (mh * 2 + q) * 16 + l16, i = px >> 3, j = px & 7;
-      av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2 + c0);
+      av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
     }
 #pragma unroll
     for (int n = 0; n < M; ++n)
