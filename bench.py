@@ -172,21 +172,27 @@ def main():
         out["speedup_vs_plain"] = value / vp
 
     if args.errors > 0:
-        from oracle import hydro_oracle as ho
+        # error of the bf16 and fp32 passes against the library's FP64 pass (which the parity
+        # tests pin to the oracle to ~1e-15)
         m = min(args.errors, n)
         log(f"[bench] logit / margin error on {m} frames")
-        fr_e = frames[:m]
-        _, _, Z = ho.truth_table(fr_e, cfg.dtype, weights, pt.class_masks, pt.thresholds, seg_len,
-                                 return_logits=True)
         es = hydro.Session(specs, hydro.make_policy(args.route, precision="bf16"), cfg.hw, m)
-        rep = {"frames": m, "tau": float(full_pol.tau), "tau32": float(full_pol.tau32)}
+
+        def margin(z, mask):
+            inside = np.array([(mask >> c) & 1 for c in range(10)], dtype=bool)
+            zin = np.where(inside, z, -np.inf).max(axis=1)
+            zout = np.where(~inside, z, -np.inf).max(axis=1)
+            return zin - zout
+
+        rep = {"frames": m, "reference": "library fp64 pass", "tau": float(full_pol.tau),
+               "tau32": float(full_pol.tau32)}
+        z64 = [es.logits(j, 2, frames_dev[:m], cfg.dtype) for j in range(cfg.k)]
         for tier, name in ((0, "bf16"), (1, "fp32")):
             ml, mm, pm = [], [], []
             for j in range(cfg.k):
                 z = es.logits(j, tier, frames_dev[:m], cfg.dtype)
-                dz = np.abs(z - Z[j])
-                dd = np.abs(ho.predicate_margin(z, pt.class_masks[j]) - ho.predicate_margin(Z[j], pt.class_masks[j]))
-                ml.append(float(dz.max()))
+                dd = np.abs(margin(z, pt.class_masks[j]) - margin(z64[j], pt.class_masks[j]))
+                ml.append(float(np.abs(z - z64[j]).max()))
                 mm.append(float(dd.max()))
                 pm.append(float(np.quantile(dd, 0.999)))
             rep[name] = {"max_logit_err": ml, "max_margin_err": mm, "p999_margin_err": pm}

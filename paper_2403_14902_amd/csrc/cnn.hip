@@ -170,11 +170,26 @@ __device__ inline void frame_store(const CnnArgs& a, const FramePrefetch& pf, un
   }
 }
 
-// One frame through the network (FR already holds it).  Writes the logits to sh.z; if
-// next_valid, fetches the next frame into FR (valid after the final barrier).
+// 4 consecutive channels of one position, stored with one LDS write.
+template <typename T>
+__device__ inline void store4(T* dst, float v0, float v1, float v2, float v3) {
+  if constexpr (sizeof(T) == 2) {
+    alignas(8) __bf16 h[4] = {static_cast<__bf16>(v0), static_cast<__bf16>(v1), static_cast<__bf16>(v2),
+                              static_cast<__bf16>(v3)};
+    *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(h);
+  } else {
+    *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+  }
+}
+
+// One frame through the network (FR already holds it).  The MFMAs compute the transposed
+// products (rows = output channels from the packed weights, columns = positions from LDS), so
+// each lane ends with 4 consecutive channels of one position.  Wave 0 finishes with FC, margin
+// and the decision record; if next_valid, the next frame is stored into FR meanwhile.  Returns
+// the logits in z (wave 0, lane 0 holds all 10).
 template <typename T, int M>
 __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, bool next_valid,
-                          uint32_t next_idx) {
+                          uint32_t next_idx, float* z_out) {
   constexpr int C2 = 32 * M, C3 = 64 * M;
   constexpr int S1P = Pad<T>::S1P, C2P = C2 + Pad<T>::L2E;
   constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
@@ -192,63 +207,66 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   const float* b2 = a.bias[slot][1];
   const float* b3 = a.bias[slot][2];
 
-  // ---- layer 1 (slab by slab) interleaved with layer-2 accumulation
+  // ---- layer-1 im2col fragments of this wave's 8 m-tiles (reused by every slab)
+  constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
   constexpr int NT2 = 2 * M;
+  frag a1[sizeof(T) == 2 ? 8 : 1][KS1];
+  auto gather1 = [&](int mt, int ks) -> frag {
+    const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
+    // im2col row of output (i, j): FR row 2i+u, elements 5 + 6j + (3v + c), k = 9u + 3v + c
+    const __bf16* rowp = FR + 2 * i * FRS + 5 + 6 * j;
+    if constexpr (sizeof(T) == 2) {
+      alignas(16) __bf16 t8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = ks * 32 + 8 * g + e;
+        t8[e] = k < 27 ? rowp[(k / 9) * FRS + k % 9] : static_cast<__bf16>(0.f);
+      }
+      return *reinterpret_cast<const bf16x8*>(t8);
+    } else {
+      const int k = ks * 4 + g;
+      return k < 27 ? (float)rowp[(k / 9) * FRS + k % 9] : 0.f;
+    }
+  };
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) a1[q][ks] = gather1(wave * 8 + q, ks);
+  }
+
   floatx4 acc2[2][NT2];
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int j = 0; j < NT2; ++j) acc2[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
 
-  constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
   for (int slab = 0; slab < M; ++slab) {
-    // layer 1: 64 m-tiles (16 positions each), one 16-channel n-tile; wave w owns 8w..8w+7
+    // layer 1: 64 m-tiles (16 positions each) x 16 channels; wave w owns m-tiles 8w..8w+7
     const frag* w1p = reinterpret_cast<const frag*>(wpk[0]) + (size_t)slab * KS1 * 64;
     frag w1f[KS1];
 #pragma unroll
     for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1p[ks * 64 + lane];
-    const float bb1 = b1[slab * CB1 + l16];
+    float bb1[4];
 #pragma unroll
-    for (int chunk = 0; chunk < 2; ++chunk) {
-      floatx4 acc[4];
+    for (int r = 0; r < 4; ++r) bb1[r] = b1[slab * CB1 + 4 * g + r];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 8; ++q) {
+      const int mt = wave * 8 + q;
+      floatx4 acc = (floatx4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int mt = wave * 8 + chunk * 4 + q;
-        const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
-        // im2col row of output (i, j): FR row 2i+u, elements 5 + 6j + (3v + c)
-        const __bf16* rowp = FR + 5 + 6 * j;
-#pragma unroll
-        for (int ks = 0; ks < KS1; ++ks) {
-          frag av;
-          if constexpr (sizeof(T) == 2) {
-            alignas(16) __bf16 t8[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int k = ks * 32 + 8 * g + e;
-              t8[e] = k < 27 ? rowp[(2 * i + k / 9) * FRS + k % 9] : static_cast<__bf16>(0.f);
-            }
-            av = *reinterpret_cast<const bf16x8*>(t8);
-          } else {
-            const int k = ks * 4 + g;
-            av = k < 27 ? (float)rowp[(2 * i + k / 9) * FRS + k % 9] : 0.f;
-          }
-          acc[q] = mfma(av, w1f[ks], acc[q]);
-        }
+      for (int ks = 0; ks < KS1; ++ks) {
+        frag av;
+        if constexpr (sizeof(T) == 2) av = a1[q][ks];
+        else av = gather1(mt, ks);
+        acc = mfma(w1f[ks], av, acc);
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int mt = wave * 8 + chunk * 4 + q;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int px = mt * 16 + 4 * g + r, i = px >> 5, j = px & 31;
-          S1[((i + 1) * S1_W + (j + 1)) * S1P + l16] = static_cast<T>(fmaxf(acc[q][r] + bb1, 0.f));
-        }
-      }
+      const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
+      store4<T>(S1 + ((i + 1) * S1_W + (j + 1)) * S1P + 4 * g, fmaxf(acc[0] + bb1[0], 0.f),
+                fmaxf(acc[1] + bb1[1], 0.f), fmaxf(acc[2] + bb1[2], 0.f), fmaxf(acc[3] + bb1[3], 0.f));
     }
     __syncthreads();
-    // layer 2 partial: K = 9 taps x 16 channels of this slab; wave w owns m-tiles 2w, 2w+1
+    // layer 2 partial: K = 9 taps x 16 channels of this slab; wave w owns position tiles 2w, 2w+1
     const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64;
     frag bcur[NT2];
 #pragma unroll
@@ -274,7 +292,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
       for (int nt = 0; nt < NT2; ++nt)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc2[q][nt] = mfma(av[q], bcur[nt], acc2[q][nt]);
+        for (int q = 0; q < 2; ++q) acc2[q][nt] = mfma(bcur[nt], av[q], acc2[q][nt]);
       if (ks + 1 < KS2) {
 #pragma unroll
         for (int nt = 0; nt < NT2; ++nt) bcur[nt] = bnext[nt];
@@ -286,27 +304,26 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   // ---- layer-2 epilogue into L2 (overwrites FR / S1)
 #pragma unroll
   for (int nt = 0; nt < NT2; ++nt) {
-    const int ch = nt * 16 + l16;
-    const float bb = b2[ch];
+    const int ch = nt * 16 + 4 * g;
+    const float bb0 = b2[ch], bb1v = b2[ch + 1], bb2 = b2[ch + 2], bb3 = b2[ch + 3];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int px = (wave * 2 + q) * 16 + 4 * g + r, i = px >> 4, j = px & 15;
-        L2[((i + 1) * L2_W + (j + 1)) * C2P + ch] = static_cast<T>(fmaxf(acc2[q][nt][r] + bb, 0.f));
-      }
+    for (int q = 0; q < 2; ++q) {
+      const int px = (wave * 2 + q) * 16 + l16, i = px >> 4, j = px & 15;
+      store4<T>(L2 + ((i + 1) * L2_W + (j + 1)) * C2P + ch, fmaxf(acc2[q][nt][0] + bb0, 0.f),
+                fmaxf(acc2[q][nt][1] + bb1v, 0.f), fmaxf(acc2[q][nt][2] + bb2, 0.f), fmaxf(acc2[q][nt][3] + bb3, 0.f));
+    }
   }
-  for (int p = tid; p < (2 * L2_W - 1) * C2; p += NTHR) {
-    const int qq = p / C2, c = p % C2;
+  for (int p = tid; p < (2 * L2_W - 1) * (C2 / 4); p += NTHR) {
+    const int qq = p / (C2 / 4), c = (p % (C2 / 4)) * 4;
     const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
-    L2[(y * L2_W + x) * C2P + c] = static_cast<T>(0.f);
+    store4<T>(L2 + (y * L2_W + x) * C2P + c, 0.f, 0.f, 0.f, 0.f);
   }
   FramePrefetch pf;
   if (next_valid) frame_issue(a, next_idx, pf);
   __syncthreads();
 
-  // ---- layer 3: 4 m-tiles (64 positions) x 4M n-tiles; wave w: m-tiles 2(w&1), 2(w&1)+1,
-  //      n-tiles (w>>1)*M .. (w>>1)*M + M - 1
+  // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave w: position tiles
+  //      2(w&1), 2(w&1)+1, channel tiles (w>>1)*M .. (w>>1)*M + M - 1
   constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
   const int mh = wave & 1, ng = wave >> 1;
   floatx4 acc3[2][M];
@@ -337,36 +354,49 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
     for (int n = 0; n < M; ++n)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc3[q][n] = mfma(av[q], b3cur[n], acc3[q][n]);
+      for (int q = 0; q < 2; ++q) acc3[q][n] = mfma(b3cur[n], av[q], acc3[q][n]);
     if (ks + 1 < KS3) {
 #pragma unroll
       for (int n = 0; n < M; ++n) b3cur[n] = b3next[n];
     }
   }
-  // ReLU + pooled partial sums over this wave's 32 positions
+  // ReLU + pooled partial sums over this wave's 32 positions (positions = lanes l16 and q)
 #pragma unroll
   for (int n = 0; n < M; ++n) {
-    const int ch = (ng * M + n) * 16 + l16;
-    const float bb = b3[ch];
-    float s = 0.f;
+    const int ch0 = (ng * M + n) * 16 + 4 * g;
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) s += fmaxf(acc3[q][n][r] + bb, 0.f);
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    if (g == 0) sh.gpart[mh][ch] = s;
+    for (int r = 0; r < 4; ++r) {
+      const float bb = b3[ch0 + r];
+      float s = fmaxf(acc3[0][n][r] + bb, 0.f) + fmaxf(acc3[1][n][r] + bb, 0.f);
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+      if (l16 == 0) sh.gpart[mh][ch0 + r] = s;
+    }
   }
   __syncthreads();
-  // FC on the pooled vector; meanwhile the next frame goes into FR
-  if (tid < kClasses) {
+  // wave 0: FC (lanes over channels) -> z; the other waves store the next frame meanwhile
+  if (wave == 0) {
     const float* fw = a.fc_w[slot];
-    float z = a.fc_b[slot][tid];
-    for (int ch = 0; ch < C3; ++ch) z += (sh.gpart[0][ch] + sh.gpart[1][ch]) * (1.0f / 64.0f) * fw[ch * kClasses + tid];
-    sh.z[tid] = z;
+    float zp[kClasses];
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c) zp[c] = 0.f;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int ch = lane + 64 * q;
+      const float gch = (sh.gpart[0][ch] + sh.gpart[1][ch]) * (1.0f / 64.0f);
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) zp[c] += gch * fw[ch * kClasses + c];
+    }
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c) {
+      float v = zp[c];
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+      z_out[c] = v + a.fc_b[slot][c];
+    }
   }
   if (next_valid) frame_store<T>(a, pf, region);
-  __syncthreads();
 }
 
 __device__ inline void decode_entry(const CnnArgs& a, int t, int& slot, int& off) {
@@ -411,12 +441,13 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
       next_idx = entry_idx(a.q.entries[(int64_t)a.pred[s2] * a.q.cap + o2]);
     }
     unsigned long long t0 = wall_clock64();
-    cnn_frame<T, M>(a, slot, region, sh, next_valid, next_idx);
+    float z[kClasses];
+    cnn_frame<T, M>(a, slot, region, sh, next_valid, next_idx, z);
     if (tid == 0) {
       if (f.logits != nullptr) {
-        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)sh.z[c];
+        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)z[c];
       } else {
-        float d = class_margin(sh.z, a.class_mask[slot]);
+        float d = class_margin(z, a.class_mask[slot]);
         float th = theta_of(f, k, idx);
         bool defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau;
         int n = sh.d_n;
@@ -438,9 +469,10 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
 // ---------------------------------------------------------------- FP64 tier
 // The frame normalised in fp64 exactly as defined, the canonical (unfolded) fp32 weights
 // widened to fp64, fp64 accumulation.  The first esc_cap escalated entries of each predicate are
-// evaluated layer-parallel across the whole GPU (one thread per output activation, weights laid
-// out [ci][3][3][co] so consecutive threads read consecutive weights); any beyond that run one
-// entry per workgroup.
+// evaluated layer-parallel across the whole GPU: layer 1 with one thread per output activation,
+// layers 2 and 3 with one wave per output activation whose lanes split the (tap, channel) sum
+// (weights laid out [co][3][3][ci] so the lanes read consecutive weights and activations) and
+// reduce it with cross-lane adds; any entries beyond that run one per workgroup.
 __device__ inline double frame_norm64(const FrameSrc& fr, uint32_t idx, int y, int x, int c) {
   const int64_t o = (int64_t)idx * fr.elems + ((int64_t)y * fr.hw + x) * 3 + c;
   double v;
@@ -468,12 +500,12 @@ __device__ inline double conv64_at(const CnnArgs& a, int slot, int layer, uint32
     for (int v = 0; v < 3; ++v) {
       const int x = 2 * j + v - 1;
       if (x < 0 || x >= hin) continue;
-      const float* w = W + (u * 3 + v) * cout + o;
+      const float* w = W + ((o * 3 + u) * 3 + v) * cin;
       if (layer == 0) {
-        for (int c = 0; c < 3; ++c) s = fma((double)w[c * 9 * cout], frame_norm64(a.fr, idx, y, x, c), s);
+        for (int c = 0; c < 3; ++c) s = fma((double)w[c], frame_norm64(a.fr, idx, y, x, c), s);
       } else {
         const double* xin = in + (y * hin + x) * cin;
-        for (int c = 0; c < cin; ++c) s = fma((double)w[c * 9 * cout], xin[c], s);
+        for (int c = 0; c < cin; ++c) s = fma((double)w[c], xin[c], s);
       }
     }
   }
@@ -483,6 +515,23 @@ __device__ inline double conv64_at(const CnnArgs& a, int slot, int layer, uint32
 __device__ inline int64_t act_off(int layer, int m) {
   // per entry: [layer-1 output | layer-2 output]; layer 3 reuses the layer-1 region
   return layer == 1 ? (int64_t)H1 * H1 * 16 * m : 0;
+}
+
+__device__ inline void f64_decode(const CnnArgs& a, int layer, int64_t gi, const int* ne, const int64_t* outs,
+                                  int& slot, int& e, int& p, int& o) {
+  slot = 0;
+  int64_t rem = gi;
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int64_t c = ne[i] * outs[i];
+    if (rem < c) { slot = i; break; }
+    rem -= c;
+  }
+  e = (int)(rem / outs[slot]);
+  const int oi = (int)(rem % outs[slot]);
+  const int m = mult_dev(a.variant[slot]);
+  const int cout = layer == 0 ? 16 * m : layer == 1 ? 32 * m : 64 * m;
+  p = oi / cout;
+  o = oi % cout;
 }
 
 __global__ __launch_bounds__(256) void cnn_f64_layer_kernel(CnnArgs a, int layer) {
@@ -497,25 +546,45 @@ __global__ __launch_bounds__(256) void cnn_f64_layer_kernel(CnnArgs a, int layer
     outs[i] = (int64_t)hout * hout * cout;
     total += ne[i] * outs[i];
   }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
-    int slot = 0;
-    int64_t rem = gi;
-    for (int i = 0; i < a.n_preds; ++i) {
-      const int64_t c = ne[i] * outs[i];
-      if (rem < c) { slot = i; break; }
-      rem -= c;
+  if (layer == 0) {
+    // layer 1 (27 products per output): one thread per output
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
+      int slot, e, p, o;
+      f64_decode(a, 0, gi, ne, outs, slot, e, p, o);
+      const int m = mult_dev(a.variant[slot]);
+      const uint32_t idx = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + e]);
+      double* act = a.esc_act[slot] + (int64_t)e * a.esc_stride;
+      act[p * 16 * m + o] = conv64_at(a, slot, 0, idx, nullptr, p, o);
     }
-    const int e = (int)(rem / outs[slot]);
-    const int oi = (int)(rem % outs[slot]);
+    return;
+  }
+  // layers 2 and 3: one wave per output, lanes over (tap, input channel)
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t gi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); gi < total; gi += nwaves) {
+    int slot, e, p, o;
+    f64_decode(a, layer, gi, ne, outs, slot, e, p, o);
     const int m = mult_dev(a.variant[slot]);
-    const int cout = layer == 0 ? 16 * m : layer == 1 ? 32 * m : 64 * m;
-    const int p = oi / cout, o = oi % cout;
-    const uint32_t idx = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + e]);
+    const int cin = layer == 1 ? 16 * m : 32 * m;
+    const int cout = layer == 1 ? 32 * m : 64 * m;
+    const int hin = layer == 1 ? H1 : H2, hout = hin / 2;
+    const int i = p / hout, j = p % hout;
     double* act = a.esc_act[slot] + (int64_t)e * a.esc_stride;
-    const double* in = layer == 0 ? nullptr : layer == 1 ? act + act_off(0, m) : act + act_off(1, m);
-    double* out = layer == 1 ? act + act_off(1, m) : act;   // layers 1 and 3 share a region
-    out[oi] = conv64_at(a, slot, layer, idx, in, p, o);
+    const double* in = layer == 1 ? act + act_off(0, m) : act + act_off(1, m);
+    const float* W = a.wt_canon[slot][layer] + (int64_t)o * 9 * cin;
+    double s = 0.0;
+    for (int kk = lane; kk < 9 * cin; kk += 64) {
+      const int t = kk / cin, c = kk % cin;
+      const int y = 2 * i + t / 3 - 1, x = 2 * j + t % 3 - 1;
+      if (y >= 0 && x >= 0 && y < hin && x < hin) s = fma((double)W[kk], in[(y * hin + x) * cin + c], s);
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) {
+      s += (double)a.b_canon[slot][layer][o];
+      double* out = layer == 1 ? act + act_off(1, m) : act;   // layers 1 and 3 share a region
+      out[p * cout + o] = s > 0.0 ? s : 0.0;
+    }
   }
 }
 

@@ -45,7 +45,7 @@ struct CnnArgs {
   const float* w_canon[kMaxK][3];   // [co][ci][3][3]
   const float* b_canon[kMaxK][3];
   float pad_raw;                    // raw frame value that normalises to 0
-  const float* wt_canon[kMaxK][3];  // FP64 tier: canonical weights as [ci][3][3][co]
+  const float* wt_canon[kMaxK][3];  // FP64 tier: canonical weights as [co][3][3][ci]
   double* esc_act[kMaxK];           // FP64 tier: per-entry activations (esc_cap entries per slot)
   int64_t esc_stride;               // doubles per entry
   int esc_cap;                      // entries handled layer-parallel; the rest run one per block

@@ -496,10 +496,11 @@ static int pack_models(hydro_session* s) {
         if ((rc = upload(s, hm.cw[l].data(), hm.cw[l].size(), &dp))) return rc;
         ca.w_canon[i][l] = dp;
         {
+          // [co][3][3][ci]: the FP64 tier's lanes walk the input channels of one tap
           std::vector<float> wt(hm.cw[l].size());
           for (int o = 0; o < co; ++o)
             for (int c = 0; c < cin; ++c)
-              for (int t = 0; t < 9; ++t) wt[((size_t)c * 9 + t) * co + o] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
+              for (int t = 0; t < 9; ++t) wt[((size_t)o * 9 + t) * cin + c] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
           if ((rc = upload(s, wt.data(), wt.size(), &dp))) return rc;
           ca.wt_canon[i][l] = dp;
         }
@@ -578,8 +579,8 @@ void hydro_policy_default(hydro_policy* p) {
   p->ewma_alpha = 0.5f;
   p->cost_source = HYDRO_COST_MEASURED;
   p->precision = HYDRO_PREC_BF16;
-  p->tau = 0.05f;
-  p->tau32 = 1e-4f;
+  p->tau = 0.015f;
+  p->tau32 = 1e-5f;
   p->grouped = 1;
   p->use_graph = 0;
   p->log_routes = 0;
@@ -628,8 +629,8 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   g_alloc_counter = 0;
   hydro_session* s = new hydro_session();
   s->pol = *policy;
-  if (s->pol.tau <= 0.f) s->pol.tau = 0.05f;
-  if (s->pol.tau32 <= 0.f) s->pol.tau32 = 1e-4f;
+  if (s->pol.tau <= 0.f) s->pol.tau = 0.015f;
+  if (s->pol.tau32 <= 0.f) s->pol.tau32 = 1e-5f;
   s->K = k;
   s->fh = frame_h;
   s->fw = frame_w;

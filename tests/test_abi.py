@@ -35,7 +35,7 @@ def test_version_and_no_error():
 def test_policy_defaults():
     p = hydro.make_policy()
     assert p.route == hydro.ROUTE_SCORE and p.routing_batch == 64 and p.wave == 8192
-    assert p.precision == hydro.PREC_BF16 and abs(p.tau - 0.05) < 1e-7 and abs(p.tau32 - 1e-4) < 1e-10
+    assert p.precision == hydro.PREC_BF16 and abs(p.tau - 0.015) < 1e-7 and abs(p.tau32 - 1e-5) < 1e-11
     assert list(p.order)[:4] == [0, 1, 2, 3]
 
 
