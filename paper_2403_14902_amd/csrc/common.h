@@ -74,11 +74,29 @@ struct DevState {
   int n_result;
   // learned router
   unsigned long long learned_routed, stats_routed;
-  double arm_cost[2], arm_tuples[2];   // judge: realised UDF cost and tuples completed per arm
-  int learned_active;
+  double arm_cost[2], arm_tuples[2];   // judge: realised UDF FLOPs and finished tuples per arm
+  int learned_active;                  // 0 once the judge has fallen back to score routing
   int train_steps;
-  int ring_count;
-  int pad_;
+  unsigned long long ring_head;        // outcomes logged so far (ring index = head mod size)
+  unsigned long long ring_trained;     // ring position the trainer has consumed up to
+};
+
+// Which arm a routing batch belongs to: 1 = learned router, 0 = score routing (control).
+__host__ __device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+  return x;
+}
+__host__ __device__ inline int arm_of(uint32_t batch, uint32_t seed, uint32_t control_below) {
+  return mix32(batch ^ seed) >= control_below ? 1 : 0;
+}
+
+// Outcome log of the learned router: idx | k << 24 | rejected << 31.
+struct OutcomeLog {
+  uint32_t* ring;            // nullptr: no learned router
+  uint32_t ring_mask;        // size - 1 (power of two)
+  const float* flops;        // per predicate, for the judge's cost accounting
+  uint32_t seed, control_below;
+  int routing_batch;
 };
 
 // Where the frames of the current push live.
@@ -114,6 +132,7 @@ struct Forward {
   int k_total;
   int count_eval;            // 1 in the first pass (counts evaluated tuples)
   double* logits;            // if set: write fp64 logits [idx][10] instead of deciding
+  OutcomeLog olog;
 };
 
 __device__ inline float theta_of(const Forward& f, int k, uint32_t idx) {
@@ -175,6 +194,30 @@ __device__ inline void forward_decision(const Forward& f, int k, uint32_t e, boo
   }
   bool done = ok && mask == f.full_mask;
   bool more = ok && mask != f.full_mask;
+  if (f.olog.ring != nullptr) {
+    // learned router: log the outcome; judge: UDF FLOPs spent and tuples finished per arm
+    unsigned long long m = __ballot(decided);
+    if (m != 0) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0;
+      if (lane_id() == leader) base = atomicAdd(&f.st->ring_head, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader);
+      if (decided) {
+        unsigned long long pos = base + __popcll(m & ((1ull << lane_id()) - 1ull));
+        f.olog.ring[pos & f.olog.ring_mask] = idx | ((uint32_t)k << 24) | (pass ? 0u : 0x80000000u);
+      }
+      const int arm = arm_of(idx / (uint32_t)f.olog.routing_batch, f.olog.seed, f.olog.control_below);
+      const bool finished = decided && (!pass || done);
+      for (int a = 0; a < 2; ++a) {
+        const int ne = __popcll(__ballot(decided && arm == a));
+        const int nf = __popcll(__ballot(finished && arm == a));
+        if (lane_id() == leader) {
+          if (ne) atomicAdd(&f.st->arm_cost[a], (double)ne * (double)f.olog.flops[k]);
+          if (nf) atomicAdd(&f.st->arm_tuples[a], (double)nf);
+        }
+      }
+    }
+  }
   if (done) atomicOr(&f.result_bits[idx >> 5], 1u << (idx & 31));
   int slot = wave_append(f.pend_out_count, more);
   if (more) f.pend_out[slot] = make_entry(idx, mask);

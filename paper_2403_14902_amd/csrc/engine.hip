@@ -141,14 +141,21 @@ struct RouteArgs {
   int k;
   Queues q;
   const float* learned_keys;   // LEARNED: per-tuple keys [idx][K] (nullptr otherwise)
-  const uint8_t* arm;          // LEARNED: per routing batch, 1 = learned arm
+  OutcomeLog olog;             // LEARNED: arm assignment of routing batches
+  int min_steps;               // LEARNED: optimiser steps before the learned arm uses the keys
 };
+
+__device__ inline bool learned_arm(const RouteArgs& a, uint32_t e) {
+  return a.learned_keys != nullptr && !(a.warmup && entry_mask(e) == 0) && a.st->learned_active &&
+         a.st->train_steps >= a.min_steps &&
+         arm_of(entry_idx(e) / (uint32_t)a.routing_batch, a.olog.seed, a.olog.control_below) == 1;
+}
 
 __device__ inline int choose_pred(const RouteArgs& a, uint32_t e, const int* order) {
   uint32_t mask = entry_mask(e);
   uint32_t idx = entry_idx(e);
   if (a.warmup && mask == 0) return (int)((idx / (uint32_t)a.routing_batch) % (uint32_t)a.k);
-  if (a.learned_keys != nullptr && a.arm[idx / (uint32_t)a.routing_batch]) {
+  if (learned_arm(a, e)) {
     const float* kk = a.learned_keys + (int64_t)idx * a.k;
     int best = -1;
     float bk = 0.f;
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(256) void k_route(RouteArgs a) {
       k = choose_pred(a, e, order);
     }
     if (a.learned_keys != nullptr) {
-      bool learned = active && a.arm[entry_idx(e) / (uint32_t)a.routing_batch] && !(a.warmup && entry_mask(e) == 0);
+      bool learned = active && learned_arm(a, e);
       wave_add_u64(&a.st->learned_routed, learned && entry_mask(e) == 0);
       wave_add_u64(&a.st->stats_routed, active && !learned && entry_mask(e) == 0);
     }
@@ -278,8 +285,21 @@ struct HostModel {
   int variant = CNN_NONE;
 };
 
-struct PushRec {
-  int64_t id_base, n;
+// What a captured push depends on besides device-resident state.
+struct GraphKey {
+  int64_t n;
+  const void* base;
+  int64_t id_base;
+  int n_seg;
+  int64_t seg_len;
+  int warm;
+  int parity;
+  const void* theta;
+  const void* out;
+  bool operator==(const GraphKey& o) const {
+    return n == o.n && base == o.base && id_base == o.id_base && n_seg == o.n_seg && seg_len == o.seg_len &&
+           warm == o.warm && parity == o.parity && theta == o.theta && out == o.out;
+  }
 };
 
 struct hydro_session {
@@ -324,6 +344,7 @@ struct hydro_session {
   double tick_us = 0.01;   // device wall clock period in microseconds
   std::vector<hipEvent_t> evpool;   // time_kernels: 5 events per round
   int ev_used = 0;
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // use_graph: captured pushes
 };
 
 static hipEvent_t next_event(hydro_session* s) {
@@ -557,6 +578,7 @@ static void free_session(hydro_session* s) {
   }
   if (s->out_ids) hipFree(s->out_ids);
   for (hipEvent_t e : s->evpool) hipEventDestroy(e);
+  for (auto& g : s->graphs) hipGraphExecDestroy(g.second);
   if (s->copy_stream) hipStreamDestroy(s->copy_stream);
   if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
   delete s;
@@ -708,8 +730,10 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   if (he != hipSuccess) return bail(fail(HYDRO_ENOMEM, "result buffer allocation failed"));
   s->out_cap = cap;
   if (s->pol.route == HYDRO_ROUTE_LEARNED) {
-    rc = router_nn_create(&s->rnn, s->K, frame_h, frame_w, cap, s->pol.seed, s->pol.routing_batch);
-    if (rc) return bail(rc);
+    double fl[kMaxK];
+    for (int i = 0; i < k; ++i) fl[i] = s->models[i].flops;
+    rc = router_nn_create(&s->rnn, s->K, frame_h, frame_w, cap, s->pol.seed, s->pol.routing_batch, s->pol.explore, fl);
+    if (rc) return bail(fail(rc, "learned router: frames must be square with a side divisible by 8"));
   }
   rc = hydro_session_reset(s);
   if (rc) return bail(rc);
@@ -731,7 +755,11 @@ int hydro_session_reset(hydro_session* s) {
   s->theta_host.clear();
   s->info = hydro_query_info{};
   s->ev_used = 0;
-  if (s->rnn) router_nn_reset(s->rnn, s->stream);
+  if (s->rnn) {
+    router_nn_reset(s->rnn, s->stream);
+    const int one = 1;
+    HIP_TRY(hipMemcpy(&s->st->learned_active, &one, sizeof(int), hipMemcpyHostToDevice));
+  }
   return HYDRO_OK;
 }
 
@@ -750,6 +778,7 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
   f.full_mask = (1u << s->K) - 1u;
   f.k_total = s->K;
   f.logits = nullptr;
+  f.olog = s->rnn ? router_nn_log(s->rnn) : OutcomeLog{};
   const bool bf = s->pol.precision == HYDRO_PREC_BF16;
   if (tier == TIER_FIRST) {
     f.count_eval = 1;
@@ -926,28 +955,17 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   }
   s->info.n_tuples += n;
 
-  const int64_t nwords = (n + 31) / 32;
-  if (nwords > 0) hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (nwords + 255) / 256)), dim3(256), 0, st,
-                                     s->result_bits, 0u, nwords);
-  if (s->route_log && n > 0)
-    hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, s->route_log, 0u, n);
-
-  if (s->rnn && n > 0) {
-    rc = router_nn_admit(s->rnn, src, n, st);
-    if (rc) return rc;
-  }
-
   // admission schedule: optional warmup round, then waves
   const bool adaptive = s->pol.route != HYDRO_ROUTE_FIXED;
+  const bool warm_now = adaptive && !s->warmed && n > 0 && s->pol.warmup_batches > 0;
   std::vector<std::pair<int64_t, int64_t>> adm;
   std::vector<int> warm;
   int64_t pos = 0;
-  if (adaptive && !s->warmed && n > 0 && s->pol.warmup_batches > 0) {
+  if (warm_now) {
     int64_t w0 = std::min<int64_t>(n, (int64_t)s->pol.warmup_batches * s->K * s->pol.routing_batch);
     adm.push_back({0, w0});
     warm.push_back(1);
     pos = w0;
-    s->warmed = true;
   }
   while (pos < n) {
     int64_t w = std::min<int64_t>(n - pos, s->pol.wave);
@@ -956,80 +974,121 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
     pos += w;
   }
   const int n_rounds = adm.empty() ? 0 : (int)adm.size() + s->K - 1;
-
   const bool timing = s->pol.time_kernels != 0;
-  for (int r = 0; r < n_rounds; ++r) {
-    const int in_slot = s->parity, out_slot = s->parity ^ 1;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    if (timing) {
-      for (int i = 0; i < 5; ++i) ev[i] = next_event(s);
-      if (ev[0]) hipEventRecord(ev[0], st);
-    }
-    FoldArgs fa{};
-    fa.st = s->st;
-    fa.k = s->K;
-    fa.route = s->pol.route;
-    for (int j = 0; j < s->K; ++j) {
-      fa.order[j] = s->pol.order[j];
-      fa.flops[j] = s->models[j].flops;
-    }
-    fa.alpha = s->pol.ewma_alpha;
-    fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
-    fa.out_slot = out_slot;
-    fa.final_fold = 0;
-    hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
+  const int parity0 = s->parity;
+  const int64_t nwords = (n + 31) / 32;
 
-    if (s->rnn) router_nn_round(s->rnn, s->st, st);
+  // Every device step of the push, in stream order.  Host state is not touched here, so the
+  // same sequence can be captured once into a HIP graph and replayed.
+  auto enqueue_push = [&](bool timed) {
+    if (nwords > 0) hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (nwords + 255) / 256)), dim3(256), 0, st,
+                                       s->result_bits, 0u, nwords);
+    if (s->route_log && n > 0)
+      hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, s->route_log, 0u, n);
+    if (s->rnn && n > 0) router_nn_admit(s->rnn, src, n, st);
+    int parity = parity0;
+    for (int r = 0; r < n_rounds; ++r) {
+      const int in_slot = parity, out_slot = parity ^ 1;
+      hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+      if (timed) {
+        for (int i = 0; i < 5; ++i) ev[i] = next_event(s);
+        if (ev[0]) hipEventRecord(ev[0], st);
+      }
+      FoldArgs fa{};
+      fa.st = s->st;
+      fa.k = s->K;
+      fa.route = s->pol.route;
+      for (int j = 0; j < s->K; ++j) {
+        fa.order[j] = s->pol.order[j];
+        fa.flops[j] = s->models[j].flops;
+      }
+      fa.alpha = s->pol.ewma_alpha;
+      fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
+      fa.out_slot = out_slot;
+      fa.final_fold = 0;
+      hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
 
-    RouteArgs ra{};
-    ra.st = s->st;
-    ra.pend_in = s->pend[in_slot];
-    ra.in_slot = in_slot;
-    if (r < (int)adm.size()) {
-      ra.adm_lo = (uint32_t)adm[r].first;
-      ra.adm_hi = (uint32_t)adm[r].second;
-      ra.warmup = warm[r];
-    } else {
-      ra.adm_lo = ra.adm_hi = 0;
-      ra.warmup = 0;
-    }
-    ra.routing_batch = s->pol.routing_batch;
-    ra.k = s->K;
-    ra.q = Queues{s->q1, s->st->qcount, s->cap};
-    ra.learned_keys = s->rnn ? router_nn_keys(s->rnn) : nullptr;
-    ra.arm = s->rnn ? router_nn_arms(s->rnn) : nullptr;
-    hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
-    if (timing && ev[1]) hipEventRecord(ev[1], st);
+      RouteArgs ra{};
+      ra.st = s->st;
+      ra.pend_in = s->pend[in_slot];
+      ra.in_slot = in_slot;
+      if (r < (int)adm.size()) {
+        ra.adm_lo = (uint32_t)adm[r].first;
+        ra.adm_hi = (uint32_t)adm[r].second;
+        ra.warmup = warm[r];
+      } else {
+        ra.adm_lo = ra.adm_hi = 0;
+        ra.warmup = 0;
+      }
+      ra.routing_batch = s->pol.routing_batch;
+      ra.k = s->K;
+      ra.q = Queues{s->q1, s->st->qcount, s->cap};
+      ra.learned_keys = s->rnn ? router_nn_keys_ptr(s->rnn) : nullptr;
+      if (s->rnn) {
+        ra.olog = router_nn_log(s->rnn);
+        ra.min_steps = router_nn_min_steps();
+        router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
+      }
+      hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
+      if (timed && ev[1]) hipEventRecord(ev[1], st);
 
-    for (int tier = TIER_FIRST; tier <= TIER_F64; ++tier) {
-      if (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_BF16) continue;
-      Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
-      enqueue_tier(s, tier, src, f, st);
-      if (timing && ev[2 + tier]) hipEventRecord(ev[2 + tier], st);
+      for (int tier = TIER_FIRST; tier <= TIER_F64; ++tier) {
+        if (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_BF16) continue;
+        Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
+        enqueue_tier(s, tier, src, f, st);
+        if (timed && ev[2 + tier]) hipEventRecord(ev[2 + tier], st);
+      }
+      if (timed && s->pol.precision != HYDRO_PREC_BF16 && ev[3]) hipEventRecord(ev[3], st);
+      if (s->rnn) router_nn_learn(s->rnn, s->st, st);
+      parity ^= 1;
     }
-    if (timing && s->pol.precision != HYDRO_PREC_BF16 && ev[3]) hipEventRecord(ev[3], st);
-    if (s->rnn) router_nn_learn(s->rnn, s->st, src, s->route_log, st);
-    s->parity ^= 1;
-    s->rounds_done++;
+    {
+      FoldArgs fa{};
+      fa.st = s->st;
+      fa.k = s->K;
+      fa.final_fold = 1;
+      fa.alpha = s->pol.ewma_alpha;
+      fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
+      for (int j = 0; j < s->K; ++j) fa.flops[j] = s->models[j].flops;
+      hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
+    }
+    // ordered result materialisation for this push
+    if (nwords > 0) {
+      const int nb = (int)((nwords + 255) / 256);
+      hipLaunchKernelGGL(k_res_count, dim3(nb), dim3(256), 0, st, s->result_bits, nwords, s->res_blocks);
+      hipLaunchKernelGGL(k_res_scan, dim3(1), dim3(1024), 0, st, s->res_blocks, nb, s->st, s->res_base);
+      hipLaunchKernelGGL(k_res_write, dim3(nb), dim3(256), 0, st, s->result_bits, nwords, s->res_blocks, fr.id_base,
+                         s->out_ids);
+    }
+  };
+
+  const bool graphable = s->pol.use_graph && fr.where == HYDRO_MEM_DEVICE && !timing;
+  if (graphable) {
+    GraphKey key{n, src.base, fr.id_base, n_seg, seg_len, (int)warm_now, parity0, s->theta, s->out_ids};
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : s->graphs)
+      if (e.first == key) exec = e.second;
+    if (!exec) {
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      enqueue_push(false);
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamEndCapture(st, &graph));
+      hipError_t he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (he != hipSuccess) return fail(HYDRO_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+      if (s->graphs.size() >= 8) {
+        hipGraphExecDestroy(s->graphs.front().second);
+        s->graphs.erase(s->graphs.begin());
+      }
+      s->graphs.push_back({key, exec});
+    }
+    HIP_TRY(hipGraphLaunch(exec, st));
+  } else {
+    enqueue_push(timing);
   }
-  {
-    FoldArgs fa{};
-    fa.st = s->st;
-    fa.k = s->K;
-    fa.final_fold = 1;
-    fa.alpha = s->pol.ewma_alpha;
-    fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
-    for (int j = 0; j < s->K; ++j) fa.flops[j] = s->models[j].flops;
-    hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
-  }
-  // ordered result materialisation for this push
-  if (nwords > 0) {
-    const int nb = (int)((nwords + 255) / 256);
-    hipLaunchKernelGGL(k_res_count, dim3(nb), dim3(256), 0, st, s->result_bits, nwords, s->res_blocks);
-    hipLaunchKernelGGL(k_res_scan, dim3(1), dim3(1024), 0, st, s->res_blocks, nb, s->st, s->res_base);
-    hipLaunchKernelGGL(k_res_write, dim3(nb), dim3(256), 0, st, s->result_bits, nwords, s->res_blocks, fr.id_base,
-                       s->out_ids);
-  }
+  if (warm_now) s->warmed = true;
+  s->parity = parity0 ^ (n_rounds & 1);
+  s->rounds_done += n_rounds;
   if (fr.where == HYDRO_MEM_HOST) HIP_TRY(hipEventRecord(s->stage_free[s->stage_next ^ 1], st));
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;

@@ -125,3 +125,47 @@ def test_cnn_fp64_tier_heavy(monkeypatch, esc_cap):
     assert np.array_equal(ids, c.expect)
     check_stats(stats, c.n, ids.size)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_learned_router_ids_stats_replay(c2, prec):
+    """Learned content-based routing (online-trained router MLP, control arm on score routing):
+    routes differ, the answer set may not."""
+    pol = hydro.make_policy("learned", precision=prec, wave=1024, log_routes=1, explore=0.1, seed=4242)
+    s = hydro.Session(c2.specs(), pol, 64, c2.n)
+    s.push(c2.device_frames(), c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+    ids, stats = s.finish()
+    info = s.info()
+    log(f"[gpu] learned prec={prec}: train_steps={info['train_steps']} active={info['learned_active']} "
+        f"learned_routed={info['learned_routed']} stats_routed={info['stats_routed']} "
+        f"evaluated={[st['evaluated'] for st in stats]}")
+    assert np.array_equal(ids, c2.expect)
+    check_stats(stats, c2.n, ids.size)
+    ok, rev, rps, out, msg = ho.replay_route(c2.P, hydro.decode_routes(s.routes(0, c2.n)))
+    assert ok, msg
+    assert [st["evaluated"] for st in stats] == list(rev)
+    assert info["train_steps"] > 0
+    assert info["learned_routed"] + info["stats_routed"] == c2.n
+    s.close()
+
+
+@pytest.mark.parametrize("route", ["score", "learned"])
+def test_graph_replays_match_eager(c2, route):
+    """A push captured in a HIP graph and replayed several times, with eager work and
+    synchronisation in between, gives the eager result every time."""
+    eager = hydro.Session(c2.specs(), hydro.make_policy(route, precision="bf16", wave=2048), 64, c2.n)
+    eager.push(c2.device_frames(), c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+    ids_e, st_e = eager.finish()
+    eager.close()
+    assert np.array_equal(ids_e, c2.expect)
+    dev = c2.device_frames()
+    s = hydro.Session(c2.specs(), hydro.make_policy(route, precision="bf16", wave=2048, use_graph=1), 64, c2.n)
+    for rep in range(4):
+        s.reset()
+        s.push(dev, c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+        ids, stats = s.finish()
+        torch.cuda.synchronize()
+        _ = torch.ones(1024, device="cuda").sum().item()      # eager work between replays
+        assert np.array_equal(ids, c2.expect), f"replay {rep}"
+        check_stats(stats, c2.n, ids.size)
+    s.close()

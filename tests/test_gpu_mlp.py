@@ -144,3 +144,15 @@ def test_mlp_fp64_tier_heavy(c1, monkeypatch, esc_cap):
     assert sum(esc) > 100
     assert np.array_equal(ids, c1.expect)
     s.close()
+
+
+def test_mlp_graph_replays(c1):
+    s = _session(c1, hydro.make_policy("score", precision="bf16", wave=256, use_graph=1))
+    dev = c1.device_frames()
+    for rep in range(3):
+        s.reset()
+        s.push(dev, c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+        ids, stats = s.finish()
+        _ = torch.ones(64, device="cuda").sum().item()
+        assert np.array_equal(ids, c1.expect), f"replay {rep}"
+    s.close()
