@@ -9,9 +9,13 @@ A step is one whole query: reset, push every tuple (route, multi-split, evaluate
 survivors, materialise the sorted ids) and copy ids and statistics to the host.
 
 Forms:
-  full   first pass in BF16 on MFMA (fp32 accumulate), margins within tau re-scored in FP32,
-         within tau32 in FP64; score-driven routing; grouped persistent launches per round.
+  full   learned content-based router (score routing as control arm, judge and fallback) +
+         grouped persistent launches per round + first pass in BF16 on MFMA (fp32 accumulate)
+         with margins within tau re-scored in FP32 and within tau32 in FP64.  `value`.
+  score  as full, but score-driven routing only.
   plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate.
+  The timed runs record HIP events around each round's phases (for the roofline); the same
+  forms replayed from a captured HIP graph are reported as `graph_value`.
 
 Prints one JSON line (the full form's throughput as `value`, the plain form beside it, the
 dominant kernel's roofline from HIP events recorded by the library on its stream, and the FP64
@@ -41,7 +45,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--wave", type=int, default=8192)
     ap.add_argument("--tau", type=float, default=0.0)
-    ap.add_argument("--route", default="score")
+    ap.add_argument("--route", default="learned")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
@@ -104,7 +108,7 @@ def main():
     if args.tau > 0:
         extra["tau"] = args.tau
     full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
-    log("[bench] full form")
+    log(f"[bench] full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
                                          args.steps, args.warmup, n)
     value = n * args.steps / dt
@@ -160,6 +164,29 @@ def main():
         "n_result": int(ids.size),
         "rounds": infos[-1]["rounds"],
     }
+
+    info_last = infos[-1]
+    out["router"] = {k: info_last[k] for k in ("learned_routed", "stats_routed", "learned_active", "train_steps")}
+    total_udf = float((ev * flops).sum()) / args.steps
+    out["udf_gflop_per_step"] = total_udf / 1e9
+
+    # the same form replayed from a captured HIP graph (no events)
+    gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, use_graph=1, **extra)
+    ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, args.steps,
+                                args.warmup, n)
+    assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
+    out["graph_value"] = n * args.steps / dtg
+
+    if args.route != "score":
+        log("[bench] score form")
+        spol = hydro.make_policy("score", precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
+        ids_s, st_s, inf_s, dts = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, spol,
+                                           args.steps, args.warmup, n)
+        assert np.array_equal(ids_s, ids), "score and learned routing disagree"
+        ev_s = np.array([[x["evaluated"] for x in st] for st in st_s], dtype=np.float64)
+        out["score"] = {"value": n * args.steps / dts, "unit": "tuples/s",
+                        "udf_gflop_per_step": float((ev_s * flops).sum()) / args.steps / 1e9,
+                        "first_pass_ms_per_step": sum(i["first_pass_ms"] for i in inf_s) / args.steps}
 
     if not args.no_plain:
         log("[bench] plain form")

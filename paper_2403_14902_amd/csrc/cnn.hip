@@ -449,7 +449,7 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
       } else {
         float d = class_margin(z, a.class_mask[slot]);
         float th = theta_of(f, k, idx);
-        bool defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau;
+        bool defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau[k];
         int n = sh.d_n;
         sh.d_e[n] = e;
         sh.d_k[n] = (uint8_t)k;

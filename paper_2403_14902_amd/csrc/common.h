@@ -123,7 +123,7 @@ struct Forward {
   uint32_t* route_log;       // optional
   Queues defer;              // next tier (band) queues; entries == nullptr for the last tier
   unsigned long long* defer_stat;   // per-predicate counter of deferred decisions
-  float tau;                 // |d - theta| < tau defers to the next tier
+  float tau[kMaxK];          // per predicate: |d - theta| < tau defers to the next tier
   const float* theta;        // [n_seg][K]
   int n_seg;
   int64_t seg_len;

@@ -58,6 +58,40 @@ struct CnnArgs {
   int prec;
 };
 
+// Grouped launch over the generic (layer-wise) CNN predicates of one tier.
+struct GcnnArgs {
+  int n_preds;
+  int pred[kMaxK];
+  int n_layers[kMaxK];
+  int in_hw[kMaxK];
+  int widths[kMaxK][HYDRO_MAX_LAYERS];
+  uint32_t class_mask[kMaxK];
+  const __bf16* w_bf[kMaxK][HYDRO_MAX_LAYERS];    // packed fragments, layer 1 folded
+  const float* w_f32[kMaxK][HYDRO_MAX_LAYERS];
+  const float* bias[kMaxK][HYDRO_MAX_LAYERS];
+  const float* fc_w[kMaxK];
+  const float* fc_b[kMaxK];
+  const float* wt_canon[kMaxK][HYDRO_MAX_LAYERS]; // FP64 tier: [co][3][3][ci]
+  const float* b_canon[kMaxK][HYDRO_MAX_LAYERS];
+  float pad_raw;
+  void* act[2];                     // activations of every queued frame (all slots, in order)
+  int64_t act_stride;               // elements per frame
+  double* esc_act[kMaxK];           // FP64 tier: [esc_cap][2][esc_half]
+  int64_t esc_stride, esc_half;
+  int esc_cap;
+  double* rest_scratch;             // FP64 tier beyond esc_cap: per block, two activation buffers
+  int64_t rest_per_block;
+  Queues q;
+  FrameSrc fr;
+  DevState* st;
+  int count_ticks;
+  int prec;
+};
+
+void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
+size_t gcnn_packed_elems(int layer, int cin, int cout, int prec);
+void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, float scale, float* out);
+
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 size_t cnn_packed_elems(int variant, int layer, int prec);

@@ -329,6 +329,7 @@ struct hydro_session {
   int stage_next = 0;
   MlpArgs mlp{};
   CnnArgs cnn{};
+  GcnnArgs gcnn{};
   RouterNN* rnn = nullptr;
   // query progress
   int rounds_done = 0;
@@ -345,6 +346,7 @@ struct hydro_session {
   std::vector<hipEvent_t> evpool;   // time_kernels: 5 events per round
   int ev_used = 0;
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // use_graph: captured pushes
+  float tau_k[kMaxK], tau32_k[kMaxK];   // per-predicate bands (policy values or calibrated)
 };
 
 static hipEvent_t next_event(hydro_session* s) {
@@ -409,8 +411,14 @@ static int validate_model(const hydro_model& m, int fh, int fw) {
   for (int l = 0; l < m.n_layers; ++l)
     if (!m.conv_w[l] || !m.conv_b[l]) return fail(HYDRO_EINVAL, "CNN conv weight pointer is NULL");
   if (!m.fc_w || !m.fc_b) return fail(HYDRO_EINVAL, "CNN fc weight pointer is NULL");
-  if (cnn_variant_of(m.in_h, m.n_layers, m.widths) == CNN_NONE || m.in_w != m.in_h)
-    return fail(HYDRO_EUNSUPPORTED, "CNN shape not supported (64x64 frames, 3 layers of widths (16m, 32m, 64m), m in {1,2,4})");
+  if (m.in_w != m.in_h) return fail(HYDRO_EUNSUPPORTED, "CNN frames must be square");
+  if (cnn_variant_of(m.in_h, m.n_layers, m.widths) != CNN_NONE) return HYDRO_OK;   // fused kernel
+  // generic layer-wise path
+  if (m.in_h % (1 << m.n_layers) != 0 || (m.in_h >> m.n_layers) < 1)
+    return fail(HYDRO_EUNSUPPORTED, "CNN input side must be divisible by 2^n_layers");
+  for (int l = 0; l < m.n_layers; ++l)
+    if (m.widths[l] < 16 || m.widths[l] % 16 != 0 || m.widths[l] > 1024)
+      return fail(HYDRO_EUNSUPPORTED, "CNN widths must be multiples of 16 (at most 1024)");
   return HYDRO_OK;
 }
 
@@ -421,6 +429,7 @@ static int pack_models(hydro_session* s) {
   CnnArgs& ca = s->cnn;
   ma = MlpArgs{};
   ca = CnnArgs{};
+  s->gcnn = GcnnArgs{};
   ca.pad_raw = pad_raw;
   const int esc_cap = esc_cap_setting();
   // grouped launches walk their slots in order: most expensive predicates first, so the
@@ -474,6 +483,67 @@ static int pack_models(hydro_session* s) {
         const int nch = (D + 1535) / 1536;   // chunking of the FP64 tier's hidden pass
         if ((rc = sess_alloc(s, (void**)&ma.esc_h[i], (size_t)nch * esc_cap * H * sizeof(double)))) return rc;
       }
+    } else if (hm.variant == CNN_NONE) {
+      GcnnArgs& ga = s->gcnn;
+      int i = ga.n_preds++;
+      ga.pred[i] = k;
+      ga.n_layers[i] = m.n_layers;
+      ga.in_hw[i] = m.in_h;
+      ga.class_mask[i] = m.class_mask;
+      int cin = 3;
+      for (int l = 0; l < m.n_layers; ++l) {
+        const int co = m.widths[l];
+        ga.widths[i][l] = co;
+        const double sc = l == 0 ? scale : 1.0;
+        std::vector<float> bias(co);
+        for (int o = 0; o < co; ++o) {
+          double b = hm.cb[l][o];
+          if (l == 0) {
+            double sum = 0;
+            for (int t = 0; t < cin * 9; ++t) sum += hm.cw[l][(size_t)o * cin * 9 + t];
+            b -= 2.0 * sum;
+          }
+          bias[o] = (float)b;
+        }
+        int rc;
+        float* dp;
+        uint16_t* bp;
+        {
+          size_t n = gcnn_packed_elems(l, cin, co, HYDRO_PREC_FP32);
+          std::vector<float> pf(n);
+          gcnn_pack_layer(l, cin, co, HYDRO_PREC_FP32, hm.cw[l].data(), (float)sc, pf.data());
+          if ((rc = upload(s, pf.data(), n, &dp))) return rc;
+          ga.w_f32[i][l] = dp;
+        }
+        {
+          size_t n = gcnn_packed_elems(l, cin, co, HYDRO_PREC_BF16);
+          std::vector<float> pf(n);
+          gcnn_pack_layer(l, cin, co, HYDRO_PREC_BF16, hm.cw[l].data(), (float)sc, pf.data());
+          std::vector<uint16_t> pb(n);
+          for (size_t t = 0; t < n; ++t) pb[t] = f32_to_bf16_bits(pf[t]);
+          if ((rc = upload(s, pb.data(), n, &bp))) return rc;
+          ga.w_bf[i][l] = reinterpret_cast<const __bf16*>(bp);
+        }
+        if ((rc = upload(s, bias.data(), bias.size(), &dp))) return rc;
+        ga.bias[i][l] = dp;
+        {
+          std::vector<float> wt(hm.cw[l].size());
+          for (int o = 0; o < co; ++o)
+            for (int c = 0; c < cin; ++c)
+              for (int t = 0; t < 9; ++t) wt[((size_t)o * 9 + t) * cin + c] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
+          if ((rc = upload(s, wt.data(), wt.size(), &dp))) return rc;
+          ga.wt_canon[i][l] = dp;
+        }
+        if ((rc = upload(s, hm.cb[l].data(), hm.cb[l].size(), &dp))) return rc;
+        ga.b_canon[i][l] = dp;
+        cin = co;
+      }
+      int rc;
+      float* dp;
+      if ((rc = upload(s, hm.fcw.data(), hm.fcw.size(), &dp))) return rc;
+      ga.fc_w[i] = dp;
+      if ((rc = upload(s, hm.fcb.data(), hm.fcb.size(), &dp))) return rc;
+      ga.fc_b[i] = dp;
     } else {
       int i = ca.n_preds++;
       ca.pred[i] = k;
@@ -538,6 +608,27 @@ static int pack_models(hydro_session* s) {
     }
   }
   ma.esc_cap = esc_cap;
+  if (s->gcnn.n_preds > 0) {
+    GcnnArgs& ga = s->gcnn;
+    ga.pad_raw = pad_raw;
+    int64_t mx = 0;
+    for (int i = 0; i < ga.n_preds; ++i)
+      for (int l = 0; l < ga.n_layers[i]; ++l) {
+        const int64_t h = ga.in_hw[i] >> (l + 1);
+        mx = std::max<int64_t>(mx, h * h * ga.widths[i][l]);
+      }
+    ga.act_stride = mx;
+    int rc;
+    for (int b = 0; b < 2; ++b)
+      if ((rc = sess_alloc(s, &ga.act[b], (size_t)s->cap * mx * sizeof(float)))) return rc;
+    ga.esc_half = mx;
+    ga.esc_stride = 2 * mx;
+    ga.esc_cap = std::min(esc_cap, 32);
+    for (int i = 0; i < ga.n_preds; ++i)
+      if ((rc = sess_alloc(s, (void**)&ga.esc_act[i], (size_t)ga.esc_cap * ga.esc_stride * sizeof(double)))) return rc;
+    ga.rest_per_block = 2 * mx;
+    if ((rc = sess_alloc(s, (void**)&ga.rest_scratch, (size_t)ga.rest_per_block * s->n_cu * sizeof(double)))) return rc;
+  }
   if (ca.n_preds > 0) {
     // FP64 tier scratch: two activation buffers per block (largest layer output)
     int64_t per = 0;
@@ -653,6 +744,10 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   s->pol = *policy;
   if (s->pol.tau <= 0.f) s->pol.tau = 0.015f;
   if (s->pol.tau32 <= 0.f) s->pol.tau32 = 1e-5f;
+  for (int i = 0; i < kMaxK; ++i) {
+    s->tau_k[i] = s->pol.tau;
+    s->tau32_k[i] = s->pol.tau32;
+  }
   s->K = k;
   s->fh = frame_h;
   s->fw = frame_w;
@@ -784,17 +879,17 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
     f.count_eval = 1;
     f.defer = Queues{bf ? s->q2 : s->q3, bf ? s->st->bcount : s->st->ecount, s->cap};
     f.defer_stat = bf ? s->st->r_rescored : s->st->r_esc;
-    f.tau = bf ? s->pol.tau : s->pol.tau32;
+    for (int k = 0; k < kMaxK; ++k) f.tau[k] = bf ? s->tau_k[k] : s->tau32_k[k];
   } else if (tier == TIER_F32) {
     f.count_eval = 0;
     f.defer = Queues{s->q3, s->st->ecount, s->cap};
     f.defer_stat = s->st->r_esc;
-    f.tau = s->pol.tau32;
+    for (int k = 0; k < kMaxK; ++k) f.tau[k] = s->tau32_k[k];
   } else {
     f.count_eval = 0;
     f.defer = Queues{nullptr, nullptr, 0};
     f.defer_stat = nullptr;
-    f.tau = 0.f;
+    for (int k = 0; k < kMaxK; ++k) f.tau[k] = 0.f;
   }
   (void)fr;
   return f;
@@ -827,6 +922,29 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
         b.b2[0] = a.b2[i]; b.w1_canon[0] = a.w1_canon[i]; b.b1_canon[0] = a.b1_canon[i]; b.partial[0] = a.partial[i];
         b.esc_h[0] = a.esc_h[i];
         launch_mlp_pass(b, f, tier, grid, st);
+      }
+    }
+  }
+  if (s->gcnn.n_preds) {
+    GcnnArgs a = s->gcnn;
+    a.q = q;
+    a.fr = fr;
+    a.st = s->st;
+    a.count_ticks = 1;
+    a.prec = s->pol.precision;
+    if (s->pol.grouped || a.n_preds == 1) {
+      launch_gcnn_pass(a, f, tier, s->n_cu, st);
+    } else {
+      for (int i = 0; i < s->gcnn.n_preds; ++i) {
+        GcnnArgs b = a;
+        b.n_preds = 1;
+        b.pred[0] = a.pred[i]; b.n_layers[0] = a.n_layers[i]; b.in_hw[0] = a.in_hw[i]; b.class_mask[0] = a.class_mask[i];
+        for (int l = 0; l < HYDRO_MAX_LAYERS; ++l) {
+          b.widths[0][l] = a.widths[i][l]; b.w_bf[0][l] = a.w_bf[i][l]; b.w_f32[0][l] = a.w_f32[i][l];
+          b.bias[0][l] = a.bias[i][l]; b.wt_canon[0][l] = a.wt_canon[i][l]; b.b_canon[0][l] = a.b_canon[i][l];
+        }
+        b.fc_w[0] = a.fc_w[i]; b.fc_b[0] = a.fc_b[i]; b.esc_act[0] = a.esc_act[i];
+        launch_gcnn_pass(b, f, tier, s->n_cu, st);
       }
     }
   }
@@ -1214,6 +1332,49 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   if (he != hipSuccess) return fail(HYDRO_EDEVICE, std::string("logits: ") + hipGetErrorString(he));
   // leave the session ready for a new query
   return hydro_session_reset(s);
+}
+
+static double host_margin(const double* z, uint32_t mask) {
+  double in = -INFINITY, out = -INFINITY;
+  for (int c = 0; c < kClasses; ++c) {
+    if ((mask >> c) & 1u) in = std::max(in, z[c]);
+    else out = std::max(out, z[c]);
+  }
+  return in - out;
+}
+
+int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float safety, float* out_tau,
+                            float* out_tau32) {
+  g_err.clear();
+  if (!s || !frames) return fail(HYDRO_EINVAL, "NULL argument");
+  if (!(safety >= 1.f)) return fail(HYDRO_EINVAL, "safety must be at least 1");
+  const int64_t n = frames->n;
+  std::vector<double> z0((size_t)n * kClasses), z1((size_t)n * kClasses), z2((size_t)n * kClasses);
+  float tau[kMaxK], tau32[kMaxK];
+  for (int k = 0; k < s->K; ++k) {
+    int rc;
+    if ((rc = hydro_session_logits(s, k, 0, frames, z0.data()))) return rc;
+    if ((rc = hydro_session_logits(s, k, 1, frames, z1.data()))) return rc;
+    if ((rc = hydro_session_logits(s, k, 2, frames, z2.data()))) return rc;
+    const uint32_t mask = s->models[k].m.class_mask;
+    double e0 = 0, e1 = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double d2 = host_margin(&z2[i * kClasses], mask);
+      if (!std::isfinite(d2)) continue;
+      e0 = std::max(e0, std::fabs(host_margin(&z0[i * kClasses], mask) - d2));
+      e1 = std::max(e1, std::fabs(host_margin(&z1[i * kClasses], mask) - d2));
+    }
+    // floors keep a band even when the sample shows (almost) no error
+    tau[k] = (float)std::max(safety * e0, 1e-4);
+    tau32[k] = (float)std::max(safety * e1, 1e-6);
+  }
+  for (int k = 0; k < s->K; ++k) {
+    s->tau_k[k] = s->pol.precision == HYDRO_PREC_BF16 ? tau[k] : tau32[k];
+    s->tau32_k[k] = tau32[k];
+    if (out_tau) out_tau[k] = s->tau_k[k];
+    if (out_tau32) out_tau32[k] = tau32[k];
+  }
+  return HYDRO_OK;
 }
 
 int hydro_session_destroy(hydro_session* s) {

@@ -1,0 +1,434 @@
+// Generic CNN predicates on gfx950 (any square input divisible by 2^L, up to 4 conv3x3/s2
+// layers with widths that are multiples of 16): used when a model's activations do not fit the
+// fused per-frame kernel (e.g. 128x128 frames with 4 layers).
+//
+// Each layer is one implicit-GEMM launch over every queued frame of the tier: rows = output
+// positions of all frames (a 64-row tile may span frames, so each weight fragment serves
+// 64 positions), columns = output channels, K = (tap, input channel).  Activations live in a
+// per-tier scratch (bf16 or fp32, NHWC per frame).  Layer 1 reads the raw frame (bf16 or uint8,
+// exact in bf16) with the normalisation folded into its weights and border taps set to the raw
+// value that normalises to zero.  A head launch pools, applies FC and decides.  The FP64 tier
+// evaluates the same layers with one wave per output activation.
+#include "engine.h"
+
+namespace hydro {
+
+typedef float floatx4_g __attribute__((ext_vector_type(4)));
+
+template <typename T> struct GMf;
+template <> struct GMf<__bf16> { static constexpr int KSTEP = 32, KPL = 8; typedef bf16x8 frag; };
+template <> struct GMf<float> { static constexpr int KSTEP = 4, KPL = 1; typedef float frag; };
+
+__device__ inline floatx4 gmfma(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx4 gmfma(float a, float b, floatx4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// K of a layer, padded: layer 1 uses k = (u*3 + v)*3 + c (27 real values); later layers
+// k = (u*3 + v)*Cin + c.
+__host__ __device__ inline int g_kreal(int layer, int cin) { return layer == 0 ? 27 : 9 * cin; }
+template <typename T>
+__host__ __device__ inline int g_ksteps(int layer, int cin) {
+  return (g_kreal(layer, cin) + GMf<T>::KSTEP - 1) / GMf<T>::KSTEP;
+}
+
+constexpr int GT_M = 64;     // positions per tile
+constexpr int GT_N = 64;     // channels per tile
+
+// One layer over all frames of all generic-CNN predicates in this launch.
+template <typename T>
+__global__ __launch_bounds__(256) void gconv_layer_kernel(GcnnArgs a, int layer) {
+  typedef typename GMf<T>::frag frag;
+  constexpr int KSTEP = GMf<T>::KSTEP, KPL = GMf<T>::KPL;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  // tiles per predicate slot: ceil(count * P / 64) position tiles x Cout / 64 channel tiles
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) {
+    if (layer >= a.n_layers[i]) continue;
+    const int hout = a.in_hw[i] >> (layer + 1);
+    const int64_t rows = (int64_t)a.q.counts[a.pred[i]] * hout * hout;
+    total += (int)((rows + GT_M - 1) / GT_M) * (a.widths[i][layer] / GT_N > 0 ? a.widths[i][layer] / GT_N : 1);
+  }
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      if (layer >= a.n_layers[i]) continue;
+      const int hout = a.in_hw[i] >> (layer + 1);
+      const int64_t rows = (int64_t)a.q.counts[a.pred[i]] * hout * hout;
+      const int c = (int)((rows + GT_M - 1) / GT_M) * (a.widths[i][layer] / GT_N > 0 ? a.widths[i][layer] / GT_N : 1);
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    const int k = a.pred[slot];
+    const int cnt = a.q.counts[k];
+    const int hin = a.in_hw[slot] >> layer, hout = hin >> 1, P = hout * hout;
+    const int cin = layer == 0 ? 3 : a.widths[slot][layer - 1];
+    const int cout = a.widths[slot][layer];
+    const int nct = cout / GT_N > 0 ? cout / GT_N : 1;
+    const int ncw = cout < GT_N ? cout / 16 : 4;        // channel tiles of 16 per wave group
+    const int mt = off / nct, ct = off % nct;
+    const int KS = g_ksteps<T>(layer, cin);
+    const frag* wp = reinterpret_cast<const frag*>(sizeof(T) == 2 ? (const void*)a.w_bf[slot][layer]
+                                                                  : (const void*)a.w_f32[slot][layer]);
+    // this wave's 16 positions
+    const int64_t row = (int64_t)mt * GT_M + wave * 16 + l16;
+    const bool rvalid = row < (int64_t)cnt * P;
+    const int e = rvalid ? (int)(row / P) : 0;
+    const int p = rvalid ? (int)(row % P) : 0;
+    const int oi = p / hout, oj = p % hout;
+    const uint32_t idx = entry_idx(a.q.entries[(int64_t)k * a.q.cap + e]);
+    int ebase = 0;
+    for (int i = 0; i < slot; ++i) ebase += a.q.counts[a.pred[i]];
+    const int64_t ent = (int64_t)ebase + e;
+    const T* in = layer == 0 ? nullptr : reinterpret_cast<const T*>(a.act[(layer - 1) & 1]) + ent * a.act_stride;
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+      frag av;
+      if (layer == 0) {
+        // raw frame gather, k = (u*3 + v)*3 + c
+        if constexpr (sizeof(T) == 2) {
+          alignas(16) __bf16 t8[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int kk = ks * 32 + 8 * g + q;
+            float v = 0.f;
+            if (kk < 27 && rvalid) {
+              const int tap = kk / 3, c = kk % 3, y = 2 * oi + tap / 3 - 1, x = 2 * oj + tap % 3 - 1;
+              if (y < 0 || x < 0 || y >= hin || x >= hin) v = a.pad_raw;
+              else {
+                const int64_t o = (int64_t)idx * a.fr.elems + ((int64_t)y * hin + x) * 3 + c;
+                v = a.fr.dtype == HYDRO_DTYPE_BF16 ? (float)static_cast<const __bf16*>(a.fr.base)[o]
+                                                  : (float)static_cast<const uint8_t*>(a.fr.base)[o];
+              }
+            }
+            t8[q] = static_cast<__bf16>(v);
+          }
+          av = *reinterpret_cast<const bf16x8*>(t8);
+        } else {
+          const int kk = ks * 4 + g;
+          float v = 0.f;
+          if (kk < 27 && rvalid) {
+            const int tap = kk / 3, c = kk % 3, y = 2 * oi + tap / 3 - 1, x = 2 * oj + tap % 3 - 1;
+            if (y < 0 || x < 0 || y >= hin || x >= hin) v = a.pad_raw;
+            else {
+              const int64_t o = (int64_t)idx * a.fr.elems + ((int64_t)y * hin + x) * 3 + c;
+              v = a.fr.dtype == HYDRO_DTYPE_BF16 ? (float)static_cast<const __bf16*>(a.fr.base)[o]
+                                                : (float)static_cast<const uint8_t*>(a.fr.base)[o];
+            }
+          }
+          av = v;
+        }
+      } else {
+        const int k0 = ks * KSTEP + KPL * g;
+        const int tap = k0 / cin, c0 = k0 % cin;
+        const int y = 2 * oi + tap / 3 - 1, x = 2 * oj + tap % 3 - 1;
+        if (rvalid && tap < 9 && y >= 0 && x >= 0 && y < hin && x < hin) {
+          const T* src = in + ((int64_t)y * hin + x) * cin + c0;
+          if constexpr (sizeof(T) == 2) av = *reinterpret_cast<const bf16x8*>(src);
+          else av = *src;
+        } else {
+          if constexpr (sizeof(T) == 2) av = bf16x8{};
+          else av = 0.f;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < ncw) acc[j] = gmfma(wp[((int64_t)ks * (cout / 16) + ct * 4 + j) * 64 + lane], av, acc[j]);
+    }
+    // bias + ReLU -> activations (rows = channels 4g.., column = this lane's position)
+    if (rvalid) {
+      const float* bias = a.bias[slot][layer];
+      T* out = reinterpret_cast<T*>(a.act[layer & 1]) + ent * a.act_stride + (int64_t)p * cout;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= ncw) continue;
+        const int ch = ct * GT_N + j * 16 + 4 * g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[ch + r] = static_cast<T>(fmaxf(acc[j][r] + bias[ch + r], 0.f));
+      }
+    }
+  }
+}
+
+// Pool + FC + margin + decision: one wave per frame.
+template <typename T>
+__global__ __launch_bounds__(256) void gcnn_head_kernel(GcnnArgs a, Forward f) {
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * 4; base < total; base += gridDim.x * 4) {
+    const int t = base + (threadIdx.x >> 6);
+    const bool active = t < total;
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = a.q.counts[a.pred[i]];
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    if (!active) { slot = 0; off = 0; }
+    const int k = a.pred[slot];
+    const uint32_t e = active ? a.q.entries[(int64_t)k * a.q.cap + off] : 0u;
+    const int L = a.n_layers[slot];
+    const int hl = a.in_hw[slot] >> L, P = hl * hl;
+    const int cl = a.widths[slot][L - 1];
+    float zp[kClasses];
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c) zp[c] = 0.f;
+    if (active) {
+      int ebase = 0;
+      for (int i = 0; i < slot; ++i) ebase += a.q.counts[a.pred[i]];
+      const T* act = reinterpret_cast<const T*>(a.act[(L - 1) & 1]) + ((int64_t)ebase + off) * a.act_stride;
+      const float* fw = a.fc_w[slot];
+      for (int ch = lane; ch < cl; ch += 64) {
+        float s = 0.f;
+        for (int p = 0; p < P; ++p) s += (float)act[(int64_t)p * cl + ch];
+        const float gch = s / (float)P;
+#pragma unroll
+        for (int c = 0; c < kClasses; ++c) zp[c] += gch * fw[ch * kClasses + c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c)
+      for (int o = 32; o >= 1; o >>= 1) zp[c] += __shfl_xor(zp[c], o);
+    bool pass = false, defer = false;
+    if (active) {
+      float z[kClasses];
+      for (int c = 0; c < kClasses; ++c) z[c] = zp[c] + a.fc_b[slot][c];
+      const uint32_t idx = entry_idx(e);
+      if (f.logits != nullptr && lane == 0)
+        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)z[c];
+      const float d = class_margin(z, a.class_mask[slot]);
+      const float th = theta_of(f, k, idx);
+      pass = d > th;
+      defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau[k];
+    }
+    if (f.logits == nullptr) forward_decision(f, k, e, active && lane == 0, defer, pass);
+  }
+}
+
+// ---------------------------------------------------------------- FP64 tier
+__device__ inline double g_frame64(const FrameSrc& fr, uint32_t idx, int hw, int y, int x, int c) {
+  const int64_t o = (int64_t)idx * fr.elems + ((int64_t)y * hw + x) * 3 + c;
+  double v;
+  if (fr.dtype == HYDRO_DTYPE_BF16) v = (double)(float)static_cast<const __bf16*>(fr.base)[o];
+  else v = (double)static_cast<const uint8_t*>(fr.base)[o] / 255.0;
+  return (v - 0.5) * 4.0;
+}
+
+// One wave per output activation of every escalated frame (up to esc_cap per predicate).
+__global__ __launch_bounds__(256) void gconv64_layer_kernel(GcnnArgs a, int layer) {
+  int64_t total = 0;
+  int64_t outs[kMaxK];
+  int ne[kMaxK];
+  for (int i = 0; i < a.n_preds; ++i) {
+    ne[i] = layer < a.n_layers[i] ? min(a.q.counts[a.pred[i]], a.esc_cap) : 0;
+    const int hout = a.in_hw[i] >> (layer + 1);
+    outs[i] = layer < a.n_layers[i] ? (int64_t)hout * hout * a.widths[i][layer] : 0;
+    total += ne[i] * outs[i];
+  }
+  const int lane = threadIdx.x & 63;
+  for (int64_t gi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); gi < total; gi += (int64_t)gridDim.x * 4) {
+    int slot = 0;
+    int64_t rem = gi;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int64_t c = ne[i] * outs[i];
+      if (rem < c) { slot = i; break; }
+      rem -= c;
+    }
+    const int e = (int)(rem / outs[slot]);
+    const int oi_all = (int)(rem % outs[slot]);
+    const int cout = a.widths[slot][layer];
+    const int cin = layer == 0 ? 3 : a.widths[slot][layer - 1];
+    const int hin = a.in_hw[slot] >> layer, hout = hin >> 1;
+    const int p = oi_all / cout, o = oi_all % cout, i = p / hout, j = p % hout;
+    const uint32_t idx = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + e]);
+    double* act = a.esc_act[slot] + (int64_t)e * a.esc_stride;
+    const double* in = layer == 0 ? nullptr : act + ((layer - 1) & 1) * a.esc_half;
+    const float* W = a.wt_canon[slot][layer] + (int64_t)o * 9 * cin;   // [co][3][3][ci]
+    double s = 0.0;
+    for (int kk = lane; kk < 9 * cin; kk += 64) {
+      const int t = kk / cin, c = kk % cin;
+      const int y = 2 * i + t / 3 - 1, x = 2 * j + t % 3 - 1;
+      if (y < 0 || x < 0 || y >= hin || x >= hin) continue;
+      const double xv = layer == 0 ? g_frame64(a.fr, idx, hin, y, x, c) : in[((int64_t)y * hin + x) * cin + c];
+      s = fma((double)W[kk], xv, s);
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) {
+      s += (double)a.b_canon[slot][layer][o];
+      act[(layer & 1) * a.esc_half + (int64_t)p * cout + o] = s > 0.0 ? s : 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gcnn64_head_kernel(GcnnArgs a, Forward f) {
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += min(a.q.counts[a.pred[i]], a.esc_cap);
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * 4; base < total; base += gridDim.x * 4) {
+    const int t = base + (threadIdx.x >> 6);
+    const bool active = t < total;
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = min(a.q.counts[a.pred[i]], a.esc_cap);
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    if (!active) { slot = 0; off = 0; }
+    const int k = a.pred[slot];
+    const uint32_t e = active ? a.q.entries[(int64_t)k * a.q.cap + off] : 0u;
+    const int L = a.n_layers[slot];
+    const int hl = a.in_hw[slot] >> L, P = hl * hl;
+    const int cl = a.widths[slot][L - 1];
+    double zp[kClasses];
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c) zp[c] = 0.0;
+    if (active) {
+      const double* act = a.esc_act[slot] + (int64_t)off * a.esc_stride + ((L - 1) & 1) * a.esc_half;
+      const float* fw = a.fc_w[slot];
+      for (int ch = lane; ch < cl; ch += 64) {
+        double s = 0.0;
+        for (int p = 0; p < P; ++p) s += act[(int64_t)p * cl + ch];
+        const double gch = s / (double)P;
+#pragma unroll
+        for (int c = 0; c < kClasses; ++c) zp[c] = fma(gch, (double)fw[ch * kClasses + c], zp[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c)
+      for (int o = 32; o >= 1; o >>= 1) zp[c] += __shfl_xor(zp[c], o);
+    bool pass = false;
+    const bool lead = active && lane == 0;
+    if (lead) {
+      double z[kClasses];
+      for (int c = 0; c < kClasses; ++c) z[c] = zp[c] + (double)a.fc_b[slot][c];
+      const uint32_t idx = entry_idx(e);
+      if (f.logits != nullptr)
+        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = z[c];
+      pass = class_margin(z, a.class_mask[slot]) > (double)theta_of(f, k, idx);
+    }
+    if (f.logits == nullptr) forward_decision(f, k, e, lead, false, pass);
+  }
+}
+
+// Escalated entries beyond esc_cap: one workgroup per entry, per-block scratch.
+__global__ __launch_bounds__(256) void gcnn64_rest_kernel(GcnnArgs a, Forward f, double* scratch, int64_t per_block) {
+  const int tid = threadIdx.x;
+  double* buf[2] = {scratch + (int64_t)blockIdx.x * per_block, scratch + (int64_t)blockIdx.x * per_block + per_block / 2};
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) total += max(0, a.q.counts[a.pred[i]] - a.esc_cap);
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = max(0, a.q.counts[a.pred[i]] - a.esc_cap);
+      if (off < c) { slot = i; break; }
+      off -= c;
+    }
+    off += a.esc_cap;
+    const int k = a.pred[slot];
+    const uint32_t e = a.q.entries[(int64_t)k * a.q.cap + off];
+    const uint32_t idx = entry_idx(e);
+    const int L = a.n_layers[slot];
+    for (int layer = 0; layer < L; ++layer) {
+      const int cout = a.widths[slot][layer];
+      const int cin = layer == 0 ? 3 : a.widths[slot][layer - 1];
+      const int hin = a.in_hw[slot] >> layer, hout = hin >> 1;
+      const double* in = buf[(layer + 1) & 1];
+      double* out = buf[layer & 1];
+      for (int q = tid; q < hout * hout * cout; q += 256) {
+        const int p = q / cout, o = q % cout, i = p / hout, j = p % hout;
+        const float* W = a.wt_canon[slot][layer] + (int64_t)o * 9 * cin;
+        double s = (double)a.b_canon[slot][layer][o];
+        for (int t9 = 0; t9 < 9; ++t9) {
+          const int y = 2 * i + t9 / 3 - 1, x = 2 * j + t9 % 3 - 1;
+          if (y < 0 || x < 0 || y >= hin || x >= hin) continue;
+          for (int c = 0; c < cin; ++c) {
+            const double xv = layer == 0 ? g_frame64(a.fr, idx, hin, y, x, c) : in[((int64_t)y * hin + x) * cin + c];
+            s = fma((double)W[t9 * cin + c], xv, s);
+          }
+        }
+        out[q] = s > 0.0 ? s : 0.0;
+      }
+      __syncthreads();
+    }
+    if (tid < 64) {
+      const int lane = tid;
+      const int hl = a.in_hw[slot] >> L, P = hl * hl, cl = a.widths[slot][L - 1];
+      const double* act = buf[(L - 1) & 1];
+      double zp[kClasses];
+      for (int c = 0; c < kClasses; ++c) zp[c] = 0.0;
+      for (int ch = lane; ch < cl; ch += 64) {
+        double s = 0.0;
+        for (int p = 0; p < P; ++p) s += act[(int64_t)p * cl + ch];
+        const double gch = s / (double)P;
+        for (int c = 0; c < kClasses; ++c) zp[c] = fma(gch, (double)a.fc_w[slot][ch * kClasses + c], zp[c]);
+      }
+      for (int c = 0; c < kClasses; ++c)
+        for (int o = 32; o >= 1; o >>= 1) zp[c] += __shfl_xor(zp[c], o);
+      bool pass = false;
+      if (lane == 0) {
+        double z[kClasses];
+        for (int c = 0; c < kClasses; ++c) z[c] = zp[c] + (double)a.fc_b[slot][c];
+        if (f.logits != nullptr)
+          for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = z[c];
+        pass = class_margin(z, a.class_mask[slot]) > (double)theta_of(f, k, idx);
+      }
+      if (f.logits == nullptr) forward_decision(f, k, e, lane == 0, false, pass);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- host side
+size_t gcnn_packed_elems(int layer, int cin, int cout, int prec) {
+  const int ks = prec == HYDRO_PREC_BF16 ? g_ksteps<__bf16>(layer, cin) : g_ksteps<float>(layer, cin);
+  const int kpl = prec == HYDRO_PREC_BF16 ? 8 : 1;
+  return (size_t)ks * (cout / 16) * 64 * kpl;
+}
+
+// [kstep][channel tile of 16][64 lanes][KPL]; lane l: output channel tile*16 + l%16,
+// k = kstep*KSTEP + KPL*(l/16) + e.
+void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, float scale, float* out) {
+  const int KSTEP = prec == HYDRO_PREC_BF16 ? 32 : 4, KPL = prec == HYDRO_PREC_BF16 ? 8 : 1;
+  const int ks_n = prec == HYDRO_PREC_BF16 ? g_ksteps<__bf16>(layer, cin) : g_ksteps<float>(layer, cin);
+  const int kreal = g_kreal(layer, cin);
+  size_t o = 0;
+  for (int ks = 0; ks < ks_n; ++ks)
+    for (int ct = 0; ct < cout / 16; ++ct)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < KPL; ++e) {
+          const int k = ks * KSTEP + KPL * (lane >> 4) + e;
+          const int oc = ct * 16 + (lane & 15);
+          float v = 0.f;
+          if (k < kreal) {
+            int tap, ic;
+            if (layer == 0) { tap = k / 3; ic = k % 3; }
+            else { tap = k / cin; ic = k % cin; }
+            v = scale * w[((size_t)(oc * cin + ic) * 3 + tap / 3) * 3 + tap % 3];
+          }
+          out[o++] = v;
+        }
+}
+
+void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
+  if (a.n_preds == 0) return;
+  int maxl = 0;
+  for (int i = 0; i < a.n_preds; ++i) maxl = a.n_layers[i] > maxl ? a.n_layers[i] : maxl;
+  if (tier == TIER_F64) {
+    for (int l = 0; l < maxl; ++l) hipLaunchKernelGGL(gconv64_layer_kernel, dim3(grid * 8), dim3(256), 0, s, a, l);
+    hipLaunchKernelGGL(gcnn64_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    hipLaunchKernelGGL(gcnn64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f, a.rest_scratch, a.rest_per_block);
+    return;
+  }
+  const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;
+  for (int l = 0; l < maxl; ++l) {
+    if (bf) hipLaunchKernelGGL(gconv_layer_kernel<__bf16>, dim3(grid * 4), dim3(256), 0, s, a, l);
+    else hipLaunchKernelGGL(gconv_layer_kernel<float>, dim3(grid * 4), dim3(256), 0, s, a, l);
+  }
+  if (bf) hipLaunchKernelGGL(gcnn_head_kernel<__bf16>, dim3(grid), dim3(256), 0, s, a, f);
+  else hipLaunchKernelGGL(gcnn_head_kernel<float>, dim3(grid), dim3(256), 0, s, a, f);
+}
+
+}  // namespace hydro

@@ -100,6 +100,7 @@ def lib():
         L.hydro_session_info.argtypes = [vp, C.POINTER(QueryInfo)]
         L.hydro_session_routes.argtypes = [vp, i64, i64, C.POINTER(C.c_uint32)]
         L.hydro_session_logits.argtypes = [vp, i32, i32, C.POINTER(Frames), C.POINTER(C.c_double)]
+        L.hydro_session_calibrate.argtypes = [vp, C.POINTER(Frames), C.c_float, FP, FP]
         L.hydro_session_destroy.argtypes = [vp]
         L.hydro_free.argtypes = [vp]
         L.hydro_free.restype = None
@@ -107,7 +108,7 @@ def lib():
         L.hydro_version.restype = C.c_char_p
         for name in ("hydro_query", "hydro_session_create", "hydro_session_reset", "hydro_session_push",
                      "hydro_session_finish", "hydro_session_info", "hydro_session_routes", "hydro_session_logits",
-                     "hydro_session_destroy"):
+                     "hydro_session_calibrate", "hydro_session_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -115,7 +116,8 @@ def lib():
 
 EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_session_create", "hydro_session_reset",
             "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
-            "hydro_session_logits", "hydro_session_destroy", "hydro_free", "hydro_last_error", "hydro_version")
+            "hydro_session_logits", "hydro_session_calibrate", "hydro_session_destroy", "hydro_free",
+            "hydro_last_error", "hydro_version")
 
 
 def _check(rc: int):
@@ -262,6 +264,14 @@ class Session:
         _check(lib().hydro_session_logits(self._h, pred, tier, C.byref(fr),
                                           out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+    def calibrate(self, frames, dtype: str, safety: float = 2.0):
+        """Per-predicate re-score bands from measured margin errors (see hydro.h)."""
+        fr = _frames_struct(frames, dtype, 0)
+        t = np.zeros(self.k, dtype=np.float32)
+        t32 = np.zeros(self.k, dtype=np.float32)
+        _check(lib().hydro_session_calibrate(self._h, C.byref(fr), float(safety), _fp(t), _fp(t32)))
+        return t, t32
 
     def close(self):
         if self._h:

@@ -78,7 +78,7 @@ def test_create_rejects_bad_arguments():
 def test_cnn_shape_support_is_checked():
     pol = hydro.make_policy()
     rng = np.random.default_rng(1)
-    widths = (16, 32, 48)                     # not (16m, 32m, 64m)
+    widths = (16, 32, 40)                     # not multiples of 16
     convs, cin = [], 3
     for co in widths:
         convs.append((rng.standard_normal((co, cin, 3, 3)), np.zeros(co)))

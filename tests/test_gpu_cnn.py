@@ -169,3 +169,16 @@ def test_graph_replays_match_eager(c2, route):
         assert np.array_equal(ids, c2.expect), f"replay {rep}"
         check_stats(stats, c2.n, ids.size)
     s.close()
+
+
+def test_cnn_calibrated_bands(c2):
+    cfg = hs.workload(2)
+    cal = torch.from_numpy(hs.make_frames(cfg, 0, 2048, data_seed=cfg.data_seed + 101)).cuda()
+    s = hydro.Session(c2.specs(), hydro.make_policy("score", precision="bf16", wave=4096), 64, c2.n)
+    tau, tau32 = s.calibrate(cal, "bf16", safety=2.0)
+    log(f"[gpu] cnn calibrated tau={np.round(tau, 5).tolist()} tau32={tau32.tolist()}")
+    assert np.all(tau > 0) and np.all(tau < 0.05) and np.all(tau32 < 1e-4)
+    s.push(c2.device_frames(), c2.cfg.dtype, c2.pt.thresholds, c2.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c2.expect)
+    s.close()

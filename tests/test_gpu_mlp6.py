@@ -1,0 +1,65 @@
+"""GPU parity of the batched MLP workload (64x64x3 bf16 frames, six MLP 12288-h-10 predicates,
+h = 256 ... 2048, grouped into one launch per tier) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import hydro_synth as hs
+from oracle import hydro_oracle as ho
+from tests.gpu_util import case, check_stats, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2403_14902_amd import hydro  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return case(3, 4096)
+
+
+@pytest.fixture(scope="module")
+def c3z():
+    return case(3, 512, logits=True)
+
+
+@pytest.fixture(scope="module")
+def calib_frames():
+    cfg = hs.workload(3)
+    return torch.from_numpy(hs.make_frames(cfg, 0, 1024, data_seed=cfg.data_seed + 101)).cuda()
+
+
+def test_mlp6_logits_each_tier(c3z):
+    s = hydro.Session(c3z.specs(), hydro.make_policy("score", precision="bf16"), 64, c3z.n)
+    dev = c3z.device_frames()
+    for k in range(c3z.cfg.k):
+        for tier, tol in ((0, 0.2), (1, 1e-3), (2, 1e-9)):
+            err = np.abs(s.logits(k, tier, dev, "bf16") - c3z.Z[k]).max()
+            log(f"[gpu] mlp6 predicate {k} (h={c3z.cfg.models[k].hidden}) tier {tier}: max |z - z64| = {err:.3e}")
+            assert err <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("route", ["score", "fixed", "learned"])
+def test_mlp6_calibrated_query(c3, calib_frames, route):
+    pol = hydro.make_policy(route, precision="bf16", wave=1024, log_routes=1)
+    s = hydro.Session(c3.specs(), pol, 64, c3.n)
+    tau, tau32 = s.calibrate(calib_frames, "bf16", safety=3.0)
+    log(f"[gpu] mlp6 calibrated tau={np.round(tau, 5).tolist()} tau32={tau32.tolist()}")
+    s.push(c3.device_frames(), "bf16", c3.pt.thresholds, c3.seg_len)
+    ids, stats = s.finish()
+    log(f"  |R|={ids.size} evaluated={[st['evaluated'] for st in stats]} rescored={[st['rescored'] for st in stats]}")
+    assert np.array_equal(ids, c3.expect)
+    check_stats(stats, c3.n, ids.size)
+    ok, rev, rps, out, msg = ho.replay_route(c3.P, hydro.decode_routes(s.routes(0, c3.n)))
+    assert ok, msg
+    if route == "fixed":
+        _, ev, ps = ho.short_circuit_eval(c3.P, list(range(6)))
+        assert [st["evaluated"] for st in stats] == list(ev)
+    s.close()
+
+
+def test_mlp6_ungrouped_matches(c3):
+    pol = hydro.make_policy("score", precision="fp32", wave=2048, grouped=0)
+    ids, stats = hydro.query(c3.device_frames(), "bf16", c3.specs(), c3.pt.thresholds, c3.seg_len, pol)
+    assert np.array_equal(ids, c3.expect)
