@@ -132,6 +132,10 @@ typedef struct {
   int32_t log_routes;                    /* 1: record every tuple's visit sequence (debug)       */
   int32_t time_kernels;                  /* 1: bracket each round's phases with HIP events and
                                             report their summed durations in hydro_query_info    */
+  int32_t autotune;                      /* 1: time each candidate GEMM tile shape on every MLP
+                                            predicate at setup (first push) and keep the fastest;
+                                            results cached in the JSON file named by
+                                            HYDRO_TUNE_CACHE when that is set (default 0)        */
   float explore;                         /* LEARNED: fraction of routing batches kept on SCORE
                                             as the judge's control arm (default 0.05)            */
   uint64_t seed;                         /* LEARNED: router init / exploration seed              */

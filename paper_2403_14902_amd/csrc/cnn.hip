@@ -235,11 +235,16 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       for (int ks = 0; ks < KS1; ++ks) a1[q][ks] = gather1(wave * 8 + q, ks);
   }
 
-  floatx4 acc2[2][NT2];
+  // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (8 waves cover 16 x NT2)
+  constexpr int MT2 = M == 1 ? 2 : 4, NW2 = M == 1 ? 2 : (M == 2 ? 2 : 4);
+  constexpr int NG2 = NT2 / NW2;                       // channel groups
+  const int mg2 = wave / NG2, ng2 = wave % NG2;
+  static_assert((16 / MT2) * NG2 == 8, "layer-2 wave tiling must cover 8 waves");
+  floatx4 acc2[MT2][NW2];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < MT2; ++q)
 #pragma unroll
-    for (int j = 0; j < NT2; ++j) acc2[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NW2; ++j) acc2[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
 
   for (int slab = 0; slab < M; ++slab) {
     // layer 1: 64 m-tiles (16 positions each) x 16 channels; wave w owns m-tiles 8w..8w+7
@@ -266,36 +271,36 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
                 fmaxf(acc[1] + bb1[1], 0.f), fmaxf(acc[2] + bb1[2], 0.f), fmaxf(acc[3] + bb1[3], 0.f));
     }
     __syncthreads();
-    // layer 2 partial: K = 9 taps x 16 channels of this slab; wave w owns position tiles 2w, 2w+1
-    const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64;
-    frag bcur[NT2];
+    // layer 2 partial: K = 9 taps x 16 channels of this slab
+    const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64 + ng2 * NW2 * 64 + lane;
+    frag bcur[NW2];
 #pragma unroll
-    for (int nt = 0; nt < NT2; ++nt) bcur[nt] = w2p[nt * 64 + lane];
+    for (int n = 0; n < NW2; ++n) bcur[n] = w2p[n * 64];
 #pragma unroll 1
     for (int ks = 0; ks < KS2; ++ks) {
-      frag bnext[NT2];
+      frag bnext[NW2];
       if (ks + 1 < KS2) {
 #pragma unroll
-        for (int nt = 0; nt < NT2; ++nt) bnext[nt] = w2p[((ks + 1) * NT2 + nt) * 64 + lane];
+        for (int n = 0; n < NW2; ++n) bnext[n] = w2p[((ks + 1) * NT2 + n) * 64];
       }
       const int k0 = ks * KSTEP + KPL * g;
       int t = k0 / CB1;
       const int c0 = k0 % CB1;
       if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
       const int u = t / 3, v = t % 3;
-      frag av[2];
+      frag av[MT2];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int px = (wave * 2 + q) * 16 + l16, i = px >> 4, j = px & 15;
+      for (int q = 0; q < MT2; ++q) {
+        const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
         av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
       }
 #pragma unroll
-      for (int nt = 0; nt < NT2; ++nt)
+      for (int n = 0; n < NW2; ++n)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc2[q][nt] = mfma(bcur[nt], av[q], acc2[q][nt]);
+        for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bcur[n], av[q], acc2[q][n]);
       if (ks + 1 < KS2) {
 #pragma unroll
-        for (int nt = 0; nt < NT2; ++nt) bcur[nt] = bnext[nt];
+        for (int n = 0; n < NW2; ++n) bcur[n] = bnext[n];
       }
     }
     __syncthreads();
@@ -303,14 +308,14 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 
   // ---- layer-2 epilogue into L2 (overwrites FR / S1)
 #pragma unroll
-  for (int nt = 0; nt < NT2; ++nt) {
-    const int ch = nt * 16 + 4 * g;
+  for (int n = 0; n < NW2; ++n) {
+    const int ch = (ng2 * NW2 + n) * 16 + 4 * g;
     const float bb0 = b2[ch], bb1v = b2[ch + 1], bb2 = b2[ch + 2], bb3 = b2[ch + 3];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int px = (wave * 2 + q) * 16 + l16, i = px >> 4, j = px & 15;
-      store4<T>(L2 + ((i + 1) * L2_W + (j + 1)) * C2P + ch, fmaxf(acc2[q][nt][0] + bb0, 0.f),
-                fmaxf(acc2[q][nt][1] + bb1v, 0.f), fmaxf(acc2[q][nt][2] + bb2, 0.f), fmaxf(acc2[q][nt][3] + bb3, 0.f));
+    for (int q = 0; q < MT2; ++q) {
+      const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
+      store4<T>(L2 + ((i + 1) * L2_W + (j + 1)) * C2P + ch, fmaxf(acc2[q][n][0] + bb0, 0.f),
+                fmaxf(acc2[q][n][1] + bb1v, 0.f), fmaxf(acc2[q][n][2] + bb2, 0.f), fmaxf(acc2[q][n][3] + bb3, 0.f));
     }
   }
   for (int p = tid; p < (2 * L2_W - 1) * (C2 / 4); p += NTHR) {
@@ -322,58 +327,65 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   if (next_valid) frame_issue(a, next_idx, pf);
   __syncthreads();
 
-  // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave w: position tiles
-  //      2(w&1), 2(w&1)+1, channel tiles (w>>1)*M .. (w>>1)*M + M - 1
+  // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave tile MT3 x NW3
   constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
-  const int mh = wave & 1, ng = wave >> 1;
-  floatx4 acc3[2][M];
+  constexpr int MT3 = M == 1 ? 2 : 4, NW3 = 2 * M / MT3;
+  constexpr int MG3 = 4 / MT3;                         // position groups (1 or 2)
+  static_assert(MG3 * (NT3 / NW3) == 8, "layer-3 wave tiling must cover 8 waves");
+  const int mh = wave % MG3, ng = wave / MG3;
+  floatx4 acc3[MT3][NW3];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < MT3; ++q)
 #pragma unroll
-    for (int j = 0; j < M; ++j) acc3[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-  const frag* w3p = reinterpret_cast<const frag*>(wpk[2]) + (size_t)(ng * M) * 64 + lane;
-  frag b3cur[M];
+    for (int j = 0; j < NW3; ++j) acc3[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  const frag* w3p = reinterpret_cast<const frag*>(wpk[2]) + (size_t)(ng * NW3) * 64 + lane;
+  frag b3cur[NW3];
 #pragma unroll
-  for (int n = 0; n < M; ++n) b3cur[n] = w3p[n * 64];
+  for (int n = 0; n < NW3; ++n) b3cur[n] = w3p[n * 64];
 #pragma unroll 1
   for (int ks = 0; ks < KS3; ++ks) {
-    frag b3next[M];
+    frag b3next[NW3];
     if (ks + 1 < KS3) {
 #pragma unroll
-      for (int n = 0; n < M; ++n) b3next[n] = w3p[((ks + 1) * NT3 + n) * 64];
+      for (int n = 0; n < NW3; ++n) b3next[n] = w3p[((ks + 1) * NT3 + n) * 64];
     }
     const int k0 = ks * KSTEP + KPL * g;
     const int t = k0 / C2, c0 = k0 % C2;
     const int u = t / 3, v = t % 3;
-    frag av[2];
+    frag av[MT3];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int px = (mh * 2 + q) * 16 + l16, i = px >> 3, j = px & 7;
+    for (int q = 0; q < MT3; ++q) {
+      const int px = (mh * MT3 + q) * 16 + l16, i = px >> 3, j = px & 7;
       av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
     }
 #pragma unroll
-    for (int n = 0; n < M; ++n)
+    for (int n = 0; n < NW3; ++n)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc3[q][n] = mfma(b3cur[n], av[q], acc3[q][n]);
+      for (int q = 0; q < MT3; ++q) acc3[q][n] = mfma(b3cur[n], av[q], acc3[q][n]);
     if (ks + 1 < KS3) {
 #pragma unroll
-      for (int n = 0; n < M; ++n) b3cur[n] = b3next[n];
+      for (int n = 0; n < NW3; ++n) b3cur[n] = b3next[n];
     }
   }
-  // ReLU + pooled partial sums over this wave's 32 positions (positions = lanes l16 and q)
+  // ReLU + pooled partial sums over this wave's positions
 #pragma unroll
-  for (int n = 0; n < M; ++n) {
-    const int ch0 = (ng * M + n) * 16 + 4 * g;
+  for (int n = 0; n < NW3; ++n) {
+    const int ch0 = (ng * NW3 + n) * 16 + 4 * g;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float bb = b3[ch0 + r];
-      float s = fmaxf(acc3[0][n][r] + bb, 0.f) + fmaxf(acc3[1][n][r] + bb, 0.f);
+      float s = 0.f;
+#pragma unroll
+      for (int q = 0; q < MT3; ++q) s += fmaxf(acc3[q][n][r] + bb, 0.f);
       s += __shfl_xor(s, 1);
       s += __shfl_xor(s, 2);
       s += __shfl_xor(s, 4);
       s += __shfl_xor(s, 8);
       if (l16 == 0) sh.gpart[mh][ch0 + r] = s;
     }
+  }
+  if (MG3 == 1) {
+    for (int c = tid; c < C3; c += NTHR) sh.gpart[1][c] = 0.f;
   }
   __syncthreads();
   // wave 0: FC (lanes over channels) -> z; the other waves store the next frame meanwhile

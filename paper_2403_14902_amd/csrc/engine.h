@@ -20,7 +20,9 @@ struct MlpArgs {
   const float* b2[kMaxK];
   const float* w1_canon[kMaxK];     // [d_in][hidden]
   const float* b1_canon[kMaxK];
-  float* partial[kMaxK];            // [hidden/64][part_cap][10]
+  float* partial[kMaxK];            // [hidden / part_w][part_cap][10]
+  int part_w[kMaxK];                // hidden units per partial-logit part (half the tile width)
+  int tile_cfg[kMaxK];              // GEMM tile configuration (see mlp_tile_bn)
   int64_t part_cap;
   double* esc_h[kMaxK];             // FP64 tier: partial hidden sums [chunk][esc_cap][hidden]
   int esc_cap;
@@ -92,7 +94,10 @@ void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, h
 size_t gcnn_packed_elems(int layer, int cin, int cout, int prec);
 void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, float scale, float* out);
 
+constexpr int MLP_TILE_CONFIGS = 4;
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
+void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s);
+int mlp_tile_bn(int cfg);
 void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 size_t cnn_packed_elems(int variant, int layer, int prec);
 void cnn_pack_layer(int variant, int layer, int prec, const float* w_canon, float scale, float* out);

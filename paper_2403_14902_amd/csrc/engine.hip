@@ -478,7 +478,15 @@ static int pack_models(hydro_session* s) {
       ma.w1_canon[i] = dp;
       if ((rc = upload(s, hm.b1.data(), hm.b1.size(), &dp))) return rc;
       ma.b1_canon[i] = dp;
-      if ((rc = sess_alloc(s, (void**)&ma.partial[i], (size_t)(H / 64) * s->cap * kClasses * sizeof(float)))) return rc;
+      if ((rc = sess_alloc(s, (void**)&ma.partial[i], (size_t)(H / 32) * s->cap * kClasses * sizeof(float)))) return rc;
+      {
+        // HYDRO_MLP_TILE forces one tile configuration (tests exercise each)
+        const char* ft = getenv("HYDRO_MLP_TILE");
+        int cfg = (ft && *ft) ? atoi(ft) : 0;
+        if (cfg < 0 || cfg >= MLP_TILE_CONFIGS) cfg = 0;
+        ma.tile_cfg[i] = cfg;
+        ma.part_w[i] = mlp_tile_bn(cfg) / 2;
+      }
       {
         const int nch = (D + 1535) / 1536;   // chunking of the FP64 tier's hidden pass
         if ((rc = sess_alloc(s, (void**)&ma.esc_h[i], (size_t)nch * esc_cap * H * sizeof(double)))) return rc;
@@ -920,7 +928,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
         b.pred[0] = a.pred[i]; b.d_in[0] = a.d_in[i]; b.hidden[0] = a.hidden[i]; b.class_mask[0] = a.class_mask[i];
         b.w1_bf[0] = a.w1_bf[i]; b.w1_f32[0] = a.w1_f32[i]; b.b1_fold[0] = a.b1_fold[i]; b.w2[0] = a.w2[i];
         b.b2[0] = a.b2[i]; b.w1_canon[0] = a.w1_canon[i]; b.b1_canon[0] = a.b1_canon[i]; b.partial[0] = a.partial[i];
-        b.esc_h[0] = a.esc_h[i];
+        b.esc_h[0] = a.esc_h[i]; b.tile_cfg[0] = a.tile_cfg[i]; b.part_w[0] = a.part_w[i];
         launch_mlp_pass(b, f, tier, grid, st);
       }
     }
@@ -975,6 +983,134 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
   }
 }
 
+// ---------------------------------------------------------------- autotuner
+// For every MLP predicate, time each GEMM tile shape on a synthetic queue of the session's size
+// class (real weights, constant frames) and keep the fastest.  Results are cached by
+// (gfx950, precision, frame dtype, input size, hidden width, queue size) in a small JSON object.
+static std::string tune_key(int prec, int dtype, int D, int H, int64_t q) {
+  return "gfx950/" + std::string(prec == HYDRO_PREC_BF16 ? "bf16" : "fp32") + "/" +
+         (dtype == HYDRO_DTYPE_BF16 ? "bf16" : dtype == HYDRO_DTYPE_U8 ? "u8" : "f32") + "/D" + std::to_string(D) +
+         "/h" + std::to_string(H) + "/q" + std::to_string(q);
+}
+
+static std::vector<std::pair<std::string, int>> tune_load(const char* path) {
+  std::vector<std::pair<std::string, int>> out;
+  FILE* f = path ? fopen(path, "r") : nullptr;
+  if (!f) return out;
+  std::string txt;
+  char buf[4096];
+  size_t r;
+  while ((r = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, r);
+  fclose(f);
+  size_t pos = 0;
+  while ((pos = txt.find('"', pos)) != std::string::npos) {
+    size_t end = txt.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    std::string key = txt.substr(pos + 1, end - pos - 1);
+    size_t colon = txt.find(':', end);
+    if (colon == std::string::npos) break;
+    out.push_back({key, atoi(txt.c_str() + colon + 1)});
+    pos = txt.find_first_of(",}", colon);
+    if (pos == std::string::npos) break;
+  }
+  return out;
+}
+
+static void tune_save(const char* path, const std::vector<std::pair<std::string, int>>& kv) {
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < kv.size(); ++i)
+    fprintf(f, "  \"%s\": %d%s\n", kv[i].first.c_str(), kv[i].second, i + 1 < kv.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+__global__ void k_fill_bytes(uint32_t* p, uint32_t v, int64_t n_words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static int autotune_mlp(hydro_session* s) {
+  MlpArgs& ma = s->mlp;
+  if (ma.n_preds == 0) return HYDRO_OK;
+  const char* path = getenv("HYDRO_TUNE_CACHE");
+  auto cache = tune_load(path);
+  const int64_t Q = std::min<int64_t>(s->cap, 4096);
+  const int D = ma.d_in[0];
+  const size_t fbytes = (size_t)D * (s->fdtype == HYDRO_DTYPE_F32 ? 4 : s->fdtype == HYDRO_DTYPE_BF16 ? 2 : 1);
+  void* frames = nullptr;
+  bool changed = false;
+  hipStream_t st = s->stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (int i = 0; i < ma.n_preds; ++i) {
+    const std::string key = tune_key(s->pol.precision, s->fdtype, ma.d_in[i], ma.hidden[i], Q);
+    int best = -1;
+    for (auto& kv : cache)
+      if (kv.first == key) best = kv.second;
+    if (best < 0 || best >= MLP_TILE_CONFIGS) {
+      if (!frames) {
+        hipError_t he = dev_alloc(&frames, fbytes * Q);
+        if (he != hipSuccess) return fail(HYDRO_ENOMEM, "autotune frame buffer");
+        // bf16 1.0 pairs / small fp32 / uint8 values: finite, representative magnitudes
+        hipLaunchKernelGGL(k_fill_bytes, dim3(1024), dim3(256), 0, st, (uint32_t*)frames, 0x3F003F00u,
+                           (int64_t)(fbytes * Q / 4));
+      }
+      const int k = ma.pred[i];
+      std::vector<uint32_t> ent(Q);
+      for (int64_t t = 0; t < Q; ++t) ent[t] = make_entry((uint32_t)t, 0u);
+      HIP_TRY(hipMemcpy(s->q1 + (int64_t)k * s->cap, ent.data(), Q * 4, hipMemcpyHostToDevice));
+      int cnt[kMaxK] = {0};
+      cnt[k] = (int)Q;
+      HIP_TRY(hipMemcpy(s->st->qcount, cnt, sizeof(cnt), hipMemcpyHostToDevice));
+      MlpArgs b = ma;
+      b.n_preds = 1;
+      b.pred[0] = ma.pred[i]; b.d_in[0] = ma.d_in[i]; b.hidden[0] = ma.hidden[i]; b.class_mask[0] = ma.class_mask[i];
+      b.w1_bf[0] = ma.w1_bf[i]; b.w1_f32[0] = ma.w1_f32[i]; b.b1_fold[0] = ma.b1_fold[i]; b.w2[0] = ma.w2[i];
+      b.b2[0] = ma.b2[i]; b.partial[0] = ma.partial[i];
+      b.q = Queues{s->q1, s->st->qcount, s->cap};
+      b.fr = FrameSrc{frames, s->fdtype, s->fh, (int64_t)D};
+      b.st = s->st;
+      b.part_cap = s->cap;
+      b.count_ticks = 0;
+      float best_ms = 1e30f;
+      for (int cfg = 0; cfg < MLP_TILE_CONFIGS; ++cfg) {
+        const bool bf = s->pol.precision == HYDRO_PREC_BF16;
+        launch_mlp_gemm(b, cfg, bf, s->n_cu * 4, st);
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int rep = 0; rep < 3; ++rep) launch_mlp_gemm(b, cfg, bf, s->n_cu * 4, st);
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cfg;
+        }
+      }
+      cache.push_back({key, best});
+      changed = true;
+    }
+    ma.tile_cfg[i] = best;
+    ma.part_w[i] = mlp_tile_bn(best) / 2;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (frames) hipFree(frames);
+  if (changed) tune_save(path, cache);
+  // leave the device state as a fresh query expects it
+  HIP_TRY(hipMemsetAsync(s->st, 0, sizeof(DevState), st));
+  if (s->rnn) {
+    const int one = 1;
+    HIP_TRY(hipMemcpyAsync(&s->st->learned_active, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return HYDRO_OK;
+}
+
 static int ensure_dtype(hydro_session* s, int dtype) {
   if (s->fdtype == dtype) return HYDRO_OK;
   if (s->fdtype != -1) return fail(HYDRO_EINVAL, "frame dtype differs from the session's first push");
@@ -986,6 +1122,7 @@ static int ensure_dtype(hydro_session* s, int dtype) {
   s->fdtype = dtype;
   HIP_TRY(hipStreamSynchronize(s->stream));
   int rc = pack_models(s);
+  if (!rc && s->pol.autotune) rc = autotune_mlp(s);
   if (rc) {
     s->fdtype = -1;
     return rc;

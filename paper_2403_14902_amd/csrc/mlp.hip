@@ -10,8 +10,6 @@
 
 namespace hydro {
 
-constexpr int MLP_BM = 128, MLP_BN = 128;
-
 template <typename T> struct MlpTile;
 template <> struct MlpTile<__bf16> { static constexpr int BK = 32, LD = 40; };   // LDS row stride (elements)
 template <> struct MlpTile<float> { static constexpr int BK = 16, LD = 20; };
@@ -55,79 +53,78 @@ __device__ inline void load_frame_run(const FrameSrc& fr, uint32_t idx, int64_t 
   }
 }
 
-// Decode a persistent-loop tile index into (predicate slot, m tile, n tile).
-__device__ inline bool mlp_decode_tile(const MlpArgs& a, int t, int& slot, int& mt, int& nt) {
-  int acc = 0;
-  for (int i = 0; i < a.n_preds; ++i) {
-    int k = a.pred[i];
-    int cnt = a.q.counts[k];
-    int n_mt = (cnt + MLP_BM - 1) / MLP_BM;
-    int n_nt = a.hidden[i] / MLP_BN;
-    int tiles = n_mt * n_nt;
-    if (t < acc + tiles) {
-      int local = t - acc;
-      slot = i;
-      mt = local / n_nt;
-      nt = local % n_nt;
-      return true;
-    }
-    acc += tiles;
-  }
-  return false;
-}
-
-template <typename T>
+// Tile shapes (rows of queued tuples x hidden units) an autotuner may pick per predicate.
+// Every launch covers the predicates of one tile shape.
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
   constexpr int BK = MlpTile<T>::BK, LD = MlpTile<T>::LD;
-  constexpr int PER = BK / 2;                     // elements each thread loads per row and k-tile
-  __shared__ __attribute__((aligned(16))) T As[2][MLP_BM * LD];
-  __shared__ __attribute__((aligned(16))) T Bs[2][MLP_BN * LD];
+  constexpr int PER = BK / 2;                     // elements a thread loads per row and k-tile
+  constexpr int WM = BM / 2, WN = BN / 2;         // 2 x 2 waves
+  constexpr int FM = WM / 16, FN = WN / 16;       // MFMA tiles per wave
+  __shared__ __attribute__((aligned(16))) T As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BN * LD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int lr = tid >> 1, lk = (tid & 1) * PER;  // this thread's load row and k offset
+  const int lr = tid >> 1, lk = (tid & 1) * PER;  // this thread's load row (< 128) and k offset
+  const bool lda = lr < BM, ldb = lr < BN;
 
-  // total tiles of this launch
   int total = 0;
   for (int i = 0; i < a.n_preds; ++i) {
-    int cnt = a.q.counts[a.pred[i]];
-    total += ((cnt + MLP_BM - 1) / MLP_BM) * (a.hidden[i] / MLP_BN);
+    const int cnt = a.q.counts[a.pred[i]];
+    total += ((cnt + BM - 1) / BM) * (a.hidden[i] / BN);
   }
 
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    int slot, mt, nt;
-    mlp_decode_tile(a, t, slot, mt, nt);
+    int slot = 0, mt = 0, nt = 0;
+    {
+      int acc0 = 0;
+      for (int i = 0; i < a.n_preds; ++i) {
+        const int cnt = a.q.counts[a.pred[i]];
+        const int n_nt = a.hidden[i] / BN;
+        const int tiles = ((cnt + BM - 1) / BM) * n_nt;
+        if (t < acc0 + tiles) {
+          slot = i;
+          mt = (t - acc0) / n_nt;
+          nt = (t - acc0) % n_nt;
+          break;
+        }
+        acc0 += tiles;
+      }
+    }
     const int k = a.pred[slot];
     const int cnt = a.q.counts[k];
     const int D = a.d_in[slot];
     const uint32_t* qe = a.q.entries + (int64_t)k * a.q.cap;
     unsigned long long t0 = wall_clock64();
 
-    int row = mt * MLP_BM + lr;
-    uint32_t idx = entry_idx(qe[row < cnt ? row : cnt - 1]);
+    const int row = mt * BM + lr;
+    const uint32_t idx = entry_idx(qe[row < cnt ? row : cnt - 1]);
     const T* wrow;
-    if constexpr (sizeof(T) == 2) wrow = reinterpret_cast<const T*>(a.w1_bf[slot]) + (int64_t)(nt * MLP_BN + lr) * D;
-    else wrow = reinterpret_cast<const T*>(a.w1_f32[slot]) + (int64_t)(nt * MLP_BN + lr) * D;
+    if constexpr (sizeof(T) == 2) wrow = reinterpret_cast<const T*>(a.w1_bf[slot]) + (int64_t)(nt * BN + (ldb ? lr : 0)) * D;
+    else wrow = reinterpret_cast<const T*>(a.w1_f32[slot]) + (int64_t)(nt * BN + (ldb ? lr : 0)) * D;
 
-    floatx4 acc[4][4];
+    floatx4 acc[FM][FN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
 
     alignas(16) T ra[PER];
     alignas(16) T rb[PER];
     auto gload = [&](int kt) {
-      load_frame_run<T, PER>(a.fr, idx, (int64_t)kt * BK + lk, ra);
-      const uint4* pb = reinterpret_cast<const uint4*>(wrow + (int64_t)kt * BK + lk);
+      if (lda) load_frame_run<T, PER>(a.fr, idx, (int64_t)kt * BK + lk, ra);
+      if (ldb) {
+        const uint4* pb = reinterpret_cast<const uint4*>(wrow + (int64_t)kt * BK + lk);
 #pragma unroll
-      for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb)[v] = pb[v];
+        for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb)[v] = pb[v];
+      }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
       for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) {
-        reinterpret_cast<uint4*>(&As[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(ra)[v];
-        reinterpret_cast<uint4*>(&Bs[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(rb)[v];
+        if (lda) reinterpret_cast<uint4*>(&As[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(ra)[v];
+        if (ldb) reinterpret_cast<uint4*>(&Bs[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(rb)[v];
       }
     };
 
@@ -139,30 +136,30 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
       const int buf = kt & 1;
       if (kt + 1 < nk) gload(kt + 1);
       if constexpr (sizeof(T) == 2) {
-        bf16x8 af[4], bfr[4];
+        bf16x8 af[FM], bfr[FN];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm * 64 + i * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
-          bfr[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn * 64 + i * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
-        }
+        for (int i = 0; i < FM; ++i)
+          af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm * WM + i * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < FN; ++j)
+          bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn * WN + j * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
       } else {
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
-          float af[4], bfr[4];
+          float af[FM], bfr[FN];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            af[i] = As[buf][(wm * 64 + i * 16 + (lane & 15)) * LD + ks * 4 + (lane >> 4)];
-            bfr[i] = Bs[buf][(wn * 64 + i * 16 + (lane & 15)) * LD + ks * 4 + (lane >> 4)];
-          }
+          for (int i = 0; i < FM; ++i) af[i] = As[buf][(wm * WM + i * 16 + (lane & 15)) * LD + ks * 4 + (lane >> 4)];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < FN; ++j) bfr[j] = Bs[buf][(wn * WN + j * 16 + (lane & 15)) * LD + ks * 4 + (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
       }
@@ -173,53 +170,37 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
       }
     }
 
-    // epilogue: H = ReLU(acc + b1'), partial logits over this wave's 64 hidden columns
+    // epilogue: H = ReLU(acc + b1'), partial logits over this wave's WN hidden columns
     const float* b1 = a.b1_fold[slot];
     const float* w2 = a.w2[slot];
-    const int col0 = nt * MLP_BN + wn * 64 + (lane & 15);
+    const int col0 = nt * BN + wn * WN + (lane & 15);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float bb = b1[col0 + j * 16];
+    for (int j = 0; j < FN; ++j) {
+      const float bb = b1[col0 + j * 16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][j][r] = fmaxf(acc[i][j][r] + bb, 0.f);
     }
     float* part = a.partial[slot] + ((int64_t)(nt * 2 + wn) * a.part_cap) * kClasses;
     for (int c = 0; c < kClasses; ++c) {
-      float w2v[4];
+      float w2v[FN];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) w2v[j] = w2[(col0 + j * 16) * kClasses + c];
-      float v[4][4];
+      for (int j = 0; j < FN; ++j) w2v[j] = w2[(col0 + j * 16) * kClasses + c];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float s = 0.f;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) s += acc[i][j][r] * w2v[j];
-          v[i][r] = s;
-        }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float s = v[i][r];
+          for (int j = 0; j < FN; ++j) s += acc[i][j][r] * w2v[j];
           s += __shfl_xor(s, 1);
           s += __shfl_xor(s, 2);
           s += __shfl_xor(s, 4);
           s += __shfl_xor(s, 8);
-          v[i][r] = s;
+          const int rr = mt * BM + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+          if ((lane & 15) == 0 && rr < cnt) part[(int64_t)rr * kClasses + c] = s;
         }
-      if ((lane & 15) == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            int rr = mt * MLP_BM + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-            if (rr < cnt) part[(int64_t)rr * kClasses + c] = v[i][r];
-          }
-      }
     }
     __syncthreads();
     if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
@@ -250,7 +231,7 @@ __global__ __launch_bounds__(256) void mlp_head_kernel(MlpArgs a, Forward f) {
       const float* b2 = a.b2[slot];
 #pragma unroll
       for (int c = 0; c < kClasses; ++c) z[c] = b2[c];
-      const int parts = a.hidden[slot] / 64;
+      const int parts = a.hidden[slot] / a.part_w[slot];
       const float* part = a.partial[slot];
       for (int p = 0; p < parts; ++p) {
         const float* pp = part + ((int64_t)p * a.part_cap + off) * kClasses;
@@ -511,6 +492,23 @@ __global__ __launch_bounds__(256) void mlp_f64_rest_kernel(MlpArgs a, Forward f)
 }
 
 // ---------------------------------------------------------------- launchers
+// Tile configurations: 0 = 128x128, 1 = 64x128, 2 = 128x64, 3 = 64x64 (rows x hidden units).
+int mlp_tile_bn(int cfg) { return cfg == 0 || cfg == 1 ? 128 : 64; }
+
+void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s) {
+  if (bf) {
+    if (cfg == 0) hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 128, 128>), dim3(grid), dim3(256), 0, s, b);
+    else if (cfg == 1) hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 64, 128>), dim3(grid), dim3(256), 0, s, b);
+    else if (cfg == 2) hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 128, 64>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 64, 64>), dim3(grid), dim3(256), 0, s, b);
+  } else {
+    if (cfg == 0) hipLaunchKernelGGL((mlp_gemm_kernel<float, 128, 128>), dim3(grid), dim3(256), 0, s, b);
+    else if (cfg == 1) hipLaunchKernelGGL((mlp_gemm_kernel<float, 64, 128>), dim3(grid), dim3(256), 0, s, b);
+    else if (cfg == 2) hipLaunchKernelGGL((mlp_gemm_kernel<float, 128, 64>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((mlp_gemm_kernel<float, 64, 64>), dim3(grid), dim3(256), 0, s, b);
+  }
+}
+
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
   if (a.n_preds == 0) return;
   if (tier == TIER_F64) {
@@ -519,10 +517,22 @@ void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hip
     hipLaunchKernelGGL(mlp_f64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f);
     return;
   }
-  if (a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)
-    hipLaunchKernelGGL(mlp_gemm_kernel<__bf16>, dim3(grid), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(mlp_gemm_kernel<float>, dim3(grid), dim3(256), 0, s, a);
+  // one GEMM launch per tile shape present among the predicates
+  const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;
+  for (int cfg = 0; cfg < MLP_TILE_CONFIGS; ++cfg) {
+    MlpArgs b = a;
+    b.n_preds = 0;
+    for (int i = 0; i < a.n_preds; ++i) {
+      if (a.tile_cfg[i] != cfg) continue;
+      const int j = b.n_preds++;
+      b.pred[j] = a.pred[i]; b.d_in[j] = a.d_in[i]; b.hidden[j] = a.hidden[i]; b.class_mask[j] = a.class_mask[i];
+      b.w1_bf[j] = a.w1_bf[i]; b.w1_f32[j] = a.w1_f32[i]; b.b1_fold[j] = a.b1_fold[i]; b.w2[j] = a.w2[i];
+      b.b2[j] = a.b2[i]; b.w1_canon[j] = a.w1_canon[i]; b.b1_canon[j] = a.b1_canon[i]; b.partial[j] = a.partial[i];
+      b.esc_h[j] = a.esc_h[i]; b.tile_cfg[j] = cfg; b.part_w[j] = a.part_w[i];
+    }
+    if (b.n_preds == 0) continue;
+    launch_mlp_gemm(b, cfg, bf, grid, s);
+  }
   hipLaunchKernelGGL(mlp_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
 }
 

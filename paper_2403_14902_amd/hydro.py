@@ -59,7 +59,7 @@ class Policy(C.Structure):
                 ("wave", C.c_int32), ("warmup_batches", C.c_int32), ("ewma_alpha", C.c_float),
                 ("cost_source", C.c_int32), ("precision", C.c_int32), ("tau", C.c_float), ("tau32", C.c_float),
                 ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
-                ("time_kernels", C.c_int32),
+                ("time_kernels", C.c_int32), ("autotune", C.c_int32),
                 ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p)]
 
 

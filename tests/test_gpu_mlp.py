@@ -156,3 +156,31 @@ def test_mlp_graph_replays(c1):
         _ = torch.ones(64, device="cuda").sum().item()
         assert np.array_equal(ids, c1.expect), f"replay {rep}"
     s.close()
+
+
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_mlp_every_tile_shape(c1, monkeypatch, tile, prec):
+    monkeypatch.setenv("HYDRO_MLP_TILE", tile)
+    pol = hydro.make_policy("score", precision=prec, tau=0.1, wave=512)
+    s = _session(c1, pol)
+    z = s.logits(0, 0, c1.device_frames(), c1.cfg.dtype)
+    assert np.abs(z - c1.Z[0]).max() <= (0.08 if prec == "bf16" else 2e-4)
+    s.push(c1.device_frames(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c1.expect)
+    s.close()
+
+
+def test_mlp_autotuned_session(c1, tmp_path, monkeypatch):
+    monkeypatch.setenv("HYDRO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    for _ in range(2):      # second session reads the cache
+        pol = hydro.make_policy("score", precision="bf16", tau=0.1, wave=512, autotune=1)
+        s = _session(c1, pol)
+        s.push(c1.device_frames(), c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+        ids, stats = s.finish()
+        assert np.array_equal(ids, c1.expect)
+        s.close()
+    import json
+    d = json.loads((tmp_path / "tune.json").read_text())
+    assert any(k.startswith("gfx950/bf16/f32/D3072/h256") for k in d)
