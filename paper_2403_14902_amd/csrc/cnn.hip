@@ -238,6 +238,8 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (8 waves cover 16 x NT2)
   constexpr int MT2 = M == 1 ? 2 : 4, NW2 = M == 1 ? 2 : (M == 2 ? 2 : 4);
   constexpr int NG2 = NT2 / NW2;                       // channel groups
+  // weight prefetch depth (k-steps); the widest bf16 class has no registers to spare in layer 2
+  constexpr int PD2 = sizeof(T) == 4 ? 4 : (M == 4 ? 2 : 3);
   const int mg2 = wave / NG2, ng2 = wave % NG2;
   static_assert((16 / MT2) * NG2 == 8, "layer-2 wave tiling must cover 8 waves");
   floatx4 acc2[MT2][NW2];
@@ -271,36 +273,42 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
                 fmaxf(acc[1] + bb1[1], 0.f), fmaxf(acc[2] + bb1[2], 0.f), fmaxf(acc[3] + bb1[3], 0.f));
     }
     __syncthreads();
-    // layer 2 partial: K = 9 taps x 16 channels of this slab
+    // layer 2 partial: K = 9 taps x 16 channels of this slab.  The weight fragments run PD2
+    // k-steps ahead of the MFMAs (they come from L2 cache; one k-step of MFMAs is far shorter
+    // than that latency).
     const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64 + ng2 * NW2 * 64 + lane;
-    frag bcur[NW2];
+    frag bw2[PD2][NW2];
 #pragma unroll
-    for (int n = 0; n < NW2; ++n) bcur[n] = w2p[n * 64];
-#pragma unroll 1
-    for (int ks = 0; ks < KS2; ++ks) {
-      frag bnext[NW2];
-      if (ks + 1 < KS2) {
-#pragma unroll
-        for (int n = 0; n < NW2; ++n) bnext[n] = w2p[((ks + 1) * NT2 + n) * 64];
-      }
-      const int k0 = ks * KSTEP + KPL * g;
-      int t = k0 / CB1;
-      const int c0 = k0 % CB1;
-      if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
-      const int u = t / 3, v = t % 3;
-      frag av[MT2];
-#pragma unroll
-      for (int q = 0; q < MT2; ++q) {
-        const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
-        av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
-      }
+    for (int d = 0; d < PD2; ++d)
 #pragma unroll
       for (int n = 0; n < NW2; ++n)
+        if (d < KS2) bw2[d][n] = w2p[(d * NT2 + n) * 64];
+#pragma unroll 1
+    for (int ks0 = 0; ks0 < KS2; ks0 += PD2) {
 #pragma unroll
-        for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bcur[n], av[q], acc2[q][n]);
-      if (ks + 1 < KS2) {
+      for (int d = 0; d < PD2; ++d) {
+        const int ks = ks0 + d;
+        if (ks < KS2) {
+          const int k0 = ks * KSTEP + KPL * g;
+          int t = k0 / CB1;
+          const int c0 = k0 % CB1;
+          if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
+          const int u = t / 3, v = t % 3;
+          frag av[MT2];
 #pragma unroll
-        for (int n = 0; n < NW2; ++n) bcur[n] = bnext[n];
+          for (int q = 0; q < MT2; ++q) {
+            const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
+            av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
+          }
+#pragma unroll
+          for (int n = 0; n < NW2; ++n)
+#pragma unroll
+            for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bw2[d][n], av[q], acc2[q][n]);
+          if (ks + PD2 < KS2) {
+#pragma unroll
+            for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[((ks + PD2) * NT2 + n) * 64];
+          }
+        }
       }
     }
     __syncthreads();
@@ -331,6 +339,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
   constexpr int MT3 = M == 1 ? 2 : 4, NW3 = 2 * M / MT3;
   constexpr int MG3 = 4 / MT3;                         // position groups (1 or 2)
+  constexpr int PD3 = sizeof(T) == 4 ? 4 : 3;
   static_assert(MG3 * (NT3 / NW3) == 8, "layer-3 wave tiling must cover 8 waves");
   const int mh = wave % MG3, ng = wave / MG3;
   floatx4 acc3[MT3][NW3];
@@ -339,32 +348,34 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
     for (int j = 0; j < NW3; ++j) acc3[q][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
   const frag* w3p = reinterpret_cast<const frag*>(wpk[2]) + (size_t)(ng * NW3) * 64 + lane;
-  frag b3cur[NW3];
+  static_assert(KS3 % PD3 == 0, "layer-3 k-steps must be a multiple of the prefetch depth");
+  frag bw3[PD3][NW3];
 #pragma unroll
-  for (int n = 0; n < NW3; ++n) b3cur[n] = w3p[n * 64];
+  for (int d = 0; d < PD3; ++d)
+#pragma unroll
+    for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(d * NT3 + n) * 64];
 #pragma unroll 1
-  for (int ks = 0; ks < KS3; ++ks) {
-    frag b3next[NW3];
-    if (ks + 1 < KS3) {
+  for (int ks0 = 0; ks0 < KS3; ks0 += PD3) {
 #pragma unroll
-      for (int n = 0; n < NW3; ++n) b3next[n] = w3p[((ks + 1) * NT3 + n) * 64];
-    }
-    const int k0 = ks * KSTEP + KPL * g;
-    const int t = k0 / C2, c0 = k0 % C2;
-    const int u = t / 3, v = t % 3;
-    frag av[MT3];
+    for (int d = 0; d < PD3; ++d) {
+      const int ks = ks0 + d;
+      const int k0 = ks * KSTEP + KPL * g;
+      const int t = k0 / C2, c0 = k0 % C2;
+      const int u = t / 3, v = t % 3;
+      frag av[MT3];
 #pragma unroll
-    for (int q = 0; q < MT3; ++q) {
-      const int px = (mh * MT3 + q) * 16 + l16, i = px >> 3, j = px & 7;
-      av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
-    }
+      for (int q = 0; q < MT3; ++q) {
+        const int px = (mh * MT3 + q) * 16 + l16, i = px >> 3, j = px & 7;
+        av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
+      }
 #pragma unroll
-    for (int n = 0; n < NW3; ++n)
+      for (int n = 0; n < NW3; ++n)
 #pragma unroll
-      for (int q = 0; q < MT3; ++q) acc3[q][n] = mfma(b3cur[n], av[q], acc3[q][n]);
-    if (ks + 1 < KS3) {
+        for (int q = 0; q < MT3; ++q) acc3[q][n] = mfma(bw3[d][n], av[q], acc3[q][n]);
+      if (ks + PD3 < KS3) {
 #pragma unroll
-      for (int n = 0; n < NW3; ++n) b3cur[n] = b3next[n];
+        for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[((ks + PD3) * NT3 + n) * 64];
+      }
     }
   }
   // ReLU + pooled partial sums over this wave's positions
@@ -421,7 +432,11 @@ __device__ inline void decode_entry(const CnnArgs& a, int t, int& slot, int& off
   }
 }
 
-template <typename T, int M>
+// Persistent over every queue of the launch: entry t of the concatenated queues goes to workgroup
+// t mod grid; slots are ordered by cost, so the widest frames come first.  VSET is the set of width
+// classes the instantiation holds code for (bit m for width multiplier m); one register
+// allocation covers them all, so classes whose union would spill get launches of their own.
+template <typename T, int VSET>
 __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
   __shared__ __attribute__((aligned(16))) unsigned char region[CnnLds<T>::REGION];
   __shared__ CnnShared sh;
@@ -430,15 +445,21 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
   if (tid < kMaxK) sh.ticks[tid] = 0;
   int total = 0;
   for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
+  // thread 0 fetches the threshold of the frame after the current one while that frame's loads are
+  // in flight, so the decision never waits on a global load
+  float th_next = 0.f;
   if ((int)blockIdx.x < total) {
     int slot, off;
     decode_entry(a, blockIdx.x, slot, off);
+    const uint32_t idx0 = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + off]);
     FramePrefetch pf;
-    frame_issue(a, entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + off]), pf);
+    frame_issue(a, idx0, pf);
+    if (tid == 0 && f.logits == nullptr) th_next = theta_of(f, a.pred[slot], idx0);
     frame_store<T>(a, pf, region);
   }
   __syncthreads();
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const float th = th_next;
     int slot, off;
     decode_entry(a, t, slot, off);
     const int k = a.pred[slot];
@@ -451,16 +472,25 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
       int s2, o2;
       decode_entry(a, tn, s2, o2);
       next_idx = entry_idx(a.q.entries[(int64_t)a.pred[s2] * a.q.cap + o2]);
+      if (tid == 0 && f.logits == nullptr) th_next = theta_of(f, a.pred[s2], next_idx);
     }
     unsigned long long t0 = wall_clock64();
     float z[kClasses];
-    cnn_frame<T, M>(a, slot, region, sh, next_valid, next_idx, z);
+    const int v = a.variant[slot];
+    if constexpr ((VSET & 4) != 0) {
+      if (v == CNN_W4) cnn_frame<T, 4>(a, slot, region, sh, next_valid, next_idx, z);
+    }
+    if constexpr ((VSET & 2) != 0) {
+      if (v == CNN_W2) cnn_frame<T, 2>(a, slot, region, sh, next_valid, next_idx, z);
+    }
+    if constexpr ((VSET & 1) != 0) {
+      if (v == CNN_W1) cnn_frame<T, 1>(a, slot, region, sh, next_valid, next_idx, z);
+    }
     if (tid == 0) {
       if (f.logits != nullptr) {
         for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)z[c];
       } else {
         float d = class_margin(z, a.class_mask[slot]);
-        float th = theta_of(f, k, idx);
         bool defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau[k];
         int n = sh.d_n;
         sh.d_e[n] = e;
@@ -760,9 +790,13 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
     hipLaunchKernelGGL(cnn_f64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f);
     return;
   }
-  // one launch per width class (each instantiation gets its own register allocation); every
-  // launch is persistent over all queues of its class
-  const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;
+  // FP32: one persistent launch over every queue of the pass.  BF16: one launch per width class
+  // (a shared launch would give the narrow classes the widest one's register allocation and code
+  // footprint, measured slower).
+  if (!(a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)) {
+    hipLaunchKernelGGL((cnn_fused_kernel<float, 7>), dim3(grid), dim3(NTHR), 0, s, a, f);
+    return;
+  }
   for (int v = CNN_W4; v >= CNN_W1; --v) {
     CnnArgs b = a;
     b.n_preds = 0;
@@ -777,15 +811,9 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
       b.fc_w[j] = a.fc_w[i]; b.fc_b[j] = a.fc_b[i]; b.esc_act[j] = a.esc_act[i];
     }
     if (b.n_preds == 0) continue;
-    if (bf) {
-      if (v == CNN_W1) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 1>), dim3(grid), dim3(NTHR), 0, s, b, f);
-      else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 2>), dim3(grid), dim3(NTHR), 0, s, b, f);
-      else hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 4>), dim3(grid), dim3(NTHR), 0, s, b, f);
-    } else {
-      if (v == CNN_W1) hipLaunchKernelGGL((cnn_fused_kernel<float, 1>), dim3(grid), dim3(NTHR), 0, s, b, f);
-      else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<float, 2>), dim3(grid), dim3(NTHR), 0, s, b, f);
-      else hipLaunchKernelGGL((cnn_fused_kernel<float, 4>), dim3(grid), dim3(NTHR), 0, s, b, f);
-    }
+    if (v == CNN_W4) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 4>), dim3(grid), dim3(NTHR), 0, s, b, f);
+    else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 2>), dim3(grid), dim3(NTHR), 0, s, b, f);
+    else hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 1>), dim3(grid), dim3(NTHR), 0, s, b, f);
   }
 }
 

@@ -27,7 +27,7 @@ constexpr int RH = 64;            // hidden units
 constexpr int RK = 8;             // output slots (K <= 8)
 constexpr int RING = 1 << 16;     // outcome log entries
 constexpr int TB = 64;            // training minibatch
-constexpr int TSTEPS = 2;         // optimiser steps per round
+constexpr int TSTEPS = 2;         // optimiser steps per round (successive windows of the log)
 constexpr int MIN_STEPS = 8;      // steps before the learned arm uses the router
 constexpr int NPARAM = RF * RH + RH + RH * RK + RK;
 
@@ -47,6 +47,7 @@ struct RouterNN {
   std::vector<float> init;
 };
 
+// Any frame side divisible by 8: one thread per output feature (scalar loads).
 __global__ void rnn_pool_kernel(FrameSrc fr, int64_t n, __bf16* feats) {
   const int64_t total = n * RF;
   const int blk = fr.hw / 8;
@@ -68,6 +69,99 @@ __global__ void rnn_pool_kernel(FrameSrc fr, int64_t n, __bf16* feats) {
       }
     feats[q] = static_cast<__bf16>((s * inv - 0.5f) * 4.0f);
   }
+}
+
+template <typename T, int CH>
+__device__ inline void load_chunk(const T* p, float (&v)[CH]) {
+  if constexpr (sizeof(T) == 2) {
+    static_assert(CH % 8 == 0 || CH == 4, "chunk");
+    if constexpr (CH == 4) {
+      const uint2 u = *reinterpret_cast<const uint2*>(p);
+      const __bf16* h = reinterpret_cast<const __bf16*>(&u);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (float)h[e];
+    } else {
+      const uint4 u = *reinterpret_cast<const uint4*>(p);
+      const __bf16* h = reinterpret_cast<const __bf16*>(&u);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (float)h[e];
+    }
+  } else if constexpr (sizeof(T) == 1) {
+    if constexpr (CH == 4) {
+      const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (float)((u >> (8 * e)) & 0xffu);
+    } else {
+      const uint2 u = *reinterpret_cast<const uint2*>(p);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (float)((u.x >> (8 * e)) & 0xffu);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 + e] = (float)((u.y >> (8 * e)) & 0xffu);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < CH / 4; ++q) {
+      const float4 u = *reinterpret_cast<const float4*>(p + 4 * q);
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
+    }
+  }
+}
+
+// One thread per (frame, 8x8 cell): the cell's rows are read as NCH vector chunks of CH elements
+// (a cell row holds 3*hw/8 = NCH*CH values); per-position sums over the rows are folded into the
+// three channel means at the end.  64 consecutive threads cover one frame, so each wave's loads
+// walk whole frame rows.
+template <typename T, int CH, int NCH>
+__global__ __launch_bounds__(256) void rnn_pool_vec_kernel(FrameSrc fr, int64_t n, __bf16* feats) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = gid >> 6;
+  if (t >= n) return;
+  const int cell = (int)(gid & 63), by = cell >> 3, bx = cell & 7;
+  const int blk = fr.hw / 8;
+  const int row_elems = fr.hw * 3;
+  const T* p = static_cast<const T*>(fr.base) + t * fr.elems + (int64_t)(by * blk) * row_elems + bx * (NCH * CH);
+  float acc[NCH][CH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int e = 0; e < CH; ++e) acc[c][e] = 0.f;
+#pragma unroll 4
+  for (int y = 0; y < blk; ++y) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      float v[CH];
+      load_chunk<T, CH>(p + (int64_t)y * row_elems + c * CH, v);
+#pragma unroll
+      for (int e = 0; e < CH; ++e) acc[c][e] += v[e];
+    }
+  }
+  float ch[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int e = 0; e < CH; ++e) ch[(c * CH + e) % 3] += acc[c][e];
+  const float scale = (sizeof(T) == 1 ? 1.0f / 255.0f : 1.0f) / (float)(blk * blk);
+  __bf16* o = feats + t * RF + by * 24 + bx * 3;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) o[c] = static_cast<__bf16>((ch[c] * scale - 0.5f) * 4.0f);
+}
+
+template <typename T>
+static bool launch_pool_vec(const FrameSrc& fr, int64_t n, __bf16* feats, hipStream_t s) {
+  const int64_t blocks = (n * 64 + 255) / 256;
+  if (fr.hw == 32) {
+    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 4, 3>), dim3((unsigned)blocks), dim3(256), 0, s, fr, n, feats);
+  } else if (fr.hw == 64) {
+    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 8, 3>), dim3((unsigned)blocks), dim3(256), 0, s, fr, n, feats);
+  } else if (fr.hw == 128) {
+    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 8, 6>), dim3((unsigned)blocks), dim3(256), 0, s, fr, n, feats);
+  } else {
+    return false;
+  }
+  return true;
 }
 
 struct KeyArgs {
@@ -138,116 +232,288 @@ __global__ __launch_bounds__(256) void rnn_keys_kernel(KeyArgs a) {
   }
 }
 
-// Adam on the router parameters from the newest logged outcomes.  One workgroup.
-__global__ __launch_bounds__(256) void rnn_train_kernel(DevState* st, const uint32_t* ring, const __bf16* feats,
-                                                        float* params, float* am, float* av, __bf16* w1_frag, int k,
-                                                        float lr, int n_seen_min) {
-  __shared__ float W1s[RF * RH];        // 48 KB
-  __shared__ float F[TB][RF];           // 48 KB
-  __shared__ float Hr[TB][RH];          // ReLU(h)
-  __shared__ float dH[TB][RH];
-  __shared__ float dO[TB];
-  __shared__ int kk[TB];
-  __shared__ float part[TB][4];
-  const int tid = threadIdx.x;
+// Online training, one workgroup of four waves: TSTEPS Adam steps per round on successive windows
+// of TB logged outcomes (newest first), masked binary cross-entropy on the evaluated predicate.
+// Both contractions run on fp32 MFMA (16x16x4): the forward pass H = F W1 (64 x 192 x 64; wave w
+// owns samples 16w..16w+15) and the W1 gradient F^T dH (192 x 64 x 64; wave w owns feature rows
+// 48w..48w+47).  Every global read the launch needs (parameters, Adam moments, the windows'
+// features, the judge's counters) is issued up front; parameters live in LDS across the steps and
+// each thread keeps the Adam moments of the parameters it updates in registers, writing
+// everything back once at the end.
+constexpr int FSB = RF + 2;  // LDS row stride (bf16) of the sample features
+constexpr int HS = RH + 4;   // LDS row stride of H and dH
+constexpr int NREST = RH + RH * RK + RK;   // b1, W2, b2
+constexpr int REST_PER = (NREST + 255) / 256;
+
+__global__ __launch_bounds__(256) void rnn_train_kernel(DevState* st, const uint32_t* __restrict__ ring,
+                                                        const __bf16* __restrict__ feats, float* __restrict__ params,
+                                                        float* __restrict__ am, float* __restrict__ av,
+                                                        __bf16* __restrict__ w1_frag, float lr) {
+  __shared__ __attribute__((aligned(16))) float W1s[RF * RH];     // 48 KB, [i][j]
+  __shared__ __attribute__((aligned(16))) __bf16 Fb[TSTEPS * TB * FSB];   // both windows, [b][i]
+  __shared__ float Hr[TB * HS];    // ReLU(h), [b][j]
+  __shared__ float dHs[TB * HS];   // dL/dh, [b][j]
+  __shared__ float rest[NREST];    // b1 | W2 | b2
+  __shared__ float part[4 * NREST];  // per-wave partial gradients of b1 | W2 | b2
+  __shared__ float dO[TB], yv[TSTEPS * TB];
+  __shared__ int kk[TSTEPS * TB];
+  __shared__ int s_go;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const unsigned long long head = st->ring_head;
-  float* b1 = params + RF * RH;
-  float* W2 = b1 + RH;
-  float* b2 = W2 + RH * RK;
-  int steps = 0;
-  for (int s = 0; s < TSTEPS; ++s) {
-    // step s trains on the TB outcomes logged just before position hi
-    const long long hi = (long long)head - (long long)s * TB;
-    if (hi < (long long)n_seen_min || hi - TB < 0) break;
-    // stage weights and samples
-    for (int q = tid; q < RF * RH; q += 256) W1s[q] = params[q];
-    for (int q = tid; q < TB * RF; q += 256) {
-      const int si = q / RF, fi = q % RF;
-      const uint32_t e = ring[(uint64_t)(hi - TB + si) & (RING - 1)];
-      F[si][fi] = (float)feats[(int64_t)(e & kIdxMask) * RF + fi];
-    }
-    if (tid < TB) {
-      const uint32_t e = ring[(uint64_t)(hi - TB + tid) & (RING - 1)];
-      kk[tid] = (e >> 24) & 7;
-    }
-    __syncthreads();
-    // forward: 4 threads per sample, 16 hidden units each
-    const int si = tid >> 2, hq = (tid & 3) * 16;
-    float hv[16];
-    const int ks = kk[si];
-    float po = 0.f;
+  const int steps0 = st->train_steps;
+  if (!st->learned_active || (long long)head < (long long)TB) return;  // uniform across the workgroup
+  const int n_steps = (long long)head >= (long long)TSTEPS * TB ? TSTEPS : (int)(head / TB);
+
+  // ---- all global reads up front
+  {
+    const float4* p4 = reinterpret_cast<const float4*>(params);
+    float4 wv[RF * RH / 4 / 256];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      float h = b1[hq + j];
-      for (int i = 0; i < RF; ++i) h += W1s[i * RH + hq + j] * F[si][i];
-      hv[j] = h;
-      const float r = fmaxf(h, 0.f);
-      Hr[si][hq + j] = r;
-      po += r * W2[(hq + j) * RK + ks];
-    }
-    part[si][tid & 3] = po;
-    __syncthreads();
-    if (tid < TB) {
-      const float o = part[tid][0] + part[tid][1] + part[tid][2] + part[tid][3] + b2[kk[tid]];
-      const uint32_t e = ring[(uint64_t)(hi - TB + tid) & (RING - 1)];
-      const float y = (e >> 31) ? 1.f : 0.f;
-      dO[tid] = (1.0f / (1.0f + __expf(-o)) - y) * (1.0f / TB);
-    }
-    __syncthreads();
+    for (int r = 0; r < RF * RH / 4 / 256; ++r) wv[r] = p4[tid + 256 * r];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) dH[si][hq + j] = hv[j] > 0.f ? dO[si] * W2[(hq + j) * RK + ks] : 0.f;
-    __syncthreads();
-    // gradients and Adam (bias-corrected), parameter by parameter
-    const int t_adam = st->train_steps + steps + 1;
-    const float c1 = 1.f / (1.f - powf(0.9f, (float)t_adam)), c2 = 1.f / (1.f - powf(0.999f, (float)t_adam));
-    for (int q = tid; q < NPARAM; q += 256) {
-      float gsum = 0.f;
-      if (q < RF * RH) {
-        const int i = q / RH, j = q % RH;
-        for (int b = 0; b < TB; ++b) gsum += F[b][i] * dH[b][j];
-      } else if (q < RF * RH + RH) {
-        const int j = q - RF * RH;
-        for (int b = 0; b < TB; ++b) gsum += dH[b][j];
-      } else if (q < RF * RH + RH + RH * RK) {
-        const int r = q - RF * RH - RH, j = r / RK, kc = r % RK;
-        for (int b = 0; b < TB; ++b) gsum += kk[b] == kc ? Hr[b][j] * dO[b] : 0.f;
-      } else {
-        const int kc = q - RF * RH - RH - RH * RK;
-        for (int b = 0; b < TB; ++b) gsum += kk[b] == kc ? dO[b] : 0.f;
-      }
-      const float m = 0.9f * am[q] + 0.1f * gsum;
-      const float v = 0.999f * av[q] + 0.001f * gsum * gsum;
-      am[q] = m;
-      av[q] = v;
-      params[q] -= lr * (m * c1) / (sqrtf(v * c2) + 1e-8f);
-    }
-    __syncthreads();
-    ++steps;
+    for (int r = 0; r < RF * RH / 4 / 256; ++r) reinterpret_cast<float4*>(W1s)[tid + 256 * r] = wv[r];
   }
-  // bf16 fragments of W1^T for inference: lane l holds rows (hidden) nt*16 + l%16, k = ks*32 + 8(l/16) + e
-  if (steps > 0) {
-    for (int q = tid; q < (RF / 32) * 4 * 64 * 8; q += 256) {
-      const int e = q & 7, lane = (q >> 3) & 63, nt = (q >> 9) & 3, ksi = q >> 11;
-      const int hu = nt * 16 + (lane & 15), fi = ksi * 32 + 8 * (lane >> 4) + e;
-      w1_frag[q] = static_cast<__bf16>(params[fi * RH + hu]);
+  for (int q = tid; q < NREST; q += 256) rest[q] = params[RF * RH + q];
+  float m1[3][4][4], v1[3][4][4];
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = (48 * w + 16 * mt + 4 * g + r) * RH + 16 * nt + l16;
+        m1[mt][nt][r] = am[q];
+        v1[mt][nt][r] = av[q];
+      }
+  float mr[REST_PER], vr[REST_PER];
+#pragma unroll
+  for (int c = 0; c < REST_PER; ++c) {
+    const int q = tid + 256 * c;
+    mr[c] = q < NREST ? am[RF * RH + q] : 0.f;
+    vr[c] = q < NREST ? av[RF * RH + q] : 0.f;
+  }
+  // window `back` covers ring positions [head - (back+1) TB, head - back TB); sample sb = back TB + b
+  if (tid < n_steps * TB) {
+    const int back = tid / TB, b = tid % TB;
+    const uint32_t e = ring[(uint64_t)((long long)head - (long long)(back + 1) * TB + b) & (RING - 1)];
+    kk[tid] = (e >> 24) & 7;
+    yv[tid] = (e >> 31) ? 1.f : 0.f;
+  }
+  {
+    constexpr int CH = TSTEPS * TB * (RF / 8);    // 16-byte chunks of features
+    uint4 fv[(CH + 255) / 256];
+    int dsto[(CH + 255) / 256];
+#pragma unroll
+    for (int r = 0; r < (CH + 255) / 256; ++r) {
+      const int q = tid + 256 * r;
+      dsto[r] = -1;
+      if (q < CH) {
+        const int sb = q / (RF / 8), f8 = q % (RF / 8), back = sb / TB, b = sb % TB;
+        if (back < n_steps) {
+          const uint32_t e = ring[(uint64_t)((long long)head - (long long)(back + 1) * TB + b) & (RING - 1)];
+          fv[r] = *reinterpret_cast<const uint4*>(feats + (int64_t)(e & kIdxMask) * RF + f8 * 8);
+          dsto[r] = sb * FSB + f8 * 8;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < (CH + 255) / 256; ++r)
+      if (dsto[r] >= 0) {
+        // FSB is even, so each chunk lands 4-byte aligned
+        uint32_t* d = reinterpret_cast<uint32_t*>(&Fb[dsto[r]]);
+        d[0] = fv[r].x; d[1] = fv[r].y; d[2] = fv[r].z; d[3] = fv[r].w;
+      }
+  }
+  // judge state (thread 0)
+  int active = 1;
+  double arm_c0 = 0.0, arm_c1 = 0.0, arm_t0 = 0.0, arm_t1 = 0.0;
+  if (tid == 0) {
+    arm_c0 = st->arm_cost[0]; arm_c1 = st->arm_cost[1];
+    arm_t0 = st->arm_tuples[0]; arm_t1 = st->arm_tuples[1];
+  }
+  bool reset_arms = false;
+  int steps = steps0;
+
+  for (int back = 0; back < n_steps; ++back) {
+    __syncthreads();  // staging done / previous step's LDS updates settled
+    if (tid == 0) s_go = active;
+    __syncthreads();
+    if (!s_go) break;
+    const __bf16* F = Fb + back * TB * FSB;
+    const float* b1s = rest;
+    const float* W2s = rest + RH;
+    const float* b2s = rest + RH + RH * RK;
+
+    // forward on MFMA: lane holds h[s = 16w + 4g + r][j = 16nt + l16]
+    floatx4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int ks = 0; ks < RF / 4; ++ks) {
+      const float a_ = (float)F[(16 * w + l16) * FSB + 4 * ks + g];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_, W1s[(4 * ks + g) * RH + 16 * nt + l16], acc[nt], 0, 0, 0);
+    }
+    float po[4] = {0.f, 0.f, 0.f, 0.f};
+    int ksl[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ksl[r] = kk[back * TB + 16 * w + 4 * g + r];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int j = 16 * nt + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[nt][r] += b1s[j];
+        const float h = fmaxf(acc[nt][r], 0.f);
+        Hr[(16 * w + 4 * g + r) * HS + j] = h;
+        po[r] += h * W2s[j * RK + ksl[r]];
+      }
+    }
+    // logit of the evaluated slot: reduce over the 16 lanes of the group
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      po[r] += __shfl_xor(po[r], 1);
+      po[r] += __shfl_xor(po[r], 2);
+      po[r] += __shfl_xor(po[r], 4);
+      po[r] += __shfl_xor(po[r], 8);
+    }
+    float d[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int sidx = 16 * w + 4 * g + r;
+      const float o = po[r] + b2s[ksl[r]];
+      d[r] = (1.0f / (1.0f + __expf(-o)) - yv[back * TB + sidx]) * (1.0f / TB);
+      if (l16 == 0) dO[sidx] = d[r];
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int j = 16 * nt + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dHs[(16 * w + 4 * g + r) * HS + j] = acc[nt][r] > 0.f ? d[r] * W2s[j * RK + ksl[r]] : 0.f;
+    }
+    __syncthreads();
+
+    const int t_adam = steps + 1;
+    const float c1 = 1.f / (1.f - powf(0.9f, (float)t_adam)), c2 = 1.f / (1.f - powf(0.999f, (float)t_adam));
+    // W1 gradient on MFMA: lane holds g[i = 48w + 16mt + 4g + r][j = 16nt + l16]
+    floatx4 gacc[3][4];
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) gacc[mt][nt] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int ks = 0; ks < TB / 4; ++ks) {
+      const int b = 4 * ks + g;
+      float a3[3], b4[4];
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt) a3[mt] = (float)F[b * FSB + 48 * w + 16 * mt + l16];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) b4[nt] = dHs[b * HS + 16 * nt + l16];
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+          gacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[mt], b4[nt], gacc[mt][nt], 0, 0, 0);
+    }
+    // b1, W2, b2 gradients: wave w sums its own 16 samples (lane j = hidden unit) into part[w],
+    // the owners add the four partials below
+    {
+      float gb1 = 0.f, gb2 = 0.f, gw2[RK];
+#pragma unroll
+      for (int kc = 0; kc < RK; ++kc) gw2[kc] = 0.f;
+#pragma unroll 4
+      for (int bi = 0; bi < 16; ++bi) {
+        const int b = 16 * w + bi;
+        const int kb = kk[back * TB + b];
+        const float o = dO[b];
+        const float ho = Hr[b * HS + lane] * o;
+        gb1 += dHs[b * HS + lane];
+#pragma unroll
+        for (int kc = 0; kc < RK; ++kc) gw2[kc] += kb == kc ? ho : 0.f;
+        gb2 += kb == lane ? o : 0.f;
+      }
+      float* pw = part + w * NREST;
+      pw[lane] = gb1;
+#pragma unroll
+      for (int kc = 0; kc < RK; ++kc) pw[RH + lane * RK + kc] = gw2[kc];
+      if (lane < RK) pw[RH + RH * RK + lane] = gb2;
+    }
+    // Adam on the owned entries (moments in registers, parameters in LDS)
+#pragma unroll
+    for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = (48 * w + 16 * mt + 4 * g + r) * RH + 16 * nt + l16;
+          const float gq = gacc[mt][nt][r];
+          const float m = 0.9f * m1[mt][nt][r] + 0.1f * gq;
+          const float v = 0.999f * v1[mt][nt][r] + 0.001f * gq * gq;
+          m1[mt][nt][r] = m;
+          v1[mt][nt][r] = v;
+          W1s[q] -= lr * (m * c1) / (sqrtf(v * c2) + 1e-8f);
+        }
+    __syncthreads();  // partials complete
+#pragma unroll
+    for (int c = 0; c < REST_PER; ++c) {
+      const int q = tid + 256 * c;
+      if (q < NREST) {
+        const float gq = part[q] + part[NREST + q] + part[2 * NREST + q] + part[3 * NREST + q];
+        const float m = 0.9f * mr[c] + 0.1f * gq;
+        const float v = 0.999f * vr[c] + 0.001f * gq * gq;
+        mr[c] = m;
+        vr[c] = v;
+        rest[q] -= lr * (m * c1) / (sqrtf(v * c2) + 1e-8f);
+      }
+    }
+    steps += 1;
+    if (tid == 0) {
+      if (steps == MIN_STEPS) {
+        // the learned arm starts routing now: judge only what follows
+        reset_arms = true;
+        arm_c0 = arm_c1 = arm_t0 = arm_t1 = 0.0;
+      }
+      // judge: learned arm's UDF FLOPs per finished tuple against the control arm's
+      if (steps >= MIN_STEPS && arm_t0 >= 2048.0 && arm_t1 >= 2048.0 && arm_c1 / arm_t1 > 1.02 * (arm_c0 / arm_t0))
+        active = 0;
+    }
+  }
+  __syncthreads();
+  // ---- write back: parameters, inference fragments, moments, counters
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 48 * w + 16 * mt + 4 * g + r, j = 16 * nt + l16, q = i * RH + j;
+        const float np = W1s[q];
+        am[q] = m1[mt][nt][r];
+        av[q] = v1[mt][nt][r];
+        params[q] = np;
+        // lane l of fragment (ks, nt) holds hidden unit nt*16 + l%16, features ks*32 + 8(l/16) + e
+        const int ksi = i / 32, gg = (i % 32) / 8, e = i % 8, ntf = j / 16, ln = gg * 16 + j % 16;
+        w1_frag[(((ksi * 4 + ntf) * 64) + ln) * 8 + e] = static_cast<__bf16>(np);
+      }
+#pragma unroll
+  for (int c = 0; c < REST_PER; ++c) {
+    const int q = tid + 256 * c;
+    if (q < NREST) {
+      am[RF * RH + q] = mr[c];
+      av[RF * RH + q] = vr[c];
+      params[RF * RH + q] = rest[q];
     }
   }
   if (tid == 0) {
-    const int before = st->train_steps;
-    st->train_steps = before + steps;
+    st->train_steps = steps;
     st->ring_trained = head;
-    if (before < MIN_STEPS && before + steps >= MIN_STEPS) {
-      // the learned arm starts routing now: judge only what follows
+    if (reset_arms) {
       st->arm_cost[0] = st->arm_cost[1] = 0.0;
       st->arm_tuples[0] = st->arm_tuples[1] = 0.0;
     }
-    // judge: learned arm's UDF FLOPs per finished tuple against the control arm's
-    if (st->learned_active && st->train_steps >= MIN_STEPS && st->arm_tuples[0] >= 2048.0 &&
-        st->arm_tuples[1] >= 2048.0) {
-      const double cl = st->arm_cost[1] / st->arm_tuples[1];
-      const double cc = st->arm_cost[0] / st->arm_tuples[0];
-      if (cl > 1.02 * cc) st->learned_active = 0;
-    }
+    if (!active) st->learned_active = 0;
   }
 }
 
@@ -311,9 +577,17 @@ void router_nn_reset(RouterNN* r, hipStream_t s) {
 int router_nn_admit(RouterNN* r, const FrameSrc& fr, int64_t n, hipStream_t s) {
   if (n <= 0) return HYDRO_OK;
   if (fr.hw != r->fh) return HYDRO_EUNSUPPORTED;
-  const int64_t work = n * RF;
-  const int grid = (int)std::min<int64_t>(4096, (work + 255) / 256);
-  hipLaunchKernelGGL(rnn_pool_kernel, dim3(grid), dim3(256), 0, s, fr, n, r->feats);
+  // vector path: frame sides 32, 64 and 128 (the cell row is a whole number of aligned chunks)
+  bool done = false;
+  if (reinterpret_cast<uintptr_t>(fr.base) % 16 != 0) {
+  } else if (fr.dtype == HYDRO_DTYPE_BF16) done = launch_pool_vec<__bf16>(fr, n, r->feats, s);
+  else if (fr.dtype == HYDRO_DTYPE_U8) done = launch_pool_vec<uint8_t>(fr, n, r->feats, s);
+  else done = launch_pool_vec<float>(fr, n, r->feats, s);
+  if (!done) {
+    const int64_t work = n * RF;
+    const int grid = (int)std::min<int64_t>(4096, (work + 255) / 256);
+    hipLaunchKernelGGL(rnn_pool_kernel, dim3(grid), dim3(256), 0, s, fr, n, r->feats);
+  }
   return HYDRO_OK;
 }
 
@@ -325,7 +599,7 @@ void router_nn_keys(RouterNN* r, DevState* st, const uint32_t* pend_in, int in_s
 
 void router_nn_learn(RouterNN* r, DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(rnn_train_kernel, dim3(1), dim3(256), 0, s, st, r->ring, r->feats, r->params, r->adam_m,
-                     r->adam_v, r->w1_frag, r->k, 3e-3f, TB);
+                     r->adam_v, r->w1_frag, 3e-3f);
 }
 
 const float* router_nn_keys_ptr(RouterNN* r) { return r->keys; }
