@@ -83,7 +83,14 @@ __host__ __device__ constexpr int cnn_ksteps(int layer, int m) {
 __host__ __device__ constexpr int cnn_slabs(int layer, int m) { return layer == 2 ? 1 : m; }
 __host__ __device__ constexpr int cnn_ntiles(int layer, int m) { return layer == 0 ? 1 : layer == 1 ? 2 * m : 4 * m; }
 
+// Per-slot constants staged in LDS when a workgroup's slot changes: biases of the three layers
+// (offsets 0, 64, 192) and, in the bf16 kernels, the FC weights and bias.
+constexpr int CB_L2 = 64, CB_L3 = 192, CB_N = 448;
+constexpr int FCW_MAX = 256 * kClasses;
+
 struct CnnShared {
+  float cb[CB_N];
+  float fcb[kClasses];
   float gpart[2][256];
   float z[kClasses];
   uint32_t d_e[DBUF];
@@ -188,8 +195,8 @@ __device__ inline void store4(T* dst, float v0, float v1, float v2, float v3) {
 // and the decision record; if next_valid, the next frame is stored into FR meanwhile.  Returns
 // the logits in z (wave 0, lane 0 holds all 10).
 template <typename T, int M>
-__device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, bool next_valid,
-                          uint32_t next_idx, float* z_out) {
+__device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, const float* fcw,
+                          bool next_valid, uint32_t next_idx, float* z_out) {
   constexpr int C2 = 32 * M, C3 = 64 * M;
   constexpr int S1P = Pad<T>::S1P, C2P = C2 + Pad<T>::L2E;
   constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
@@ -203,9 +210,14 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   const T* const* wpk;
   if constexpr (sizeof(T) == 2) wpk = reinterpret_cast<const T* const*>(a.w_bf[slot]);
   else wpk = reinterpret_cast<const T* const*>(a.w_f32[slot]);
-  const float* b1 = a.bias[slot][0];
-  const float* b2 = a.bias[slot][1];
-  const float* b3 = a.bias[slot][2];
+  const float* b1 = sh.cb;
+  const float* b2 = sh.cb + CB_L2;
+  const float* b3 = sh.cb + CB_L3;
+  // The narrow classes fetch the next frame now: their layer 3 is too short to cover the HBM
+  // latency before the frame is stored.
+  constexpr bool kEarlyFetch = M <= 2;
+  FramePrefetch pf;
+  if (kEarlyFetch && next_valid) frame_issue(a, next_idx, pf);
 
   // ---- layer-1 im2col fragments of this wave's 8 m-tiles (reused by every slab)
   constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
@@ -331,8 +343,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
     store4<T>(L2 + (y * L2_W + x) * C2P + c, 0.f, 0.f, 0.f, 0.f);
   }
-  FramePrefetch pf;
-  if (next_valid) frame_issue(a, next_idx, pf);
+  if (!kEarlyFetch && next_valid) frame_issue(a, next_idx, pf);
   __syncthreads();
 
   // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave tile MT3 x NW3
@@ -401,7 +412,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   __syncthreads();
   // wave 0: FC (lanes over channels) -> z; the other waves store the next frame meanwhile
   if (wave == 0) {
-    const float* fw = a.fc_w[slot];
+    const float* fw = fcw;
     float zp[kClasses];
 #pragma unroll
     for (int c = 0; c < kClasses; ++c) zp[c] = 0.f;
@@ -416,20 +427,10 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     for (int c = 0; c < kClasses; ++c) {
       float v = zp[c];
       for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-      z_out[c] = v + a.fc_b[slot][c];
+      z_out[c] = v + sh.fcb[c];
     }
   }
   if (next_valid) frame_store<T>(a, pf, region);
-}
-
-__device__ inline void decode_entry(const CnnArgs& a, int t, int& slot, int& off) {
-  slot = 0;
-  off = t;
-  for (int i = 0; i < a.n_preds; ++i) {
-    const int c = a.q.counts[a.pred[i]];
-    if (off < c) { slot = i; return; }
-    off -= c;
-  }
 }
 
 // Persistent over every queue of the launch: entry t of the concatenated queues goes to workgroup
@@ -440,51 +441,104 @@ template <typename T, int VSET>
 __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
   __shared__ __attribute__((aligned(16))) unsigned char region[CnnLds<T>::REGION];
   __shared__ CnnShared sh;
+  // FC weights of the current slot (bf16 kernels; the FP32 kernel has no LDS left and reads them
+  // from global memory)
+  __shared__ float fcw_s[sizeof(T) == 2 ? FCW_MAX : 1];
   const int tid = threadIdx.x;
   if (tid == 0) sh.d_n = 0;
   if (tid < kMaxK) sh.ticks[tid] = 0;
-  int total = 0;
-  for (int i = 0; i < a.n_preds; ++i) total += a.q.counts[a.pred[i]];
-  // thread 0 fetches the threshold of the frame after the current one while that frame's loads are
-  // in flight, so the decision never waits on a global load
-  float th_next = 0.f;
+  // queue prefix offsets (read once; uniform), so locating entry t is arithmetic
+  int cum[kMaxK + 1];
+  cum[0] = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxK; ++i) cum[i + 1] = cum[i] + (i < a.n_preds ? a.q.counts[a.pred[i]] : 0);
+  const int total = cum[kMaxK];
+  auto locate = [&](int t, int& slot) -> uint32_t {
+    int base = 0;
+    slot = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxK; ++i)
+      if (i < a.n_preds && t >= cum[i]) { slot = i; base = cum[i]; }
+    return a.q.entries[(int64_t)a.pred[slot] * a.q.cap + (t - base)];
+  };
+  const int G = gridDim.x;
+  // Entries are fetched two frames ahead and thresholds one frame ahead (thread 0), so neither
+  // the frame fetch nor the decision waits on a dependent global load.
+  uint32_t e_cur = 0, e_nxt = 0;
+  float th_cur = 0.f, th_nxt = 0.f;
   if ((int)blockIdx.x < total) {
-    int slot, off;
-    decode_entry(a, blockIdx.x, slot, off);
-    const uint32_t idx0 = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + off]);
+    int slot;
+    e_cur = locate(blockIdx.x, slot);
     FramePrefetch pf;
-    frame_issue(a, idx0, pf);
-    if (tid == 0 && f.logits == nullptr) th_next = theta_of(f, a.pred[slot], idx0);
+    frame_issue(a, entry_idx(e_cur), pf);
+    if (tid == 0 && f.logits == nullptr) th_cur = theta_of(f, a.pred[slot], entry_idx(e_cur));
     frame_store<T>(a, pf, region);
   }
+  if ((int)blockIdx.x + G < total) {
+    int s2;
+    e_nxt = locate(blockIdx.x + G, s2);
+  }
   __syncthreads();
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const float th = th_next;
-    int slot, off;
-    decode_entry(a, t, slot, off);
+  int loaded = -1;
+  for (int t = blockIdx.x; t < total; t += G) {
+    int slot;
+    {
+      int base = 0;
+      slot = 0;
+#pragma unroll
+      for (int i = 1; i < kMaxK; ++i)
+        if (i < a.n_preds && t >= cum[i]) { slot = i; base = cum[i]; }
+      (void)base;
+    }
     const int k = a.pred[slot];
-    const uint32_t e = a.q.entries[(int64_t)k * a.q.cap + off];
+    const int v = a.variant[slot];
+    if (slot != loaded) {
+      const int m = v == CNN_W4 ? 4 : v == CNN_W2 ? 2 : 1;
+      for (int q = tid; q < 16 * m; q += NTHR) sh.cb[q] = a.bias[slot][0][q];
+      for (int q = tid; q < 32 * m; q += NTHR) sh.cb[CB_L2 + q] = a.bias[slot][1][q];
+      for (int q = tid; q < 64 * m; q += NTHR) sh.cb[CB_L3 + q] = a.bias[slot][2][q];
+      if (tid < kClasses) sh.fcb[tid] = a.fc_b[slot][tid];
+      if constexpr (sizeof(T) == 2) {
+        for (int q = tid; q < 64 * m * kClasses; q += NTHR) fcw_s[q] = a.fc_w[slot][q];
+      }
+      __syncthreads();
+      loaded = slot;
+    }
+    const float* fcw = sizeof(T) == 2 ? fcw_s : a.fc_w[slot];
+    const uint32_t e = e_cur;
     const uint32_t idx = entry_idx(e);
-    const int tn = t + gridDim.x;
-    bool next_valid = tn < total;
+    const float th = th_cur;
+    const int tn = t + G;
+    const bool next_valid = tn < total;
     uint32_t next_idx = 0;
     if (next_valid) {
-      int s2, o2;
-      decode_entry(a, tn, s2, o2);
-      next_idx = entry_idx(a.q.entries[(int64_t)a.pred[s2] * a.q.cap + o2]);
-      if (tid == 0 && f.logits == nullptr) th_next = theta_of(f, a.pred[s2], next_idx);
+      next_idx = entry_idx(e_nxt);
+      if (tid == 0 && f.logits == nullptr) {
+        int s2;
+        int base = 0;
+        s2 = 0;
+#pragma unroll
+        for (int i = 1; i < kMaxK; ++i)
+          if (i < a.n_preds && tn >= cum[i]) { s2 = i; base = cum[i]; }
+        (void)base;
+        th_nxt = theta_of(f, a.pred[s2], next_idx);
+      }
+    }
+    uint32_t e_nn = 0;
+    if (tn + G < total) {
+      int s3;
+      e_nn = locate(tn + G, s3);
     }
     unsigned long long t0 = wall_clock64();
     float z[kClasses];
-    const int v = a.variant[slot];
     if constexpr ((VSET & 4) != 0) {
-      if (v == CNN_W4) cnn_frame<T, 4>(a, slot, region, sh, next_valid, next_idx, z);
+      if (v == CNN_W4) cnn_frame<T, 4>(a, slot, region, sh, fcw, next_valid, next_idx, z);
     }
     if constexpr ((VSET & 2) != 0) {
-      if (v == CNN_W2) cnn_frame<T, 2>(a, slot, region, sh, next_valid, next_idx, z);
+      if (v == CNN_W2) cnn_frame<T, 2>(a, slot, region, sh, fcw, next_valid, next_idx, z);
     }
     if constexpr ((VSET & 1) != 0) {
-      if (v == CNN_W1) cnn_frame<T, 1>(a, slot, region, sh, next_valid, next_idx, z);
+      if (v == CNN_W1) cnn_frame<T, 1>(a, slot, region, sh, fcw, next_valid, next_idx, z);
     }
     if (tid == 0) {
       if (f.logits != nullptr) {
@@ -502,6 +556,9 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
     }
     __syncthreads();
     if (sh.d_n == DBUF) flush_decisions(f, sh, a.n_preds, a.pred);
+    e_cur = e_nxt;
+    e_nxt = e_nn;
+    th_cur = th_nxt;
   }
   if (f.logits == nullptr) flush_decisions(f, sh, a.n_preds, a.pred);
   __syncthreads();
@@ -530,7 +587,6 @@ __device__ inline int mult_dev(int variant) { return variant == CNN_W1 ? 1 : var
 __device__ inline double conv64_at(const CnnArgs& a, int slot, int layer, uint32_t idx, const double* in, int p, int o) {
   const int m = mult_dev(a.variant[slot]);
   const int cin = layer == 0 ? 3 : layer == 1 ? 16 * m : 32 * m;
-  const int cout = layer == 0 ? 16 * m : layer == 1 ? 32 * m : 64 * m;
   const int hin = layer == 0 ? H0 : layer == 1 ? H1 : H2;
   const int hout = hin / 2;
   const int i = p / hout, j = p % hout;
