@@ -399,10 +399,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       float s = 0.f;
 #pragma unroll
       for (int q = 0; q < MT3; ++q) s += fmaxf(acc3[q][n][r] + bb, 0.f);
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 4);
-      s += __shfl_xor(s, 8);
+      s = row_sum16(s);
       if (l16 == 0) sh.gpart[mh][ch0 + r] = s;
     }
   }
@@ -423,12 +420,9 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
       for (int c = 0; c < kClasses; ++c) zp[c] += gch * fw[ch * kClasses + c];
     }
+    wave_sum_n(zp);
 #pragma unroll
-    for (int c = 0; c < kClasses; ++c) {
-      float v = zp[c];
-      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-      z_out[c] = v + sh.fcb[c];
-    }
+    for (int c = 0; c < kClasses; ++c) z_out[c] = zp[c] + sh.fcb[c];
   }
   if (next_valid) frame_store<T>(a, pf, region);
 }

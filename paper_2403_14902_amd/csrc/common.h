@@ -128,6 +128,9 @@ struct Forward {
   int n_seg;
   int64_t seg_len;
   int64_t id_base;
+  int64_t seg_first;         // segment of local index 0 (id_base / seg_len)
+  uint32_t seg_off;          // id_base mod seg_len
+  uint32_t seg_len32;        // seg_len when below 2^31 (32-bit segment arithmetic), else 0
   uint32_t full_mask;        // (1 << K) - 1
   int k_total;
   int count_eval;            // 1 in the first pass (counts evaluated tuples)
@@ -136,10 +139,36 @@ struct Forward {
 };
 
 __device__ inline float theta_of(const Forward& f, int k, uint32_t idx) {
-  int64_t g = f.id_base + (int64_t)idx;
-  int64_t s = g / f.seg_len;
+  int64_t s;
+  if (f.seg_len32 != 0) s = f.seg_first + (int64_t)((f.seg_off + idx) / f.seg_len32);  // idx < 2^24
+  else s = (f.id_base + (int64_t)idx) / f.seg_len;
   if (s >= f.n_seg) s = f.n_seg - 1;
   return f.theta[s * f.k_total + k];
+}
+
+// Cross-lane sums.  row_sum16: over the 16 lanes of each DPP row (lanes 16r..16r+15), by
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and row_mirror (each step adds a lane
+// whose partial covers the complementary lanes, so every lane ends with the row total).
+// wave_sum: all 64 lanes (two more steps across rows).
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float row_sum16(float v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  return v;
+}
+template <int N>
+__device__ inline void wave_sum_n(float (&v)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] = row_sum16(v[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 16);
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 32);
 }
 
 __device__ inline int lane_id() { return __lane_id(); }

@@ -878,6 +878,9 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
   f.n_seg = n_seg;
   f.seg_len = seg_len;
   f.id_base = id_base;
+  f.seg_first = id_base >= 0 ? id_base / seg_len : 0;
+  f.seg_off = id_base >= 0 ? (uint32_t)(id_base % seg_len) : 0;
+  f.seg_len32 = (id_base >= 0 && seg_len < ((int64_t)1 << 31)) ? (uint32_t)seg_len : 0u;
   f.full_mask = (1u << s->K) - 1u;
   f.k_total = s->K;
   f.logits = nullptr;

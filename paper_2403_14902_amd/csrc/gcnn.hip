@@ -189,9 +189,7 @@ __global__ __launch_bounds__(256) void gcnn_head_kernel(GcnnArgs a, Forward f) {
         for (int c = 0; c < kClasses; ++c) zp[c] += gch * fw[ch * kClasses + c];
       }
     }
-#pragma unroll
-    for (int c = 0; c < kClasses; ++c)
-      for (int o = 32; o >= 1; o >>= 1) zp[c] += __shfl_xor(zp[c], o);
+    wave_sum_n(zp);
     bool pass = false, defer = false;
     if (active) {
       float z[kClasses];

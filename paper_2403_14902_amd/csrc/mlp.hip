@@ -194,10 +194,7 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
           float s = 0.f;
 #pragma unroll
           for (int j = 0; j < FN; ++j) s += acc[i][j][r] * w2v[j];
-          s += __shfl_xor(s, 1);
-          s += __shfl_xor(s, 2);
-          s += __shfl_xor(s, 4);
-          s += __shfl_xor(s, 8);
+          s = row_sum16(s);
           const int rr = mt * BM + wm * WM + i * 16 + 4 * (lane >> 4) + r;
           if ((lane & 15) == 0 && rr < cnt) part[(int64_t)rr * kClasses + c] = s;
         }

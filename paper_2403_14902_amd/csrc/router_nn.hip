@@ -373,10 +373,7 @@ __global__ __launch_bounds__(256) void rnn_train_kernel(DevState* st, const uint
     // logit of the evaluated slot: reduce over the 16 lanes of the group
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      po[r] += __shfl_xor(po[r], 1);
-      po[r] += __shfl_xor(po[r], 2);
-      po[r] += __shfl_xor(po[r], 4);
-      po[r] += __shfl_xor(po[r], 8);
+      po[r] = row_sum16(po[r]);
     }
     float d[4];
 #pragma unroll
