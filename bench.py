@@ -16,6 +16,9 @@ Forms:
   plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate.
   The timed runs record HIP events around each round's phases (for the roofline); the same
   forms replayed from a captured HIP graph are reported as `graph_value`.
+  Every form's session calibrates its per-predicate bands at setup (untimed): tau_k and tau32_k
+  are `--safety` (2) times the largest margin error of the first pass / FP32 pass against the
+  FP64 pass on 8,192 separate frames of the same generator (--no-calibrate: fixed defaults).
 
 Prints one JSON line (the full form's throughput as `value`, the plain form beside it, the
 dominant kernel's roofline from HIP events recorded by the library on its stream, and the FP64
@@ -45,10 +48,13 @@ def parse():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--wave", type=int, default=8192)
     ap.add_argument("--tau", type=float, default=0.0)
+    ap.add_argument("--no-calibrate", action="store_true",
+                    help="use the policy's fixed bands instead of bands calibrated on separate frames")
+    ap.add_argument("--safety", type=float, default=2.0)
     ap.add_argument("--route", default="learned")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--check-sample", type=int, default=2048)
     ap.add_argument("--errors", type=int, default=4096,
                     help="frames on which bf16 / fp32 logits and margins are compared with fp64 (0: skip)")
@@ -59,8 +65,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps, warmup, n):
+def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps, warmup, n, cal=None,
+             safety=2.0):
+    """Session setup (weights, autotune and, with `cal`, band calibration) is untimed."""
     sess = hydro.Session(specs, policy, frames_dev.shape[1], n)
+    bands = sess.calibrate(cal, dtype, safety) if cal is not None else None
     res = None
     for _ in range(warmup):
         sess.reset()
@@ -78,6 +87,7 @@ def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps,
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sess.close()
+    run_form.bands = bands
     return res[0], stats_all, infos, t1 - t0
 
 
@@ -103,6 +113,8 @@ def main():
     seg_len = cfg.n // cfg.n_seg
     frames_dev = torch.from_numpy(frames).cuda()
     flops = np.array([d.flops() for d in cfg.models])
+    # band calibration sample: frames of the same generator, different seed (not the query's)
+    cal = None if args.no_calibrate else torch.from_numpy(hs.calibration_frames(cfg)).cuda()
 
     extra = {}
     if args.tau > 0:
@@ -110,7 +122,8 @@ def main():
     full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
     log(f"[bench] full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
-                                         args.steps, args.warmup, n)
+                                         args.steps, args.warmup, n, cal, args.safety)
+    bands = run_form.bands
     value = n * args.steps / dt
     ms_per_step = dt * 1e3 / args.steps
 
@@ -162,6 +175,10 @@ def main():
         "per_predicate": [{"evaluated": s["evaluated"], "passed": s["passed"], "rescored": s["rescored"],
                            "escalated": s["escalated"], "selectivity": round(s["selectivity"], 4)} for s in last],
         "n_result": int(ids.size),
+        "bands": ({"calibrated_on": f"{cal.shape[0]} separate frames", "safety": args.safety,
+                   "tau": [round(float(x), 6) for x in bands[0]],
+                   "tau32": [float(x) for x in bands[1]]} if bands is not None else
+                  {"tau": float(full_pol.tau), "tau32": float(full_pol.tau32)}),
         "rounds": infos[-1]["rounds"],
     }
 
@@ -173,7 +190,7 @@ def main():
     # the same form replayed from a captured HIP graph (no events)
     gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, use_graph=1, **extra)
     ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, args.steps,
-                                args.warmup, n)
+                                args.warmup, n, cal, args.safety)
     assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
     out["graph_value"] = n * args.steps / dtg
 
@@ -181,7 +198,7 @@ def main():
         log("[bench] score form")
         spol = hydro.make_policy("score", precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
         ids_s, st_s, inf_s, dts = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, spol,
-                                           args.steps, args.warmup, n)
+                                           args.steps, args.warmup, n, cal, args.safety)
         assert np.array_equal(ids_s, ids), "score and learned routing disagree"
         ev_s = np.array([[x["evaluated"] for x in st] for st in st_s], dtype=np.float64)
         out["score"] = {"value": n * args.steps / dts, "unit": "tuples/s",
@@ -192,7 +209,7 @@ def main():
         log("[bench] plain form")
         plain_pol = hydro.make_policy("score", precision="fp32", wave=args.wave, grouped=0, time_kernels=0)
         ids_p, _, _, dtp = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, plain_pol,
-                                    max(1, args.steps // 2), 1, n)
+                                    max(1, args.steps // 2), 1, n, cal, args.safety)
         assert np.array_equal(ids_p, ids), "plain and full forms disagree"
         vp = n * max(1, args.steps // 2) / dtp
         out["plain"] = {"value": vp, "unit": "tuples/s",
@@ -212,8 +229,7 @@ def main():
             zout = np.where(~inside, z, -np.inf).max(axis=1)
             return zin - zout
 
-        rep = {"frames": m, "reference": "library fp64 pass", "tau": float(full_pol.tau),
-               "tau32": float(full_pol.tau32)}
+        rep = {"frames": m, "reference": "library fp64 pass"}
         z64 = [es.logits(j, 2, frames_dev[:m], cfg.dtype) for j in range(cfg.k)]
         for tier, name in ((0, "bf16"), (1, "fp32")):
             ml, mm, pm = [], [], []
