@@ -46,7 +46,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2)
-    ap.add_argument("--wave", type=int, default=8192)
+    ap.add_argument("--n", type=int, default=0,
+                    help="tuples: a prefix of the workload (0: all; the 1,048,576-frame uint8 workload "
+                         "defaults to a 131,072-frame prefix)")
+    ap.add_argument("--host", action="store_true",
+                    help="also time the full form pushed from pinned host memory in the workload's "
+                         "push batches (PCIe-inclusive)")
+    ap.add_argument("--wave", type=int, default=16384)
     ap.add_argument("--tau", type=float, default=0.0)
     ap.add_argument("--no-calibrate", action="store_true",
                     help="use the policy's fixed bands instead of bands calibrated on separate frames")
@@ -66,22 +72,28 @@ def log(msg):
 
 
 def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps, warmup, n, cal=None,
-             safety=2.0):
-    """Session setup (weights, autotune and, with `cal`, band calibration) is untimed."""
-    sess = hydro.Session(specs, policy, frames_dev.shape[1], n)
+             safety=2.0, push_batch=0):
+    """Session setup (weights, autotune and, with `cal`, band calibration) is untimed.  With
+    push_batch > 0 the tuples are pushed in blocks of that size (from wherever frames_dev lives,
+    e.g. pinned host memory)."""
+    blk = push_batch if push_batch > 0 else n
+    sess = hydro.Session(specs, policy, frames_dev.shape[1], blk)
     bands = sess.calibrate(cal, dtype, safety) if cal is not None else None
     res = None
-    for _ in range(warmup):
+
+    def one_query():
         sess.reset()
-        sess.push(frames_dev, dtype, pt.thresholds, seg_len)
-        res = sess.finish()
+        for lo in range(0, n, blk):
+            sess.push(frames_dev[lo:lo + blk], dtype, pt.thresholds, seg_len, id_base=lo)
+        return sess.finish()
+
+    for _ in range(warmup):
+        res = one_query()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos, stats_all = [], []
     for _ in range(steps):
-        sess.reset()
-        sess.push(frames_dev, dtype, pt.thresholds, seg_len)
-        res = sess.finish()
+        res = one_query()
         infos.append(sess.info())
         stats_all.append(res[1])
     torch.cuda.synchronize()
@@ -104,7 +116,8 @@ def main():
     torch.cuda.set_device(0)
     hydro.lib()
     cfg = hs.workload(args.workload)
-    n = cfg.n
+    n = args.n if args.n > 0 else (131072 if cfg.index == 5 else cfg.n)
+    n = min(n, cfg.n)
     log(f"[bench] generating {n} frames of workload {cfg.name}")
     frames = hs.make_frames_parallel(cfg, 0, n)
     pt = hs.load_predicates(cfg)
@@ -119,6 +132,13 @@ def main():
     extra = {}
     if args.tau > 0:
         extra["tau"] = args.tau
+    d0 = cfg.models[0]
+    if d0.arch == "mlp":
+        kernel_label = "mlp_gemm_kernel<bf16> + mlp_head_kernel (first pass, grouped over predicates)"
+    elif cfg.hw == 64 and all(len(d.widths) == 3 for d in cfg.models):
+        kernel_label = "cnn_fused_kernel<bf16, *> (first pass: one launch per width class)"
+    else:
+        kernel_label = "gconv_layer_kernel<bf16> per layer + gcnn_head_kernel (first pass, grouped)"
     full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
     log(f"[bench] full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
@@ -151,12 +171,13 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {n} frames {cfg.hw}x{cfg.hw}x3 {cfg.dtype}, "
-                               f"{cfg.k} predicates, {cfg.n_seg} threshold segments",
+                               f"{cfg.k} predicates, {cfg.n_seg} threshold segments"
+                               + (f" (first {n} of {cfg.n} tuples)" if n < cfg.n else ""),
                    "form": "full: bf16 first pass + fp32/fp64 re-score, " + args.route + " routing, grouped",
                    "wave": args.wave, "tuples_per_step": n},
         "roofline": {
             "bound": "mfma",
-            "kernel": "cnn_fused_kernel<bf16, *> (first pass: widest class, then the two narrower classes)",
+            "kernel": kernel_label,
             "achieved": achieved,
             "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
@@ -205,6 +226,19 @@ def main():
                         "udf_gflop_per_step": float((ev_s * flops).sum()) / args.steps / 1e9,
                         "first_pass_ms_per_step": sum(i["first_pass_ms"] for i in inf_s) / args.steps}
 
+    if args.host or cfg.push_batch > 0:
+        blk = cfg.push_batch if cfg.push_batch > 0 else 16384
+        log(f"[bench] full form pushed from pinned host memory in blocks of {blk}")
+        frames_host = torch.from_numpy(frames).pin_memory()
+        hpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, **extra)
+        ids_h, _, _, dth = run_form(hydro, torch, specs, frames_host, cfg.dtype, pt, seg_len, hpol,
+                                    max(1, args.steps // 2), 1, n, cal, args.safety, push_batch=blk)
+        assert np.array_equal(ids_h, ids), "host-pushed and device-resident runs disagree"
+        out["host_pinned"] = {"value": n * max(1, args.steps // 2) / dth, "unit": "tuples/s",
+                              "push_batch": blk, "note": "PCIe-inclusive: frames start in pinned host memory",
+                              "h2d_gb_per_s_equiv": frames.nbytes * max(1, args.steps // 2) / dth / 1e9}
+        del frames_host
+
     if not args.no_plain:
         log("[bench] plain form")
         plain_pol = hydro.make_policy("score", precision="fp32", wave=args.wave, grouped=0, time_kernels=0)
@@ -247,7 +281,8 @@ def main():
         # FP64 oracle on a bounded, evenly spread sample of the same workload
         from threadpoolctl import threadpool_info
         from oracle import hydro_oracle as ho
-        m = min(args.cpu_sample, n)
+        # bounded sample: about 1e13 FP64 FLOPs of oracle work (every predicate on every tuple)
+        m = int(min(args.cpu_sample, n, max(1024, 1e13 // float(flops.sum()))))
         sel = np.linspace(0, n - 1, m).astype(np.int64)
         fr_s = np.ascontiguousarray(frames[sel])
         cores = min(16, os.cpu_count() or 1)
@@ -262,7 +297,7 @@ def main():
         exp_in = P.all(axis=1)
         got_in = np.isin(sel, ids)
         out["cpu_baseline"] = {"value": m / tc, "unit": "tuples/s", "cores": cores, "kind": "oracle",
-                               "sample": f"{m} tuples evenly spaced over the {n}-tuple workload, every predicate "
+                               "sample": f"{m} tuples evenly spaced over the {n} tuples, every predicate "
                                          f"evaluated in fp64 (numpy, BLAS 1 thread per worker)",
                                "os_cpu_count": os.cpu_count(),
                                "blas": [d.get("internal_api") for d in threadpool_info()]}

@@ -26,6 +26,11 @@ struct MlpArgs {
   int64_t part_cap;
   double* esc_h[kMaxK];             // FP64 tier: partial hidden sums [chunk][esc_cap][hidden]
   int esc_cap;
+  float* splitk_ws;                 // split-K partial sums, split_slots tiles of 128 x 128
+  int* split_cnt;                   // per base tile: parts finished (zero between launches)
+  int split_below;                  // launches with fewer (rows x hidden) tiles than this split K
+  int split_target;                 // ... into about this many tiles
+  int split_slots;
   Queues q;
   FrameSrc fr;
   DevState* st;

@@ -479,6 +479,17 @@ static int pack_models(hydro_session* s) {
       if ((rc = upload(s, hm.b1.data(), hm.b1.size(), &dp))) return rc;
       ma.b1_canon[i] = dp;
       if ((rc = sess_alloc(s, (void**)&ma.partial[i], (size_t)(H / 32) * s->cap * kClasses * sizeof(float)))) return rc;
+      if (ma.splitk_ws == nullptr) {
+        // split-K workspace shared by the MLP predicates: 1024 tiles of 128 x 128 fp32 (64 MB)
+        ma.split_slots = 1024;
+        // HYDRO_SPLITK_BELOW overrides the tile count under which a launch splits K
+        const char* sb = getenv("HYDRO_SPLITK_BELOW");
+        ma.split_below = (sb && *sb) ? atoi(sb) : s->n_cu / 2;
+        ma.split_target = 2 * s->n_cu;
+        if ((rc = sess_alloc(s, (void**)&ma.splitk_ws, (size_t)ma.split_slots * 128 * 128 * sizeof(float)))) return rc;
+        if ((rc = sess_alloc(s, (void**)&ma.split_cnt, (size_t)ma.split_slots * sizeof(int)))) return rc;
+        HIP_TRY(hipMemset(ma.split_cnt, 0, (size_t)ma.split_slots * sizeof(int)));
+      }
       {
         // HYDRO_MLP_TILE forces one tile configuration (tests exercise each)
         const char* ft = getenv("HYDRO_MLP_TILE");

@@ -53,6 +53,22 @@ __device__ inline void load_frame_run(const FrameSrc& fr, uint32_t idx, int64_t 
   }
 }
 
+// Split-K: when a launch has fewer (rows x hidden) tiles than split_below (small queues, e.g.
+// the re-score bands), every tile's K range is divided into S parts computed by different
+// workgroups, S ~ split_target / tiles.  Each part stores its raw sums in the workspace and
+// counts itself in the tile's counter; the part that arrives last adds the S sums in split order
+// (deterministic whichever part is last), resets the counter and runs the usual epilogue.  S is
+// a pure function of the queue counts.
+constexpr int SPLIT_MAX = 8;
+__device__ inline int mlp_splits(int base_total, int nk_min, const MlpArgs& a) {
+  if (a.splitk_ws == nullptr || base_total <= 0 || base_total >= a.split_below) return 1;
+  int sp = (a.split_target + base_total - 1) / base_total;
+  sp = min(sp, SPLIT_MAX);
+  sp = min(sp, a.split_slots / base_total);
+  sp = min(sp, nk_min / 4);
+  return max(sp, 1);
+}
+
 // Tile shapes (rows of queued tuples x hidden units) an autotuner may pick per predicate.
 // Every launch covers the predicates of one tile shape.
 template <typename T, int BM, int BN>
@@ -63,19 +79,24 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
   constexpr int FM = WM / 16, FN = WN / 16;       // MFMA tiles per wave
   __shared__ __attribute__((aligned(16))) T As[2][BM * LD];
   __shared__ __attribute__((aligned(16))) T Bs[2][BN * LD];
+  __shared__ int s_last;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = tid >> 1, lk = (tid & 1) * PER;  // this thread's load row (< 128) and k offset
   const bool lda = lr < BM, ldb = lr < BN;
 
-  int total = 0;
+  int base_total = 0, nk_min = 1 << 30;
   for (int i = 0; i < a.n_preds; ++i) {
     const int cnt = a.q.counts[a.pred[i]];
-    total += ((cnt + BM - 1) / BM) * (a.hidden[i] / BN);
+    base_total += ((cnt + BM - 1) / BM) * (a.hidden[i] / BN);
+    nk_min = min(nk_min, a.d_in[i] / BK);
   }
+  const int S = mlp_splits(base_total, nk_min, a);
+  const int total = base_total * S;
 
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int tb = t / S, sp = t % S;
     int slot = 0, mt = 0, nt = 0;
     {
       int acc0 = 0;
@@ -83,10 +104,10 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
         const int cnt = a.q.counts[a.pred[i]];
         const int n_nt = a.hidden[i] / BN;
         const int tiles = ((cnt + BM - 1) / BM) * n_nt;
-        if (t < acc0 + tiles) {
+        if (tb < acc0 + tiles) {
           slot = i;
-          mt = (t - acc0) / n_nt;
-          nt = (t - acc0) % n_nt;
+          mt = (tb - acc0) / n_nt;
+          nt = (tb - acc0) % n_nt;
           break;
         }
         acc0 += tiles;
@@ -110,31 +131,27 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
 
-    alignas(16) T ra[PER];
-    alignas(16) T rb[PER];
-    auto gload = [&](int kt) {
-      if (lda) load_frame_run<T, PER>(a.fr, idx, (int64_t)kt * BK + lk, ra);
+    // NS register stages: the global loads of k-tile kt + NS - 1 are issued while tile kt is
+    // computed, so NS - 1 tiles are in flight per thread (the gathered frame rows come from HBM).
+    constexpr int NS = 4;
+    alignas(16) T ra[NS][PER];
+    alignas(16) T rb[NS][PER];
+    auto gload = [&](int kt, int st) {
+      if (lda) load_frame_run<T, PER>(a.fr, idx, (int64_t)kt * BK + lk, ra[st]);
       if (ldb) {
         const uint4* pb = reinterpret_cast<const uint4*>(wrow + (int64_t)kt * BK + lk);
 #pragma unroll
-        for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb)[v] = pb[v];
+        for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb[st])[v] = pb[v];
       }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int st, int buf) {
 #pragma unroll
       for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) {
-        if (lda) reinterpret_cast<uint4*>(&As[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(ra)[v];
-        if (ldb) reinterpret_cast<uint4*>(&Bs[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(rb)[v];
+        if (lda) reinterpret_cast<uint4*>(&As[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(ra[st])[v];
+        if (ldb) reinterpret_cast<uint4*>(&Bs[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(rb[st])[v];
       }
     };
-
-    const int nk = D / BK;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-      const int buf = kt & 1;
-      if (kt + 1 < nk) gload(kt + 1);
+    auto compute = [&](int buf) {
       if constexpr (sizeof(T) == 2) {
         bf16x8 af[FM], bfr[FN];
 #pragma unroll
@@ -163,13 +180,69 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
       }
-      if (kt + 1 < nk) {
-        __syncthreads();
-        lstore(buf ^ 1);
-        __syncthreads();
+    };
+
+    const int nk_all = D / BK;
+    const int kt0 = (int)((int64_t)nk_all * sp / S), nk = (int)((int64_t)nk_all * (sp + 1) / S);
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+      if (kt0 + u < nk) gload(kt0 + u, u);
+    lstore(0, kt0 & 1);
+    __syncthreads();
+    // k-tile kt = kb + u lives in register stage u (kb - kt0 is a multiple of NS)
+    for (int kb = kt0; kb < nk; kb += NS) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        const int kt = kb + u;
+        if (kt < nk) {
+          const int buf = kt & 1;
+          if (kt + NS - 1 < nk) gload(kt + NS - 1, (u + NS - 1) % NS);
+          compute(buf);
+          if (kt + 1 < nk) {
+            __syncthreads();
+            lstore((u + 1) % NS, buf ^ 1);
+            __syncthreads();
+          }
+        }
       }
     }
 
+    if (S > 1) {
+      // raw sums of this K range: ws[tb][sp][column in tile][row in tile], each lane's four
+      // consecutive rows in one 16-byte store
+      float* wt = a.splitk_ws + (int64_t)tb * S * (BM * BN);
+      auto at = [&](int q, int i, int j) -> float4* {
+        return reinterpret_cast<float4*>(
+            &wt[(int64_t)q * (BM * BN) + (wn * WN + j * 16 + (lane & 15)) * BM + wm * WM + i * 16 + 4 * (lane >> 4)]);
+      };
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) *at(sp, i, j) = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_last = atomicAdd(&a.split_cnt[tb], 1) == S - 1;
+      __syncthreads();
+      if (!s_last) {
+        if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
+        continue;
+      }
+      __threadfence();
+      if (tid == 0) a.split_cnt[tb] = 0;      // ready for the next launch
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          floatx4 sum = (floatx4){0.f, 0.f, 0.f, 0.f};
+          for (int q = 0; q < S; ++q) {
+            float4 v;
+            if (q == sp) v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+            else v = *at(q, i, j);
+            sum[0] += v.x; sum[1] += v.y; sum[2] += v.z; sum[3] += v.w;
+          }
+          acc[i][j] = sum;
+        }
+    }
     // epilogue: H = ReLU(acc + b1'), partial logits over this wave's WN hidden columns
     const float* b1 = a.b1_fold[slot];
     const float* w2 = a.w2[slot];
@@ -492,17 +565,22 @@ __global__ __launch_bounds__(256) void mlp_f64_rest_kernel(MlpArgs a, Forward f)
 // Tile configurations: 0 = 128x128, 1 = 64x128, 2 = 128x64, 3 = 64x64 (rows x hidden units).
 int mlp_tile_bn(int cfg) { return cfg == 0 || cfg == 1 ? 128 : 64; }
 
+template <typename T, int BM, int BN>
+static void launch_gemm_t(const MlpArgs& b, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((mlp_gemm_kernel<T, BM, BN>), dim3(grid), dim3(256), 0, s, b);
+}
+
 void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s) {
   if (bf) {
-    if (cfg == 0) hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 128, 128>), dim3(grid), dim3(256), 0, s, b);
-    else if (cfg == 1) hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 64, 128>), dim3(grid), dim3(256), 0, s, b);
-    else if (cfg == 2) hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 128, 64>), dim3(grid), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((mlp_gemm_kernel<__bf16, 64, 64>), dim3(grid), dim3(256), 0, s, b);
+    if (cfg == 0) launch_gemm_t<__bf16, 128, 128>(b, grid, s);
+    else if (cfg == 1) launch_gemm_t<__bf16, 64, 128>(b, grid, s);
+    else if (cfg == 2) launch_gemm_t<__bf16, 128, 64>(b, grid, s);
+    else launch_gemm_t<__bf16, 64, 64>(b, grid, s);
   } else {
-    if (cfg == 0) hipLaunchKernelGGL((mlp_gemm_kernel<float, 128, 128>), dim3(grid), dim3(256), 0, s, b);
-    else if (cfg == 1) hipLaunchKernelGGL((mlp_gemm_kernel<float, 64, 128>), dim3(grid), dim3(256), 0, s, b);
-    else if (cfg == 2) hipLaunchKernelGGL((mlp_gemm_kernel<float, 128, 64>), dim3(grid), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((mlp_gemm_kernel<float, 64, 64>), dim3(grid), dim3(256), 0, s, b);
+    if (cfg == 0) launch_gemm_t<float, 128, 128>(b, grid, s);
+    else if (cfg == 1) launch_gemm_t<float, 64, 128>(b, grid, s);
+    else if (cfg == 2) launch_gemm_t<float, 128, 64>(b, grid, s);
+    else launch_gemm_t<float, 64, 64>(b, grid, s);
   }
 }
 
