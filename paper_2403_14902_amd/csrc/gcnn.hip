@@ -152,6 +152,180 @@ __global__ __launch_bounds__(256) void gconv_layer_kernel(GcnnArgs a, int layer)
   }
 }
 
+// Layers after the first when Cin is a multiple of the k-block and Cout of 64: an LDS-tiled
+// implicit GEMM.  Tile = 128 output positions (any frames of one slot) x BN output channels
+// (128 when Cout allows, else 64);
+// k-block = 32 (bf16) or 16 (fp32) consecutive input channels of one tap, so each position's
+// slice of the block is one contiguous run of its NHWC input.  Activations and the packed
+// weight fragments of a block are staged in LDS (double buffer) from NS register stages of
+// global loads; wave w multiplies channels 0..BN-1 (MFMA A, from the weights) by positions
+// 32w..32w+31 (MFMA B), so each lane ends with 4 consecutive channels of one position.
+template <typename T> struct GTile;
+template <> struct GTile<__bf16> { static constexpr int BK = 32, LD = 40; };
+template <> struct GTile<float> { static constexpr int BK = 16, LD = 20; };
+constexpr int GB_M = 128;
+
+__host__ __device__ inline bool gconv_tiled_ok(int layer, int cin, int cout, int bk, int bn) {
+  return layer > 0 && cin % bk == 0 && cout % bn == 0;
+}
+
+template <typename T, int GB_N>
+__global__ __launch_bounds__(256) void gconv_tile_kernel(GcnnArgs a, int layer) {
+  typedef typename GMf<T>::frag frag;
+  constexpr int BK = GTile<T>::BK, LD = GTile<T>::LD, KSTEP = GMf<T>::KSTEP, KPL = GMf<T>::KPL;
+  constexpr int KSUB = BK / KSTEP;                 // MFMA k-steps per block (1 bf16, 4 fp32)
+  constexpr int NS = 4;
+  constexpr int NCT = GB_N / 16;                   // 16-channel MFMA tiles per block
+  constexpr int WV = NCT / 4;                      // 16-byte weight chunks per thread and block
+  __shared__ __attribute__((aligned(16))) T Xs[2][GB_M * LD];
+  __shared__ __attribute__((aligned(16))) uint4 Ws[2][256 * WV];   // KSUB x NCT tiles x 64 lanes
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) {
+    if (layer >= a.n_layers[i]) continue;
+    const int hout = a.in_hw[i] >> (layer + 1);
+    const int64_t rows = (int64_t)a.q.counts[a.pred[i]] * hout * hout;
+    total += (int)((rows + GB_M - 1) / GB_M) * (a.widths[i][layer] / GB_N);
+  }
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t, ebase = 0;
+    for (int i = 0; i < a.n_preds; ++i) {
+      if (layer >= a.n_layers[i]) { ebase += a.q.counts[a.pred[i]]; continue; }
+      const int hout = a.in_hw[i] >> (layer + 1);
+      const int64_t rows = (int64_t)a.q.counts[a.pred[i]] * hout * hout;
+      const int c = (int)((rows + GB_M - 1) / GB_M) * (a.widths[i][layer] / GB_N);
+      if (off < c) { slot = i; break; }
+      off -= c;
+      ebase += a.q.counts[a.pred[i]];
+    }
+    const int cnt = a.q.counts[a.pred[slot]];
+    const int hin = a.in_hw[slot] >> layer, hout = hin >> 1, P = hout * hout;
+    const int cin = a.widths[slot][layer - 1], cout = a.widths[slot][layer];
+    const int nct = cout / GB_N;
+    const int mt = off / nct, cb = off % nct;   // cb: block of GB_N channels
+    const int nkb = 9 * cin / BK;
+    const int ctile16 = cout / 16;
+    const frag* wp = reinterpret_cast<const frag*>(sizeof(T) == 2 ? (const void*)a.w_bf[slot][layer]
+                                                                  : (const void*)a.w_f32[slot][layer]);
+    const T* act_in = reinterpret_cast<const T*>(a.act[(layer - 1) & 1]);
+    // staging row of this thread (two threads per row, BK / 2 elements each)
+    const int srow = tid >> 1, shalf = tid & 1;
+    const int64_t R = (int64_t)mt * GB_M + srow;
+    const bool svalid = R < (int64_t)cnt * P;
+    const int se = svalid ? (int)(R / P) : 0, sp = svalid ? (int)(R % P) : 0;
+    const int soi = sp / hout, soj = sp % hout;
+    const T* sin = act_in + ((int64_t)ebase + se) * a.act_stride;
+
+    uint4 rx[NS][BK * (int)sizeof(T) / 32];   // 32 bytes of activations per stage
+    uint4 rw[NS][WV];
+    auto gload = [&](int kb, int st) {
+      const int k0 = kb * BK, tap = k0 / cin, c0 = k0 % cin;
+      const int y = 2 * soi + tap / 3 - 1, x = 2 * soj + tap % 3 - 1;
+      if (svalid && y >= 0 && x >= 0 && y < hin && x < hin) {
+        const uint4* src = reinterpret_cast<const uint4*>(sin + ((int64_t)y * hin + x) * cin + c0 + shalf * (BK / 2));
+#pragma unroll
+        for (int v = 0; v < BK * (int)sizeof(T) / 32; ++v) rx[st][v] = src[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < BK * (int)sizeof(T) / 32; ++v) rx[st][v] = make_uint4(0u, 0u, 0u, 0u);
+      }
+      // weights, chunk q = tid + 256 v: bf16 fragment (ks = kb, tile cb*NCT + q/64, lane q%64);
+      // fp32: 4 consecutive lanes of (ks = kb*4 + kss, tile) with q = (kss*NCT + tile)*16 + lane/4
+#pragma unroll
+      for (int v = 0; v < WV; ++v) {
+        const int q = tid + 256 * v;
+        if constexpr (sizeof(T) == 2) {
+          rw[st][v] = *reinterpret_cast<const uint4*>(&wp[((int64_t)kb * ctile16 + cb * NCT + (q >> 6)) * 64 + (q & 63)]);
+        } else {
+          const int kss = q / (NCT * 16), tl = (q >> 4) % NCT, l4 = (q & 15) * 4;
+          rw[st][v] = *reinterpret_cast<const uint4*>(&wp[((int64_t)(kb * 4 + kss) * ctile16 + cb * NCT + tl) * 64 + l4]);
+        }
+      }
+    };
+    auto lstore = [&](int st, int buf) {
+#pragma unroll
+      for (int v = 0; v < BK * (int)sizeof(T) / 32; ++v)
+        reinterpret_cast<uint4*>(&Xs[buf][srow * LD + shalf * (BK / 2)])[v] = rx[st][v];
+#pragma unroll
+      for (int v = 0; v < WV; ++v) Ws[buf][tid + 256 * v] = rw[st][v];
+    };
+
+    floatx4 acc[NCT][2];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[c][q] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](int buf) {
+#pragma unroll
+      for (int kss = 0; kss < KSUB; ++kss) {
+        frag xf[2], wf[NCT];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const T* xp = &Xs[buf][(wave * 32 + q * 16 + l16) * LD + kss * KSTEP + KPL * g];
+          if constexpr (sizeof(T) == 2) xf[q] = *reinterpret_cast<const bf16x8*>(xp);
+          else xf[q] = *xp;
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+          if constexpr (sizeof(T) == 2) wf[c] = *reinterpret_cast<const bf16x8*>(&Ws[buf][c * 64 + lane]);
+          else wf[c] = reinterpret_cast<const float*>(&Ws[buf][0])[(kss * NCT + c) * 64 + lane];
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) acc[c][q] = gmfma(wf[c], xf[q], acc[c][q]);
+      }
+    };
+
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+      if (u < nkb) gload(u, u);
+    lstore(0, 0);
+    __syncthreads();
+    for (int kb0 = 0; kb0 < nkb; kb0 += NS) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        const int kb = kb0 + u;
+        if (kb < nkb) {
+          const int buf = kb & 1;
+          if (kb + NS - 1 < nkb) gload(kb + NS - 1, (u + NS - 1) % NS);
+          compute(buf);
+          if (kb + 1 < nkb) {
+            __syncthreads();
+            lstore((u + 1) % NS, buf ^ 1);
+            __syncthreads();
+          }
+        }
+      }
+    }
+    // bias + ReLU; lane holds channels 4g..4g+3 of tile c for position 16q + l16 of its wave
+    const float* bias = a.bias[slot][layer] + cb * GB_N;
+    T* out = reinterpret_cast<T*>(a.act[layer & 1]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int64_t Ro = (int64_t)mt * GB_M + wave * 32 + q * 16 + l16;
+      if (Ro >= (int64_t)cnt * P) continue;
+      const int e = (int)(Ro / P), p = (int)(Ro % P);
+      T* o = out + ((int64_t)ebase + e) * a.act_stride + (int64_t)p * cout + cb * GB_N;
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int ch = c * 16 + 4 * g;
+        const float v0 = fmaxf(acc[c][q][0] + bias[ch], 0.f), v1 = fmaxf(acc[c][q][1] + bias[ch + 1], 0.f);
+        const float v2 = fmaxf(acc[c][q][2] + bias[ch + 2], 0.f), v3 = fmaxf(acc[c][q][3] + bias[ch + 3], 0.f);
+        if constexpr (sizeof(T) == 2) {
+          alignas(8) __bf16 h[4] = {static_cast<__bf16>(v0), static_cast<__bf16>(v1), static_cast<__bf16>(v2),
+                                    static_cast<__bf16>(v3)};
+          *reinterpret_cast<uint2*>(o + ch) = *reinterpret_cast<const uint2*>(h);
+        } else {
+          *reinterpret_cast<float4*>(o + ch) = make_float4(v0, v1, v2, v3);
+        }
+      }
+    }
+    __syncthreads();   // the next tile's prologue rewrites the LDS buffers
+  }
+}
+
 // Pool + FC + margin + decision: one wave per frame.
 template <typename T>
 __global__ __launch_bounds__(256) void gcnn_head_kernel(GcnnArgs a, Forward f) {
@@ -183,6 +357,7 @@ __global__ __launch_bounds__(256) void gcnn_head_kernel(GcnnArgs a, Forward f) {
       const float* fw = a.fc_w[slot];
       for (int ch = lane; ch < cl; ch += 64) {
         float s = 0.f;
+#pragma unroll 8
         for (int p = 0; p < P; ++p) s += (float)act[(int64_t)p * cl + ch];
         const float gch = s / (float)P;
 #pragma unroll
@@ -422,8 +597,24 @@ void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, h
   }
   const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;
   for (int l = 0; l < maxl; ++l) {
-    if (bf) hipLaunchKernelGGL(gconv_layer_kernel<__bf16>, dim3(grid * 4), dim3(256), 0, s, a, l);
-    else hipLaunchKernelGGL(gconv_layer_kernel<float>, dim3(grid * 4), dim3(256), 0, s, a, l);
+    // the tiled kernel when every slot that has this layer fits its shape constraints
+    bool tiled = true, wide = true;
+    for (int i = 0; i < a.n_preds; ++i) {
+      if (l >= a.n_layers[i]) continue;
+      const int cin = l == 0 ? 3 : a.widths[i][l - 1], cout = a.widths[i][l];
+      tiled = tiled && gconv_tiled_ok(l, cin, cout, bf ? 32 : 16, 64);
+      wide = wide && gconv_tiled_ok(l, cin, cout, bf ? 32 : 16, 128);
+    }
+    if (tiled && wide) {
+      if (bf) hipLaunchKernelGGL((gconv_tile_kernel<__bf16, 128>), dim3(grid * 4), dim3(256), 0, s, a, l);
+      else hipLaunchKernelGGL((gconv_tile_kernel<float, 128>), dim3(grid * 4), dim3(256), 0, s, a, l);
+    } else if (tiled) {
+      if (bf) hipLaunchKernelGGL((gconv_tile_kernel<__bf16, 64>), dim3(grid * 4), dim3(256), 0, s, a, l);
+      else hipLaunchKernelGGL((gconv_tile_kernel<float, 64>), dim3(grid * 4), dim3(256), 0, s, a, l);
+    } else {
+      if (bf) hipLaunchKernelGGL(gconv_layer_kernel<__bf16>, dim3(grid * 4), dim3(256), 0, s, a, l);
+      else hipLaunchKernelGGL(gconv_layer_kernel<float>, dim3(grid * 4), dim3(256), 0, s, a, l);
+    }
   }
   if (bf) hipLaunchKernelGGL(gcnn_head_kernel<__bf16>, dim3(grid), dim3(256), 0, s, a, f);
   else hipLaunchKernelGGL(gcnn_head_kernel<float>, dim3(grid), dim3(256), 0, s, a, f);
