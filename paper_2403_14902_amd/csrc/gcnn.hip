@@ -326,6 +326,114 @@ __global__ __launch_bounds__(256) void gconv_tile_kernel(GcnnArgs a, int layer) 
   }
 }
 
+// First layer (Cin = 3, K = 27) when 128 output positions are whole output rows of one frame
+// (hout divides 128, P a multiple of 128) and Cout <= 64: a tile stages the 2*(128/hout) + 1
+// input rows it reads (raw values, top border = the pad value) in LDS once, builds the im2col
+// fragments from there and writes 128 positions x Cout channels.
+__host__ __device__ inline bool gconv_first_ok(int hout, int cout) {
+  return hout >= 16 && 128 % hout == 0 && cout % 16 == 0 && cout <= 64;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gconv_first_kernel(GcnnArgs a) {
+  typedef typename GMf<T>::frag frag;
+  constexpr int KSTEP = GMf<T>::KSTEP, KPL = GMf<T>::KPL, KS = (27 + KSTEP - 1) / KSTEP;
+  constexpr int MAXV = 17 * 33 * 3 > 5 * 129 * 3 ? (17 * 33 * 3 > 3 * 257 * 3 ? 17 * 33 * 3 : 3 * 257 * 3) : 5 * 129 * 3;
+  __shared__ float xin[MAXV + 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int hout = a.in_hw[i] >> 1;
+    total += (int)((int64_t)a.q.counts[a.pred[i]] * hout * hout / 128);
+  }
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int slot = 0, off = t, ebase = 0;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int hout = a.in_hw[i] >> 1;
+      const int c = (int)((int64_t)a.q.counts[a.pred[i]] * hout * hout / 128);
+      if (off < c) { slot = i; break; }
+      off -= c;
+      ebase += a.q.counts[a.pred[i]];
+    }
+    const int hin = a.in_hw[slot], hout = hin >> 1, P = hout * hout;
+    const int cout = a.widths[slot][0], nct = cout / 16;
+    const int tiles_per_frame = P / 128, rows_out = 128 / hout, rows_in = 2 * rows_out + 1, W = hin + 1;
+    const int e = off / tiles_per_frame, oi0 = (off % tiles_per_frame) * rows_out;
+    const uint32_t idx = entry_idx(a.q.entries[(int64_t)a.pred[slot] * a.q.cap + e]);
+    // stage input rows y = 2*oi0 - 1 + r, columns x = c - 1 (c = 0 is the left border)
+    const int nvals = rows_in * W * 3;
+    for (int q = tid; q < nvals; q += 256) {
+      const int r = q / (W * 3), rem = q % (W * 3), c = rem / 3, ch = rem % 3;
+      const int y = 2 * oi0 - 1 + r, x = c - 1;
+      float v = a.pad_raw;
+      if (y >= 0 && x >= 0) {
+        const int64_t o = (int64_t)idx * a.fr.elems + ((int64_t)y * hin + x) * 3 + ch;
+        v = a.fr.dtype == HYDRO_DTYPE_BF16 ? (float)static_cast<const __bf16*>(a.fr.base)[o]
+                                          : (float)static_cast<const uint8_t*>(a.fr.base)[o];
+      }
+      xin[q] = v;
+    }
+    __syncthreads();
+    const frag* wp = reinterpret_cast<const frag*>(sizeof(T) == 2 ? (const void*)a.w_bf[slot][0]
+                                                                  : (const void*)a.w_f32[slot][0]);
+    floatx4 acc[4][2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[c][q] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      frag xf[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int pl = wave * 32 + q * 16 + l16, oi = pl / hout, oj = pl % hout;
+        const float* base = xin + ((2 * oi) * W + 2 * oj) * 3;
+        if constexpr (sizeof(T) == 2) {
+          alignas(16) __bf16 t8[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int k = ks * KSTEP + KPL * g + j, tap = k / 3, ch = k % 3;
+            t8[j] = static_cast<__bf16>(k < 27 ? base[((tap / 3) * W + tap % 3) * 3 + ch] : 0.f);
+          }
+          xf[q] = *reinterpret_cast<const bf16x8*>(t8);
+        } else {
+          const int k = ks * KSTEP + g, tap = k / 3, ch = k % 3;
+          xf[q] = k < 27 ? base[((tap / 3) * W + tap % 3) * 3 + ch] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c >= nct) continue;
+        const frag wf = wp[((int64_t)ks * nct + c) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[c][q] = gmfma(wf, xf[q], acc[c][q]);
+      }
+    }
+    const float* bias = a.bias[slot][0];
+    T* o0 = reinterpret_cast<T*>(a.act[0]) + ((int64_t)ebase + e) * a.act_stride + (int64_t)oi0 * hout * cout;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int pl = wave * 32 + q * 16 + l16;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c >= nct) continue;
+        const int ch = c * 16 + 4 * g;
+        const float v0 = fmaxf(acc[c][q][0] + bias[ch], 0.f), v1 = fmaxf(acc[c][q][1] + bias[ch + 1], 0.f);
+        const float v2 = fmaxf(acc[c][q][2] + bias[ch + 2], 0.f), v3 = fmaxf(acc[c][q][3] + bias[ch + 3], 0.f);
+        T* o = o0 + (int64_t)pl * cout + ch;
+        if constexpr (sizeof(T) == 2) {
+          alignas(8) __bf16 h[4] = {static_cast<__bf16>(v0), static_cast<__bf16>(v1), static_cast<__bf16>(v2),
+                                    static_cast<__bf16>(v3)};
+          *reinterpret_cast<uint2*>(o) = *reinterpret_cast<const uint2*>(h);
+        } else {
+          *reinterpret_cast<float4*>(o) = make_float4(v0, v1, v2, v3);
+        }
+      }
+    }
+    __syncthreads();   // the next tile restages xin
+  }
+}
+
 // Pool + FC + margin + decision: one wave per frame.
 template <typename T>
 __global__ __launch_bounds__(256) void gcnn_head_kernel(GcnnArgs a, Forward f) {
@@ -598,6 +706,15 @@ void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, h
   const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;
   for (int l = 0; l < maxl; ++l) {
     // the tiled kernel when every slot that has this layer fits its shape constraints
+    if (l == 0) {
+      bool first_ok = true;
+      for (int i = 0; i < a.n_preds; ++i) first_ok = first_ok && gconv_first_ok(a.in_hw[i] >> 1, a.widths[i][0]);
+      if (first_ok) {
+        if (bf) hipLaunchKernelGGL(gconv_first_kernel<__bf16>, dim3(grid * 4), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(gconv_first_kernel<float>, dim3(grid * 4), dim3(256), 0, s, a);
+        continue;
+      }
+    }
     bool tiled = true, wide = true;
     for (int i = 0; i < a.n_preds; ++i) {
       if (l >= a.n_layers[i]) continue;
