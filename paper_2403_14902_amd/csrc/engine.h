@@ -100,6 +100,7 @@ size_t gcnn_packed_elems(int layer, int cin, int cout, int prec);
 void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, float scale, float* out);
 
 constexpr int MLP_TILE_CONFIGS = 4;
+int mlp_f64_chunks(int d_in);    // input chunks of the FP64 MLP hidden pass
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s);
 int mlp_tile_bn(int cfg);

@@ -499,7 +499,7 @@ static int pack_models(hydro_session* s) {
         ma.part_w[i] = mlp_tile_bn(cfg) / 2;
       }
       {
-        const int nch = (D + 1535) / 1536;   // chunking of the FP64 tier's hidden pass
+        const int nch = mlp_f64_chunks(D);   // chunking of the FP64 tier's hidden pass
         if ((rc = sess_alloc(s, (void**)&ma.esc_h[i], (size_t)nch * esc_cap * H * sizeof(double)))) return rc;
       }
     } else if (hm.variant == CNN_NONE) {

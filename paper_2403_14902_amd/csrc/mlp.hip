@@ -132,8 +132,8 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
       for (int j = 0; j < FN; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
 
     // NS register stages: the global loads of k-tile kt + NS - 1 are issued while tile kt is
-    // computed, so NS - 1 tiles are in flight per thread (the gathered frame rows come from HBM).
-    constexpr int NS = 4;
+    // computed (two stages measured fastest: deeper staging costs more than it hides here).
+    constexpr int NS = 2;
     alignas(16) T ra[NS][PER];
     alignas(16) T rb[NS][PER];
     auto gload = [&](int kt, int st) {
@@ -331,11 +331,12 @@ __global__ __launch_bounds__(256) void mlp_head_kernel(MlpArgs a, Forward f) {
 
 // FP64 tier: frames normalised in fp64 exactly as defined; canonical fp32 weights widened to
 // fp64.  The first esc_cap escalated entries of each predicate are evaluated across many
-// workgroups: work item = (predicate, group of 8 entries, 256 hidden units, 1536-long chunk of
+// workgroups: work item = (predicate, group of 8 entries, 256 hidden units, 256-long chunk of
 // the input) -> partial hidden sums; a head (one wave per entry) adds the chunks, applies
 // ReLU, GEMM2, the margin and the decision.  Entries beyond esc_cap run one group per block.
 constexpr int F64_B = 8;
-constexpr int F64_DCH = 1536;
+constexpr int F64_DCH = 256;
+int mlp_f64_chunks(int d_in) { return (d_in + F64_DCH - 1) / F64_DCH; }
 
 __device__ inline double frame_norm64_flat(const FrameSrc& fr, uint32_t idx, int64_t d) {
   const int64_t o = (int64_t)idx * fr.elems + d;
@@ -390,6 +391,7 @@ __global__ __launch_bounds__(256) void mlp_f64_hidden_kernel(MlpArgs a) {
       }
       __syncthreads();
       if (j < H) {
+#pragma unroll 16
         for (int dd = 0; dd < dl; ++dd) {
           const double w = (double)W1[(int64_t)(d0 + dd) * H + j];
 #pragma unroll
