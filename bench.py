@@ -3,15 +3,18 @@
 Workload (default): 65,536 synthetic frames 64x64x3 bf16, three CNN predicates of widths
 (16m, 32m, 64m), m = 1, 2, 4, class-subset thresholds that drift over 8 segments of 8,192
 tuples.  Frames are resident in HBM before timing starts; models are uploaded at session
-creation (setup, not timed).
+creation (setup, not timed).  --workload 1..5 selects the other synthetic workloads (the
+1,048,576-frame uint8 one as a 131,072-frame prefix unless --n is given); those add a form
+pushed from pinned host memory when the workload streams from the host.
 
 A step is one whole query: reset, push every tuple (route, multi-split, evaluate, forward
 survivors, materialise the sorted ids) and copy ids and statistics to the host.
 
 Forms:
   full   learned content-based router (score routing as control arm, judge and fallback) +
-         grouped persistent launches per round + first pass in BF16 on MFMA (fp32 accumulate)
-         with margins within tau re-scored in FP32 and within tau32 in FP64.  `value`.
+         grouped persistent launches per round (MLP tile shapes from the autotuner, timed at
+         setup) + first pass in BF16 on MFMA (fp32 accumulate) with margins within tau
+         re-scored in FP32 and within tau32 in FP64.  `value`.
   score  as full, but score-driven routing only.
   plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate.
   The timed runs record HIP events around each round's phases (for the roofline); the same
@@ -36,6 +39,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs plain; MFMA util"
+# HBM bytes per first-pass round (reads + writes), from FETCH_SIZE / WRITE_SIZE runs of this script
+# scaled by the same counters on a 1 GiB device copy (the byte-counter summary in profiles/).  Valid
+# only for the kernel build those runs measured: None for a workload without such a run.
+FIRST_PASS_TRAFFIC = {"cnn3_drift64": 406.53e6 + 0.22e6}
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 
@@ -62,6 +69,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--check-sample", type=int, default=2048)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB: first copy a device buffer of this size three times (a plain copy kernel "
+                         "of known traffic, to scale hardware byte counters)")
     ap.add_argument("--errors", type=int, default=4096,
                     help="frames on which bf16 / fp32 logits and margins are compared with fp64 (0: skip)")
     return ap.parse_args()
@@ -115,6 +125,13 @@ def main():
 
     torch.cuda.set_device(0)
     hydro.lib()
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = hs.workload(args.workload)
     n = args.n if args.n > 0 else (131072 if cfg.index == 5 else cfg.n)
     n = min(n, cfg.n)
@@ -139,7 +156,8 @@ def main():
         kernel_label = "cnn_fused_kernel<bf16, *> (first pass: one launch per width class)"
     else:
         kernel_label = "gconv_layer_kernel<bf16> per layer + gcnn_head_kernel (first pass, grouped)"
-    full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
+    full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, time_kernels=1,
+                                 **extra)
     log(f"[bench] full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
                                          args.steps, args.warmup, n, cal, args.safety)
@@ -182,7 +200,7 @@ def main():
             "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS,
-            "traffic": None,
+            "traffic": FIRST_PASS_TRAFFIC.get(cfg.name) if n == cfg.n else None,
             "flops_per_launch": first_flops / max(1, launches),
             "avg_launch_ms": first_ms / max(1, launches),
         },
@@ -209,7 +227,8 @@ def main():
     out["udf_gflop_per_step"] = total_udf / 1e9
 
     # the same form replayed from a captured HIP graph (no events)
-    gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, use_graph=1, **extra)
+    gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, use_graph=1,
+                             **extra)
     ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, args.steps,
                                 args.warmup, n, cal, args.safety)
     assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
@@ -217,7 +236,8 @@ def main():
 
     if args.route != "score":
         log("[bench] score form")
-        spol = hydro.make_policy("score", precision="bf16", wave=args.wave, grouped=1, time_kernels=1, **extra)
+        spol = hydro.make_policy("score", precision="bf16", wave=args.wave, grouped=1, autotune=1, time_kernels=1,
+                                 **extra)
         ids_s, st_s, inf_s, dts = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, spol,
                                            args.steps, args.warmup, n, cal, args.safety)
         assert np.array_equal(ids_s, ids), "score and learned routing disagree"
@@ -230,7 +250,7 @@ def main():
         blk = cfg.push_batch if cfg.push_batch > 0 else 16384
         log(f"[bench] full form pushed from pinned host memory in blocks of {blk}")
         frames_host = torch.from_numpy(frames).pin_memory()
-        hpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, **extra)
+        hpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, **extra)
         ids_h, _, _, dth = run_form(hydro, torch, specs, frames_host, cfg.dtype, pt, seg_len, hpol,
                                     max(1, args.steps // 2), 1, n, cal, args.safety, push_batch=blk)
         assert np.array_equal(ids_h, ids), "host-pushed and device-resident runs disagree"
