@@ -225,8 +225,9 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
  * predicate's first-pass and FP32 margins are compared with its FP64 margins; tau_k and tau32_k
  * become `safety` (>= 1) times the largest difference seen (floors 1e-4 and 1e-6).  Later pushes
  * use these bands instead of policy.tau / policy.tau32.  out_tau / out_tau32: caller-allocated
- * [K] (may be NULL).  This is the per-configuration band of the low-precision form: an empirical
- * bound, so the sample should be representative of the query's frames. */
+ * [K] (may be NULL).  Any number of frames (>= 1); more than the session's max_push are taken
+ * in blocks of max_push.  This is the per-configuration band of the low-precision form: an
+ * empirical bound, so the sample should be representative of the query's frames. */
 int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float safety, float* out_tau,
                             float* out_tau32);
 

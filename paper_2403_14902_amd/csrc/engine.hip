@@ -1500,20 +1500,30 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
   if (!s || !frames) return fail(HYDRO_EINVAL, "NULL argument");
   if (!(safety >= 1.f)) return fail(HYDRO_EINVAL, "safety must be at least 1");
   const int64_t n = frames->n;
-  std::vector<double> z0((size_t)n * kClasses), z1((size_t)n * kClasses), z2((size_t)n * kClasses);
+  if (n < 1) return fail(HYDRO_EINVAL, "calibration needs at least one frame");
+  // frames beyond the session's push capacity are taken in blocks of that size
+  const int64_t blk = std::min<int64_t>(n, s->cap);
+  const int esize = frames->dtype == HYDRO_DTYPE_F32 ? 4 : frames->dtype == HYDRO_DTYPE_BF16 ? 2 : 1;
+  const int64_t fbytes = (int64_t)frames->h * frames->w * 3 * esize;
+  std::vector<double> z0((size_t)blk * kClasses), z1((size_t)blk * kClasses), z2((size_t)blk * kClasses);
   float tau[kMaxK], tau32[kMaxK];
   for (int k = 0; k < s->K; ++k) {
-    int rc;
-    if ((rc = hydro_session_logits(s, k, 0, frames, z0.data()))) return rc;
-    if ((rc = hydro_session_logits(s, k, 1, frames, z1.data()))) return rc;
-    if ((rc = hydro_session_logits(s, k, 2, frames, z2.data()))) return rc;
     const uint32_t mask = s->models[k].m.class_mask;
     double e0 = 0, e1 = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      const double d2 = host_margin(&z2[i * kClasses], mask);
-      if (!std::isfinite(d2)) continue;
-      e0 = std::max(e0, std::fabs(host_margin(&z0[i * kClasses], mask) - d2));
-      e1 = std::max(e1, std::fabs(host_margin(&z1[i * kClasses], mask) - d2));
+    for (int64_t i0 = 0; i0 < n; i0 += blk) {
+      hydro_frames sub = *frames;
+      sub.data = static_cast<const char*>(frames->data) + i0 * fbytes;
+      sub.n = std::min(blk, n - i0);
+      int rc;
+      if ((rc = hydro_session_logits(s, k, 0, &sub, z0.data()))) return rc;
+      if ((rc = hydro_session_logits(s, k, 1, &sub, z1.data()))) return rc;
+      if ((rc = hydro_session_logits(s, k, 2, &sub, z2.data()))) return rc;
+      for (int64_t i = 0; i < sub.n; ++i) {
+        const double d2 = host_margin(&z2[i * kClasses], mask);
+        if (!std::isfinite(d2)) continue;
+        e0 = std::max(e0, std::fabs(host_margin(&z0[i * kClasses], mask) - d2));
+        e1 = std::max(e1, std::fabs(host_margin(&z1[i * kClasses], mask) - d2));
+      }
     }
     // floors keep a band even when the sample shows (almost) no error
     tau[k] = (float)std::max(safety * e0, 1e-4);

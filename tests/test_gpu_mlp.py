@@ -184,3 +184,23 @@ def test_mlp_autotuned_session(c1, tmp_path, monkeypatch):
     import json
     d = json.loads((tmp_path / "tune.json").read_text())
     assert any(k.startswith("gfx950/bf16/f32/D3072/h256") for k in d)
+
+
+def test_calibration_in_blocks_of_max_push(c1):
+    """Calibrating on more frames than a session's push capacity takes them in blocks: the bands
+    equal those of a session that holds every frame in one block, and the query stays exact."""
+    dev = c1.device_frames()
+    pol = hydro.make_policy("score", precision="bf16")
+    big = _session(c1, pol)
+    t_big, t32_big = big.calibrate(dev[:1500], c1.cfg.dtype, 2.0)
+    big.close()
+    small = _session(c1, pol, max_push=512)
+    t_small, t32_small = small.calibrate(dev[:1500], c1.cfg.dtype, 2.0)
+    log(f"[gpu] blocked calibration tau={t_small.tolist()} tau32={t32_small.tolist()}")
+    assert np.array_equal(t_big, t_small) and np.array_equal(t32_big, t32_small)
+    for lo in range(0, c1.n, 512):
+        small.push(dev[lo:lo + 512], c1.cfg.dtype, c1.pt.thresholds, c1.seg_len, id_base=lo)
+    ids, stats = small.finish()
+    assert np.array_equal(ids, c1.expect)
+    check_stats(stats, c1.n, ids.size)
+    small.close()
