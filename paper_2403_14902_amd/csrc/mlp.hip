@@ -14,43 +14,25 @@ template <typename T> struct MlpTile;
 template <> struct MlpTile<__bf16> { static constexpr int BK = 32, LD = 40; };   // LDS row stride (elements)
 template <> struct MlpTile<float> { static constexpr int BK = 16, LD = 20; };
 
-// Load `N` consecutive frame elements starting at element `off` of frame `idx`, converted to T.
-template <typename T, int N>
+// Load `N` consecutive frame elements of type In starting at element `off` of frame `idx`,
+// converted to T.  The element type is a template parameter, so the loads are straight-line code
+// and the compiler can count the ones in flight precisely.
+template <typename T, typename In, int N>
 __device__ inline void load_frame_run(const FrameSrc& fr, uint32_t idx, int64_t off, T* out) {
-  const int64_t base = (int64_t)idx * fr.elems + off;
-  if (fr.dtype == HYDRO_DTYPE_BF16) {
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const __bf16*>(fr.base) + base);
+  constexpr int BYTES = N * (int)sizeof(In);
+  static_assert(BYTES == 4 || BYTES == 8 || BYTES % 16 == 0, "frame run size");
+  const In* p = static_cast<const In*>(fr.base) + (int64_t)idx * fr.elems + off;
+  alignas(16) In buf[N];
+  if constexpr (BYTES % 16 == 0) {
 #pragma unroll
-    for (int v = 0; v < N / 8; ++v) {
-      uint4 u = p[v];
-      const __bf16* b = reinterpret_cast<const __bf16*>(&u);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) out[v * 8 + j] = static_cast<T>(b[j]);
-    }
-  } else if (fr.dtype == HYDRO_DTYPE_U8) {
-    const uint8_t* p = static_cast<const uint8_t*>(fr.base) + base;
-    if constexpr (N == 16) {
-      uint4 u = *reinterpret_cast<const uint4*>(p);
-      const uint8_t* b = reinterpret_cast<const uint8_t*>(&u);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) out[j] = static_cast<T>((float)b[j]);
-    } else {
-      uint2 u = *reinterpret_cast<const uint2*>(p);
-      const uint8_t* b = reinterpret_cast<const uint8_t*>(&u);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) out[j] = static_cast<T>((float)b[j]);
-    }
+    for (int v = 0; v < BYTES / 16; ++v) reinterpret_cast<uint4*>(buf)[v] = reinterpret_cast<const uint4*>(p)[v];
+  } else if constexpr (BYTES == 8) {
+    *reinterpret_cast<uint2*>(buf) = *reinterpret_cast<const uint2*>(p);
   } else {
-    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(fr.base) + base);
-#pragma unroll
-    for (int v = 0; v < N / 4; ++v) {
-      float4 f = p[v];
-      out[v * 4 + 0] = static_cast<T>(f.x);
-      out[v * 4 + 1] = static_cast<T>(f.y);
-      out[v * 4 + 2] = static_cast<T>(f.z);
-      out[v * 4 + 3] = static_cast<T>(f.w);
-    }
+    *reinterpret_cast<uint32_t*>(buf) = *reinterpret_cast<const uint32_t*>(p);
   }
+#pragma unroll
+  for (int j = 0; j < N; ++j) out[j] = static_cast<T>((float)buf[j]);
 }
 
 // Split-K: when a launch has fewer (rows x hidden) tiles than split_below (small queues, e.g.
@@ -71,10 +53,12 @@ __device__ inline int mlp_splits(int base_total, int nk_min, const MlpArgs& a) {
 
 // Tile shapes (rows of queued tuples x hidden units) an autotuner may pick per predicate.
 // Every launch covers the predicates of one tile shape.
-template <typename T, int BM, int BN>
+template <typename T, typename In, int BM, int BN>
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
   constexpr int BK = MlpTile<T>::BK, LD = MlpTile<T>::LD;
-  constexpr int PER = BK / 2;                     // elements a thread loads per row and k-tile
+  // every thread loads one run of each k-tile: 256 / BM threads per gathered frame row (PA
+  // elements each) and 256 / BN per weight row (PB elements each)
+  constexpr int TPA = 256 / BM, PA = BK / TPA, TPB = 256 / BN, PB = BK / TPB;
   constexpr int WM = BM / 2, WN = BN / 2;         // 2 x 2 waves
   constexpr int FM = WM / 16, FN = WN / 16;       // MFMA tiles per wave
   __shared__ __attribute__((aligned(16))) T As[2][BM * LD];
@@ -83,8 +67,8 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int lr = tid >> 1, lk = (tid & 1) * PER;  // this thread's load row (< 128) and k offset
-  const bool lda = lr < BM, ldb = lr < BN;
+  const int ar = tid / TPA, ak = (tid % TPA) * PA;   // this thread's frame row in the tile, k offset
+  const int br = tid / TPB, bk = (tid % TPB) * PB;   // this thread's weight row in the tile, k offset
 
   int base_total = 0, nk_min = 1 << 30;
   for (int i = 0; i < a.n_preds; ++i) {
@@ -119,11 +103,11 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
     const uint32_t* qe = a.q.entries + (int64_t)k * a.q.cap;
     unsigned long long t0 = wall_clock64();
 
-    const int row = mt * BM + lr;
+    const int row = mt * BM + ar;
     const uint32_t idx = entry_idx(qe[row < cnt ? row : cnt - 1]);
     const T* wrow;
-    if constexpr (sizeof(T) == 2) wrow = reinterpret_cast<const T*>(a.w1_bf[slot]) + (int64_t)(nt * BN + (ldb ? lr : 0)) * D;
-    else wrow = reinterpret_cast<const T*>(a.w1_f32[slot]) + (int64_t)(nt * BN + (ldb ? lr : 0)) * D;
+    if constexpr (sizeof(T) == 2) wrow = reinterpret_cast<const T*>(a.w1_bf[slot]) + (int64_t)(nt * BN + br) * D;
+    else wrow = reinterpret_cast<const T*>(a.w1_f32[slot]) + (int64_t)(nt * BN + br) * D;
 
     floatx4 acc[FM][FN];
 #pragma unroll
@@ -134,22 +118,21 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(MlpArgs a) {
     // NS register stages: the global loads of k-tile kt + NS - 1 are issued while tile kt is
     // computed (two stages measured fastest: deeper staging costs more than it hides here).
     constexpr int NS = 2;
-    alignas(16) T ra[NS][PER];
-    alignas(16) T rb[NS][PER];
+    alignas(16) T ra[NS][PA];
+    alignas(16) T rb[NS][PB];
     auto gload = [&](int kt, int st) {
-      if (lda) load_frame_run<T, PER>(a.fr, idx, (int64_t)kt * BK + lk, ra[st]);
-      if (ldb) {
-        const uint4* pb = reinterpret_cast<const uint4*>(wrow + (int64_t)kt * BK + lk);
+      load_frame_run<T, In, PA>(a.fr, idx, (int64_t)kt * BK + ak, ra[st]);
+      const uint4* pb = reinterpret_cast<const uint4*>(wrow + (int64_t)kt * BK + bk);
 #pragma unroll
-        for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb[st])[v] = pb[v];
-      }
+      for (int v = 0; v < PB * (int)sizeof(T) / 16; ++v) reinterpret_cast<uint4*>(rb[st])[v] = pb[v];
     };
     auto lstore = [&](int st, int buf) {
 #pragma unroll
-      for (int v = 0; v < PER * (int)sizeof(T) / 16; ++v) {
-        if (lda) reinterpret_cast<uint4*>(&As[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(ra[st])[v];
-        if (ldb) reinterpret_cast<uint4*>(&Bs[buf][lr * LD + lk])[v] = reinterpret_cast<uint4*>(rb[st])[v];
-      }
+      for (int v = 0; v < PA * (int)sizeof(T) / 16; ++v)
+        reinterpret_cast<uint4*>(&As[buf][ar * LD + ak])[v] = reinterpret_cast<uint4*>(ra[st])[v];
+#pragma unroll
+      for (int v = 0; v < PB * (int)sizeof(T) / 16; ++v)
+        reinterpret_cast<uint4*>(&Bs[buf][br * LD + bk])[v] = reinterpret_cast<uint4*>(rb[st])[v];
     };
     auto compute = [&](int buf) {
       if constexpr (sizeof(T) == 2) {
@@ -569,7 +552,12 @@ int mlp_tile_bn(int cfg) { return cfg == 0 || cfg == 1 ? 128 : 64; }
 
 template <typename T, int BM, int BN>
 static void launch_gemm_t(const MlpArgs& b, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((mlp_gemm_kernel<T, BM, BN>), dim3(grid), dim3(256), 0, s, b);
+  if (b.fr.dtype == HYDRO_DTYPE_BF16)
+    hipLaunchKernelGGL((mlp_gemm_kernel<T, __bf16, BM, BN>), dim3(grid), dim3(256), 0, s, b);
+  else if (b.fr.dtype == HYDRO_DTYPE_U8)
+    hipLaunchKernelGGL((mlp_gemm_kernel<T, uint8_t, BM, BN>), dim3(grid), dim3(256), 0, s, b);
+  else
+    hipLaunchKernelGGL((mlp_gemm_kernel<T, float, BM, BN>), dim3(grid), dim3(256), 0, s, b);
 }
 
 void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s) {
