@@ -21,7 +21,8 @@ Forms:
   forms replayed from a captured HIP graph are reported as `graph_value`.
   Every form's session calibrates its per-predicate bands at setup (untimed): tau_k and tau32_k
   are `--safety` (2) times the largest margin error of the first pass / FP32 pass against the
-  FP64 pass on 8,192 separate frames of the same generator (--no-calibrate: fixed defaults).
+  FP64 pass on 8,192 separate frames of the same generator (--no-calibrate: fixed bands 0.015 /
+  1e-5).
 
 Prints one JSON line (the full form's throughput as `value`, the plain form beside it, the
 dominant kernel's roofline from HIP events recorded by the library on its stream, and the FP64
@@ -62,7 +63,7 @@ def parse():
     ap.add_argument("--wave", type=int, default=16384)
     ap.add_argument("--tau", type=float, default=0.0)
     ap.add_argument("--no-calibrate", action="store_true",
-                    help="use the policy's fixed bands instead of bands calibrated on separate frames")
+                    help="fixed bands tau = 0.015, tau32 = 1e-5 instead of bands calibrated on separate frames")
     ap.add_argument("--safety", type=float, default=2.0)
     ap.add_argument("--route", default="learned")
     ap.add_argument("--no-plain", action="store_true")
@@ -147,6 +148,8 @@ def main():
     cal = None if args.no_calibrate else torch.from_numpy(hs.calibration_frames(cfg)).cuda()
 
     extra = {}
+    if args.no_calibrate:
+        extra.update(tau=0.015, tau32=1e-5)      # the fixed bands
     if args.tau > 0:
         extra["tau"] = args.tau
     d0 = cfg.models[0]
@@ -261,7 +264,7 @@ def main():
 
     if not args.no_plain:
         log("[bench] plain form")
-        plain_pol = hydro.make_policy("score", precision="fp32", wave=args.wave, grouped=0, time_kernels=0)
+        plain_pol = hydro.make_policy("score", precision="fp32", wave=args.wave, grouped=0, time_kernels=0, **extra)
         ids_p, _, _, dtp = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, plain_pol,
                                     max(1, args.steps // 2), 1, n, cal, args.safety)
         assert np.array_equal(ids_p, ids), "plain and full forms disagree"

@@ -123,9 +123,12 @@ typedef struct {
                                             STATIC: the model's FLOPs (deterministic routes)     */
   int32_t precision;                     /* first-pass arithmetic; see tau                       */
   float tau;                             /* BF16 first pass: |d - theta| < tau is re-scored in
-                                            FP32 (<= 0: default 0.015)                           */
-  float tau32;                           /* FP32 pass: |d - theta| < tau32 is re-scored in FP64
-                                            (<= 0: default 1e-5)                                 */
+                                            FP32.  <= 0 (default): automatic, see below          */
+  float tau32;                           /* FP32 pass: |d - theta| < tau32 is re-scored in FP64.
+                                            <= 0 (default): automatic.  Automatic bands are
+                                            measured on the session's first push (up to 1,024 of
+                                            its frames, as hydro_session_calibrate with safety 3)
+                                            and never set below 0.015 / 1e-5                     */
   int32_t grouped;                       /* 1: one persistent launch per round and tier for all
                                             predicates (default 1)                               */
   int32_t use_graph;                     /* 1: replay the round sequence from a HIP graph        */

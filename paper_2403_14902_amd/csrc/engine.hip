@@ -302,6 +302,9 @@ struct GraphKey {
   }
 };
 
+constexpr float kAutoTauFloor = 0.015f;     // automatic bands never go below these
+constexpr float kAutoTau32Floor = 1e-5f;
+
 struct hydro_session {
   int device = 0;
   int n_cu = 256;
@@ -347,6 +350,7 @@ struct hydro_session {
   int ev_used = 0;
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // use_graph: captured pushes
   float tau_k[kMaxK], tau32_k[kMaxK];   // per-predicate bands (policy values or calibrated)
+  bool auto_tau = false, auto_tau32 = false;   // bands still to be measured on the first push
 };
 
 static hipEvent_t next_event(hydro_session* s) {
@@ -711,8 +715,8 @@ void hydro_policy_default(hydro_policy* p) {
   p->ewma_alpha = 0.5f;
   p->cost_source = HYDRO_COST_MEASURED;
   p->precision = HYDRO_PREC_BF16;
-  p->tau = 0.015f;
-  p->tau32 = 1e-5f;
+  p->tau = 0.f;      // automatic: calibrated on the first push
+  p->tau32 = 0.f;
   p->grouped = 1;
   p->use_graph = 0;
   p->log_routes = 0;
@@ -761,8 +765,10 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   g_alloc_counter = 0;
   hydro_session* s = new hydro_session();
   s->pol = *policy;
-  if (s->pol.tau <= 0.f) s->pol.tau = 0.015f;
-  if (s->pol.tau32 <= 0.f) s->pol.tau32 = 1e-5f;
+  s->auto_tau = s->pol.tau <= 0.f;
+  s->auto_tau32 = s->pol.tau32 <= 0.f;
+  if (s->auto_tau) s->pol.tau = kAutoTauFloor;
+  if (s->auto_tau32) s->pol.tau32 = kAutoTau32Floor;
   for (int i = 0; i < kMaxK; ++i) {
     s->tau_k[i] = s->pol.tau;
     s->tau32_k[i] = s->pol.tau32;
@@ -1146,6 +1152,39 @@ static int ensure_dtype(hydro_session* s, int dtype) {
 
 static size_t dtype_size(int dt) { return dt == HYDRO_DTYPE_F32 ? 4 : dt == HYDRO_DTYPE_BF16 ? 2 : 1; }
 
+static int measure_bands(hydro_session* s, const hydro_frames* frames, float safety, float* tau, float* tau32);
+
+// Automatic bands (policy tau / tau32 <= 0): measured once, on up to 1,024 frames of the
+// session's first push, with safety 3, and never below the fixed defaults.
+static int auto_bands(hydro_session* s, const hydro_frames& fr) {
+  hydro_frames sub = fr;
+  sub.n = std::min<int64_t>(fr.n, 1024);
+  void* tmp = nullptr;
+  if (fr.where != HYDRO_MEM_DEVICE) {
+    const size_t bytes = (size_t)sub.n * fr.h * fr.w * 3 * dtype_size(fr.dtype);
+    hipError_t e = dev_alloc(&tmp, bytes);
+    if (e != hipSuccess) return fail(HYDRO_ENOMEM, "band calibration frame buffer");
+    e = hipMemcpy(tmp, fr.data, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      hipFree(tmp);
+      return fail(HYDRO_EDEVICE, std::string("band calibration copy: ") + hipGetErrorString(e));
+    }
+    sub.data = tmp;
+    sub.where = HYDRO_MEM_DEVICE;
+  }
+  float tau[kMaxK], tau32[kMaxK];
+  const int rc = measure_bands(s, &sub, 3.0f, tau, tau32);
+  if (tmp) hipFree(tmp);
+  if (rc) return rc;
+  const bool bf = s->pol.precision == HYDRO_PREC_BF16;
+  for (int k = 0; k < s->K; ++k) {
+    if (s->auto_tau) s->tau_k[k] = bf ? std::max(tau[k], kAutoTauFloor) : std::max(tau32[k], kAutoTau32Floor);
+    if (s->auto_tau32) s->tau32_k[k] = std::max(tau32[k], kAutoTau32Floor);
+  }
+  s->auto_tau = s->auto_tau32 = false;
+  return HYDRO_OK;
+}
+
 int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float* thresholds, int32_t n_seg,
                        int64_t seg_len) {
   g_err.clear();
@@ -1165,6 +1204,8 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   if (rc) return rc;
   for (int64_t i = 0; i < (int64_t)n_seg * s->K; ++i)
     if (std::isnan(thresholds[i])) return fail(HYDRO_EINVAL, "threshold is NaN");
+  if ((s->auto_tau || s->auto_tau32) && fr.n > 0 && s->pushes == 0)
+    if ((rc = auto_bands(s, fr))) return rc;
 
   if (s->pushes == 0) s->t_start = std::chrono::steady_clock::now();
   s->pushes++;
@@ -1494,11 +1535,9 @@ static double host_margin(const double* z, uint32_t mask) {
   return in - out;
 }
 
-int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float safety, float* out_tau,
-                            float* out_tau32) {
-  g_err.clear();
-  if (!s || !frames) return fail(HYDRO_EINVAL, "NULL argument");
-  if (!(safety >= 1.f)) return fail(HYDRO_EINVAL, "safety must be at least 1");
+// Largest first-pass and FP32 margin errors against the FP64 tier on `frames` (device memory),
+// times `safety`, floored at 1e-4 / 1e-6.
+static int measure_bands(hydro_session* s, const hydro_frames* frames, float safety, float* tau, float* tau32) {
   const int64_t n = frames->n;
   if (n < 1) return fail(HYDRO_EINVAL, "calibration needs at least one frame");
   // frames beyond the session's push capacity are taken in blocks of that size
@@ -1506,7 +1545,6 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
   const int esize = frames->dtype == HYDRO_DTYPE_F32 ? 4 : frames->dtype == HYDRO_DTYPE_BF16 ? 2 : 1;
   const int64_t fbytes = (int64_t)frames->h * frames->w * 3 * esize;
   std::vector<double> z0((size_t)blk * kClasses), z1((size_t)blk * kClasses), z2((size_t)blk * kClasses);
-  float tau[kMaxK], tau32[kMaxK];
   for (int k = 0; k < s->K; ++k) {
     const uint32_t mask = s->models[k].m.class_mask;
     double e0 = 0, e1 = 0;
@@ -1529,12 +1567,24 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
     tau[k] = (float)std::max(safety * e0, 1e-4);
     tau32[k] = (float)std::max(safety * e1, 1e-6);
   }
+  return HYDRO_OK;
+}
+
+int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float safety, float* out_tau,
+                            float* out_tau32) {
+  g_err.clear();
+  if (!s || !frames) return fail(HYDRO_EINVAL, "NULL argument");
+  if (!(safety >= 1.f)) return fail(HYDRO_EINVAL, "safety must be at least 1");
+  float tau[kMaxK], tau32[kMaxK];
+  int rc = measure_bands(s, frames, safety, tau, tau32);
+  if (rc) return rc;
   for (int k = 0; k < s->K; ++k) {
     s->tau_k[k] = s->pol.precision == HYDRO_PREC_BF16 ? tau[k] : tau32[k];
     s->tau32_k[k] = tau32[k];
     if (out_tau) out_tau[k] = s->tau_k[k];
     if (out_tau32) out_tau32[k] = tau32[k];
   }
+  s->auto_tau = s->auto_tau32 = false;
   return HYDRO_OK;
 }
 

@@ -204,3 +204,26 @@ def test_calibration_in_blocks_of_max_push(c1):
     assert np.array_equal(ids, c1.expect)
     check_stats(stats, c1.n, ids.size)
     small.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_mlp_split_k_forced(c1, monkeypatch, prec):
+    """Every GEMM launch split along K (the last part of each tile adds the parts in order): the
+    ids stay exact and the logits match the unsplit ones to rounding."""
+    pol = hydro.make_policy("score", precision=prec, wave=512)
+    dev = c1.device_frames()
+    monkeypatch.setenv("HYDRO_SPLITK_BELOW", "0")          # never split
+    s0 = _session(c1, pol)
+    z0 = s0.logits(0, 0, dev[:700], c1.cfg.dtype)
+    s0.close()
+    monkeypatch.setenv("HYDRO_SPLITK_BELOW", "1000000")
+    s = _session(c1, pol)
+    z1 = s.logits(0, 0, dev[:700], c1.cfg.dtype)
+    log(f"[gpu] split-K {prec}: max logit change {np.abs(z1 - z0).max():.3g}")
+    # only the fp32 summation order differs (3,072-term dot products)
+    assert np.allclose(z1, z0, rtol=0, atol=1e-3 if prec == "bf16" else 2e-4)
+    s.push(dev, c1.cfg.dtype, c1.pt.thresholds, c1.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c1.expect)
+    check_stats(stats, c1.n, ids.size)
+    s.close()
