@@ -48,7 +48,7 @@ __device__ inline typename Mf<T>::frag ld_frag(const T* p) {
 
 // geometry
 constexpr int H0 = 64, H1 = 32, H2 = 16, H3 = 8;
-constexpr int NTHR = 512;           // 8 wave64s per workgroup
+constexpr int NTHR = 512;           // 8 wave64s per workgroup (the narrowest class: 4, two per CU)
 constexpr int FRS = 200;            // FR row stride (bf16 elements): 5 unused, border pixel, 64 pixels
 constexpr int FR_X0 = 8;            // element offset of pixel 0 in an FR row (16-byte aligned)
 constexpr int S1_W = H1 + 1;        // layer-1 slab row stride in pixels (top/left border)
@@ -62,15 +62,17 @@ template <typename T> struct Pad {
   static constexpr int L2E = 16 / (int)sizeof(T);      // extra elements per layer-2 pixel
 };
 
-template <typename T> struct CnnLds {
+template <typename T, int MMAX = 4> struct CnnLds {
   static constexpr int FR_BYTES = (H0 + 1) * FRS * 2;
   static constexpr int S1_OFF = (FR_BYTES + 15) / 16 * 16;
   static constexpr int S1_BYTES = S1_W * S1_W * Pad<T>::S1P * (int)sizeof(T);
-  static constexpr int L2_BYTES_MAX = L2_W * L2_W * (128 + Pad<T>::L2E) * (int)sizeof(T);
+  static constexpr int L2_BYTES_MAX = L2_W * L2_W * (32 * MMAX + Pad<T>::L2E) * (int)sizeof(T);
   static constexpr int REGION = (S1_OFF + S1_BYTES) > L2_BYTES_MAX ? (S1_OFF + S1_BYTES) : L2_BYTES_MAX;
 };
 
 constexpr int DBUF = 64;
+// First pass, the two narrower classes: workgroups of four waves (with the LDS of their own
+// width), two per CU, so one frame's barriers and per-frame work overlap another frame's MFMAs.
 
 // packed-layer geometry: [slab][kstep][ntile][64][KPL]
 // layer 1: K = 27 in (row u, column v, channel c) order, k = 9u + 3v + c, padded to KSTEP
@@ -122,38 +124,41 @@ __device__ void flush_decisions(const Forward& f, CnnShared& sh, int n_slots, co
 
 // Raw frame bytes held in registers between the issue of their loads and their LDS store
 // (the next frame is fetched while the current one is in layer 3).
+template <int NT>
 struct FramePrefetch {
-  uint4 v[3];
+  uint4 v[1536 / NT];
 };
 
-__device__ inline void frame_issue(const CnnArgs& a, uint32_t idx, FramePrefetch& pf) {
+template <int NT>
+__device__ inline void frame_issue(const CnnArgs& a, uint32_t idx, FramePrefetch<NT>& pf) {
   const int tid = threadIdx.x;
   if (a.fr.dtype == HYDRO_DTYPE_BF16) {
     const uint4* src = reinterpret_cast<const uint4*>(static_cast<const __bf16*>(a.fr.base) + (int64_t)idx * a.fr.elems);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) pf.v[r] = src[tid + r * NTHR];      // 1536 chunks of 8 elements
+    for (int r = 0; r < 1536 / NT; ++r) pf.v[r] = src[tid + r * NT];   // 1536 chunks of 8 elements
   } else {
     const uint4* src = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(a.fr.base) + (int64_t)idx * a.fr.elems);
-    pf.v[0] = src[tid];                                              // 768 chunks of 16 elements
-    if (tid + NTHR < 768) pf.v[1] = src[tid + NTHR];
+#pragma unroll
+    for (int r = 0; r < (768 + NT - 1) / NT; ++r)                     // 768 chunks of 16 elements
+      if (tid + r * NT < 768) pf.v[r] = src[tid + r * NT];
   }
 }
 
 // Store a prefetched frame into FR and (re)write the borders of FR and the layer-1 slab.
-template <typename T>
-__device__ inline void frame_store(const CnnArgs& a, const FramePrefetch& pf, unsigned char* region) {
+template <typename T, int NT>
+__device__ inline void frame_store(const CnnArgs& a, const FramePrefetch<NT>& pf, unsigned char* region) {
   const int tid = threadIdx.x;
   __bf16* FR = reinterpret_cast<__bf16*>(region);
   if (a.fr.dtype == HYDRO_DTYPE_BF16) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int q = tid + r * NTHR, y = q / 24, c = q % 24;
+    for (int r = 0; r < 1536 / NT; ++r) {
+      const int q = tid + r * NT, y = q / 24, c = q % 24;
       *reinterpret_cast<uint4*>(FR + (y + 1) * FRS + FR_X0 + c * 8) = pf.v[r];
     }
   } else {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int q = tid + r * NTHR;
+    for (int r = 0; r < (768 + NT - 1) / NT; ++r) {
+      const int q = tid + r * NT;
       if (q < 768) {
         const int y = q / 12, c = q % 12;
         const uint8_t* b = reinterpret_cast<const uint8_t*>(&pf.v[r]);
@@ -167,10 +172,10 @@ __device__ inline void frame_store(const CnnArgs& a, const FramePrefetch& pf, un
     }
   }
   const __bf16 padv = static_cast<__bf16>(a.pad_raw);
-  for (int e = tid; e < FRS; e += NTHR) FR[e] = padv;                              // top border row
-  for (int e = tid; e < H0 * 3; e += NTHR) FR[(e / 3 + 1) * FRS + FR_X0 - 3 + e % 3] = padv;  // left border
+  for (int e = tid; e < FRS; e += NT) FR[e] = padv;                                // top border row
+  for (int e = tid; e < H0 * 3; e += NT) FR[(e / 3 + 1) * FRS + FR_X0 - 3 + e % 3] = padv;  // left border
   T* S1 = reinterpret_cast<T*>(region + CnnLds<T>::S1_OFF);
-  for (int p = tid; p < (2 * S1_W - 1) * CB1; p += NTHR) {
+  for (int p = tid; p < (2 * S1_W - 1) * CB1; p += NT) {
     const int q = p / CB1, c = p % CB1;
     const int y = q < S1_W ? 0 : q - S1_W + 1, x = q < S1_W ? q : 0;
     S1[(y * S1_W + x) * Pad<T>::S1P + c] = static_cast<T>(0.f);
@@ -194,9 +199,10 @@ __device__ inline void store4(T* dst, float v0, float v1, float v2, float v3) {
 // each lane ends with 4 consecutive channels of one position.  Wave 0 finishes with FC, margin
 // and the decision record; if next_valid, the next frame is stored into FR meanwhile.  Returns
 // the logits in z (wave 0, lane 0 holds all 10).
-template <typename T, int M>
+template <typename T, int M, int NWV>
 __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, const float* fcw,
                           bool next_valid, uint32_t next_idx, float* z_out) {
+  constexpr int NT = NWV * 64;                       // threads
   constexpr int C2 = 32 * M, C3 = 64 * M;
   constexpr int S1P = Pad<T>::S1P, C2P = C2 + Pad<T>::L2E;
   constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
@@ -214,15 +220,17 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   const float* b2 = sh.cb + CB_L2;
   const float* b3 = sh.cb + CB_L3;
   // The narrow classes fetch the next frame now: their layer 3 is too short to cover the HBM
-  // latency before the frame is stored.
-  constexpr bool kEarlyFetch = M <= 2;
-  FramePrefetch pf;
-  if (kEarlyFetch && next_valid) frame_issue(a, next_idx, pf);
+  // latency before the frame is stored (not the four-wave m = 2 form: no registers to spare).
+  constexpr bool kEarlyFetch = M == 1 || (M == 2 && NWV == 8);
+  FramePrefetch<NT> pf;
+  if (kEarlyFetch && next_valid) frame_issue<NT>(a, next_idx, pf);
 
-  // ---- layer-1 im2col fragments of this wave's 8 m-tiles (reused by every slab)
+  // ---- layer-1 im2col fragments of this wave's MPW m-tiles (cached when several slabs reuse them)
   constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
   constexpr int NT2 = 2 * M;
-  frag a1[sizeof(T) == 2 ? 8 : 1][KS1];
+  constexpr int MPW = 64 / NWV;                      // layer-1 m-tiles per wave
+  constexpr bool kCacheA1 = sizeof(T) == 2 && M > 1 && NWV == 8;
+  frag a1[kCacheA1 ? MPW : 1][KS1];
   auto gather1 = [&](int mt, int ks) -> frag {
     const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
     // im2col row of output (i, j): FR row 2i+u, elements 5 + 6j + (3v + c), k = 9u + 3v + c
@@ -240,20 +248,20 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       return k < 27 ? (float)rowp[(k / 9) * FRS + k % 9] : 0.f;
     }
   };
-  if constexpr (sizeof(T) == 2) {
+  if constexpr (kCacheA1) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < MPW; ++q)
 #pragma unroll
-      for (int ks = 0; ks < KS1; ++ks) a1[q][ks] = gather1(wave * 8 + q, ks);
+      for (int ks = 0; ks < KS1; ++ks) a1[q][ks] = gather1(wave * MPW + q, ks);
   }
 
-  // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (8 waves cover 16 x NT2)
-  constexpr int MT2 = M == 1 ? 2 : 4, NW2 = M == 1 ? 2 : (M == 2 ? 2 : 4);
+  // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (the waves cover 16 x NT2)
+  constexpr int MT2 = (M == 1 && NWV == 8) ? 2 : 4, NW2 = NT2 * (16 / MT2) / NWV;
   constexpr int NG2 = NT2 / NW2;                       // channel groups
   // weight prefetch depth (k-steps); the widest bf16 class has no registers to spare in layer 2
-  constexpr int PD2 = sizeof(T) == 4 ? 4 : (M == 4 ? 2 : 3);
+  constexpr int PD2 = sizeof(T) == 4 ? 4 : ((M == 4 || (M == 2 && NWV == 4)) ? 2 : 3);
   const int mg2 = wave / NG2, ng2 = wave % NG2;
-  static_assert((16 / MT2) * NG2 == 8, "layer-2 wave tiling must cover 8 waves");
+  static_assert((16 / MT2) * NG2 == NWV, "layer-2 wave tiling must cover the waves");
   floatx4 acc2[MT2][NW2];
 #pragma unroll
   for (int q = 0; q < MT2; ++q)
@@ -269,14 +277,14 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     float bb1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb1[r] = b1[slab * CB1 + 4 * g + r];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int mt = wave * 8 + q;
+#pragma unroll 8
+    for (int q = 0; q < MPW; ++q) {
+      const int mt = wave * MPW + q;
       floatx4 acc = (floatx4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < KS1; ++ks) {
         frag av;
-        if constexpr (sizeof(T) == 2) av = a1[q][ks];
+        if constexpr (kCacheA1) av = a1[q][ks];
         else av = gather1(mt, ks);
         acc = mfma(w1f[ks], av, acc);
       }
@@ -338,20 +346,20 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
                 fmaxf(acc2[q][n][1] + bb1v, 0.f), fmaxf(acc2[q][n][2] + bb2, 0.f), fmaxf(acc2[q][n][3] + bb3, 0.f));
     }
   }
-  for (int p = tid; p < (2 * L2_W - 1) * (C2 / 4); p += NTHR) {
+  for (int p = tid; p < (2 * L2_W - 1) * (C2 / 4); p += NT) {
     const int qq = p / (C2 / 4), c = (p % (C2 / 4)) * 4;
     const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
     store4<T>(L2 + (y * L2_W + x) * C2P + c, 0.f, 0.f, 0.f, 0.f);
   }
-  if (!kEarlyFetch && next_valid) frame_issue(a, next_idx, pf);
+  if (!kEarlyFetch && next_valid) frame_issue<NT>(a, next_idx, pf);
   __syncthreads();
 
   // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave tile MT3 x NW3
   constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
-  constexpr int MT3 = M == 1 ? 2 : 4, NW3 = 2 * M / MT3;
+  constexpr int MT3 = (M == 1 && NWV == 8) ? 2 : 4, NW3 = NT3 * (4 / MT3) / NWV;
   constexpr int MG3 = 4 / MT3;                         // position groups (1 or 2)
-  constexpr int PD3 = sizeof(T) == 4 ? 4 : 3;
-  static_assert(MG3 * (NT3 / NW3) == 8, "layer-3 wave tiling must cover 8 waves");
+  constexpr int PD3 = sizeof(T) == 4 ? 4 : ((M == 2 && NWV == 4) ? 2 : 3);
+  static_assert(MG3 * (NT3 / NW3) == NWV, "layer-3 wave tiling must cover the waves");
   const int mh = wave % MG3, ng = wave / MG3;
   floatx4 acc3[MT3][NW3];
 #pragma unroll
@@ -404,7 +412,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     }
   }
   if (MG3 == 1) {
-    for (int c = tid; c < C3; c += NTHR) sh.gpart[1][c] = 0.f;
+    for (int c = tid; c < C3; c += NT) sh.gpart[1][c] = 0.f;
   }
   __syncthreads();
   // wave 0: FC (lanes over channels) -> z; the other waves store the next frame meanwhile
@@ -424,20 +432,23 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
     for (int c = 0; c < kClasses; ++c) z_out[c] = zp[c] + sh.fcb[c];
   }
-  if (next_valid) frame_store<T>(a, pf, region);
+  if (next_valid) frame_store<T, NT>(a, pf, region);
 }
 
 // Persistent over every queue of the launch: entry t of the concatenated queues goes to workgroup
 // t mod grid; slots are ordered by cost, so the widest frames come first.  VSET is the set of width
 // classes the instantiation holds code for (bit m for width multiplier m); one register
 // allocation covers them all, so classes whose union would spill get launches of their own.
-template <typename T, int VSET>
-__global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
-  __shared__ __attribute__((aligned(16))) unsigned char region[CnnLds<T>::REGION];
+template <typename T, int VSET, int NWV = 8>
+__global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(NWV == 4 ? 2 : 1)))
+void cnn_fused_kernel(CnnArgs a, Forward f) {
+  constexpr int NT = NWV * 64;
+  constexpr int MMAX = (VSET & 4) ? 4 : (VSET & 2) ? 2 : 1;   // widest class of the launch
+  __shared__ __attribute__((aligned(16))) unsigned char region[CnnLds<T, MMAX>::REGION];
   __shared__ CnnShared sh;
   // FC weights of the current slot (bf16 kernels; the FP32 kernel has no LDS left and reads them
   // from global memory)
-  __shared__ float fcw_s[sizeof(T) == 2 ? FCW_MAX : 1];
+  __shared__ float fcw_s[sizeof(T) == 2 ? 64 * MMAX * kClasses : 1];
   const int tid = threadIdx.x;
   if (tid == 0) sh.d_n = 0;
   if (tid < kMaxK) sh.ticks[tid] = 0;
@@ -463,10 +474,10 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
   if ((int)blockIdx.x < total) {
     int slot;
     e_cur = locate(blockIdx.x, slot);
-    FramePrefetch pf;
-    frame_issue(a, entry_idx(e_cur), pf);
+    FramePrefetch<NT> pf;
+    frame_issue<NT>(a, entry_idx(e_cur), pf);
     if (tid == 0 && f.logits == nullptr) th_cur = theta_of(f, a.pred[slot], entry_idx(e_cur));
-    frame_store<T>(a, pf, region);
+    frame_store<T, NT>(a, pf, region);
   }
   if ((int)blockIdx.x + G < total) {
     int s2;
@@ -488,12 +499,12 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
     const int v = a.variant[slot];
     if (slot != loaded) {
       const int m = v == CNN_W4 ? 4 : v == CNN_W2 ? 2 : 1;
-      for (int q = tid; q < 16 * m; q += NTHR) sh.cb[q] = a.bias[slot][0][q];
-      for (int q = tid; q < 32 * m; q += NTHR) sh.cb[CB_L2 + q] = a.bias[slot][1][q];
-      for (int q = tid; q < 64 * m; q += NTHR) sh.cb[CB_L3 + q] = a.bias[slot][2][q];
+      for (int q = tid; q < 16 * m; q += NT) sh.cb[q] = a.bias[slot][0][q];
+      for (int q = tid; q < 32 * m; q += NT) sh.cb[CB_L2 + q] = a.bias[slot][1][q];
+      for (int q = tid; q < 64 * m; q += NT) sh.cb[CB_L3 + q] = a.bias[slot][2][q];
       if (tid < kClasses) sh.fcb[tid] = a.fc_b[slot][tid];
       if constexpr (sizeof(T) == 2) {
-        for (int q = tid; q < 64 * m * kClasses; q += NTHR) fcw_s[q] = a.fc_w[slot][q];
+        for (int q = tid; q < 64 * m * kClasses; q += NT) fcw_s[q] = a.fc_w[slot][q];
       }
       __syncthreads();
       loaded = slot;
@@ -526,13 +537,13 @@ __global__ __launch_bounds__(NTHR) void cnn_fused_kernel(CnnArgs a, Forward f) {
     unsigned long long t0 = wall_clock64();
     float z[kClasses];
     if constexpr ((VSET & 4) != 0) {
-      if (v == CNN_W4) cnn_frame<T, 4>(a, slot, region, sh, fcw, next_valid, next_idx, z);
+      if (v == CNN_W4) cnn_frame<T, 4, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, z);
     }
     if constexpr ((VSET & 2) != 0) {
-      if (v == CNN_W2) cnn_frame<T, 2>(a, slot, region, sh, fcw, next_valid, next_idx, z);
+      if (v == CNN_W2) cnn_frame<T, 2, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, z);
     }
     if constexpr ((VSET & 1) != 0) {
-      if (v == CNN_W1) cnn_frame<T, 1>(a, slot, region, sh, fcw, next_valid, next_idx, z);
+      if (v == CNN_W1) cnn_frame<T, 1, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, z);
     }
     if (tid == 0) {
       if (f.logits != nullptr) {
@@ -862,8 +873,8 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
     }
     if (b.n_preds == 0) continue;
     if (v == CNN_W4) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 4>), dim3(grid), dim3(NTHR), 0, s, b, f);
-    else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 2>), dim3(grid), dim3(NTHR), 0, s, b, f);
-    else hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 1>), dim3(grid), dim3(NTHR), 0, s, b, f);
+    else if (v == CNN_W2) hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 2, 4>), dim3(grid * 2), dim3(256), 0, s, b, f);
+    else hipLaunchKernelGGL((cnn_fused_kernel<__bf16, 1, 4>), dim3(grid * 2), dim3(256), 0, s, b, f);
   }
 }
 
