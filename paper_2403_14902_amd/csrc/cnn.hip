@@ -4,9 +4,11 @@
 // Model (synthetic UDF): 64x64x3 frame -> conv(16m) -> conv(32m) -> conv(64m) -> mean over 8x8 ->
 // FC 10, m in {1, 2, 4}; every conv has stride 2, zero padding 1 (in normalised space), ReLU.
 //
-// Per frame, one workgroup (4 wave64s):
-//   FR   the raw frame in LDS as bf16 (exact for bf16 and uint8 inputs), 4 channels (the 4th is 0),
-//        with a one-pixel top/left border holding the raw value that normalises to zero.
+// Per frame, one workgroup (8 wave64s for the widest class; 4 for the two narrower ones in the
+// bf16 first pass, two workgroups per CU):
+//   FR   the raw frame in LDS as bf16 (exact for bf16 and uint8 inputs): rows of 64 pixels x 3
+//        channels (row stride 200 elements), with a one-pixel top/left border holding the raw
+//        value that normalises to zero.
 //        Layer 1 uses the folded form sW * raw + (b - 2 sum W), so no normalisation pass runs.
 //   S1   one 16-channel slab of layer-1 output (all 32x32 positions);
 //   ACC2 layer-2 accumulators for all 16x16 positions and all 32m channels stay in registers while
@@ -853,7 +855,9 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
   }
   // FP32: one persistent launch over every queue of the pass.  BF16: one launch per width class
   // (a shared launch would give the narrow classes the widest one's register allocation and code
-  // footprint, measured slower).
+  // footprint, measured slower): the widest class runs 8-wave workgroups, one per CU; the two
+  // narrower classes run 4-wave workgroups, two per CU, so one workgroup's LDS phases overlap the
+  // other's matrix phases.
   if (!(a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST)) {
     hipLaunchKernelGGL((cnn_fused_kernel<float, 7>), dim3(grid), dim3(NTHR), 0, s, a, f);
     return;
