@@ -12,8 +12,9 @@ HIP path (tests, bench).  Nothing here imports either of them.
 
 Frame recipe (structured, low-frequency content so that a random GAP-CNN gives
 frame-dependent margins): per frame, z ~ N(0,1)^{3x8x8}, U = bilinear upsample
-to HxH with half-pixel centres, e ~ U[-1,1] iid per pixel value;
-frame = clip(0.5 + 0.25*U(z) + 0.10*e, 0, 1), stored NHWC and quantised to
+to HxH with half-pixel centres (two taps per axis, elementwise fp64 operations in
+a fixed order, so the frames do not depend on the machine's BLAS), e ~ U[-1,1]
+iid per pixel value; frame = clip(0.5 + 0.25*U(z) + 0.10*e, 0, 1), stored NHWC and quantised to
 bf16 (fp64 -> fp32 RNE -> bf16 RNE) or uint8 (round-half-even of 255*x).
 The small MLP workload uses iid uniform[0,1) fp32 frames instead.
 
@@ -164,6 +165,27 @@ def _upsample_matrix(src: int, dst: int) -> np.ndarray:
     return a
 
 
+def _upsample(z: np.ndarray, dst: int) -> np.ndarray:
+    """Bilinear upsample of z [n][3][8][8] to [n][dst][dst][3] (NHWC), columns then rows.
+
+    Every output is the two-tap sum w_lo * v[lo] + w_hi * v[hi] of the interpolation matrix's
+    nonzero entries, built from elementwise fp64 multiplies and adds only (no BLAS), so the frames
+    are bit-identical on every machine and thread count.
+    """
+    src = z.shape[-1]
+    a = _upsample_matrix(src, dst)
+    rows = np.arange(dst)
+    lo = np.argmax(a != 0.0, axis=1)
+    hi = np.minimum(lo + 1, src - 1)
+    w_lo = a[rows, lo]
+    w_hi = np.where(hi != lo, a[rows, hi], 0.0)
+    zt = z.transpose(0, 2, 3, 1)                                           # n, i, j, c
+    t = (w_lo[None, None, :, None] * np.take(zt, lo, axis=2)
+         + w_hi[None, None, :, None] * np.take(zt, hi, axis=2))           # n, i, x, c
+    return (w_lo[None, :, None, None] * np.take(t, lo, axis=1)
+            + w_hi[None, :, None, None] * np.take(t, hi, axis=1))         # n, y, x, c
+
+
 def f64_to_bf16_bits(x: np.ndarray) -> np.ndarray:
     """fp64 -> fp32 (round to nearest even) -> bf16 (round to nearest even), as uint16 bits."""
     u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
@@ -180,8 +202,7 @@ def _chunk_frames(cfg: WorkloadConfig, chunk: int, data_seed: int) -> np.ndarray
         return x.astype(np.float32)
     z = rng.standard_normal((CHUNK, 3, 8, 8))
     e = rng.uniform(-1.0, 1.0, size=(CHUNK, hw, hw, 3))
-    a = _upsample_matrix(8, hw)
-    up = np.einsum("yi,ncij,xj->nyxc", a, z, a, optimize=True)  # (n, hw, hw, 3)
+    up = _upsample(z, hw)                                       # (n, hw, hw, 3)
     x = np.clip(0.5 + 0.25 * up + 0.10 * e, 0.0, 1.0)
     if cfg.dtype == DTYPE_BF16:
         return f64_to_bf16_bits(x)
