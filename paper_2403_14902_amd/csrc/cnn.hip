@@ -131,19 +131,28 @@ struct FramePrefetch {
   uint4 v[1536 / NT];
 };
 
+// bf16 frames: 1536 chunks of 8 elements; uint8 frames: 768 chunks of 16 elements.  One
+// unconditional load sequence serves both (uint8 chunk indices past the frame are clamped to its
+// last chunk and the values ignored), so the loads are never skipped and no register is the
+// target of two alternative loads: the compiler can count outstanding loads exactly.
 template <int NT>
 __device__ inline void frame_issue(const CnnArgs& a, uint32_t idx, FramePrefetch<NT>& pf) {
   const int tid = threadIdx.x;
-  if (a.fr.dtype == HYDRO_DTYPE_BF16) {
-    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const __bf16*>(a.fr.base) + (int64_t)idx * a.fr.elems);
+  const bool bf = a.fr.dtype == HYDRO_DTYPE_BF16;
+  const int last = bf ? 1535 : 767;
+  const uint4* src = reinterpret_cast<const uint4*>(static_cast<const unsigned char*>(a.fr.base) +
+                                                    (int64_t)idx * a.fr.elems * (bf ? 2 : 1));
 #pragma unroll
-    for (int r = 0; r < 1536 / NT; ++r) pf.v[r] = src[tid + r * NT];   // 1536 chunks of 8 elements
-  } else {
-    const uint4* src = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(a.fr.base) + (int64_t)idx * a.fr.elems);
-#pragma unroll
-    for (int r = 0; r < (768 + NT - 1) / NT; ++r)                     // 768 chunks of 16 elements
-      if (tid + r * NT < 768) pf.v[r] = src[tid + r * NT];
-  }
+  for (int r = 0; r < 1536 / NT; ++r) pf.v[r] = src[min(tid + r * NT, last)];
+}
+
+// The loaded registers pass through an empty asm statement at the point of use, so no
+// computation on them (the uint8 unpacking, which the compiler otherwise evaluates speculatively
+// for every frame type) can be scheduled next to the loads: the wave does not wait for the frame
+// until it stores it.
+__device__ inline uint4 frame_regs_ready(uint4 v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+  return v;
 }
 
 // Store a prefetched frame into FR and (re)write the borders of FR and the layer-1 slab.
@@ -155,7 +164,7 @@ __device__ inline void frame_store(const CnnArgs& a, const FramePrefetch<NT>& pf
 #pragma unroll
     for (int r = 0; r < 1536 / NT; ++r) {
       const int q = tid + r * NT, y = q / 24, c = q % 24;
-      *reinterpret_cast<uint4*>(FR + (y + 1) * FRS + FR_X0 + c * 8) = pf.v[r];
+      *reinterpret_cast<uint4*>(FR + (y + 1) * FRS + FR_X0 + c * 8) = frame_regs_ready(pf.v[r]);
     }
   } else {
 #pragma unroll
@@ -163,7 +172,8 @@ __device__ inline void frame_store(const CnnArgs& a, const FramePrefetch<NT>& pf
       const int q = tid + r * NT;
       if (q < 768) {
         const int y = q / 12, c = q % 12;
-        const uint8_t* b = reinterpret_cast<const uint8_t*>(&pf.v[r]);
+        const uint4 raw = frame_regs_ready(pf.v[r]);
+        const uint8_t* b = reinterpret_cast<const uint8_t*>(&raw);
         alignas(16) __bf16 o[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) o[j] = static_cast<__bf16>((float)b[j]);
@@ -224,12 +234,40 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   // The narrow classes fetch the next frame now: their layer 3 is too short to cover the HBM
   // latency before the frame is stored (not the four-wave m = 2 form: no registers to spare).
   constexpr bool kEarlyFetch = M == 1 || (M == 2 && NWV == 8);
-  FramePrefetch<NT> pf;
-  if (kEarlyFetch && next_valid) frame_issue<NT>(a, next_idx, pf);
-
-  // ---- layer-1 im2col fragments of this wave's MPW m-tiles (cached when several slabs reuse them)
   constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
   constexpr int NT2 = 2 * M;
+  // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (the waves cover 16 x NT2)
+  constexpr int MT2 = (M == 1 && NWV == 8) ? 2 : 4, NW2 = NT2 * (16 / MT2) / NWV;
+  constexpr int NG2 = NT2 / NW2;                       // channel groups
+  // weight prefetch depth (k-steps); the widest bf16 class has no registers to spare in layer 2
+  constexpr int PD2 = sizeof(T) == 4 ? 4 : ((M == 4 || (M == 2 && NWV == 4)) ? 2 : 3);
+  const int mg2 = wave / NG2, ng2 = wave % NG2;
+  static_assert((16 / MT2) * NG2 == NWV, "layer-2 wave tiling must cover the waves");
+  // With the early fetch, slab 0's layer-1 weights and its first PD2 layer-2 weight k-steps are
+  // requested before the frame: a wave's vector loads complete in issue order, so a weight load
+  // issued after the frame's would wait for the frame's HBM latency.  (Not in the FP32 kernel:
+  // it has no registers to spare.)
+  constexpr bool kPreW = kEarlyFetch && sizeof(T) == 2;
+  frag w1_0[kPreW ? KS1 : 1];
+  frag bw2_0[kPreW ? PD2 : 1][NW2];
+  if constexpr (kPreW) {
+    const frag* w1p0 = reinterpret_cast<const frag*>(wpk[0]);
+#pragma unroll
+    for (int ks = 0; ks < KS1; ++ks) w1_0[ks] = w1p0[ks * 64 + lane];
+    const frag* w2p0 = reinterpret_cast<const frag*>(wpk[1]) + ng2 * NW2 * 64 + lane;
+#pragma unroll
+    for (int d = 0; d < PD2; ++d)
+#pragma unroll
+      for (int n = 0; n < NW2; ++n)
+        if (d < KS2) bw2_0[d][n] = w2p0[(d * NT2 + n) * 64];
+  }
+  // The frame loads are issued whether or not a next frame exists (next_idx is then the current
+  // frame and nothing is stored): a conditional issue would leave the compiler unsure how many
+  // loads are outstanding, and every later weight wait would then also wait for the frame.
+  FramePrefetch<NT> pf;
+  if (kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
+
+  // ---- layer-1 im2col fragments of this wave's MPW m-tiles (cached when several slabs reuse them)
   constexpr int MPW = 64 / NWV;                      // layer-1 m-tiles per wave
   constexpr bool kCacheA1 = sizeof(T) == 2 && M > 1 && NWV == 8;
   frag a1[kCacheA1 ? MPW : 1][KS1];
@@ -257,13 +295,6 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       for (int ks = 0; ks < KS1; ++ks) a1[q][ks] = gather1(wave * MPW + q, ks);
   }
 
-  // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (the waves cover 16 x NT2)
-  constexpr int MT2 = (M == 1 && NWV == 8) ? 2 : 4, NW2 = NT2 * (16 / MT2) / NWV;
-  constexpr int NG2 = NT2 / NW2;                       // channel groups
-  // weight prefetch depth (k-steps); the widest bf16 class has no registers to spare in layer 2
-  constexpr int PD2 = sizeof(T) == 4 ? 4 : ((M == 4 || (M == 2 && NWV == 4)) ? 2 : 3);
-  const int mg2 = wave / NG2, ng2 = wave % NG2;
-  static_assert((16 / MT2) * NG2 == NWV, "layer-2 wave tiling must cover the waves");
   floatx4 acc2[MT2][NW2];
 #pragma unroll
   for (int q = 0; q < MT2; ++q)
@@ -274,8 +305,13 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     // layer 1: 64 m-tiles (16 positions each) x 16 channels; wave w owns m-tiles 8w..8w+7
     const frag* w1p = reinterpret_cast<const frag*>(wpk[0]) + (size_t)slab * KS1 * 64;
     frag w1f[KS1];
+    if (kPreW && slab == 0) {
 #pragma unroll
-    for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1p[ks * 64 + lane];
+      for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1_0[ks];
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1p[ks * 64 + lane];
+    }
     float bb1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb1[r] = b1[slab * CB1 + 4 * g + r];
@@ -300,12 +336,20 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     // than that latency).
     const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64 + ng2 * NW2 * 64 + lane;
     frag bw2[PD2][NW2];
+    if (kPreW && slab == 0) {
 #pragma unroll
-    for (int d = 0; d < PD2; ++d)
+      for (int d = 0; d < PD2; ++d)
 #pragma unroll
-      for (int n = 0; n < NW2; ++n)
-        if (d < KS2) bw2[d][n] = w2p[(d * NT2 + n) * 64];
-#pragma unroll 1
+        for (int n = 0; n < NW2; ++n)
+          if (d < KS2) bw2[d][n] = bw2_0[d][n];
+    } else {
+#pragma unroll
+      for (int d = 0; d < PD2; ++d)
+#pragma unroll
+        for (int n = 0; n < NW2; ++n)
+          if (d < KS2) bw2[d][n] = w2p[(d * NT2 + n) * 64];
+    }
+#pragma unroll (kPreW && M == 1 ? 4 : 1)
     for (int ks0 = 0; ks0 < KS2; ks0 += PD2) {
 #pragma unroll
       for (int d = 0; d < PD2; ++d) {
@@ -353,7 +397,6 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     const int y = qq < L2_W ? 0 : qq - L2_W + 1, x = qq < L2_W ? qq : 0;
     store4<T>(L2 + (y * L2_W + x) * C2P + c, 0.f, 0.f, 0.f, 0.f);
   }
-  if (!kEarlyFetch && next_valid) frame_issue<NT>(a, next_idx, pf);
   __syncthreads();
 
   // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave tile MT3 x NW3
@@ -375,27 +418,51 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   for (int d = 0; d < PD3; ++d)
 #pragma unroll
     for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(d * NT3 + n) * 64];
+  auto l3_step = [&](int ks, const frag (&b)[NW3]) {
+    const int k0 = ks * KSTEP + KPL * g;
+    const int t = k0 / C2, c0 = k0 % C2;
+    const int u = t / 3, v = t % 3;
+    frag av[MT3];
+#pragma unroll
+    for (int q = 0; q < MT3; ++q) {
+      const int px = (mh * MT3 + q) * 16 + l16, i = px >> 3, j = px & 7;
+      av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
+    }
+#pragma unroll
+    for (int n = 0; n < NW3; ++n)
+#pragma unroll
+      for (int q = 0; q < MT3; ++q) acc3[q][n] = mfma(b[n], av[q], acc3[q][n]);
+  };
+  if constexpr (sizeof(T) == 2) {
+    // every k-step but the last PD3 refills its buffer PD3 k-steps ahead
 #pragma unroll 1
-  for (int ks0 = 0; ks0 < KS3; ks0 += PD3) {
+    for (int ks0 = 0; ks0 < KS3 - PD3; ks0 += PD3) {
 #pragma unroll
-    for (int d = 0; d < PD3; ++d) {
-      const int ks = ks0 + d;
-      const int k0 = ks * KSTEP + KPL * g;
-      const int t = k0 / C2, c0 = k0 % C2;
-      const int u = t / 3, v = t % 3;
-      frag av[MT3];
-#pragma unroll
-      for (int q = 0; q < MT3; ++q) {
-        const int px = (mh * MT3 + q) * 16 + l16, i = px >> 3, j = px & 7;
-        av[q] = ld_frag<T>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
-      }
-#pragma unroll
-      for (int n = 0; n < NW3; ++n)
-#pragma unroll
-        for (int q = 0; q < MT3; ++q) acc3[q][n] = mfma(bw3[d][n], av[q], acc3[q][n]);
-      if (ks + PD3 < KS3) {
+      for (int d = 0; d < PD3; ++d) {
+        const int ks = ks0 + d;
+        l3_step(ks, bw3[d]);
 #pragma unroll
         for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[((ks + PD3) * NT3 + n) * 64];
+      }
+    }
+    // The late fetch goes after the last weight request: loads complete in issue order, so any
+    // weight requested after the frame would wait for it.
+    if (!kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
+#pragma unroll
+    for (int d = 0; d < PD3; ++d) l3_step(KS3 - PD3 + d, bw3[d]);
+  } else {
+    // FP32: the split loop above costs spills; the frame is requested before layer 3
+    if (!kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
+#pragma unroll 1
+    for (int ks0 = 0; ks0 < KS3; ks0 += PD3) {
+#pragma unroll
+      for (int d = 0; d < PD3; ++d) {
+        const int ks = ks0 + d;
+        l3_step(ks, bw3[d]);
+        if (ks + PD3 < KS3) {
+#pragma unroll
+          for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[((ks + PD3) * NT3 + n) * 64];
+        }
       }
     }
   }
@@ -517,7 +584,7 @@ void cnn_fused_kernel(CnnArgs a, Forward f) {
     const float th = th_cur;
     const int tn = t + G;
     const bool next_valid = tn < total;
-    uint32_t next_idx = 0;
+    uint32_t next_idx = idx;   // with no next frame, the loads re-read this one (cached) unused
     if (next_valid) {
       next_idx = entry_idx(e_nxt);
       if (tid == 0 && f.logits == nullptr) {
