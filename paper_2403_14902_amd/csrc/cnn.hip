@@ -521,49 +521,56 @@ void cnn_fused_kernel(CnnArgs a, Forward f) {
   const int tid = threadIdx.x;
   if (tid == 0) sh.d_n = 0;
   if (tid < kMaxK) sh.ticks[tid] = 0;
-  // queue prefix offsets (read once; uniform), so locating entry t is arithmetic
-  int cum[kMaxK + 1];
-  cum[0] = 0;
-#pragma unroll
-  for (int i = 0; i < kMaxK; ++i) cum[i + 1] = cum[i] + (i < a.n_preds ? a.q.counts[a.pred[i]] : 0);
-  const int total = cum[kMaxK];
-  auto locate = [&](int t, int& slot) -> uint32_t {
-    int base = 0;
-    slot = 0;
-#pragma unroll
-    for (int i = 1; i < kMaxK; ++i)
-      if (i < a.n_preds && t >= cum[i]) { slot = i; base = cum[i]; }
-    return a.q.entries[(int64_t)a.pred[slot] * a.q.cap + (t - base)];
-  };
-  const int G = gridDim.x;
-  // Entries are fetched two frames ahead and thresholds one frame ahead (thread 0), so neither
-  // the frame fetch nor the decision waits on a dependent global load.
-  uint32_t e_cur = 0, e_nxt = 0;
-  float th_cur = 0.f, th_nxt = 0.f;
-  if ((int)blockIdx.x < total) {
-    int slot;
-    e_cur = locate(blockIdx.x, slot);
-    FramePrefetch<NT> pf;
-    frame_issue<NT>(a, entry_idx(e_cur), pf);
-    if (tid == 0 && f.logits == nullptr) th_cur = theta_of(f, a.pred[slot], entry_idx(e_cur));
-    frame_store<T, NT>(a, pf, region);
+  // queue prefix offsets, kept in LDS (read when entries are staged)
+  __shared__ int cum_s[kMaxK + 1];
+  if (tid == 0) {
+    int c = 0;
+    cum_s[0] = 0;
+    for (int i = 0; i < kMaxK; ++i) {
+      c += i < a.n_preds ? a.q.counts[a.pred[i]] : 0;
+      cum_s[i + 1] = c;
+    }
   }
-  if ((int)blockIdx.x + G < total) {
-    int s2;
-    e_nxt = locate(blockIdx.x + G, s2);
+  __syncthreads();
+  const int total = cum_s[kMaxK];
+  const int G = gridDim.x;
+  // This workgroup's queue entries, their slots and decision thresholds are staged in LDS, ECH
+  // frames per chunk, double-buffered: wave 0 requests chunk c + 1 when chunk c starts.  The
+  // per-frame path then issues no dependent global load (a wave's vector loads complete in issue
+  // order, so a per-frame entry or threshold load would hold up the next weight wait).
+  constexpr int ECH = 64;
+  __shared__ uint32_t ring_e[2 * ECH];
+  __shared__ float ring_th[2 * ECH];
+  __shared__ uint8_t ring_s[2 * ECH];
+  auto fill = [&](int c, int lo) {
+    const int i = tid - lo;
+    if (i >= 0 && i < ECH) {
+      const int t = (int)blockIdx.x + (c * ECH + i) * G;
+      if (t < total) {
+        int slot = 0, base = 0;
+        for (int j = 1; j < a.n_preds; ++j)
+          if (t >= cum_s[j]) { slot = j; base = cum_s[j]; }
+        const uint32_t e = a.q.entries[(int64_t)a.pred[slot] * a.q.cap + (t - base)];
+        ring_e[(c & 1) * ECH + i] = e;
+        ring_s[(c & 1) * ECH + i] = (uint8_t)slot;
+        ring_th[(c & 1) * ECH + i] = f.logits == nullptr ? theta_of(f, a.pred[slot], entry_idx(e)) : 0.f;
+      }
+    }
+  };
+  fill(0, 0);
+  fill(1, 64);
+  __syncthreads();
+  if ((int)blockIdx.x < total) {
+    FramePrefetch<NT> pf;
+    frame_issue<NT>(a, entry_idx(ring_e[0]), pf);
+    frame_store<T, NT>(a, pf, region);
   }
   __syncthreads();
   int loaded = -1;
-  for (int t = blockIdx.x; t < total; t += G) {
-    int slot;
-    {
-      int base = 0;
-      slot = 0;
-#pragma unroll
-      for (int i = 1; i < kMaxK; ++i)
-        if (i < a.n_preds && t >= cum[i]) { slot = i; base = cum[i]; }
-      (void)base;
-    }
+  int nf = 0;   // frames of this workgroup so far
+  for (int t = blockIdx.x; t < total; t += G, ++nf) {
+    if (nf % ECH == 0 && nf > 0) fill(nf / ECH + 1, 0);   // read after this frame's barriers
+    const int slot = ring_s[nf % (2 * ECH)];
     const int k = a.pred[slot];
     const int v = a.variant[slot];
     if (slot != loaded) {
@@ -579,30 +586,12 @@ void cnn_fused_kernel(CnnArgs a, Forward f) {
       loaded = slot;
     }
     const float* fcw = sizeof(T) == 2 ? fcw_s : a.fc_w[slot];
-    const uint32_t e = e_cur;
+    const uint32_t e = ring_e[nf % (2 * ECH)];
     const uint32_t idx = entry_idx(e);
-    const float th = th_cur;
-    const int tn = t + G;
-    const bool next_valid = tn < total;
-    uint32_t next_idx = idx;   // with no next frame, the loads re-read this one (cached) unused
-    if (next_valid) {
-      next_idx = entry_idx(e_nxt);
-      if (tid == 0 && f.logits == nullptr) {
-        int s2;
-        int base = 0;
-        s2 = 0;
-#pragma unroll
-        for (int i = 1; i < kMaxK; ++i)
-          if (i < a.n_preds && tn >= cum[i]) { s2 = i; base = cum[i]; }
-        (void)base;
-        th_nxt = theta_of(f, a.pred[s2], next_idx);
-      }
-    }
-    uint32_t e_nn = 0;
-    if (tn + G < total) {
-      int s3;
-      e_nn = locate(tn + G, s3);
-    }
+    const float th = ring_th[nf % (2 * ECH)];
+    const bool next_valid = t + G < total;
+    // with no next frame, the loads re-read this one (cached) unused
+    const uint32_t next_idx = next_valid ? entry_idx(ring_e[(nf + 1) % (2 * ECH)]) : idx;
     unsigned long long t0 = wall_clock64();
     float z[kClasses];
     if constexpr ((VSET & 4) != 0) {
@@ -630,9 +619,6 @@ void cnn_fused_kernel(CnnArgs a, Forward f) {
     }
     __syncthreads();
     if (sh.d_n == DBUF) flush_decisions(f, sh, a.n_preds, a.pred);
-    e_cur = e_nxt;
-    e_nxt = e_nn;
-    th_cur = th_nxt;
   }
   if (f.logits == nullptr) flush_decisions(f, sh, a.n_preds, a.pred);
   __syncthreads();
