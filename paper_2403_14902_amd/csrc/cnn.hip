@@ -275,17 +275,19 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
     // im2col row of output (i, j): FR row 2i+u, elements 5 + 6j + (3v + c), k = 9u + 3v + c
     const __bf16* rowp = FR + 2 * i * FRS + 5 + 6 * j;
+    // padded k (27..31, zero weights) reads element 26, a finite value: the reads need no
+    // per-lane predication, so the tiles' reads can be scheduled ahead of the MFMAs
     if constexpr (sizeof(T) == 2) {
       alignas(16) __bf16 t8[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int k = ks * 32 + 8 * g + e;
-        t8[e] = k < 27 ? rowp[(k / 9) * FRS + k % 9] : static_cast<__bf16>(0.f);
+        const int k = min(ks * 32 + 8 * g + e, 26);
+        t8[e] = rowp[(k / 9) * FRS + k % 9];
       }
       return *reinterpret_cast<const bf16x8*>(t8);
     } else {
-      const int k = ks * 4 + g;
-      return k < 27 ? (float)rowp[(k / 9) * FRS + k % 9] : 0.f;
+      const int k = min(ks * 4 + g, 26);
+      return (float)rowp[(k / 9) * FRS + k % 9];
     }
   };
   if constexpr (kCacheA1) {
@@ -315,20 +317,37 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     float bb1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb1[r] = b1[slab * CB1 + 4 * g + r];
-#pragma unroll 8
-    for (int q = 0; q < MPW; ++q) {
-      const int mt = wave * MPW + q;
-      floatx4 acc = (floatx4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KS1; ++ks) {
-        frag av;
-        if constexpr (kCacheA1) av = a1[q][ks];
-        else av = gather1(mt, ks);
-        acc = mfma(w1f[ks], av, acc);
-      }
+    auto l1_store = [&](int mt, const floatx4& acc) {
       const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
       store4<T>(S1 + ((i + 1) * S1_W + (j + 1)) * S1P + 4 * g, fmaxf(acc[0] + bb1[0], 0.f),
                 fmaxf(acc[1] + bb1[1], 0.f), fmaxf(acc[2] + bb1[2], 0.f), fmaxf(acc[3] + bb1[3], 0.f));
+    };
+    if constexpr (sizeof(T) == 2 && !kCacheA1 && KS1 == 1) {
+      // tiles in pairs: both gathers, both MFMAs, then both epilogues, so one tile's LDS and
+      // MFMA latencies overlap the other's
+      const floatx4 zero = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int q = 0; q < MPW; q += 2) {
+        const int mt = wave * MPW + q;
+        const frag av0 = gather1(mt, 0), av1 = gather1(mt + 1, 0);
+        const floatx4 acc0 = mfma(w1f[0], av0, zero), acc1 = mfma(w1f[0], av1, zero);
+        l1_store(mt, acc0);
+        l1_store(mt + 1, acc1);
+      }
+    } else {
+#pragma unroll 8
+      for (int q = 0; q < MPW; ++q) {
+        const int mt = wave * MPW + q;
+        floatx4 acc = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {
+          frag av;
+          if constexpr (kCacheA1) av = a1[q][ks];
+          else av = gather1(mt, ks);
+          acc = mfma(w1f[ks], av, acc);
+        }
+        l1_store(mt, acc);
+      }
     }
     __syncthreads();
     // layer 2 partial: K = 9 taps x 16 channels of this slab.  The weight fragments run PD2
