@@ -149,7 +149,8 @@ __device__ inline float theta_of(const Forward& f, int k, uint32_t idx) {
 // Cross-lane sums.  row_sum16: over the 16 lanes of each DPP row (lanes 16r..16r+15), by
 // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and row_mirror (each step adds a lane
 // whose partial covers the complementary lanes, so every lane ends with the row total).
-// wave_sum: all 64 lanes (two more steps across rows).
+// wave_sum_n: all 64 lanes: the four row totals are read out of lanes 0, 16, 32, 48 (no LDS
+// round trip) and added as (r0 + r1) + (r2 + r3); every lane ends with the same total.
 template <int CTRL>
 __device__ inline float dpp_mov(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
@@ -161,14 +162,16 @@ __device__ inline float row_sum16(float v) {
   v += dpp_mov<0x140>(v);
   return v;
 }
+__device__ inline float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 template <int N>
 __device__ inline void wave_sum_n(float (&v)[N]) {
 #pragma unroll
   for (int c = 0; c < N; ++c) v[c] = row_sum16(v[c]);
 #pragma unroll
-  for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 16);
-#pragma unroll
-  for (int c = 0; c < N; ++c) v[c] += __shfl_xor(v[c], 32);
+  for (int c = 0; c < N; ++c)
+    v[c] = (lane_value(v[c], 0) + lane_value(v[c], 16)) + (lane_value(v[c], 32) + lane_value(v[c], 48));
 }
 
 __device__ inline int lane_id() { return __lane_id(); }
