@@ -102,6 +102,7 @@ struct CnnShared {
   uint8_t d_f[DBUF];
   int d_n;
   unsigned long long ticks[kMaxK];
+  __attribute__((aligned(16))) __bf16 feat[192];   // router features of the current frame
 };
 
 __device__ void flush_decisions(const Forward& f, CnnShared& sh, int n_slots, const int* pred) {
@@ -211,9 +212,55 @@ __device__ inline void store4(T* dst, float v0, float v1, float v2, float v3) {
 // each lane ends with 4 consecutive channels of one position.  Wave 0 finishes with FC, margin
 // and the decision record; if next_valid, the next frame is stored into FR meanwhile.  Returns
 // the logits in z (wave 0, lane 0 holds all 10).
+// Router features of the frame in FR: the 8x8-pixel cell means per channel (8 x 8 cells x 3),
+// normalised as the predicates normalise their input.  Each (cell, row) segment is 8 pixels x 3
+// channels = 24 contiguous elements (three aligned 16-byte reads); lanes 8m..8m+7 hold the eight
+// rows of one cell and add them with three DPP steps.  Pass it (0 .. 512/NT - 1) covers segments
+// tid + it * NT; lanes with row 0 hold their cell's three values.
+template <int NT>
+struct FrameFeat {
+  float v[512 / NT][3];
+};
+template <int NT>
+__device__ inline void frame_features(const __bf16* FR, float scale, FrameFeat<NT>& ff) {
+#pragma unroll
+  for (int it = 0; it < 512 / NT; ++it) {
+    const int sg = threadIdx.x + it * NT;
+    const int cell = sg >> 3, r = sg & 7, by = cell >> 3, bx = cell & 7;
+    const uint4* p = reinterpret_cast<const uint4*>(FR + (8 * by + r + 1) * FRS + FR_X0 + 24 * bx);
+    float c3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint4 u = p[q];
+      const __bf16* h = reinterpret_cast<const __bf16*>(&u);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) c3[(8 * q + e) % 3] += (float)h[e];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      c3[c] += dpp_mov<0xB1>(c3[c]);    // quad_perm [1,0,3,2]
+      c3[c] += dpp_mov<0x4E>(c3[c]);    // quad_perm [2,3,0,1]
+      c3[c] += dpp_mov<0x141>(c3[c]);   // row_half_mirror: the other quad of the 8 lanes
+      ff.v[it][c] = (c3[c] * scale - 0.5f) * 4.0f;
+    }
+  }
+}
+// Each thread with row 0 writes its cells' values (to HBM, or to sh.feat).
+template <int NT>
+__device__ inline void frame_features_put(const FrameFeat<NT>& ff, __bf16* dst) {
+#pragma unroll
+  for (int it = 0; it < 512 / NT; ++it) {
+    const int sg = threadIdx.x + it * NT;
+    if ((sg & 7) == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dst[(sg >> 3) * 3 + c] = static_cast<__bf16>(ff.v[it][c]);
+    }
+  }
+}
+
 template <typename T, int M, int NWV>
 __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, CnnShared& sh, const float* fcw,
-                          bool next_valid, uint32_t next_idx, float* z_out) {
+                          bool next_valid, uint32_t next_idx, __bf16* feat_dst, float* z_out) {
   constexpr int NT = NWV * 64;                       // threads
   constexpr int C2 = 32 * M, C3 = 64 * M;
   constexpr int S1P = Pad<T>::S1P, C2P = C2 + Pad<T>::L2E;
@@ -264,8 +311,16 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   // The frame loads are issued whether or not a next frame exists (next_idx is then the current
   // frame and nothing is stored): a conditional issue would leave the compiler unsure how many
   // loads are outstanding, and every later weight wait would then also wait for the frame.
+  // First evaluation of a tuple in the first pass: its router features, from the frame in LDS.
+  // Early fetch: computed now and stored by every wave right after the frame loads are issued
+  // (everything waited on later already waits for those loads, which complete in issue order).
+  // Late fetch: staged in LDS at slab 0 and stored by wave 0 after the late frame issue.
+  const float fscale = (a.fr.dtype == HYDRO_DTYPE_U8 ? 1.0f / 255.0f : 1.0f) * (1.0f / 64.0f);
+  FrameFeat<NT> ff;
+  if (kEarlyFetch && feat_dst != nullptr) frame_features<NT>(FR, fscale, ff);
   FramePrefetch<NT> pf;
   if (kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
+  if (kEarlyFetch && feat_dst != nullptr) frame_features_put<NT>(ff, feat_dst);
 
   // ---- layer-1 im2col fragments of this wave's MPW m-tiles (cached when several slabs reuse them)
   constexpr int MPW = 64 / NWV;                      // layer-1 m-tiles per wave
@@ -317,6 +372,10 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     float bb1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb1[r] = b1[slab * CB1 + 4 * g + r];
+    if (!kEarlyFetch && slab == 0 && feat_dst != nullptr) {
+      frame_features<NT>(FR, fscale, ff);
+      frame_features_put<NT>(ff, sh.feat);
+    }
     auto l1_store = [&](int mt, const floatx4& acc) {
       const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
       store4<T>(S1 + ((i + 1) * S1_W + (j + 1)) * S1P + 4 * g, fmaxf(acc[0] + bb1[0], 0.f),
@@ -467,11 +526,15 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
     // The late fetch goes after the last weight request: loads complete in issue order, so any
     // weight requested after the frame would wait for it.
     if (!kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
+    if (!kEarlyFetch && feat_dst != nullptr && wave == 0 && lane < 24)
+      reinterpret_cast<uint4*>(feat_dst)[lane] = reinterpret_cast<const uint4*>(sh.feat)[lane];
 #pragma unroll
     for (int d = 0; d < PD3; ++d) l3_step(KS3 - PD3 + d, bw3[d]);
   } else {
     // FP32: the split loop above costs spills; the frame is requested before layer 3
     if (!kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
+    if (!kEarlyFetch && feat_dst != nullptr && wave == 0 && lane < 24)
+      reinterpret_cast<uint4*>(feat_dst)[lane] = reinterpret_cast<const uint4*>(sh.feat)[lane];
 #pragma unroll 1
     for (int ks0 = 0; ks0 < KS3; ks0 += PD3) {
 #pragma unroll
@@ -611,16 +674,18 @@ void cnn_fused_kernel(CnnArgs a, Forward f) {
     const bool next_valid = t + G < total;
     // with no next frame, the loads re-read this one (cached) unused
     const uint32_t next_idx = next_valid ? entry_idx(ring_e[(nf + 1) % (2 * ECH)]) : idx;
+    __bf16* feat_dst = a.feats != nullptr && f.logits == nullptr && entry_mask(e) == 0
+                           ? a.feats + (int64_t)idx * 192 : nullptr;
     unsigned long long t0 = wall_clock64();
     float z[kClasses];
     if constexpr ((VSET & 4) != 0) {
-      if (v == CNN_W4) cnn_frame<T, 4, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, z);
+      if (v == CNN_W4) cnn_frame<T, 4, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, feat_dst, z);
     }
     if constexpr ((VSET & 2) != 0) {
-      if (v == CNN_W2) cnn_frame<T, 2, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, z);
+      if (v == CNN_W2) cnn_frame<T, 2, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, feat_dst, z);
     }
     if constexpr ((VSET & 1) != 0) {
-      if (v == CNN_W1) cnn_frame<T, 1, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, z);
+      if (v == CNN_W1) cnn_frame<T, 1, NWV>(a, slot, region, sh, fcw, next_valid, next_idx, feat_dst, z);
     }
     if (tid == 0) {
       if (f.logits != nullptr) {

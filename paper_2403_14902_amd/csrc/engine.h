@@ -63,6 +63,8 @@ struct CnnArgs {
   DevState* st;
   int count_ticks;
   int prec;
+  __bf16* feats;                    // first pass: router features of each tuple's first evaluation
+                                    // ([n][192] bf16), or nullptr
 };
 
 // Grouped launch over the generic (layer-wise) CNN predicates of one tier.

@@ -334,6 +334,7 @@ struct hydro_session {
   CnnArgs cnn{};
   GcnnArgs gcnn{};
   RouterNN* rnn = nullptr;
+  bool fused_feats = false;   // every predicate is a fused CNN: its first pass writes the router features
   // query progress
   int rounds_done = 0;
   bool warmed = false;
@@ -854,6 +855,9 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
     for (int i = 0; i < k; ++i) fl[i] = s->models[i].flops;
     rc = router_nn_create(&s->rnn, s->K, frame_h, frame_w, cap, s->pol.seed, s->pol.routing_batch, s->pol.explore, fl);
     if (rc) return bail(fail(rc, "learned router: frames must be square with a side divisible by 8"));
+    s->fused_feats = true;
+    for (int i = 0; i < k; ++i)
+      if (s->models[i].m.arch != HYDRO_ARCH_CNN || s->models[i].variant == CNN_NONE) s->fused_feats = false;
   }
   rc = hydro_session_reset(s);
   if (rc) return bail(rc);
@@ -983,6 +987,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
     a.st = s->st;
     a.count_ticks = 1;
     a.prec = s->pol.precision;
+    a.feats = tier == TIER_FIRST && s->fused_feats ? router_nn_feats_ptr(s->rnn) : nullptr;
     if (s->pol.grouped || a.n_preds == 1) {
       launch_cnn_pass(a, f, tier, s->n_cu, st);
     } else {
@@ -1295,7 +1300,9 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
                                        s->result_bits, 0u, nwords);
     if (s->route_log && n > 0)
       hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, s->route_log, 0u, n);
-    if (s->rnn && n > 0) router_nn_admit(s->rnn, src, n, st);
+    // router features: pooled for the whole push up front, unless the fused CNN first pass
+    // computes them (then only admitted waves that the learned arm routes are pooled, below)
+    if (s->rnn && n > 0 && !s->fused_feats) router_nn_admit(s->rnn, src, 0, n, nullptr, st);
     int parity = parity0;
     for (int r = 0; r < n_rounds; ++r) {
       const int in_slot = parity, out_slot = parity ^ 1;
@@ -1337,6 +1344,8 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       if (s->rnn) {
         ra.olog = router_nn_log(s->rnn);
         ra.min_steps = router_nn_min_steps();
+        if (s->fused_feats && r < (int)adm.size() && r >= router_nn_first_learned_round())
+          router_nn_admit(s->rnn, src, adm[r].first, adm[r].second, s->st, st);
         router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
       }
       hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);

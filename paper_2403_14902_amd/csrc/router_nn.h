@@ -12,8 +12,12 @@ int router_nn_create(RouterNN** out, int k, int fh, int fw, int64_t cap, uint64_
 void router_nn_destroy(RouterNN* r);
 // New query: initial weights, cleared optimiser state.
 void router_nn_reset(RouterNN* r, hipStream_t s);
-// Pooled features of every tuple of a push.
-int router_nn_admit(RouterNN* r, const FrameSrc& fr, int64_t n, hipStream_t s);
+// Pooled features of the push's tuples lo..hi-1.  With `guard`, the launch does nothing unless the
+// learned arm is routing (the fused CNN first pass computes every tuple's features on its first
+// evaluation; only tuples admitted while the learned arm routes need them earlier).
+int router_nn_admit(RouterNN* r, const FrameSrc& fr, int64_t lo, int64_t hi, const DevState* guard, hipStream_t s);
+// Feature rows [cap][192] bf16 (written by the pooling kernels or by the fused CNN first pass).
+__bf16* router_nn_feats_ptr(RouterNN* r);
 // Keys of this round's live tuples (survivors in pend_in plus the admitted range).
 void router_nn_keys(RouterNN* r, DevState* st, const uint32_t* pend_in, int in_slot, uint32_t adm_lo,
                     uint32_t adm_hi, int grid, hipStream_t s);
@@ -22,5 +26,7 @@ void router_nn_learn(RouterNN* r, DevState* st, hipStream_t s);
 const float* router_nn_keys_ptr(RouterNN* r);
 OutcomeLog router_nn_log(RouterNN* r);
 int router_nn_min_steps();
+// First round (0-based) in which the learned arm can route.
+int router_nn_first_learned_round();
 
 }  // namespace hydro

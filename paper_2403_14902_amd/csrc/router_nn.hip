@@ -47,13 +47,20 @@ struct RouterNN {
   std::vector<float> init;
 };
 
-// Any frame side divisible by 8: one thread per output feature (scalar loads).
-__global__ void rnn_pool_kernel(FrameSrc fr, int64_t n, __bf16* feats) {
+// With `guard` set, a pooling launch does nothing unless the learned arm is routing (the keys
+// of newly admitted tuples need their features before any predicate has seen the frame).
+__device__ inline bool pool_skipped(const DevState* guard) {
+  return guard != nullptr && (!guard->learned_active || guard->train_steps < MIN_STEPS);
+}
+
+// Any frame side divisible by 8: one thread per output feature (scalar loads).  Frames lo..lo+n-1.
+__global__ void rnn_pool_kernel(FrameSrc fr, int64_t lo, int64_t n, __bf16* feats, const DevState* guard) {
+  if (pool_skipped(guard)) return;
   const int64_t total = n * RF;
   const int blk = fr.hw / 8;
   const float inv = 1.0f / (float)(blk * blk);
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t t = q / RF;
+    const int64_t t = lo + q / RF;
     const int o = (int)(q % RF);
     const int by = o / 24, bx = (o / 3) % 8, c = o % 3;
     float s = 0.f;
@@ -67,7 +74,7 @@ __global__ void rnn_pool_kernel(FrameSrc fr, int64_t n, __bf16* feats) {
         else v = static_cast<const float*>(fr.base)[e];
         s += v;
       }
-    feats[q] = static_cast<__bf16>((s * inv - 0.5f) * 4.0f);
+    feats[t * RF + o] = static_cast<__bf16>((s * inv - 0.5f) * 4.0f);
   }
 }
 
@@ -115,49 +122,54 @@ __device__ inline void load_chunk(const T* p, float (&v)[CH]) {
 // three channel means at the end.  64 consecutive threads cover one frame, so each wave's loads
 // walk whole frame rows.
 template <typename T, int CH, int NCH>
-__global__ __launch_bounds__(256) void rnn_pool_vec_kernel(FrameSrc fr, int64_t n, __bf16* feats) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t t = gid >> 6;
-  if (t >= n) return;
-  const int cell = (int)(gid & 63), by = cell >> 3, bx = cell & 7;
+__global__ __launch_bounds__(256) void rnn_pool_vec_kernel(FrameSrc fr, int64_t lo, int64_t n, __bf16* feats,
+                                                           const DevState* guard) {
+  if (pool_skipped(guard)) return;
   const int blk = fr.hw / 8;
   const int row_elems = fr.hw * 3;
-  const T* p = static_cast<const T*>(fr.base) + t * fr.elems + (int64_t)(by * blk) * row_elems + bx * (NCH * CH);
-  float acc[NCH][CH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c)
-#pragma unroll
-    for (int e = 0; e < CH; ++e) acc[c][e] = 0.f;
-#pragma unroll 4
-  for (int y = 0; y < blk; ++y) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      float v[CH];
-      load_chunk<T, CH>(p + (int64_t)y * row_elems + c * CH, v);
-#pragma unroll
-      for (int e = 0; e < CH; ++e) acc[c][e] += v[e];
-    }
-  }
-  float ch[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-  for (int c = 0; c < NCH; ++c)
-#pragma unroll
-    for (int e = 0; e < CH; ++e) ch[(c * CH + e) % 3] += acc[c][e];
   const float scale = (sizeof(T) == 1 ? 1.0f / 255.0f : 1.0f) / (float)(blk * blk);
-  __bf16* o = feats + t * RF + by * 24 + bx * 3;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; (gid >> 6) < n;
+       gid += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = lo + (gid >> 6);
+    const int cell = (int)(gid & 63), by = cell >> 3, bx = cell & 7;
+    const T* p = static_cast<const T*>(fr.base) + t * fr.elems + (int64_t)(by * blk) * row_elems + bx * (NCH * CH);
+    float acc[NCH][CH];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) o[c] = static_cast<__bf16>((ch[c] * scale - 0.5f) * 4.0f);
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int e = 0; e < CH; ++e) acc[c][e] = 0.f;
+#pragma unroll 4
+    for (int y = 0; y < blk; ++y) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        float v[CH];
+        load_chunk<T, CH>(p + (int64_t)y * row_elems + c * CH, v);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) acc[c][e] += v[e];
+      }
+    }
+    float ch[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int e = 0; e < CH; ++e) ch[(c * CH + e) % 3] += acc[c][e];
+    __bf16* o = feats + t * RF + by * 24 + bx * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[c] = static_cast<__bf16>((ch[c] * scale - 0.5f) * 4.0f);
+  }
 }
 
 template <typename T>
-static bool launch_pool_vec(const FrameSrc& fr, int64_t n, __bf16* feats, hipStream_t s) {
-  const int64_t blocks = (n * 64 + 255) / 256;
+static bool launch_pool_vec(const FrameSrc& fr, int64_t lo, int64_t n, __bf16* feats, const DevState* guard,
+                            hipStream_t s) {
+  // guarded launches (most of which return at once) take a small grid and stride over the frames
+  const int64_t blocks = std::min<int64_t>((n * 64 + 255) / 256, guard != nullptr ? 2048 : INT32_MAX);
   if (fr.hw == 32) {
-    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 4, 3>), dim3((unsigned)blocks), dim3(256), 0, s, fr, n, feats);
+    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 4, 3>), dim3((unsigned)blocks), dim3(256), 0, s, fr, lo, n, feats, guard);
   } else if (fr.hw == 64) {
-    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 8, 3>), dim3((unsigned)blocks), dim3(256), 0, s, fr, n, feats);
+    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 8, 3>), dim3((unsigned)blocks), dim3(256), 0, s, fr, lo, n, feats, guard);
   } else if (fr.hw == 128) {
-    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 8, 6>), dim3((unsigned)blocks), dim3(256), 0, s, fr, n, feats);
+    hipLaunchKernelGGL((rnn_pool_vec_kernel<T, 8, 6>), dim3((unsigned)blocks), dim3(256), 0, s, fr, lo, n, feats, guard);
   } else {
     return false;
   }
@@ -571,22 +583,25 @@ void router_nn_reset(RouterNN* r, hipStream_t s) {
   hipStreamSynchronize(s);
 }
 
-int router_nn_admit(RouterNN* r, const FrameSrc& fr, int64_t n, hipStream_t s) {
+int router_nn_admit(RouterNN* r, const FrameSrc& fr, int64_t lo, int64_t hi, const DevState* guard, hipStream_t s) {
+  const int64_t n = hi - lo;
   if (n <= 0) return HYDRO_OK;
   if (fr.hw != r->fh) return HYDRO_EUNSUPPORTED;
   // vector path: frame sides 32, 64 and 128 (the cell row is a whole number of aligned chunks)
   bool done = false;
   if (reinterpret_cast<uintptr_t>(fr.base) % 16 != 0) {
-  } else if (fr.dtype == HYDRO_DTYPE_BF16) done = launch_pool_vec<__bf16>(fr, n, r->feats, s);
-  else if (fr.dtype == HYDRO_DTYPE_U8) done = launch_pool_vec<uint8_t>(fr, n, r->feats, s);
-  else done = launch_pool_vec<float>(fr, n, r->feats, s);
+  } else if (fr.dtype == HYDRO_DTYPE_BF16) done = launch_pool_vec<__bf16>(fr, lo, n, r->feats, guard, s);
+  else if (fr.dtype == HYDRO_DTYPE_U8) done = launch_pool_vec<uint8_t>(fr, lo, n, r->feats, guard, s);
+  else done = launch_pool_vec<float>(fr, lo, n, r->feats, guard, s);
   if (!done) {
     const int64_t work = n * RF;
     const int grid = (int)std::min<int64_t>(4096, (work + 255) / 256);
-    hipLaunchKernelGGL(rnn_pool_kernel, dim3(grid), dim3(256), 0, s, fr, n, r->feats);
+    hipLaunchKernelGGL(rnn_pool_kernel, dim3(grid), dim3(256), 0, s, fr, lo, n, r->feats, guard);
   }
   return HYDRO_OK;
 }
+
+__bf16* router_nn_feats_ptr(RouterNN* r) { return r->feats; }
 
 void router_nn_keys(RouterNN* r, DevState* st, const uint32_t* pend_in, int in_slot, uint32_t adm_lo,
                     uint32_t adm_hi, int grid, hipStream_t s) {
@@ -613,5 +628,8 @@ OutcomeLog router_nn_log(RouterNN* r) {
 }
 
 int router_nn_min_steps() { return MIN_STEPS; }
+// Training takes at most TSTEPS steps a round, after the round's passes: keys can first be
+// learned in this round (0-based).
+int router_nn_first_learned_round() { return (MIN_STEPS + TSTEPS - 1) / TSTEPS; }
 
 }  // namespace hydro
