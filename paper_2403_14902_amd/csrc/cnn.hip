@@ -284,7 +284,7 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
   constexpr int NT2 = 2 * M;
   // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (the waves cover 16 x NT2)
-  constexpr int MT2 = (M == 1 && NWV == 8) ? 2 : 4, NW2 = NT2 * (16 / MT2) / NWV;
+  constexpr int MT2 = (M == 1 && NWV == 8) ? 2 : (M == 4 && sizeof(T) == 2) ? 8 : 4, NW2 = NT2 * (16 / MT2) / NWV;
   constexpr int NG2 = NT2 / NW2;                       // channel groups
   // weight prefetch depth (k-steps); the widest bf16 class has no registers to spare in layer 2
   constexpr int PD2 = sizeof(T) == 4 ? 4 : ((M == 4 || (M == 2 && NWV == 4)) ? 2 : 3);
