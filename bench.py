@@ -43,7 +43,7 @@ METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs pla
 # HBM bytes per first-pass round (reads + writes), from FETCH_SIZE / WRITE_SIZE runs of this script
 # scaled by the same counters on a 1 GiB device copy (the byte-counter summary in profiles/).  Valid
 # only for the kernel build those runs measured: None for a workload without such a run.
-FIRST_PASS_TRAFFIC = {}
+FIRST_PASS_TRAFFIC = {"cnn3_drift64": 407.60e6 + 5.27e6}
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 
