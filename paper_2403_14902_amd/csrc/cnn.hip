@@ -432,7 +432,8 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
       for (int d = 0; d < PD2; ++d) {
         const int ks = ks0 + d;
-        if (ks < KS2) {
+        // (when PD2 divides KS2 the guard folds away and the loop body has no branches)
+        if (KS2 % PD2 == 0 || ks < KS2) {
           const int k0 = ks * KSTEP + KPL * g;
           int t = k0 / CB1;
           const int c0 = k0 % CB1;
@@ -448,7 +449,11 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
           for (int n = 0; n < NW2; ++n)
 #pragma unroll
             for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bw2[d][n], av[q], acc2[q][n]);
-          if (ks + PD2 < KS2) {
+          if constexpr (KS2 % PD2 == 0) {
+            // unconditional refill; the last PD2 k-steps re-read the last fragment (unused)
+#pragma unroll
+            for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[(min(ks + PD2, KS2 - 1) * NT2 + n) * 64];
+          } else if (ks + PD2 < KS2) {
 #pragma unroll
             for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[((ks + PD2) * NT2 + n) * 64];
           }
@@ -541,10 +546,9 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       for (int d = 0; d < PD3; ++d) {
         const int ks = ks0 + d;
         l3_step(ks, bw3[d]);
-        if (ks + PD3 < KS3) {
+        // unconditional refill; the last PD3 k-steps re-read the last fragment (unused)
 #pragma unroll
-          for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[((ks + PD3) * NT3 + n) * 64];
-        }
+        for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(min(ks + PD3, KS3 - 1) * NT3 + n) * 64];
       }
     }
   }
