@@ -393,6 +393,21 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
         l1_store(mt, acc0);
         l1_store(mt + 1, acc1);
       }
+    } else if constexpr (!kCacheA1) {
+      // FP32 (7 k-steps): tiles in pairs as well, two independent accumulation chains
+#pragma unroll 1
+      for (int q = 0; q < MPW; q += 2) {
+        const int mt = wave * MPW + q;
+        floatx4 acc0 = (floatx4){0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {
+          const frag av0 = gather1(mt, ks), av1 = gather1(mt + 1, ks);
+          acc0 = mfma(w1f[ks], av0, acc0);
+          acc1 = mfma(w1f[ks], av1, acc1);
+        }
+        l1_store(mt, acc0);
+        l1_store(mt + 1, acc1);
+      }
     } else {
 #pragma unroll 8
       for (int q = 0; q < MPW; ++q) {
