@@ -13,12 +13,14 @@ survivors, materialise the sorted ids) and copy ids and statistics to the host.
 Forms:
   full   learned content-based router (score routing as control arm, judge and fallback) +
          grouped persistent launches per round (MLP tile shapes from the autotuner, timed at
-         setup) + first pass in BF16 on MFMA (fp32 accumulate) with margins within tau
-         re-scored in FP32 and within tau32 in FP64.  `value`.
-  score  as full, but score-driven routing only.
-  plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate.
-  The timed runs record HIP events around each round's phases (for the roofline); the same
-  forms replayed from a captured HIP graph are reported as `graph_value`.
+         setup), each whole push captured once in a HIP graph (at setup) and replayed + first
+         pass in BF16 on MFMA (fp32 accumulate) with margins within tau re-scored in FP32 and
+         within tau32 in FP64.  `value`.
+  eager  the full form launched kernel by kernel, with HIP events recorded around each round's
+         phases: the roofline, phase times and statistics come from this run (`eager_value`).
+  score  as eager, but score-driven routing only.
+  plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate,
+         no graph.
   Every form's session calibrates its per-predicate bands at setup (untimed): tau_k and tau32_k
   are `--safety` (2) times the largest margin error of the first pass / FP32 pass against the
   FP64 pass on 8,192 separate frames of the same generator (--no-calibrate: fixed bands 0.015 /
@@ -194,7 +196,8 @@ def main():
         "config": {"workload": f"{cfg.name}: {n} frames {cfg.hw}x{cfg.hw}x3 {cfg.dtype}, "
                                f"{cfg.k} predicates, {cfg.n_seg} threshold segments"
                                + (f" (first {n} of {cfg.n} tuples)" if n < cfg.n else ""),
-                   "form": "full: bf16 first pass + fp32/fp64 re-score, " + args.route + " routing, grouped",
+                   "form": "full: bf16 first pass + fp32/fp64 re-score, " + args.route + " routing, grouped, "
+                           "each push replayed from a captured HIP graph",
                    "wave": args.wave, "tuples_per_step": n},
         "roofline": {
             "bound": "mfma",
@@ -235,7 +238,12 @@ def main():
     ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, args.steps,
                                 args.warmup, n, cal, args.safety)
     assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
-    out["graph_value"] = n * args.steps / dtg
+    # headline: the full form as deployed (graph replay); the instrumented eager run beside it
+    out["eager_value"] = value
+    out["eager_ms_per_step"] = ms_per_step
+    value = n * args.steps / dtg
+    out["value"] = value
+    out["ms_per_step"] = dtg * 1e3 / args.steps
 
     if args.route != "score":
         log("[bench] score form")
