@@ -465,9 +465,12 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
             for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bw2[d][n], av[q], acc2[q][n]);
           if constexpr (KS2 % PD2 == 0) {
-            // unconditional refill; the last PD2 k-steps re-read the last fragment (unused)
+            // unconditional refill; the last PD2 k-steps re-read the last fragment (unused).  The
+            // scheduling barrier keeps the loads here: sunk to the end of the iteration (to
+            // shorten register lifetimes) they would be waited on right after being issued.
 #pragma unroll
             for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[(min(ks + PD2, KS2 - 1) * NT2 + n) * 64];
+            __builtin_amdgcn_sched_barrier(0);
           } else if (ks + PD2 < KS2) {
 #pragma unroll
             for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[((ks + PD2) * NT2 + n) * 64];
@@ -561,9 +564,11 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       for (int d = 0; d < PD3; ++d) {
         const int ks = ks0 + d;
         l3_step(ks, bw3[d]);
-        // unconditional refill; the last PD3 k-steps re-read the last fragment (unused)
+        // unconditional refill; the last PD3 k-steps re-read the last fragment (unused); kept in
+        // place by the scheduling barrier as in layer 2
 #pragma unroll
         for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(min(ks + PD3, KS3 - 1) * NT3 + n) * 64];
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
