@@ -120,7 +120,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus above 1 is not supported "
-                                   "(the multi-GPU sharding design is described in DESIGN.md)"}))
+                                   "(sharding across GPUs is a design note only, nothing runs on several)"}))
         sys.exit(2)
     import torch
     import hydro_synth as hs
