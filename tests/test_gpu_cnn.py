@@ -26,6 +26,27 @@ def c2():
     return case(2, 16384)
 
 
+@pytest.mark.parametrize("tier", [0, 1])
+def test_cnn_logits_batch_invariant_across_entry_ring_refills(tier):
+    """One logits call over 70,000 frames (each workgroup then takes more than 128 frames, so the
+    LDS ring holding its queue entries is refilled at least twice) equals four calls of 17,500
+    frames bit for bit: a frame's logits do not depend on the batch it travels in."""
+    cfg = hs.workload(2)
+    n, blk = 70000, 17500
+    frames = hs.make_frames_parallel(cfg, 0, n)
+    pt = hs.load_predicates(cfg)
+    specs = [hydro.ModelSpec.from_weights(hs.make_model(d), m) for d, m in zip(cfg.models, pt.class_masks)]
+    s = hydro.Session(specs, hydro.make_policy("score", precision="bf16"), 64, n)
+    dev = torch.from_numpy(frames).cuda()
+    for k in (0, 2):          # the narrowest and the widest class
+        log(f"[gpu] ring refills: tier {tier} predicate {k}, {n} frames")
+        z_all = s.logits(k, tier, dev, cfg.dtype)
+        z_blk = np.concatenate([s.logits(k, tier, dev[lo:lo + blk].contiguous(), cfg.dtype)
+                                for lo in range(0, n, blk)])
+        assert np.array_equal(z_all, z_blk)
+    s.close()
+
+
 @pytest.mark.parametrize("prec,tier,tol", [("bf16", 0, 0.1), ("bf16", 1, 1e-4), ("fp32", 0, 1e-4), ("bf16", 2, 1e-10)])
 def test_cnn_logits_each_tier_vs_oracle(c2small, prec, tier, tol):
     c = c2small
