@@ -308,9 +308,6 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       for (int n = 0; n < NW2; ++n)
         if (d < KS2) bw2_0[d][n] = w2p0[(d * NT2 + n) * 64];
   }
-  // The frame loads are issued whether or not a next frame exists (next_idx is then the current
-  // frame and nothing is stored): a conditional issue would leave the compiler unsure how many
-  // loads are outstanding, and every later weight wait would then also wait for the frame.
   // First evaluation of a tuple in the first pass: its router features, from the frame in LDS.
   // Early fetch: computed now and stored by every wave right after the frame loads are issued
   // (everything waited on later already waits for those loads, which complete in issue order).
@@ -318,6 +315,9 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   const float fscale = (a.fr.dtype == HYDRO_DTYPE_U8 ? 1.0f / 255.0f : 1.0f) * (1.0f / 64.0f);
   FrameFeat<NT> ff;
   if (kEarlyFetch && feat_dst != nullptr) frame_features<NT>(FR, fscale, ff);
+  // The frame loads are issued whether or not a next frame exists (next_idx is then the current
+  // frame and nothing is stored): a conditional issue would leave the compiler unsure how many
+  // loads are outstanding, and every later weight wait would then also wait for the frame.
   FramePrefetch<NT> pf;
   if (kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
   if (kEarlyFetch && feat_dst != nullptr) frame_features_put<NT>(ff, feat_dst);
