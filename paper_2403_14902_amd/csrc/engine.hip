@@ -1344,9 +1344,12 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       if (s->rnn) {
         ra.olog = router_nn_log(s->rnn);
         ra.min_steps = router_nn_min_steps();
-        if (s->fused_feats && r < (int)adm.size() && r >= router_nn_first_learned_round())
-          router_nn_admit(s->rnn, src, adm[r].first, adm[r].second, s->st, st);
-        router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
+        // before the round in which the learned arm can first route, no keys are read
+        if (r >= router_nn_first_learned_round()) {
+          if (s->fused_feats && r < (int)adm.size())
+            router_nn_admit(s->rnn, src, adm[r].first, adm[r].second, s->st, st);
+          router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
+        }
       }
       hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
       if (timed && ev[1]) hipEventRecord(ev[1], st);
