@@ -171,7 +171,27 @@ typedef struct {
   double f64_pass_ms;                      /* FP64 escalation launches                            */
   uint32_t timed_rounds;                   /* rounds bracketed                                    */
   uint32_t pad_;
+  uint64_t learned_stale;                  /* LEARNED: learned-arm decisions whose keys had not
+                                              been computed in the deciding round (routed by the
+                                              statistics ranking instead; 0 in a correct run)    */
 } hydro_query_info;
+
+/* One routing round of the last query (policy.log_routes = 1), for checking the router against
+ * the policy definitions of section 4.1 ("Cost-Driven Routing Policy", "System Variants"): the
+ * per-predicate counts of the previous round that were folded into the running estimates at the
+ * start of this round, the estimates after the fold, and the ranking this round's router used. */
+typedef struct {
+  int32_t order[HYDRO_MAX_PREDICATES];              /* order[0] is the preferred predicate       */
+  uint64_t folded_evaluated[HYDRO_MAX_PREDICATES];  /* previous round's first-pass evaluations   */
+  uint64_t folded_passed[HYDRO_MAX_PREDICATES];     /* ... and passes                             */
+  double selectivity[HYDRO_MAX_PREDICATES];         /* running estimates after the fold: EWMA of
+                                                       (passed + 1) / (evaluated + 2)             */
+  double cost[HYDRO_MAX_PREDICATES];                /* device ticks per evaluation, or the model's
+                                                       FLOPs with cost_source = STATIC            */
+  uint32_t seen_mask;                               /* bit k: predicate k had statistics when the
+                                                       ranking was made (unseen ones go first)    */
+  uint32_t pad_;
+} hydro_round_record;
 
 typedef struct hydro_session hydro_session;
 
@@ -218,9 +238,16 @@ int hydro_session_info(const hydro_session* s, hydro_query_info* out);
  * evaluated, 0 after the last one.  n must not exceed the tuples of the last push. */
 int hydro_session_routes(const hydro_session* s, int64_t first_id, int64_t n, uint32_t* out);
 
+/* Debug: records first .. first + n - 1 of the last query's rounds (policy.log_routes = 1; at most
+ * the first 16,384 rounds are recorded).  out: caller-allocated [n].  EINVAL outside the recorded
+ * rounds, ESTATE without log_routes. */
+int hydro_session_round_log(const hydro_session* s, int32_t first, int32_t n, hydro_round_record* out);
+
 /* Evaluate predicate `pred`'s model on every given tuple at one arithmetic tier
  * (0 = the first-pass precision of the session, 1 = FP32, 2 = FP64) and return its logits as
- * fp64 [n][10] in host memory.  Used for logit-error reports and kernel parity tests. */
+ * fp64 [n][10] in host memory.  Used for logit-error reports and kernel parity tests.  Runs between
+ * queries only: ESTATE while a query is open (a push since the last reset or finish); it leaves
+ * the session reset. */
 int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hydro_frames* frames,
                          double* out_logits);
 
@@ -230,11 +257,31 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
  * use these bands instead of policy.tau / policy.tau32.  out_tau / out_tau32: caller-allocated
  * [K] (may be NULL).  Any number of frames (>= 1); more than the session's max_push are taken
  * in blocks of max_push.  This is the per-configuration band of the low-precision form: an
- * empirical bound, so the sample should be representative of the query's frames. */
+ * empirical bound, so the sample should be representative of the query's frames.  Runs between
+ * queries only (ESTATE while a push is open); it leaves the session reset, and pushes captured in
+ * HIP graphs under the old bands are discarded (they are re-captured with the new ones). */
 int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float safety, float* out_tau,
                             float* out_tau32);
 
+/* Replace the written order that route = FIXED follows (section 4.1, "No Reordering": the
+ * conjunction evaluated left to right) for the session's next queries.  order: a permutation of
+ * 0..K-1.  EINVAL if it is not one; ESTATE while a query is open. */
+int hydro_session_set_order(hydro_session* s, const int32_t* order);
+
 int hydro_session_destroy(hydro_session* s);
+
+/* Debug: one launch of the learned router's online-training kernel (content-based routing,
+ * section 2.2; the router MLP 192-64-8 predicts for each predicate the probability that it rejects
+ * the tuple) on caller data in host memory, for checking its arithmetic.  n = 128 logged outcomes,
+ * oldest first: feats [n][192] bf16 bit patterns, pred [n] (0 <= pred < k <= 8), rejected [n]
+ * (1 = the predicate rejected the tuple).  The kernel takes two Adam steps (beta 0.9 / 0.999,
+ * eps 1e-8, learning rate lr) of masked binary cross-entropy (only the output of the evaluated
+ * predicate), first on samples 64..127, then on 0..63; steps_done is the number of steps already
+ * taken (Adam's bias correction).  params: W1 [192][64] | b1 [64] | W2 [64][8] | b2 [8] fp32
+ * (12,872 values), adam_m / adam_v the moments in the same layout; all three are updated in place.
+ * Allocates and frees its own device memory; EINVAL on bad sizes, EDEVICE on a HIP failure. */
+int hydro_router_train_debug(int32_t k, const uint16_t* feats, const int32_t* pred, const uint8_t* rejected,
+                             int32_t n, float* params, float* adam_m, float* adam_v, int32_t steps_done, float lr);
 
 /* Release memory returned by the library. */
 void hydro_free(void* p);

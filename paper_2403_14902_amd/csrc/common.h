@@ -74,6 +74,8 @@ struct DevState {
   int n_result;
   // learned router
   unsigned long long learned_routed, stats_routed;
+  unsigned long long learned_stale;    // learned-arm decisions whose keys were not computed this
+                                       // round (routed by the ranking instead)
   double arm_cost[2], arm_tuples[2];   // judge: realised UDF FLOPs and finished tuples per arm
   int learned_active;                  // 0 once the judge has fallen back to score routing
   int train_steps;

@@ -76,11 +76,15 @@ struct FoldArgs {
   double flops[kMaxK];
   int out_slot;         // pend_count slot that receives this round's survivors
   int final_fold;       // 1: only fold counts (after the last round)
+  hydro_round_record* rlog;   // debug: one record per round (nullptr: not recorded)
+  int rlog_cap;
 };
 
 __global__ void k_fold(FoldArgs a) {
   DevState* st = a.st;
   const int k = threadIdx.x;
+  const int rec = st->rounds;   // this round's number (read before thread 0 advances it)
+  hydro_round_record* rr = (a.rlog != nullptr && !a.final_fold && rec < a.rlog_cap) ? a.rlog + rec : nullptr;
   if (k < a.k) {
     unsigned long long e = st->r_eval[k], p = st->r_pass[k], tk = st->r_ticks[k];
     st->t_eval[k] += e;
@@ -103,6 +107,12 @@ __global__ void k_fold(FoldArgs a) {
     }
     st->r_eval[k] = st->r_pass[k] = st->r_ticks[k] = st->r_rescored[k] = st->r_esc[k] = 0;
     st->qcount[k] = st->bcount[k] = st->ecount[k] = 0;
+    if (rr != nullptr) {
+      rr->folded_evaluated[k] = e;
+      rr->folded_passed[k] = p;
+      rr->selectivity[k] = st->sel_est[k];
+      rr->cost[k] = st->cost_est[k];
+    }
   }
   __syncthreads();
   if (k == 0 && !a.final_fold) {
@@ -128,6 +138,14 @@ __global__ void k_fold(FoldArgs a) {
         st->order[r] = best;
       }
     }
+    if (rr != nullptr) {
+      uint32_t seen = 0;
+      for (int j = 0; j < a.k; ++j) {
+        rr->order[j] = st->order[j];
+        seen |= st->seen[j] ? 1u << j : 0u;
+      }
+      rr->seen_mask = seen;
+    }
   }
 }
 
@@ -141,14 +159,20 @@ struct RouteArgs {
   int k;
   Queues q;
   const float* learned_keys;   // LEARNED: per-tuple keys [idx][K] (nullptr otherwise)
+  const uint32_t* key_stamps;  // LEARNED: round in which each tuple's keys were computed
   OutcomeLog olog;             // LEARNED: arm assignment of routing batches
   int min_steps;               // LEARNED: optimiser steps before the learned arm uses the keys
 };
 
-__device__ inline bool learned_arm(const RouteArgs& a, uint32_t e) {
+// The tuple belongs to the learned arm and the router is active (keys may still be missing).
+__device__ inline bool learned_eligible(const RouteArgs& a, uint32_t e) {
   return a.learned_keys != nullptr && !(a.warmup && entry_mask(e) == 0) && a.st->learned_active &&
          a.st->train_steps >= a.min_steps &&
          arm_of(entry_idx(e) / (uint32_t)a.routing_batch, a.olog.seed, a.olog.control_below) == 1;
+}
+// ... and its keys were computed in this round (DevState::rounds is this round's stamp).
+__device__ inline bool learned_arm(const RouteArgs& a, uint32_t e) {
+  return learned_eligible(a, e) && a.key_stamps[entry_idx(e)] == (uint32_t)a.st->rounds;
 }
 
 __device__ inline int choose_pred(const RouteArgs& a, uint32_t e, const int* order) {
@@ -187,9 +211,11 @@ __global__ __launch_bounds__(256) void k_route(RouteArgs a) {
       k = choose_pred(a, e, order);
     }
     if (a.learned_keys != nullptr) {
-      bool learned = active && learned_arm(a, e);
+      const bool eligible = active && learned_eligible(a, e);
+      const bool learned = eligible && learned_arm(a, e);
       wave_add_u64(&a.st->learned_routed, learned && entry_mask(e) == 0);
       wave_add_u64(&a.st->stats_routed, active && !learned && entry_mask(e) == 0);
+      wave_add_u64(&a.st->learned_stale, eligible && !learned);
     }
     for (int j = 0; j < a.k; ++j) {
       bool mine = active && k == j;
@@ -294,11 +320,13 @@ struct GraphKey {
   int64_t seg_len;
   int warm;
   int parity;
+  int learned_from;   // first round of the push that runs the learned router's keys
   const void* theta;
   const void* out;
   bool operator==(const GraphKey& o) const {
     return n == o.n && base == o.base && id_base == o.id_base && n_seg == o.n_seg && seg_len == o.seg_len &&
-           warm == o.warm && parity == o.parity && theta == o.theta && out == o.out;
+           warm == o.warm && parity == o.parity && learned_from == o.learned_from && theta == o.theta &&
+           out == o.out;
   }
 };
 
@@ -321,6 +349,8 @@ struct hydro_session {
   uint32_t *q1 = nullptr, *q2 = nullptr, *q3 = nullptr;
   uint32_t* result_bits = nullptr;
   uint32_t* route_log = nullptr;
+  hydro_round_record* round_log = nullptr;   // log_routes: per-round rankings and folded counts
+  int round_log_cap = 0;
   int* res_blocks = nullptr;
   int* res_base = nullptr;
   int64_t* out_ids = nullptr;
@@ -340,6 +370,7 @@ struct hydro_session {
   bool warmed = false;
   int parity = 0;
   int pushes = 0;
+  bool in_query = false;     // pushes since the last reset / finish
   bool ids_sorted = true;
   int64_t last_id_end = INT64_MIN;
   int64_t last_push_n = 0;
@@ -353,6 +384,12 @@ struct hydro_session {
   float tau_k[kMaxK], tau32_k[kMaxK];   // per-predicate bands (policy values or calibrated)
   bool auto_tau = false, auto_tau32 = false;   // bands still to be measured on the first push
 };
+
+// Captured pushes bake the bands (and every other launch argument) into their kernel nodes.
+static void drop_graphs(hydro_session* s) {
+  for (auto& g : s->graphs) hipGraphExecDestroy(g.second);
+  s->graphs.clear();
+}
 
 static hipEvent_t next_event(hydro_session* s) {
   if (s->ev_used == (int)s->evpool.size()) {
@@ -845,6 +882,11 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   if ((rc = sess_alloc(s, (void**)&s->res_blocks, ((nwords + 255) / 256 + 1) * 4))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->res_base, 16))) return bail(rc);
   if (s->pol.log_routes && (rc = sess_alloc(s, (void**)&s->route_log, cap * 4))) return bail(rc);
+  if (s->pol.log_routes) {
+    s->round_log_cap = 16384;
+    if ((rc = sess_alloc(s, (void**)&s->round_log, (size_t)s->round_log_cap * sizeof(hydro_round_record))))
+      return bail(rc);
+  }
   if ((rc = sess_alloc(s, (void**)&s->theta, 4096 * sizeof(float)))) return bail(rc);
   s->theta_cap = 4096;
   he = dev_alloc((void**)&s->out_ids, cap * sizeof(int64_t));
@@ -874,6 +916,7 @@ int hydro_session_reset(hydro_session* s) {
   s->warmed = false;
   s->parity = 0;
   s->pushes = 0;
+  s->in_query = false;
   s->ids_sorted = true;
   s->last_id_end = INT64_MIN;
   s->theta_host.clear();
@@ -1187,6 +1230,7 @@ static int auto_bands(hydro_session* s, const hydro_frames& fr) {
     if (s->auto_tau32) s->tau32_k[k] = std::max(tau32[k], kAutoTau32Floor);
   }
   s->auto_tau = s->auto_tau32 = false;
+  drop_graphs(s);
   return HYDRO_OK;
 }
 
@@ -1214,6 +1258,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
 
   if (s->pushes == 0) s->t_start = std::chrono::steady_clock::now();
   s->pushes++;
+  s->in_query = true;
   if (fr.id_base < s->last_id_end) s->ids_sorted = false;
   s->last_id_end = fr.id_base + fr.n;
   s->last_push_n = fr.n;
@@ -1291,6 +1336,10 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   const int n_rounds = adm.empty() ? 0 : (int)adm.size() + s->K - 1;
   const bool timing = s->pol.time_kernels != 0;
   const int parity0 = s->parity;
+  // The learned arm can route from the query's router_nn_first_learned_round()-th round on
+  // (training takes at most a fixed number of steps per round); from that round of the query on,
+  // every round computes the keys of its live tuples, whichever push it belongs to.
+  const int learned_from = s->rnn ? std::max(0, router_nn_first_learned_round() - s->rounds_done) : 0;
   const int64_t nwords = (n + 31) / 32;
 
   // Every device step of the push, in stream order.  Host state is not touched here, so the
@@ -1323,6 +1372,8 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       fa.static_cost = s->pol.cost_source == HYDRO_COST_STATIC;
       fa.out_slot = out_slot;
       fa.final_fold = 0;
+      fa.rlog = s->round_log;
+      fa.rlog_cap = s->round_log_cap;
       hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, fa);
 
       RouteArgs ra{};
@@ -1341,11 +1392,12 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       ra.k = s->K;
       ra.q = Queues{s->q1, s->st->qcount, s->cap};
       ra.learned_keys = s->rnn ? router_nn_keys_ptr(s->rnn) : nullptr;
+      ra.key_stamps = s->rnn ? router_nn_stamps_ptr(s->rnn) : nullptr;
       if (s->rnn) {
         ra.olog = router_nn_log(s->rnn);
         ra.min_steps = router_nn_min_steps();
         // before the round in which the learned arm can first route, no keys are read
-        if (r >= router_nn_first_learned_round()) {
+        if (r >= learned_from) {
           if (s->fused_feats && r < (int)adm.size())
             router_nn_admit(s->rnn, src, adm[r].first, adm[r].second, s->st, st);
           router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
@@ -1386,7 +1438,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
 
   const bool graphable = s->pol.use_graph && fr.where == HYDRO_MEM_DEVICE && !timing;
   if (graphable) {
-    GraphKey key{n, src.base, fr.id_base, n_seg, seg_len, (int)warm_now, parity0, s->theta, s->out_ids};
+    GraphKey key{n, src.base, fr.id_base, n_seg, seg_len, (int)warm_now, parity0, learned_from, s->theta, s->out_ids};
     hipGraphExec_t exec = nullptr;
     for (auto& e : s->graphs)
       if (e.first == key) exec = e.second;
@@ -1461,6 +1513,7 @@ int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hy
   s->info.rounds = h.rounds;
   s->info.k = s->K;
   s->info.learned_routed = h.learned_routed;
+  s->info.learned_stale = h.learned_stale;
   s->info.stats_routed = h.stats_routed;
   s->info.learned_active = h.learned_active;
   s->info.train_steps = h.train_steps;
@@ -1480,6 +1533,7 @@ int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hy
   *out_ids = ids;
   *out_n = nres;
   s->theta_host.clear();
+  s->in_query = false;
   return HYDRO_OK;
 }
 
@@ -1498,11 +1552,24 @@ int hydro_session_routes(const hydro_session* s, int64_t first_id, int64_t n, ui
   return HYDRO_OK;
 }
 
+int hydro_session_round_log(const hydro_session* s, int32_t first, int32_t n, hydro_round_record* out) {
+  if (!s || !out) return fail(HYDRO_EINVAL, "NULL argument");
+  if (!s->round_log) return fail(HYDRO_ESTATE, "session was created without log_routes");
+  const int64_t have = std::min<int64_t>(s->info.rounds, s->round_log_cap);
+  if (first < 0 || n < 0 || (int64_t)first + n > have) return fail(HYDRO_EINVAL, "range outside the recorded rounds");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (n > 0) HIP_TRY(hipMemcpy(out, s->round_log + first, (size_t)n * sizeof(hydro_round_record), hipMemcpyDeviceToHost));
+  return HYDRO_OK;
+}
+
 int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hydro_frames* frames, double* out_logits) {
   g_err.clear();
   if (!s || !frames || !out_logits) return fail(HYDRO_EINVAL, "NULL argument");
   if (pred < 0 || pred >= s->K) return fail(HYDRO_EINVAL, "predicate index out of range");
   if (tier < 0 || tier > 2) return fail(HYDRO_EINVAL, "tier must be 0, 1 or 2");
+  if (s->in_query)
+    return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): logits and "
+                              "calibration run between queries");
   const hydro_frames& fr = *frames;
   if (fr.where != HYDRO_MEM_DEVICE) return fail(HYDRO_EUNSUPPORTED, "logits take device frames");
   if (fr.n <= 0 || fr.n > s->max_push) return fail(HYDRO_ECAPACITY, "tuple count outside 1..max_push");
@@ -1587,6 +1654,9 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
   g_err.clear();
   if (!s || !frames) return fail(HYDRO_EINVAL, "NULL argument");
   if (!(safety >= 1.f)) return fail(HYDRO_EINVAL, "safety must be at least 1");
+  if (s->in_query)
+    return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): calibrate "
+                              "between queries");
   float tau[kMaxK], tau32[kMaxK];
   int rc = measure_bands(s, frames, safety, tau, tau32);
   if (rc) return rc;
@@ -1597,6 +1667,22 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
     if (out_tau32) out_tau32[k] = tau32[k];
   }
   s->auto_tau = s->auto_tau32 = false;
+  drop_graphs(s);   // captured pushes hold the old bands in their kernel arguments
+  return HYDRO_OK;
+}
+
+int hydro_session_set_order(hydro_session* s, const int32_t* order) {
+  g_err.clear();
+  if (!s || !order) return fail(HYDRO_EINVAL, "NULL argument");
+  if (s->in_query) return fail(HYDRO_ESTATE, "a query is in progress: change the order between queries");
+  unsigned seen = 0;
+  for (int i = 0; i < s->K; ++i) {
+    const int o = order[i];
+    if (o < 0 || o >= s->K || (seen >> o) & 1u) return fail(HYDRO_EINVAL, "order is not a permutation of 0..K-1");
+    seen |= 1u << o;
+  }
+  for (int i = 0; i < s->K; ++i) s->pol.order[i] = order[i];
+  drop_graphs(s);   // the order is a launch argument of the captured fold kernels
   return HYDRO_OK;
 }
 

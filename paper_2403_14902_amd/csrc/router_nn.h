@@ -24,6 +24,8 @@ void router_nn_keys(RouterNN* r, DevState* st, const uint32_t* pend_in, int in_s
 // Optimiser steps on the newest logged outcomes, then the judge.
 void router_nn_learn(RouterNN* r, DevState* st, hipStream_t s);
 const float* router_nn_keys_ptr(RouterNN* r);
+// Per tuple: the round (DevState::rounds) in which its keys were last computed.
+const uint32_t* router_nn_stamps_ptr(RouterNN* r);
 OutcomeLog router_nn_log(RouterNN* r);
 int router_nn_min_steps();
 // First round (0-based) in which the learned arm can route.

@@ -38,6 +38,7 @@ struct RouterNN {
   float explore;
   __bf16* feats = nullptr;        // [cap][192]
   float* keys = nullptr;          // [cap][K]
+  uint32_t* stamps = nullptr;     // [cap]: round whose keys kernel wrote the tuple's keys
   uint32_t* ring = nullptr;
   float* params = nullptr;        // W1 [192][64] | b1 [64] | W2 [64][8] | b2 [8]
   float* adam_m = nullptr;
@@ -185,6 +186,7 @@ struct KeyArgs {
   const __bf16* w1_frag;
   const float* params;
   float* keys;
+  uint32_t* stamps;
   int k;
 };
 
@@ -240,6 +242,7 @@ __global__ __launch_bounds__(256) void rnn_keys_kernel(KeyArgs a) {
         const float p = 1.0f / (1.0f + __expf(-(o[j] + b2[j])));
         a.keys[(int64_t)idx * a.k + j] = (float)(cost[j] / fmaxf(p, 0.02f));
       }
+      a.stamps[idx] = (uint32_t)st->rounds;
     }
   }
 }
@@ -540,6 +543,7 @@ int router_nn_create(RouterNN** out, int k, int fh, int fw, int64_t cap, uint64_
   r->explore = explore;
   bool ok = hipMalloc(&r->feats, (size_t)cap * RF * sizeof(__bf16)) == hipSuccess &&
             hipMalloc(&r->keys, (size_t)cap * k * sizeof(float)) == hipSuccess &&
+            hipMalloc(&r->stamps, (size_t)cap * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(&r->ring, (size_t)RING * sizeof(uint32_t)) == hipSuccess &&
             hipMalloc(&r->params, NPARAM * sizeof(float)) == hipSuccess &&
             hipMalloc(&r->adam_m, NPARAM * sizeof(float)) == hipSuccess &&
@@ -567,6 +571,7 @@ void router_nn_destroy(RouterNN* r) {
   if (!r) return;
   hipFree(r->feats);
   hipFree(r->keys);
+  hipFree(r->stamps);
   hipFree(r->ring);
   hipFree(r->params);
   hipFree(r->adam_m);
@@ -580,6 +585,8 @@ void router_nn_reset(RouterNN* r, hipStream_t s) {
   hipMemcpyAsync(r->params, r->init.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s);
   hipMemsetAsync(r->adam_m, 0, NPARAM * sizeof(float), s);
   hipMemsetAsync(r->adam_v, 0, NPARAM * sizeof(float), s);
+  // no tuple has keys of this query yet (round numbers restart at every reset)
+  hipMemsetAsync(r->stamps, 0xFF, (size_t)r->cap * sizeof(uint32_t), s);
   hipStreamSynchronize(s);
 }
 
@@ -605,7 +612,7 @@ __bf16* router_nn_feats_ptr(RouterNN* r) { return r->feats; }
 
 void router_nn_keys(RouterNN* r, DevState* st, const uint32_t* pend_in, int in_slot, uint32_t adm_lo,
                     uint32_t adm_hi, int grid, hipStream_t s) {
-  KeyArgs a{st, pend_in, in_slot, adm_lo, adm_hi, r->feats, r->w1_frag, r->params, r->keys, r->k};
+  KeyArgs a{st, pend_in, in_slot, adm_lo, adm_hi, r->feats, r->w1_frag, r->params, r->keys, r->stamps, r->k};
   hipLaunchKernelGGL(rnn_keys_kernel, dim3(grid), dim3(256), 0, s, a);
 }
 
@@ -615,6 +622,7 @@ void router_nn_learn(RouterNN* r, DevState* st, hipStream_t s) {
 }
 
 const float* router_nn_keys_ptr(RouterNN* r) { return r->keys; }
+const uint32_t* router_nn_stamps_ptr(RouterNN* r) { return r->stamps; }
 
 OutcomeLog router_nn_log(RouterNN* r) {
   OutcomeLog o{};
@@ -628,6 +636,57 @@ OutcomeLog router_nn_log(RouterNN* r) {
 }
 
 int router_nn_min_steps() { return MIN_STEPS; }
+
+}  // namespace hydro
+
+// Debug entry (declared in include/hydro.h): one launch of the training kernel on caller data.
+extern "C" int hydro_router_train_debug(int32_t k, const uint16_t* feats, const int32_t* pred, const uint8_t* rejected,
+                                        int32_t n, float* params, float* adam_m, float* adam_v, int32_t steps_done,
+                                        float lr) {
+  using namespace hydro;
+  if (!feats || !pred || !rejected || !params || !adam_m || !adam_v) return HYDRO_EINVAL;
+  if (k < 1 || k > RK || n != TSTEPS * TB || steps_done < 0) return HYDRO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (pred[i] < 0 || pred[i] >= k) return HYDRO_EINVAL;
+  DevState* st = nullptr;
+  uint32_t* ring = nullptr;
+  __bf16* f = nullptr;
+  float *p = nullptr, *m = nullptr, *v = nullptr;
+  __bf16* frag = nullptr;
+  int rc = HYDRO_OK;
+  bool ok = hipMalloc(&st, sizeof(DevState)) == hipSuccess && hipMalloc(&ring, RING * sizeof(uint32_t)) == hipSuccess &&
+            hipMalloc(&f, (size_t)n * RF * sizeof(__bf16)) == hipSuccess &&
+            hipMalloc(&p, NPARAM * sizeof(float)) == hipSuccess && hipMalloc(&m, NPARAM * sizeof(float)) == hipSuccess &&
+            hipMalloc(&v, NPARAM * sizeof(float)) == hipSuccess &&
+            hipMalloc(&frag, (size_t)(RF / 32) * 4 * 64 * 8 * sizeof(__bf16)) == hipSuccess;
+  if (!ok) rc = HYDRO_ENOMEM;
+  if (rc == HYDRO_OK) {
+    DevState h{};
+    h.learned_active = 1;
+    h.train_steps = steps_done;
+    h.ring_head = (unsigned long long)n;     // the samples occupy ring positions 0 .. n-1, oldest first
+    std::vector<uint32_t> r(RING, 0u);
+    for (int i = 0; i < n; ++i) r[i] = (uint32_t)i | ((uint32_t)pred[i] << 24) | (rejected[i] ? 0x80000000u : 0u);
+    ok = hipMemcpy(st, &h, sizeof(h), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(ring, r.data(), RING * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(f, feats, (size_t)n * RF * sizeof(__bf16), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(p, params, NPARAM * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m, adam_m, NPARAM * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(v, adam_v, NPARAM * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) {
+      hipLaunchKernelGGL(rnn_train_kernel, dim3(1), dim3(256), 0, nullptr, st, ring, f, p, m, v, frag, lr);
+      ok = hipDeviceSynchronize() == hipSuccess &&
+           hipMemcpy(params, p, NPARAM * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+           hipMemcpy(adam_m, m, NPARAM * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+           hipMemcpy(adam_v, v, NPARAM * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    if (!ok) rc = HYDRO_EDEVICE;
+  }
+  hipFree(st); hipFree(ring); hipFree(f); hipFree(p); hipFree(m); hipFree(v); hipFree(frag);
+  return rc;
+}
+
+namespace hydro {
 // Training takes at most TSTEPS steps a round, after the round's passes: keys can first be
 // learned in this round (0-based).
 int router_nn_first_learned_round() { return (MIN_STEPS + TSTEPS - 1) / TSTEPS; }

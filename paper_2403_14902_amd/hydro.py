@@ -74,7 +74,13 @@ class QueryInfo(C.Structure):
                 ("learned_routed", C.c_uint64), ("stats_routed", C.c_uint64), ("learned_active", C.c_uint32),
                 ("train_steps", C.c_uint32), ("elapsed_us", C.c_double), ("route_ms", C.c_double),
                 ("first_pass_ms", C.c_double), ("f32_pass_ms", C.c_double), ("f64_pass_ms", C.c_double),
-                ("timed_rounds", C.c_uint32), ("pad_", C.c_uint32)]
+                ("timed_rounds", C.c_uint32), ("pad_", C.c_uint32), ("learned_stale", C.c_uint64)]
+
+
+class RoundRecord(C.Structure):
+    _fields_ = [("order", C.c_int32 * MAX_PREDICATES), ("folded_evaluated", C.c_uint64 * MAX_PREDICATES),
+                ("folded_passed", C.c_uint64 * MAX_PREDICATES), ("selectivity", C.c_double * MAX_PREDICATES),
+                ("cost", C.c_double * MAX_PREDICATES), ("seen_mask", C.c_uint32), ("pad_", C.c_uint32)]
 
 
 _lib = None
@@ -99,6 +105,10 @@ def lib():
                                            C.POINTER(PredStats)]
         L.hydro_session_info.argtypes = [vp, C.POINTER(QueryInfo)]
         L.hydro_session_routes.argtypes = [vp, i64, i64, C.POINTER(C.c_uint32)]
+        L.hydro_session_round_log.argtypes = [vp, i32, i32, C.POINTER(RoundRecord)]
+        L.hydro_session_set_order.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.hydro_router_train_debug.argtypes = [i32, C.POINTER(C.c_uint16), C.POINTER(C.c_int32),
+                                               C.POINTER(C.c_uint8), i32, FP, FP, FP, i32, C.c_float]
         L.hydro_session_logits.argtypes = [vp, i32, i32, C.POINTER(Frames), C.POINTER(C.c_double)]
         L.hydro_session_calibrate.argtypes = [vp, C.POINTER(Frames), C.c_float, FP, FP]
         L.hydro_session_destroy.argtypes = [vp]
@@ -107,7 +117,9 @@ def lib():
         L.hydro_last_error.restype = C.c_char_p
         L.hydro_version.restype = C.c_char_p
         for name in ("hydro_query", "hydro_session_create", "hydro_session_reset", "hydro_session_push",
-                     "hydro_session_finish", "hydro_session_info", "hydro_session_routes", "hydro_session_logits",
+                     "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
+                     "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
+                     "hydro_session_logits",
                      "hydro_session_calibrate", "hydro_session_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -116,6 +128,7 @@ def lib():
 
 EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_session_create", "hydro_session_reset",
             "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
+            "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
             "hydro_session_logits", "hydro_session_calibrate", "hydro_session_destroy", "hydro_free",
             "hydro_last_error", "hydro_version")
 
@@ -258,6 +271,20 @@ class Session:
         _check(lib().hydro_session_routes(self._h, first, n, out.ctypes.data_as(C.POINTER(C.c_uint32))))
         return out
 
+    def set_order(self, order: Sequence[int]):
+        """The FIXED route's order for the next queries."""
+        o = (C.c_int32 * MAX_PREDICATES)(*[int(x) for x in order])
+        _check(lib().hydro_session_set_order(self._h, o))
+
+    def round_log(self, first: int, n: int) -> List[Dict]:
+        """Per-round rankings and folded statistics of the last query (policy.log_routes = 1)."""
+        recs = (RoundRecord * max(1, n))()
+        _check(lib().hydro_session_round_log(self._h, first, n, recs))
+        k = self.k
+        return [{"order": list(r.order)[:k], "folded_evaluated": list(r.folded_evaluated)[:k],
+                 "folded_passed": list(r.folded_passed)[:k], "selectivity": list(r.selectivity)[:k],
+                 "cost": list(r.cost)[:k], "seen_mask": r.seen_mask} for r in recs[:n]]
+
     def logits(self, pred: int, tier: int, frames, dtype: str) -> np.ndarray:
         fr = _frames_struct(frames, dtype, 0)
         out = np.zeros((fr.n, 10), dtype=np.float64)
@@ -301,6 +328,24 @@ def query(frames, dtype: str, models: Sequence[ModelSpec], thresholds: np.ndarra
     ids = np.ctypeslib.as_array(ptr, shape=(n.value,)).copy() if n.value > 0 else np.zeros(0, np.int64)
     lib().hydro_free(ptr)
     return ids, _stats_list(st, len(models))
+
+
+ROUTER_NPARAM = 192 * 64 + 64 + 64 * 8 + 8
+
+
+def router_train_debug(k: int, feats_bf16: np.ndarray, pred: np.ndarray, rejected: np.ndarray,
+                       params: np.ndarray, adam_m: np.ndarray, adam_v: np.ndarray, steps_done: int, lr: float):
+    """One launch of the learned router's training kernel (see hydro_router_train_debug);
+    returns updated copies of (params, adam_m, adam_v)."""
+    f = np.ascontiguousarray(feats_bf16, dtype=np.uint16)
+    pr = np.ascontiguousarray(pred, dtype=np.int32)
+    rj = np.ascontiguousarray(rejected, dtype=np.uint8)
+    p, m, v = (np.array(a, dtype=np.float32, copy=True) for a in (params, adam_m, adam_v))
+    _check(lib().hydro_router_train_debug(int(k), f.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                          pr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          rj.ctypes.data_as(C.POINTER(C.c_uint8)), int(f.shape[0]),
+                                          _fp(p), _fp(m), _fp(v), int(steps_done), float(lr)))
+    return p, m, v
 
 
 def decode_routes(codes: np.ndarray) -> List[List[int]]:

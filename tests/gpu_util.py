@@ -29,6 +29,10 @@ class Case:
         self.Z = out[2] if logits else None
         self.expect = ho.result_ids(self.P, id_base=start)
         self.flops = [d.flops() for d in cfg.models]
+        # near-tie audit: "bit-exact against FP64" is well defined only when no margin lies within
+        # FP64 summation-order noise of its threshold
+        self.gap = ho.near_tie_gap(self.D, self.pt.thresholds, self.seg_len, id_base=start)
+        assert self.gap > 1e-9, f"workload {wl} [{start}, {start + n}): margin within {self.gap:.3g} of a threshold"
 
     def specs(self):
         from paper_2403_14902_amd import hydro
@@ -43,7 +47,7 @@ class Case:
 def case(wl: int, n: int, start: int = 0, logits: bool = False) -> Case:
     log(f"[oracle] workload {wl} tuples [{start}, {start + n}) ...")
     c = Case(wl, n, start, logits)
-    log(f"[oracle] workload {wl}: |R| = {c.expect.size}")
+    log(f"[oracle] workload {wl}: |R| = {c.expect.size}, min |d - theta| = {c.gap:.3g}")
     return c
 
 

@@ -363,3 +363,69 @@ def test_frame_chunks_regenerate_independently():
     a = hs.make_frames(cfg, 1000, 100)
     b = hs.make_frames(cfg, 0, 1100)[1000:]
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- threshold rows, static orders, bound
+def test_tuple_thresholds_hand_pin():
+    """theta row of a tuple = its segment, min(id // seg_len, n_seg - 1), from the global id."""
+    th = np.array([[1.0, 10.0], [2.0, 20.0], [3.0, 30.0]], dtype=np.float32)
+    ids = np.array([0, 4, 5, 9, 10, 14, 15, 100])
+    got = ho.tuple_thresholds(th, 5, ids)
+    want = np.array([[1, 10], [1, 10], [2, 20], [2, 20], [3, 30], [3, 30], [3, 30], [3, 30]], dtype=np.float64)
+    assert np.array_equal(got, want)
+    # fp32 thresholds are used as stored (widened exactly)
+    odd = np.array([[0.1]], dtype=np.float32)
+    assert ho.tuple_thresholds(odd, 7, np.array([3]))[0, 0] == float(np.float32(0.1))
+
+
+def test_truth_table_uses_global_ids_for_segments():
+    """Zero weights make every margin the same constant d0 (= max over S of b - max outside S);
+    thresholds just below / above d0 per segment fix which tuples pass, by hand, for a block that
+    starts at id_base = 7 and crosses two segment boundaries (segments of 4 ids)."""
+    m = tiny_mlp(3, 12, 128)
+    t = m.tensors
+    t["W1"][:] = 0
+    t["W2"][:] = 0
+    t["b2"][:] = np.arange(10, dtype=np.float32) * 0.25        # z = b2, class 9 largest
+    mask = 1 << 9                                              # S = {9}: d0 = 2.25 - 2.0 = 0.25
+    th = np.array([[0.3], [0.2], [0.3], [0.2]], dtype=np.float32)   # segment 1 and 3 pass
+    frames = np.zeros((10, 2, 2, 3), dtype=np.float32)
+    P, D = ho.truth_table(frames, "f32", [m], [mask], th, seg_len=4, id_base=7)
+    assert np.allclose(D[:, 0], 0.25)
+    # ids 7..16: segments 1,2,2,2,2,3,3,3,3,3 (id 16 is segment 4 -> clamped to the last row, 3)
+    assert P[:, 0].tolist() == [True, False, False, False, False, True, True, True, True, True]
+    assert ho.result_ids(P, id_base=7).tolist() == [7, 12, 13, 14, 15, 16]
+
+
+HAND_P = np.array([[1, 1, 1], [1, 0, 1], [1, 0, 0], [1, 0, 1], [1, 1, 0], [1, 0, 0]], dtype=bool)
+HAND_F = [1.0, 4.0, 2.0]
+
+
+def test_best_static_order_hand_pin():
+    # totals by hand: (0,1,2) 34, (0,2,1) 30, (1,0,2) 30, (1,2,0) 29, (2,0,1) 27, (2,1,0) 25
+    order, total = ho.best_static_order(HAND_P, HAND_F)
+    assert order == [2, 1, 0] and total == 25.0
+    ev, _ = ho.fixed_order_counts(HAND_P, (0, 1, 2))
+    assert list(ev) == [6, 6, 2] and float(np.dot(ev, HAND_F)) == 34.0
+
+
+def test_clairvoyant_flops_hand_pin():
+    # failing tuples pay their cheapest failing predicate (t1 4, t2 2, t3 4, t4 2, t5 2), the
+    # passing tuple t0 pays all three (7)
+    assert ho.clairvoyant_flops(HAND_P, HAND_F) == 21.0
+
+
+def test_bounds_ordered_on_random_tables():
+    """clairvoyant <= best static <= every static order, and all >= |R| * sum(F)."""
+    rng = np.random.default_rng(3)
+    for trial in range(30):
+        k = int(rng.integers(2, 5))
+        P = rng.random((int(rng.integers(1, 40)), k)) < rng.uniform(0.2, 0.9, k)
+        f = rng.uniform(1, 10, k)
+        best_o, best = ho.best_static_order(P, f)
+        cl = ho.clairvoyant_flops(P, f)
+        floor = P.all(axis=1).sum() * f.sum()
+        assert floor - 1e-9 <= cl <= best + 1e-9
+        for order in itertools.permutations(range(k)):
+            ev, _ = ho.fixed_order_counts(P, order)
+            assert best <= float(np.dot(ev, f)) + 1e-9
