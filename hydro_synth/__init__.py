@@ -165,6 +165,18 @@ def _upsample_matrix(src: int, dst: int) -> np.ndarray:
     return a
 
 
+def _upsample_taps(src: int, dst: int):
+    """The two taps of every output index of the interpolation matrix: (lo, hi, w_lo, w_hi),
+    with w_hi = 0 where the edge clamp leaves a single tap."""
+    a = _upsample_matrix(src, dst)
+    rows = np.arange(dst)
+    lo = np.argmax(a != 0.0, axis=1)
+    hi = np.minimum(lo + 1, src - 1)
+    w_lo = a[rows, lo]
+    w_hi = np.where(hi != lo, a[rows, hi], 0.0)
+    return lo, hi, w_lo, w_hi
+
+
 def _upsample(z: np.ndarray, dst: int) -> np.ndarray:
     """Bilinear upsample of z [n][3][8][8] to [n][dst][dst][3] (NHWC), columns then rows.
 
@@ -173,12 +185,7 @@ def _upsample(z: np.ndarray, dst: int) -> np.ndarray:
     are bit-identical on every machine and thread count.
     """
     src = z.shape[-1]
-    a = _upsample_matrix(src, dst)
-    rows = np.arange(dst)
-    lo = np.argmax(a != 0.0, axis=1)
-    hi = np.minimum(lo + 1, src - 1)
-    w_lo = a[rows, lo]
-    w_hi = np.where(hi != lo, a[rows, hi], 0.0)
+    lo, hi, w_lo, w_hi = _upsample_taps(src, dst)
     zt = z.transpose(0, 2, 3, 1)                                           # n, i, j, c
     t = (w_lo[None, None, :, None] * np.take(zt, lo, axis=2)
          + w_hi[None, None, :, None] * np.take(zt, hi, axis=2))           # n, i, x, c

@@ -89,7 +89,11 @@ def test_device_ranking_equals_oracle_policy_order(c2, route, name):
         p = np.array(rec["folded_passed"], dtype=np.float64)
         sel = np.where(e > 0, (p + 1.0) / (e + 2.0), sel)
         assert np.array_equal(np.array(rec["selectivity"]), sel), f"round {r}: estimates"
-        assert np.allclose(rec["cost"], c2.flops, rtol=1e-6), f"round {r}: static cost"
+        seen = np.array([(rec["seen_mask"] >> j) & 1 for j in range(k)], dtype=bool)
+        assert np.array_equal(seen, sel > 0), f"round {r}: seen mask"
+        # static costs are the model FLOPs, taken at a predicate's first fold (0 before it)
+        assert np.allclose(np.array(rec["cost"])[seen], np.array(c2.flops)[seen], rtol=1e-6), f"round {r}: cost"
+        assert not np.any(np.array(rec["cost"])[~seen]), f"round {r}: cost of an unseen predicate"
         if rec["seen_mask"] == (1 << k) - 1:
             want = ho.policy_order(name, np.array(rec["cost"]), sel)
             assert rec["order"] == want, f"round {r}: device {rec['order']} oracle {want}"

@@ -38,3 +38,35 @@ def test_two_tap_upsample_equals_interpolation_matrix(dst):
     assert np.allclose(a.sum(axis=1), 1.0) and ((a != 0).sum(axis=1) <= 2).all()
     dense = np.einsum("yi,ncij,xj->nyxc", a, z, a)
     assert np.abs(hs._upsample(z, dst) - dense).max() < 1e-13
+
+
+# ---------------------------------------------------------------- compiled frame generator
+@pytest.fixture(scope="module")
+def framegen():
+    from hydro_synth import build, device
+    if not __import__("os").path.exists(device.LIB_PATH):
+        build.build()
+    return device
+
+
+@pytest.mark.parametrize("w,start,count", [(2, 0, 3), (2, 1022, 4), (4, 524286, 2), (5, 0, 2), (5, 3071, 3),
+                                           (5, 1048574, 2)])
+def test_compiled_generator_equals_numpy(framegen, w, start, count):
+    """The compiled generator (PCG64 jump-ahead to each frame row, the same fp64 expressions) is
+    bit-identical to the numpy recipe, across chunk boundaries and at the end of the largest stream."""
+    cfg = hs.workload(w)
+    assert np.array_equal(framegen.make_frames_host(cfg, start, count), hs.make_frames(cfg, start, count))
+
+
+def test_compiled_generator_calibration_seed(framegen):
+    cfg = hs.workload(5)
+    seed = cfg.data_seed + cfg.calib_seed_offset
+    assert np.array_equal(framegen.make_frames_host(cfg, 2047, 2, data_seed=seed),
+                          hs.make_frames(cfg, 2047, 2, data_seed=seed))
+
+
+def test_pcg_jump_ahead_matches_stepping(framegen):
+    """A planted check of the draw positions: frame 1 of a chunk is not frame 0 of it."""
+    cfg = hs.workload(5)
+    a = framegen.make_frames_host(cfg, 0, 2)
+    assert not np.array_equal(a[0], a[1])
