@@ -207,6 +207,34 @@ int hydro_query(const hydro_frames* frames, const hydro_model* models, int32_t k
                 const hydro_policy* policy, int64_t** out_ids, int64_t* out_n,
                 hydro_pred_stats* out_stats);
 
+/* Bytes of the device array that hydro_query_noalloc works in (one copy per GPU). */
+#define HYDRO_NOALLOC_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (serving loops and harnesses that forbid
+ * hipMalloc, code that must not allocate between captured or timed regions): hydro_query without
+ * any device allocation.  Every device buffer of the query (packed weights, queues, live lists,
+ * statistics, result bitmap and ids, FP64-tier activations, learned-router state) is carved from
+ * one library-owned device array of HYDRO_NOALLOC_BYTES bytes, one per GPU, held until the
+ * process ends.  No stream, event or graph is created.  Differences from hydro_query:
+ *   - frames must be in device memory (EUNSUPPORTED otherwise);
+ *   - policy.use_graph, policy.autotune and policy.time_kernels must be 0 (EUNSUPPORTED);
+ *   - the work runs on policy.stream, or on the null stream when that is NULL;
+ *   - the ids are written to the caller's host array out_ids[out_cap], sorted ascending, and
+ *     *out_n is their number; if the result has more than out_cap ids the call returns ECAPACITY
+ *     with *out_n set to the number needed;
+ *   - a query whose buffers do not fit the array returns ECAPACITY (the message names the size):
+ *     e.g. two MLP 3072-256 predicates fit up to about 100k tuples, three 64x64 CNNs of the
+ *     16-32-64 family up to about 1M;
+ *   - the FP64 tier evaluates at most 8 escalated tuples per predicate and round layer-parallel,
+ *     the rest one per block on 16 blocks (same decisions, slower when many escalate).
+ * Calls on one GPU share its array and keep nothing from the previous call (everything a call
+ * reads is initialised by that call); calls that overlap on one GPU (several threads or streams)
+ * race and must be serialised by the caller. */
+int hydro_query_noalloc(const hydro_frames* frames, const hydro_model* models, int32_t k,
+                        const float* thresholds, int32_t n_seg, int64_t seg_len,
+                        const hydro_policy* policy, int64_t* out_ids, int64_t out_cap,
+                        int64_t* out_n, hydro_pred_stats* out_stats);
+
 /* Create a session: validates and uploads the K models (1 <= K <= 8), allocates device state
  * for pushes of at most max_push tuples of frame_h x frame_w x 3 frames.  The policy is copied.
  * Setup cost (weight upload and packing, buffer allocation) is paid here. */

@@ -1011,7 +1011,7 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
     for (int layer = 0; layer < 3; ++layer)
       hipLaunchKernelGGL(cnn_f64_layer_kernel, dim3(grid * 4), dim3(256), 0, s, a, layer);
     hipLaunchKernelGGL(cnn_f64_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
-    hipLaunchKernelGGL(cnn_f64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f);
+    hipLaunchKernelGGL(cnn_f64_rest_kernel, dim3(a.rest_grid), dim3(256), 0, s, a, f);
     return;
   }
   // FP32: one persistent launch over every queue of the pass.  BF16: one launch per width class

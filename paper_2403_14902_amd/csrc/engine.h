@@ -58,6 +58,7 @@ struct CnnArgs {
   int esc_cap;                      // entries handled layer-parallel; the rest run one per block
   double* scratch64;                // FP64 tier fallback: per-block activation scratch
   int64_t scratch64_per_block;      // doubles
+  int rest_grid;                    // blocks of the FP64 fallback launch (one scratch slot each)
   Queues q;
   FrameSrc fr;
   DevState* st;
@@ -90,6 +91,7 @@ struct GcnnArgs {
   int esc_cap;
   double* rest_scratch;             // FP64 tier beyond esc_cap: per block, two activation buffers
   int64_t rest_per_block;
+  int rest_grid;                    // blocks of that launch (one scratch slot each)
   Queues q;
   FrameSrc fr;
   DevState* st;

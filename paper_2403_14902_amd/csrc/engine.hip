@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,32 @@ static hipError_t dev_alloc(void** p, size_t bytes) {
   }
   if (bytes == 0) bytes = 16;
   return hipMalloc(p, bytes);
+}
+
+// ---------------------------------------------------------------- allocation-free arena
+// hydro_query_noalloc places all of a query's device state (packed weights, queues, live lists,
+// statistics, result buffers) in this array instead of allocating it: one copy per GPU, held
+// until the process ends.  In host code `scratch` is only a stand-in for the symbol: its device
+// address (per device) comes from hipGetSymbolAddress and is the only form passed to kernels and
+// copies.
+static __device__ __align__(256) unsigned char scratch[HYDRO_NOALLOC_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's copy of `scratch` (resolved once per device).
+static int scratch_ptr(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return fail(HYDRO_EUNSUPPORTED, "device ordinal above 63");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(HYDRO_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return HYDRO_OK;
 }
 
 // ---------------------------------------------------------------- round kernels
@@ -297,6 +324,9 @@ __global__ __launch_bounds__(256) void k_res_write(const uint32_t* bits, int64_t
 // ---------------------------------------------------------------- session
 // Escalated (FP64) entries per predicate and round evaluated layer-parallel; more run one per
 // block.  HYDRO_ESC_CAP overrides the default (tests use it to exercise the per-block path).
+constexpr int kArenaEscCap = 8;      // allocation-free sessions: FP64 layer-parallel entries per slot
+constexpr int kArenaRestGrid = 16;   // ... and FP64 fallback blocks
+
 static int esc_cap_setting() {
   const char* e = getenv("HYDRO_ESC_CAP");
   int v = (e && *e) ? atoi(e) : 128;
@@ -383,6 +413,10 @@ struct hydro_session {
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // use_graph: captured pushes
   float tau_k[kMaxK], tau32_k[kMaxK];   // per-predicate bands (policy values or calibrated)
   bool auto_tau = false, auto_tau32 = false;   // bands still to be measured on the first push
+  // allocation-free sessions: every device buffer is carved from `arena` (the current device's
+  // copy of `scratch`); nothing is allocated or freed
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
 };
 
 // Captured pushes bake the bands (and every other launch argument) into their kernel nodes.
@@ -401,6 +435,18 @@ static hipEvent_t next_event(hydro_session* s) {
 }
 
 static int sess_alloc(hydro_session* s, void** p, size_t bytes) {
+  if (s->arena) {
+    const size_t off = (s->arena_used + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 16;
+    if (off > s->arena_cap || bytes > s->arena_cap - off) {
+      *p = nullptr;
+      return fail(HYDRO_ECAPACITY, "the query needs more than the " + std::to_string(s->arena_cap) +
+                                       " bytes of the allocation-free device arena");
+    }
+    *p = s->arena + off;
+    s->arena_used = off + bytes;
+    return HYDRO_OK;
+  }
   hipError_t e = dev_alloc(p, bytes);
   if (e != hipSuccess) return fail(HYDRO_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes failed");
   s->allocs.push_back(*p);
@@ -473,7 +519,9 @@ static int pack_models(hydro_session* s) {
   ca = CnnArgs{};
   s->gcnn = GcnnArgs{};
   ca.pad_raw = pad_raw;
-  const int esc_cap = esc_cap_setting();
+  // allocation-free sessions keep the FP64 tier's layer-parallel batch and fallback slots small
+  const int esc_cap = s->arena ? std::min(esc_cap_setting(), kArenaEscCap) : esc_cap_setting();
+  const int rest_grid = s->arena ? kArenaRestGrid : s->n_cu;
   // grouped launches walk their slots in order: most expensive predicates first, so the
   // longest work items start early (longest-processing-time-first)
   std::vector<int> slots_order(s->K);
@@ -522,15 +570,17 @@ static int pack_models(hydro_session* s) {
       ma.b1_canon[i] = dp;
       if ((rc = sess_alloc(s, (void**)&ma.partial[i], (size_t)(H / 32) * s->cap * kClasses * sizeof(float)))) return rc;
       if (ma.splitk_ws == nullptr) {
-        // split-K workspace shared by the MLP predicates: 1024 tiles of 128 x 128 fp32 (64 MB)
-        ma.split_slots = 1024;
+        // split-K workspace shared by the MLP predicates: 1024 tiles of 128 x 128 fp32 (64 MB;
+        // 8 MB in allocation-free sessions, which split fewer tiles)
+        ma.split_slots = s->arena ? 128 : 1024;
         // HYDRO_SPLITK_BELOW overrides the tile count under which a launch splits K
         const char* sb = getenv("HYDRO_SPLITK_BELOW");
         ma.split_below = (sb && *sb) ? atoi(sb) : s->n_cu / 2;
         ma.split_target = 2 * s->n_cu;
         if ((rc = sess_alloc(s, (void**)&ma.splitk_ws, (size_t)ma.split_slots * 128 * 128 * sizeof(float)))) return rc;
         if ((rc = sess_alloc(s, (void**)&ma.split_cnt, (size_t)ma.split_slots * sizeof(int)))) return rc;
-        HIP_TRY(hipMemset(ma.split_cnt, 0, (size_t)ma.split_slots * sizeof(int)));
+        HIP_TRY(hipMemsetAsync(ma.split_cnt, 0, (size_t)ma.split_slots * sizeof(int), s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
       }
       {
         // HYDRO_MLP_TILE forces one tile configuration (tests exercise each)
@@ -688,7 +738,8 @@ static int pack_models(hydro_session* s) {
     for (int i = 0; i < ga.n_preds; ++i)
       if ((rc = sess_alloc(s, (void**)&ga.esc_act[i], (size_t)ga.esc_cap * ga.esc_stride * sizeof(double)))) return rc;
     ga.rest_per_block = 2 * mx;
-    if ((rc = sess_alloc(s, (void**)&ga.rest_scratch, (size_t)ga.rest_per_block * s->n_cu * sizeof(double)))) return rc;
+    ga.rest_grid = rest_grid;
+    if ((rc = sess_alloc(s, (void**)&ga.rest_scratch, (size_t)ga.rest_per_block * rest_grid * sizeof(double)))) return rc;
   }
   if (ca.n_preds > 0) {
     // FP64 tier scratch: two activation buffers per block (largest layer output)
@@ -702,7 +753,8 @@ static int pack_models(hydro_session* s) {
       }
     }
     ca.scratch64_per_block = 2 * per;
-    int rc = sess_alloc(s, (void**)&ca.scratch64, (size_t)ca.scratch64_per_block * s->n_cu * sizeof(double));
+    ca.rest_grid = rest_grid;
+    int rc = sess_alloc(s, (void**)&ca.scratch64, (size_t)ca.scratch64_per_block * rest_grid * sizeof(double));
     if (rc) return rc;
     // layer-parallel FP64 tier: per entry, layer-1 output then layer-2 output
     ca.esc_stride = 0;
@@ -728,7 +780,7 @@ static void free_session(hydro_session* s) {
     if (s->stage_free[i]) hipEventDestroy(s->stage_free[i]);
     if (s->stage_ready[i]) hipEventDestroy(s->stage_ready[i]);
   }
-  if (s->out_ids) hipFree(s->out_ids);
+  if (s->out_ids && !s->arena) hipFree(s->out_ids);
   for (hipEvent_t e : s->evpool) hipEventDestroy(e);
   for (auto& g : s->graphs) hipGraphExecDestroy(g.second);
   if (s->copy_stream) hipStreamDestroy(s->copy_stream);
@@ -784,9 +836,15 @@ static int validate_policy(const hydro_policy* p, int K) {
   return HYDRO_OK;
 }
 
-int hydro_session_create(const hydro_model* models, int32_t k, const hydro_policy* policy, int32_t frame_h,
-                         int32_t frame_w, int64_t max_push, hydro_session** out) {
-  g_err.clear();
+static int rnn_arena_alloc(void* ctx, void** p, size_t bytes) {
+  return sess_alloc(static_cast<hydro_session*>(ctx), p, bytes);
+}
+
+// Session creation; with `arena`, every device buffer is carved from it (no allocation, no stream
+// or event creation: the work runs on policy->stream, or the null stream when that is NULL).
+static int session_create(const hydro_model* models, int32_t k, const hydro_policy* policy, int32_t frame_h,
+                          int32_t frame_w, int64_t max_push, unsigned char* arena, size_t arena_cap,
+                          hydro_session** out) {
   if (!out) return fail(HYDRO_EINVAL, "out is NULL");
   *out = nullptr;
   if (!models) return fail(HYDRO_EINVAL, "models is NULL");
@@ -802,6 +860,8 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
 
   g_alloc_counter = 0;
   hydro_session* s = new hydro_session();
+  s->arena = arena;
+  s->arena_cap = arena ? arena_cap : 0;
   s->pol = *policy;
   s->auto_tau = s->pol.tau <= 0.f;
   s->auto_tau32 = s->pol.tau32 <= 0.f;
@@ -857,18 +917,20 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   int clk_khz = 0;
   if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, s->device) == hipSuccess && clk_khz > 0)
     s->tick_us = 1000.0 / clk_khz;
-  if (s->pol.stream) {
+  if (s->pol.stream || s->arena) {
     s->stream = (hipStream_t)s->pol.stream;
   } else {
     he = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(he)));
     s->own_stream = true;
   }
-  he = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
-  if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(he)));
-  for (int i = 0; i < 2; ++i) {
-    hipEventCreateWithFlags(&s->stage_free[i], hipEventDisableTiming);
-    hipEventCreateWithFlags(&s->stage_ready[i], hipEventDisableTiming);
+  if (!s->arena) {   // the host-frame staging ring (allocation-free sessions take device frames only)
+    he = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(he)));
+    for (int i = 0; i < 2; ++i) {
+      hipEventCreateWithFlags(&s->stage_free[i], hipEventDisableTiming);
+      hipEventCreateWithFlags(&s->stage_ready[i], hipEventDisableTiming);
+    }
   }
   const int64_t cap = s->cap;
   if ((rc = sess_alloc(s, (void**)&s->st, sizeof(DevState)))) return bail(rc);
@@ -889,14 +951,21 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   }
   if ((rc = sess_alloc(s, (void**)&s->theta, 4096 * sizeof(float)))) return bail(rc);
   s->theta_cap = 4096;
-  he = dev_alloc((void**)&s->out_ids, cap * sizeof(int64_t));
-  if (he != hipSuccess) return bail(fail(HYDRO_ENOMEM, "result buffer allocation failed"));
+  if (s->arena) {
+    if ((rc = sess_alloc(s, (void**)&s->out_ids, cap * sizeof(int64_t)))) return bail(rc);
+  } else {
+    he = dev_alloc((void**)&s->out_ids, cap * sizeof(int64_t));
+    if (he != hipSuccess) return bail(fail(HYDRO_ENOMEM, "result buffer allocation failed"));
+  }
   s->out_cap = cap;
   if (s->pol.route == HYDRO_ROUTE_LEARNED) {
     double fl[kMaxK];
     for (int i = 0; i < k; ++i) fl[i] = s->models[i].flops;
-    rc = router_nn_create(&s->rnn, s->K, frame_h, frame_w, cap, s->pol.seed, s->pol.routing_batch, s->pol.explore, fl);
-    if (rc) return bail(fail(rc, "learned router: frames must be square with a side divisible by 8"));
+    rc = router_nn_create(&s->rnn, s->K, frame_h, frame_w, cap, s->pol.seed, s->pol.routing_batch, s->pol.explore, fl,
+                          s->arena ? rnn_arena_alloc : nullptr, s);
+    if (rc == HYDRO_EUNSUPPORTED) return bail(fail(rc, "learned router: frames must be square with a side divisible by 8"));
+    if (rc == HYDRO_ENOMEM) return bail(fail(rc, "learned router: device allocation failed"));
+    if (rc) return bail(rc);
     s->fused_feats = true;
     for (int i = 0; i < k; ++i)
       if (s->models[i].m.arch != HYDRO_ARCH_CNN || s->models[i].variant == CNN_NONE) s->fused_feats = false;
@@ -905,6 +974,12 @@ int hydro_session_create(const hydro_model* models, int32_t k, const hydro_polic
   if (rc) return bail(rc);
   *out = s;
   return HYDRO_OK;
+}
+
+int hydro_session_create(const hydro_model* models, int32_t k, const hydro_policy* policy, int32_t frame_h,
+                         int32_t frame_w, int64_t max_push, hydro_session** out) {
+  g_err.clear();
+  return session_create(models, k, policy, frame_h, frame_w, max_push, nullptr, 0, out);
 }
 
 int hydro_session_reset(hydro_session* s) {
@@ -1286,6 +1361,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   if (fr.where == HYDRO_MEM_DEVICE) {
     src.base = fr.data;
   } else {
+    if (s->arena) return fail(HYDRO_EUNSUPPORTED, "allocation-free queries take device frames");
     int slot = s->stage_next;
     s->stage_next ^= 1;
     if (!s->stage[slot]) {
@@ -1303,6 +1379,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
 
   // result capacity
   if (s->info.n_tuples + n > (uint64_t)s->out_cap) {
+    if (s->arena) return fail(HYDRO_ECAPACITY, "allocation-free sessions hold the results of one push");
     HIP_TRY(hipStreamSynchronize(st));
     int64_t ncap = std::max<int64_t>(s->out_cap * 2, s->info.n_tuples + n);
     int64_t* p;
@@ -1468,23 +1545,31 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   return HYDRO_OK;
 }
 
-int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hydro_pred_stats* out_stats) {
-  g_err.clear();
-  if (out_ids) *out_ids = nullptr;
-  if (out_n) *out_n = 0;
-  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
-  if (!out_ids || !out_n) return fail(HYDRO_EINVAL, "out_ids / out_n is NULL");
+// Wait for the query, copy its ids and fill the statistics.  The ids go to a malloc'd array
+// (*alloc_out) or, when `dst` is given, into the caller's host array of dst_cap ids (ECAPACITY,
+// with *out_n = the result size, when it is too small).
+static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int64_t dst_cap, int64_t* out_n,
+                        hydro_pred_stats* out_stats) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   HIP_TRY(hipGetLastError());
   DevState h;
   HIP_TRY(hipMemcpy(&h, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
   const int64_t nres = h.n_result;
-  int64_t* ids = (int64_t*)malloc(std::max<int64_t>(1, nres) * sizeof(int64_t));
-  if (!ids) return fail(HYDRO_ENOMEM, "host allocation of the result failed");
+  int64_t* ids = dst;
+  if (dst) {
+    if (nres > dst_cap) {
+      *out_n = nres;
+      return fail(HYDRO_ECAPACITY, "the result holds " + std::to_string(nres) + " ids, the output array " +
+                                       std::to_string(dst_cap));
+    }
+  } else {
+    ids = (int64_t*)malloc(std::max<int64_t>(1, nres) * sizeof(int64_t));
+    if (!ids) return fail(HYDRO_ENOMEM, "host allocation of the result failed");
+  }
   if (nres > 0) {
     hipError_t he = hipMemcpy(ids, s->out_ids, nres * sizeof(int64_t), hipMemcpyDeviceToHost);
     if (he != hipSuccess) {
-      free(ids);
+      if (!dst) free(ids);
       return fail(HYDRO_EDEVICE, std::string("result copy: ") + hipGetErrorString(he));
     }
   }
@@ -1530,11 +1615,20 @@ int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hy
       o.selectivity = h.t_eval[k] ? (double)h.t_pass[k] / (double)h.t_eval[k] : 0.0;
     }
   }
-  *out_ids = ids;
+  if (alloc_out) *alloc_out = ids;
   *out_n = nres;
   s->theta_host.clear();
   s->in_query = false;
   return HYDRO_OK;
+}
+
+int hydro_session_finish(hydro_session* s, int64_t** out_ids, int64_t* out_n, hydro_pred_stats* out_stats) {
+  g_err.clear();
+  if (out_ids) *out_ids = nullptr;
+  if (out_n) *out_n = 0;
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  if (!out_ids || !out_n) return fail(HYDRO_EINVAL, "out_ids / out_n is NULL");
+  return finish_query(s, out_ids, nullptr, 0, out_n, out_stats);
 }
 
 int hydro_session_info(const hydro_session* s, hydro_query_info* out) {
@@ -1591,7 +1685,12 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   int* cptr = t == TIER_FIRST ? s->st->qcount : t == TIER_F32 ? s->st->bcount : s->st->ecount;
   HIP_TRY(hipMemcpy(cptr, cnt, sizeof(cnt), hipMemcpyHostToDevice));
   double* dlog;
-  HIP_TRY(hipMalloc(&dlog, fr.n * kClasses * sizeof(double)));
+  const size_t arena_mark = s->arena_used;   // allocation-free sessions: a temporary arena slice
+  if (s->arena) {
+    if ((rc = sess_alloc(s, (void**)&dlog, fr.n * kClasses * sizeof(double)))) return rc;
+  } else {
+    HIP_TRY(hipMalloc(&dlog, fr.n * kClasses * sizeof(double)));
+  }
   FrameSrc src{fr.data, fr.dtype, fr.h, (int64_t)fr.h * fr.w * 3};
   Forward f = make_forward(s, t, 0, src, 1, 1, 0);
   f.logits = dlog;
@@ -1599,7 +1698,8 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   enqueue_tier(s, t, src, f, st);
   hipError_t he = hipStreamSynchronize(st);
   if (he == hipSuccess) he = hipMemcpy(out_logits, dlog, fr.n * kClasses * sizeof(double), hipMemcpyDeviceToHost);
-  hipFree(dlog);
+  if (s->arena) s->arena_used = arena_mark;
+  else hipFree(dlog);
   if (he != hipSuccess) return fail(HYDRO_EDEVICE, std::string("logits: ") + hipGetErrorString(he));
   // leave the session ready for a new query
   return hydro_session_reset(s);
@@ -1704,6 +1804,33 @@ int hydro_query(const hydro_frames* frames, const hydro_model* models, int32_t k
   if (rc) return rc;
   rc = hydro_session_push(s, frames, thresholds, n_seg, seg_len);
   if (!rc) rc = hydro_session_finish(s, out_ids, out_n, out_stats);
+  std::string err = g_err;
+  hydro_session_destroy(s);
+  g_err = err;
+  return rc;
+}
+
+int hydro_query_noalloc(const hydro_frames* frames, const hydro_model* models, int32_t k, const float* thresholds,
+                        int32_t n_seg, int64_t seg_len, const hydro_policy* policy, int64_t* out_ids, int64_t out_cap,
+                        int64_t* out_n, hydro_pred_stats* out_stats) {
+  g_err.clear();
+  if (out_n) *out_n = 0;
+  if (!frames || !policy || !out_n) return fail(HYDRO_EINVAL, "frames / policy / out_n is NULL");
+  if (out_cap < 0 || (out_cap > 0 && !out_ids)) return fail(HYDRO_EINVAL, "out_ids is NULL or out_cap negative");
+  if (frames->where != HYDRO_MEM_DEVICE) return fail(HYDRO_EUNSUPPORTED, "allocation-free queries take device frames");
+  if (policy->use_graph || policy->autotune || policy->time_kernels)
+    return fail(HYDRO_EUNSUPPORTED, "allocation-free queries run without graphs, autotuning or kernel timing");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned char* arena = nullptr;
+  int rc = scratch_ptr(dev, &arena);
+  if (rc) return rc;
+  hydro_session* s = nullptr;
+  rc = session_create(models, k, policy, frames->h, frames->w, std::max<int64_t>(1, frames->n), arena,
+                      HYDRO_NOALLOC_BYTES, &s);
+  if (rc) return rc;
+  rc = hydro_session_push(s, frames, thresholds, n_seg, seg_len);
+  if (!rc) rc = finish_query(s, nullptr, out_ids, out_cap, out_n, out_stats);
   std::string err = g_err;
   hydro_session_destroy(s);
   g_err = err;

@@ -700,7 +700,7 @@ void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, h
   if (tier == TIER_F64) {
     for (int l = 0; l < maxl; ++l) hipLaunchKernelGGL(gconv64_layer_kernel, dim3(grid * 8), dim3(256), 0, s, a, l);
     hipLaunchKernelGGL(gcnn64_head_kernel, dim3(grid), dim3(256), 0, s, a, f);
-    hipLaunchKernelGGL(gcnn64_rest_kernel, dim3(grid), dim3(256), 0, s, a, f, a.rest_scratch, a.rest_per_block);
+    hipLaunchKernelGGL(gcnn64_rest_kernel, dim3(a.rest_grid), dim3(256), 0, s, a, f, a.rest_scratch, a.rest_per_block);
     return;
   }
   const bool bf = a.prec == HYDRO_PREC_BF16 && tier == TIER_FIRST;

@@ -7,8 +7,11 @@ namespace hydro {
 
 struct RouterNN;
 
+// Device buffers come from `alloc(ctx, &p, bytes)` when it is given (and are then not freed by
+// router_nn_destroy), else from hipMalloc.
+typedef int (*RouterAllocFn)(void* ctx, void** p, size_t bytes);
 int router_nn_create(RouterNN** out, int k, int fh, int fw, int64_t cap, uint64_t seed, int routing_batch,
-                     float explore, const double* flops);
+                     float explore, const double* flops, RouterAllocFn alloc, void* alloc_ctx);
 void router_nn_destroy(RouterNN* r);
 // New query: initial weights, cleared optimiser state.
 void router_nn_reset(RouterNN* r, hipStream_t s);

@@ -36,6 +36,7 @@ struct RouterNN {
   int64_t cap;
   uint64_t seed;
   float explore;
+  bool external = false;          // buffers owned by the caller's allocator (not freed here)
   __bf16* feats = nullptr;        // [cap][192]
   float* keys = nullptr;          // [cap][K]
   uint32_t* stamps = nullptr;     // [cap]: round whose keys kernel wrote the tuple's keys
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(256) void rnn_train_kernel(DevState* st, const uint
 }
 
 int router_nn_create(RouterNN** out, int k, int fh, int fw, int64_t cap, uint64_t seed, int routing_batch,
-                     float explore, const double* flops) {
+                     float explore, const double* flops, RouterAllocFn alloc, void* alloc_ctx) {
   *out = nullptr;
   if (fh != fw || fh % 8 != 0) return HYDRO_EUNSUPPORTED;
   RouterNN* r = new RouterNN();
@@ -541,18 +542,28 @@ int router_nn_create(RouterNN** out, int k, int fh, int fw, int64_t cap, uint64_
   r->seed = seed;
   r->routing_batch = routing_batch;
   r->explore = explore;
-  bool ok = hipMalloc(&r->feats, (size_t)cap * RF * sizeof(__bf16)) == hipSuccess &&
-            hipMalloc(&r->keys, (size_t)cap * k * sizeof(float)) == hipSuccess &&
-            hipMalloc(&r->stamps, (size_t)cap * sizeof(uint32_t)) == hipSuccess &&
-            hipMalloc(&r->ring, (size_t)RING * sizeof(uint32_t)) == hipSuccess &&
-            hipMalloc(&r->params, NPARAM * sizeof(float)) == hipSuccess &&
-            hipMalloc(&r->adam_m, NPARAM * sizeof(float)) == hipSuccess &&
-            hipMalloc(&r->adam_v, NPARAM * sizeof(float)) == hipSuccess &&
-            hipMalloc(&r->w1_frag, (size_t)(RF / 32) * 4 * 64 * 8 * sizeof(__bf16)) == hipSuccess &&
-            hipMalloc(&r->flops, RK * sizeof(float)) == hipSuccess;
+  r->external = alloc != nullptr;
+  int fail_rc = HYDRO_ENOMEM;
+  auto get = [&](void** p, size_t bytes) {
+    if (alloc) {
+      const int rc = alloc(alloc_ctx, p, bytes);
+      if (rc) fail_rc = rc;
+      return rc == 0;
+    }
+    return hipMalloc(p, bytes) == hipSuccess;
+  };
+  bool ok = get((void**)&r->feats, (size_t)cap * RF * sizeof(__bf16)) &&
+            get((void**)&r->keys, (size_t)cap * k * sizeof(float)) &&
+            get((void**)&r->stamps, (size_t)cap * sizeof(uint32_t)) &&
+            get((void**)&r->ring, (size_t)RING * sizeof(uint32_t)) &&
+            get((void**)&r->params, NPARAM * sizeof(float)) &&
+            get((void**)&r->adam_m, NPARAM * sizeof(float)) &&
+            get((void**)&r->adam_v, NPARAM * sizeof(float)) &&
+            get((void**)&r->w1_frag, (size_t)(RF / 32) * 4 * 64 * 8 * sizeof(__bf16)) &&
+            get((void**)&r->flops, RK * sizeof(float));
   if (!ok) {
     router_nn_destroy(r);
-    return HYDRO_ENOMEM;
+    return fail_rc;
   }
   // He-normal init of W1 and W2 (fp32), zero biases
   std::mt19937_64 rng(seed);
@@ -569,6 +580,10 @@ int router_nn_create(RouterNN** out, int k, int fh, int fw, int64_t cap, uint64_
 
 void router_nn_destroy(RouterNN* r) {
   if (!r) return;
+  if (r->external) {
+    delete r;
+    return;
+  }
   hipFree(r->feats);
   hipFree(r->keys);
   hipFree(r->stamps);

@@ -98,6 +98,8 @@ def lib():
         L.hydro_policy_default.restype = None
         L.hydro_query.argtypes = [C.POINTER(Frames), C.POINTER(Model), i32, FP, i32, i64, C.POINTER(Policy),
                                   C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.c_int64), C.POINTER(PredStats)]
+        L.hydro_query_noalloc.argtypes = [C.POINTER(Frames), C.POINTER(Model), i32, FP, i32, i64, C.POINTER(Policy),
+                                          C.POINTER(C.c_int64), i64, C.POINTER(C.c_int64), C.POINTER(PredStats)]
         L.hydro_session_create.argtypes = [C.POINTER(Model), i32, C.POINTER(Policy), i32, i32, i64, C.POINTER(vp)]
         L.hydro_session_reset.argtypes = [vp]
         L.hydro_session_push.argtypes = [vp, C.POINTER(Frames), FP, i32, i64]
@@ -116,7 +118,7 @@ def lib():
         L.hydro_free.restype = None
         L.hydro_last_error.restype = C.c_char_p
         L.hydro_version.restype = C.c_char_p
-        for name in ("hydro_query", "hydro_session_create", "hydro_session_reset", "hydro_session_push",
+        for name in ("hydro_query", "hydro_query_noalloc", "hydro_session_create", "hydro_session_reset", "hydro_session_push",
                      "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
                      "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
                      "hydro_session_logits",
@@ -126,7 +128,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_session_create", "hydro_session_reset",
+EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_query_noalloc", "hydro_session_create", "hydro_session_reset",
             "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
             "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
             "hydro_session_logits", "hydro_session_calibrate", "hydro_session_destroy", "hydro_free",
@@ -328,6 +330,24 @@ def query(frames, dtype: str, models: Sequence[ModelSpec], thresholds: np.ndarra
     ids = np.ctypeslib.as_array(ptr, shape=(n.value,)).copy() if n.value > 0 else np.zeros(0, np.int64)
     lib().hydro_free(ptr)
     return ids, _stats_list(st, len(models))
+
+
+def query_noalloc(frames, dtype: str, models: Sequence[ModelSpec], thresholds: np.ndarray, seg_len: int,
+                  policy: Policy, out_cap: int, id_base: int = 0):
+    """One-shot query through hydro_query_noalloc (no device allocation; ids into a host array of
+    out_cap entries).  Returns (ids, stats)."""
+    cm = (Model * len(models))(*[m.to_c() for m in models])
+    th = np.ascontiguousarray(thresholds, dtype=np.float32)
+    if th.ndim == 1:
+        th = th[None, :]
+    fr = _frames_struct(frames, dtype, id_base)
+    out = np.zeros(max(1, int(out_cap)), dtype=np.int64)
+    n = C.c_int64()
+    st = (PredStats * len(models))()
+    _check(lib().hydro_query_noalloc(C.byref(fr), cm, len(models), _fp(th), th.shape[0], int(seg_len),
+                                     C.byref(policy), out.ctypes.data_as(C.POINTER(C.c_int64)), int(out_cap),
+                                     C.byref(n), st))
+    return out[:n.value].copy(), _stats_list(st, len(models))
 
 
 ROUTER_NPARAM = 192 * 64 + 64 + 64 * 8 + 8
