@@ -1,11 +1,12 @@
 """Throughput of the conjunctive ML-UDF query on one MI355X.
 
-Workload (default): 65,536 synthetic frames 64x64x3 bf16, three CNN predicates of widths
-(16m, 32m, 64m), m = 1, 2, 4, class-subset thresholds that drift over 8 segments of 8,192
-tuples.  Frames are resident in HBM before timing starts; models are uploaded at session
-creation (setup, not timed).  --workload 1..5 selects the other synthetic workloads (the
-1,048,576-frame uint8 one as a 131,072-frame prefix unless --n is given); those add a form
-pushed from pinned host memory when the workload streams from the host.
+Workload (default): cnn4_u8_128, the largest single-GPU configuration: 1,048,576 synthetic frames
+128x128x3 uint8 (51.5 GB, generated straight into HBM by the device frame generator, bit-identical
+to the numpy recipe), four CNN predicates (conv 32-64-128-256, stride 2, global mean, FC 10) with
+class-subset thresholds for selectivities 0.8 / 0.6 / 0.4 / 0.2.  Frames are resident in HBM before
+timing starts; models are uploaded at session creation (setup, not timed).  --workload 1..4
+selects the other synthetic workloads; a second, smaller line for the 65,536-frame 64x64 CNN
+workload is added under "cnn3_drift64" (--no-secondary skips it).
 
 A step is one whole query: reset, push every tuple (route, multi-split, evaluate, forward
 survivors, materialise the sorted ids) and copy ids and statistics to the host.
@@ -13,22 +14,25 @@ survivors, materialise the sorted ids) and copy ids and statistics to the host.
 Forms:
   full   learned content-based router (score routing as control arm, judge and fallback) +
          grouped persistent launches per round (MLP tile shapes from the autotuner, timed at
-         setup), each whole push captured once in a HIP graph (at setup) and replayed + first
-         pass in BF16 on MFMA (fp32 accumulate) with margins within tau re-scored in FP32 and
-         within tau32 in FP64.  `value`.
+         setup), each whole push captured once in a HIP graph (at setup) and replayed + low
+         precision first pass on MFMA (fp32 accumulate) with margins within tau re-scored in FP32
+         and within tau32 in FP64.  `value`; timed over exactly --steps steps.
   eager  the full form launched kernel by kernel, with HIP events recorded around each round's
          phases: the roofline, phase times and statistics come from this run (`eager_value`).
   score  as eager, but score-driven routing only.
   plain  FP32 first pass (tau32 band -> FP64), score-driven routing, one launch per predicate,
          no graph.
+  host   the full form pushed from pinned host memory in the workload's push batches, over a
+         prefix of --host-blocks batches (PCIe-inclusive; never `value`).
+  The eager / score / plain / host forms are ablations, timed over --ablation-steps steps.
   Every form's session calibrates its per-predicate bands at setup (untimed): tau_k and tau32_k
   are `--safety` (2) times the largest margin error of the first pass / FP32 pass against the
   FP64 pass on 8,192 separate frames of the same generator (--no-calibrate: fixed bands 0.015 /
   1e-5).
 
 Prints one JSON line (the full form's throughput as `value`, the plain form beside it, the
-dominant kernel's roofline from HIP events recorded by the library on its stream, and the FP64
-oracle timed on the host cores on a bounded sample).
+dominant kernels' roofline from HIP events recorded by the library on its stream, and the FP64
+oracle timed on the host cores on a bounded sample whose ids are also checked).
 """
 import argparse
 import json
@@ -55,13 +59,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=2)
-    ap.add_argument("--n", type=int, default=0,
-                    help="tuples: a prefix of the workload (0: all; the 1,048,576-frame uint8 workload "
-                         "defaults to a 131,072-frame prefix)")
+    ap.add_argument("--workload", type=int, default=5)
+    ap.add_argument("--n", type=int, default=0, help="tuples: a prefix of the workload (0: all)")
     ap.add_argument("--host", action="store_true",
-                    help="also time the full form pushed from pinned host memory in the workload's "
-                         "push batches (PCIe-inclusive)")
+                    help="also time the full form pushed from pinned host memory (workloads without "
+                         "push batches; the streamed workload always adds it)")
+    ap.add_argument("--host-blocks", type=int, default=16,
+                    help="push batches of the pinned-host form (a prefix of the workload)")
+    ap.add_argument("--ablation-steps", type=int, default=3)
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--wave", type=int, default=16384)
     ap.add_argument("--tau", type=float, default=0.0)
     ap.add_argument("--no-calibrate", action="store_true",
@@ -116,35 +122,36 @@ def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps,
     return res[0], stats_all, infos, t1 - t0
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; --gpus above 1 is not supported "
-                                   "(sharding across GPUs is a design note only, nothing runs on several)"}))
-        sys.exit(2)
-    import torch
-    import hydro_synth as hs
-    from paper_2403_14902_amd import hydro
+def make_device_frames(hs, torch, cfg, n):
+    """The workload's first n frames in HBM: structured frames come from the device generator
+    (bit-identical to the numpy recipe, no 51.5 GB host copy); the small uniform fp32 workload is
+    generated by numpy and copied."""
+    if cfg.frame_kind == "uniform":
+        return torch.from_numpy(hs.make_frames_parallel(cfg, 0, n)).cuda()
+    from hydro_synth import device as hd
+    t = time.perf_counter()
+    out = hd.make_frames_device(cfg, 0, n, chunks_per_call=256)
+    torch.cuda.synchronize()
+    log(f"[bench] {n} frames generated on the device in {time.perf_counter() - t:.1f} s")
+    return out
 
-    torch.cuda.set_device(0)
-    hydro.lib()
-    if args.copy_probe > 0:
-        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    cfg = hs.workload(args.workload)
-    n = args.n if args.n > 0 else (131072 if cfg.index == 5 else cfg.n)
-    n = min(n, cfg.n)
-    log(f"[bench] generating {n} frames of workload {cfg.name}")
-    frames = hs.make_frames_parallel(cfg, 0, n)
+
+def host_frames(frames_dev, sel, torch):
+    """Host (numpy) copy of the frames at indices `sel` of a device tensor."""
+    idx = torch.from_numpy(np.ascontiguousarray(sel)).cuda()
+    return frames_dev.index_select(0, idx).cpu().numpy()
+
+
+def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary):
+    """Every form of one workload; returns the JSON object of its line."""
+    cfg = hs.workload(wl)
+    n = min(n_req if n_req > 0 else cfg.n, cfg.n)
+    log(f"[bench] workload {cfg.name}: {n} tuples")
+    frames_dev = make_device_frames(hs, torch, cfg, n)
     pt = hs.load_predicates(cfg)
     weights = [hs.make_model(d) for d in cfg.models]
     specs = [hydro.ModelSpec.from_weights(w, m) for w, m in zip(weights, pt.class_masks)]
     seg_len = cfg.n // cfg.n_seg
-    frames_dev = torch.from_numpy(frames).cuda()
     flops = np.array([d.flops() for d in cfg.models])
     # band calibration sample: frames of the same generator, different seed (not the query's)
     cal = None if args.no_calibrate else torch.from_numpy(hs.calibration_frames(cfg)).cuda()
@@ -160,17 +167,16 @@ def main():
     elif cfg.hw == 64 and all(len(d.widths) == 3 for d in cfg.models):
         kernel_label = "cnn_fused_kernel<bf16, *> (first pass: one launch per width class)"
     else:
-        kernel_label = "gconv_layer_kernel<bf16> per layer + gcnn_head_kernel (first pass, grouped)"
+        kernel_label = "gconv_* layer kernels + gcnn_head_kernel (first pass, grouped over predicates)"
     full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, time_kernels=1,
                                  **extra)
-    log(f"[bench] full form ({args.route} routing)")
+    log(f"[bench] eager full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
-                                         args.steps, args.warmup, n, cal, args.safety)
+                                         abl_steps, 1, n, cal, args.safety)
     bands = run_form.bands
-    value = n * args.steps / dt
-    ms_per_step = dt * 1e3 / args.steps
+    eager_value = n * abl_steps / dt
 
-    # dominant kernel: the first-pass launch of every round (grouped bf16 MFMA kernel)
+    # dominant kernels: the first-pass launches of every round
     ev = np.array([[s["evaluated"] for s in st] for st in stats_all], dtype=np.float64)
     first_flops = float((ev * flops).sum())
     first_ms = sum(i["first_pass_ms"] for i in infos)
@@ -180,14 +186,23 @@ def main():
     f32_flops = float((resc * flops).sum())
     f32_ms = sum(i["f32_pass_ms"] for i in infos)
     last = stats_all[-1]
+
+    # headline: the full form as deployed, each push replayed from its captured HIP graph
+    log(f"[bench] full form, graph replay: {warmup} warmup + {steps} timed steps")
+    gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, use_graph=1,
+                             **extra)
+    ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, steps, warmup, n,
+                                cal, args.safety)
+    assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
+    value = n * steps / dtg
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "tuples/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": dtg * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -198,7 +213,8 @@ def main():
                                + (f" (first {n} of {cfg.n} tuples)" if n < cfg.n else ""),
                    "form": "full: bf16 first pass + fp32/fp64 re-score, " + args.route + " routing, grouped, "
                            "each push replayed from a captured HIP graph",
-                   "wave": args.wave, "tuples_per_step": n},
+                   "frames_in": "HBM (generated on the device before timing)",
+                   "wave": args.wave, "tuples_per_step": n, "ablation_steps": abl_steps},
         "roofline": {
             "bound": "mfma",
             "kernel": kernel_label,
@@ -210,11 +226,13 @@ def main():
             "flops_per_launch": first_flops / max(1, launches),
             "avg_launch_ms": first_ms / max(1, launches),
         },
+        "eager_value": eager_value,
+        "eager_ms_per_step": dt * 1e3 / abl_steps,
         "phases_ms_per_step": {
-            "route": sum(i["route_ms"] for i in infos) / args.steps,
-            "first_pass": first_ms / args.steps,
-            "fp32_rescore": f32_ms / args.steps,
-            "fp64_escalate": sum(i["f64_pass_ms"] for i in infos) / args.steps,
+            "route": sum(i["route_ms"] for i in infos) / abl_steps,
+            "first_pass": first_ms / abl_steps,
+            "fp32_rescore": f32_ms / abl_steps,
+            "fp64_escalate": sum(i["f64_pass_ms"] for i in infos) / abl_steps,
         },
         "fp32_rescore_tflops": f32_flops / (f32_ms * 1e-3) / 1e12 if f32_ms > 0 else 0.0,
         "per_predicate": [{"evaluated": s["evaluated"], "passed": s["passed"], "rescored": s["rescored"],
@@ -226,62 +244,59 @@ def main():
                   {"tau": float(full_pol.tau), "tau32": float(full_pol.tau32)}),
         "rounds": infos[-1]["rounds"],
     }
-
     info_last = infos[-1]
     out["router"] = {k: info_last[k] for k in ("learned_routed", "stats_routed", "learned_active", "train_steps")}
-    total_udf = float((ev * flops).sum()) / args.steps
-    out["udf_gflop_per_step"] = total_udf / 1e9
-
-    # the same form replayed from a captured HIP graph (no events)
-    gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, use_graph=1,
-                             **extra)
-    ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, args.steps,
-                                args.warmup, n, cal, args.safety)
-    assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
-    # headline: the full form as deployed (graph replay); the instrumented eager run beside it
-    out["eager_value"] = value
-    out["eager_ms_per_step"] = ms_per_step
-    value = n * args.steps / dtg
-    out["value"] = value
-    out["ms_per_step"] = dtg * 1e3 / args.steps
+    out["udf_gflop_per_step"] = float((ev * flops).sum()) / abl_steps / 1e9
 
     if args.route != "score":
         log("[bench] score form")
         spol = hydro.make_policy("score", precision="bf16", wave=args.wave, grouped=1, autotune=1, time_kernels=1,
                                  **extra)
         ids_s, st_s, inf_s, dts = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, spol,
-                                           args.steps, args.warmup, n, cal, args.safety)
+                                           abl_steps, 1, n, cal, args.safety)
         assert np.array_equal(ids_s, ids), "score and learned routing disagree"
         ev_s = np.array([[x["evaluated"] for x in st] for st in st_s], dtype=np.float64)
-        out["score"] = {"value": n * args.steps / dts, "unit": "tuples/s",
-                        "udf_gflop_per_step": float((ev_s * flops).sum()) / args.steps / 1e9,
-                        "first_pass_ms_per_step": sum(i["first_pass_ms"] for i in inf_s) / args.steps}
+        out["score"] = {"value": n * abl_steps / dts, "unit": "tuples/s",
+                        "udf_gflop_per_step": float((ev_s * flops).sum()) / abl_steps / 1e9,
+                        "first_pass_ms_per_step": sum(i["first_pass_ms"] for i in inf_s) / abl_steps}
 
-    if args.host or cfg.push_batch > 0:
+    if primary and (args.host or cfg.push_batch > 0):
         blk = cfg.push_batch if cfg.push_batch > 0 else 16384
-        log(f"[bench] full form pushed from pinned host memory in blocks of {blk}")
-        frames_host = torch.from_numpy(frames).pin_memory()
+        nh = min(n, blk * args.host_blocks)
+        log(f"[bench] full form pushed from pinned host memory: {nh} tuples in blocks of {blk}")
+        frames_host = torch.empty(tuple(frames_dev[:nh].shape), dtype=frames_dev.dtype, pin_memory=True)
+        frames_host.copy_(frames_dev[:nh])
         hpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, **extra)
         ids_h, _, _, dth = run_form(hydro, torch, specs, frames_host, cfg.dtype, pt, seg_len, hpol,
-                                    max(1, args.steps // 2), 1, n, cal, args.safety, push_batch=blk)
-        assert np.array_equal(ids_h, ids), "host-pushed and device-resident runs disagree"
-        out["host_pinned"] = {"value": n * max(1, args.steps // 2) / dth, "unit": "tuples/s",
+                                    abl_steps, 1, nh, cal, args.safety, push_batch=blk)
+        assert np.array_equal(ids_h, ids[ids < nh]), "host-pushed and device-resident runs disagree"
+        out["host_pinned"] = {"value": nh * abl_steps / dth, "unit": "tuples/s", "tuples": nh,
                               "push_batch": blk, "note": "PCIe-inclusive: frames start in pinned host memory",
-                              "h2d_gb_per_s_equiv": frames.nbytes * max(1, args.steps // 2) / dth / 1e9}
-        del frames_host
+                              "h2d_gb_per_s_equiv": frames_host.numel() * frames_host.element_size() * abl_steps
+                              / dth / 1e9}
+        # pinned-copy peak of the same bytes, for the H2D fraction
+        dst = torch.empty_like(frames_dev[:blk])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lo in range(0, nh, blk):
+            dst.copy_(frames_host[lo:lo + blk], non_blocking=True)
+        torch.cuda.synchronize()
+        out["host_pinned"]["pinned_copy_gb_per_s"] = frames_host.numel() * frames_host.element_size() / \
+            (time.perf_counter() - t0) / 1e9
+        del frames_host, dst
 
     if not args.no_plain:
         log("[bench] plain form")
         plain_pol = hydro.make_policy("score", precision="fp32", wave=args.wave, grouped=0, time_kernels=0, **extra)
         ids_p, _, _, dtp = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, plain_pol,
-                                    max(1, args.steps // 2), 1, n, cal, args.safety)
+                                    abl_steps, 1, n, cal, args.safety)
         assert np.array_equal(ids_p, ids), "plain and full forms disagree"
-        vp = n * max(1, args.steps // 2) / dtp
+        vp = n * abl_steps / dtp
         out["plain"] = {"value": vp, "unit": "tuples/s",
                         "form": "fp32 first pass, score routing, per-predicate launches, no graph"}
         out["speedup_vs_plain"] = value / vp
 
-    if args.errors > 0:
+    if args.errors > 0 and primary:
         # error of the bf16 and fp32 passes against the library's FP64 pass (which the parity
         # tests pin to the oracle to ~1e-15)
         m = min(args.errors, n)
@@ -308,22 +323,24 @@ def main():
         es.close()
         out["logit_error"] = rep
 
-    if not args.no_cpu:
+    if not args.no_cpu and primary:
         # FP64 oracle on a bounded, evenly spread sample of the same workload
         from threadpoolctl import threadpool_info
         from oracle import hydro_oracle as ho
         # bounded sample: about 1e13 FP64 FLOPs of oracle work (every predicate on every tuple)
         m = int(min(args.cpu_sample, n, max(1024, 1e13 // float(flops.sum()))))
         sel = np.linspace(0, n - 1, m).astype(np.int64)
-        fr_s = np.ascontiguousarray(frames[sel])
+        fr_s = host_frames(frames_dev, sel, torch)
         cores = min(16, os.cpu_count() or 1)
         log(f"[bench] cpu oracle on {m} sampled tuples, {cores} threads")
         t0 = time.perf_counter()
         P = np.zeros((m, cfg.k), dtype=bool)
+        D = np.zeros((m, cfg.k), dtype=np.float64)
         th = ho.tuple_thresholds(pt.thresholds, seg_len, sel)
         for j, w in enumerate(weights):
             z = ho.model_logits(w, fr_s, cfg.dtype, workers=cores)
-            P[:, j] = ho.decide(ho.predicate_margin(z, pt.class_masks[j]), th[:, j])
+            D[:, j] = ho.predicate_margin(z, pt.class_masks[j])
+            P[:, j] = ho.decide(D[:, j], th[:, j])
         tc = time.perf_counter() - t0
         exp_in = P.all(axis=1)
         got_in = np.isin(sel, ids)
@@ -332,9 +349,44 @@ def main():
                                          f"evaluated in fp64 (numpy, BLAS 1 thread per worker)",
                                "os_cpu_count": os.cpu_count(),
                                "blas": [d.get("internal_api") for d in threadpool_info()]}
-        out["sample_check"] = {"tuples": m, "mismatches": int((exp_in != got_in).sum())}
+        # near-tie audit of the sample: exactness against FP64 is well defined where no margin lies
+        # within FP64 rounding noise of its threshold
+        gap = float(np.abs(D - th)[np.isfinite(D)].min()) if np.isfinite(D).any() else float("inf")
+        out["sample_check"] = {"tuples": m, "mismatches": int((exp_in != got_in).sum()), "min_margin_gap": gap}
         if (exp_in != got_in).any():
             log("[bench] WARNING: GPU ids differ from the oracle on the sample")
+    del frames_dev, cal
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus above 1 is not supported "
+                                   "(sharding across GPUs is a design note only, nothing runs on several)"}))
+        sys.exit(2)
+    import torch
+    import hydro_synth as hs
+    from paper_2403_14902_amd import hydro
+
+    torch.cuda.set_device(0)
+    hydro.lib()
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    abl = max(1, min(args.ablation_steps, args.steps))
+    out = measure(args, args.workload, args.n, args.steps, args.warmup, abl, hydro, torch, hs, True)
+    if not args.no_secondary and args.workload != 2:
+        # the 65,536-frame 64x64 CNN workload (fused per-frame kernel), as a second line
+        sec = measure(args, 2, 0, max(1, min(args.steps, 10)), 2, abl, hydro, torch, hs, False)
+        out["cnn3_drift64"] = {k: sec[k] for k in ("value", "ms_per_step", "steps", "eager_value", "roofline",
+                                                    "plain", "speedup_vs_plain", "score", "n_result", "config")
+                               if k in sec}
     print(json.dumps(out), flush=True)
 
 

@@ -81,6 +81,7 @@ struct DevState {
   int train_steps;
   unsigned long long ring_head;        // outcomes logged so far (ring index = head mod size)
   unsigned long long ring_trained;     // ring position the trainer has consumed up to
+  int overflow;                        // set if a launch saw more evaluations than its buffers hold
 };
 
 // Which arm a routing batch belongs to: 1 = learned router, 0 = score routing (control).

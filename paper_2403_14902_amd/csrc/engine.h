@@ -1,6 +1,8 @@
 // Internal interfaces between the round driver (engine.hip) and the predicate kernels.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace hydro {
@@ -97,7 +99,34 @@ struct GcnnArgs {
   DevState* st;
   int count_ticks;
   int prec;
+  // 4-layer 128x128 CNNs (conv 32-64-128-256): dedicated kernels (cnn4.hip); per slot
+  int c4[kMaxK];                               // 1: the slot takes the dedicated kernels
+  const void* c4_w1b[kMaxK];                   // layer 1, bf16 MFMA fragments [2][64][8]
+  const void* c4_w1f[kMaxK];                   // layer 1, fp32 fragments [7][2][64]
+  const void* c4_w2[kMaxK][3];                 // layer 2 register fragments per tier (C4_*)
+  const void* c4_img[kMaxK][2][3];             // layers 3, 4: A tile images per tier
+  const float* c4_wscale[kMaxK][3];            // FP8 tier: per-channel weight scales, layers 2..4
+  float c4_ascale[kMaxK][3];                   // FP8 tier: activation scales, outputs of layers 1..3
+  void* c4_act2;                               // layer-2 outputs [act_cap][32][32][64]
+  void* c4_act3;                               // layer-3 outputs [act_cap][16][16][128]
+  int64_t act_cap;                             // evaluations one launch may hold
+  unsigned* c4_act_max;                        // calibration: [kMaxK][4] activation maxima (bits)
+  const void* zero_page;                       // 256 zero bytes (padding taps of the GEMM gathers)
 };
+
+// Arithmetic tiers of the dedicated 4-layer CNN kernels.
+enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2 };
+struct C4FrontPack {
+  std::vector<float> w1b, w1f, w2b;   // layer 1 (bf16 / fp32 fragment order), layer 2 (fp32 values)
+  std::vector<uint8_t> w2q;           // layer 2 e4m3
+};
+bool c4_shape_ok(int in_hw, int n_layers, const int* widths);
+void c4_pack_front(const float* w1, float scale1, const float* w2, const float* s2, C4FrontPack* out);
+size_t c4_img_bytes(int prec, int layer);
+void c4_pack_img(int prec, int layer, const float* w, const float* scale, unsigned char* out);
+uint8_t c4_fp8_e4m3(float x);
+float c4_fp8_value(uint8_t b);
+void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hipStream_t s);
 
 void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 size_t gcnn_packed_elems(int layer, int cin, int cout, int prec);

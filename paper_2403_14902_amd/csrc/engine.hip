@@ -417,6 +417,7 @@ struct hydro_session {
   // copy of `scratch`); nothing is allocated or freed
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_used = 0;
+  int64_t act_cap = 0;   // entries of the layer-wise CNN activation buffers (evaluations per launch)
 };
 
 // Captured pushes bake the bands (and every other launch argument) into their kernel nodes.
@@ -510,6 +511,58 @@ static int validate_model(const hydro_model& m, int fh, int fw) {
   return HYDRO_OK;
 }
 
+// Weight forms of the dedicated 4-layer CNN kernels for gcnn slot i: layer-1/2 register fragments
+// and layer-3/4 A tile images per tier, and the FP8 tier's per-output-channel weight scales
+// (largest |w| of the channel maps to 448, the largest finite e4m3 value).
+static int pack_c4(hydro_session* s, const HostModel& hm, float scale1, int i) {
+  GcnnArgs& ga = s->gcnn;
+  int rc;
+  std::vector<float> sc[3];
+  for (int l = 1; l < 4; ++l) {
+    const int co = hm.m.widths[l], cin = hm.m.widths[l - 1];
+    sc[l - 1].resize(co);
+    for (int o = 0; o < co; ++o) {
+      double mx = 0;
+      for (int t = 0; t < cin * 9; ++t) mx = std::max(mx, (double)std::fabs(hm.cw[l][(size_t)o * cin * 9 + t]));
+      sc[l - 1][o] = mx > 0 ? (float)(mx / 448.0) : 1.f;
+    }
+    float* dp;
+    if ((rc = upload(s, sc[l - 1].data(), sc[l - 1].size(), &dp))) return rc;
+    ga.c4_wscale[i][l - 1] = dp;
+  }
+  C4FrontPack fp;
+  c4_pack_front(hm.cw[0].data(), scale1, hm.cw[1].data(), sc[0].data(), &fp);
+  {
+    std::vector<uint16_t> b(fp.w1b.size());
+    for (size_t t = 0; t < b.size(); ++t) b[t] = f32_to_bf16_bits(fp.w1b[t]);
+    uint16_t* bp;
+    if ((rc = upload(s, b.data(), b.size(), &bp))) return rc;
+    ga.c4_w1b[i] = bp;
+    float* dp;
+    if ((rc = upload(s, fp.w1f.data(), fp.w1f.size(), &dp))) return rc;
+    ga.c4_w1f[i] = dp;
+    std::vector<uint16_t> b2(fp.w2b.size());
+    for (size_t t = 0; t < b2.size(); ++t) b2[t] = f32_to_bf16_bits(fp.w2b[t]);
+    if ((rc = upload(s, b2.data(), b2.size(), &bp))) return rc;
+    ga.c4_w2[i][C4_BF16] = bp;
+    if ((rc = upload(s, fp.w2b.data(), fp.w2b.size(), &dp))) return rc;
+    ga.c4_w2[i][C4_F32] = dp;
+    uint8_t* qp;
+    if ((rc = upload(s, fp.w2q.data(), fp.w2q.size(), &qp))) return rc;
+    ga.c4_w2[i][C4_FP8] = qp;
+  }
+  for (int l = 2; l < 4; ++l)
+    for (int p = 0; p < 3; ++p) {
+      std::vector<unsigned char> img(c4_img_bytes(p, l));
+      c4_pack_img(p, l, hm.cw[l].data(), sc[l - 1].data(), img.data());
+      unsigned char* dp;
+      if ((rc = upload(s, img.data(), img.size(), &dp))) return rc;
+      ga.c4_img[i][l - 2][p] = dp;
+    }
+  for (int l = 0; l < 3; ++l) ga.c4_ascale[i][l] = 1.f;   // until calibrated
+  return HYDRO_OK;
+}
+
 static int pack_models(hydro_session* s) {
   const double scale = s->fdtype == HYDRO_DTYPE_U8 ? 4.0 / 255.0 : 4.0;
   const float pad_raw = s->fdtype == HYDRO_DTYPE_U8 ? 127.5f : 0.5f;
@@ -522,6 +575,13 @@ static int pack_models(hydro_session* s) {
   // allocation-free sessions keep the FP64 tier's layer-parallel batch and fallback slots small
   const int esc_cap = s->arena ? std::min(esc_cap_setting(), kArenaEscCap) : esc_cap_setting();
   const int rest_grid = s->arena ? kArenaRestGrid : s->n_cu;
+  // Layer-wise CNN launches keep per-evaluation activations.  A round's queues hold only live
+  // tuples: those admitted in the last K rounds (a tuple is evaluated at most once per round and
+  // leaves after K evaluations), so at most K x (largest admission) entries, whatever the push size.
+  {
+    const int64_t warm = (int64_t)s->pol.warmup_batches * s->K * s->pol.routing_batch;
+    s->act_cap = std::min<int64_t>(s->cap, (int64_t)s->K * std::max<int64_t>(s->pol.wave, warm));
+  }
   // grouped launches walk their slots in order: most expensive predicates first, so the
   // longest work items start early (longest-processing-time-first)
   std::vector<int> slots_order(s->K);
@@ -655,6 +715,8 @@ static int pack_models(hydro_session* s) {
       ga.fc_w[i] = dp;
       if ((rc = upload(s, hm.fcb.data(), hm.fcb.size(), &dp))) return rc;
       ga.fc_b[i] = dp;
+      ga.c4[i] = c4_shape_ok(m.in_h, m.n_layers, m.widths) ? 1 : 0;
+      if (ga.c4[i] && (rc = pack_c4(s, hm, (float)scale, i))) return rc;
     } else {
       int i = ca.n_preds++;
       ca.pred[i] = k;
@@ -730,8 +792,27 @@ static int pack_models(hydro_session* s) {
       }
     ga.act_stride = mx;
     int rc;
-    for (int b = 0; b < 2; ++b)
-      if ((rc = sess_alloc(s, &ga.act[b], (size_t)s->cap * mx * sizeof(float)))) return rc;
+    bool generic = false, any_c4 = false;
+    for (int i = 0; i < ga.n_preds; ++i) {
+      generic = generic || !ga.c4[i];
+      any_c4 = any_c4 || ga.c4[i];
+    }
+    ga.act_cap = s->act_cap;
+    if (generic)
+      for (int b = 0; b < 2; ++b)
+        if ((rc = sess_alloc(s, &ga.act[b], (size_t)s->act_cap * mx * sizeof(float)))) return rc;
+    if (any_c4) {
+      // dedicated kernels: layer-2 and layer-3 outputs of every evaluation of a launch (sized for
+      // the FP32 tier), the activation maxima of calibration, and a zero page for padding taps
+      if ((rc = sess_alloc(s, &ga.c4_act2, (size_t)s->act_cap * 32 * 32 * 64 * sizeof(float)))) return rc;
+      if ((rc = sess_alloc(s, &ga.c4_act3, (size_t)s->act_cap * 16 * 16 * 128 * sizeof(float)))) return rc;
+      void* zp;
+      if ((rc = sess_alloc(s, &zp, 256))) return rc;
+      HIP_TRY(hipMemsetAsync(zp, 0, 256, s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      ga.zero_page = zp;
+      ga.c4_act_max = nullptr;
+    }
     ga.esc_half = mx;
     ga.esc_stride = 2 * mx;
     ga.esc_cap = std::min(esc_cap, 32);
@@ -1554,6 +1635,7 @@ static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int
   HIP_TRY(hipGetLastError());
   DevState h;
   HIP_TRY(hipMemcpy(&h, s->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  if (h.overflow) return fail(HYDRO_EDEVICE, "internal: a launch held more evaluations than its activation buffers");
   const int64_t nres = h.n_result;
   int64_t* ids = dst;
   if (dst) {
@@ -1677,13 +1759,9 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   std::vector<uint32_t> ent(fr.n);
   for (int64_t i = 0; i < fr.n; ++i) ent[i] = make_entry((uint32_t)i, 0u);
   uint32_t* qbase = t == TIER_FIRST ? s->q1 : t == TIER_F32 ? s->q2 : s->q3;
-  HIP_TRY(hipMemcpy(qbase + (int64_t)pred * s->cap, ent.data(), fr.n * 4, hipMemcpyHostToDevice));
-  DevState zero{};
-  HIP_TRY(hipMemcpy(s->st, &zero, sizeof(DevState), hipMemcpyHostToDevice));
-  int cnt[kMaxK] = {0};
-  cnt[pred] = (int)fr.n;
   int* cptr = t == TIER_FIRST ? s->st->qcount : t == TIER_F32 ? s->st->bcount : s->st->ecount;
-  HIP_TRY(hipMemcpy(cptr, cnt, sizeof(cnt), hipMemcpyHostToDevice));
+  // layer-wise CNN launches hold activations for at most act_cap queued evaluations
+  const int64_t chunk = s->gcnn.n_preds > 0 ? std::max<int64_t>(1, s->act_cap) : fr.n;
   double* dlog;
   const size_t arena_mark = s->arena_used;   // allocation-free sessions: a temporary arena slice
   if (s->arena) {
@@ -1695,8 +1773,20 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   Forward f = make_forward(s, t, 0, src, 1, 1, 0);
   f.logits = dlog;
   f.defer = Queues{nullptr, nullptr, 0};
-  enqueue_tier(s, t, src, f, st);
-  hipError_t he = hipStreamSynchronize(st);
+  hipError_t he = hipSuccess;
+  for (int64_t i0 = 0; i0 < fr.n && he == hipSuccess; i0 += chunk) {
+    const int64_t m = std::min(chunk, fr.n - i0);
+    DevState zero{};
+    int cnt[kMaxK] = {0};
+    cnt[pred] = (int)m;
+    he = hipMemcpy(qbase + (int64_t)pred * s->cap, ent.data() + i0, m * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(s->st, &zero, sizeof(DevState), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(cptr, cnt, sizeof(cnt), hipMemcpyHostToDevice);
+    if (he == hipSuccess) {
+      enqueue_tier(s, t, src, f, st);
+      he = hipStreamSynchronize(st);
+    }
+  }
   if (he == hipSuccess) he = hipMemcpy(out_logits, dlog, fr.n * kClasses * sizeof(double), hipMemcpyDeviceToHost);
   if (s->arena) s->arena_used = arena_mark;
   else hipFree(dlog);

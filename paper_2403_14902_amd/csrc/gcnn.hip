@@ -662,6 +662,8 @@ __global__ __launch_bounds__(256) void gcnn64_rest_kernel(GcnnArgs a, Forward f,
   }
 }
 
+void launch_gcnn_layerwise(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
+
 // ---------------------------------------------------------------- host side
 size_t gcnn_packed_elems(int layer, int cin, int cout, int prec) {
   const int ks = prec == HYDRO_PREC_BF16 ? g_ksteps<__bf16>(layer, cin) : g_ksteps<float>(layer, cin);
@@ -693,8 +695,45 @@ void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, flo
         }
 }
 
-void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
-  if (a.n_preds == 0) return;
+// Slot i of src becomes slot j of dst.
+static void gcnn_copy_slot(GcnnArgs& dst, int j, const GcnnArgs& src, int i) {
+  dst.pred[j] = src.pred[i]; dst.n_layers[j] = src.n_layers[i]; dst.in_hw[j] = src.in_hw[i];
+  dst.class_mask[j] = src.class_mask[i]; dst.fc_w[j] = src.fc_w[i]; dst.fc_b[j] = src.fc_b[i];
+  dst.esc_act[j] = src.esc_act[i]; dst.c4[j] = src.c4[i];
+  dst.c4_w1b[j] = src.c4_w1b[i]; dst.c4_w1f[j] = src.c4_w1f[i];
+  for (int l = 0; l < HYDRO_MAX_LAYERS; ++l) {
+    dst.widths[j][l] = src.widths[i][l]; dst.w_bf[j][l] = src.w_bf[i][l]; dst.w_f32[j][l] = src.w_f32[i][l];
+    dst.bias[j][l] = src.bias[i][l]; dst.wt_canon[j][l] = src.wt_canon[i][l]; dst.b_canon[j][l] = src.b_canon[i][l];
+  }
+  for (int p = 0; p < 3; ++p) {
+    dst.c4_w2[j][p] = src.c4_w2[i][p]; dst.c4_wscale[j][p] = src.c4_wscale[i][p];
+    dst.c4_ascale[j][p] = src.c4_ascale[i][p];
+    dst.c4_img[j][0][p] = src.c4_img[i][0][p]; dst.c4_img[j][1][p] = src.c4_img[i][1][p];
+  }
+}
+
+void launch_gcnn_pass(const GcnnArgs& a0, const Forward& f, int tier, int grid, hipStream_t s) {
+  if (a0.n_preds == 0) return;
+  if (tier != TIER_F64) {
+    // slots of the 4-layer 128x128 shape take the dedicated kernels; the rest the layer-wise ones
+    GcnnArgs c4a = a0, gen = a0;
+    c4a.n_preds = gen.n_preds = 0;
+    for (int i = 0; i < a0.n_preds; ++i) {
+      if (a0.c4[i]) gcnn_copy_slot(c4a, c4a.n_preds++, a0, i);
+      else gcnn_copy_slot(gen, gen.n_preds++, a0, i);
+    }
+    if (c4a.n_preds > 0) {
+      const int p = tier == TIER_FIRST && a0.prec == HYDRO_PREC_BF16 ? C4_BF16 : C4_F32;
+      launch_c4_pass(c4a, f, p, grid, s);
+    }
+    if (gen.n_preds == 0) return;
+    launch_gcnn_layerwise(gen, f, tier, grid, s);
+    return;
+  }
+  launch_gcnn_layerwise(a0, f, tier, grid, s);
+}
+
+void launch_gcnn_layerwise(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
   int maxl = 0;
   for (int i = 0; i < a.n_preds; ++i) maxl = a.n_layers[i] > maxl ? a.n_layers[i] : maxl;
   if (tier == TIER_F64) {
