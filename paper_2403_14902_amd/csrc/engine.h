@@ -129,6 +129,8 @@ float c4_fp8_value(uint8_t b);
 void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hipStream_t s);
 
 void launch_gcnn_pass(const GcnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
+// Slot i of src becomes slot j of dst (every per-slot field).
+void gcnn_copy_slot(GcnnArgs& dst, int j, const GcnnArgs& src, int i);
 size_t gcnn_packed_elems(int layer, int cin, int cout, int prec);
 void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, float scale, float* out);
 

@@ -1169,12 +1169,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
       for (int i = 0; i < s->gcnn.n_preds; ++i) {
         GcnnArgs b = a;
         b.n_preds = 1;
-        b.pred[0] = a.pred[i]; b.n_layers[0] = a.n_layers[i]; b.in_hw[0] = a.in_hw[i]; b.class_mask[0] = a.class_mask[i];
-        for (int l = 0; l < HYDRO_MAX_LAYERS; ++l) {
-          b.widths[0][l] = a.widths[i][l]; b.w_bf[0][l] = a.w_bf[i][l]; b.w_f32[0][l] = a.w_f32[i][l];
-          b.bias[0][l] = a.bias[i][l]; b.wt_canon[0][l] = a.wt_canon[i][l]; b.b_canon[0][l] = a.b_canon[i][l];
-        }
-        b.fc_w[0] = a.fc_w[i]; b.fc_b[0] = a.fc_b[i]; b.esc_act[0] = a.esc_act[i];
+        gcnn_copy_slot(b, 0, a, i);
         launch_gcnn_pass(b, f, tier, s->n_cu, st);
       }
     }

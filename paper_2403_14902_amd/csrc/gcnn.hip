@@ -696,7 +696,7 @@ void gcnn_pack_layer(int layer, int cin, int cout, int prec, const float* w, flo
 }
 
 // Slot i of src becomes slot j of dst.
-static void gcnn_copy_slot(GcnnArgs& dst, int j, const GcnnArgs& src, int i) {
+void gcnn_copy_slot(GcnnArgs& dst, int j, const GcnnArgs& src, int i) {
   dst.pred[j] = src.pred[i]; dst.n_layers[j] = src.n_layers[i]; dst.in_hw[j] = src.in_hw[i];
   dst.class_mask[j] = src.class_mask[i]; dst.fc_w[j] = src.fc_w[i]; dst.fc_b[j] = src.fc_b[i];
   dst.esc_act[j] = src.esc_act[i]; dst.c4[j] = src.c4[i];

@@ -55,6 +55,23 @@ def test_c5_query_device_frames(c5, route, prec):
     s.close()
 
 
+def test_c5_ungrouped_launches(c5z, c5):
+    """One launch per predicate (the plain form): every predicate runs its own weights."""
+    pol = hydro.make_policy("score", precision="fp32", grouped=0, wave=256)
+    s = hydro.Session(c5z.specs(), pol, 128, 1024)
+    dev = c5z.device_frames()
+    for k in range(c5z.cfg.k):
+        for tier in (0, 2):
+            err = np.abs(s.logits(k, tier, dev, "u8") - c5z.Z[k]).max()
+            log(f"[gpu] c5 ungrouped predicate {k} tier {tier}: max |z - z64| = {err:.3e}")
+            assert err <= (1e-5 if tier == 0 else 1e-12)
+    s.push(c5.device_frames(), "u8", c5.pt.thresholds, c5.seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, c5.expect)
+    check_stats(stats, c5.n, ids.size)
+    s.close()
+
+
 def test_c5_pinned_host_pushes(c5):
     """Frames pushed from pinned host memory in blocks, as the streaming form does."""
     pin = torch.from_numpy(c5.frames).pin_memory()
