@@ -106,7 +106,13 @@ typedef enum {
                                SCORE and falling back to it                                       */
 } hydro_route;
 
-typedef enum { HYDRO_PREC_FP32 = 0, HYDRO_PREC_BF16 = 1 } hydro_precision;
+/* First-pass arithmetic.  FP32: fp32 operands.  BF16: bf16 operands, fp32 accumulation; margins
+ * within tau of the threshold are re-scored in FP32.  FP8: OCP e4m3 operands with per-output-channel
+ * weight scales and per-layer activation scales, fp32 accumulation (4-layer 128x128 CNN predicates
+ * conv 32-64-128-256 only; layer 1 runs bf16, exact for raw frame values); margins within tau are
+ * re-scored in BF16, BF16 margins within tau16 in FP32.  Every chain ends with FP32 margins within
+ * tau32 re-scored in FP64, which decides.  The answer never depends on the precision. */
+typedef enum { HYDRO_PREC_FP32 = 0, HYDRO_PREC_BF16 = 1, HYDRO_PREC_FP8 = 2 } hydro_precision;
 typedef enum { HYDRO_COST_MEASURED = 0, HYDRO_COST_STATIC = 1 } hydro_cost_source;
 
 /* Execution policy.  Fill with hydro_policy_default() and override fields. */
@@ -143,6 +149,9 @@ typedef struct {
                                             as the judge's control arm (default 0.05)            */
   uint64_t seed;                         /* LEARNED: router init / exploration seed              */
   void* stream;                          /* hipStream_t to run on; NULL: the session's own       */
+  float tau16;                           /* FP8 first pass: |d - theta| < tau16 of the BF16
+                                            re-score goes on to FP32.  <= 0 (default): automatic */
+  int32_t pad_;
 } hydro_policy;
 
 /* Per-predicate statistics of one query. */
@@ -154,6 +163,7 @@ typedef struct {
   double device_us;            /* summed device time of this predicate's first-pass tiles       */
   double cost_us_per_tuple;    /* final running cost estimate                                   */
   double selectivity;          /* passed / evaluated: conditional on the tuples it saw          */
+  uint64_t rescored16;         /* FP8 first pass: BF16 decisions deferred to the FP32 pass      */
 } hydro_pred_stats;
 
 /* Whole-query counters. */
@@ -174,6 +184,7 @@ typedef struct {
   uint64_t learned_stale;                  /* LEARNED: learned-arm decisions whose keys had not
                                               been computed in the deciding round (routed by the
                                               statistics ranking instead; 0 in a correct run)    */
+  double mid_pass_ms;                      /* policy.time_kernels, FP8 first pass: BF16 re-score */
 } hydro_query_info;
 
 /* One routing round of the last query (policy.log_routes = 1), for checking the router against
@@ -272,7 +283,8 @@ int hydro_session_routes(const hydro_session* s, int64_t first_id, int64_t n, ui
 int hydro_session_round_log(const hydro_session* s, int32_t first, int32_t n, hydro_round_record* out);
 
 /* Evaluate predicate `pred`'s model on every given tuple at one arithmetic tier
- * (0 = the first-pass precision of the session, 1 = FP32, 2 = FP64) and return its logits as
+ * (0 = the first-pass precision of the session, 1 = FP32, 2 = FP64, 3 = the BF16 re-score tier of
+ * an FP8 session; sessions of other precisions map 3 to their first pass) and return its logits as
  * fp64 [n][10] in host memory.  Used for logit-error reports and kernel parity tests.  Runs between
  * queries only: ESTATE while a query is open (a push since the last reset or finish); it leaves
  * the session reset. */
@@ -280,8 +292,10 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
                          double* out_logits);
 
 /* Set every predicate's re-score bands from measurement: on the given device frames, each
- * predicate's first-pass and FP32 margins are compared with its FP64 margins; tau_k and tau32_k
- * become `safety` (>= 1) times the largest difference seen (floors 1e-4 and 1e-6).  Later pushes
+ * predicate's first-pass, BF16 (FP8 sessions) and FP32 margins are compared with its FP64 margins;
+ * tau_k, tau16_k and tau32_k become `safety` (>= 1) times the largest difference seen (floors 1e-4,
+ * 1e-4 and 1e-6).  FP8 sessions first set each layer's activation scale so that the largest FP32
+ * activation on these frames maps to 224 (half of e4m3's largest value).  Later pushes
  * use these bands instead of policy.tau / policy.tau32.  out_tau / out_tau32: caller-allocated
  * [K] (may be NULL).  Any number of frames (>= 1); more than the session's max_push are taken
  * in blocks of max_push.  This is the per-configuration band of the low-precision form: an
@@ -290,6 +304,11 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
  * HIP graphs under the old bands are discarded (they are re-captured with the new ones). */
 int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float safety, float* out_tau,
                             float* out_tau32);
+
+/* The per-predicate bands the next push uses (policy values, automatic or calibrated): caller
+ * arrays [K], each may be NULL.  tau: first pass; tau16: BF16 re-score of an FP8 first pass;
+ * tau32: FP32 pass. */
+int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float* tau32);
 
 /* Replace the written order that route = FIXED follows (section 4.1, "No Reordering": the
  * conjunction evaluated left to right) for the session's next queries.  order: a permutation of

@@ -178,8 +178,8 @@ void c4_front_kernel(GcnnArgs a) {
     const unsigned long long t0 = wall_clock64();
     const unsigned char* frame = static_cast<const unsigned char*>(a.fr.base) + (int64_t)idx * a.fr.elems * (u8 ? 1 : 2);
     T* out2 = reinterpret_cast<T*>(a.c4_act2) + ent * (32 * 32 * 64);
-    unsigned* amax1 = a.c4_act_max ? a.c4_act_max + slot * 4 + 0 : nullptr;
-    unsigned* amax2 = a.c4_act_max ? a.c4_act_max + slot * 4 + 1 : nullptr;
+    unsigned* amax1 = a.c4_act_max ? a.c4_act_max + k * 4 + 0 : nullptr;
+    unsigned* amax2 = a.c4_act_max ? a.c4_act_max + k * 4 + 1 : nullptr;
 
     for (int b = 0; b < F_NB; ++b) {
       // ---- stage frame rows 16b-1 .. 16b+15 (raw values as bf16); row -1 is the pad value
@@ -583,7 +583,7 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
     if constexpr (!HEAD) {
       T* out = reinterpret_cast<T*>(a.c4_act3);
       const float inv_out = P == C4_FP8 ? 1.f / a.c4_ascale[slot][2] : 1.f;
-      unsigned* amax = a.c4_act_max ? a.c4_act_max + slot * 4 + 2 : nullptr;
+      unsigned* amax = a.c4_act_max ? a.c4_act_max + k * 4 + 2 : nullptr;
       float m = 0.f;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {

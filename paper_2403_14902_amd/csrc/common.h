@@ -59,9 +59,9 @@ struct PredDesc {
 // Device-resident routing state and statistics (one per session).
 struct DevState {
   // per-round accumulators (cleared by the fold kernel at the start of every round)
-  unsigned long long r_eval[kMaxK], r_pass[kMaxK], r_ticks[kMaxK], r_rescored[kMaxK], r_esc[kMaxK];
+  unsigned long long r_eval[kMaxK], r_pass[kMaxK], r_ticks[kMaxK], r_rescored[kMaxK], r_esc[kMaxK], r_mid[kMaxK];
   // query totals
-  unsigned long long t_eval[kMaxK], t_pass[kMaxK], t_ticks[kMaxK], t_rescored[kMaxK], t_esc[kMaxK];
+  unsigned long long t_eval[kMaxK], t_pass[kMaxK], t_ticks[kMaxK], t_rescored[kMaxK], t_esc[kMaxK], t_mid[kMaxK];
   double sel_est[kMaxK], cost_est[kMaxK];
   int seen[kMaxK];
   int order[kMaxK];            // predicate ranking used by this round's router
@@ -71,6 +71,7 @@ struct DevState {
   int qcount[kMaxK];           // first-pass queues
   int bcount[kMaxK];           // FP32 re-score queues
   int ecount[kMaxK];           // FP64 escalation queues
+  int mcount[kMaxK];           // BF16 re-score queues of an FP8 first pass
   int n_result;
   // learned router
   unsigned long long learned_routed, stats_routed;

@@ -7,7 +7,8 @@
 
 namespace hydro {
 
-enum Tier { TIER_FIRST = 0, TIER_F32 = 1, TIER_F64 = 2 };
+// TIER_MID: the BF16 re-score tier between an FP8 first pass and the FP32 tier.
+enum Tier { TIER_FIRST = 0, TIER_F32 = 1, TIER_F64 = 2, TIER_MID = 3 };
 
 // Grouped launch over the MLP predicates of one tier.
 struct MlpArgs {
@@ -110,7 +111,7 @@ struct GcnnArgs {
   void* c4_act2;                               // layer-2 outputs [act_cap][32][32][64]
   void* c4_act3;                               // layer-3 outputs [act_cap][16][16][128]
   int64_t act_cap;                             // evaluations one launch may hold
-  unsigned* c4_act_max;                        // calibration: [kMaxK][4] activation maxima (bits)
+  unsigned* c4_act_max;                        // calibration: [predicate][4] activation maxima (bits)
   const void* zero_page;                       // 256 zero bytes (padding taps of the GEMM gathers)
 };
 

@@ -119,6 +119,7 @@ __global__ void k_fold(FoldArgs a) {
     st->t_ticks[k] += tk;
     st->t_rescored[k] += st->r_rescored[k];
     st->t_esc[k] += st->r_esc[k];
+    st->t_mid[k] += st->r_mid[k];
     if (e > 0) {
       // running estimates; the +1/+2 prior keeps the selectivity off 0 and 1
       double s_obs = ((double)p + 1.0) / ((double)e + 2.0);
@@ -132,8 +133,8 @@ __global__ void k_fold(FoldArgs a) {
         st->cost_est[k] = (1.0 - a.alpha) * st->cost_est[k] + a.alpha * c_obs;
       }
     }
-    st->r_eval[k] = st->r_pass[k] = st->r_ticks[k] = st->r_rescored[k] = st->r_esc[k] = 0;
-    st->qcount[k] = st->bcount[k] = st->ecount[k] = 0;
+    st->r_eval[k] = st->r_pass[k] = st->r_ticks[k] = st->r_rescored[k] = st->r_esc[k] = st->r_mid[k] = 0;
+    st->qcount[k] = st->bcount[k] = st->ecount[k] = st->mcount[k] = 0;
     if (rr != nullptr) {
       rr->folded_evaluated[k] = e;
       rr->folded_passed[k] = p;
@@ -360,6 +361,7 @@ struct GraphKey {
   }
 };
 
+constexpr int kEvPerRound = 6;               // start, routed, first pass, BF16 mid, FP32, FP64
 constexpr float kAutoTauFloor = 0.015f;     // automatic bands never go below these
 constexpr float kAutoTau32Floor = 1e-5f;
 
@@ -376,7 +378,7 @@ struct hydro_session {
   // device state
   DevState* st = nullptr;
   uint32_t* pend[2] = {nullptr, nullptr};
-  uint32_t *q1 = nullptr, *q2 = nullptr, *q3 = nullptr;
+  uint32_t *q1 = nullptr, *q2 = nullptr, *q3 = nullptr, *qm = nullptr;   // first, FP32, FP64, BF16-mid
   uint32_t* result_bits = nullptr;
   uint32_t* route_log = nullptr;
   hydro_round_record* round_log = nullptr;   // log_routes: per-round rankings and folded counts
@@ -408,11 +410,14 @@ struct hydro_session {
   std::chrono::steady_clock::time_point t_start;
   hydro_query_info info{};
   double tick_us = 0.01;   // device wall clock period in microseconds
-  std::vector<hipEvent_t> evpool;   // time_kernels: 5 events per round
+  std::vector<hipEvent_t> evpool;   // time_kernels: kEvPerRound events per round
   int ev_used = 0;
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // use_graph: captured pushes
   float tau_k[kMaxK], tau32_k[kMaxK];   // per-predicate bands (policy values or calibrated)
+  float tau16_k[kMaxK];                 // FP8 sessions: band of the BF16 re-score tier
   bool auto_tau = false, auto_tau32 = false;   // bands still to be measured on the first push
+  bool auto_tau16 = false;
+  bool ascales_set = false;                    // FP8: activation scales measured
   // allocation-free sessions: every device buffer is carved from `arena` (the current device's
   // copy of `scratch`); nothing is allocated or freed
   unsigned char* arena = nullptr;
@@ -911,7 +916,8 @@ static int validate_policy(const hydro_policy* p, int K) {
   if (p->wave <= 0) return fail(HYDRO_EINVAL, "wave must be positive");
   if (p->warmup_batches < 0) return fail(HYDRO_EINVAL, "warmup_batches must be >= 0");
   if (!(p->ewma_alpha > 0.f && p->ewma_alpha <= 1.f)) return fail(HYDRO_EINVAL, "ewma_alpha must be in (0, 1]");
-  if (p->precision != HYDRO_PREC_FP32 && p->precision != HYDRO_PREC_BF16) return fail(HYDRO_EUNSUPPORTED, "precision not supported");
+  if (p->precision != HYDRO_PREC_FP32 && p->precision != HYDRO_PREC_BF16 && p->precision != HYDRO_PREC_FP8)
+    return fail(HYDRO_EUNSUPPORTED, "precision not supported");
   if (p->cost_source != HYDRO_COST_MEASURED && p->cost_source != HYDRO_COST_STATIC) return fail(HYDRO_EINVAL, "unknown cost_source");
   if (p->explore < 0.f || p->explore > 1.f) return fail(HYDRO_EINVAL, "explore must be in [0, 1]");
   return HYDRO_OK;
@@ -938,6 +944,10 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
   if (rc) return rc;
   for (int i = 0; i < k; ++i)
     if ((rc = validate_model(models[i], frame_h, frame_w))) return rc;
+  if (policy->precision == HYDRO_PREC_FP8)
+    for (int i = 0; i < k; ++i)
+      if (models[i].arch != HYDRO_ARCH_CNN || !c4_shape_ok(models[i].in_h, models[i].n_layers, models[i].widths))
+        return fail(HYDRO_EUNSUPPORTED, "the FP8 first pass is built for 4-layer 128x128 CNN predicates (32-64-128-256)");
 
   g_alloc_counter = 0;
   hydro_session* s = new hydro_session();
@@ -946,11 +956,14 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
   s->pol = *policy;
   s->auto_tau = s->pol.tau <= 0.f;
   s->auto_tau32 = s->pol.tau32 <= 0.f;
+  s->auto_tau16 = s->pol.precision == HYDRO_PREC_FP8 && s->pol.tau16 <= 0.f;
   if (s->auto_tau) s->pol.tau = kAutoTauFloor;
   if (s->auto_tau32) s->pol.tau32 = kAutoTau32Floor;
+  if (s->pol.tau16 <= 0.f) s->pol.tau16 = kAutoTauFloor;
   for (int i = 0; i < kMaxK; ++i) {
     s->tau_k[i] = s->pol.tau;
     s->tau32_k[i] = s->pol.tau32;
+    s->tau16_k[i] = s->pol.tau16;
   }
   s->K = k;
   s->fh = frame_h;
@@ -1020,6 +1033,7 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
   if ((rc = sess_alloc(s, (void**)&s->q1, cap * 4 * k))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->q2, cap * 4 * k))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->q3, cap * 4 * k))) return bail(rc);
+  if (s->pol.precision == HYDRO_PREC_FP8 && (rc = sess_alloc(s, (void**)&s->qm, cap * 4 * k))) return bail(rc);
   const int64_t nwords = (cap + 31) / 32;
   if ((rc = sess_alloc(s, (void**)&s->result_bits, nwords * 4 + 1024))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->res_blocks, ((nwords + 255) / 256 + 1) * 4))) return bail(rc);
@@ -1106,11 +1120,22 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
   f.logits = nullptr;
   f.olog = s->rnn ? router_nn_log(s->rnn) : OutcomeLog{};
   const bool bf = s->pol.precision == HYDRO_PREC_BF16;
-  if (tier == TIER_FIRST) {
+  const bool f8 = s->pol.precision == HYDRO_PREC_FP8;
+  if (tier == TIER_FIRST && f8) {
+    f.count_eval = 1;
+    f.defer = Queues{s->qm, s->st->mcount, s->cap};
+    f.defer_stat = s->st->r_rescored;
+    for (int k = 0; k < kMaxK; ++k) f.tau[k] = s->tau_k[k];
+  } else if (tier == TIER_FIRST) {
     f.count_eval = 1;
     f.defer = Queues{bf ? s->q2 : s->q3, bf ? s->st->bcount : s->st->ecount, s->cap};
     f.defer_stat = bf ? s->st->r_rescored : s->st->r_esc;
     for (int k = 0; k < kMaxK; ++k) f.tau[k] = bf ? s->tau_k[k] : s->tau32_k[k];
+  } else if (tier == TIER_MID) {
+    f.count_eval = 0;
+    f.defer = Queues{s->q2, s->st->bcount, s->cap};
+    f.defer_stat = s->st->r_mid;
+    for (int k = 0; k < kMaxK; ++k) f.tau[k] = s->tau16_k[k];
   } else if (tier == TIER_F32) {
     f.count_eval = 0;
     f.defer = Queues{s->q3, s->st->ecount, s->cap};
@@ -1130,6 +1155,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
   Queues q;
   if (tier == TIER_FIRST) q = Queues{s->q1, s->st->qcount, s->cap};
   else if (tier == TIER_F32) q = Queues{s->q2, s->st->bcount, s->cap};
+  else if (tier == TIER_MID) q = Queues{s->qm, s->st->mcount, s->cap};
   else q = Queues{s->q3, s->st->ecount, s->cap};
   // grouped: one launch covers every predicate of an architecture; otherwise one launch per
   // predicate (the plain form)
@@ -1351,7 +1377,9 @@ static int ensure_dtype(hydro_session* s, int dtype) {
 
 static size_t dtype_size(int dt) { return dt == HYDRO_DTYPE_F32 ? 4 : dt == HYDRO_DTYPE_BF16 ? 2 : 1; }
 
-static int measure_bands(hydro_session* s, const hydro_frames* frames, float safety, float* tau, float* tau32);
+static int measure_bands(hydro_session* s, const hydro_frames* frames, float safety, float* tau, float* tau16,
+                         float* tau32);
+static int measure_ascales(hydro_session* s, const hydro_frames* frames);
 
 // Automatic bands (policy tau / tau32 <= 0): measured once, on up to 1,024 frames of the
 // session's first push, with safety 3, and never below the fixed defaults.
@@ -1371,16 +1399,19 @@ static int auto_bands(hydro_session* s, const hydro_frames& fr) {
     sub.data = tmp;
     sub.where = HYDRO_MEM_DEVICE;
   }
-  float tau[kMaxK], tau32[kMaxK];
-  const int rc = measure_bands(s, &sub, 3.0f, tau, tau32);
+  float tau[kMaxK], tau16[kMaxK], tau32[kMaxK];
+  int rc = HYDRO_OK;
+  if (s->pol.precision == HYDRO_PREC_FP8 && !s->ascales_set) rc = measure_ascales(s, &sub);
+  if (!rc) rc = measure_bands(s, &sub, 3.0f, tau, tau16, tau32);
   if (tmp) hipFree(tmp);
   if (rc) return rc;
-  const bool bf = s->pol.precision == HYDRO_PREC_BF16;
+  const bool low = s->pol.precision != HYDRO_PREC_FP32;
   for (int k = 0; k < s->K; ++k) {
-    if (s->auto_tau) s->tau_k[k] = bf ? std::max(tau[k], kAutoTauFloor) : std::max(tau32[k], kAutoTau32Floor);
+    if (s->auto_tau) s->tau_k[k] = low ? std::max(tau[k], kAutoTauFloor) : std::max(tau32[k], kAutoTau32Floor);
+    if (s->auto_tau16) s->tau16_k[k] = std::max(tau16[k], kAutoTauFloor);
     if (s->auto_tau32) s->tau32_k[k] = std::max(tau32[k], kAutoTau32Floor);
   }
-  s->auto_tau = s->auto_tau32 = false;
+  s->auto_tau = s->auto_tau32 = s->auto_tau16 = false;
   drop_graphs(s);
   return HYDRO_OK;
 }
@@ -1404,7 +1435,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   if (rc) return rc;
   for (int64_t i = 0; i < (int64_t)n_seg * s->K; ++i)
     if (std::isnan(thresholds[i])) return fail(HYDRO_EINVAL, "threshold is NaN");
-  if ((s->auto_tau || s->auto_tau32) && fr.n > 0 && s->pushes == 0)
+  if ((s->auto_tau || s->auto_tau32 || s->auto_tau16) && fr.n > 0 && s->pushes == 0)
     if ((rc = auto_bands(s, fr))) return rc;
 
   if (s->pushes == 0) s->t_start = std::chrono::steady_clock::now();
@@ -1508,9 +1539,9 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
     int parity = parity0;
     for (int r = 0; r < n_rounds; ++r) {
       const int in_slot = parity, out_slot = parity ^ 1;
-      hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+      hipEvent_t ev[kEvPerRound] = {};
       if (timed) {
-        for (int i = 0; i < 5; ++i) ev[i] = next_event(s);
+        for (int i = 0; i < kEvPerRound; ++i) ev[i] = next_event(s);
         if (ev[0]) hipEventRecord(ev[0], st);
       }
       FoldArgs fa{};
@@ -1559,13 +1590,21 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
       if (timed && ev[1]) hipEventRecord(ev[1], st);
 
-      for (int tier = TIER_FIRST; tier <= TIER_F64; ++tier) {
-        if (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_BF16) continue;
-        Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
-        enqueue_tier(s, tier, src, f, st);
-        if (timed && ev[2 + tier]) hipEventRecord(ev[2 + tier], st);
+      // tier chain: first pass, [BF16 re-score of an FP8 first pass], [FP32 re-score of a
+      // low-precision first pass], FP64; events: after first, mid, FP32, FP64 (skipped tiers
+      // record their event right after the previous one)
+      const int chain[4] = {TIER_FIRST, TIER_MID, TIER_F32, TIER_F64};
+      for (int ci = 0; ci < 4; ++ci) {
+        const int tier = chain[ci];
+        const bool run = tier == TIER_FIRST || tier == TIER_F64 ||
+                         (tier == TIER_MID && s->pol.precision == HYDRO_PREC_FP8) ||
+                         (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_FP32);
+        if (run) {
+          Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
+          enqueue_tier(s, tier, src, f, st);
+        }
+        if (timed && ev[2 + ci]) hipEventRecord(ev[2 + ci], st);
       }
-      if (timed && s->pol.precision != HYDRO_PREC_BF16 && ev[3]) hipEventRecord(ev[3], st);
       if (s->rnn) router_nn_learn(s->rnn, s->st, st);
       parity ^= 1;
     }
@@ -1652,20 +1691,22 @@ static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int
   }
   if (!s->ids_sorted) std::sort(ids, ids + nres);
   if (s->pol.time_kernels) {
-    // events were recorded in groups of 5 per round: start, routed, first, f32, f64
-    double tr = 0, t1 = 0, t2 = 0, t3 = 0;
+    // events were recorded in groups of kEvPerRound per round: start, routed, first, mid, f32, f64
+    double tr = 0, t1 = 0, tm = 0, t2 = 0, t3 = 0;
     int nr = 0;
-    for (int i = 0; i + 4 < s->ev_used; i += 5) {
-      float a = 0, b = 0, c = 0, d = 0;
+    for (int i = 0; i + kEvPerRound - 1 < s->ev_used; i += kEvPerRound) {
+      float a = 0, b = 0, m = 0, c = 0, d = 0;
       if (hipEventElapsedTime(&a, s->evpool[i], s->evpool[i + 1]) != hipSuccess) continue;
       hipEventElapsedTime(&b, s->evpool[i + 1], s->evpool[i + 2]);
-      hipEventElapsedTime(&c, s->evpool[i + 2], s->evpool[i + 3]);
-      hipEventElapsedTime(&d, s->evpool[i + 3], s->evpool[i + 4]);
-      tr += a; t1 += b; t2 += c; t3 += d;
+      hipEventElapsedTime(&m, s->evpool[i + 2], s->evpool[i + 3]);
+      hipEventElapsedTime(&c, s->evpool[i + 3], s->evpool[i + 4]);
+      hipEventElapsedTime(&d, s->evpool[i + 4], s->evpool[i + 5]);
+      tr += a; t1 += b; tm += m; t2 += c; t3 += d;
       ++nr;
     }
     s->info.route_ms = tr;
     s->info.first_pass_ms = t1;
+    s->info.mid_pass_ms = tm;
     s->info.f32_pass_ms = t2;
     s->info.f64_pass_ms = t3;
     s->info.timed_rounds = nr;
@@ -1687,6 +1728,7 @@ static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int
       o.passed = h.t_pass[k];
       o.rescored = h.t_rescored[k];
       o.escalated = h.t_esc[k];
+      o.rescored16 = h.t_mid[k];
       o.device_us = (double)h.t_ticks[k] * s->tick_us;
       o.cost_us_per_tuple = s->pol.cost_source == HYDRO_COST_STATIC ? h.cost_est[k] : h.cost_est[k] * s->tick_us;
       o.selectivity = h.t_eval[k] ? (double)h.t_pass[k] / (double)h.t_eval[k] : 0.0;
@@ -1737,7 +1779,8 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   g_err.clear();
   if (!s || !frames || !out_logits) return fail(HYDRO_EINVAL, "NULL argument");
   if (pred < 0 || pred >= s->K) return fail(HYDRO_EINVAL, "predicate index out of range");
-  if (tier < 0 || tier > 2) return fail(HYDRO_EINVAL, "tier must be 0, 1 or 2");
+  if (tier < 0 || tier > 3) return fail(HYDRO_EINVAL, "tier must be 0, 1, 2 or 3");
+  if (tier == 3 && s->pol.precision != HYDRO_PREC_FP8) tier = s->pol.precision == HYDRO_PREC_BF16 ? 0 : 1;
   if (s->in_query)
     return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): logits and "
                               "calibration run between queries");
@@ -1749,12 +1792,13 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   if (rc) return rc;
   hipStream_t st = s->stream;
   HIP_TRY(hipStreamSynchronize(st));
-  const int t = tier == 0 ? TIER_FIRST : tier == 1 ? TIER_F32 : TIER_F64;
+  const int t = tier == 0 ? TIER_FIRST : tier == 1 ? TIER_F32 : tier == 2 ? TIER_F64 : TIER_MID;
   // queue of every tuple for this predicate at the chosen tier
   std::vector<uint32_t> ent(fr.n);
   for (int64_t i = 0; i < fr.n; ++i) ent[i] = make_entry((uint32_t)i, 0u);
-  uint32_t* qbase = t == TIER_FIRST ? s->q1 : t == TIER_F32 ? s->q2 : s->q3;
-  int* cptr = t == TIER_FIRST ? s->st->qcount : t == TIER_F32 ? s->st->bcount : s->st->ecount;
+  uint32_t* qbase = t == TIER_FIRST ? s->q1 : t == TIER_F32 ? s->q2 : t == TIER_MID ? s->qm : s->q3;
+  int* cptr = t == TIER_FIRST ? s->st->qcount : t == TIER_F32 ? s->st->bcount
+              : t == TIER_MID ? s->st->mcount : s->st->ecount;
   // layer-wise CNN launches hold activations for at most act_cap queued evaluations
   const int64_t chunk = s->gcnn.n_preds > 0 ? std::max<int64_t>(1, s->act_cap) : fr.n;
   double* dlog;
@@ -1799,38 +1843,106 @@ static double host_margin(const double* z, uint32_t mask) {
   return in - out;
 }
 
-// Largest first-pass and FP32 margin errors against the FP64 tier on `frames` (device memory),
-// times `safety`, floored at 1e-4 / 1e-6.
-static int measure_bands(hydro_session* s, const hydro_frames* frames, float safety, float* tau, float* tau32) {
+// Largest first-pass, BF16 (FP8 sessions) and FP32 margin errors against the FP64 tier on
+// `frames` (device memory), times `safety`, floored at 1e-4 / 1e-4 / 1e-6.
+static int measure_bands(hydro_session* s, const hydro_frames* frames, float safety, float* tau, float* tau16,
+                         float* tau32) {
   const int64_t n = frames->n;
   if (n < 1) return fail(HYDRO_EINVAL, "calibration needs at least one frame");
   // frames beyond the session's push capacity are taken in blocks of that size
   const int64_t blk = std::min<int64_t>(n, s->cap);
   const int esize = frames->dtype == HYDRO_DTYPE_F32 ? 4 : frames->dtype == HYDRO_DTYPE_BF16 ? 2 : 1;
   const int64_t fbytes = (int64_t)frames->h * frames->w * 3 * esize;
-  std::vector<double> z0((size_t)blk * kClasses), z1((size_t)blk * kClasses), z2((size_t)blk * kClasses);
+  const bool f8 = s->pol.precision == HYDRO_PREC_FP8;
+  std::vector<double> z0((size_t)blk * kClasses), zm((size_t)blk * kClasses), z1((size_t)blk * kClasses),
+      z2((size_t)blk * kClasses);
   for (int k = 0; k < s->K; ++k) {
     const uint32_t mask = s->models[k].m.class_mask;
-    double e0 = 0, e1 = 0;
+    double e0 = 0, em = 0, e1 = 0;
     for (int64_t i0 = 0; i0 < n; i0 += blk) {
       hydro_frames sub = *frames;
       sub.data = static_cast<const char*>(frames->data) + i0 * fbytes;
       sub.n = std::min(blk, n - i0);
       int rc;
       if ((rc = hydro_session_logits(s, k, 0, &sub, z0.data()))) return rc;
+      if (f8 && (rc = hydro_session_logits(s, k, 3, &sub, zm.data()))) return rc;
       if ((rc = hydro_session_logits(s, k, 1, &sub, z1.data()))) return rc;
       if ((rc = hydro_session_logits(s, k, 2, &sub, z2.data()))) return rc;
       for (int64_t i = 0; i < sub.n; ++i) {
         const double d2 = host_margin(&z2[i * kClasses], mask);
         if (!std::isfinite(d2)) continue;
         e0 = std::max(e0, std::fabs(host_margin(&z0[i * kClasses], mask) - d2));
+        if (f8) em = std::max(em, std::fabs(host_margin(&zm[i * kClasses], mask) - d2));
         e1 = std::max(e1, std::fabs(host_margin(&z1[i * kClasses], mask) - d2));
       }
     }
     // floors keep a band even when the sample shows (almost) no error
     tau[k] = (float)std::max(safety * e0, 1e-4);
+    tau16[k] = (float)std::max(safety * em, 1e-4);
     tau32[k] = (float)std::max(safety * e1, 1e-6);
   }
+  return HYDRO_OK;
+}
+
+// FP8 sessions: each 4-layer CNN predicate's activation scales (outputs of layers 1..3), from the
+// largest activations of its FP32 tier on `frames` (device memory): the largest maps to 224, half
+// of e4m3's largest finite value, which leaves headroom for frames beyond the sample (larger values
+// saturate at 448).
+static int measure_ascales(hydro_session* s, const hydro_frames* frames) {
+  const int64_t n = frames->n;
+  if (n < 1) return fail(HYDRO_EINVAL, "calibration needs at least one frame");
+  if (s->in_query) return fail(HYDRO_ESTATE, "calibration runs between queries");
+  int rc = ensure_dtype(s, frames->dtype);
+  if (rc) return rc;
+  unsigned* dmax = nullptr;
+  const size_t mark = s->arena_used;
+  const size_t bytes = (size_t)kMaxK * 4 * sizeof(unsigned);
+  if (s->arena) {
+    if ((rc = sess_alloc(s, (void**)&dmax, bytes))) return rc;
+  } else {
+    HIP_TRY(hipMalloc(&dmax, bytes));
+  }
+  auto release = [&]() {
+    s->gcnn.c4_act_max = nullptr;
+    if (s->arena) s->arena_used = mark;
+    else hipFree(dmax);
+  };
+  hipError_t he = hipMemsetAsync(dmax, 0, bytes, s->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(s->stream);
+  if (he != hipSuccess) {
+    release();
+    return fail(HYDRO_EDEVICE, std::string("activation maxima: ") + hipGetErrorString(he));
+  }
+  s->gcnn.c4_act_max = dmax;
+  const int64_t blk = std::min<int64_t>(n, s->cap);
+  const int esize = frames->dtype == HYDRO_DTYPE_F32 ? 4 : frames->dtype == HYDRO_DTYPE_BF16 ? 2 : 1;
+  const int64_t fbytes = (int64_t)frames->h * frames->w * 3 * esize;
+  std::vector<double> z((size_t)blk * kClasses);
+  for (int k = 0; k < s->K && !rc; ++k)
+    for (int64_t i0 = 0; i0 < n && !rc; i0 += blk) {
+      hydro_frames sub = *frames;
+      sub.data = static_cast<const char*>(frames->data) + i0 * fbytes;
+      sub.n = std::min(blk, n - i0);
+      rc = hydro_session_logits(s, k, 1, &sub, z.data());
+    }
+  unsigned hmax[kMaxK * 4];
+  if (!rc) {
+    he = hipMemcpy(hmax, dmax, bytes, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) rc = fail(HYDRO_EDEVICE, std::string("activation maxima: ") + hipGetErrorString(he));
+  }
+  release();
+  if (rc) return rc;
+  GcnnArgs& ga = s->gcnn;
+  for (int i = 0; i < ga.n_preds; ++i) {
+    if (!ga.c4[i]) continue;
+    for (int l = 0; l < 3; ++l) {
+      float mx;
+      memcpy(&mx, &hmax[ga.pred[i] * 4 + l], 4);
+      ga.c4_ascale[i][l] = mx > 0.f ? mx / 224.f : 1.f;
+    }
+  }
+  s->ascales_set = true;
+  drop_graphs(s);
   return HYDRO_OK;
 }
 
@@ -1842,17 +1954,31 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
   if (s->in_query)
     return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): calibrate "
                               "between queries");
-  float tau[kMaxK], tau32[kMaxK];
-  int rc = measure_bands(s, frames, safety, tau, tau32);
+  float tau[kMaxK], tau16[kMaxK], tau32[kMaxK];
+  int rc = HYDRO_OK;
+  if (s->pol.precision == HYDRO_PREC_FP8) rc = measure_ascales(s, frames);
+  if (!rc) rc = measure_bands(s, frames, safety, tau, tau16, tau32);
   if (rc) return rc;
   for (int k = 0; k < s->K; ++k) {
-    s->tau_k[k] = s->pol.precision == HYDRO_PREC_BF16 ? tau[k] : tau32[k];
+    s->tau_k[k] = s->pol.precision != HYDRO_PREC_FP32 ? tau[k] : tau32[k];
+    s->tau16_k[k] = tau16[k];
     s->tau32_k[k] = tau32[k];
     if (out_tau) out_tau[k] = s->tau_k[k];
     if (out_tau32) out_tau32[k] = tau32[k];
   }
-  s->auto_tau = s->auto_tau32 = false;
+  s->auto_tau = s->auto_tau32 = s->auto_tau16 = false;
   drop_graphs(s);   // captured pushes hold the old bands in their kernel arguments
+  return HYDRO_OK;
+}
+
+int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float* tau32) {
+  g_err.clear();
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  for (int k = 0; k < s->K; ++k) {
+    if (tau) tau[k] = s->tau_k[k];
+    if (tau16) tau16[k] = s->tau16_k[k];
+    if (tau32) tau32[k] = s->tau32_k[k];
+  }
   return HYDRO_OK;
 }
 

@@ -23,12 +23,12 @@ DTYPE_F32, DTYPE_BF16, DTYPE_U8 = 0, 1, 2
 MEM_DEVICE, MEM_HOST = 0, 1
 ARCH_MLP, ARCH_CNN = 0, 1
 ROUTE_FIXED, ROUTE_SEL, ROUTE_SCORE, ROUTE_COST, ROUTE_LEARNED = 0, 1, 2, 3, 4
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 COST_MEASURED, COST_STATIC = 0, 1
 
 ROUTES = {"fixed": ROUTE_FIXED, "selectivity": ROUTE_SEL, "score": ROUTE_SCORE, "cost": ROUTE_COST,
           "learned": ROUTE_LEARNED}
-PRECISIONS = {"fp32": PREC_FP32, "bf16": PREC_BF16}
+PRECISIONS = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8}
 DTYPES = {"f32": DTYPE_F32, "bf16": DTYPE_BF16, "u8": DTYPE_U8}
 
 
@@ -60,13 +60,14 @@ class Policy(C.Structure):
                 ("cost_source", C.c_int32), ("precision", C.c_int32), ("tau", C.c_float), ("tau32", C.c_float),
                 ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
                 ("time_kernels", C.c_int32), ("autotune", C.c_int32),
-                ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+                ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p), ("tau16", C.c_float),
+                ("pad_", C.c_int32)]
 
 
 class PredStats(C.Structure):
     _fields_ = [("evaluated", C.c_uint64), ("passed", C.c_uint64), ("rescored", C.c_uint64),
                 ("escalated", C.c_uint64), ("device_us", C.c_double), ("cost_us_per_tuple", C.c_double),
-                ("selectivity", C.c_double)]
+                ("selectivity", C.c_double), ("rescored16", C.c_uint64)]
 
 
 class QueryInfo(C.Structure):
@@ -74,7 +75,8 @@ class QueryInfo(C.Structure):
                 ("learned_routed", C.c_uint64), ("stats_routed", C.c_uint64), ("learned_active", C.c_uint32),
                 ("train_steps", C.c_uint32), ("elapsed_us", C.c_double), ("route_ms", C.c_double),
                 ("first_pass_ms", C.c_double), ("f32_pass_ms", C.c_double), ("f64_pass_ms", C.c_double),
-                ("timed_rounds", C.c_uint32), ("pad_", C.c_uint32), ("learned_stale", C.c_uint64)]
+                ("timed_rounds", C.c_uint32), ("pad_", C.c_uint32), ("learned_stale", C.c_uint64),
+                ("mid_pass_ms", C.c_double)]
 
 
 class RoundRecord(C.Structure):
@@ -113,6 +115,7 @@ def lib():
                                                C.POINTER(C.c_uint8), i32, FP, FP, FP, i32, C.c_float]
         L.hydro_session_logits.argtypes = [vp, i32, i32, C.POINTER(Frames), C.POINTER(C.c_double)]
         L.hydro_session_calibrate.argtypes = [vp, C.POINTER(Frames), C.c_float, FP, FP]
+        L.hydro_session_bands.argtypes = [vp, FP, FP, FP]
         L.hydro_session_destroy.argtypes = [vp]
         L.hydro_free.argtypes = [vp]
         L.hydro_free.restype = None
@@ -122,7 +125,7 @@ def lib():
                      "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
                      "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
                      "hydro_session_logits",
-                     "hydro_session_calibrate", "hydro_session_destroy"):
+                     "hydro_session_calibrate", "hydro_session_bands", "hydro_session_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -131,7 +134,8 @@ def lib():
 EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_query_noalloc", "hydro_session_create", "hydro_session_reset",
             "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
             "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
-            "hydro_session_logits", "hydro_session_calibrate", "hydro_session_destroy", "hydro_free",
+            "hydro_session_logits", "hydro_session_calibrate", "hydro_session_bands", "hydro_session_destroy",
+            "hydro_free",
             "hydro_last_error", "hydro_version")
 
 
@@ -301,6 +305,12 @@ class Session:
         t32 = np.zeros(self.k, dtype=np.float32)
         _check(lib().hydro_session_calibrate(self._h, C.byref(fr), float(safety), _fp(t), _fp(t32)))
         return t, t32
+
+    def bands(self):
+        """The per-predicate bands the next push uses: (tau, tau16, tau32)."""
+        t, t16, t32 = (np.zeros(self.k, dtype=np.float32) for _ in range(3))
+        _check(lib().hydro_session_bands(self._h, _fp(t), _fp(t16), _fp(t32)))
+        return t, t16, t32
 
     def close(self):
         if self._h:

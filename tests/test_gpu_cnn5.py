@@ -1,5 +1,6 @@
-"""GPU parity of the generic layer-wise CNN path on the uint8 128x128x3 workload (four CNN
-predicates conv 32-64-128-256 + FC), including host-memory pushes through the staging ring."""
+"""GPU parity of the 4-layer CNN kernels on the uint8 128x128x3 workload (four CNN predicates conv
+32-64-128-256 + FC) at every arithmetic tier (FP8, BF16, FP32 against the FP64 oracle), including
+the FP8 -> BF16 -> FP32 -> FP64 re-score chain and host-memory pushes through the staging ring."""
 import numpy as np
 import pytest
 
@@ -70,6 +71,63 @@ def test_c5_ungrouped_launches(c5z, c5):
     assert np.array_equal(ids, c5.expect)
     check_stats(stats, c5.n, ids.size)
     s.close()
+
+
+def _margin(z, mask):
+    inside = np.array([(mask >> c) & 1 for c in range(10)], dtype=bool)
+    return np.where(inside, z, -np.inf).max(axis=1) - np.where(~inside, z, -np.inf).max(axis=1)
+
+
+def test_c5_fp8_tier_logits(c5z):
+    """FP8 first pass (per-channel weight scales, activation scales calibrated on separate frames)
+    and the BF16 tier of the same session against the oracle's FP64 logits."""
+    cfg = c5z.cfg
+    cal = torch.from_numpy(hs.make_frames(cfg, 0, 256, data_seed=cfg.data_seed + 101)).cuda()
+    s = hydro.Session(c5z.specs(), hydro.make_policy("score", precision="fp8"), 128, 256)
+    tau, tau32 = s.calibrate(cal, "u8", safety=2.0)
+    t8, t16, t32 = s.bands()
+    log(f"[gpu] c5 fp8 bands tau={np.round(t8, 4).tolist()} tau16={np.round(t16, 4).tolist()} tau32={t32.tolist()}")
+    dev = c5z.device_frames()
+    for k in range(cfg.k):
+        z8 = s.logits(k, 0, dev, "u8")
+        z16 = s.logits(k, 3, dev, "u8")
+        d64 = _margin(c5z.Z[k], c5z.pt.class_masks[k])
+        e8 = np.abs(_margin(z8, c5z.pt.class_masks[k]) - d64).max()
+        e16 = np.abs(_margin(z16, c5z.pt.class_masks[k]) - d64).max()
+        log(f"  predicate {k}: fp8 max |z - z64| = {np.abs(z8 - c5z.Z[k]).max():.3e} margin {e8:.3e}; "
+            f"bf16 max |z - z64| = {np.abs(z16 - c5z.Z[k]).max():.3e} margin {e16:.3e}")
+        assert np.abs(z16 - c5z.Z[k]).max() <= 0.03
+        assert np.abs(z8 - c5z.Z[k]).max() <= 0.5
+    s.close()
+
+
+@pytest.mark.parametrize("route", ["score", "learned"])
+def test_c5_fp8_query(c5, route):
+    """Ids equal to the oracle with the FP8 first pass; every tier's counts are consistent."""
+    cfg = c5.cfg
+    cal = torch.from_numpy(hs.make_frames(cfg, 0, 256, data_seed=cfg.data_seed + 101)).cuda()
+    s = hydro.Session(c5.specs(), hydro.make_policy(route, precision="fp8", wave=256, log_routes=1), 128, c5.n)
+    s.calibrate(cal, "u8", safety=3.0)
+    s.push(c5.device_frames(), "u8", c5.pt.thresholds, c5.seg_len)
+    ids, stats = s.finish()
+    log(f"[gpu] c5 fp8 {route}: |R|={ids.size} evaluated={[st['evaluated'] for st in stats]} "
+        f"rescored={[st['rescored'] for st in stats]} rescored16={[st['rescored16'] for st in stats]} "
+        f"escalated={[st['escalated'] for st in stats]}")
+    assert np.array_equal(ids, c5.expect)
+    check_stats(stats, c5.n, ids.size)
+    for st in stats:
+        assert st["rescored16"] <= st["rescored"] and st["rescored"] <= st["evaluated"]
+    ok, rev, rps, out, msg = ho.replay_route(c5.P, hydro.decode_routes(s.routes(0, c5.n)))
+    assert ok, msg
+    assert [st["evaluated"] for st in stats] == list(rev)
+    s.close()
+
+
+def test_c5_fp8_refused_for_other_shapes():
+    c = case(1, 2048)
+    with pytest.raises(hydro.HydroError) as e:
+        hydro.Session(c.specs(), hydro.make_policy("score", precision="fp8"), 32, 16)
+    assert e.value.code == hydro.EUNSUPPORTED
 
 
 def test_c5_pinned_host_pushes(c5):
