@@ -52,6 +52,7 @@ METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs pla
 FIRST_PASS_TRAFFIC = {"cnn3_drift64": 407.60e6 + 5.27e6}
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}   # dense MFMA peaks, TFLOP/s
 
 
 def parse():
@@ -74,6 +75,8 @@ def parse():
                     help="fixed bands tau = 0.015, tau32 = 1e-5 instead of bands calibrated on separate frames")
     ap.add_argument("--safety", type=float, default=2.0)
     ap.add_argument("--route", default="learned")
+    ap.add_argument("--precision", default="bf16", help="first pass of the full form: bf16 or fp8")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 first-pass form")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
@@ -171,7 +174,8 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
                         "c4_gemm_kernel<bf16, 3> (layer 4, pool, FC, decision): the first pass of a round")
     else:
         kernel_label = "gconv_* layer kernels + gcnn_head_kernel (first pass, grouped over predicates)"
-    full_pol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, time_kernels=1,
+    prec = args.precision
+    full_pol = hydro.make_policy(args.route, precision=prec, wave=args.wave, grouped=1, autotune=1, time_kernels=1,
                                  **extra)
     log(f"[bench] eager full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
@@ -192,7 +196,7 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
 
     # headline: the full form as deployed, each push replayed from its captured HIP graph
     log(f"[bench] full form, graph replay: {warmup} warmup + {steps} timed steps")
-    gpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, use_graph=1,
+    gpol = hydro.make_policy(args.route, precision=prec, wave=args.wave, grouped=1, autotune=1, use_graph=1,
                              **extra)
     ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, steps, warmup, n,
                                 cal, args.safety)
@@ -209,22 +213,22 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": prec,
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {n} frames {cfg.hw}x{cfg.hw}x3 {cfg.dtype}, "
                                f"{cfg.k} predicates, {cfg.n_seg} threshold segments"
                                + (f" (first {n} of {cfg.n} tuples)" if n < cfg.n else ""),
-                   "form": "full: bf16 first pass + fp32/fp64 re-score, " + args.route + " routing, grouped, "
-                           "each push replayed from a captured HIP graph",
+                   "form": f"full: {prec} first pass + " + ("bf16/" if prec == "fp8" else "") + "fp32/fp64 re-score, "
+                           + args.route + " routing, grouped, each push replayed from a captured HIP graph",
                    "frames_in": "HBM (generated on the device before timing)",
                    "wave": args.wave, "tuples_per_step": n, "ablation_steps": abl_steps},
         "roofline": {
             "bound": "mfma",
             "kernel": kernel_label,
             "achieved": achieved,
-            "peak": PEAK_BF16_TFLOPS,
+            "peak": PEAK[prec],
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_BF16_TFLOPS,
+            "frac": achieved / PEAK[prec],
             "traffic": FIRST_PASS_TRAFFIC.get(cfg.name) if n == cfg.n else None,
             "flops_per_launch": first_flops / max(1, launches),
             "avg_launch_ms": first_ms / max(1, launches),
@@ -239,7 +243,11 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         },
         "fp32_rescore_tflops": f32_flops / (f32_ms * 1e-3) / 1e12 if f32_ms > 0 else 0.0,
         "per_predicate": [{"evaluated": s["evaluated"], "passed": s["passed"], "rescored": s["rescored"],
-                           "escalated": s["escalated"], "selectivity": round(s["selectivity"], 4)} for s in last],
+                           "rescored16": s["rescored16"], "escalated": s["escalated"],
+                           "selectivity": round(s["selectivity"], 4)} for s in last],
+        "band_fraction": {"first_pass": float(resc.sum() / max(1.0, ev.sum())),
+                          "fp32": float(sum(x["escalated"] for st in stats_all for x in st)
+                                        / max(1.0, float(resc.sum())))},
         "n_result": int(ids.size),
         "bands": ({"calibrated_on": f"{cal.shape[0]} separate frames", "safety": args.safety,
                    "tau": [round(float(x), 6) for x in bands[0]],
@@ -262,6 +270,31 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         out["score"] = {"value": n * abl_steps / dts, "unit": "tuples/s",
                         "udf_gflop_per_step": float((ev_s * flops).sum()) / abl_steps / 1e9,
                         "first_pass_ms_per_step": sum(i["first_pass_ms"] for i in inf_s) / abl_steps}
+
+    if primary and not args.no_fp8 and prec != "fp8" and all(
+            d.arch == "cnn" and d.in_hw == 128 and tuple(d.widths) == (32, 64, 128, 256) for d in cfg.models):
+        # the FP8 first pass (e4m3, per-channel weight scales, calibrated activation scales) with its
+        # BF16 -> FP32 -> FP64 re-score chain, eager with HIP events per tier
+        log("[bench] fp8 form")
+        fpol = hydro.make_policy(args.route, precision="fp8", wave=args.wave, grouped=1, time_kernels=1, **extra)
+        ids_8, st_8, inf_8, dt8 = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, fpol,
+                                           abl_steps, 1, n, cal, args.safety)
+        assert np.array_equal(ids_8, ids), "fp8 and bf16 first passes disagree"
+        ev8 = np.array([[x["evaluated"] for x in st] for st in st_8], dtype=np.float64)
+        r8 = np.array([[x["rescored"] for x in st] for st in st_8], dtype=np.float64)
+        r16 = np.array([[x["rescored16"] for x in st] for st in st_8], dtype=np.float64)
+        fp8_ms = sum(i["first_pass_ms"] for i in inf_8)
+        out["fp8"] = {"value": n * abl_steps / dt8, "unit": "tuples/s",
+                      "band_fraction": {"fp8_to_bf16": float(r8.sum() / ev8.sum()),
+                                        "bf16_to_fp32": float(r16.sum() / max(1.0, r8.sum()))},
+                      "bands": ({"tau": [round(float(x), 5) for x in run_form.bands[0]]} if run_form.bands else None),
+                      "phases_ms_per_step": {"first_pass_fp8": fp8_ms / abl_steps,
+                                             "bf16_rescore": sum(i["mid_pass_ms"] for i in inf_8) / abl_steps,
+                                             "fp32_rescore": sum(i["f32_pass_ms"] for i in inf_8) / abl_steps,
+                                             "fp64_escalate": sum(i["f64_pass_ms"] for i in inf_8) / abl_steps},
+                      "first_pass_tflops": float((ev8 * flops).sum()) / (fp8_ms * 1e-3) / 1e12 if fp8_ms > 0 else 0.0,
+                      "first_pass_frac_of_fp8_peak": float((ev8 * flops).sum()) / (fp8_ms * 1e-3) / 1e12 / PEAK["fp8"]
+                      if fp8_ms > 0 else 0.0}
 
     if primary and (args.host or cfg.push_batch > 0):
         blk = cfg.push_batch if cfg.push_batch > 0 else 16384
@@ -314,16 +347,25 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
 
         rep = {"frames": m, "reference": "library fp64 pass"}
         z64 = [es.logits(j, 2, frames_dev[:m], cfg.dtype) for j in range(cfg.k)]
-        for tier, name in ((0, "bf16"), (1, "fp32")):
+        sessions = [(es, 0, "bf16"), (es, 1, "fp32")]
+        f8s = None
+        if "fp8" in out:
+            f8s = hydro.Session(specs, hydro.make_policy(args.route, precision="fp8"), cfg.hw, m)
+            if cal is not None:
+                f8s.calibrate(cal, cfg.dtype, args.safety)   # sets the activation scales
+            sessions.append((f8s, 0, "fp8"))
+        for sess_e, tier, name in sessions:
             ml, mm, pm = [], [], []
             for j in range(cfg.k):
-                z = es.logits(j, tier, frames_dev[:m], cfg.dtype)
+                z = sess_e.logits(j, tier, frames_dev[:m], cfg.dtype)
                 dd = np.abs(margin(z, pt.class_masks[j]) - margin(z64[j], pt.class_masks[j]))
                 ml.append(float(np.abs(z - z64[j]).max()))
                 mm.append(float(dd.max()))
                 pm.append(float(np.quantile(dd, 0.999)))
             rep[name] = {"max_logit_err": ml, "max_margin_err": mm, "p999_margin_err": pm}
         es.close()
+        if f8s is not None:
+            f8s.close()
         out["logit_error"] = rep
 
     if not args.no_cpu and primary:

@@ -40,6 +40,13 @@ __device__ inline floatx4 c4_mfma(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 __device__ inline floatx4 c4_mfma(float a, float b, floatx4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+// BF16 contractions use the 32x32x16 MFMA, which keeps the matrix pipe busy with few independent
+// accumulators.  Lane l supplies A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32]; output
+// element (i, j) sits in lane j + 32 ((i / 4) % 2), value (i % 4) + 4 (i / 8).
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+__device__ inline floatx16 c4_mfma32(bf16x8 a, bf16x8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
 // e4m3 x e4m3, K = 128, block scales 2^0 (E8M0 127)
 __device__ inline floatx4 c4_mfma(i32x8 a, i32x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
@@ -90,44 +97,91 @@ template <> struct FrontCfg<C4_F32> { static constexpr int PITCH = 144; };
 template <> struct FrontCfg<C4_BF16> { static constexpr int PITCH = 80; };
 template <> struct FrontCfg<C4_FP8> { static constexpr int PITCH = 48; };
 
-constexpr int F_FRAME_B = (F_FROWS * F_FPITCH * 2 + 15) / 16 * 16;   // staged frame band, bytes
-__host__ __device__ constexpr int front_lds_bytes(int pitch) { return F_FRAME_B + F_RING * F_SLOTS * pitch; }
+// bytes per position row of the layer-2 output staging (64 channels + 16 bytes of padding)
+template <int P> constexpr int F_TPITCH = 64 * C4T<P>::ES + 16;
+// the frame band area, which also stages the layer-2 output (4 waves x 32 positions) after
+// layer 1 has read the band
+template <int P>
+constexpr int F_FRAME_B = ((F_FROWS * F_FPITCH * 2 > 4 * 32 * F_TPITCH<P> ? F_FROWS * F_FPITCH * 2 : 4 * 32 * F_TPITCH<P>) + 15) / 16 * 16;
+template <int P> constexpr int front_lds_bytes() { return F_FRAME_B<P> + F_RING * F_SLOTS * FrontCfg<P>::PITCH; }
 
 // Layer-1 column j -> its slot in a ring row.
 __device__ inline int f_slot(int j) { return (j & 1) ? 32 + ((j + 1) >> 1) : (j >> 1); }
 
-template <int P>
+template <int P, bool U8>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == C4_F32 ? 1 : 2)))
 void c4_front_kernel(GcnnArgs a) {
   typedef typename C4T<P>::T T;
   constexpr int ES = C4T<P>::ES;
   constexpr int PITCH = FrontCfg<P>::PITCH;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[front_lds_bytes(PITCH)];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[front_lds_bytes<P>()];
   __shared__ unsigned long long ticks_s[kMaxK];
+  // per-slot epilogue constants: layer-1 bias [32], layer-2 bias [64], FP8 layer-2 scales [64]
+  __shared__ __attribute__((aligned(16))) float consts_s[160];
+  __shared__ __attribute__((aligned(16))) bf16x8 w1_s[2][64];   // layer-1 fragments (bf16 tiers)
   __bf16* fb = reinterpret_cast<__bf16*>(lds);          // staged frame band (raw values, bf16)
-  unsigned char* ring = lds + F_FRAME_B;                   // layer-1 output rows
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  unsigned char* ring = lds + F_FRAME_B<P>;                // layer-1 output rows
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, l16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < kMaxK) ticks_s[tid] = 0;
   // the left pad column (slot 32) of every ring row is a zero activation
   for (int q = tid; q < F_RING * (PITCH / 4); q += 256)
     reinterpret_cast<uint32_t*>(ring + (q / (PITCH / 4)) * F_SLOTS * PITCH + 32 * PITCH)[q % (PITCH / 4)] = 0u;
-  // frame band pad column: elements 1..3 of every row
-  for (int q = tid; q < F_FROWS * 4; q += 256) fb[(q >> 2) * F_FPITCH + (q & 3)] = static_cast<__bf16>(a.pad_raw);
 
   int total = 0;
   for (int i = 0; i < a.n_preds; ++i) total += a.c4[i] ? a.q.counts[a.pred[i]] : 0;
-  const bool u8 = a.fr.dtype == HYDRO_DTYPE_U8;
-  // frame staging: chunk q (16 bytes) of band row r; u8: 24 chunks a row, bf16: 48
-  const int cpr = u8 ? 24 : 48;
-  const int nchunks = F_FROWS * cpr;
+  // frame staging: chunk q (16 bytes) of band row r; uint8 frames: 24 chunks a row, bf16: 48.
+  // The next band's chunks are loaded into registers while the current band's layer 2 runs (the
+  // next frame's first band during the last band), and converted into LDS after it.
+  constexpr int CPR = U8 ? 24 : 48;
+  constexpr int NCHUNK = F_FROWS * CPR;
+  constexpr int NPF = (NCHUNK + 255) / 256;
+  constexpr int FROWB = 128 * 3 * (U8 ? 1 : 2);
+  u32x4 pf[NPF];
+  // the loads are unconditional (indices clamped; a clamped chunk is never committed), so that the
+  // registers are not merged across branches and the wait for them falls at the commit
+#define C4_FISSUE(frm_, band_)                                                                     \
+  do {                                                                                             \
+    _Pragma("unroll") for (int c = 0; c < NPF; ++c) {                                              \
+      const int q = min(tid + 256 * c, NCHUNK - 1);                                                \
+      const int y = max(16 * (band_) - 1 + q / CPR, 0);                                            \
+      pf[c] = reinterpret_cast<const u32x4*>((frm_) + (int64_t)y * FROWB)[q % CPR];                \
+    }                                                                                              \
+  } while (0)
+#define C4_FCOMMIT(band_)                                                                          \
+  do {                                                                                             \
+    /* the pad column (elements 1..3 of each row; the area also stages layer-2 output) */           \
+    if (tid < F_FROWS * 4) fb[(tid >> 2) * F_FPITCH + (tid & 3)] = static_cast<__bf16>(a.pad_raw); \
+    _Pragma("unroll") for (int c = 0; c < NPF; ++c) {                                              \
+      const int q = tid + 256 * c;                                                                 \
+      if (q < NCHUNK) {                                                                            \
+        const int r = q / CPR, j = q % CPR, y = 16 * (band_) - 1 + r;                              \
+        __bf16* dst = fb + r * F_FPITCH + 4 + (U8 ? 16 : 8) * j;                                   \
+        if (y < 0) {                                                                               \
+          _Pragma("unroll") for (int e = 0; e < (U8 ? 16 : 8); ++e) dst[e] = static_cast<__bf16>(a.pad_raw); \
+        } else if (U8) {                                                                           \
+          _Pragma("unroll") for (int h = 0; h < 4; ++h) {                                          \
+            alignas(8) __bf16 e4[4];                                                               \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e)                                          \
+              e4[e] = static_cast<__bf16>((float)((pf[c][h] >> (8 * e)) & 0xFFu));                 \
+            *reinterpret_cast<uint2*>(dst + 4 * h) = *reinterpret_cast<const uint2*>(e4);           \
+          }                                                                                        \
+        } else {                                                                                   \
+          *reinterpret_cast<uint2*>(dst) = make_uint2(pf[c][0], pf[c][1]);                         \
+          *reinterpret_cast<uint2*>(dst + 4) = make_uint2(pf[c][2], pf[c][3]);                     \
+        }                                                                                          \
+      }                                                                                            \
+    }                                                                                              \
+  } while (0)
+  bool pf_valid = false;      // pf holds the first band of frame pf_idx
+  uint32_t pf_idx = 0;
 
   // per-slot state (reloaded when the slot changes)
   int cur = -1;
-  bf16x8 w1b[2];                      // layer-1 weights, bf16 tiers
   float w1f[7][2];                    // layer-1 weights, FP32 tier
-  bf16x8 w2b[P == C4_BF16 ? 9 : 1][P == C4_BF16 ? 4 : 1];
+  bf16x8 w2b[P == C4_BF16 ? 9 : 1][2][2];            // [tap][channel half of the tap][32-channel tile]
   i32x8 w2q[P == C4_FP8 ? 3 : 1][P == C4_FP8 ? 4 : 1];
-  float inv_s1 = 1.f, inv_s2 = 1.f, asc1 = 1.f;
+  float inv_s1 = 1.f, inv_s2 = 1.f;
 
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int slot = 0, off = t, ebase = 0;
@@ -146,6 +200,11 @@ void c4_front_kernel(GcnnArgs a) {
     const uint32_t idx = entry_idx(a.q.entries[(int64_t)k * a.q.cap + off]);
     if (slot != cur) {
       cur = slot;
+      // (the previous frame's last barrier ordered every read of the previous slot's constants)
+      if (tid < 32) consts_s[tid] = a.bias[slot][0][tid];
+      else if (tid < 96) consts_s[tid] = a.bias[slot][1][tid - 32];
+      else if (tid < 160)
+        consts_s[tid] = P == C4_FP8 ? a.c4_wscale[slot][0][tid - 96] * a.c4_ascale[slot][0] : 1.f;
       if constexpr (P == C4_F32) {
         const float* w1 = static_cast<const float*>(a.c4_w1f[slot]);
 #pragma unroll
@@ -153,16 +212,16 @@ void c4_front_kernel(GcnnArgs a) {
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) w1f[s][ct] = w1[(s * 2 + ct) * 64 + lane];
       } else {
-        const bf16x8* w1 = static_cast<const bf16x8*>(a.c4_w1b[slot]);
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) w1b[ct] = w1[ct * 64 + lane];
+        if (tid < 128) w1_s[tid >> 6][tid & 63] = static_cast<const bf16x8*>(a.c4_w1b[slot])[tid];
       }
       if constexpr (P == C4_BF16) {
         const bf16x8* w2 = static_cast<const bf16x8*>(a.c4_w2[slot][C4_BF16]);
 #pragma unroll
         for (int tp = 0; tp < 9; ++tp)
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) w2b[tp][ct] = w2[(tp * 4 + ct) * 64 + lane];
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) w2b[tp][h][c2] = w2[((tp * 2 + h) * 2 + c2) * 64 + lane];
       }
       if constexpr (P == C4_FP8) {
         const i32x8* w2 = static_cast<const i32x8*>(a.c4_w2[slot][C4_FP8]);
@@ -170,39 +229,47 @@ void c4_front_kernel(GcnnArgs a) {
         for (int s = 0; s < 3; ++s)
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) w2q[s][ct] = w2[(s * 4 + ct) * 64 + lane];
-        asc1 = a.c4_ascale[slot][0];
         inv_s1 = 1.f / a.c4_ascale[slot][0];
         inv_s2 = 1.f / a.c4_ascale[slot][1];
       }
     }
     const unsigned long long t0 = wall_clock64();
-    const unsigned char* frame = static_cast<const unsigned char*>(a.fr.base) + (int64_t)idx * a.fr.elems * (u8 ? 1 : 2);
+    const unsigned char* frame = static_cast<const unsigned char*>(a.fr.base) + (int64_t)idx * a.fr.elems * (U8 ? 1 : 2);
+    // the work item after this one (its first band is prefetched during this frame's last band)
+    const unsigned char* next_frame = nullptr;
+    uint32_t nidx = 0;
+    {
+      const int t2 = t + gridDim.x;
+      if (t2 < total) {
+        int off2 = t2, eb2 = 0, s2 = -1;
+        for (int i = 0; i < a.n_preds; ++i) {
+          const int c = a.c4[i] ? a.q.counts[a.pred[i]] : 0;
+          if (off2 < c) { s2 = i; break; }
+          off2 -= c;
+          eb2 += a.q.counts[a.pred[i]];
+        }
+        if (s2 >= 0 && (int64_t)eb2 + off2 < a.act_cap) {
+          nidx = entry_idx(a.q.entries[(int64_t)a.pred[s2] * a.q.cap + off2]);
+          next_frame = static_cast<const unsigned char*>(a.fr.base) + (int64_t)nidx * a.fr.elems * (U8 ? 1 : 2);
+        }
+      }
+    }
+    if (!(pf_valid && pf_idx == idx)) C4_FISSUE(frame, 0);
+    C4_FCOMMIT(0);
+    pf_valid = false;
     T* out2 = reinterpret_cast<T*>(a.c4_act2) + ent * (32 * 32 * 64);
     unsigned* amax1 = a.c4_act_max ? a.c4_act_max + k * 4 + 0 : nullptr;
     unsigned* amax2 = a.c4_act_max ? a.c4_act_max + k * 4 + 1 : nullptr;
 
     for (int b = 0; b < F_NB; ++b) {
-      // ---- stage frame rows 16b-1 .. 16b+15 (raw values as bf16); row -1 is the pad value
-      for (int q = tid; q < nchunks; q += 256) {
-        const int r = q / cpr, j = q % cpr, y = 16 * b - 1 + r;
-        __bf16* dst = fb + r * F_FPITCH + 4 + (u8 ? 16 : 8) * j;
-        if (y < 0) {
-          for (int e = 0; e < (u8 ? 16 : 8); ++e) dst[e] = static_cast<__bf16>(a.pad_raw);
-          continue;
-        }
-        const uint4 v = reinterpret_cast<const uint4*>(frame + (int64_t)y * 128 * 3 * (u8 ? 1 : 2))[j];
-        if (u8) {
-          const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            alignas(8) __bf16 e4[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) e4[e] = static_cast<__bf16>((float)((wv[h] >> (8 * e)) & 0xFFu));
-            *reinterpret_cast<uint2*>(dst + 4 * h) = *reinterpret_cast<const uint2*>(e4);
-          }
-        } else {
-          *reinterpret_cast<uint2*>(dst) = make_uint2(v.x, v.y);
-          *reinterpret_cast<uint2*>(dst + 4) = make_uint2(v.z, v.w);
+      {
+        // next band of this frame, or the first band of the next work item (this frame again when
+        // there is none: a load whose data is not used); in flight over this band's layers 1 and 2
+        const unsigned char* src = b + 1 < F_NB ? frame : next_frame != nullptr ? next_frame : frame;
+        C4_FISSUE(src, b + 1 < F_NB ? b + 1 : 0);
+        if (b + 1 == F_NB && next_frame != nullptr) {
+          pf_valid = true;
+          pf_idx = nidx;
         }
       }
       // the ring slot of layer-1 row -1 is zero for the first band
@@ -212,7 +279,7 @@ void c4_front_kernel(GcnnArgs a) {
       __syncthreads();
 
       // ---- layer 1: rows 8b + 2w, 8b + 2w + 1 (local i = 2w, 2w+1), 64 columns each
-#pragma unroll 2
+#pragma unroll 1
       for (int pt = 0; pt < 8; ++pt) {
         const int il = 2 * wave + (pt >> 2), j = (pt & 3) * 16 + l16;
         floatx4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
@@ -236,15 +303,15 @@ void c4_front_kernel(GcnnArgs a) {
             const int u = kk / 9, tt = kk % 9;
             xb[e] = fr[u * F_FPITCH + tt];
           }
-          acc[0] = c4_mfma(w1b[0], xb, acc[0]);
-          acc[1] = c4_mfma(w1b[1], xb, acc[1]);
+          acc[0] = c4_mfma(w1_s[0][lane], xb, acc[0]);
+          acc[1] = c4_mfma(w1_s[1][lane], xb, acc[1]);
         }
         const int ridx = (base_slot + 1 + il) % F_RING;
         unsigned char* dst = ring + (ridx * F_SLOTS + f_slot(j)) * PITCH;
         float m = 0.f;
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const float4 bb = *reinterpret_cast<const float4*>(a.bias[slot][0] + ct * 16 + 4 * g);
+          const float4 bb = *reinterpret_cast<const float4*>(consts_s + ct * 16 + 4 * g);
           const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
           float v[4];
 #pragma unroll
@@ -262,13 +329,21 @@ void c4_front_kernel(GcnnArgs a) {
       // ---- layer 2: output row 4b + w, columns 0..31 (two position tiles).  The FP8 and FP32
       // tiers split the k-steps over two accumulation chains (the BF16 tier has no registers
       // left for a second chain: its layer-2 weights take 144)
-      floatx4 acc[2][4][2];
+      floatx4 acc[P == C4_BF16 ? 1 : 2][4][2];
+      floatx16 acc32[P == C4_BF16 ? 2 : 1];
+      if constexpr (P == C4_BF16) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+        for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
+          for (int e = 0; e < 16; ++e) acc32[c2][e] = 0.f;
+      } else {
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt) acc[h][ct][mt] = (floatx4){0.f, 0.f, 0.f, 0.f};
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) acc[h][ct][mt] = (floatx4){0.f, 0.f, 0.f, 0.f};
+      }
       // ring row of layer-1 row 8b + 2w + u - 1 is (base_slot + 2w + u) mod 9
       if constexpr (P == C4_FP8) {
 #pragma unroll
@@ -292,21 +367,22 @@ void c4_front_kernel(GcnnArgs a) {
             for (int mt = 0; mt < 2; ++mt) acc[s & 1][ct][mt] = c4_mfma(w2q[s][ct], xb[mt], acc[s & 1][ct][mt]);
         }
       } else if constexpr (P == C4_BF16) {
+        // the wave's 32 positions (lane % 32) x two 32-channel tiles; k-step (tap, h): channels
+        // 16h .. 16h + 15 of the tap, lane half lane / 32 taking 8 of them
+        const int j = lane & 31, hg = lane >> 5;
 #pragma unroll
         for (int tp = 0; tp < 9; ++tp) {
           const int u = tp / 3, v = tp % 3;
           const int rr = (base_slot + 2 * wave + u) % F_RING;
-          bf16x8 xb[2];
+          const int sl = v == 1 ? j : v == 0 ? 32 + j : 33 + j;
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            const int j = mt * 16 + l16;
-            const int sl = v == 1 ? j : v == 0 ? 32 + j : 33 + j;
-            xb[mt] = *reinterpret_cast<const bf16x8*>(ring + (rr * F_SLOTS + sl) * PITCH + 16 * g);
+          for (int h = 0; h < 2; ++h) {
+            const bf16x8 xb = *reinterpret_cast<const bf16x8*>(ring + (rr * F_SLOTS + sl) * PITCH + (16 * h + 8 * hg) * 2);
+            acc32[0] = c4_mfma32(w2b[tp][h][0], xb, acc32[0]);
+            acc32[1] = c4_mfma32(w2b[tp][h][1], xb, acc32[1]);
           }
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt) acc[0][ct][mt] = c4_mfma(w2b[tp][ct], xb[mt], acc[0][ct][mt]);
+          // keep each tap's fragment reads next to its MFMAs (hoisting them all spills registers)
+          if (tp & 1) __builtin_amdgcn_sched_barrier(0);
         }
       } else {
         // FP32: weights from global (L2-resident) per tap; lane group g holds channels 8g..8g+7,
@@ -337,50 +413,76 @@ void c4_front_kernel(GcnnArgs a) {
           }
         }
       }
-      // bias + ReLU -> layer-2 activations of row 4b + w
+      // bias + ReLU -> layer-2 activations of row 4b + w, staged through this wave's slice of the
+      // (now free) frame band area so that the global stores are whole contiguous lines
       {
         const int orow = 4 * b + wave;
+        unsigned char* tw = lds + wave * 32 * F_TPITCH<P>;
         float m = 0.f;
+        // 8 quads of 4 consecutive channels per lane: (position j, first channel c0, values)
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          const int j = mt * 16 + l16;
-          T* o = out2 + (orow * 32 + j) * 64;
+        for (int qd = 0; qd < 8; ++qd) {
+          int j, c0;
+          float x[4];
+          if constexpr (P == C4_BF16) {
+            const int c2 = qd >> 2, vq = qd & 3;
+            j = lane & 31;
+            c0 = c2 * 32 + 8 * vq + 4 * (lane >> 5);
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) {
-            const float4 bb = *reinterpret_cast<const float4*>(a.bias[slot][1] + ct * 16 + 4 * g);
-            const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
-            float sv[4] = {1.f, 1.f, 1.f, 1.f};
-            if constexpr (P == C4_FP8) {
-              const float4 ss = *reinterpret_cast<const float4*>(a.c4_wscale[slot][0] + ct * 16 + 4 * g);
-              sv[0] = ss.x * asc1; sv[1] = ss.y * asc1; sv[2] = ss.z * asc1; sv[3] = ss.w * asc1;
-            }
-            float v[4];
+            for (int r = 0; r < 4; ++r) x[r] = acc32[c2][4 * vq + r];
+          } else {
+            const int mt = qd >> 2, ct = qd & 3;
+            j = mt * 16 + l16;
+            c0 = ct * 16 + 4 * g;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              float x = acc[0][ct][mt][r] + acc[1][ct][mt][r];
-              if constexpr (P == C4_FP8) x *= sv[r];
-              v[r] = fmaxf(x + bv[r], 0.f);
-              m = fmaxf(m, v[r]);
-              v[r] *= inv_s2;
-            }
-            c4_store4<P>(o + ct * 16 + 4 * g, v[0], v[1], v[2], v[3]);
+            for (int r = 0; r < 4; ++r) x[r] = acc[0][ct][mt][r] + acc[1][ct][mt][r];
           }
+          const float4 bb = *reinterpret_cast<const float4*>(consts_s + 32 + c0);
+          const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+          float sv[4] = {1.f, 1.f, 1.f, 1.f};
+          if constexpr (P == C4_FP8) {
+            const float4 ss = *reinterpret_cast<const float4*>(consts_s + 96 + c0);
+            sv[0] = ss.x; sv[1] = ss.y; sv[2] = ss.z; sv[3] = ss.w;
+          }
+          float v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float xr = x[r];
+            if constexpr (P == C4_FP8) xr *= sv[r];
+            v[r] = fmaxf(xr + bv[r], 0.f);
+            m = fmaxf(m, v[r]);
+            v[r] *= inv_s2;
+          }
+          c4_store4<P>(tw + j * F_TPITCH<P> + c0 * ES, v[0], v[1], v[2], v[3]);
         }
         if constexpr (P == C4_F32) c4_track_max(amax2, m);
+        // the wave's 32 positions x 64 channels are contiguous in the output: 16 bytes a lane
+        constexpr int RB = 64 * ES;                      // bytes of one position
+        u32x4* dst = reinterpret_cast<u32x4*>(reinterpret_cast<unsigned char*>(out2) + (int64_t)orow * 32 * RB);
+#pragma unroll
+        for (int i = 0; i < RB / 32; ++i) {
+          const int off = i * 1024 + lane * 16;
+          dst[off / 16] = *reinterpret_cast<const u32x4*>(tw + (off / RB) * F_TPITCH<P> + off % RB);
+        }
       }
       __syncthreads();   // the next band restages the frame rows and overwrites ring rows
+      if (b + 1 < F_NB) C4_FCOMMIT(b + 1);
     }
     if (tid == 0) ticks_s[k] += wall_clock64() - t0;
   }
   __syncthreads();
   if (tid < kMaxK && ticks_s[tid] && a.count_ticks) atomicAdd(&a.st->r_ticks[tid], ticks_s[tid]);
+#undef C4_FISSUE
+#undef C4_FCOMMIT
 }
 
 // ---------------------------------------------------------------- layers 3 and 4: implicit GEMM
 template <int P> struct GemmCfg;
-// ROWB: bytes of one LDS tile row per k-block; UPR: 16-byte units per row; CE: elements per unit
-template <> struct GemmCfg<C4_F32> { static constexpr int ROWB = 64, UPR = 4, CE = 4, KSUB = 4; };
-template <> struct GemmCfg<C4_BF16> { static constexpr int ROWB = 64, UPR = 4, CE = 8, KSUB = 1; };
+// ROWB: bytes of one LDS tile row per k-block; UPR: 16-byte units per row; CE: elements per unit;
+// KSUB: MFMA k-steps per k-block
+// (128-byte rows: 2 bf16 / 8 fp32 / 1 fp8 MFMA k-steps per k-block and barrier)
+template <> struct GemmCfg<C4_F32> { static constexpr int ROWB = 128, UPR = 8, CE = 4, KSUB = 8; };
+template <> struct GemmCfg<C4_BF16> { static constexpr int ROWB = 128, UPR = 8, CE = 8, KSUB = 2; };
 template <> struct GemmCfg<C4_FP8> { static constexpr int ROWB = 128, UPR = 8, CE = 16, KSUB = 1; };
 
 // chunk swizzle of tile row r: rows of 4 units xor (r/2) mod 4, rows of 8 units xor r mod 8
@@ -388,54 +490,76 @@ template <int UPR>
 __host__ __device__ inline int c4_swz(int r) { return UPR == 4 ? ((r >> 1) & 3) : (r & 7); }
 
 template <int P, int LAYER> struct GemmShape;
-// LAYER 2 = the third conv (32x32x64 -> 16x16x128), LAYER 3 = the fourth (16x16x128 -> 8x8x256)
+// LAYER 2 = the third conv (32x32x64 -> 16x16x128), LAYER 3 = the fourth (16x16x128 -> 8x8x256).
+// Eight waves, each a 64 x 64 tile (4 x 4 MFMA tiles): layer 3 tiles one frame (256 positions) x
+// all 128 channels, layer 4 two frames (128 positions) x all 256 channels (the head needs every
+// channel of a frame in one workgroup).
 template <int P> struct GemmShape<P, 2> {
-  static constexpr int CIN = 64, COUT = 128, HIN = 32, HOUT = 16;
-  static constexpr int BM = P == C4_BF16 ? 256 : 128, BN = 128;
-  static constexpr int WM = 64, WN = P == C4_BF16 ? 128 : 64;
+  static constexpr int CIN = 64, COUT = 128, HIN = 32, HOUT = 16, BM = 256, BN = 128;
 };
 template <int P> struct GemmShape<P, 3> {
-  static constexpr int CIN = 128, COUT = 256, HIN = 16, HOUT = 8;
-  static constexpr int BM = P == C4_BF16 ? 128 : 64, BN = 256;
-  static constexpr int WM = 64, WN = P == C4_BF16 ? 128 : 64;
+  static constexpr int CIN = 128, COUT = 256, HIN = 16, HOUT = 8, BM = 128, BN = 256;
 };
 
 __host__ __device__ inline int c4_nkb(int prec, int layer) {
   const int cin = layer == 2 ? 64 : 128;
-  const int bke = prec == C4_FP8 ? 128 : prec == C4_BF16 ? 32 : 16;
+  const int bke = prec == C4_FP8 ? 128 : prec == C4_BF16 ? 64 : 32;
   return (9 * cin + bke - 1) / bke;
 }
 
+// 16 bytes per lane from global memory straight into LDS (lane i at lds_off + 16 i), issued as
+// one instruction per wave.  The asynchronous write is tracked by vmcnt; the caller waits for it
+// explicitly (the compiler does not see this LDS write, so it adds no waits of its own).
+__device__ inline void c4_dma16(const void* src, uint32_t lds_off) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds_off)
+               : "memory", "m0");
+}
+// s_waitcnt vmcnt(N) (other counters not waited for)
+template <int N>
+__device__ inline void c4_wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 template <int P, int LAYER>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == C4_FP8 && LAYER == 3 ? 1 : 2)))
-void c4_gemm_kernel(GcnnArgs a, Forward f) {
+__global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
   typedef typename C4T<P>::T T;
   typedef GemmCfg<P> G;
   typedef GemmShape<P, LAYER> S;
   constexpr int ES = C4T<P>::ES, UPR = G::UPR, CE = G::CE, BKE = G::ROWB / ES;
   constexpr int CIN = S::CIN, COUT = S::COUT, HIN = S::HIN, HOUT = S::HOUT, PP = HOUT * HOUT;
-  constexpr int BM = S::BM, BN = S::BN, WM = S::WM, WN = S::WN;
+  constexpr int BM = S::BM, BN = S::BN, WM = 64, WN = 64;
   constexpr int MT = WM / 16, NT = WN / 16;
-  constexpr int WGM = BM / WM;                       // waves along M
+  constexpr int WGM = BM / WM;                        // waves along M (8 waves in all)
   constexpr int NKB = (9 * CIN + BKE - 1) / BKE;
-  constexpr int UNITS = (BN + BM) * UPR, NU = UNITS / 256, NA = BN * UPR / 256;
+  constexpr int UNITS = (BN + BM) * UPR;              // 16-byte units of one stage
+  constexpr int NI = UNITS / 64 / 8;                  // load instructions per wave and stage
+  constexpr int NIA = BN * UPR / 64 / 8;              // ... of them for A (the rest gather B)
   constexpr int STAGE = UNITS * 16;
+  constexpr int NS = 3;                               // stages in flight
   constexpr bool HEAD = LAYER == 3;
-  static_assert(UNITS % 256 == 0 && (BN * UPR) % 256 == 0, "tile rows must fill the thread units");
-  static_assert(WGM * (BN / WN) == 4, "four waves per tile");
+  static_assert(UNITS % 512 == 0 && (BN * UPR) % 512 == 0, "stage rows must fill the waves' load units");
+  static_assert(WGM * (BN / WN) == 8, "eight waves per tile");
   static_assert(!HEAD || (BN == COUT && WM == PP), "the head needs whole frames per wave and all channels");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
-  __shared__ float zpart[4][kClasses];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[NS * STAGE];
+  __shared__ float zpart[8][kClasses];
+  // epilogue constants of the tile, staged before its k loop: bias and (FP8) weight scale x input
+  // activation scale of its channels, and (last layer) the FC weights
+  __shared__ __attribute__((aligned(16))) float ep_bias[BN];
+  __shared__ __attribute__((aligned(16))) float ep_scale[P == C4_FP8 ? BN : 1];
+  __shared__ float fcw_s[HEAD ? COUT * kClasses : 1];
   __shared__ unsigned long long ticks_s[kMaxK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int wm = wave % WGM, wn = wave / WGM;
   if (tid < kMaxK) ticks_s[tid] = 0;
   const T* act_in = reinterpret_cast<const T*>(LAYER == 2 ? a.c4_act2 : a.c4_act3);
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds);
   // tiles: per slot ceil(count * PP / BM) x COUT / BN
   int total = 0;
   for (int i = 0; i < a.n_preds; ++i)
     if (a.c4[i]) total += (int)(((int64_t)a.q.counts[a.pred[i]] * PP + BM - 1) / BM) * (COUT / BN);
-  const int u_slot = tid % UPR;     // the LDS slot of every unit this thread stages
+  const int u_slot = lane % UPR;     // the LDS slot of every unit this lane loads
 
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int slot = 0, off = t, ebase = 0;
@@ -452,45 +576,49 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
     const int64_t rows = (int64_t)cnt * PP;
     const unsigned long long t0 = wall_clock64();
     const unsigned char* img = static_cast<const unsigned char*>(a.c4_img[slot][LAYER - 2][P]) + (size_t)cb * BN * G::ROWB;
+    // (the previous tile's closing barrier ordered every read of these)
+    for (int i = tid; i < BN; i += 512) {
+      ep_bias[i] = a.bias[slot][LAYER][cb * BN + i];
+      if constexpr (P == C4_FP8) ep_scale[i] = a.c4_wscale[slot][LAYER - 1][cb * BN + i] * a.c4_ascale[slot][LAYER - 1];
+    }
+    if constexpr (HEAD)
+      for (int i = tid; i < COUT * kClasses; i += 512) fcw_s[i] = a.fc_w[slot][i];
 
-    // B rows this thread stages: precomputed frame pointer, output position and chunk
-    const T* bsrc[NU - NA];
-    int boi[NU - NA], boj[NU - NA], bch[NU - NA];
+    // B rows this lane gathers: frame pointer, output position and chunk, per load instruction
+    const T* bsrc[NI - NIA];
+    int boi[NI - NIA], boj[NI - NIA], bch[NI - NIA];
 #pragma unroll
-    for (int v = NA; v < NU; ++v) {
-      const int U = tid + 256 * v - BN * UPR;
+    for (int i = NIA; i < NI; ++i) {
+      const int U = (wave + 8 * i) * 64 + lane - BN * UPR;
       const int rb = U / UPR;
       const int64_t row = row0 + rb;
       const bool valid = row < rows && ebase + row / PP < a.act_cap;
       const int64_t e = valid ? row / PP : 0;
       const int p = valid ? (int)(row % PP) : 0;
-      bsrc[v - NA] = act_in + ((int64_t)ebase + e) * (HIN * HIN * CIN);
-      boi[v - NA] = valid ? p / HOUT : -1000;        // invalid rows read the zero page
-      boj[v - NA] = p % HOUT;
-      bch[v - NA] = (u_slot ^ c4_swz<UPR>(rb)) * CE;  // element offset of the chunk in the k-block
+      bsrc[i - NIA] = act_in + ((int64_t)ebase + e) * (HIN * HIN * CIN);
+      boi[i - NIA] = valid ? p / HOUT : -1000;        // invalid rows read the zero page
+      boj[i - NIA] = p % HOUT;
+      bch[i - NIA] = (u_slot ^ c4_swz<UPR>(rb)) * CE;  // element offset of the chunk in the k-block
     }
-    u32x4 stg[NU];
-    // stage k-block kb of A (the packed image) and B (im2col gathers) into registers
-#define C4_GLOAD(kb_)                                                                              \
-  do {                                                                                             \
-    const int kbv = (kb_);                                                                         \
-    _Pragma("unroll") for (int v = 0; v < NA; ++v)                                                 \
-      stg[v] = reinterpret_cast<const u32x4*>(img + (size_t)kbv * COUT * G::ROWB)[tid + 256 * v];  \
-    _Pragma("unroll") for (int v = NA; v < NU; ++v) {                                              \
-      const int ke = kbv * BKE + bch[v - NA];                                                      \
-      const int tap = ke / CIN, ch = ke % CIN;                                                     \
-      const int y = 2 * boi[v - NA] + tap / 3 - 1, x = 2 * boj[v - NA] + tap % 3 - 1;              \
-      const bool ok = tap < 9 && y >= 0 && x >= 0 && y < HIN && x < HIN;                           \
-      const u32x4* src = ok ? reinterpret_cast<const u32x4*>(bsrc[v - NA] + (y * HIN + x) * CIN + ch) \
-                            : static_cast<const u32x4*>(a.zero_page);                              \
-      stg[v] = *src;                                                                               \
-    }                                                                                              \
-  } while (0)
-#define C4_LSTORE(buf_)                                                                            \
-  do {                                                                                             \
-    _Pragma("unroll") for (int v = 0; v < NU; ++v)                                                 \
-      reinterpret_cast<u32x4*>(lds + (buf_) * STAGE)[tid + 256 * v] = stg[v];                      \
-  } while (0)
+    // stage kb of A (packed image, a straight copy) and B (im2col gathers) into LDS buffer buf
+    auto issue = [&](int kb, int buf) {
+      const uint32_t base = lds0 + buf * STAGE;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const int q = wave + 8 * i;
+        const void* src;
+        if (i < NIA) {
+          src = img + (size_t)kb * COUT * G::ROWB + (size_t)(q * 64 + lane) * 16;
+        } else {
+          const int ke = kb * BKE + bch[i - NIA];
+          const int tap = ke / CIN, ch = ke % CIN;
+          const int y = 2 * boi[i - NIA] + tap / 3 - 1, x = 2 * boj[i - NIA] + tap % 3 - 1;
+          const bool ok = tap < 9 && y >= 0 && x >= 0 && y < HIN && x < HIN;
+          src = ok ? static_cast<const void*>(bsrc[i - NIA] + (y * HIN + x) * CIN + ch) : a.zero_page;
+        }
+        c4_dma16(src, __builtin_amdgcn_readfirstlane(base + q * 1024));
+      }
+    };
 
     floatx4 acc[NT][MT];
 #pragma unroll
@@ -522,64 +650,68 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = c4_mfma(af[nt], bfr[mt], acc[nt][mt]);
       } else if constexpr (P == C4_BF16) {
-        bf16x8 af[NT], bfr[MT];
+        // k-step ks reads chunk 4 ks + g of each row
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int r = wn * WN + nt * 16 + l16;
-          af[nt] = *reinterpret_cast<const bf16x8*>(A + (r * UPR + (g ^ c4_swz<UPR>(r))) * 16);
-        }
+        for (int ks = 0; ks < G::KSUB; ++ks) {
+          bf16x8 af[NT], bfr[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int r = wm * WM + mt * 16 + l16;
-          bfr[mt] = *reinterpret_cast<const bf16x8*>(B + (r * UPR + (g ^ c4_swz<UPR>(r))) * 16);
-        }
+          for (int nt = 0; nt < NT; ++nt) {
+            const int r = wn * WN + nt * 16 + l16;
+            af[nt] = *reinterpret_cast<const bf16x8*>(A + (r * UPR + ((4 * ks + g) ^ c4_swz<UPR>(r))) * 16);
+          }
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = c4_mfma(af[nt], bfr[mt], acc[nt][mt]);
-      } else {
-        floatx4 af[NT], bfr[MT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int r = wn * WN + nt * 16 + l16;
-          af[nt] = *reinterpret_cast<const floatx4*>(A + (r * UPR + (g ^ c4_swz<UPR>(r))) * 16);
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int r = wm * WM + mt * 16 + l16;
-          bfr[mt] = *reinterpret_cast<const floatx4*>(B + (r * UPR + (g ^ c4_swz<UPR>(r))) * 16);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
+          for (int mt = 0; mt < MT; ++mt) {
+            const int r = wm * WM + mt * 16 + l16;
+            bfr[mt] = *reinterpret_cast<const bf16x8*>(B + (r * UPR + ((4 * ks + g) ^ c4_swz<UPR>(r))) * 16);
+          }
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = c4_mfma(af[nt][j], bfr[mt][j], acc[nt][mt]);
+            for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = c4_mfma(af[nt], bfr[mt], acc[nt][mt]);
+        }
+      } else {
+        // lane group g reads chunks 2g and 2g + 1 (8 values); k-step j uses value j
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          floatx4 af[NT], bfr[MT];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const int r = wn * WN + nt * 16 + l16;
+            af[nt] = *reinterpret_cast<const floatx4*>(A + (r * UPR + ((2 * g + h) ^ c4_swz<UPR>(r))) * 16);
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const int r = wm * WM + mt * 16 + l16;
+            bfr[mt] = *reinterpret_cast<const floatx4*>(B + (r * UPR + ((2 * g + h) ^ c4_swz<UPR>(r))) * 16);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = c4_mfma(af[nt][j], bfr[mt][j], acc[nt][mt]);
+        }
       }
     };
 
-    // double-buffered k loop, one barrier per k-block: block kb+1 is stored while block kb is
-    // read; block kb+2 is in flight meanwhile
-    C4_GLOAD(0);
-    C4_LSTORE(0);
-    if (NKB > 1) C4_GLOAD(1);
-    __syncthreads();
+    // NS-stage ring, one barrier per k-block: block kb + NS - 1 is loaded while block kb is read.
+    // The wait before the barrier covers this wave's loads of block kb (the blocks issued after
+    // it may stay in flight); the barrier then covers every wave's.
+#pragma unroll
+    for (int s0 = 0; s0 < NS - 1; ++s0)
+      if (s0 < NKB) issue(s0, s0);
 #pragma unroll 1
     for (int kb = 0; kb < NKB; ++kb) {
-      if (kb + 1 < NKB) {
-        C4_LSTORE((kb + 1) & 1);
-        if (kb + 2 < NKB) C4_GLOAD(kb + 2);
-      }
-      compute(kb & 1);
+      const int ahead = min(NS - 2, NKB - 1 - kb);
+      if (ahead >= 2) c4_wait_vm<2 * NI>();
+      else if (ahead == 1) c4_wait_vm<NI>();
+      else c4_wait_vm<0>();
       __syncthreads();
+      if (kb + NS - 1 < NKB) issue(kb + NS - 1, (kb + NS - 1) % NS);
+      compute(kb % NS);
     }
-#undef C4_GLOAD
-#undef C4_LSTORE
 
     // ---- epilogue
-    const float* bias = a.bias[slot][LAYER];
-    const float* wsc = a.c4_wscale[slot][LAYER - 1];
-    const float asc = P == C4_FP8 ? a.c4_ascale[slot][LAYER - 1] : 1.f;
     if constexpr (!HEAD) {
       T* out = reinterpret_cast<T*>(a.c4_act3);
       const float inv_out = P == C4_FP8 ? 1.f / a.c4_ascale[slot][2] : 1.f;
@@ -594,13 +726,17 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
         T* o = out + ((int64_t)ebase + e) * (PP * COUT) + (int64_t)p * COUT;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const int ch = cb * BN + wn * WN + nt * 16 + 4 * g;
+          const int cl = wn * WN + nt * 16 + 4 * g;    // channel within the tile
+          const int ch = cb * BN + cl;
+          const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + cl);
+          floatx4 sc = {1.f, 1.f, 1.f, 1.f};
+          if constexpr (P == C4_FP8) sc = *reinterpret_cast<const floatx4*>(ep_scale + cl);
           float v[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             float x = acc[nt][mt][r];
-            if constexpr (P == C4_FP8) x *= wsc[ch + r] * asc;
-            v[r] = fmaxf(x + bias[ch + r], 0.f);
+            if constexpr (P == C4_FP8) x *= sc[r];
+            v[r] = fmaxf(x + bb[r], 0.f);
             m = fmaxf(m, valid ? v[r] : 0.f);
             v[r] *= inv_out;
           }
@@ -613,26 +749,30 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
       // positions, then this wave's share of FC.
       const int64_t frow = row0 + wm * WM;             // first row of the frame
       const bool fvalid = frow < rows;
-      const float* fw = a.fc_w[slot];
       float zc = 0.f;                                   // lane l16 < 10: class l16
+      const int cls = l16 < kClasses ? l16 : 0;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int chb = wn * WN + nt * 16 + 4 * g;
+        const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + chb);
+        floatx4 sc = {1.f, 1.f, 1.f, 1.f};
+        if constexpr (P == C4_FP8) sc = *reinterpret_cast<const floatx4*>(ep_scale + chb);
         float s[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             float x = acc[nt][mt][r];
-            if constexpr (P == C4_FP8) x *= wsc[chb + r] * asc;
-            s[r] += fmaxf(x + bias[chb + r], 0.f);
+            if constexpr (P == C4_FP8) x *= sc[r];
+            s[r] += fmaxf(x + bb[r], 0.f);
           }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float gch = row_sum16(s[r]) * (1.f / PP);
-          if (l16 < kClasses) zc += gch * fw[(chb + r) * kClasses + l16];
+          zc += gch * fcw_s[(chb + r) * kClasses + cls];
         }
       }
+      if (l16 >= kClasses) zc = 0.f;
       // rows g = 0..3 hold different channel groups: add them
       zc = (__shfl(zc, l16) + __shfl(zc, 16 + l16)) + (__shfl(zc, 32 + l16) + __shfl(zc, 48 + l16));
       if (lane < kClasses) zpart[wave][lane] = zc;
@@ -648,9 +788,9 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
             float z[kClasses];
 #pragma unroll
             for (int c = 0; c < kClasses; ++c) {
-              float s = 0.f;
-              for (int w2 = 0; w2 < BN / WN; ++w2) s += zpart[wm + WGM * w2][c];
-              z[c] = s + a.fc_b[slot][c];
+              float sum = 0.f;
+              for (int w2 = 0; w2 < BN / WN; ++w2) sum += zpart[wm + WGM * w2][c];
+              z[c] = sum + a.fc_b[slot][c];
             }
             const uint32_t idx = entry_idx(e);
             if (f.logits != nullptr)
@@ -665,26 +805,32 @@ void c4_gemm_kernel(GcnnArgs a, Forward f) {
       }
     }
     if (tid == 0) ticks_s[k] += wall_clock64() - t0;
-    __syncthreads();   // the next tile's prologue rewrites LDS (and zpart)
+    __syncthreads();   // the next tile's prologue rewrites LDS (stages, constants, zpart)
   }
   if (tid < kMaxK && ticks_s[tid] && a.count_ticks) atomicAdd(&a.st->r_ticks[tid], ticks_s[tid]);
 }
 
 // ---------------------------------------------------------------- launch
+template <int P>
+static void launch_front(const GcnnArgs& a, int grid, hipStream_t s) {
+  if (a.fr.dtype == HYDRO_DTYPE_U8) hipLaunchKernelGGL((c4_front_kernel<P, true>), dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((c4_front_kernel<P, false>), dim3(grid), dim3(256), 0, s, a);
+}
+
 void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hipStream_t s) {
   const int g1 = grid * (prec == C4_F32 ? 1 : 2);
   if (prec == C4_FP8) {
-    hipLaunchKernelGGL(c4_front_kernel<C4_FP8>, dim3(g1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_FP8, 2>), dim3(grid * 2), dim3(256), 0, s, a, f);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_FP8, 3>), dim3(grid * 2), dim3(256), 0, s, a, f);
+    launch_front<C4_FP8>(a, g1, s);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_FP8, 2>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_FP8, 3>), dim3(grid), dim3(512), 0, s, a, f);
   } else if (prec == C4_BF16) {
-    hipLaunchKernelGGL(c4_front_kernel<C4_BF16>, dim3(g1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 2>), dim3(grid * 2), dim3(256), 0, s, a, f);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 3>), dim3(grid * 2), dim3(256), 0, s, a, f);
+    launch_front<C4_BF16>(a, g1, s);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 2>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 3>), dim3(grid), dim3(512), 0, s, a, f);
   } else {
-    hipLaunchKernelGGL(c4_front_kernel<C4_F32>, dim3(g1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_F32, 2>), dim3(grid * 2), dim3(256), 0, s, a, f);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_F32, 3>), dim3(grid * 2), dim3(256), 0, s, a, f);
+    launch_front<C4_F32>(a, g1, s);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_F32, 2>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_F32, 3>), dim3(grid), dim3(512), 0, s, a, f);
   }
 }
 
@@ -746,13 +892,23 @@ void c4_pack_front(const float* w1, float scale1, const float* w2, const float* 
   for (int s = 0; s < 7; ++s)
     for (int ct = 0; ct < 2; ++ct)
       for (int l = 0; l < 64; ++l) out->w1f[(s * 2 + ct) * 64 + l] = w1k(ct * 16 + (l & 15), 4 * s + (l >> 4));
-  // layer 2 (cin 32): bf16 [tap][ct][lane][8]: channels 8g + e; fp32 the same order
-  out->w2b.assign(9 * 4 * 64 * 8, 0.f);
+  // layer 2 (cin 32), bf16 32x32x16 fragments [tap][h][c2][lane][8]: output channel
+  // 32 c2 + lane % 32, input channel 16 h + 8 (lane / 32) + e
+  out->w2b.assign(9 * 2 * 2 * 64 * 8, 0.f);
+  for (int tp = 0; tp < 9; ++tp)
+    for (int h = 0; h < 2; ++h)
+      for (int c2 = 0; c2 < 2; ++c2)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e)
+            out->w2b[(((tp * 2 + h) * 2 + c2) * 64 + l) * 8 + e] =
+                c4_w(w2, 32, c2 * 32 + (l & 31), tp * 32 + 16 * h + 8 * (l >> 5) + e);
+  // fp32 [tap][ct][lane][8]: output channel 16 ct + lane % 16, input channels 8 (lane / 16) + e
+  out->w2f.assign(9 * 4 * 64 * 8, 0.f);
   for (int tp = 0; tp < 9; ++tp)
     for (int ct = 0; ct < 4; ++ct)
       for (int l = 0; l < 64; ++l)
         for (int e = 0; e < 8; ++e)
-          out->w2b[((tp * 4 + ct) * 64 + l) * 8 + e] = c4_w(w2, 32, ct * 16 + (l & 15), tp * 32 + 8 * (l >> 4) + e);
+          out->w2f[((tp * 4 + ct) * 64 + l) * 8 + e] = c4_w(w2, 32, ct * 16 + (l & 15), tp * 32 + 8 * (l >> 4) + e);
   // fp8 [s][ct][lane][32 bytes]: tap 4s + g, channels 0..31
   out->w2q.assign(3 * 4 * 64 * 32, 0);
   for (int s = 0; s < 3; ++s)
@@ -766,8 +922,7 @@ void c4_pack_front(const float* w1, float scale1, const float* w2, const float* 
 
 size_t c4_img_bytes(int prec, int layer) {
   const int cout = layer == 2 ? 128 : 256;
-  const int rowb = prec == C4_FP8 ? 128 : 64;
-  return (size_t)c4_nkb(prec, layer) * cout * rowb;
+  return (size_t)c4_nkb(prec, layer) * cout * 128;
 }
 
 // A image of a GEMM layer: [kb][oc][UPR units of 16 bytes], unit s holding chunk s ^ swz(oc);
@@ -775,7 +930,7 @@ size_t c4_img_bytes(int prec, int layer) {
 void c4_pack_img(int prec, int layer, const float* w, const float* scale, unsigned char* out) {
   const int cin = layer == 2 ? 64 : 128, cout = layer == 2 ? 128 : 256;
   const int es = prec == C4_FP8 ? 1 : prec == C4_BF16 ? 2 : 4;
-  const int rowb = prec == C4_FP8 ? 128 : 64, upr = rowb / 16, ce = 16 / es, bke = rowb / es;
+  const int rowb = 128, upr = rowb / 16, ce = 16 / es, bke = rowb / es;
   const int nkb = c4_nkb(prec, layer);
   for (int kb = 0; kb < nkb; ++kb)
     for (int oc = 0; oc < cout; ++oc)

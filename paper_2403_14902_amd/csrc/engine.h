@@ -118,7 +118,8 @@ struct GcnnArgs {
 // Arithmetic tiers of the dedicated 4-layer CNN kernels.
 enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2 };
 struct C4FrontPack {
-  std::vector<float> w1b, w1f, w2b;   // layer 1 (bf16 / fp32 fragment order), layer 2 (fp32 values)
+  std::vector<float> w1b, w1f;        // layer 1 (bf16 / fp32 fragment order)
+  std::vector<float> w2b, w2f;        // layer 2 (bf16 / fp32 fragment order, fp32 values)
   std::vector<uint8_t> w2q;           // layer 2 e4m3
 };
 bool c4_shape_ok(int in_hw, int n_layers, const int* widths);

@@ -550,7 +550,7 @@ static int pack_c4(hydro_session* s, const HostModel& hm, float scale1, int i) {
     for (size_t t = 0; t < b2.size(); ++t) b2[t] = f32_to_bf16_bits(fp.w2b[t]);
     if ((rc = upload(s, b2.data(), b2.size(), &bp))) return rc;
     ga.c4_w2[i][C4_BF16] = bp;
-    if ((rc = upload(s, fp.w2b.data(), fp.w2b.size(), &dp))) return rc;
+    if ((rc = upload(s, fp.w2f.data(), fp.w2f.size(), &dp))) return rc;
     ga.c4_w2[i][C4_F32] = dp;
     uint8_t* qp;
     if ((rc = upload(s, fp.w2q.data(), fp.w2q.size(), &qp))) return rc;
