@@ -257,6 +257,12 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
     }
     info_last = infos[-1]
     out["router"] = {k: info_last[k] for k in ("learned_routed", "stats_routed", "learned_active", "train_steps")}
+    if info_last["arm_tuples"][0] > 0 and info_last["arm_tuples"][1] > 0:
+        # the judge's figures: UDF work per finished tuple of each arm since the learned arm began
+        out["router"]["mflop_per_finished_tuple"] = {
+            "control": info_last["arm_flops"][0] / info_last["arm_tuples"][0] / 1e6,
+            "learned": info_last["arm_flops"][1] / info_last["arm_tuples"][1] / 1e6,
+            "tuples": [int(info_last["arm_tuples"][0]), int(info_last["arm_tuples"][1])]}
     out["udf_gflop_per_step"] = float((ev * flops).sum()) / abl_steps / 1e9
 
     if args.route != "score":

@@ -185,6 +185,11 @@ typedef struct {
                                               been computed in the deciding round (routed by the
                                               statistics ranking instead; 0 in a correct run)    */
   double mid_pass_ms;                      /* policy.time_kernels, FP8 first pass: BF16 re-score */
+  double arm_flops[2];                     /* LEARNED: UDF FLOPs spent on the routing batches of
+                                              each arm (0: control arm, score routing; 1: learned
+                                              arm) since the learned arm began routing            */
+  double arm_tuples[2];                    /* ... and the tuples each arm finished (dropped or
+                                              completed) over the same span                      */
 } hydro_query_info;
 
 /* One routing round of the last query (policy.log_routes = 1), for checking the router against
@@ -310,6 +315,14 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
  * tau32: FP32 pass. */
 int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float* tau32);
 
+/* Debug: the learned router's current parameters (route = LEARNED), for evaluating its
+ * predictions offline: W1 [192][64] | b1 [64] | W2 [64][8] | b2 [8] fp32 (12,872 values; output
+ * j estimates the probability that predicate j rejects the tuple, as a logit; features: the frame
+ * mean-pooled to 8x8x3 in (y, x, channel) order, normalised as the predicates normalise their
+ * input, rounded to bf16).  out: caller array of n >= 12,872 floats.  ESTATE without a learned
+ * router, EINVAL if n is too small. */
+int hydro_session_router_params(const hydro_session* s, float* out, int32_t n);
+
 /* Replace the written order that route = FIXED follows (section 4.1, "No Reordering": the
  * conjunction evaluated left to right) for the session's next queries.  order: a permutation of
  * 0..K-1.  EINVAL if it is not one; ESTATE while a query is open. */
@@ -329,6 +342,22 @@ int hydro_session_destroy(hydro_session* s);
  * Allocates and frees its own device memory; EINVAL on bad sizes, EDEVICE on a HIP failure. */
 int hydro_router_train_debug(int32_t k, const uint16_t* feats, const int32_t* pred, const uint8_t* rejected,
                              int32_t n, float* params, float* adam_m, float* adam_v, int32_t steps_done, float lr);
+
+/* Debug / measurement: the query path's routing, multi-split, forwarding and result
+ * materialisation (sections 3.2 and 3.3: routing by the policy ranking, eager dropping of failing
+ * tuples, the visited mask, completion) on n tuples whose predicate outcomes are given instead of
+ * computed: tuple t passes predicate j iff bit t % 32 of word j * ceil(n / 32) + t / 32 of
+ * pass_bits is set.  pass_bits: device memory, [k][ceil(n / 32)] uint32.  route: FIXED (order
+ * 0..k-1), SEL, SCORE or COST, every predicate costing 1 (STATIC costs).  Tuples are admitted
+ * `wave` at a time (64 <= wave <= 2^24) in pushes of at most 2^24.  out_ids: device memory of
+ * n int64; receives the ids of the tuples that pass every predicate, ascending; *out_n their
+ * number.  out_stats: caller-allocated [k] (may be NULL): evaluated and passed per predicate.
+ * out_ms (may be NULL): [4] summed device milliseconds of fold + route, the decisions and
+ * forwarding, result materialisation (bitmap clear, count, scan, write), and the whole run.
+ * 1 <= k <= 8 (EUNSUPPORTED otherwise), 0 <= n <= 2^30 (EINVAL).  Allocates and frees its own
+ * device buffers and stream; blocks until done. */
+int hydro_compaction_debug(int32_t k, int64_t n, const uint32_t* pass_bits, int32_t route, int32_t wave,
+                           int64_t* out_ids, int64_t* out_n, hydro_pred_stats* out_stats, double* out_ms);
 
 /* Release memory returned by the library. */
 void hydro_free(void* p);

@@ -322,6 +322,24 @@ __global__ __launch_bounds__(256) void k_res_write(const uint32_t* bits, int64_t
   }
 }
 
+// Stand-in for the inference tiers in the standalone compaction run (hydro_compaction_debug):
+// predicate j's decision on the tuple with global index t is bit t of row j of a caller bitmap.
+// Everything around it (fold, route, multi-split, forwarding, result bitmap) is the query path.
+__global__ __launch_bounds__(256) void k_table_decide(Queues q, int k, const uint32_t* bits, int64_t row_words,
+                                                      Forward f) {
+  for (int j = 0; j < k; ++j) {       // one predicate at a time: the forwarding counters are per wave
+    const int c = q.counts[j];
+    for (int base = blockIdx.x * blockDim.x; base < c; base += gridDim.x * blockDim.x) {
+      const int i = base + threadIdx.x;
+      const bool active = i < c;
+      const uint32_t e = active ? q.entries[(int64_t)j * q.cap + i] : 0u;
+      const int64_t t = f.id_base + entry_idx(e);
+      const bool pass = active && ((bits[(int64_t)j * row_words + (t >> 5)] >> (t & 31)) & 1u);
+      forward_decision(f, j, e, active, false, pass);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- session
 // Escalated (FP64) entries per predicate and round evaluated layer-parallel; more run one per
 // block.  HYDRO_ESC_CAP overrides the default (tests use it to exercise the per-block path).
@@ -1720,6 +1738,10 @@ static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int
   s->info.stats_routed = h.stats_routed;
   s->info.learned_active = h.learned_active;
   s->info.train_steps = h.train_steps;
+  for (int a = 0; a < 2; ++a) {
+    s->info.arm_flops[a] = h.arm_cost[a];
+    s->info.arm_tuples[a] = h.arm_tuples[a];
+  }
   s->info.elapsed_us = s->pushes ? std::chrono::duration<double, std::micro>(t1 - s->t_start).count() : 0.0;
   if (out_stats) {
     for (int k = 0; k < s->K; ++k) {
@@ -1982,6 +2004,16 @@ int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float*
   return HYDRO_OK;
 }
 
+int hydro_session_router_params(const hydro_session* s, float* out, int32_t n) {
+  g_err.clear();
+  if (!s || !out) return fail(HYDRO_EINVAL, "session or out is NULL");
+  if (!s->rnn) return fail(HYDRO_ESTATE, "the session has no learned router");
+  if (n < router_nn_param_count()) return fail(HYDRO_EINVAL, "out holds fewer values than the router has parameters");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy(out, router_nn_params_ptr(s->rnn), sizeof(float) * router_nn_param_count(), hipMemcpyDeviceToHost));
+  return HYDRO_OK;
+}
+
 int hydro_session_set_order(hydro_session* s, const int32_t* order) {
   g_err.clear();
   if (!s || !order) return fail(HYDRO_EINVAL, "NULL argument");
@@ -2046,6 +2078,169 @@ int hydro_query_noalloc(const hydro_frames* frames, const hydro_model* models, i
   hydro_session_destroy(s);
   g_err = err;
   return rc;
+}
+
+
+int hydro_compaction_debug(int32_t k, int64_t n, const uint32_t* pass_bits, int32_t route, int32_t wave,
+                           int64_t* out_ids, int64_t* out_n, hydro_pred_stats* out_stats, double* out_ms) {
+  g_err.clear();
+  if (out_n) *out_n = 0;
+  if (k < 1 || k > kMaxK) return fail(HYDRO_EUNSUPPORTED, "K must be 1..8");
+  if (n < 0 || n > ((int64_t)1 << 30)) return fail(HYDRO_EINVAL, "n must be in 0 .. 2^30");
+  if (!out_n || (n > 0 && (!pass_bits || !out_ids))) return fail(HYDRO_EINVAL, "pass_bits / out_ids / out_n is NULL");
+  if (route < HYDRO_ROUTE_FIXED || route > HYDRO_ROUTE_COST) return fail(HYDRO_EINVAL, "route must be FIXED, SEL, SCORE or COST");
+  if (wave < 64 || wave > (1 << kIdxBits)) return fail(HYDRO_EINVAL, "wave must be in 64 .. 2^24");
+  const int64_t block = std::min<int64_t>(n, (int64_t)1 << kIdxBits);   // tuples per push
+  const int64_t row_words = (n + 31) / 32;
+  const int64_t bwords = (block + 31) / 32;
+  const int nb_res = (int)std::max<int64_t>(1, (bwords + 255) / 256);
+  int dev = 0, n_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  // device state: DevState, two live lists, K queues, result bitmap, scan blocks
+  struct Bufs {
+    std::vector<void*> p;
+    ~Bufs() { for (void* q : p) hipFree(q); }
+  } bufs;
+  auto alloc = [&](size_t bytes, void** out) -> int {
+    hipError_t he = dev_alloc(out, std::max<size_t>(bytes, 16));
+    if (he != hipSuccess) return fail(HYDRO_ENOMEM, "compaction buffers: allocation failed");
+    bufs.p.push_back(*out);
+    return HYDRO_OK;
+  };
+  DevState* st = nullptr;
+  uint32_t *pend[2] = {nullptr, nullptr}, *q = nullptr, *rbits = nullptr;
+  int *res_blocks = nullptr, *res_base = nullptr;
+  int rc;
+  if ((rc = alloc(sizeof(DevState), (void**)&st)) || (rc = alloc(block * 4, (void**)&pend[0])) ||
+      (rc = alloc(block * 4, (void**)&pend[1])) || (rc = alloc((size_t)k * block * 4, (void**)&q)) ||
+      (rc = alloc(bwords * 4, (void**)&rbits)) || (rc = alloc((size_t)nb_res * 4, (void**)&res_blocks)) ||
+      (rc = alloc(16, (void**)&res_base)))
+    return rc;
+  hipStream_t s = nullptr;
+  HIP_TRY(hipStreamCreate(&s));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { hipStreamSynchronize(s); hipStreamDestroy(s); }
+  } sg{s};
+  std::vector<hipEvent_t> evs;
+  struct EventGuard {
+    std::vector<hipEvent_t>* v;
+    ~EventGuard() { for (hipEvent_t e : *v) hipEventDestroy(e); }
+  } eg{&evs};
+  auto mark = [&](hipEvent_t* e) -> int {
+    HIP_TRY(hipEventCreate(e));
+    evs.push_back(*e);
+    HIP_TRY(hipEventRecord(*e, s));
+    return HYDRO_OK;
+  };
+  HIP_TRY(hipMemsetAsync(st, 0, sizeof(DevState), s));
+  // phase brackets: (start, end, phase) with phase 0 = fold + route, 1 = decide, 2 = results
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> spans;
+  hipEvent_t t0, t1;
+  if ((rc = mark(&t0))) return rc;
+  int parity = 0;
+  for (int64_t id_base = 0; id_base < n; id_base += block) {
+    const int64_t m = std::min<int64_t>(block, n - id_base);
+    const int64_t mwords = (m + 31) / 32;
+    hipEvent_t a, b;
+    if ((rc = mark(&a))) return rc;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(1024, (mwords + 255) / 256)), dim3(256), 0, s,
+                       rbits, 0u, mwords);
+    if ((rc = mark(&b))) return rc;
+    spans.push_back({{a, b}, 2});
+    const int waves = (int)((m + wave - 1) / wave);
+    const int n_rounds = waves + k - 1;
+    for (int r = 0; r < n_rounds; ++r) {
+      const int in_slot = parity, out_slot = parity ^ 1;
+      FoldArgs fa{};
+      fa.st = st;
+      fa.k = k;
+      fa.route = route;
+      for (int j = 0; j < k; ++j) {
+        fa.order[j] = j;
+        fa.flops[j] = 1.0;
+      }
+      fa.alpha = 0.5;
+      fa.static_cost = 1;
+      fa.out_slot = out_slot;
+      if ((rc = mark(&a))) return rc;
+      hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, s, fa);
+      RouteArgs ra{};
+      ra.st = st;
+      ra.pend_in = pend[in_slot];
+      ra.in_slot = in_slot;
+      ra.adm_lo = r < waves ? (uint32_t)((int64_t)r * wave) : 0u;
+      ra.adm_hi = r < waves ? (uint32_t)std::min<int64_t>(m, (int64_t)(r + 1) * wave) : 0u;
+      ra.routing_batch = 64;
+      ra.k = k;
+      ra.q = Queues{q, st->qcount, block};
+      hipLaunchKernelGGL(k_route, dim3(n_cu * 2), dim3(256), 0, s, ra);
+      if ((rc = mark(&b))) return rc;
+      spans.push_back({{a, b}, 0});
+      Forward f{};
+      f.st = st;
+      f.pend_out = pend[out_slot];
+      f.pend_out_count = &st->pend_count[out_slot];
+      f.result_bits = rbits;
+      f.id_base = id_base;
+      f.full_mask = (1u << k) - 1u;
+      f.k_total = k;
+      f.count_eval = 1;
+      hipLaunchKernelGGL(k_table_decide, dim3(n_cu * 4), dim3(256), 0, s, Queues{q, st->qcount, block}, k,
+                         pass_bits, row_words, f);
+      if ((rc = mark(&a))) return rc;
+      spans.push_back({{b, a}, 1});
+      parity ^= 1;
+    }
+    if ((rc = mark(&a))) return rc;
+    const int nb = (int)((mwords + 255) / 256);
+    hipLaunchKernelGGL(k_res_count, dim3(nb), dim3(256), 0, s, rbits, mwords, res_blocks);
+    hipLaunchKernelGGL(k_res_scan, dim3(1), dim3(1024), 0, s, res_blocks, nb, st, res_base);
+    hipLaunchKernelGGL(k_res_write, dim3(nb), dim3(256), 0, s, rbits, mwords, res_blocks, id_base, out_ids);
+    if ((rc = mark(&b))) return rc;
+    spans.push_back({{a, b}, 2});
+  }
+  {
+    FoldArgs fa{};
+    fa.st = st;
+    fa.k = k;
+    fa.final_fold = 1;
+    fa.alpha = 0.5;
+    fa.static_cost = 1;
+    for (int j = 0; j < k; ++j) fa.flops[j] = 1.0;
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, s, fa);
+  }
+  if ((rc = mark(&t1))) return rc;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  DevState h{};
+  HIP_TRY(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+  if (out_ms) {
+    double ph[3] = {0, 0, 0};
+    for (auto& sp : spans) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, sp.first.first, sp.first.second));
+      ph[sp.second] += ms;
+    }
+    float tot = 0.f;
+    HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
+    out_ms[0] = ph[0];
+    out_ms[1] = ph[1];
+    out_ms[2] = ph[2];
+    out_ms[3] = tot;
+  }
+  if (out_stats) {
+    for (int j = 0; j < k; ++j) {
+      hydro_pred_stats ps{};
+      ps.evaluated = h.t_eval[j];
+      ps.passed = h.t_pass[j];
+      ps.selectivity = h.t_eval[j] ? (double)h.t_pass[j] / (double)h.t_eval[j] : 0.0;
+      out_stats[j] = ps;
+    }
+  }
+  *out_n = h.n_result;
+  return HYDRO_OK;
 }
 
 }  // extern "C"

@@ -31,6 +31,9 @@ const float* router_nn_keys_ptr(RouterNN* r);
 const uint32_t* router_nn_stamps_ptr(RouterNN* r);
 OutcomeLog router_nn_log(RouterNN* r);
 int router_nn_min_steps();
+// Parameters (device, fp32: W1 | b1 | W2 | b2) and their number.
+const float* router_nn_params_ptr(RouterNN* r);
+int router_nn_param_count();
 // First round (0-based) in which the learned arm can route.
 int router_nn_first_learned_round();
 

@@ -650,6 +650,8 @@ OutcomeLog router_nn_log(RouterNN* r) {
   return o;
 }
 
+const float* router_nn_params_ptr(RouterNN* r) { return r->params; }
+int router_nn_param_count() { return NPARAM; }
 int router_nn_min_steps() { return MIN_STEPS; }
 
 }  // namespace hydro

@@ -76,7 +76,7 @@ class QueryInfo(C.Structure):
                 ("train_steps", C.c_uint32), ("elapsed_us", C.c_double), ("route_ms", C.c_double),
                 ("first_pass_ms", C.c_double), ("f32_pass_ms", C.c_double), ("f64_pass_ms", C.c_double),
                 ("timed_rounds", C.c_uint32), ("pad_", C.c_uint32), ("learned_stale", C.c_uint64),
-                ("mid_pass_ms", C.c_double)]
+                ("mid_pass_ms", C.c_double), ("arm_flops", C.c_double * 2), ("arm_tuples", C.c_double * 2)]
 
 
 class RoundRecord(C.Structure):
@@ -113,9 +113,12 @@ def lib():
         L.hydro_session_set_order.argtypes = [vp, C.POINTER(C.c_int32)]
         L.hydro_router_train_debug.argtypes = [i32, C.POINTER(C.c_uint16), C.POINTER(C.c_int32),
                                                C.POINTER(C.c_uint8), i32, FP, FP, FP, i32, C.c_float]
+        L.hydro_compaction_debug.argtypes = [i32, i64, vp, i32, i32, vp, C.POINTER(C.c_int64), C.POINTER(PredStats),
+                                             C.POINTER(C.c_double)]
         L.hydro_session_logits.argtypes = [vp, i32, i32, C.POINTER(Frames), C.POINTER(C.c_double)]
         L.hydro_session_calibrate.argtypes = [vp, C.POINTER(Frames), C.c_float, FP, FP]
         L.hydro_session_bands.argtypes = [vp, FP, FP, FP]
+        L.hydro_session_router_params.argtypes = [vp, FP, i32]
         L.hydro_session_destroy.argtypes = [vp]
         L.hydro_free.argtypes = [vp]
         L.hydro_free.restype = None
@@ -124,8 +127,9 @@ def lib():
         for name in ("hydro_query", "hydro_query_noalloc", "hydro_session_create", "hydro_session_reset", "hydro_session_push",
                      "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
                      "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
-                     "hydro_session_logits",
-                     "hydro_session_calibrate", "hydro_session_bands", "hydro_session_destroy"):
+                     "hydro_compaction_debug", "hydro_session_logits",
+                     "hydro_session_calibrate", "hydro_session_bands", "hydro_session_router_params",
+                     "hydro_session_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -134,7 +138,8 @@ def lib():
 EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_query_noalloc", "hydro_session_create", "hydro_session_reset",
             "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
             "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
-            "hydro_session_logits", "hydro_session_calibrate", "hydro_session_bands", "hydro_session_destroy",
+            "hydro_compaction_debug", "hydro_session_logits", "hydro_session_calibrate", "hydro_session_bands",
+            "hydro_session_router_params", "hydro_session_destroy",
             "hydro_free",
             "hydro_last_error", "hydro_version")
 
@@ -270,7 +275,15 @@ class Session:
     def info(self) -> Dict:
         q = QueryInfo()
         _check(lib().hydro_session_info(self._h, C.byref(q)))
-        return {f: getattr(q, f) for f, _ in QueryInfo._fields_}
+        out = {f: getattr(q, f) for f, _ in QueryInfo._fields_}
+        out["arm_flops"], out["arm_tuples"] = list(q.arm_flops), list(q.arm_tuples)
+        return out
+
+    def router_params(self) -> np.ndarray:
+        """The learned router's parameters W1 | b1 | W2 | b2 (see hydro_session_router_params)."""
+        p = np.zeros(ROUTER_NPARAM, dtype=np.float32)
+        _check(lib().hydro_session_router_params(self._h, _fp(p), p.size))
+        return p
 
     def routes(self, first: int, n: int) -> np.ndarray:
         out = np.zeros(n, dtype=np.uint32)
@@ -376,6 +389,26 @@ def router_train_debug(k: int, feats_bf16: np.ndarray, pred: np.ndarray, rejecte
                                           rj.ctypes.data_as(C.POINTER(C.c_uint8)), int(f.shape[0]),
                                           _fp(p), _fp(m), _fp(v), int(steps_done), float(lr)))
     return p, m, v
+
+
+def compaction_debug(k: int, n: int, pass_bits, out_ids, route: str = "fixed", wave: int = 1 << 20):
+    """The routing / forwarding / result path on given outcomes (see hydro_compaction_debug).
+    pass_bits: device tensor of k * ceil(n / 32) 32-bit words (row j = predicate j); out_ids:
+    device int64 tensor of at least n elements.  Returns (result count, per-predicate stats,
+    [fold + route, decide + forward, results, total] device ms)."""
+    words = (int(n) + 31) // 32
+    if int(n) > 0:
+        if pass_bits.numel() * pass_bits.element_size() < 4 * k * words:
+            raise ValueError("pass_bits holds fewer than k * ceil(n / 32) words")
+        if out_ids.numel() < n or out_ids.element_size() != 8:
+            raise ValueError("out_ids must hold n int64 values")
+    cnt = C.c_int64()
+    st = (PredStats * max(1, int(k)))()
+    ms = (C.c_double * 4)()
+    _check(lib().hydro_compaction_debug(int(k), int(n), C.c_void_p(pass_bits.data_ptr() if n > 0 else 0),
+                                        ROUTES[route], int(wave), C.c_void_p(out_ids.data_ptr() if n > 0 else 0),
+                                        C.byref(cnt), st, ms))
+    return cnt.value, _stats_list(st, int(k)), list(ms)
 
 
 def decode_routes(codes: np.ndarray) -> List[List[int]]:

@@ -47,7 +47,9 @@ def test_cnn_logits_batch_invariant_across_entry_ring_refills(tier):
     s.close()
 
 
-@pytest.mark.parametrize("prec,tier,tol", [("bf16", 0, 0.1), ("bf16", 1, 1e-4), ("fp32", 0, 1e-4), ("bf16", 2, 1e-10)])
+# tolerances: a few times the largest errors measured on these frames (bf16 6.6e-3, fp32 4.5e-7,
+# fp64 2.7e-15); the kernels are deterministic, so the errors do not vary between runs
+@pytest.mark.parametrize("prec,tier,tol", [("bf16", 0, 0.03), ("bf16", 1, 5e-6), ("fp32", 0, 5e-6), ("bf16", 2, 1e-13)])
 def test_cnn_logits_each_tier_vs_oracle(c2small, prec, tier, tol):
     c = c2small
     s = hydro.Session(c.specs(), hydro.make_policy("score", precision=prec), 64, c.n)
@@ -74,7 +76,7 @@ def test_cnn_uint8_frames_logits_and_ids():
     dev = torch.from_numpy(u8).cuda()
     s = hydro.Session(specs, hydro.make_policy("score", precision="bf16"), 64, 512)
     for k in range(3):
-        for tier, tol in ((0, 0.1), (1, 1e-4), (2, 1e-10)):
+        for tier, tol in ((0, 0.05), (1, 5e-6), (2, 1e-13)):      # measured 1.04e-2, 5.2e-7, 2.2e-15
             err = np.abs(s.logits(k, tier, dev, "u8") - Z[k]).max()
             log(f"[gpu] u8 logits tier {tier} predicate {k}: {err:.3e}")
             assert err <= tol

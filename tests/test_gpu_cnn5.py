@@ -28,7 +28,7 @@ def test_c5_logits_each_tier(c5z):
     s = hydro.Session(c5z.specs(), hydro.make_policy("score", precision="bf16"), 128, c5z.n)
     dev = c5z.device_frames()
     for k in range(c5z.cfg.k):
-        for tier, tol in ((0, 0.1), (1, 1e-4), (2, 1e-9)):
+        for tier, tol in ((0, 0.03), (1, 5e-6), (2, 1e-13)):      # measured 6.9e-3, 7.5e-7, 3.1e-15
             err = np.abs(s.logits(k, tier, dev, "u8") - c5z.Z[k]).max()
             log(f"[gpu] c5 predicate {k} tier {tier}: max |z - z64| = {err:.3e}")
             assert err <= tol
@@ -65,7 +65,7 @@ def test_c5_ungrouped_launches(c5z, c5):
         for tier in (0, 2):
             err = np.abs(s.logits(k, tier, dev, "u8") - c5z.Z[k]).max()
             log(f"[gpu] c5 ungrouped predicate {k} tier {tier}: max |z - z64| = {err:.3e}")
-            assert err <= (1e-5 if tier == 0 else 1e-12)
+            assert err <= (5e-6 if tier == 0 else 1e-13)
     s.push(c5.device_frames(), "u8", c5.pt.thresholds, c5.seg_len)
     ids, stats = s.finish()
     assert np.array_equal(ids, c5.expect)
@@ -97,7 +97,7 @@ def test_c5_fp8_tier_logits(c5z):
         log(f"  predicate {k}: fp8 max |z - z64| = {np.abs(z8 - c5z.Z[k]).max():.3e} margin {e8:.3e}; "
             f"bf16 max |z - z64| = {np.abs(z16 - c5z.Z[k]).max():.3e} margin {e16:.3e}")
         assert np.abs(z16 - c5z.Z[k]).max() <= 0.03
-        assert np.abs(z8 - c5z.Z[k]).max() <= 0.5
+        assert np.abs(z8 - c5z.Z[k]).max() <= 0.3                # measured 8.1e-2
     s.close()
 
 

@@ -23,7 +23,9 @@ def _session(c, policy, max_push=None):
     return hydro.Session(c.specs(), policy, c.cfg.hw, max_push or c.n)
 
 
-@pytest.mark.parametrize("prec,tier,tol", [("fp32", 0, 2e-4), ("bf16", 0, 0.08), ("bf16", 1, 2e-4), ("fp32", 2, 1e-10)])
+# tolerances: a few times the largest errors measured on these frames (fp32 5.7e-6, bf16 3.7e-2 over
+# 12,288-term dot products, fp64 1e-14); the kernels are deterministic
+@pytest.mark.parametrize("prec,tier,tol", [("fp32", 0, 3e-5), ("bf16", 0, 0.08), ("bf16", 1, 3e-5), ("fp32", 2, 1e-12)])
 def test_logits_each_tier_vs_oracle(c1, prec, tier, tol):
     log(f"[gpu] logits prec={prec} tier={tier}")
     s = _session(c1, hydro.make_policy("score", precision=prec))

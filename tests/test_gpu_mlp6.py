@@ -33,7 +33,7 @@ def test_mlp6_logits_each_tier(c3z):
     s = hydro.Session(c3z.specs(), hydro.make_policy("score", precision="bf16"), 64, c3z.n)
     dev = c3z.device_frames()
     for k in range(c3z.cfg.k):
-        for tier, tol in ((0, 0.2), (1, 1e-3), (2, 1e-9)):
+        for tier, tol in ((0, 0.06), (1, 4e-5), (2, 1e-12)):      # measured 2.3e-2, 8.3e-6, 4.9e-15
             err = np.abs(s.logits(k, tier, dev, "bf16") - c3z.Z[k]).max()
             log(f"[gpu] mlp6 predicate {k} (h={c3z.cfg.models[k].hidden}) tier {tier}: max |z - z64| = {err:.3e}")
             assert err <= tol
