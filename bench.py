@@ -84,6 +84,10 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: first copy a device buffer of this size three times (a plain copy kernel "
                          "of known traffic, to scale hardware byte counters)")
+    ap.add_argument("--no-compaction", action="store_true", help="skip the standalone routing/compaction run")
+    ap.add_argument("--compaction-only", action="store_true",
+                    help="run only the standalone routing/compaction measurement and print its JSON")
+    ap.add_argument("--compaction-log2n", type=int, default=26)
     ap.add_argument("--errors", type=int, default=4096,
                     help="frames on which bf16 / fp32 logits and margins are compared with fp64 (0: skip)")
     return ap.parse_args()
@@ -411,6 +415,47 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
     return out
 
 
+def compaction(args, hydro, torch):
+    """Routing, multi-split, forwarding and result materialisation on 2^26 tuples whose outcomes
+    for four predicates (pass rates 0.5 / 0.7 / 0.8 / 0.9, independent) are drawn on the device:
+    the query path with the inference tiers replaced by a bitmap lookup, timed with HIP events per
+    phase, against the algorithmic bytes of each phase."""
+    n, k = 1 << args.compaction_log2n, 4
+    rates = [0.5, 0.7, 0.8, 0.9]
+    g = torch.Generator(device="cuda").manual_seed(26)
+    weights = (torch.ones(32, dtype=torch.int64, device="cuda") << torch.arange(32, device="cuda"))
+    rows = []
+    for p in rates:
+        b = torch.rand(n, generator=g, device="cuda") < p
+        rows.append((b.view(-1, 32).to(torch.int64) * weights).sum(dim=1).to(torch.int32))   # bit t % 32 of word t / 32
+    bits = torch.stack(rows).contiguous()
+    del rows
+    out_ids = torch.empty(n, dtype=torch.int64, device="cuda")
+    runs = []
+    for _ in range(3):
+        cnt, stats, ms = hydro.compaction_debug(k, n, bits, out_ids, route="fixed", wave=1 << 22)
+        runs.append(ms)
+    ms = min(runs, key=lambda m: m[3])
+    ev = sum(x["evaluated"] for x in stats)
+    surv = ev - n                      # entries re-routed from a live list (admitted ones are generated)
+    words = (n + 31) // 32
+    route_b = 4 * ev + 4 * surv        # queue entry writes + live-list reads
+    decide_b = 4 * ev + 4 * surv + 4 * words * k + 4 * words   # queue reads, survivor writes, outcome bitmaps, result bits
+    result_b = 3 * 4 * words + 8 * cnt                          # bitmap clear, count and write passes; ids
+    tot_b = route_b + decide_b + result_b
+    del bits, out_ids
+    torch.cuda.empty_cache()
+    return {"n": n, "k": k, "pass_rates": rates, "route": "fixed", "wave": 1 << 22, "result": int(cnt),
+            "evaluated": [int(x["evaluated"]) for x in stats],
+            "ms": {"fold_route": ms[0], "decide_forward": ms[1], "results": ms[2], "total": ms[3]},
+            "bytes": {"fold_route": route_b, "decide_forward": decide_b, "results": result_b},
+            "GB_per_s": {"fold_route": route_b / ms[0] / 1e6, "decide_forward": decide_b / ms[1] / 1e6,
+                         "results": result_b / ms[2] / 1e6, "total": tot_b / ms[3] / 1e6},
+            "frac_of_hbm_peak": tot_b / ms[3] / 1e6 / 8000.0,
+            "note": "HIP-event phase sums over all rounds (fold + route, bitmap decisions + forwarding, "
+                    "result materialisation), best of 3 runs; algorithmic bytes, 8 TB/s peak"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -430,6 +475,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.compaction_only:
+        print(json.dumps({"compaction": compaction(args, hydro, torch)}), flush=True)
+        return
     abl = max(1, min(args.ablation_steps, args.steps))
     out = measure(args, args.workload, args.n, args.steps, args.warmup, abl, hydro, torch, hs, True)
     if not args.no_secondary and args.workload != 2:
@@ -438,6 +486,9 @@ def main():
         out["cnn3_drift64"] = {k: sec[k] for k in ("value", "ms_per_step", "steps", "eager_value", "roofline",
                                                     "plain", "speedup_vs_plain", "score", "n_result", "config")
                                if k in sec}
+    if not args.no_compaction:
+        log("[bench] standalone routing / compaction")
+        out["compaction"] = compaction(args, hydro, torch)
     print(json.dumps(out), flush=True)
 
 

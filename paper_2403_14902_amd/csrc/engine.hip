@@ -222,34 +222,85 @@ __device__ inline int choose_pred(const RouteArgs& a, uint32_t e, const int* ord
   return 0;
 }
 
-__global__ __launch_bounds__(256) void k_route(RouteArgs a) {
+// Multi-split in chunks of kRouteItems entries per thread: each wave counts its entries per
+// predicate with ballots, the workgroup reserves one range per predicate with a single atomic,
+// and every entry is written to its slot (one atomic per predicate per 2,048 entries instead of
+// one per wave).  (A variant that gave each workgroup one contiguous range and one atomic per
+// predicate per round, with a second pass to write, measured slower: its longer dependent chains
+// cost more than the atomics it saved.)
+constexpr int kRouteThreads = 256, kRouteItems = 8, kRouteChunk = kRouteThreads * kRouteItems;
+
+__global__ __launch_bounds__(kRouteThreads) void k_route(RouteArgs a) {
   __shared__ int order[kMaxK];
+  __shared__ int wslot[kRouteThreads / kWave][kMaxK];   // per wave: entries, then first slot
   if (threadIdx.x < a.k) order[threadIdx.x] = a.st->order[threadIdx.x];
   __syncthreads();
   const int n_in = a.st->pend_count[a.in_slot];
-  const int total = n_in + (int)(a.adm_hi - a.adm_lo);
-  const int stride = gridDim.x * blockDim.x;
-  for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
-    int i = base + threadIdx.x;
-    bool active = i < total;
-    uint32_t e = 0;
-    int k = -1;
-    if (active) {
-      e = i < n_in ? a.pend_in[i] : make_entry(a.adm_lo + (uint32_t)(i - n_in), 0u);
-      k = choose_pred(a, e, order);
+  const int64_t total = n_in + (int64_t)(a.adm_hi - a.adm_lo);
+  const int wv = threadIdx.x / kWave, lane = lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  uint32_t n_learned = 0, n_stats = 0, n_stale = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kRouteChunk; base < total; base += (int64_t)gridDim.x * kRouteChunk) {
+    uint32_t e[kRouteItems];
+    int kk[kRouteItems], off[kRouteItems];
+#pragma unroll
+    for (int r = 0; r < kRouteItems; ++r) {
+      const int64_t i = base + r * kRouteThreads + threadIdx.x;
+      e[r] = 0u;
+      kk[r] = -1;
+      if (i < total) {
+        e[r] = i < n_in ? a.pend_in[i] : make_entry(a.adm_lo + (uint32_t)(i - n_in), 0u);
+        kk[r] = choose_pred(a, e[r], order);
+        if (a.learned_keys != nullptr) {
+          const bool eligible = learned_eligible(a, e[r]);
+          const bool learned = eligible && learned_arm(a, e[r]);
+          const bool fresh = entry_mask(e[r]) == 0;     // the tuple's first routing
+          n_learned += learned && fresh;
+          n_stats += !learned && fresh;
+          n_stale += eligible && !learned;
+        }
+      }
     }
-    if (a.learned_keys != nullptr) {
-      const bool eligible = active && learned_eligible(a, e);
-      const bool learned = eligible && learned_arm(a, e);
-      wave_add_u64(&a.st->learned_routed, learned && entry_mask(e) == 0);
-      wave_add_u64(&a.st->stats_routed, active && !learned && entry_mask(e) == 0);
-      wave_add_u64(&a.st->learned_stale, eligible && !learned);
+    // wave totals per predicate and each entry's offset within its wave's range
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (j >= a.k) break;
+      int run = 0;
+#pragma unroll
+      for (int r = 0; r < kRouteItems; ++r) {
+        const unsigned long long m = __ballot(kk[r] == j);
+        if (kk[r] == j) off[r] = run + __popcll(m & below);
+        run += __popcll(m);
+      }
+      if (lane == 0) wslot[wv][j] = run;
     }
-    for (int j = 0; j < a.k; ++j) {
-      bool mine = active && k == j;
-      if (__ballot(mine) == 0) continue;
-      int slot = wave_append(&a.q.counts[j], mine);
-      if (mine) a.q.entries[(int64_t)j * a.q.cap + slot] = e;
+    __syncthreads();
+    if (threadIdx.x < a.k) {
+      const int j = threadIdx.x;
+      int sum = 0;
+      for (int w = 0; w < kRouteThreads / kWave; ++w) sum += wslot[w][j];
+      int p = sum ? atomicAdd(&a.q.counts[j], sum) : 0;
+      for (int w = 0; w < kRouteThreads / kWave; ++w) {
+        const int c = wslot[w][j];
+        wslot[w][j] = p;
+        p += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRouteItems; ++r)
+      if (kk[r] >= 0) a.q.entries[(int64_t)kk[r] * a.q.cap + wslot[wv][kk[r]] + off[r]] = e[r];
+    __syncthreads();   // wslot is rewritten by the next chunk
+  }
+  if (a.learned_keys != nullptr) {
+    unsigned long long c[3] = {n_learned, n_stats, n_stale};
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      for (int o = 32; o > 0; o >>= 1) c[t] += __shfl_xor(c[t], o);
+    if (lane == 0) {
+      if (c[0]) atomicAdd(&a.st->learned_routed, c[0]);
+      if (c[1]) atomicAdd(&a.st->stats_routed, c[1]);
+      if (c[2]) atomicAdd(&a.st->learned_stale, c[2]);
     }
   }
 }
@@ -324,19 +375,96 @@ __global__ __launch_bounds__(256) void k_res_write(const uint32_t* bits, int64_t
 
 // Stand-in for the inference tiers in the standalone compaction run (hydro_compaction_debug):
 // predicate j's decision on the tuple with global index t is bit t of row j of a caller bitmap.
-// Everything around it (fold, route, multi-split, forwarding, result bitmap) is the query path.
-__global__ __launch_bounds__(256) void k_table_decide(Queues q, int k, const uint32_t* bits, int64_t row_words,
-                                                      Forward f) {
-  for (int j = 0; j < k; ++j) {       // one predicate at a time: the forwarding counters are per wave
+// Forwarding as in forward_decision (failures dropped, survivors with predicates left appended to
+// the next live list with their visited bit set, completed tuples set in the result bitmap), but
+// aggregated like k_route: kRouteItems entries per thread, one atomic per workgroup chunk for the
+// survivor list, one per wave and distinct bitmap word for the result bits, and the counters
+// summed per wave over the whole launch.
+__global__ __launch_bounds__(kRouteThreads) void k_table_decide(Queues q, int k, const uint32_t* bits,
+                                                                int64_t row_words, Forward f) {
+  __shared__ int wslot[kRouteThreads / kWave];
+  __shared__ unsigned long long cnt_s[2][kMaxK];     // evaluations and passes of this workgroup
+  __shared__ int chunks_s[kMaxK + 1];                // prefix of the per-predicate chunk counts
+  const int wv = threadIdx.x / kWave, lane = lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  if (threadIdx.x < 2 * kMaxK) cnt_s[threadIdx.x / kMaxK][threadIdx.x % kMaxK] = 0;
+  if (threadIdx.x == 0) {
+    chunks_s[0] = 0;
+    for (int j = 0; j < k; ++j) chunks_s[j + 1] = chunks_s[j] + (q.counts[j] + kRouteChunk - 1) / kRouteChunk;
+  }
+  __syncthreads();
+  // the chunks of every predicate form one index space: all predicates' queues are drained at once
+  for (int ch = blockIdx.x; ch < chunks_s[k]; ch += gridDim.x) {
+    int j = 0;
+    while (ch >= chunks_s[j + 1]) ++j;
     const int c = q.counts[j];
-    for (int base = blockIdx.x * blockDim.x; base < c; base += gridDim.x * blockDim.x) {
-      const int i = base + threadIdx.x;
-      const bool active = i < c;
-      const uint32_t e = active ? q.entries[(int64_t)j * q.cap + i] : 0u;
-      const int64_t t = f.id_base + entry_idx(e);
-      const bool pass = active && ((bits[(int64_t)j * row_words + (t >> 5)] >> (t & 31)) & 1u);
-      forward_decision(f, j, e, active, false, pass);
+    const int64_t base = (int64_t)(ch - chunks_s[j]) * kRouteChunk;
+    uint32_t e[kRouteItems];
+    bool more[kRouteItems];
+    int off[kRouteItems];
+    int run = 0, n_eval = 0, n_pass = 0;
+#pragma unroll
+    for (int r = 0; r < kRouteItems; ++r) {
+      const int64_t i = base + r * kRouteThreads + threadIdx.x;
+      e[r] = i < c ? q.entries[(int64_t)j * q.cap + i] : 0u;
     }
+#pragma unroll
+    for (int r = 0; r < kRouteItems; ++r) {
+      const int64_t i = base + r * kRouteThreads + threadIdx.x;
+      const bool active = i < c;
+      const uint32_t idx = entry_idx(e[r]);
+      const int64_t t = f.id_base + idx;
+      const bool pass = active && ((bits[(int64_t)j * row_words + (t >> 5)] >> (t & 31)) & 1u);
+      n_eval += active;
+      n_pass += pass;
+      const uint32_t mask = entry_mask(e[r]) | (1u << j);
+      const bool done = pass && mask == f.full_mask;
+      more[r] = pass && !done;
+      // result bits: one atomic per distinct word among the wave's completed tuples
+      const uint32_t word = idx >> 5;
+      unsigned long long dm = __ballot(done);
+      while (dm) {
+        const int leader = __ffsll((long long)dm) - 1;
+        const uint32_t w = __shfl(word, leader);
+        const bool same = done && word == w;
+        uint32_t v = same ? 1u << (idx & 31) : 0u;
+        for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+        if (lane == leader) atomicOr(&f.result_bits[w], v);
+        dm &= ~__ballot(same);
+      }
+      const unsigned long long m = __ballot(more[r]);
+      if (more[r]) off[r] = run + __popcll(m & below);
+      run += __popcll(m);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      n_eval += __shfl_xor(n_eval, o);
+      n_pass += __shfl_xor(n_pass, o);
+    }
+    if (lane == 0) {
+      wslot[wv] = run;
+      atomicAdd(&cnt_s[0][j], (unsigned long long)n_eval);
+      atomicAdd(&cnt_s[1][j], (unsigned long long)n_pass);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int sum = 0;
+      for (int w = 0; w < kRouteThreads / kWave; ++w) sum += wslot[w];
+      int p = sum ? atomicAdd(f.pend_out_count, sum) : 0;
+      for (int w = 0; w < kRouteThreads / kWave; ++w) {
+        const int cw = wslot[w];
+        wslot[w] = p;
+        p += cw;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRouteItems; ++r)
+      if (more[r]) f.pend_out[wslot[wv] + off[r]] = make_entry(entry_idx(e[r]), entry_mask(e[r]) | (1u << j));
+    __syncthreads();
+  }
+  if (threadIdx.x < k) {
+    if (cnt_s[0][threadIdx.x]) atomicAdd(&f.st->r_eval[threadIdx.x], cnt_s[0][threadIdx.x]);
+    if (cnt_s[1][threadIdx.x]) atomicAdd(&f.st->r_pass[threadIdx.x], cnt_s[1][threadIdx.x]);
   }
 }
 
@@ -1605,7 +1733,11 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
           router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
         }
       }
-      hipLaunchKernelGGL(k_route, dim3(s->n_cu * 2), dim3(256), 0, st, ra);
+      // enough workgroups for the round's live tuples (at most act_cap), up to 2 per CU
+      const int64_t live_bound = std::min<int64_t>(s->act_cap, n);
+      const int route_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * 2,
+                                                                          (live_bound + kRouteChunk - 1) / kRouteChunk));
+      hipLaunchKernelGGL(k_route, dim3(route_grid), dim3(kRouteThreads), 0, st, ra);
       if (timed && ev[1]) hipEventRecord(ev[1], st);
 
       // tier chain: first pass, [BF16 re-score of an FP8 first pass], [FP32 re-score of a
@@ -2175,7 +2307,7 @@ int hydro_compaction_debug(int32_t k, int64_t n, const uint32_t* pass_bits, int3
       ra.routing_batch = 64;
       ra.k = k;
       ra.q = Queues{q, st->qcount, block};
-      hipLaunchKernelGGL(k_route, dim3(n_cu * 2), dim3(256), 0, s, ra);
+      hipLaunchKernelGGL(k_route, dim3(n_cu * 2), dim3(kRouteThreads), 0, s, ra);
       if ((rc = mark(&b))) return rc;
       spans.push_back({{a, b}, 0});
       Forward f{};
@@ -2187,7 +2319,7 @@ int hydro_compaction_debug(int32_t k, int64_t n, const uint32_t* pass_bits, int3
       f.full_mask = (1u << k) - 1u;
       f.k_total = k;
       f.count_eval = 1;
-      hipLaunchKernelGGL(k_table_decide, dim3(n_cu * 4), dim3(256), 0, s, Queues{q, st->qcount, block}, k,
+      hipLaunchKernelGGL(k_table_decide, dim3(n_cu * 8), dim3(kRouteThreads), 0, s, Queues{q, st->qcount, block}, k,
                          pass_bits, row_words, f);
       if ((rc = mark(&a))) return rc;
       spans.push_back({{b, a}, 1});
