@@ -85,6 +85,7 @@ def parse():
                     help="MiB: first copy a device buffer of this size three times (a plain copy kernel "
                          "of known traffic, to scale hardware byte counters)")
     ap.add_argument("--no-compaction", action="store_true", help="skip the standalone routing/compaction run")
+    ap.add_argument("--no-reuse", action="store_true", help="skip the result-reuse (recurrent query) run")
     ap.add_argument("--compaction-only", action="store_true",
                     help="run only the standalone routing/compaction measurement and print its JSON")
     ap.add_argument("--compaction-log2n", type=int, default=26)
@@ -456,6 +457,62 @@ def compaction(args, hydro, torch):
                     "result materialisation), best of 3 runs; algorithmic bytes, 8 TB/s peak"}
 
 
+def reuse_leg(args, hydro, torch, hs):
+    """Result reuse on the 65,536-frame CNN workload (UC2's recurrent query, section 4.3): an
+    exploratory query (written order, most expensive predicate first) fills the session's result
+    cache on the middle half of the ids; the recurrent query then runs over all of them with cost
+    routing (static costs), once reuse-unaware (cached decisions used, ranking unchanged) and once
+    reuse-aware ((1 - hit rate) x cost per batch of 64).  The cache is cleared and refilled before
+    each timed recurrent query (untimed), which alone is timed."""
+    cfg = hs.workload(2)
+    n = cfg.n
+    frames_dev = make_device_frames(hs, torch, cfg, n)
+    pt = hs.load_predicates(cfg)
+    weights = [hs.make_model(d) for d in cfg.models]
+    specs = [hydro.ModelSpec.from_weights(w, m) for w, m in zip(weights, pt.class_masks)]
+    seg_len = cfg.n // cfg.n_seg
+    flops = np.array([d.flops() for d in cfg.models])
+    order = sorted(range(cfg.k), key=lambda j: -flops[j])
+    lo, hi = n // 4, 3 * n // 4
+    cal = torch.from_numpy(hs.calibration_frames(cfg)).cuda()
+    out, ids_ref = {}, None
+    for reuse in (1, 2):
+        pol = hydro.make_policy("cost", wave=args.wave, reuse=reuse, cost_source="static")
+        s = hydro.Session(specs, pol, cfg.hw, n)
+        s.calibrate(cal, cfg.dtype, args.safety)
+        s.set_order(order)
+        times, gf = [], []
+        for step in range(4):
+            s.cache_clear()
+            s.set_route("fixed")
+            s.reset()
+            s.push(frames_dev[lo:hi], cfg.dtype, pt.thresholds, seg_len, id_base=lo)
+            s.finish()
+            s.set_route("cost")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.reset()
+            s.push(frames_dev, cfg.dtype, pt.thresholds, seg_len)
+            ids, st = s.finish()
+            t1 = time.perf_counter()
+            if step > 0:                     # the first recurrent query is warm-up
+                times.append(t1 - t0)
+                gf.append(float(np.dot([x["evaluated"] for x in st], flops)) / 1e9)
+        s.close()
+        if ids_ref is None:
+            ids_ref = ids
+        assert np.array_equal(ids, ids_ref), "reuse-aware and reuse-unaware results differ"
+        out["reuse_aware" if reuse == 2 else "reuse_unaware"] = {
+            "value": n / float(np.median(times)), "unit": "tuples/s", "udf_gflop": float(np.mean(gf)),
+            "cache_hits": [int(x["cache_hits"]) for x in st], "evaluated": [int(x["evaluated"]) for x in st]}
+    out["speedup"] = out["reuse_aware"]["value"] / out["reuse_unaware"]["value"]
+    out["workload"] = {"name": cfg.name, "tuples": n, "cached_range": [lo, hi], "route": "cost (static)",
+                       "steps": 3, "note": "exploratory query (untimed) fills the cache before each recurrent query"}
+    del frames_dev, cal
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -486,6 +543,9 @@ def main():
         out["cnn3_drift64"] = {k: sec[k] for k in ("value", "ms_per_step", "steps", "eager_value", "roofline",
                                                     "plain", "speedup_vs_plain", "score", "n_result", "config")
                                if k in sec}
+    if not args.no_reuse:
+        log("[bench] result reuse (recurrent query)")
+        out["reuse"] = reuse_leg(args, hydro, torch, hs)
     if not args.no_compaction:
         log("[bench] standalone routing / compaction")
         out["compaction"] = compaction(args, hydro, torch)

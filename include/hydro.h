@@ -151,7 +151,21 @@ typedef struct {
   void* stream;                          /* hipStream_t to run on; NULL: the session's own       */
   float tau16;                           /* FP8 first pass: |d - theta| < tau16 of the BF16
                                             re-score goes on to FP32.  <= 0 (default): automatic */
-  int32_t pad_;
+  int32_t reuse;                         /* UDF result reuse (section 4.3, "Reuse-aware Routing"):
+                                            0 (default): none.  1: the session keeps a device
+                                            cache per predicate of every decision it takes (tuple
+                                            id -> pass/fail and the threshold it was decided
+                                            against), kept across its queries; a tuple reaching
+                                            a predicate whose cached decision still decides at the
+                                            tuple's threshold takes it from the cache instead of
+                                            being evaluated.  2: as 1, and routing is reuse-aware:
+                                            within every batch of 64 routed tuples the ranking
+                                            uses (1 - cache hit rate of the batch) x cost in place
+                                            of the cost (SCORE and COST; SEL and FIXED only use
+                                            the cache).  Not with LEARNED                          */
+  int32_t cache_log2;                    /* reuse > 0: log2 of the cache slots per predicate
+                                            (16 B each; 0: default 22, at most 28); a decision is
+                                            not cached when its 16 probe slots are taken          */
 } hydro_policy;
 
 /* Per-predicate statistics of one query. */
@@ -164,6 +178,8 @@ typedef struct {
   double cost_us_per_tuple;    /* final running cost estimate                                   */
   double selectivity;          /* passed / evaluated: conditional on the tuples it saw          */
   uint64_t rescored16;         /* FP8 first pass: BF16 decisions deferred to the FP32 pass      */
+  uint64_t cache_hits;         /* policy.reuse: decisions taken from the result cache (not
+                                  counted in evaluated / passed)                                */
 } hydro_pred_stats;
 
 /* Whole-query counters. */
@@ -315,6 +331,10 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
  * tau32: FP32 pass. */
 int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float* tau32);
 
+/* Empty the session's result cache (policy.reuse > 0); the next queries start without cached
+ * decisions.  ESTATE while a query is open or when the session keeps no cache. */
+int hydro_session_cache_clear(hydro_session* s);
+
 /* Debug: the learned router's current parameters (route = LEARNED), for evaluating its
  * predictions offline: W1 [192][64] | b1 [64] | W2 [64][8] | b2 [8] fp32 (12,872 values; output
  * j estimates the probability that predicate j rejects the tuple, as a logit; features: the frame
@@ -327,6 +347,12 @@ int hydro_session_router_params(const hydro_session* s, float* out, int32_t n);
  * conjunction evaluated left to right) for the session's next queries.  order: a permutation of
  * 0..K-1.  EINVAL if it is not one; ESTATE while a query is open. */
 int hydro_session_set_order(hydro_session* s, const int32_t* order);
+
+/* Replace the routing policy (FIXED, SEL, SCORE or COST) of the session's next queries, so that
+ * queries with different policies share one session and its result cache (section 4.3: earlier
+ * exploratory queries fill the cache that a recurrent query reuses).  EINVAL for an unknown
+ * route, EUNSUPPORTED for LEARNED or on a session created with it, ESTATE while a query is open. */
+int hydro_session_set_route(hydro_session* s, int32_t route);
 
 int hydro_session_destroy(hydro_session* s);
 

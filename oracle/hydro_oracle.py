@@ -27,6 +27,13 @@ function follows:
 * ``fixed_order_counts``: "No Reordering" evaluates the written order with
   short-circuit (section 4.1, "System Variants"); section 4.1 "System
   Variants" also computes selectivity from the count of filtered rows.
+* ``reuse_aware_cost`` / ``reuse_aware_order`` / ``cached_decision``:
+  section 4.3, "Reuse-aware Routing": cached UDF results are reused, and the
+  estimated cost of a predicate for a routing batch is (1 - cache hit rate)
+  times the cost of computing it (cache access taken as free).  A cached
+  decision taken at one threshold answers another threshold only where the
+  comparison is implied (this build's reading: its cache holds decisions, not
+  raw UDF outputs).
 * ``replay_route``: checks a per-tuple visit sequence against the routing
   rules of section 3.3 ("Metadata for Data Routing": a batch visits each
   predicate at most once and is complete when all are visited; "Eager
@@ -339,6 +346,31 @@ def policy_order(policy: str, cost, selectivity) -> List[int]:
     """Predicates sorted by ascending key; equal keys go to the lower index."""
     key = policy_keys(policy, cost, selectivity)
     return sorted(range(len(key)), key=lambda j: (key[j], j))
+
+
+def reuse_aware_cost(hit_rate, cost) -> np.ndarray:
+    """Estimated cost of each predicate for a routing batch: (1 - cache hit rate) * cost."""
+    return (1.0 - np.asarray(hit_rate, dtype=np.float64)) * np.asarray(cost, dtype=np.float64)
+
+
+def reuse_aware_order(policy: str, cost, selectivity, hit_rate) -> List[int]:
+    """The policy's order with the reuse-aware estimate in place of the cost (cost and score
+    policies; the selectivity policy does not use the cost)."""
+    return policy_order(policy, reuse_aware_cost(hit_rate, cost), selectivity)
+
+
+def cached_decision(theta_cached: float, passed_cached: bool, theta: float) -> Tuple[bool, bool]:
+    """(decided, pass) for a tuple whose margin d was found to satisfy d > theta_cached
+    (passed_cached) or d <= theta_cached (not passed_cached), now compared with theta.
+
+    d > theta_cached implies d > theta when theta <= theta_cached; d <= theta_cached implies
+    d <= theta when theta >= theta_cached.  Otherwise the cached outcome does not decide.
+    """
+    if passed_cached and theta <= theta_cached:
+        return True, True
+    if not passed_cached and theta >= theta_cached:
+        return True, False
+    return False, False
 
 
 # --------------------------------------------------------------------------

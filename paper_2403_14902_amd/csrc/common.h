@@ -83,6 +83,7 @@ struct DevState {
   unsigned long long ring_head;        // outcomes logged so far (ring index = head mod size)
   unsigned long long ring_trained;     // ring position the trainer has consumed up to
   int overflow;                        // set if a launch saw more evaluations than its buffers hold
+  unsigned long long r_hit[kMaxK], t_hit[kMaxK];   // decisions taken from the result cache
 };
 
 // Which arm a routing batch belongs to: 1 = learned router, 0 = score routing (control).
@@ -110,6 +111,58 @@ struct FrameSrc {
   int hw;               // frame side
   int64_t elems;        // elements per frame (hw*hw*3)
 };
+
+// Device result cache (section 4.3, "Reuse-aware Routing": results of earlier queries reused
+// instead of running the UDF).  One open-addressing table per predicate: keys[k << log2 | slot]
+// is a global tuple id (kCacheEmpty when free), vals the decision taken on it: the threshold it
+// was decided against (fp32 bits) and 1 for pass.  A decision "d > theta0 holds" also decides
+// d > theta for every theta <= theta0, and "fails" for every theta >= theta0, so an entry answers
+// exactly whenever the new threshold lies on the decided side; otherwise the tuple is evaluated.
+constexpr unsigned long long kCacheEmpty = ~0ull;
+constexpr int kCacheProbes = 16;
+struct ResultCache {
+  unsigned long long* keys;   // nullptr: no cache
+  uint2* vals;
+  uint32_t log2;
+};
+
+__device__ inline uint32_t cache_home(const ResultCache& c, unsigned long long id) {
+  return (uint32_t)((id * 0x9E3779B97F4A7C15ull) >> (64 - c.log2));
+}
+
+// 0: no decisive entry; 1: cached pass; 2: cached fail (at threshold theta).
+__device__ inline int cache_get(const ResultCache& c, int k, unsigned long long id, float theta) {
+  const uint32_t mask = (1u << c.log2) - 1u;
+  const uint32_t h = cache_home(c, id);
+  const size_t row = (size_t)k << c.log2;
+  for (int p = 0; p < kCacheProbes; ++p) {
+    const size_t s = row + ((h + p) & mask);
+    const unsigned long long key = c.keys[s];
+    if (key == kCacheEmpty) return 0;
+    if (key == id) {
+      const uint2 v = c.vals[s];
+      const float th = __uint_as_float(v.x);
+      if (v.y && theta <= th) return 1;
+      if (!v.y && theta >= th) return 2;
+      return 0;
+    }
+  }
+  return 0;
+}
+
+__device__ inline void cache_put(const ResultCache& c, int k, unsigned long long id, float theta, bool pass) {
+  const uint32_t mask = (1u << c.log2) - 1u;
+  const uint32_t h = cache_home(c, id);
+  const size_t row = (size_t)k << c.log2;
+  for (int p = 0; p < kCacheProbes; ++p) {
+    const size_t s = row + ((h + p) & mask);
+    const unsigned long long prev = atomicCAS(&c.keys[s], kCacheEmpty, id);
+    if (prev == kCacheEmpty || prev == id) {
+      c.vals[s] = make_uint2(__float_as_uint(theta), pass ? 1u : 0u);
+      return;
+    }
+  }
+}
 
 // Queues of one tier: entries[k * cap + i], i < counts[k].
 struct Queues {
@@ -140,6 +193,7 @@ struct Forward {
   int count_eval;            // 1 in the first pass (counts evaluated tuples)
   double* logits;            // if set: write fp64 logits [idx][10] instead of deciding
   OutcomeLog olog;
+  ResultCache cache;         // decisions are recorded here when cache.keys is set
 };
 
 __device__ inline float theta_of(const Forward& f, int k, uint32_t idx) {
@@ -223,6 +277,7 @@ __device__ inline void forward_decision(const Forward& f, int k, uint32_t e, boo
   bool ok = decided && pass;
   wave_add_u64(&f.st->r_pass[k], ok);
   uint32_t idx = entry_idx(e);
+  if (f.cache.keys != nullptr && decided) cache_put(f.cache, k, (unsigned long long)(f.id_base + idx), theta_of(f, k, idx), pass);
   uint32_t mask = entry_mask(e) | (1u << k);
   if (decided && f.route_log != nullptr) {
     int step = __popc(entry_mask(e));

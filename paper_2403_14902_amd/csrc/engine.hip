@@ -120,6 +120,8 @@ __global__ void k_fold(FoldArgs a) {
     st->t_rescored[k] += st->r_rescored[k];
     st->t_esc[k] += st->r_esc[k];
     st->t_mid[k] += st->r_mid[k];
+    st->t_hit[k] += st->r_hit[k];
+    st->r_hit[k] = 0;
     if (e > 0) {
       // running estimates; the +1/+2 prior keeps the selectivity off 0 and 1
       double s_obs = ((double)p + 1.0) / ((double)e + 2.0);
@@ -190,7 +192,69 @@ struct RouteArgs {
   const uint32_t* key_stamps;  // LEARNED: round in which each tuple's keys were computed
   OutcomeLog olog;             // LEARNED: arm assignment of routing batches
   int min_steps;               // LEARNED: optimiser steps before the learned arm uses the keys
+  Forward fw;                  // result reuse: cache, thresholds, result bits and route log
+  int route;                   // result reuse: the policy (for the per-batch ranking)
+  int reuse_aware;             // rank each batch of 64 by (1 - cache hit rate) x cost
 };
+
+// Result reuse (policy.reuse > 0): the tuple's cached decisions are looked up for its unvisited
+// predicates; the batch of 64 tuples routed together (one wave) is ranked with the reuse-aware
+// cost estimate of section 4.3, (1 - hit rate of the batch) x cost (SCORE and COST), else with
+// the round's ranking; the tuple then walks that ranking, taking cached decisions (a cached pass
+// marks the predicate visited, a cached fail drops the tuple) until it reaches a predicate without
+// one, whose queue it joins, or passes every predicate.  Returns the predicate (-1: finished) and
+// the entry with its visited mask updated; *cached gets the predicates decided from the cache.
+__device__ inline int route_with_cache(const RouteArgs& a, bool active, uint32_t* e, const int* order,
+                                       const double* sel, const double* cost, const int* seen, uint32_t* cached) {
+  const uint32_t idx = entry_idx(*e);
+  uint32_t m = entry_mask(*e);
+  uint32_t hit = 0, hpass = 0;
+  if (active)
+    for (int j = 0; j < a.k; ++j)
+      if (!((m >> j) & 1u)) {
+        const int r = cache_get(a.fw.cache, j, (unsigned long long)(a.fw.id_base + idx), theta_of(a.fw, j, idx));
+        hit |= (r != 0 ? 1u : 0u) << j;
+        hpass |= (r == 1 ? 1u : 0u) << j;
+      }
+  int ord[kMaxK];
+  if (a.reuse_aware) {
+    double key[kMaxK];
+    for (int j = 0; j < a.k; ++j) {
+      const int cand = __popcll(__ballot(active && !((m >> j) & 1u)));
+      const int h = __popcll(__ballot((hit >> j) & 1u));
+      const double rate = cand > 0 ? (double)h / (double)cand : 0.0;
+      const double est = (1.0 - rate) * cost[j];          // reuse-aware cost estimate
+      key[j] = !seen[j] ? -1.0 : a.route == HYDRO_ROUTE_COST ? est : est / (1.0 - sel[j]);
+    }
+    uint32_t used = 0;
+    for (int r = 0; r < a.k; ++r) {
+      int best = -1;
+      for (int j = 0; j < a.k; ++j)
+        if (!((used >> j) & 1u) && (best < 0 || key[j] < key[best])) best = j;
+      used |= 1u << best;
+      ord[r] = best;
+    }
+  } else {
+    for (int r = 0; r < a.k; ++r) ord[r] = order[r];
+  }
+  *cached = 0;
+  if (!active) return -1;
+  const int first = (a.warmup && m == 0) ? (int)((idx / (uint32_t)a.routing_batch) % (uint32_t)a.k) : -1;
+  for (int r = -1; r < a.k; ++r) {
+    const int j = r < 0 ? first : ord[r];
+    if (j < 0 || ((m >> j) & 1u)) continue;
+    if (!((hit >> j) & 1u)) {
+      *e = make_entry(idx, m);
+      return j;
+    }
+    *cached |= 1u << j;
+    if (a.fw.route_log != nullptr) a.fw.route_log[idx] |= (uint32_t)(j + 1) << (4 * __popc(m));
+    if (!((hpass >> j) & 1u)) return -1;                   // cached fail: dropped
+    m |= 1u << j;
+  }
+  atomicOr(&a.fw.result_bits[idx >> 5], 1u << (idx & 31));   // every predicate passed
+  return -1;
+}
 
 // The tuple belongs to the learned arm and the router is active (keys may still be missing).
 __device__ inline bool learned_eligible(const RouteArgs& a, uint32_t e) {
@@ -233,8 +297,19 @@ constexpr int kRouteThreads = 256, kRouteItems = 8, kRouteChunk = kRouteThreads 
 __global__ __launch_bounds__(kRouteThreads) void k_route(RouteArgs a) {
   __shared__ int order[kMaxK];
   __shared__ int wslot[kRouteThreads / kWave][kMaxK];   // per wave: entries, then first slot
-  if (threadIdx.x < a.k) order[threadIdx.x] = a.st->order[threadIdx.x];
+  __shared__ double sel_s[kMaxK], cost_s[kMaxK];
+  __shared__ int seen_s[kMaxK];
+  if (threadIdx.x < a.k) {
+    order[threadIdx.x] = a.st->order[threadIdx.x];
+    sel_s[threadIdx.x] = a.st->sel_est[threadIdx.x];
+    cost_s[threadIdx.x] = a.st->cost_est[threadIdx.x];
+    seen_s[threadIdx.x] = a.st->seen[threadIdx.x];
+  }
   __syncthreads();
+  const bool reuse = a.fw.cache.keys != nullptr;
+  unsigned long long hits[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) hits[j] = 0;
   const int n_in = a.st->pend_count[a.in_slot];
   const int64_t total = n_in + (int64_t)(a.adm_hi - a.adm_lo);
   const int wv = threadIdx.x / kWave, lane = lane_id();
@@ -248,6 +323,14 @@ __global__ __launch_bounds__(kRouteThreads) void k_route(RouteArgs a) {
       const int64_t i = base + r * kRouteThreads + threadIdx.x;
       e[r] = 0u;
       kk[r] = -1;
+      if (reuse) {
+        if (i < total) e[r] = i < n_in ? a.pend_in[i] : make_entry(a.adm_lo + (uint32_t)(i - n_in), 0u);
+        uint32_t cached;
+        kk[r] = route_with_cache(a, i < total, &e[r], order, sel_s, cost_s, seen_s, &cached);
+#pragma unroll
+        for (int j = 0; j < kMaxK; ++j) hits[j] += __popcll(__ballot((cached >> j) & 1u));
+        continue;
+      }
       if (i < total) {
         e[r] = i < n_in ? a.pend_in[i] : make_entry(a.adm_lo + (uint32_t)(i - n_in), 0u);
         kk[r] = choose_pred(a, e[r], order);
@@ -292,6 +375,9 @@ __global__ __launch_bounds__(kRouteThreads) void k_route(RouteArgs a) {
       if (kk[r] >= 0) a.q.entries[(int64_t)kk[r] * a.q.cap + wslot[wv][kk[r]] + off[r]] = e[r];
     __syncthreads();   // wslot is rewritten by the next chunk
   }
+  if (reuse && lane_id() == 0)
+    for (int j = 0; j < a.k; ++j)
+      if (hits[j]) atomicAdd(&a.st->r_hit[j], hits[j]);
   if (a.learned_keys != nullptr) {
     unsigned long long c[3] = {n_learned, n_stats, n_stale};
 #pragma unroll
@@ -569,6 +655,7 @@ struct hydro_session {
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_used = 0;
   int64_t act_cap = 0;   // entries of the layer-wise CNN activation buffers (evaluations per launch)
+  ResultCache cache{};   // policy.reuse > 0: decisions kept across the session's queries
 };
 
 // Captured pushes bake the bands (and every other launch argument) into their kernel nodes.
@@ -1066,6 +1153,10 @@ static int validate_policy(const hydro_policy* p, int K) {
     return fail(HYDRO_EUNSUPPORTED, "precision not supported");
   if (p->cost_source != HYDRO_COST_MEASURED && p->cost_source != HYDRO_COST_STATIC) return fail(HYDRO_EINVAL, "unknown cost_source");
   if (p->explore < 0.f || p->explore > 1.f) return fail(HYDRO_EINVAL, "explore must be in [0, 1]");
+  if (p->reuse < 0 || p->reuse > 2) return fail(HYDRO_EINVAL, "reuse must be 0, 1 or 2");
+  if (p->reuse && p->route == HYDRO_ROUTE_LEARNED)
+    return fail(HYDRO_EUNSUPPORTED, "result reuse is not combined with the learned router");
+  if (p->cache_log2 < 0 || p->cache_log2 > 28) return fail(HYDRO_EINVAL, "cache_log2 must be in 0 .. 28");
   return HYDRO_OK;
 }
 
@@ -1192,6 +1283,15 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
   }
   if ((rc = sess_alloc(s, (void**)&s->theta, 4096 * sizeof(float)))) return bail(rc);
   s->theta_cap = 4096;
+  if (s->pol.reuse) {
+    if (s->arena) return bail(fail(HYDRO_EUNSUPPORTED, "allocation-free queries keep no result cache"));
+    s->cache.log2 = s->pol.cache_log2 > 0 ? (uint32_t)s->pol.cache_log2 : 22u;
+    const size_t slots = (size_t)k << s->cache.log2;
+    if ((rc = sess_alloc(s, (void**)&s->cache.keys, slots * sizeof(unsigned long long)))) return bail(rc);
+    if ((rc = sess_alloc(s, (void**)&s->cache.vals, slots * sizeof(uint2)))) return bail(rc);
+    he = hipMemset(s->cache.keys, 0xFF, slots * sizeof(unsigned long long));   // every slot kCacheEmpty
+    if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipMemset(cache): ") + hipGetErrorString(he)));
+  }
   if (s->arena) {
     if ((rc = sess_alloc(s, (void**)&s->out_ids, cap * sizeof(int64_t)))) return bail(rc);
   } else {
@@ -1265,6 +1365,7 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
   f.k_total = s->K;
   f.logits = nullptr;
   f.olog = s->rnn ? router_nn_log(s->rnn) : OutcomeLog{};
+  f.cache = s->cache;
   const bool bf = s->pol.precision == HYDRO_PREC_BF16;
   const bool f8 = s->pol.precision == HYDRO_PREC_FP8;
   if (tier == TIER_FIRST && f8) {
@@ -1721,6 +1822,11 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       ra.routing_batch = s->pol.routing_batch;
       ra.k = s->K;
       ra.q = Queues{s->q1, s->st->qcount, s->cap};
+      if (s->cache.keys) {
+        ra.fw = make_forward(s, TIER_FIRST, out_slot, src, n_seg, seg_len, fr.id_base);
+        ra.route = s->pol.route;
+        ra.reuse_aware = s->pol.reuse == 2 && (s->pol.route == HYDRO_ROUTE_SCORE || s->pol.route == HYDRO_ROUTE_COST);
+      }
       ra.learned_keys = s->rnn ? router_nn_keys_ptr(s->rnn) : nullptr;
       ra.key_stamps = s->rnn ? router_nn_stamps_ptr(s->rnn) : nullptr;
       if (s->rnn) {
@@ -1883,6 +1989,7 @@ static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int
       o.rescored = h.t_rescored[k];
       o.escalated = h.t_esc[k];
       o.rescored16 = h.t_mid[k];
+      o.cache_hits = h.t_hit[k];
       o.device_us = (double)h.t_ticks[k] * s->tick_us;
       o.cost_us_per_tuple = s->pol.cost_source == HYDRO_COST_STATIC ? h.cost_est[k] : h.cost_est[k] * s->tick_us;
       o.selectivity = h.t_eval[k] ? (double)h.t_pass[k] / (double)h.t_eval[k] : 0.0;
@@ -1965,6 +2072,7 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   FrameSrc src{fr.data, fr.dtype, fr.h, (int64_t)fr.h * fr.w * 3};
   Forward f = make_forward(s, t, 0, src, 1, 1, 0);
   f.logits = dlog;
+  f.cache = ResultCache{};
   f.defer = Queues{nullptr, nullptr, 0};
   hipError_t he = hipSuccess;
   for (int64_t i0 = 0; i0 < fr.n && he == hipSuccess; i0 += chunk) {
@@ -2136,6 +2244,16 @@ int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float*
   return HYDRO_OK;
 }
 
+int hydro_session_cache_clear(hydro_session* s) {
+  g_err.clear();
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  if (!s->cache.keys) return fail(HYDRO_ESTATE, "the session keeps no result cache (policy.reuse = 0)");
+  if (s->in_query) return fail(HYDRO_ESTATE, "a query is open (push without finish)");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemset(s->cache.keys, 0xFF, ((size_t)s->K << s->cache.log2) * sizeof(unsigned long long)));
+  return HYDRO_OK;
+}
+
 int hydro_session_router_params(const hydro_session* s, float* out, int32_t n) {
   g_err.clear();
   if (!s || !out) return fail(HYDRO_EINVAL, "session or out is NULL");
@@ -2158,6 +2276,19 @@ int hydro_session_set_order(hydro_session* s, const int32_t* order) {
   }
   for (int i = 0; i < s->K; ++i) s->pol.order[i] = order[i];
   drop_graphs(s);   // the order is a launch argument of the captured fold kernels
+  return HYDRO_OK;
+}
+
+int hydro_session_set_route(hydro_session* s, int32_t route) {
+  g_err.clear();
+  if (!s) return fail(HYDRO_EINVAL, "session is NULL");
+  if (s->in_query) return fail(HYDRO_ESTATE, "a query is in progress: change the route between queries");
+  if (route < HYDRO_ROUTE_FIXED || route > HYDRO_ROUTE_COST)
+    return fail(route == HYDRO_ROUTE_LEARNED ? HYDRO_EUNSUPPORTED : HYDRO_EINVAL,
+                "route must be FIXED, SEL, SCORE or COST (the learned router is chosen at session creation)");
+  if (s->pol.route == HYDRO_ROUTE_LEARNED) return fail(HYDRO_EUNSUPPORTED, "a learned-router session keeps its route");
+  s->pol.route = route;
+  drop_graphs(s);   // the route is a launch argument of the captured fold and route kernels
   return HYDRO_OK;
 }
 

@@ -61,13 +61,13 @@ class Policy(C.Structure):
                 ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
                 ("time_kernels", C.c_int32), ("autotune", C.c_int32),
                 ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p), ("tau16", C.c_float),
-                ("pad_", C.c_int32)]
+                ("reuse", C.c_int32), ("cache_log2", C.c_int32)]
 
 
 class PredStats(C.Structure):
     _fields_ = [("evaluated", C.c_uint64), ("passed", C.c_uint64), ("rescored", C.c_uint64),
                 ("escalated", C.c_uint64), ("device_us", C.c_double), ("cost_us_per_tuple", C.c_double),
-                ("selectivity", C.c_double), ("rescored16", C.c_uint64)]
+                ("selectivity", C.c_double), ("rescored16", C.c_uint64), ("cache_hits", C.c_uint64)]
 
 
 class QueryInfo(C.Structure):
@@ -119,6 +119,8 @@ def lib():
         L.hydro_session_calibrate.argtypes = [vp, C.POINTER(Frames), C.c_float, FP, FP]
         L.hydro_session_bands.argtypes = [vp, FP, FP, FP]
         L.hydro_session_router_params.argtypes = [vp, FP, i32]
+        L.hydro_session_cache_clear.argtypes = [vp]
+        L.hydro_session_set_route.argtypes = [vp, i32]
         L.hydro_session_destroy.argtypes = [vp]
         L.hydro_free.argtypes = [vp]
         L.hydro_free.restype = None
@@ -129,7 +131,7 @@ def lib():
                      "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
                      "hydro_compaction_debug", "hydro_session_logits",
                      "hydro_session_calibrate", "hydro_session_bands", "hydro_session_router_params",
-                     "hydro_session_destroy"):
+                     "hydro_session_cache_clear", "hydro_session_set_route", "hydro_session_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -139,7 +141,8 @@ EXPORTED = ("hydro_policy_default", "hydro_query", "hydro_query_noalloc", "hydro
             "hydro_session_push", "hydro_session_finish", "hydro_session_info", "hydro_session_routes",
             "hydro_session_round_log", "hydro_session_set_order", "hydro_router_train_debug",
             "hydro_compaction_debug", "hydro_session_logits", "hydro_session_calibrate", "hydro_session_bands",
-            "hydro_session_router_params", "hydro_session_destroy",
+            "hydro_session_router_params", "hydro_session_cache_clear", "hydro_session_set_route",
+            "hydro_session_destroy",
             "hydro_free",
             "hydro_last_error", "hydro_version")
 
@@ -279,6 +282,10 @@ class Session:
         out["arm_flops"], out["arm_tuples"] = list(q.arm_flops), list(q.arm_tuples)
         return out
 
+    def cache_clear(self):
+        """Drop every cached decision (policy.reuse > 0)."""
+        _check(lib().hydro_session_cache_clear(self._h))
+
     def router_params(self) -> np.ndarray:
         """The learned router's parameters W1 | b1 | W2 | b2 (see hydro_session_router_params)."""
         p = np.zeros(ROUTER_NPARAM, dtype=np.float32)
@@ -294,6 +301,10 @@ class Session:
         """The FIXED route's order for the next queries."""
         o = (C.c_int32 * MAX_PREDICATES)(*[int(x) for x in order])
         _check(lib().hydro_session_set_order(self._h, o))
+
+    def set_route(self, route: str):
+        """The routing policy of the next queries (fixed, selectivity, score or cost)."""
+        _check(lib().hydro_session_set_route(self._h, ROUTES[route] if isinstance(route, str) else int(route)))
 
     def round_log(self, first: int, n: int) -> List[Dict]:
         """Per-round rankings and folded statistics of the last query (policy.log_routes = 1)."""

@@ -429,3 +429,40 @@ def test_bounds_ordered_on_random_tables():
         for order in itertools.permutations(range(k)):
             ev, _ = ho.fixed_order_counts(P, order)
             assert best <= float(np.dot(ev, f)) + 1e-9
+
+
+def test_reuse_aware_cost_closed_forms():
+    """(1 - hit rate) * cost: a fully cached predicate costs nothing, an uncached one its full
+    cost, and the estimate is linear in between (section 4.3)."""
+    c = np.array([35.11, 1.98, 7.0])
+    assert np.array_equal(ho.reuse_aware_cost([0.0, 0.0, 0.0], c), c)
+    assert np.array_equal(ho.reuse_aware_cost([1.0, 1.0, 1.0], c), np.zeros(3))
+    assert np.allclose(ho.reuse_aware_cost([0.25, 0.5, 0.75], c), [0.75 * 35.11, 0.5 * 1.98, 0.25 * 7.0], rtol=0, atol=1e-15)
+
+
+def test_reuse_aware_order_prefers_cached_expensive_predicate():
+    """The paper's UC2 situation: an expensive detector whose results are cached for the batch goes
+    before a cheaper uncached one; without cache hits the cheaper one goes first."""
+    cost, sel = [35.11, 1.98], [0.254, 0.633]
+    assert ho.reuse_aware_order(ho.POLICY_COST, cost, sel, [0.0, 0.0]) == [1, 0]
+    assert ho.reuse_aware_order(ho.POLICY_COST, cost, sel, [1.0, 0.0]) == [0, 1]
+    assert ho.reuse_aware_order(ho.POLICY_SCORE, cost, sel, [0.0, 0.0]) == [1, 0]
+    assert ho.reuse_aware_order(ho.POLICY_SCORE, cost, sel, [0.99, 0.0]) == [0, 1]
+    # the selectivity policy ignores costs, hence the cache
+    assert ho.reuse_aware_order(ho.POLICY_SEL, cost, sel, [0.0, 1.0]) == [0, 1]
+
+
+def test_cached_decision_brute_force():
+    """A cached outcome decides a new threshold exactly when every margin consistent with it gives
+    the same decision there (brute force over a grid of margins)."""
+    grid = np.linspace(-2.0, 2.0, 401)
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        tc, t = (float(x) for x in rng.choice(grid[50:-50], 2))
+        for passed in (True, False):
+            consistent = grid[grid > tc] if passed else grid[grid <= tc]
+            outs = set(bool(d > t) for d in consistent)
+            decided, p = ho.cached_decision(tc, passed, t)
+            assert decided == (len(outs) == 1), (tc, passed, t)
+            if decided:
+                assert {p} == outs
