@@ -32,7 +32,11 @@ Forms:
 
 Prints one JSON line (the full form's throughput as `value`, the plain form beside it, the
 dominant kernels' roofline from HIP events recorded by the library on its stream, and the FP64
-oracle timed on the host cores on a bounded sample whose ids are also checked).
+oracle timed on the host cores on a bounded sample whose ids are also checked).  Two more
+objects: `reuse` (the 65,536-frame workload's recurrent query after an exploratory one filled
+the result cache, with and without reuse-aware routing; --no-reuse skips it) and `compaction`
+(routing, multi-split, forwarding and result materialisation on 2^26 tuples with given outcomes,
+against their algorithmic bytes; --no-compaction skips it, --compaction-only runs only it).
 """
 import argparse
 import json
