@@ -507,19 +507,6 @@ __host__ __device__ inline int c4_nkb(int prec, int layer) {
   return (9 * cin + bke - 1) / bke;
 }
 
-// 16 bytes per lane from global memory straight into LDS (lane i at lds_off + 16 i), issued as
-// one instruction per wave.  The asynchronous write is tracked by vmcnt; the caller waits for it
-// explicitly (the compiler does not see this LDS write, so it adds no waits of its own).
-__device__ inline void c4_dma16(const void* src, uint32_t lds_off) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds_off)
-               : "memory", "m0");
-}
-// s_waitcnt vmcnt(N) (other counters not waited for)
-template <int N>
-__device__ inline void c4_wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
 
 template <int P, int LAYER>
 __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
@@ -616,7 +603,7 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
           const bool ok = tap < 9 && y >= 0 && x >= 0 && y < HIN && x < HIN;
           src = ok ? static_cast<const void*>(bsrc[i - NIA] + (y * HIN + x) * CIN + ch) : a.zero_page;
         }
-        c4_dma16(src, __builtin_amdgcn_readfirstlane(base + q * 1024));
+        lds_dma16(src, __builtin_amdgcn_readfirstlane(base + q * 1024));
       }
     };
 
@@ -703,9 +690,9 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
 #pragma unroll 1
     for (int kb = 0; kb < NKB; ++kb) {
       const int ahead = min(NS - 2, NKB - 1 - kb);
-      if (ahead >= 2) c4_wait_vm<2 * NI>();
-      else if (ahead == 1) c4_wait_vm<NI>();
-      else c4_wait_vm<0>();
+      if (ahead >= 2) wait_vmcnt<2 * NI>();
+      else if (ahead == 1) wait_vmcnt<NI>();
+      else wait_vmcnt<0>();
       __syncthreads();
       if (kb + NS - 1 < NKB) issue(kb + NS - 1, (kb + NS - 1) % NS);
       compute(kb % NS);

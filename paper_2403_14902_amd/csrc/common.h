@@ -234,6 +234,21 @@ __device__ inline void wave_sum_n(float (&v)[N]) {
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// 16 bytes per lane from global memory straight into LDS (lane i at lds_off + 16 i), issued as
+// one instruction per wave.  The asynchronous write is tracked by vmcnt; the caller waits for it
+// explicitly with wait_vmcnt (the compiler does not see this LDS write, so it adds no waits of
+// its own).  lds_off must be wave-uniform.
+__device__ inline void lds_dma16(const void* src, uint32_t lds_off) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds_off)
+               : "memory", "m0");
+}
+// s_waitcnt vmcnt(N) (other counters not waited for)
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 // Wave-aggregated append: every active lane with `want` set gets a unique slot in *counter.
 __device__ inline int wave_append(int* counter, bool want) {
   unsigned long long m = __ballot(want);

@@ -550,6 +550,199 @@ __global__ __launch_bounds__(256) void mlp_f64_rest_kernel(MlpArgs a, Forward f)
 // Tile configurations: 0 = 128x128, 1 = 64x128, 2 = 128x64, 3 = 64x64 (rows x hidden units).
 int mlp_tile_bn(int cfg) { return cfg == 0 || cfg == 1 ? 128 : 64; }
 
+// BF16 first pass on bf16 frames (d_in a multiple of 64): 256 queued rows x 128 hidden units per
+// tile, eight waves of 64 x 64.  Each k-block (64 elements: 128 bytes of every frame row and
+// weight row) is copied global -> LDS with global_load_lds_dwordx4 into a three-stage ring, one
+// barrier per k-block; the 16-byte chunks of row r sit at slot chunk ^ (r mod 8), so the MFMA
+// operand reads of 16 rows spread over the banks.  Split-K and the epilogue as in
+// mlp_gemm_kernel (workspace tiles of 256 x 128: the launch passes half the 128 x 128 slots).
+constexpr int MD_BM = 256, MD_BN = 128, MD_NS = 3;
+__global__ __launch_bounds__(512) void mlp_gemm_dma_kernel(MlpArgs a) {
+  constexpr int UPR = 8, ROWB = 128, BKE = 64;             // 16-byte units per row, bytes, elements
+  constexpr int UNITS = (MD_BM + MD_BN) * UPR;
+  constexpr int NI = UNITS / 512, NIF = MD_BM * UPR / 512; // loads per wave and stage (frames first)
+  constexpr int STAGE = UNITS * 16;
+  constexpr int WM = 64, WN = 64, MT = WM / 16, NT = WN / 16;
+  static_assert(UNITS % 512 == 0 && (MD_BM * UPR) % 512 == 0, "stage rows fill the waves' loads");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[MD_NS * STAGE];
+  __shared__ int s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave & 3, wn = wave >> 2;
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds);
+  const int u_slot = lane % UPR;
+
+  int base_total = 0, nk_min = 1 << 30;
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int cnt = a.q.counts[a.pred[i]];
+    base_total += ((cnt + MD_BM - 1) / MD_BM) * (a.hidden[i] / MD_BN);
+    nk_min = min(nk_min, a.d_in[i] / BKE);
+  }
+  const int S = mlp_splits(base_total, nk_min, a);
+  const int total = base_total * S;
+
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int tb = t / S, sp = t % S;
+    int slot = 0, mt = 0, nt = 0;
+    {
+      int acc0 = 0;
+      for (int i = 0; i < a.n_preds; ++i) {
+        const int cnt = a.q.counts[a.pred[i]];
+        const int n_nt = a.hidden[i] / MD_BN;
+        const int tiles = ((cnt + MD_BM - 1) / MD_BM) * n_nt;
+        if (tb < acc0 + tiles) {
+          slot = i;
+          mt = (tb - acc0) / n_nt;
+          nt = (tb - acc0) % n_nt;
+          break;
+        }
+        acc0 += tiles;
+      }
+    }
+    const int k = a.pred[slot];
+    const int cnt = a.q.counts[k];
+    const int D = a.d_in[slot];
+    const uint32_t* qe = a.q.entries + (int64_t)k * a.q.cap;
+    const unsigned long long t0 = wall_clock64();
+
+    // the rows this lane copies: gathered frame rows (rows past the queue re-read its last entry;
+    // their results are never stored), then weight rows; element offset of the lane's chunk
+    const __bf16* src[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int U = (wave + 8 * i) * 64 + lane;
+      if (i < NIF) {
+        const int r = U / UPR;
+        const int row = mt * MD_BM + r;
+        const uint32_t idx = entry_idx(qe[row < cnt ? row : cnt - 1]);
+        src[i] = static_cast<const __bf16*>(a.fr.base) + (int64_t)idx * a.fr.elems + (u_slot ^ (r & 7)) * 8;
+      } else {
+        const int r = U / UPR - MD_BM;
+        src[i] = a.w1_bf[slot] + (int64_t)(nt * MD_BN + r) * D + (u_slot ^ (r & 7)) * 8;
+      }
+    }
+    auto issue = [&](int kb, int buf) {
+      const uint32_t base = lds0 + buf * STAGE;
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+        lds_dma16(src[i] + (int64_t)kb * BKE, __builtin_amdgcn_readfirstlane(base + (wave + 8 * i) * 1024));
+    };
+
+    floatx4 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](int buf) {
+      const unsigned char* F = lds + buf * STAGE;
+      const unsigned char* W = F + MD_BM * ROWB;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {      // k-step ks reads chunk 4 ks + g of each row
+        bf16x8 af[MT], bfr[NT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          const int r = wm * WM + i * 16 + l16;
+          af[i] = *reinterpret_cast<const bf16x8*>(F + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int r = wn * WN + j * 16 + l16;
+          bfr[j] = *reinterpret_cast<const bf16x8*>(W + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
+        }
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      }
+    };
+
+    const int nk_all = D / BKE;
+    const int kt0 = (int)((int64_t)nk_all * sp / S), kt1 = (int)((int64_t)nk_all * (sp + 1) / S);
+    const int nkb = kt1 - kt0;
+    // (the previous tile's last barrier ordered every read of the ring)
+#pragma unroll
+    for (int s0 = 0; s0 < MD_NS - 1; ++s0)
+      if (s0 < nkb) issue(kt0 + s0, s0);
+#pragma unroll 1
+    for (int kb = 0; kb < nkb; ++kb) {
+      const int ahead = min(MD_NS - 2, nkb - 1 - kb);
+      if (ahead >= 1) wait_vmcnt<NI>();
+      else wait_vmcnt<0>();
+      __syncthreads();
+      if (kb + MD_NS - 1 < nkb) issue(kt0 + kb + MD_NS - 1, (kb + MD_NS - 1) % MD_NS);
+      compute(kb % MD_NS);
+    }
+
+    if (S > 1) {
+      // raw sums of this K range: ws[tb][sp][column in tile][row in tile]
+      float* wt = a.splitk_ws + (int64_t)tb * S * (MD_BM * MD_BN);
+      auto at = [&](int q, int i, int j) -> float4* {
+        return reinterpret_cast<float4*>(
+            &wt[(int64_t)q * (MD_BM * MD_BN) + (wn * WN + j * 16 + l16) * MD_BM + wm * WM + i * 16 + 4 * g]);
+      };
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) *at(sp, i, j) = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_last = atomicAdd(&a.split_cnt[tb], 1) == S - 1;
+      __syncthreads();
+      if (!s_last) {
+        if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
+        continue;
+      }
+      __threadfence();
+      if (tid == 0) a.split_cnt[tb] = 0;      // ready for the next launch
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          floatx4 sum = (floatx4){0.f, 0.f, 0.f, 0.f};
+          for (int q = 0; q < S; ++q) {
+            float4 v;
+            if (q == sp) v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+            else v = *at(q, i, j);
+            sum[0] += v.x; sum[1] += v.y; sum[2] += v.z; sum[3] += v.w;
+          }
+          acc[i][j] = sum;
+        }
+    }
+    // epilogue: H = ReLU(acc + b1'), partial logits over this wave's 64 hidden columns
+    const float* b1 = a.b1_fold[slot];
+    const float* w2 = a.w2[slot];
+    const int col0 = nt * MD_BN + wn * WN + l16;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const float bb = b1[col0 + j * 16];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = fmaxf(acc[i][j][r] + bb, 0.f);
+    }
+    float* part = a.partial[slot] + ((int64_t)(nt * 2 + wn) * a.part_cap) * kClasses;
+    for (int c = 0; c < kClasses; ++c) {
+      float w2v[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) w2v[j] = w2[(col0 + j * 16) * kClasses + c];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float sacc = 0.f;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) sacc += acc[i][j][r] * w2v[j];
+          sacc = row_sum16(sacc);
+          const int rr = mt * MD_BM + wm * WM + i * 16 + 4 * g + r;
+          if (l16 == 0 && rr < cnt) part[(int64_t)rr * kClasses + c] = sacc;
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
+  }
+}
+
 template <typename T, int BM, int BN>
 static void launch_gemm_t(const MlpArgs& b, int grid, hipStream_t s) {
   if (b.fr.dtype == HYDRO_DTYPE_BF16)
@@ -561,7 +754,13 @@ static void launch_gemm_t(const MlpArgs& b, int grid, hipStream_t s) {
 }
 
 void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s) {
-  if (bf) {
+  bool dma = bf && b.fr.dtype == HYDRO_DTYPE_BF16 && (cfg == 0 || cfg == 1);
+  for (int i = 0; i < b.n_preds && dma; ++i) dma = b.d_in[i] % 64 == 0 && b.hidden[i] % MD_BN == 0;
+  if (dma) {
+    MlpArgs c = b;
+    c.split_slots = b.split_slots / 2;     // workspace tiles of 256 x 128
+    hipLaunchKernelGGL(mlp_gemm_dma_kernel, dim3(grid), dim3(512), 0, s, c);
+  } else if (bf) {
     if (cfg == 0) launch_gemm_t<__bf16, 128, 128>(b, grid, s);
     else if (cfg == 1) launch_gemm_t<__bf16, 64, 128>(b, grid, s);
     else if (cfg == 2) launch_gemm_t<__bf16, 128, 64>(b, grid, s);
