@@ -18,6 +18,8 @@ struct MlpArgs {
   uint32_t class_mask[kMaxK];
   const __bf16* w1_bf[kMaxK];       // [hidden][d_in], folded
   const float* w1_f32[kMaxK];       // [hidden][d_in], folded
+  const __bf16* w1_s3[kMaxK];       // bf16 frames: w1_f32 as three bf16 terms [3][hidden][d_in]
+                                    // (hi, mid, lo; nullptr where not built)
   const float* b1_fold[kMaxK];
   const float* w2[kMaxK];           // [hidden][10]
   const float* b2[kMaxK];
@@ -141,6 +143,8 @@ int mlp_f64_chunks(int d_in);    // input chunks of the FP64 MLP hidden pass
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s);
 int mlp_tile_bn(int cfg);
+// Copy every per-predicate field of slot i of src into slot j of dst.
+void mlp_copy_slot(MlpArgs& dst, int j, const MlpArgs& src, int i);
 void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hipStream_t s);
 size_t cnn_packed_elems(int variant, int layer, int prec);
 void cnn_pack_layer(int variant, int layer, int prec, const float* w_canon, float scale, float* out);

@@ -707,6 +707,13 @@ static uint16_t f32_to_bf16_bits(float f) {
   return (uint16_t)(u >> 16);
 }
 
+static float bf16_bits_to_f32(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
 static double model_flops(const hydro_model& m) {
   if (m.arch == HYDRO_ARCH_MLP) {
     double d = (double)m.in_h * m.in_w * 3;
@@ -856,6 +863,24 @@ static int pack_models(hydro_session* s) {
       ma.w1_f32[i] = dp;
       if ((rc = upload(s, wb.data(), wb.size(), &bp))) return rc;
       ma.w1_bf[i] = reinterpret_cast<const __bf16*>(bp);
+      ma.w1_s3[i] = nullptr;
+      if (s->fdtype == HYDRO_DTYPE_BF16 && D % 64 == 0 && H % 128 == 0 && !s->arena) {
+        // FP32 arithmetic on bf16 frames from three bf16 weight terms (see mlp_gemm_s3_kernel):
+        // hi = bf16(w), mid = bf16(w - hi), lo = bf16(w - hi - mid), each difference exact in fp32
+        std::vector<uint16_t> w3((size_t)3 * H * D);
+        for (size_t q = 0; q < (size_t)H * D; ++q) {
+          const float v = wt[q];
+          const uint16_t hi = f32_to_bf16_bits(v);
+          const float r1 = v - bf16_bits_to_f32(hi);
+          const uint16_t mid = f32_to_bf16_bits(r1);
+          const float r2 = r1 - bf16_bits_to_f32(mid);
+          w3[q] = hi;
+          w3[(size_t)H * D + q] = mid;
+          w3[(size_t)2 * H * D + q] = f32_to_bf16_bits(r2);
+        }
+        if ((rc = upload(s, w3.data(), w3.size(), &bp))) return rc;
+        ma.w1_s3[i] = reinterpret_cast<const __bf16*>(bp);
+      }
       if ((rc = upload(s, b1f.data(), b1f.size(), &dp))) return rc;
       ma.b1_fold[i] = dp;
       if ((rc = upload(s, hm.w2.data(), hm.w2.size(), &dp))) return rc;
@@ -1421,10 +1446,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
       for (int i = 0; i < s->mlp.n_preds; ++i) {
         MlpArgs b = a;
         b.n_preds = 1;
-        b.pred[0] = a.pred[i]; b.d_in[0] = a.d_in[i]; b.hidden[0] = a.hidden[i]; b.class_mask[0] = a.class_mask[i];
-        b.w1_bf[0] = a.w1_bf[i]; b.w1_f32[0] = a.w1_f32[i]; b.b1_fold[0] = a.b1_fold[i]; b.w2[0] = a.w2[i];
-        b.b2[0] = a.b2[i]; b.w1_canon[0] = a.w1_canon[i]; b.b1_canon[0] = a.b1_canon[i]; b.partial[0] = a.partial[i];
-        b.esc_h[0] = a.esc_h[i]; b.tile_cfg[0] = a.tile_cfg[i]; b.part_w[0] = a.part_w[i];
+        mlp_copy_slot(b, 0, a, i);      // every per-slot field (a partial copy mixes predicates)
         launch_mlp_pass(b, f, tier, grid, st);
       }
     }
@@ -1568,9 +1590,7 @@ static int autotune_mlp(hydro_session* s) {
       HIP_TRY(hipMemcpy(s->st->qcount, cnt, sizeof(cnt), hipMemcpyHostToDevice));
       MlpArgs b = ma;
       b.n_preds = 1;
-      b.pred[0] = ma.pred[i]; b.d_in[0] = ma.d_in[i]; b.hidden[0] = ma.hidden[i]; b.class_mask[0] = ma.class_mask[i];
-      b.w1_bf[0] = ma.w1_bf[i]; b.w1_f32[0] = ma.w1_f32[i]; b.b1_fold[0] = ma.b1_fold[i]; b.w2[0] = ma.w2[i];
-      b.b2[0] = ma.b2[i]; b.partial[0] = ma.partial[i];
+      mlp_copy_slot(b, 0, ma, i);
       b.q = Queues{s->q1, s->st->qcount, s->cap};
       b.fr = FrameSrc{frames, s->fdtype, s->fh, (int64_t)D};
       b.st = s->st;

@@ -743,6 +743,199 @@ __global__ __launch_bounds__(512) void mlp_gemm_dma_kernel(MlpArgs a) {
   }
 }
 
+// FP32 arithmetic on bf16 frames (the FP32 tier, and an FP32 first pass): every fp32 weight w is
+// split into three bf16 terms w = hi + mid + lo (each the bf16 rounding of what is left; three
+// terms carry all 24 bits of the fp32 significand), so x * w = x * hi + x * mid + x * lo with
+// every product exact (a bf16 x bf16 product fits fp32) and fp32 accumulation: the fp32 GEMM's
+// result up to summation order, from three bf16 MFMAs instead of eight fp32 ones (16x16x32 bf16
+// against 16x16x4 fp32).  128 x 128 tiles, four waves of 64 x 64, k-blocks of 64 elements (the
+// frame rows, then the hi, mid and lo weight rows) in a two-stage direct-to-LDS ring.
+constexpr int M3_BM = 128, M3_BN = 128, M3_NS = 2;
+__global__ __launch_bounds__(256) void mlp_gemm_s3_kernel(MlpArgs a) {
+  constexpr int UPR = 8, ROWB = 128, BKE = 64;
+  constexpr int UNITS = (M3_BM + 3 * M3_BN) * UPR;
+  constexpr int NI = UNITS / 256, NIF = M3_BM * UPR / 256;   // loads per wave and stage (frames first)
+  constexpr int STAGE = UNITS * 16;
+  constexpr int WM = 64, WN = 64, MT = WM / 16, NT = WN / 16;
+  static_assert(UNITS % 256 == 0 && (M3_BM * UPR) % 256 == 0, "stage rows fill the waves' loads");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[M3_NS * STAGE];
+  __shared__ int s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave >> 1, wn = wave & 1;
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds);
+  const int u_slot = lane % UPR;
+
+  int base_total = 0, nk_min = 1 << 30;
+  for (int i = 0; i < a.n_preds; ++i) {
+    const int cnt = a.q.counts[a.pred[i]];
+    base_total += ((cnt + M3_BM - 1) / M3_BM) * (a.hidden[i] / M3_BN);
+    nk_min = min(nk_min, a.d_in[i] / BKE);
+  }
+  const int S = mlp_splits(base_total, nk_min, a);
+  const int total = base_total * S;
+
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int tb = t / S, sp = t % S;
+    int slot = 0, mt = 0, nt = 0;
+    {
+      int acc0 = 0;
+      for (int i = 0; i < a.n_preds; ++i) {
+        const int cnt = a.q.counts[a.pred[i]];
+        const int n_nt = a.hidden[i] / M3_BN;
+        const int tiles = ((cnt + M3_BM - 1) / M3_BM) * n_nt;
+        if (tb < acc0 + tiles) {
+          slot = i;
+          mt = (tb - acc0) / n_nt;
+          nt = (tb - acc0) % n_nt;
+          break;
+        }
+        acc0 += tiles;
+      }
+    }
+    const int k = a.pred[slot];
+    const int cnt = a.q.counts[k];
+    const int D = a.d_in[slot], H = a.hidden[slot];
+    const uint32_t* qe = a.q.entries + (int64_t)k * a.q.cap;
+    const unsigned long long t0 = wall_clock64();
+
+    const __bf16* src[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int U = (wave + 4 * i) * 64 + lane;
+      if (i < NIF) {
+        const int r = U / UPR;
+        const int row = mt * M3_BM + r;
+        const uint32_t idx = entry_idx(qe[row < cnt ? row : cnt - 1]);
+        src[i] = static_cast<const __bf16*>(a.fr.base) + (int64_t)idx * a.fr.elems + (u_slot ^ (r & 7)) * 8;
+      } else {
+        const int r = U / UPR - M3_BM;                   // 0 .. 3 * BN - 1: term r / BN, row r % BN
+        const int term = r / M3_BN, rr = r % M3_BN;
+        src[i] = a.w1_s3[slot] + ((int64_t)term * H + nt * M3_BN + rr) * D + (u_slot ^ (rr & 7)) * 8;
+      }
+    }
+    auto issue = [&](int kb, int buf) {
+      const uint32_t base = lds0 + buf * STAGE;
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+        lds_dma16(src[i] + (int64_t)kb * BKE, __builtin_amdgcn_readfirstlane(base + (wave + 4 * i) * 1024));
+    };
+
+    floatx4 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](int buf) {
+      const unsigned char* F = lds + buf * STAGE;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        bf16x8 af[MT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          const int r = wm * WM + i * 16 + l16;
+          af[i] = *reinterpret_cast<const bf16x8*>(F + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
+        }
+        // smallest terms first: the three partial products enter each sum in the order lo, mid, hi
+#pragma unroll
+        for (int term = 2; term >= 0; --term) {
+          const unsigned char* W = F + (M3_BM + term * M3_BN) * ROWB;
+          bf16x8 bfr[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int r = wn * WN + j * 16 + l16;
+            bfr[j] = *reinterpret_cast<const bf16x8*>(W + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
+          }
+#pragma unroll
+          for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    };
+
+    const int nk_all = D / BKE;
+    const int kt0 = (int)((int64_t)nk_all * sp / S), kt1 = (int)((int64_t)nk_all * (sp + 1) / S);
+    const int nkb = kt1 - kt0;
+    // two stages: block kb + 1 is copied while block kb is read; the barrier at the top of each
+    // iteration also retires every wave's reads of the buffer the next copy overwrites
+    if (nkb > 0) issue(kt0, 0);
+#pragma unroll 1
+    for (int kb = 0; kb < nkb; ++kb) {
+      wait_vmcnt<0>();
+      __syncthreads();
+      if (kb + 1 < nkb) issue(kt0 + kb + 1, (kb + 1) & 1);
+      compute(kb & 1);
+    }
+
+    if (S > 1) {
+      float* wt = a.splitk_ws + (int64_t)tb * S * (M3_BM * M3_BN);
+      auto at = [&](int q, int i, int j) -> float4* {
+        return reinterpret_cast<float4*>(
+            &wt[(int64_t)q * (M3_BM * M3_BN) + (wn * WN + j * 16 + l16) * M3_BM + wm * WM + i * 16 + 4 * g]);
+      };
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) *at(sp, i, j) = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_last = atomicAdd(&a.split_cnt[tb], 1) == S - 1;
+      __syncthreads();
+      if (!s_last) {
+        if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
+        continue;
+      }
+      __threadfence();
+      if (tid == 0) a.split_cnt[tb] = 0;
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          floatx4 sum = (floatx4){0.f, 0.f, 0.f, 0.f};
+          for (int q = 0; q < S; ++q) {
+            float4 v;
+            if (q == sp) v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+            else v = *at(q, i, j);
+            sum[0] += v.x; sum[1] += v.y; sum[2] += v.z; sum[3] += v.w;
+          }
+          acc[i][j] = sum;
+        }
+    }
+    const float* b1 = a.b1_fold[slot];
+    const float* w2 = a.w2[slot];
+    const int col0 = nt * M3_BN + wn * WN + l16;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const float bb = b1[col0 + j * 16];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = fmaxf(acc[i][j][r] + bb, 0.f);
+    }
+    float* part = a.partial[slot] + ((int64_t)(nt * 2 + wn) * a.part_cap) * kClasses;
+    for (int c = 0; c < kClasses; ++c) {
+      float w2v[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) w2v[j] = w2[(col0 + j * 16) * kClasses + c];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float sacc = 0.f;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) sacc += acc[i][j][r] * w2v[j];
+          sacc = row_sum16(sacc);
+          const int rr = mt * M3_BM + wm * WM + i * 16 + 4 * g + r;
+          if (l16 == 0 && rr < cnt) part[(int64_t)rr * kClasses + c] = sacc;
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && a.count_ticks) atomicAdd(&a.st->r_ticks[k], (unsigned long long)(wall_clock64() - t0));
+  }
+}
+
 template <typename T, int BM, int BN>
 static void launch_gemm_t(const MlpArgs& b, int grid, hipStream_t s) {
   if (b.fr.dtype == HYDRO_DTYPE_BF16)
@@ -756,7 +949,11 @@ static void launch_gemm_t(const MlpArgs& b, int grid, hipStream_t s) {
 void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s) {
   bool dma = bf && b.fr.dtype == HYDRO_DTYPE_BF16 && (cfg == 0 || cfg == 1);
   for (int i = 0; i < b.n_preds && dma; ++i) dma = b.d_in[i] % 64 == 0 && b.hidden[i] % MD_BN == 0;
-  if (dma) {
+  bool s3 = !bf && b.fr.dtype == HYDRO_DTYPE_BF16 && (cfg == 0 || cfg == 1);
+  for (int i = 0; i < b.n_preds && s3; ++i) s3 = b.w1_s3[i] != nullptr;
+  if (s3) {
+    hipLaunchKernelGGL(mlp_gemm_s3_kernel, dim3(grid), dim3(256), 0, s, b);
+  } else if (dma) {
     MlpArgs c = b;
     c.split_slots = b.split_slots / 2;     // workspace tiles of 256 x 128
     hipLaunchKernelGGL(mlp_gemm_dma_kernel, dim3(grid), dim3(512), 0, s, c);
@@ -771,6 +968,25 @@ void launch_mlp_gemm(const MlpArgs& b, int cfg, bool bf, int grid, hipStream_t s
     else if (cfg == 2) launch_gemm_t<float, 128, 64>(b, grid, s);
     else launch_gemm_t<float, 64, 64>(b, grid, s);
   }
+}
+
+void mlp_copy_slot(MlpArgs& dst, int j, const MlpArgs& src, int i) {
+  dst.pred[j] = src.pred[i];
+  dst.d_in[j] = src.d_in[i];
+  dst.hidden[j] = src.hidden[i];
+  dst.class_mask[j] = src.class_mask[i];
+  dst.w1_bf[j] = src.w1_bf[i];
+  dst.w1_f32[j] = src.w1_f32[i];
+  dst.w1_s3[j] = src.w1_s3[i];
+  dst.b1_fold[j] = src.b1_fold[i];
+  dst.w2[j] = src.w2[i];
+  dst.b2[j] = src.b2[i];
+  dst.w1_canon[j] = src.w1_canon[i];
+  dst.b1_canon[j] = src.b1_canon[i];
+  dst.partial[j] = src.partial[i];
+  dst.part_w[j] = src.part_w[i];
+  dst.tile_cfg[j] = src.tile_cfg[i];
+  dst.esc_h[j] = src.esc_h[i];
 }
 
 void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hipStream_t s) {
@@ -788,11 +1004,7 @@ void launch_mlp_pass(const MlpArgs& a, const Forward& f, int tier, int grid, hip
     b.n_preds = 0;
     for (int i = 0; i < a.n_preds; ++i) {
       if (a.tile_cfg[i] != cfg) continue;
-      const int j = b.n_preds++;
-      b.pred[j] = a.pred[i]; b.d_in[j] = a.d_in[i]; b.hidden[j] = a.hidden[i]; b.class_mask[j] = a.class_mask[i];
-      b.w1_bf[j] = a.w1_bf[i]; b.w1_f32[j] = a.w1_f32[i]; b.b1_fold[j] = a.b1_fold[i]; b.w2[j] = a.w2[i];
-      b.b2[j] = a.b2[i]; b.w1_canon[j] = a.w1_canon[i]; b.b1_canon[j] = a.b1_canon[i]; b.partial[j] = a.partial[i];
-      b.esc_h[j] = a.esc_h[i]; b.tile_cfg[j] = cfg; b.part_w[j] = a.part_w[i];
+      mlp_copy_slot(b, b.n_preds++, a, i);
     }
     if (b.n_preds == 0) continue;
     launch_mlp_gemm(b, cfg, bf, grid, s);
