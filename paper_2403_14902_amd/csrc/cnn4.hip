@@ -33,6 +33,7 @@ template <int P> struct C4T;
 template <> struct C4T<C4_F32> { typedef float T; static constexpr int ES = 4; };
 template <> struct C4T<C4_BF16> { typedef __bf16 T; static constexpr int ES = 2; };
 template <> struct C4T<C4_FP8> { typedef uint8_t T; static constexpr int ES = 1; };
+template <> struct C4T<C4_S3> { typedef float T; static constexpr int ES = 4; };
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
@@ -64,7 +65,7 @@ __device__ inline uint32_t c4_pack_fp8x4(float v0, float v1, float v2, float v3)
 // Stores 4 consecutive activations (already >= 0) in the tier's element type.
 template <int P>
 __device__ inline void c4_store4(void* dst, float v0, float v1, float v2, float v3) {
-  if constexpr (P == C4_F32) {
+  if constexpr (P == C4_F32 || P == C4_S3) {
     *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
   } else if constexpr (P == C4_BF16) {
     alignas(8) __bf16 h[4] = {static_cast<__bf16>(v0), static_cast<__bf16>(v1), static_cast<__bf16>(v2),
@@ -484,6 +485,8 @@ template <int P> struct GemmCfg;
 template <> struct GemmCfg<C4_F32> { static constexpr int ROWB = 128, UPR = 8, CE = 4, KSUB = 8; };
 template <> struct GemmCfg<C4_BF16> { static constexpr int ROWB = 128, UPR = 8, CE = 8, KSUB = 2; };
 template <> struct GemmCfg<C4_FP8> { static constexpr int ROWB = 128, UPR = 8, CE = 16, KSUB = 1; };
+// S3: B rows (fp32 activations) as FP32; A rows are three 64-byte bf16 rows (hi, mid, lo)
+template <> struct GemmCfg<C4_S3> { static constexpr int ROWB = 128, UPR = 8, CE = 4, KSUB = 1; };
 
 // chunk swizzle of tile row r: rows of 4 units xor (r/2) mod 4, rows of 8 units xor r mod 8
 template <int UPR>
@@ -503,7 +506,7 @@ template <int P> struct GemmShape<P, 3> {
 
 __host__ __device__ inline int c4_nkb(int prec, int layer) {
   const int cin = layer == 2 ? 64 : 128;
-  const int bke = prec == C4_FP8 ? 128 : prec == C4_BF16 ? 64 : 32;
+  const int bke = prec == C4_FP8 ? 128 : prec == C4_BF16 ? 64 : 32;   // FP32 and S3: 32
   return (9 * cin + bke - 1) / bke;
 }
 
@@ -519,13 +522,15 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
   constexpr int MT = WM / 16, NT = WN / 16;
   constexpr int WGM = BM / WM;                        // waves along M (8 waves in all)
   constexpr int NKB = (9 * CIN + BKE - 1) / BKE;
-  constexpr int UNITS = (BN + BM) * UPR;              // 16-byte units of one stage
+  constexpr bool S3 = P == C4_S3;
+  constexpr int AUNITS = S3 ? 3 * BN * 4 : BN * UPR;   // A: S3 holds three 64-byte rows per channel
+  constexpr int UNITS = AUNITS + BM * UPR;            // 16-byte units of one stage
   constexpr int NI = UNITS / 64 / 8;                  // load instructions per wave and stage
-  constexpr int NIA = BN * UPR / 64 / 8;              // ... of them for A (the rest gather B)
+  constexpr int NIA = AUNITS / 64 / 8;                // ... of them for A (the rest gather B)
   constexpr int STAGE = UNITS * 16;
-  constexpr int NS = 3;                               // stages in flight
+  constexpr int NS = S3 ? 2 : 3;                      // stages in flight
   constexpr bool HEAD = LAYER == 3;
-  static_assert(UNITS % 512 == 0 && (BN * UPR) % 512 == 0, "stage rows must fill the waves' load units");
+  static_assert(UNITS % 512 == 0 && AUNITS % 512 == 0, "stage rows must fill the waves' load units");
   static_assert(WGM * (BN / WN) == 8, "eight waves per tile");
   static_assert(!HEAD || (BN == COUT && WM == PP), "the head needs whole frames per wave and all channels");
   __shared__ __attribute__((aligned(1024))) unsigned char lds[NS * STAGE];
@@ -562,7 +567,8 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
     const int64_t row0 = (int64_t)mt0 * BM;           // first position row of the tile (slot-local)
     const int64_t rows = (int64_t)cnt * PP;
     const unsigned long long t0 = wall_clock64();
-    const unsigned char* img = static_cast<const unsigned char*>(a.c4_img[slot][LAYER - 2][P]) + (size_t)cb * BN * G::ROWB;
+    const unsigned char* img = static_cast<const unsigned char*>(a.c4_img[slot][LAYER - 2][P]) +
+                               (size_t)cb * BN * (S3 ? 64 : G::ROWB);
     // (the previous tile's closing barrier ordered every read of these)
     for (int i = tid; i < BN; i += 512) {
       ep_bias[i] = a.bias[slot][LAYER][cb * BN + i];
@@ -576,7 +582,7 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
     int boi[NI - NIA], boj[NI - NIA], bch[NI - NIA];
 #pragma unroll
     for (int i = NIA; i < NI; ++i) {
-      const int U = (wave + 8 * i) * 64 + lane - BN * UPR;
+      const int U = (wave + 8 * i) * 64 + lane - AUNITS;
       const int rb = U / UPR;
       const int64_t row = row0 + rb;
       const bool valid = row < rows && ebase + row / PP < a.act_cap;
@@ -595,7 +601,13 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
         const int q = wave + 8 * i;
         const void* src;
         if (i < NIA) {
-          src = img + (size_t)kb * COUT * G::ROWB + (size_t)(q * 64 + lane) * 16;
+          // S3 image: [kb][term][oc][64 bytes], the tile's channels of each term contiguous
+          if constexpr (S3) {
+            const int U = q * 64 + lane, term = U / (BN * 4), r = (U / 4) % BN;
+            src = img + (size_t)kb * 3 * COUT * 64 + ((size_t)term * COUT + r) * 64 + (U % 4) * 16;
+          } else {
+            src = img + (size_t)kb * COUT * G::ROWB + (size_t)(q * 64 + lane) * 16;
+          }
         } else {
           const int ke = kb * BKE + bch[i - NIA];
           const int tap = ke / CIN, ch = ke % CIN;
@@ -615,8 +627,48 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
 
     auto compute = [&](int buf) {
       const unsigned char* A = lds + buf * STAGE;
-      const unsigned char* B = A + BN * G::ROWB;
-      if constexpr (P == C4_FP8) {
+      const unsigned char* B = A + AUNITS * 16;
+      if constexpr (S3) {
+        // one 32-deep k-step: lane group g takes k = 8 g .. 8 g + 7 (A chunk g of each 64-byte
+        // row, B chunks 2 g and 2 g + 1 of each 128-byte fp32 row); the fp32 activations are
+        // split a = hi + mid + lo in bf16 and the six products down to 2^-24 relative are summed,
+        // smallest first
+        bf16x8 aw[3][NT];
+#pragma unroll
+        for (int term = 0; term < 3; ++term)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const int r = wn * WN + nt * 16 + l16;
+            aw[term][nt] = *reinterpret_cast<const bf16x8*>(A + ((term * BN + r) * 4 + (g ^ c4_swz<4>(r))) * 16);
+          }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int r = wm * WM + mt * 16 + l16;
+          const floatx4 x0 = *reinterpret_cast<const floatx4*>(B + (r * UPR + ((2 * g) ^ c4_swz<UPR>(r))) * 16);
+          const floatx4 x1 = *reinterpret_cast<const floatx4*>(B + (r * UPR + ((2 * g + 1) ^ c4_swz<UPR>(r))) * 16);
+          bf16x8 xh, xm, xl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float v = e < 4 ? x0[e] : x1[e - 4];
+            const __bf16 h = static_cast<__bf16>(v);
+            const float r1 = v - static_cast<float>(h);
+            const __bf16 m = static_cast<__bf16>(r1);
+            xh[e] = h;
+            xm[e] = m;
+            xl[e] = static_cast<__bf16>(r1 - static_cast<float>(m));
+          }
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            floatx4 c = acc[nt][mt];
+            c = c4_mfma(aw[0][nt], xl, c);
+            c = c4_mfma(aw[1][nt], xm, c);
+            c = c4_mfma(aw[0][nt], xm, c);
+            c = c4_mfma(aw[2][nt], xh, c);
+            c = c4_mfma(aw[1][nt], xh, c);
+            acc[nt][mt] = c4_mfma(aw[0][nt], xh, c);
+          }
+        }
+      } else if constexpr (P == C4_FP8) {
         i32x8 af[NT], bfr[MT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -690,8 +742,8 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
 #pragma unroll 1
     for (int kb = 0; kb < NKB; ++kb) {
       const int ahead = min(NS - 2, NKB - 1 - kb);
-      if (ahead >= 2) wait_vmcnt<2 * NI>();
-      else if (ahead == 1) wait_vmcnt<NI>();
+      if (NS >= 4 && ahead >= 2) wait_vmcnt<2 * NI>();
+      else if (NS >= 3 && ahead >= 1) wait_vmcnt<NI>();
       else wait_vmcnt<0>();
       __syncthreads();
       if (kb + NS - 1 < NKB) issue(kb + NS - 1, (kb + NS - 1) % NS);
@@ -730,7 +782,7 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
           if (valid) c4_store4<P>(o + ch, v[0], v[1], v[2], v[3]);
         }
       }
-      if constexpr (P == C4_F32) c4_track_max(amax, m);
+      if constexpr (P == C4_F32 || P == C4_S3) c4_track_max(amax, m);
     } else {
       // wave (wm, wn): frame wm of the tile, channels wn*WN .. +WN-1.  Pool over the frame's 64
       // positions, then this wave's share of FC.
@@ -815,9 +867,10 @@ void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hip
     hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 2>), dim3(grid), dim3(512), 0, s, a, f);
     hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 3>), dim3(grid), dim3(512), 0, s, a, f);
   } else {
+    // FP32 arithmetic: the front in fp32, layers 3 and 4 as three-term bf16 products
     launch_front<C4_F32>(a, g1, s);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_F32, 2>), dim3(grid), dim3(512), 0, s, a, f);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_F32, 3>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_S3, 2>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_S3, 3>), dim3(grid), dim3(512), 0, s, a, f);
   }
 }
 
@@ -909,13 +962,46 @@ void c4_pack_front(const float* w1, float scale1, const float* w2, const float* 
 
 size_t c4_img_bytes(int prec, int layer) {
   const int cout = layer == 2 ? 128 : 256;
-  return (size_t)c4_nkb(prec, layer) * cout * 128;
+  return (size_t)c4_nkb(prec, layer) * cout * (prec == C4_S3 ? 3 * 64 : 128);
+}
+
+static uint16_t c4_bf16_bits(float v) {
+  uint32_t u;
+  memcpy(&u, &v, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float c4_bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float v;
+  memcpy(&v, &u, 4);
+  return v;
 }
 
 // A image of a GEMM layer: [kb][oc][UPR units of 16 bytes], unit s holding chunk s ^ swz(oc);
 // chunk c of k-block kb holds k = kb * BKE + c * CE + e.
 void c4_pack_img(int prec, int layer, const float* w, const float* scale, unsigned char* out) {
   const int cin = layer == 2 ? 64 : 128, cout = layer == 2 ? 128 : 256;
+  if (prec == C4_S3) {
+    // [kb][term][oc][4 units]: unit s of a row holds chunk s ^ swz4(oc), chunk c holds
+    // k = 32 kb + 8 c + e; term t of w is the bf16 rounding of w minus the earlier terms
+    const int nkb = c4_nkb(prec, layer);
+    for (int kb = 0; kb < nkb; ++kb)
+      for (int oc = 0; oc < cout; ++oc)
+        for (int s = 0; s < 4; ++s) {
+          const int c = s ^ c4_swz<4>(oc);
+          for (int e = 0; e < 8; ++e) {
+            const int kk = kb * 32 + c * 8 + e;
+            float v = kk < 9 * cin ? c4_w(w, cin, oc, kk) : 0.f;
+            for (int t = 0; t < 3; ++t) {
+              const uint16_t h = c4_bf16_bits(v);
+              memcpy(out + ((((size_t)kb * 3 + t) * cout + oc) * 4 + s) * 16 + 2 * e, &h, 2);
+              v -= c4_bf16_value(h);
+            }
+          }
+        }
+    return;
+  }
   const int es = prec == C4_FP8 ? 1 : prec == C4_BF16 ? 2 : 4;
   const int rowb = 128, upr = rowb / 16, ce = 16 / es, bke = rowb / es;
   const int nkb = c4_nkb(prec, layer);

@@ -107,7 +107,7 @@ struct GcnnArgs {
   const void* c4_w1b[kMaxK];                   // layer 1, bf16 MFMA fragments [2][64][8]
   const void* c4_w1f[kMaxK];                   // layer 1, fp32 fragments [7][2][64]
   const void* c4_w2[kMaxK][3];                 // layer 2 register fragments per tier (C4_*)
-  const void* c4_img[kMaxK][2][3];             // layers 3, 4: A tile images per tier
+  const void* c4_img[kMaxK][2][4];             // layers 3, 4: A tile images per arithmetic (C4_*)
   const float* c4_wscale[kMaxK][3];            // FP8 tier: per-channel weight scales, layers 2..4
   float c4_ascale[kMaxK][3];                   // FP8 tier: activation scales, outputs of layers 1..3
   void* c4_act2;                               // layer-2 outputs [act_cap][32][32][64]
@@ -118,7 +118,9 @@ struct GcnnArgs {
 };
 
 // Arithmetic tiers of the dedicated 4-layer CNN kernels.
-enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2 };
+// C4_S3: FP32 arithmetic of the layer-3/4 GEMMs from bf16 MFMAs (fp32 activations split into
+// three bf16 terms on the fly, weights packed as three bf16 terms; see cnn4.hip).
+enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2, C4_S3 = 3 };
 struct C4FrontPack {
   std::vector<float> w1b, w1f;        // layer 1 (bf16 / fp32 fragment order)
   std::vector<float> w2b, w2f;        // layer 2 (bf16 / fp32 fragment order, fp32 values)

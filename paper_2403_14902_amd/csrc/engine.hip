@@ -797,7 +797,7 @@ static int pack_c4(hydro_session* s, const HostModel& hm, float scale1, int i) {
     ga.c4_w2[i][C4_FP8] = qp;
   }
   for (int l = 2; l < 4; ++l)
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < 4; ++p) {
       std::vector<unsigned char> img(c4_img_bytes(p, l));
       c4_pack_img(p, l, hm.cw[l].data(), sc[l - 1].data(), img.data());
       unsigned char* dp;

@@ -705,11 +705,12 @@ void gcnn_copy_slot(GcnnArgs& dst, int j, const GcnnArgs& src, int i) {
     dst.widths[j][l] = src.widths[i][l]; dst.w_bf[j][l] = src.w_bf[i][l]; dst.w_f32[j][l] = src.w_f32[i][l];
     dst.bias[j][l] = src.bias[i][l]; dst.wt_canon[j][l] = src.wt_canon[i][l]; dst.b_canon[j][l] = src.b_canon[i][l];
   }
-  for (int p = 0; p < 3; ++p) {
-    dst.c4_w2[j][p] = src.c4_w2[i][p]; dst.c4_wscale[j][p] = src.c4_wscale[i][p];
-    dst.c4_ascale[j][p] = src.c4_ascale[i][p];
-    dst.c4_img[j][0][p] = src.c4_img[i][0][p]; dst.c4_img[j][1][p] = src.c4_img[i][1][p];
-  }
+  // (array extents, so that a new entry is never left behind)
+  for (size_t p = 0; p < sizeof(src.c4_w2[0]) / sizeof(src.c4_w2[0][0]); ++p) dst.c4_w2[j][p] = src.c4_w2[i][p];
+  for (size_t p = 0; p < sizeof(src.c4_wscale[0]) / sizeof(src.c4_wscale[0][0]); ++p) dst.c4_wscale[j][p] = src.c4_wscale[i][p];
+  for (size_t p = 0; p < sizeof(src.c4_ascale[0]) / sizeof(src.c4_ascale[0][0]); ++p) dst.c4_ascale[j][p] = src.c4_ascale[i][p];
+  for (int l = 0; l < 2; ++l)
+    for (size_t p = 0; p < sizeof(src.c4_img[0][0]) / sizeof(src.c4_img[0][0][0]); ++p) dst.c4_img[j][l][p] = src.c4_img[i][l][p];
 }
 
 void launch_gcnn_pass(const GcnnArgs& a0, const Forward& f, int tier, int grid, hipStream_t s) {
