@@ -386,31 +386,48 @@ void c4_front_kernel(GcnnArgs a) {
           if (tp & 1) __builtin_amdgcn_sched_barrier(0);
         }
       } else {
-        // FP32: weights from global (L2-resident) per tap; lane group g holds channels 8g..8g+7,
-        // k-step e of a tap uses channel 8g + e
-        const float4* w2 = static_cast<const float4*>(a.c4_w2[slot][C4_F32]);
+        // FP32 arithmetic from bf16 MFMAs: per tap, lane group g takes input channels 8g..8g+7
+        // (one 16x16x32 k-step); the fp32 layer-1 activations are split into three bf16 terms
+        // and multiplied with the three-term weights (L2-resident, [tap][ct][term][lane]); the
+        // six products down to 2^-24 relative are summed, smallest first
+        const bf16x8* w2 = static_cast<const bf16x8*>(a.c4_w2[slot][C4_S3]);
 #pragma unroll 1
         for (int tp = 0; tp < 9; ++tp) {
           const int u = tp / 3, v = tp % 3;
           const int rr = (base_slot + 2 * wave + u) % F_RING;
-          float xf[2][8];
+          bf16x8 xs[2][3];
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
             const int j = mt * 16 + l16;
             const int sl = v == 1 ? j : v == 0 ? 32 + j : 33 + j;
             const float4* src = reinterpret_cast<const float4*>(ring + (rr * F_SLOTS + sl) * PITCH + 32 * g);
             const float4 p0 = src[0], p1 = src[1];
-            xf[mt][0] = p0.x; xf[mt][1] = p0.y; xf[mt][2] = p0.z; xf[mt][3] = p0.w;
-            xf[mt][4] = p1.x; xf[mt][5] = p1.y; xf[mt][6] = p1.z; xf[mt][7] = p1.w;
+            const float xv[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const __bf16 h = static_cast<__bf16>(xv[e]);
+              const float r1 = xv[e] - static_cast<float>(h);
+              const __bf16 m = static_cast<__bf16>(r1);
+              xs[mt][0][e] = h;
+              xs[mt][1][e] = m;
+              xs[mt][2][e] = static_cast<__bf16>(r1 - static_cast<float>(m));
+            }
           }
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) {
-            const float4 q0 = w2[((tp * 4 + ct) * 64 + lane) * 2], q1 = w2[((tp * 4 + ct) * 64 + lane) * 2 + 1];
-            const float wf[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+            const bf16x8 wh = w2[((tp * 4 + ct) * 3 + 0) * 64 + lane];
+            const bf16x8 wm = w2[((tp * 4 + ct) * 3 + 1) * 64 + lane];
+            const bf16x8 wl = w2[((tp * 4 + ct) * 3 + 2) * 64 + lane];
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-#pragma unroll
-              for (int mt = 0; mt < 2; ++mt) acc[e & 1][ct][mt] = c4_mfma(wf[e], xf[mt][e], acc[e & 1][ct][mt]);
+            for (int mt = 0; mt < 2; ++mt) {
+              floatx4 c = acc[0][ct][mt];
+              c = c4_mfma(wh, xs[mt][2], c);
+              c = c4_mfma(wm, xs[mt][1], c);
+              c = c4_mfma(wh, xs[mt][1], c);
+              c = c4_mfma(wl, xs[mt][0], c);
+              c = c4_mfma(wm, xs[mt][0], c);
+              acc[0][ct][mt] = c4_mfma(wh, xs[mt][0], c);
+            }
           }
         }
       }
@@ -910,6 +927,19 @@ float c4_fp8_value(uint8_t b) {
   return s ? -v : v;
 }
 
+static uint16_t c4_bf16_bits(float v) {
+  uint32_t u;
+  memcpy(&u, &v, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float c4_bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float v;
+  memcpy(&v, &u, 4);
+  return v;
+}
+
 // conv weights w: [cout][cin][3][3] canonical fp32.  Element (oc, k) of the GEMM with
 // k = tap * cin + ch, tap = 3u + v.
 static inline float c4_w(const float* w, int cin, int oc, int k) {
@@ -949,6 +979,20 @@ void c4_pack_front(const float* w1, float scale1, const float* w2, const float* 
       for (int l = 0; l < 64; ++l)
         for (int e = 0; e < 8; ++e)
           out->w2f[((tp * 4 + ct) * 64 + l) * 8 + e] = c4_w(w2, 32, ct * 16 + (l & 15), tp * 32 + 8 * (l >> 4) + e);
+  // FP32 arithmetic from bf16 terms, [tap][ct][term][lane][8]: the fp32 fragment's eight values
+  // (output channel 16 ct + lane % 16, input channels 8 (lane / 16) + e) split hi, mid, lo
+  out->w2s3.assign(9 * 4 * 3 * 64 * 8, 0);
+  for (int tp = 0; tp < 9; ++tp)
+    for (int ct = 0; ct < 4; ++ct)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          float v = c4_w(w2, 32, ct * 16 + (l & 15), tp * 32 + 8 * (l >> 4) + e);
+          for (int t = 0; t < 3; ++t) {
+            const uint16_t h = c4_bf16_bits(v);
+            out->w2s3[((((size_t)tp * 4 + ct) * 3 + t) * 64 + l) * 8 + e] = h;
+            v -= c4_bf16_value(h);
+          }
+        }
   // fp8 [s][ct][lane][32 bytes]: tap 4s + g, channels 0..31
   out->w2q.assign(3 * 4 * 64 * 32, 0);
   for (int s = 0; s < 3; ++s)
@@ -965,18 +1009,6 @@ size_t c4_img_bytes(int prec, int layer) {
   return (size_t)c4_nkb(prec, layer) * cout * (prec == C4_S3 ? 3 * 64 : 128);
 }
 
-static uint16_t c4_bf16_bits(float v) {
-  uint32_t u;
-  memcpy(&u, &v, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-static float c4_bf16_value(uint16_t h) {
-  const uint32_t u = (uint32_t)h << 16;
-  float v;
-  memcpy(&v, &u, 4);
-  return v;
-}
 
 // A image of a GEMM layer: [kb][oc][UPR units of 16 bytes], unit s holding chunk s ^ swz(oc);
 // chunk c of k-block kb holds k = kb * BKE + c * CE + e.

@@ -795,6 +795,9 @@ static int pack_c4(hydro_session* s, const HostModel& hm, float scale1, int i) {
     uint8_t* qp;
     if ((rc = upload(s, fp.w2q.data(), fp.w2q.size(), &qp))) return rc;
     ga.c4_w2[i][C4_FP8] = qp;
+    uint16_t* sp;
+    if ((rc = upload(s, fp.w2s3.data(), fp.w2s3.size(), &sp))) return rc;
+    ga.c4_w2[i][C4_S3] = sp;
   }
   for (int l = 2; l < 4; ++l)
     for (int p = 0; p < 4; ++p) {
