@@ -179,7 +179,7 @@ void c4_front_kernel(GcnnArgs a) {
 
   // per-slot state (reloaded when the slot changes)
   int cur = -1;
-  float w1f[7][2];                    // layer-1 weights, FP32 tier
+  bf16x8 w1t[P == C4_F32 ? 3 : 1][2];   // layer-1 weights, FP32 arithmetic: [term][channel tile]
   bf16x8 w2b[P == C4_BF16 ? 9 : 1][2][2];            // [tap][channel half of the tap][32-channel tile]
   i32x8 w2q[P == C4_FP8 ? 3 : 1][P == C4_FP8 ? 4 : 1];
   float inv_s1 = 1.f, inv_s2 = 1.f;
@@ -207,11 +207,11 @@ void c4_front_kernel(GcnnArgs a) {
       else if (tid < 160)
         consts_s[tid] = P == C4_FP8 ? a.c4_wscale[slot][0][tid - 96] * a.c4_ascale[slot][0] : 1.f;
       if constexpr (P == C4_F32) {
-        const float* w1 = static_cast<const float*>(a.c4_w1f[slot]);
+        const bf16x8* w1 = static_cast<const bf16x8*>(a.c4_w1f[slot]);
 #pragma unroll
-        for (int s = 0; s < 7; ++s)
+        for (int t = 0; t < 3; ++t)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) w1f[s][ct] = w1[(s * 2 + ct) * 64 + lane];
+          for (int ct = 0; ct < 2; ++ct) w1t[t][ct] = w1[(t * 2 + ct) * 64 + lane];
       } else {
         if (tid < 128) w1_s[tid >> 6][tid & 63] = static_cast<const bf16x8*>(a.c4_w1b[slot])[tid];
       }
@@ -285,25 +285,24 @@ void c4_front_kernel(GcnnArgs a) {
         const int il = 2 * wave + (pt >> 2), j = (pt & 3) * 16 + l16;
         floatx4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         const __bf16* fr = fb + (2 * il) * F_FPITCH + 1 + 6 * j;
-        if constexpr (P == C4_F32) {
+        bf16x8 xb;
 #pragma unroll
-          for (int s = 0; s < 7; ++s) {
-            int kk = 4 * s + g;
-            kk = kk > 26 ? 26 : kk;
-            const int u = kk / 9, tt = kk % 9;
-            const float x = static_cast<float>(fr[u * F_FPITCH + tt]);
-            acc[0] = c4_mfma(w1f[s][0], x, acc[0]);
-            acc[1] = c4_mfma(w1f[s][1], x, acc[1]);
+        for (int e = 0; e < 8; ++e) {
+          int kk = 8 * g + e;
+          kk = kk > 26 ? 26 : kk;   // k = 27..31: zero weights (any finite element)
+          const int u = kk / 9, tt = kk % 9;
+          xb[e] = fr[u * F_FPITCH + tt];
+        }
+        if constexpr (P == C4_F32) {
+          // raw frame values are exact in bf16 and the weights are the sum of their three terms:
+          // every product exact, fp32 sums (smallest term first)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            acc[ct] = c4_mfma(w1t[2][ct], xb, acc[ct]);
+            acc[ct] = c4_mfma(w1t[1][ct], xb, acc[ct]);
+            acc[ct] = c4_mfma(w1t[0][ct], xb, acc[ct]);
           }
         } else {
-          bf16x8 xb;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            int kk = 8 * g + e;
-            kk = kk > 26 ? 26 : kk;   // k = 27..31: zero weights (any finite element)
-            const int u = kk / 9, tt = kk % 9;
-            xb[e] = fr[u * F_FPITCH + tt];
-          }
           acc[0] = c4_mfma(w1_s[0][lane], xb, acc[0]);
           acc[1] = c4_mfma(w1_s[1][lane], xb, acc[1]);
         }
@@ -958,6 +957,18 @@ void c4_pack_front(const float* w1, float scale1, const float* w2, const float* 
   for (int ct = 0; ct < 2; ++ct)
     for (int l = 0; l < 64; ++l)
       for (int e = 0; e < 8; ++e) out->w1b[(ct * 64 + l) * 8 + e] = w1k(ct * 16 + (l & 15), 8 * (l >> 4) + e);
+  // FP32 arithmetic: the bf16 fragments' values split into three bf16 terms [term][ct][lane][8]
+  out->w1s3.assign(3 * 2 * 64 * 8, 0);
+  for (int ct = 0; ct < 2; ++ct)
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 8; ++e) {
+        float v = w1k(ct * 16 + (l & 15), 8 * (l >> 4) + e);
+        for (int t = 0; t < 3; ++t) {
+          const uint16_t h = c4_bf16_bits(v);
+          out->w1s3[(((size_t)t * 2 + ct) * 64 + l) * 8 + e] = h;
+          v -= c4_bf16_value(h);
+        }
+      }
   out->w1f.assign(7 * 2 * 64, 0.f);
   for (int s = 0; s < 7; ++s)
     for (int ct = 0; ct < 2; ++ct)

@@ -105,7 +105,7 @@ struct GcnnArgs {
   // 4-layer 128x128 CNNs (conv 32-64-128-256): dedicated kernels (cnn4.hip); per slot
   int c4[kMaxK];                               // 1: the slot takes the dedicated kernels
   const void* c4_w1b[kMaxK];                   // layer 1, bf16 MFMA fragments [2][64][8]
-  const void* c4_w1f[kMaxK];                   // layer 1, fp32 fragments [7][2][64]
+  const void* c4_w1f[kMaxK];                   // layer 1, FP32 arithmetic: three-term bf16 fragments [3][2][64][8]
   const void* c4_w2[kMaxK][4];                 // layer 2 fragments per arithmetic (C4_*)
   const void* c4_img[kMaxK][2][4];             // layers 3, 4: A tile images per arithmetic (C4_*)
   const float* c4_wscale[kMaxK][3];            // FP8 tier: per-channel weight scales, layers 2..4
@@ -124,7 +124,7 @@ enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2, C4_S3 = 3 };
 struct C4FrontPack {
   std::vector<float> w1b, w1f;        // layer 1 (bf16 / fp32 fragment order)
   std::vector<float> w2b, w2f;        // layer 2 (bf16 / fp32 fragment order, fp32 values)
-  std::vector<uint16_t> w2s3;         // layer 2 for FP32 arithmetic from three bf16 terms
+  std::vector<uint16_t> w1s3, w2s3;   // layers 1 and 2 for FP32 arithmetic from three bf16 terms
   std::vector<uint8_t> w2q;           // layer 2 e4m3
 };
 bool c4_shape_ok(int in_hw, int n_layers, const int* widths);

@@ -784,8 +784,9 @@ static int pack_c4(hydro_session* s, const HostModel& hm, float scale1, int i) {
     if ((rc = upload(s, b.data(), b.size(), &bp))) return rc;
     ga.c4_w1b[i] = bp;
     float* dp;
-    if ((rc = upload(s, fp.w1f.data(), fp.w1f.size(), &dp))) return rc;
-    ga.c4_w1f[i] = dp;
+    uint16_t* tp;
+    if ((rc = upload(s, fp.w1s3.data(), fp.w1s3.size(), &tp))) return rc;
+    ga.c4_w1f[i] = tp;
     std::vector<uint16_t> b2(fp.w2b.size());
     for (size_t t = 0; t < b2.size(); ++t) b2[t] = f32_to_bf16_bits(fp.w2b[t]);
     if ((rc = upload(s, b2.data(), b2.size(), &bp))) return rc;
