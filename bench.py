@@ -54,6 +54,20 @@ METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs pla
 # scaled by the same counters on a 1 GiB device copy (the byte-counter summary in profiles/).  Valid
 # only for the kernel build those runs measured: None for a workload without such a run.
 FIRST_PASS_TRAFFIC = {"cnn3_drift64": 407.60e6 + 5.27e6}
+# The 4-layer CNN first pass (front + layer-3 + layer-4 launches, bf16): HBM bytes per evaluated
+# frame from the same counters (profiles/cnn4_u8_128_first_pass.md), valid while the kernel
+# sources hash to the recorded value; the figure per launch is this times the launch's frames.
+FIRST_PASS_BYTES_PER_EVAL = {"cnn4_u8_128": ('6521d873692a3eb6', 8.4224e9 / 17435.0)}
+FIRST_PASS_SOURCES = ("paper_2403_14902_amd/csrc/cnn4.hip", "paper_2403_14902_amd/csrc/common.h")
+
+
+def sources_hash(paths) -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in paths:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}   # dense MFMA peaks, TFLOP/s
@@ -96,6 +110,17 @@ def parse():
     ap.add_argument("--errors", type=int, default=4096,
                     help="frames on which bf16 / fp32 logits and margins are compared with fp64 (0: skip)")
     return ap.parse_args()
+
+
+def first_pass_traffic(cfg, n, ev, launches):
+    """HBM bytes per first-pass launch from the byte-counter runs of this kernel build, else None."""
+    if n == cfg.n and cfg.name in FIRST_PASS_TRAFFIC:
+        return FIRST_PASS_TRAFFIC[cfg.name]
+    if cfg.name in FIRST_PASS_BYTES_PER_EVAL:
+        sha, per_eval = FIRST_PASS_BYTES_PER_EVAL[cfg.name]
+        if sources_hash(FIRST_PASS_SOURCES) == sha:
+            return per_eval * float(ev.sum()) / max(1, launches)
+    return None
 
 
 def log(msg):
@@ -238,7 +263,7 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
             "peak": PEAK[prec],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK[prec],
-            "traffic": FIRST_PASS_TRAFFIC.get(cfg.name) if n == cfg.n else None,
+            "traffic": first_pass_traffic(cfg, n, ev, launches),
             "flops_per_launch": first_flops / max(1, launches),
             "avg_launch_ms": first_ms / max(1, launches),
         },
