@@ -104,6 +104,11 @@ def parse():
                          "of known traffic, to scale hardware byte counters)")
     ap.add_argument("--no-compaction", action="store_true", help="skip the standalone routing/compaction run")
     ap.add_argument("--no-reuse", action="store_true", help="skip the result-reuse (recurrent query) run")
+    ap.add_argument("--no-concurrent", action="store_true", help="skip the concurrent host/GPU predicate run")
+    ap.add_argument("--concurrent-only", action="store_true", help="run only the concurrent host/GPU predicate run")
+    ap.add_argument("--concurrent-points", type=lambda v: [tuple(float(x) for x in p.split(":")) for p in v.split(",")],
+                    default=[(0.0, 0.05), (0.1, 0.05), (0.2, 0.05), (0.1, 0.12)],
+                    help="GPU-threshold shift : host threshold pairs of the concurrent run")
     ap.add_argument("--compaction-only", action="store_true",
                     help="run only the standalone routing/compaction measurement and print its JSON")
     ap.add_argument("--compaction-log2n", type=int, default=26)
@@ -542,6 +547,64 @@ def reuse_leg(args, hydro, torch, hs):
     return out
 
 
+def concurrent_leg(args, hydro, torch, hs):
+    """Section 4.1's concurrent setting on one MI355X and its host: the 65,536-frame CNN workload's
+    widest predicate on the GPU and a colour-box predicate decided by the host's CPU threads (every
+    8th pixel row and column), frames resident in HBM for the GPU and in host memory for the CPU.
+    Each round the CPU decides its queue while the GPU evaluates the other, so a query takes about
+    the longer of the two per round.
+    The three routing policies are timed (median of 3 queries each) at three host thresholds;
+    the selectivities are the ones each query measured."""
+    cfg = hs.workload(2)
+    n = cfg.n
+    frames_host = hs.make_frames_parallel(cfg, 0, n)
+    frames = torch.from_numpy(frames_host).cuda()
+    pt = hs.load_predicates(cfg)
+    weights = [hs.make_model(d) for d in cfg.models]
+    gpu = hydro.ModelSpec.from_weights(weights[2], pt.class_masks[2])
+    lo, hi, stride = [0.5, 0.5, 0.5], [1.0, 1.0, 1.0], 8
+    host = hydro.ModelSpec.host_color(cfg.hw, lo, hi, stride)
+    seg_len = cfg.n // cfg.n_seg
+    points = []
+    for gpu_shift, theta in args.concurrent_points:
+        th = np.stack([pt.thresholds[:, 2] + np.float32(gpu_shift), np.full(cfg.n_seg, theta, dtype=np.float32)],
+                      axis=1).astype(np.float32)
+        pt_out = {"gpu_threshold_shift": gpu_shift, "host_threshold": theta, "ms": {}, "evaluated": {}}
+        for route in ("cost", "score", "selectivity"):
+            s = hydro.Session([gpu, host], hydro.make_policy(route, wave=args.wave), cfg.hw, n)
+            times, ids_ref = [], None
+            for rep in range(4):
+                s.reset()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.push(frames, cfg.dtype, th, seg_len, host_copy=frames_host)
+                ids, st = s.finish()
+                t1 = time.perf_counter()
+                if rep > 0:
+                    times.append(t1 - t0)
+                if ids_ref is None:
+                    ids_ref = ids
+            s.close()
+            if "ids" in pt_out:
+                assert np.array_equal(pt_out["ids"], ids_ref), "routing policies disagree"
+            pt_out["ids"] = ids_ref
+            pt_out["ms"][route] = float(np.median(times)) * 1e3
+            pt_out["evaluated"][route] = [int(x["evaluated"]) for x in st]
+            if route == "cost":
+                pt_out["selectivity"] = {"gpu_cnn": round(st[0]["selectivity"], 3), "host_color": round(st[1]["selectivity"], 3)}
+                pt_out["cost_us_per_tuple"] = {"gpu_cnn": st[0]["cost_us_per_tuple"], "host_color": st[1]["cost_us_per_tuple"]}
+        pt_out["n_result"] = int(pt_out.pop("ids").size)
+        points.append(pt_out)
+    del frames, frames_host
+    torch.cuda.empty_cache()
+    return {"workload": f"{cfg.name}: {n} frames in HBM, with a host copy for the CPU predicate",
+            "predicates": {"gpu": "CNN (64, 128, 256), 79 MFLOP per tuple",
+                           "host": {"box": [lo, hi], "stride": stride, "threads": os.cpu_count()}},
+            "points": points,
+            "note": "median of 3 queries per policy; cost units: device time per tuple summed over compute "
+                    "units (host: thread time x compute units / threads)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -564,6 +627,9 @@ def main():
     if args.compaction_only:
         print(json.dumps({"compaction": compaction(args, hydro, torch)}), flush=True)
         return
+    if args.concurrent_only:
+        print(json.dumps({"concurrent": concurrent_leg(args, hydro, torch, hs)}), flush=True)
+        return
     abl = max(1, min(args.ablation_steps, args.steps))
     out = measure(args, args.workload, args.n, args.steps, args.warmup, abl, hydro, torch, hs, True)
     if not args.no_secondary and args.workload != 2:
@@ -575,6 +641,9 @@ def main():
     if not args.no_reuse:
         log("[bench] result reuse (recurrent query)")
         out["reuse"] = reuse_leg(args, hydro, torch, hs)
+    if not args.no_concurrent:
+        log("[bench] concurrent host and GPU predicates")
+        out["concurrent"] = concurrent_leg(args, hydro, torch, hs)
     if not args.no_compaction:
         log("[bench] standalone routing / compaction")
         out["compaction"] = compaction(args, hydro, torch)

@@ -67,9 +67,11 @@ typedef struct {
   int64_t n;
   int32_t h, w;
   int64_t id_base;
+  const void* host_data;   /* optional, with where == DEVICE: the same frames in host memory, read by
+                              HOST predicates (NULL: none); borrowed until hydro_session_finish     */
 } hydro_frames;
 
-typedef enum { HYDRO_ARCH_MLP = 0, HYDRO_ARCH_CNN = 1 } hydro_arch;
+typedef enum { HYDRO_ARCH_MLP = 0, HYDRO_ARCH_CNN = 1, HYDRO_ARCH_HOST = 2 } hydro_arch;
 
 /* One predicate: a classifier with 10 logits z and a class subset S (class_mask bit c <=> c in S).
  * Its margin is d = max_{c in S} z_c - max_{c not in S} z_c and it holds iff d > theta (strict),
@@ -83,6 +85,20 @@ typedef enum { HYDRO_ARCH_MLP = 0, HYDRO_ARCH_CNN = 1 } hydro_arch;
  *   each followed by ReLU; then the mean over all final positions; then z = g Wfc + bfc.
  *   conv_w[l]: [widths[l]][c_in][3][3] (c_in = 3 for l = 0, else widths[l-1]), conv_b[l]:
  *   [widths[l]]; fc_w: [widths[n_layers-1]][10], fc_b: [10]; all fp32, row-major.
+ * HOST (arch = HOST): a cheap heuristic evaluated by the library's CPU threads concurrently with
+ *   the GPU predicates (section 4.1: a colour classifier on the CPU beside a deep model on the
+ *   GPU): d = the fraction of the frame's sampled pixels (rows and columns 0, s, 2s, ... with
+ *   s = color_stride) whose three values x_c (in [0,1], as above) all lie in
+ *   [color_lo[c], color_hi[c]]; it holds iff d > theta.  A session with a HOST predicate
+ *   takes frames in host memory, or device frames with their host copy in host_data
+ *   (EUNSUPPORTED otherwise); every round its queue is
+ *   copied to the host, evaluated on up to HYDRO_HOST_THREADS (default: all) threads while the GPU
+ *   evaluates the other queues, and the decisions are copied back and forwarded; its cost is the
+ *   measured time per tuple of the thread pool, scaled to the GPU's scale of cost (device time
+ *   per tuple summed over its compute units) by the ratio of compute units to threads, so that
+ *   either resource's figure reads as that resource's wall time per tuple times the same
+ *   constant (STATIC cost source: 6 operations per sampled pixel).  No weights,
+ *   class_mask unused; not with route = LEARNED; pushes are not captured in graphs.
  * Weights are copied (and re-packed per precision) when a session is created. */
 typedef struct {
   int32_t arch;
@@ -95,6 +111,9 @@ typedef struct {
   const float* conv_b[HYDRO_MAX_LAYERS];
   const float *fc_w, *fc_b;
   uint32_t class_mask;
+  float color_lo[3], color_hi[3];   /* HOST: the channel box */
+  int32_t color_stride;             /* HOST: pixels sampled every stride-th row and column
+                                       (0 or 1: every pixel)                                     */
 } hydro_model;
 
 typedef enum {

@@ -34,6 +34,10 @@ function follows:
   decision taken at one threshold answers another threshold only where the
   comparison is implied (this build's reading: its cache holds decisions, not
   raw UDF outputs).
+* ``color_fraction``: a cheap CPU predicate beside the GPU UDFs (section 4.1:
+  the colour classifier runs on the CPU concurrently with the breed model on
+  the GPU); this build's reading is a channel box, the fraction of pixels whose
+  three values all lie inside it, compared with theta like the UDF margins.
 * ``replay_route``: checks a per-tuple visit sequence against the routing
   rules of section 3.3 ("Metadata for Data Routing": a batch visits each
   predicate at most once and is complete when all are visited; "Eager
@@ -182,6 +186,17 @@ def predicate_margin(z: np.ndarray, class_mask: int) -> np.ndarray:
 def decide(d: np.ndarray, theta) -> np.ndarray:
     """pass iff d > theta (strict); theta is the fp32 threshold widened to fp64."""
     return d > np.asarray(theta, dtype=np.float64)
+
+
+def color_fraction(frames: np.ndarray, dtype: str, lo: Sequence[float], hi: Sequence[float],
+                   stride: int = 1) -> np.ndarray:
+    """Fraction of each frame's sampled pixels (rows and columns 0, stride, 2 stride, ...) with
+    lo[c] <= x_c <= hi[c] for all three channels (fp64)."""
+    x = frames_to_f64(np.asarray(frames)[:, ::stride, ::stride], dtype)
+    lo64 = np.asarray(lo, dtype=np.float32).astype(np.float64)
+    hi64 = np.asarray(hi, dtype=np.float32).astype(np.float64)
+    inside = np.all((x >= lo64) & (x <= hi64), axis=-1)
+    return inside.reshape(x.shape[0], -1).mean(axis=1)
 
 
 # --------------------------------------------------------------------------
@@ -371,6 +386,37 @@ def cached_decision(theta_cached: float, passed_cached: bool, theta: float) -> T
     if not passed_cached and theta >= theta_cached:
         return True, False
     return False, False
+
+
+def concurrent_makespan(order: Sequence[int], passes: np.ndarray, cost: Sequence[float]) -> float:
+    """Predicates on separate resources running concurrently (section 4.1, "Example comparison"):
+    each predicate has one worker that takes its tuples first come, first served, cost[j] time
+    units each; every tuple starts at the first predicate of ``order`` at time 0, moves to the
+    next one when it passes and is dropped when it fails.  passes[t, j]: tuple t passes j.
+    Returns the time the last evaluation ends."""
+    passes = np.asarray(passes, dtype=bool)
+    n = passes.shape[0]
+    arrive = np.zeros(n)                    # arrival time of each live tuple at the current stage
+    live = np.arange(n)
+    end = 0.0
+    for j in order:
+        free = 0.0
+        done = np.empty(live.size)
+        for q, t in enumerate(live):         # first come, first served (arrival order; ties by id)
+            start = max(free, arrive[q])
+            free = start + cost[j]
+            done[q] = free
+        end = max(end, free if live.size else 0.0)
+        keep = passes[live, j]
+        live, arrive = live[keep], done[keep]
+        o = np.lexsort((live, arrive))
+        live, arrive = live[o], arrive[o]
+    return float(end)
+
+
+def policy_first(policy: str, cost, selectivity) -> int:
+    """The predicate a policy evaluates first (lowest key, lowest index on ties)."""
+    return policy_order(policy, cost, selectivity)[0]
 
 
 # --------------------------------------------------------------------------

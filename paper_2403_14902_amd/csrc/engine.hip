@@ -25,8 +25,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <condition_variable>
+#include <functional>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.h"
@@ -554,6 +558,20 @@ __global__ __launch_bounds__(kRouteThreads) void k_table_decide(Queues q, int k,
   }
 }
 
+// Decisions of a HOST predicate (taken on the CPU for the round's queue entries, dec[i] for entry
+// i) forwarded like any tier's; the CPU threads' time of the round is added to its cost.
+__global__ __launch_bounds__(256) void k_apply_host(Queues q, int k, const uint8_t* dec, Forward f,
+                                                    unsigned long long ticks) {
+  const int c = q.counts[k];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && ticks) atomicAdd(&f.st->r_ticks[k], ticks);
+  for (int base = blockIdx.x * blockDim.x; base < c; base += gridDim.x * blockDim.x) {
+    const int i = base + threadIdx.x;
+    const bool active = i < c;
+    const uint32_t e = active ? q.entries[(int64_t)k * q.cap + i] : 0u;
+    forward_decision(f, k, e, active, false, active && dec[i] != 0);
+  }
+}
+
 // ---------------------------------------------------------------- session
 // Escalated (FP64) entries per predicate and round evaluated layer-parallel; more run one per
 // block.  HYDRO_ESC_CAP overrides the default (tests use it to exercise the per-block path).
@@ -596,6 +614,60 @@ struct GraphKey {
 constexpr int kEvPerRound = 6;               // start, routed, first pass, BF16 mid, FP32, FP64
 constexpr float kAutoTauFloor = 0.015f;     // automatic bands never go below these
 constexpr float kAutoTau32Floor = 1e-5f;
+
+// Persistent CPU threads for HOST predicates: run(n, fn) calls fn(t) for t = 0..n-1, the caller
+// taking t = 0, and returns when all have finished (no thread is created per round).
+struct HostPool {
+  std::vector<std::thread> threads;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::function<void(int)> job;
+  uint64_t generation = 0;
+  int active = 0, pending = 0;
+  bool stop = false;
+  void start(int n) {
+    for (int t = 1; t < n; ++t)
+      threads.emplace_back([this, t] {
+        uint64_t seen = 0;
+        for (;;) {
+          std::function<void(int)> fn;
+          {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || generation != seen; });
+            if (stop) return;
+            seen = generation;
+            if (t >= active) continue;
+            fn = job;
+          }
+          fn(t);
+          std::lock_guard<std::mutex> lk(mu);
+          if (--pending == 0) done_cv.notify_one();
+        }
+      });
+  }
+  void run(int n, const std::function<void(int)>& fn) {
+    n = std::max(1, std::min<int>(n, (int)threads.size() + 1));
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      job = fn;
+      active = n;
+      pending = n - 1;
+      ++generation;
+    }
+    cv.notify_all();
+    fn(0);
+    std::unique_lock<std::mutex> lk(mu);
+    done_cv.wait(lk, [&] { return pending == 0; });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto& th : threads) th.join();
+  }
+};
 
 struct hydro_session {
   int device = 0;
@@ -656,6 +728,17 @@ struct hydro_session {
   size_t arena_cap = 0, arena_used = 0;
   int64_t act_cap = 0;   // entries of the layer-wise CNN activation buffers (evaluations per launch)
   ResultCache cache{};   // policy.reuse > 0: decisions kept across the session's queries
+  // HOST predicates: evaluated by CPU threads on host-memory frames while the GPU evaluates the
+  // other queues of the round; entries copied down, decisions copied up, forwarded on the device
+  std::vector<int> host_preds;
+  int64_t h_cap = 0;                 // entries per host predicate and round (the live-tuple bound)
+  int* h_counts = nullptr;           // pinned: the round's first-pass queue counts [kMaxK]
+  uint32_t* h_entries = nullptr;     // pinned: [host predicate][h_cap] queue entries
+  uint8_t* h_dec = nullptr;          // pinned: [host predicate][h_cap] decisions
+  uint8_t* d_dec = nullptr;          // device copy of h_dec
+  hipEvent_t h_routed = nullptr, h_ready = nullptr, h_done = nullptr;
+  int host_threads = 1;
+  std::unique_ptr<HostPool> pool;
 };
 
 // Captured pushes bake the bands (and every other launch argument) into their kernel nodes.
@@ -715,6 +798,10 @@ static float bf16_bits_to_f32(uint16_t b) {
 }
 
 static double model_flops(const hydro_model& m) {
+  if (m.arch == HYDRO_ARCH_HOST) {                               // six comparisons per sampled pixel
+    const int st = m.color_stride > 1 ? m.color_stride : 1;
+    return 6.0 * ((m.in_h + st - 1) / st) * ((m.in_w + st - 1) / st);
+  }
   if (m.arch == HYDRO_ARCH_MLP) {
     double d = (double)m.in_h * m.in_w * 3;
     return 2.0 * (d * m.hidden + (double)m.hidden * kClasses);
@@ -732,6 +819,14 @@ static double model_flops(const hydro_model& m) {
 static int validate_model(const hydro_model& m, int fh, int fw) {
   if (m.in_h != fh || m.in_w != fw) return fail(HYDRO_EINVAL, "model input shape differs from the session's frame shape");
   if (m.class_mask >= (1u << kClasses)) return fail(HYDRO_EINVAL, "class_mask has bits above class 9");
+  if (m.arch == HYDRO_ARCH_HOST) {
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(m.color_lo[c]) || !std::isfinite(m.color_hi[c]) || m.color_lo[c] > m.color_hi[c])
+        return fail(HYDRO_EINVAL, "HOST predicate: color_lo / color_hi must be finite with lo <= hi");
+    if (m.color_stride < 0 || m.color_stride > m.in_h || m.color_stride > m.in_w)
+      return fail(HYDRO_EINVAL, "HOST predicate: color_stride must be in 0 .. frame side");
+    return HYDRO_OK;
+  }
   if (m.arch == HYDRO_ARCH_MLP) {
     if (!m.w1 || !m.b1 || !m.w2 || !m.b2) return fail(HYDRO_EINVAL, "MLP weight pointer is NULL");
     if (m.hidden <= 0 || m.hidden % 128 != 0 || m.hidden > 2048)
@@ -840,6 +935,7 @@ static int pack_models(hydro_session* s) {
   for (int k : slots_order) {
     HostModel& hm = s->models[k];
     const hydro_model& m = hm.m;
+    if (m.arch == HYDRO_ARCH_HOST) continue;     // evaluated on the CPU (no device weights)
     if (m.arch == HYDRO_ARCH_MLP) {
       const int D = m.in_h * m.in_w * 3, H = m.hidden;
       std::vector<float> wt((size_t)H * D), b1f(H);
@@ -1129,6 +1225,11 @@ static void free_session(hydro_session* s) {
     if (s->stage_ready[i]) hipEventDestroy(s->stage_ready[i]);
   }
   if (s->out_ids && !s->arena) hipFree(s->out_ids);
+  if (s->h_counts) hipHostFree(s->h_counts);
+  if (s->h_entries) hipHostFree(s->h_entries);
+  if (s->h_dec) hipHostFree(s->h_dec);
+  for (hipEvent_t e : {s->h_routed, s->h_ready, s->h_done})
+    if (e) hipEventDestroy(e);
   for (hipEvent_t e : s->evpool) hipEventDestroy(e);
   for (auto& g : s->graphs) hipGraphExecDestroy(g.second);
   if (s->copy_stream) hipStreamDestroy(s->copy_stream);
@@ -1244,7 +1345,9 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
     hm.m = models[i];
     const hydro_model& m = models[i];
     hm.flops = model_flops(m);
-    if (m.arch == HYDRO_ARCH_MLP) {
+    if (m.arch == HYDRO_ARCH_HOST) {
+      s->host_preds.push_back(i);
+    } else if (m.arch == HYDRO_ARCH_MLP) {
       size_t D = (size_t)m.in_h * m.in_w * 3;
       hm.w1.assign(m.w1, m.w1 + D * m.hidden);
       hm.b1.assign(m.b1, m.b1 + m.hidden);
@@ -1328,6 +1431,28 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
     if (he != hipSuccess) return bail(fail(HYDRO_ENOMEM, "result buffer allocation failed"));
   }
   s->out_cap = cap;
+  if (!s->host_preds.empty()) {
+    if (s->pol.route == HYDRO_ROUTE_LEARNED)
+      return bail(fail(HYDRO_EUNSUPPORTED, "HOST predicates are not combined with the learned router"));
+    if (s->arena) return bail(fail(HYDRO_EUNSUPPORTED, "allocation-free queries take no HOST predicates"));
+    const int64_t warm = (int64_t)s->pol.warmup_batches * s->K * s->pol.routing_batch;
+    s->h_cap = std::min<int64_t>(cap, (int64_t)s->K * std::max<int64_t>(s->pol.wave, warm));
+    const size_t nh = s->host_preds.size();
+    if (hipHostMalloc((void**)&s->h_counts, kMaxK * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&s->h_entries, nh * s->h_cap * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&s->h_dec, nh * s->h_cap) != hipSuccess)
+      return bail(fail(HYDRO_ENOMEM, "pinned host buffers of the HOST predicates"));
+    if ((rc = sess_alloc(s, (void**)&s->d_dec, nh * s->h_cap))) return bail(rc);
+    for (hipEvent_t* e : {&s->h_routed, &s->h_ready, &s->h_done}) {
+      he = hipEventCreateWithFlags(e, hipEventDisableTiming);
+      if (he != hipSuccess) return bail(fail(HYDRO_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(he)));
+    }
+    const char* ht = getenv("HYDRO_HOST_THREADS");
+    const int hw = (int)std::thread::hardware_concurrency();
+    s->host_threads = (ht && *ht) ? std::max(1, atoi(ht)) : std::max(1, hw);
+    s->pool.reset(new HostPool());
+    s->pool->start(s->host_threads);
+  }
   if (s->pol.route == HYDRO_ROUTE_LEARNED) {
     double fl[kMaxK];
     for (int i = 0; i < k; ++i) fl[i] = s->models[i].flops;
@@ -1695,6 +1820,101 @@ static int auto_bands(hydro_session* s, const hydro_frames& fr) {
   return HYDRO_OK;
 }
 
+// ---------------------------------------------------------------- HOST predicates
+// The colour-box fraction of one frame over its sampled pixels (x in [0,1]: bf16 value,
+// uint8 / 255, or fp32).
+static double host_color_fraction(const hydro_model& m, const void* base, int dtype, int64_t idx, int64_t pixels) {
+  const int st = m.color_stride > 1 ? m.color_stride : 1;
+  int64_t inside = 0, sampled = 0;
+  for (int y = 0; y < m.in_h; y += st)
+    for (int x = 0; x < m.in_w; x += st) {
+      const int64_t e0 = (idx * pixels + (int64_t)y * m.in_w + x) * 3;
+      bool in = true;
+      for (int c = 0; c < 3; ++c) {
+        double v;
+        if (dtype == HYDRO_DTYPE_BF16) {
+          const uint32_t u = (uint32_t) static_cast<const uint16_t*>(base)[e0 + c] << 16;
+          float f;
+          memcpy(&f, &u, 4);
+          v = f;
+        } else if (dtype == HYDRO_DTYPE_U8) {
+          v = (double)static_cast<const uint8_t*>(base)[e0 + c] / 255.0;
+        } else {
+          v = static_cast<const float*>(base)[e0 + c];
+        }
+        in = in && v >= (double)m.color_lo[c] && v <= (double)m.color_hi[c];
+      }
+      inside += in;
+      ++sampled;
+    }
+  return (double)inside / (double)sampled;
+}
+
+// After the round's route kernel: copy the counts and every HOST predicate's queue to pinned host
+// memory on the copy stream (the GPU tiers are enqueued behind the route on the main stream).
+static int host_round_copy(hydro_session* s, hipStream_t st) {
+  HIP_TRY(hipEventRecord(s->h_routed, st));
+  HIP_TRY(hipStreamWaitEvent(s->copy_stream, s->h_routed, 0));
+  HIP_TRY(hipMemcpyAsync(s->h_counts, s->st->qcount, kMaxK * sizeof(int), hipMemcpyDeviceToHost, s->copy_stream));
+  for (size_t h = 0; h < s->host_preds.size(); ++h)
+    HIP_TRY(hipMemcpyAsync(s->h_entries + h * s->h_cap, s->q1 + (int64_t)s->host_preds[h] * s->cap,
+                           s->h_cap * sizeof(uint32_t), hipMemcpyDeviceToHost, s->copy_stream));
+  HIP_TRY(hipEventRecord(s->h_ready, s->copy_stream));
+  return HYDRO_OK;
+}
+
+// After the round's GPU tiers are enqueued: wait for the copies, decide the HOST queues on CPU
+// threads (while the GPU works through its queues), copy the decisions up and enqueue their
+// forwarding behind the GPU tiers.
+static int host_round_decide(hydro_session* s, hipStream_t st, const hydro_frames& fr, const float* theta, int n_seg,
+                             int64_t seg_len, const Forward& f) {
+  HIP_TRY(hipEventSynchronize(s->h_ready));
+  const int64_t pixels = (int64_t)fr.h * fr.w;
+  const void* host_frames = fr.where == HYDRO_MEM_HOST ? fr.data : fr.host_data;
+  std::vector<unsigned long long> ticks(s->host_preds.size(), 0);
+  for (size_t h = 0; h < s->host_preds.size(); ++h) {
+    const int k = s->host_preds[h];
+    const int64_t n = s->h_counts[k];
+    if (n > s->h_cap) return fail(HYDRO_EDEVICE, "HOST predicate queue above its round bound");
+    if (n == 0) continue;
+    const hydro_model& m = s->models[k].m;
+    const uint32_t* ent = s->h_entries + h * s->h_cap;
+    uint8_t* dec = s->h_dec + h * s->h_cap;
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(s->host_threads, (n + 63) / 64));
+    std::vector<double> us(T, 0.0);
+    auto work = [&](int t) {
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) {
+        const uint32_t idx = entry_idx(ent[i]);
+        const int64_t id = fr.id_base + idx;
+        const int64_t sg = std::min<int64_t>(id / seg_len, n_seg - 1);
+        const double th = theta[sg * s->K + k];
+        dec[i] = host_color_fraction(m, host_frames, fr.dtype, idx, pixels) > th ? 1 : 0;
+      }
+      us[t] = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    };
+    s->pool->run(T, work);
+    double tot = 0;
+    for (double u : us) tot += u;
+    // thread time in device clock ticks, scaled by compute units / threads: the cost estimates of
+    // both resources are then each resource's wall time per tuple times the same constant
+    ticks[h] = (unsigned long long)(tot / s->tick_us * (double)s->n_cu / (double)s->host_threads);
+    HIP_TRY(hipMemcpyAsync(s->d_dec + h * s->h_cap, dec, n, hipMemcpyHostToDevice, s->copy_stream));
+  }
+  HIP_TRY(hipEventRecord(s->h_done, s->copy_stream));
+  HIP_TRY(hipStreamWaitEvent(st, s->h_done, 0));
+  for (size_t h = 0; h < s->host_preds.size(); ++h) {
+    const int k = s->host_preds[h];
+    const int64_t n = s->h_counts[k];
+    if (n == 0) continue;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)s->n_cu * 4);
+    hipLaunchKernelGGL(k_apply_host, dim3(grid), dim3(256), 0, st, Queues{s->q1, s->st->qcount, s->cap}, k,
+                       s->d_dec + h * s->h_cap, f, ticks[h]);
+  }
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
 int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float* thresholds, int32_t n_seg,
                        int64_t seg_len) {
   g_err.clear();
@@ -1710,6 +1930,9 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   if (fr.where != HYDRO_MEM_DEVICE && fr.where != HYDRO_MEM_HOST) return fail(HYDRO_EINVAL, "unknown frame location");
   if (fr.n > 0 && !fr.data) return fail(HYDRO_EINVAL, "frame data is NULL");
   if (fr.id_base < 0) return fail(HYDRO_EINVAL, "negative id_base");
+  const bool host_mode = !s->host_preds.empty();
+  if (host_mode && fr.where != HYDRO_MEM_HOST && !fr.host_data)
+    return fail(HYDRO_EUNSUPPORTED, "a session with HOST predicates takes frames in host memory (or host_data)");
   int rc = ensure_dtype(s, fr.dtype);
   if (rc) return rc;
   for (int64_t i = 0; i < (int64_t)n_seg * s->K; ++i)
@@ -1806,7 +2029,9 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   const int64_t nwords = (n + 31) / 32;
 
   // Every device step of the push, in stream order.  Host state is not touched here, so the
-  // same sequence can be captured once into a HIP graph and replayed.
+  // same sequence can be captured once into a HIP graph and replayed (sessions with HOST
+  // predicates excepted: each round waits for the CPU's decisions, so they run eagerly).
+  int host_rc = HYDRO_OK;
   auto enqueue_push = [&](bool timed) {
     if (nwords > 0) hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(1024, (nwords + 255) / 256)), dim3(256), 0, st,
                                        s->result_bits, 0u, nwords);
@@ -1876,6 +2101,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       const int route_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * 2,
                                                                           (live_bound + kRouteChunk - 1) / kRouteChunk));
       hipLaunchKernelGGL(k_route, dim3(route_grid), dim3(kRouteThreads), 0, st, ra);
+      if (host_mode && !host_rc) host_rc = host_round_copy(s, st);
       if (timed && ev[1]) hipEventRecord(ev[1], st);
 
       // tier chain: first pass, [BF16 re-score of an FP8 first pass], [FP32 re-score of a
@@ -1893,6 +2119,9 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
         }
         if (timed && ev[2 + ci]) hipEventRecord(ev[2 + ci], st);
       }
+      if (host_mode && !host_rc)
+        host_rc = host_round_decide(s, st, fr, s->theta_host.back().data(), n_seg, seg_len,
+                                    make_forward(s, TIER_FIRST, out_slot, src, n_seg, seg_len, fr.id_base));
       if (s->rnn) router_nn_learn(s->rnn, s->st, st);
       parity ^= 1;
     }
@@ -1916,7 +2145,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
     }
   };
 
-  const bool graphable = s->pol.use_graph && fr.where == HYDRO_MEM_DEVICE && !timing;
+  const bool graphable = s->pol.use_graph && fr.where == HYDRO_MEM_DEVICE && !timing && !host_mode;
   if (graphable) {
     GraphKey key{n, src.base, fr.id_base, n_seg, seg_len, (int)warm_now, parity0, learned_from, s->theta, s->out_ids};
     hipGraphExec_t exec = nullptr;
@@ -1939,6 +2168,7 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
     HIP_TRY(hipGraphLaunch(exec, st));
   } else {
     enqueue_push(timing);
+    if (host_rc) return host_rc;
   }
   if (warm_now) s->warmed = true;
   s->parity = parity0 ^ (n_rounds & 1);
@@ -2073,6 +2303,7 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   if (!s || !frames || !out_logits) return fail(HYDRO_EINVAL, "NULL argument");
   if (pred < 0 || pred >= s->K) return fail(HYDRO_EINVAL, "predicate index out of range");
   if (tier < 0 || tier > 3) return fail(HYDRO_EINVAL, "tier must be 0, 1, 2 or 3");
+  if (s->models[pred].m.arch == HYDRO_ARCH_HOST) return fail(HYDRO_EUNSUPPORTED, "a HOST predicate has no logits");
   if (tier == 3 && s->pol.precision != HYDRO_PREC_FP8) tier = s->pol.precision == HYDRO_PREC_BF16 ? 0 : 1;
   if (s->in_query)
     return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): logits and "
@@ -2151,6 +2382,10 @@ static int measure_bands(hydro_session* s, const hydro_frames* frames, float saf
   std::vector<double> z0((size_t)blk * kClasses), zm((size_t)blk * kClasses), z1((size_t)blk * kClasses),
       z2((size_t)blk * kClasses);
   for (int k = 0; k < s->K; ++k) {
+    if (s->models[k].m.arch == HYDRO_ARCH_HOST) {    // decided exactly on the CPU: no band
+      tau[k] = tau16[k] = tau32[k] = 0.f;
+      continue;
+    }
     const uint32_t mask = s->models[k].m.class_mask;
     double e0 = 0, em = 0, e1 = 0;
     for (int64_t i0 = 0; i0 < n; i0 += blk) {

@@ -21,7 +21,7 @@ MAX_LAYERS = 4
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ECAPACITY, ESTATE = 0, -1, -2, -3, -4, -5, -6
 DTYPE_F32, DTYPE_BF16, DTYPE_U8 = 0, 1, 2
 MEM_DEVICE, MEM_HOST = 0, 1
-ARCH_MLP, ARCH_CNN = 0, 1
+ARCH_MLP, ARCH_CNN, ARCH_HOST = 0, 1, 2
 ROUTE_FIXED, ROUTE_SEL, ROUTE_SCORE, ROUTE_COST, ROUTE_LEARNED = 0, 1, 2, 3, 4
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 COST_MEASURED, COST_STATIC = 0, 1
@@ -40,7 +40,7 @@ class HydroError(RuntimeError):
 
 class Frames(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("where", C.c_int32), ("n", C.c_int64),
-                ("h", C.c_int32), ("w", C.c_int32), ("id_base", C.c_int64)]
+                ("h", C.c_int32), ("w", C.c_int32), ("id_base", C.c_int64), ("host_data", C.c_void_p)]
 
 
 FP = C.POINTER(C.c_float)
@@ -51,7 +51,8 @@ class Model(C.Structure):
                 ("w1", FP), ("b1", FP), ("w2", FP), ("b2", FP),
                 ("n_layers", C.c_int32), ("widths", C.c_int32 * MAX_LAYERS),
                 ("conv_w", FP * MAX_LAYERS), ("conv_b", FP * MAX_LAYERS),
-                ("fc_w", FP), ("fc_b", FP), ("class_mask", C.c_uint32)]
+                ("fc_w", FP), ("fc_b", FP), ("class_mask", C.c_uint32),
+                ("color_lo", C.c_float * 3), ("color_hi", C.c_float * 3), ("color_stride", C.c_int32)]
 
 
 class Policy(C.Structure):
@@ -166,11 +167,20 @@ class ModelSpec:
         self.arch, self.in_hw, self.class_mask = arch, in_hw, int(class_mask)
         self.hidden, self.widths = hidden, tuple(widths)
         f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
-        if arch == "mlp":
+        if arch == "host":
+            self.t = {"lo": [float(x) for x in tensors["lo"]], "hi": [float(x) for x in tensors["hi"]],
+                      "stride": int(tensors.get("stride", 1))}
+        elif arch == "mlp":
             self.t = {k: f32(tensors[k]) for k in ("W1", "b1", "W2", "b2")}
         else:
             self.t = {"convs": [(f32(w), f32(b)) for w, b in tensors["convs"]],
                       "Wfc": f32(tensors["Wfc"]), "bfc": f32(tensors["bfc"])}
+
+    @classmethod
+    def host_color(cls, in_hw: int, lo: Sequence[float], hi: Sequence[float], stride: int = 1) -> "ModelSpec":
+        """A HOST predicate: the fraction of sampled pixels (every stride-th row and column) inside
+        the channel box [lo, hi], decided by CPU threads."""
+        return cls("host", in_hw, 0, {"lo": lo, "hi": hi, "stride": stride})
 
     @classmethod
     def from_weights(cls, weights, class_mask: int) -> "ModelSpec":
@@ -185,7 +195,12 @@ class ModelSpec:
         m = Model()
         m.in_h = m.in_w = self.in_hw
         m.class_mask = self.class_mask
-        if self.arch == "mlp":
+        if self.arch == "host":
+            m.arch = ARCH_HOST
+            for c in range(3):
+                m.color_lo[c], m.color_hi[c] = self.t["lo"][c], self.t["hi"][c]
+            m.color_stride = self.t["stride"]
+        elif self.arch == "mlp":
             m.arch = ARCH_MLP
             m.hidden = self.hidden
             m.w1, m.b1, m.w2, m.b2 = (_fp(self.t[k]) for k in ("W1", "b1", "W2", "b2"))
@@ -257,11 +272,17 @@ class Session:
         self._keep = []
         _check(lib().hydro_session_reset(self._h))
 
-    def push(self, frames, dtype: str, thresholds: np.ndarray, seg_len: int, id_base: int = 0):
+    def push(self, frames, dtype: str, thresholds: np.ndarray, seg_len: int, id_base: int = 0, host_copy=None):
+        """host_copy: the same frames in host memory (numpy or CPU tensor) for HOST predicates when
+        `frames` is on the device."""
         th = np.ascontiguousarray(thresholds, dtype=np.float32)
         if th.ndim == 1:
             th = th[None, :]
         fr = _frames_struct(frames, dtype, id_base)
+        if host_copy is not None:
+            hc = host_copy if hasattr(host_copy, "data_ptr") else np.ascontiguousarray(host_copy)
+            fr.host_data = hc.data_ptr() if hasattr(hc, "data_ptr") else hc.ctypes.data
+            self._keep.append(hc)
         self._keep.append((frames, th))
         _check(lib().hydro_session_push(self._h, C.byref(fr), _fp(th), th.shape[0], int(seg_len)))
 

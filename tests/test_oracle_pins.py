@@ -466,3 +466,63 @@ def test_cached_decision_brute_force():
             assert decided == (len(outs) == 1), (tc, passed, t)
             if decided:
                 assert {p} == outs
+
+
+def test_color_fraction_hand_pin():
+    """A 2x2 frame with one pixel inside the box on every channel, one outside on one channel,
+    one exactly on the box's edges (inside: the bounds are inclusive), one far outside."""
+    px = np.array([[[0.5, 0.5, 0.5], [0.5, 0.9, 0.5]],
+                   [[0.25, 0.75, 0.25], [0.0, 0.0, 0.0]]], dtype=np.float32)[None]
+    d = ho.color_fraction(px, "f32", [0.25, 0.25, 0.25], [0.75, 0.75, 0.75])
+    assert d.tolist() == [0.5]
+    # uint8 values are v / 255: 64 / 255 is just above 0.25, 63 / 255 just below
+    u8 = np.array([[[[64, 64, 64], [63, 64, 64]]]], dtype=np.uint8)
+    assert ho.color_fraction(u8, "u8", [0.25] * 3, [1.0] * 3).tolist() == [0.5]
+
+
+def test_concurrent_makespan_paper_example():
+    """Section 4.1's example: colour classifier (CPU, cost 1, selectivity 0.6) and breed classifier
+    (GPU, cost 2, selectivity 0.1) running concurrently on 10 tuples: breed first takes 20 time
+    units, colour first 14.  The pass patterns are this build's reading of the figure (the one
+    breed pass is not the last tuple; the six colour passes are tuples 2, 3, 5, 6, 8, 10)."""
+    P = np.zeros((10, 2), dtype=bool)           # column 0: colour, column 1: breed
+    P[[1, 2, 4, 5, 7, 9], 0] = True
+    P[[1, 2, 4, 5, 7, 9][:1], 1] = True
+    assert ho.concurrent_makespan([1, 0], P, [1.0, 2.0]) == 20.0
+    assert ho.concurrent_makespan([0, 1], P, [1.0, 2.0]) == 14.0
+    # the policies: selectivity and score put breed first, cost puts colour first
+    cost, sel = [1.0, 2.0], [0.6, 0.1]
+    assert ho.policy_first(ho.POLICY_SEL, cost, sel) == 1
+    assert ho.policy_first(ho.POLICY_SCORE, cost, sel) == 1
+    assert ho.policy_first(ho.POLICY_COST, cost, sel) == 0
+
+
+def test_concurrent_makespan_brute_force_small():
+    """Against an explicit event list on a tiny case with a tuple arriving while the second worker
+    is busy (FIFO waits) and one arriving while it is idle."""
+    P = np.array([[1, 1], [0, 1], [1, 1], [1, 0]], dtype=bool)
+    # first stage (cost 3): ends 3, 6, 9, 12; passes tuples 0, 2, 3 -> arrive 3, 9, 12
+    # second stage (cost 5): 3 -> 8, 9 -> 14, 14 -> 19
+    assert ho.concurrent_makespan([0, 1], P, [3.0, 5.0]) == 19.0
+
+
+def test_ab_sweep_cost_policy_never_worse():
+    """The A/B sweep of section 4.1 on the concurrent model: A costs 10, B 20 (separate resources),
+    selectivity of A from 0.1 to 0.9, of B 0.1, 0.5 and 0.9, 2,000 tuples with independent
+    outcomes: the cost-driven first choice is never slower than the score- or selectivity-driven
+    one (up to one tuple's pipeline fill), and the selectivity-driven one is the slowest on
+    average."""
+    rng = np.random.default_rng(17)
+    cost = [10.0, 20.0]
+    tot = {ho.POLICY_COST: 0.0, ho.POLICY_SCORE: 0.0, ho.POLICY_SEL: 0.0}
+    for sb in (0.1, 0.5, 0.9):
+        for sa in np.arange(0.1, 0.91, 0.1):
+            P = np.stack([rng.random(2000) < sa, rng.random(2000) < sb], axis=1)
+            sel = [P[:, 0].mean(), P[:, 1].mean()]
+            ms = {}
+            for pol in tot:
+                first = ho.policy_first(pol, cost, sel)
+                ms[pol] = ho.concurrent_makespan([first, 1 - first], P, cost)
+                tot[pol] += ms[pol]
+            assert ms[ho.POLICY_COST] <= min(ms[ho.POLICY_SCORE], ms[ho.POLICY_SEL]) + max(cost)
+    assert tot[ho.POLICY_SEL] >= tot[ho.POLICY_SCORE] >= tot[ho.POLICY_COST]
