@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--no-compaction", action="store_true", help="skip the standalone routing/compaction run")
     ap.add_argument("--no-reuse", action="store_true", help="skip the result-reuse (recurrent query) run")
     ap.add_argument("--no-concurrent", action="store_true", help="skip the concurrent host/GPU predicate run")
+    ap.add_argument("--no-variable", action="store_true", help="skip the variable-size (crop) run")
+    ap.add_argument("--variable-only", action="store_true", help="run only the variable-size (crop) run")
     ap.add_argument("--concurrent-only", action="store_true", help="run only the concurrent host/GPU predicate run")
     ap.add_argument("--concurrent-points", type=lambda v: [tuple(float(x) for x in p.split(":")) for p in v.split(",")],
                     default=[(0.0, 0.05), (0.1, 0.05), (0.2, 0.05), (0.1, 0.12)],
@@ -605,6 +607,55 @@ def concurrent_leg(args, hydro, torch, hs):
                     "units (host: thread time x compute units / threads)"}
 
 
+def variable_leg(args, hydro, torch, hs):
+    """Variable-size inputs (section 5.3): a CNN (16, 32, 64) on each tuple's crop of the
+    65,536-frame workload's frames, crop sides log-uniform from 2 to 64 (many small crops, a few
+    large: the work per tuple spans three orders of magnitude).  Query time with the round's
+    tuples dealt to the workgroups in queue order against largest-estimated-work-first from a
+    shared counter (the input-size heuristic), at two admission wave sizes (fewer tuples per
+    workgroup and round make the imbalance of a fixed assignment larger).  Median of 3 queries."""
+    cfg = hs.workload(2)
+    n = cfg.n
+    frames = make_device_frames(hs, torch, cfg, n)
+    pt = hs.load_predicates(cfg)
+    w0 = hs.make_model(cfg.models[0])
+    rng = np.random.default_rng(23)
+    side = cfg.hw
+    hh = np.minimum(side, np.round(np.exp(rng.uniform(np.log(2), np.log(side), n)))).astype(np.int32)
+    ww = np.minimum(side, np.round(np.exp(rng.uniform(np.log(2), np.log(side), n)))).astype(np.int32)
+    crops = np.stack([(rng.random(n) * (side - hh + 1)).astype(np.int32),
+                      (rng.random(n) * (side - ww + 1)).astype(np.int32), hh, ww], axis=1).astype(np.int32)
+    spec = hydro.ModelSpec.from_weights(w0, pt.class_masks[0], on_crop=True, in_hw=side)
+    th = np.zeros((1, 1), dtype=np.float32)
+    out = {"workload": f"{cfg.name}: {n} frames, one crop per tuple (sides log-uniform 2..{side})",
+           "predicate": "CNN (16, 32, 64) on the crop, FP64", "points": []}
+    ids_ref = None
+    for wave in (2048, 16384):
+        pt_out = {"wave": wave, "ms": {}}
+        for balance in (0, 1):
+            s = hydro.Session([spec], hydro.make_policy("score", wave=wave, balance=balance), side, n)
+            times = []
+            for rep in range(4):
+                s.reset()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.push(frames, cfg.dtype, th, n, crops=crops)
+                ids, st = s.finish()
+                if rep > 0:
+                    times.append(time.perf_counter() - t0)
+            s.close()
+            if ids_ref is None:
+                ids_ref = ids
+            assert np.array_equal(ids, ids_ref), "the two schedules disagree"
+            pt_out["ms"]["data_aware" if balance else "queue_order"] = float(np.median(times)) * 1e3
+        pt_out["speedup"] = pt_out["ms"]["queue_order"] / pt_out["ms"]["data_aware"]
+        out["points"].append(pt_out)
+    out["n_result"] = int(ids_ref.size)
+    del frames
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -627,6 +678,9 @@ def main():
     if args.compaction_only:
         print(json.dumps({"compaction": compaction(args, hydro, torch)}), flush=True)
         return
+    if args.variable_only:
+        print(json.dumps({"variable": variable_leg(args, hydro, torch, hs)}), flush=True)
+        return
     if args.concurrent_only:
         print(json.dumps({"concurrent": concurrent_leg(args, hydro, torch, hs)}), flush=True)
         return
@@ -644,6 +698,9 @@ def main():
     if not args.no_concurrent:
         log("[bench] concurrent host and GPU predicates")
         out["concurrent"] = concurrent_leg(args, hydro, torch, hs)
+    if not args.no_variable:
+        log("[bench] variable-size inputs")
+        out["variable"] = variable_leg(args, hydro, torch, hs)
     if not args.no_compaction:
         log("[bench] standalone routing / compaction")
         out["compaction"] = compaction(args, hydro, torch)

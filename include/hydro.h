@@ -69,6 +69,8 @@ typedef struct {
   int64_t id_base;
   const void* host_data;   /* optional, with where == DEVICE: the same frames in host memory, read by
                               HOST predicates (NULL: none); borrowed until hydro_session_finish     */
+  const int32_t* crops;    /* optional, host memory [n][4]: tuple i's crop (y0, x0, h, w) of its frame,
+                              the input of predicates with on_crop = 1 (NULL: none); copied         */
 } hydro_frames;
 
 typedef enum { HYDRO_ARCH_MLP = 0, HYDRO_ARCH_CNN = 1, HYDRO_ARCH_HOST = 2 } hydro_arch;
@@ -99,6 +101,11 @@ typedef enum { HYDRO_ARCH_MLP = 0, HYDRO_ARCH_CNN = 1, HYDRO_ARCH_HOST = 2 } hyd
  *   either resource's figure reads as that resource's wall time per tuple times the same
  *   constant (STATIC cost source: 6 operations per sampled pixel).  No weights,
  *   class_mask unused; not with route = LEARNED; pushes are not captured in graphs.
+ * CNN with on_crop = 1: the same layers on the crop (y0, x0, h, w) of the tuple's frame, zero
+ *   padding at the crop's border (the crop is the image), the mean over the crop's final positions,
+ *   FC; any crop size from 1 x 1 to the frame (widths at most 256).  Evaluated in FP64 on the GPU
+ *   (its decisions are final), one workgroup per tuple; work per tuple follows the crop's area, so
+ *   policy.balance chooses how the tuples of a round are dealt to the workgroups.
  * Weights are copied (and re-packed per precision) when a session is created. */
 typedef struct {
   int32_t arch;
@@ -114,6 +121,9 @@ typedef struct {
   float color_lo[3], color_hi[3];   /* HOST: the channel box */
   int32_t color_stride;             /* HOST: pixels sampled every stride-th row and column
                                        (0 or 1: every pixel)                                     */
+  int32_t on_crop;                  /* CNN: 1 = the input is the tuple's crop (hydro_frames.crops),
+                                       a variable-size image (section 5.3: UDF composition such as
+                                       a classifier on Crop(frame, bbox)); see below             */
 } hydro_model;
 
 typedef enum {
@@ -185,6 +195,13 @@ typedef struct {
   int32_t cache_log2;                    /* reuse > 0: log2 of the cache slots per predicate
                                             (16 B each; 0: default 22, at most 28); a decision is
                                             not cached when its 16 probe slots are taken          */
+  int32_t balance;                       /* on_crop predicates (section 5.3, "Data-Aware Load
+                                            Balancing"): 0 (default) = each round's tuples dealt
+                                            to the workgroups in queue order, round robin;
+                                            1 = data-aware: ordered by estimated work (the crop's
+                                            area, the input-size heuristic), largest first, each
+                                            workgroup taking the next from a shared counter      */
+  int32_t pad2_;
 } hydro_policy;
 
 /* Per-predicate statistics of one query. */

@@ -38,6 +38,8 @@ function follows:
   the colour classifier runs on the CPU concurrently with the breed model on
   the GPU); this build's reading is a channel box, the fraction of pixels whose
   three values all lie inside it, compared with theta like the UDF margins.
+* ``crop_logits``: a CNN on each tuple's crop of its frame, the variable-size
+  inputs of section 5.3 (UDF composition, a classifier on Crop(frame, bbox)).
 * ``replay_route``: checks a per-tuple visit sequence against the routing
   rules of section 3.3 ("Metadata for Data Routing": a batch visits each
   predicate at most once and is complete when all are visited; "Eager
@@ -166,6 +168,18 @@ def model_logits(model, frames: np.ndarray, dtype: str, chunk: int = 0, workers:
     with threadpool_limits(1):
         with ThreadPoolExecutor(workers) as ex:
             list(ex.map(job, range(0, n, chunk)))
+    return out
+
+
+def crop_logits(model, frames: np.ndarray, dtype: str, crops: np.ndarray) -> np.ndarray:
+    """fp64 logits [n][10] of a CNN model applied to each tuple's crop (y0, x0, h, w) of its
+    frame: the crop is the image (zero padding at its border in normalised space), the mean runs
+    over the crop's final positions (section 5.3: a classifier on Crop(frame, bbox))."""
+    t64 = _f64_tensors(model.tensors)
+    out = np.empty((frames.shape[0], N_CLASSES), dtype=np.float64)
+    for i, (y0, x0, h, w) in enumerate(np.asarray(crops, dtype=np.int64)):
+        xn = normalize(frames_to_f64(frames[i:i + 1, y0:y0 + h, x0:x0 + w], dtype))
+        out[i] = cnn_logits(t64, xn)[0]
     return out
 
 

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["engine.hip", "mlp.hip", "cnn.hip", "gcnn.hip", "cnn4.hip", "router_nn.hip"]
+SOURCES = ["engine.hip", "mlp.hip", "cnn.hip", "gcnn.hip", "cnn4.hip", "crop.hip", "router_nn.hip"]
 LIB = os.path.join(HERE, "libhydro.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -117,6 +117,30 @@ struct GcnnArgs {
   const void* zero_page;                       // 256 zero bytes (padding taps of the GEMM gathers)
 };
 
+// Grouped launch over the CNN predicates that take each tuple's crop (variable-size inputs).
+struct CropArgs {
+  int n_preds;
+  int pred[kMaxK];
+  uint32_t class_mask[kMaxK];
+  int n_layers[kMaxK];
+  int widths[kMaxK][HYDRO_MAX_LAYERS];
+  const float* wt[kMaxK][HYDRO_MAX_LAYERS];   // [co][3][3][ci] (channels last per tap), fp32
+  const float* bias[kMaxK][HYDRO_MAX_LAYERS];
+  const float* fc_w[kMaxK];                    // [c_last][10]
+  const float* fc_b[kMaxK];
+  const int32_t* crops;        // device copy of the push's crops [n][4]: y0, x0, h, w
+  Queues q;
+  FrameSrc fr;
+  int fh, fw;                  // frame side lengths
+  DevState* st;
+  double* scratch;             // per workgroup: two activation buffers of act_doubles each
+  int64_t act_doubles;
+  int balance;                 // 1: data-aware order (largest crop first, shared counter)
+  uint32_t* order;             // balance: queue positions by decreasing area, [kMaxK][cap]
+  int* next;                   // balance: the launch's work counter (set to 0 by the order kernel)
+};
+void launch_crop_pass(const CropArgs& a, const Forward& f, int grid, hipStream_t s);
+
 // Arithmetic tiers of the dedicated 4-layer CNN kernels.
 // C4_S3: FP32 arithmetic of the layer-3/4 GEMMs from bf16 MFMAs (fp32 activations split into
 // three bf16 terms on the fly, weights packed as three bf16 terms; see cnn4.hip).

@@ -739,6 +739,12 @@ struct hydro_session {
   hipEvent_t h_routed = nullptr, h_ready = nullptr, h_done = nullptr;
   int host_threads = 1;
   std::unique_ptr<HostPool> pool;
+  // CNN predicates on each tuple's crop (variable-size inputs)
+  CropArgs crop{};
+  std::vector<int> crop_preds;
+  int32_t* crops_dev = nullptr;                 // the push's crops [max_push][4]
+  std::deque<std::vector<int32_t>> crops_host;  // host copies until finish (async copies read them)
+  int crop_grid = 0;
 };
 
 // Captured pushes bake the bands (and every other launch argument) into their kernel nodes.
@@ -840,6 +846,11 @@ static int validate_model(const hydro_model& m, int fh, int fw) {
   for (int l = 0; l < m.n_layers; ++l)
     if (!m.conv_w[l] || !m.conv_b[l]) return fail(HYDRO_EINVAL, "CNN conv weight pointer is NULL");
   if (!m.fc_w || !m.fc_b) return fail(HYDRO_EINVAL, "CNN fc weight pointer is NULL");
+  if (m.on_crop) {      // variable-size inputs: any crop of the frame, FP64 kernel
+    for (int l = 0; l < m.n_layers; ++l)
+      if (m.widths[l] < 1 || m.widths[l] > 256) return fail(HYDRO_EUNSUPPORTED, "on_crop CNN widths must be 1..256");
+    return HYDRO_OK;
+  }
   if (m.in_w != m.in_h) return fail(HYDRO_EUNSUPPORTED, "CNN frames must be square");
   if (cnn_variant_of(m.in_h, m.n_layers, m.widths) != CNN_NONE) return HYDRO_OK;   // fused kernel
   // generic layer-wise path
@@ -913,6 +924,7 @@ static int pack_models(hydro_session* s) {
   MlpArgs& ma = s->mlp;
   CnnArgs& ca = s->cnn;
   ma = MlpArgs{};
+  s->crop.n_preds = 0;
   ca = CnnArgs{};
   s->gcnn = GcnnArgs{};
   ca.pad_raw = pad_raw;
@@ -936,6 +948,34 @@ static int pack_models(hydro_session* s) {
     HostModel& hm = s->models[k];
     const hydro_model& m = hm.m;
     if (m.arch == HYDRO_ARCH_HOST) continue;     // evaluated on the CPU (no device weights)
+    if (m.arch == HYDRO_ARCH_CNN && m.on_crop) {  // FP64 on each tuple's crop: canonical weights
+      CropArgs& cr = s->crop;
+      const int i = cr.n_preds++;
+      cr.pred[i] = k;
+      cr.class_mask[i] = m.class_mask;
+      cr.n_layers[i] = m.n_layers;
+      int cin = 3, rc;
+      for (int l = 0; l < m.n_layers; ++l) {
+        const int co = m.widths[l];
+        cr.widths[i][l] = co;
+        std::vector<float> wt(hm.cw[l].size());
+        for (int o = 0; o < co; ++o)
+          for (int c = 0; c < cin; ++c)
+            for (int t = 0; t < 9; ++t) wt[((size_t)o * 9 + t) * cin + c] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
+        float* dp;
+        if ((rc = upload(s, wt.data(), wt.size(), &dp))) return rc;
+        cr.wt[i][l] = dp;
+        if ((rc = upload(s, hm.cb[l].data(), hm.cb[l].size(), &dp))) return rc;
+        cr.bias[i][l] = dp;
+        cin = co;
+      }
+      float* dp;
+      if ((rc = upload(s, hm.fcw.data(), hm.fcw.size(), &dp))) return rc;
+      cr.fc_w[i] = dp;
+      if ((rc = upload(s, hm.fcb.data(), hm.fcb.size(), &dp))) return rc;
+      cr.fc_b[i] = dp;
+      continue;
+    }
     if (m.arch == HYDRO_ARCH_MLP) {
       const int D = m.in_h * m.in_w * 3, H = m.hidden;
       std::vector<float> wt((size_t)H * D), b1f(H);
@@ -1362,7 +1402,8 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
       }
       hm.fcw.assign(m.fc_w, m.fc_w + (size_t)cin * kClasses);
       hm.fcb.assign(m.fc_b, m.fc_b + kClasses);
-      hm.variant = cnn_variant_of(m.in_h, m.n_layers, m.widths);
+      hm.variant = m.on_crop ? CNN_NONE : cnn_variant_of(m.in_h, m.n_layers, m.widths);
+      if (m.on_crop) s->crop_preds.push_back(i);
     }
   }
   auto bail = [&](int code) {
@@ -1431,6 +1472,31 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
     if (he != hipSuccess) return bail(fail(HYDRO_ENOMEM, "result buffer allocation failed"));
   }
   s->out_cap = cap;
+  if (!s->crop_preds.empty()) {
+    // activations of the largest crop (the whole frame), two buffers per workgroup
+    int64_t act = 0;
+    for (int k : s->crop_preds) {
+      const hydro_model& m = s->models[k].m;
+      int h = frame_h, w = frame_w;
+      for (int l = 0; l < m.n_layers; ++l) {
+        h = (h + 1) / 2;
+        w = (w + 1) / 2;
+        act = std::max<int64_t>(act, (int64_t)h * w * m.widths[l]);
+      }
+    }
+    s->crop_grid = s->n_cu * 2;
+    CropArgs& ca = s->crop;
+    ca.act_doubles = (act + 31) / 32 * 32;
+    ca.fh = frame_h;
+    ca.fw = frame_w;
+    ca.balance = s->pol.balance;
+    if ((rc = sess_alloc(s, (void**)&s->crops_dev, (size_t)cap * 4 * sizeof(int32_t)))) return bail(rc);
+    if ((rc = sess_alloc(s, (void**)&ca.scratch, (size_t)s->crop_grid * 2 * ca.act_doubles * sizeof(double))))
+      return bail(rc);
+    if ((rc = sess_alloc(s, (void**)&ca.order, (size_t)s->crop_preds.size() * cap * sizeof(uint32_t)))) return bail(rc);
+    if ((rc = sess_alloc(s, (void**)&ca.next, 256))) return bail(rc);
+    ca.crops = s->crops_dev;
+  }
   if (!s->host_preds.empty()) {
     if (s->pol.route == HYDRO_ROUTE_LEARNED)
       return bail(fail(HYDRO_EUNSUPPORTED, "HOST predicates are not combined with the learned router"));
@@ -1490,6 +1556,7 @@ int hydro_session_reset(hydro_session* s) {
   s->ids_sorted = true;
   s->last_id_end = INT64_MIN;
   s->theta_host.clear();
+  s->crops_host.clear();
   s->info = hydro_query_info{};
   s->ev_used = 0;
   if (s->rnn) {
@@ -1555,6 +1622,13 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
 static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const Forward& f, hipStream_t st) {
   Queues q;
   if (tier == TIER_FIRST) q = Queues{s->q1, s->st->qcount, s->cap};
+  if (tier == TIER_FIRST && s->crop.n_preds) {     // FP64 on crops: final decisions, first tier only
+    CropArgs a = s->crop;
+    a.q = q;
+    a.fr = fr;
+    a.st = s->st;
+    launch_crop_pass(a, f, s->crop_grid, st);
+  }
   else if (tier == TIER_F32) q = Queues{s->q2, s->st->bcount, s->cap};
   else if (tier == TIER_MID) q = Queues{s->qm, s->st->mcount, s->cap};
   else q = Queues{s->q3, s->st->ecount, s->cap};
@@ -1931,6 +2005,14 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
   if (fr.n > 0 && !fr.data) return fail(HYDRO_EINVAL, "frame data is NULL");
   if (fr.id_base < 0) return fail(HYDRO_EINVAL, "negative id_base");
   const bool host_mode = !s->host_preds.empty();
+  if (!s->crop_preds.empty()) {
+    if (!fr.crops) return fail(HYDRO_EINVAL, "the session has on_crop predicates: the push needs crops");
+    for (int64_t i = 0; i < fr.n; ++i) {
+      const int32_t* c = fr.crops + 4 * i;
+      if (c[0] < 0 || c[1] < 0 || c[2] < 1 || c[3] < 1 || (int64_t)c[0] + c[2] > fr.h || (int64_t)c[1] + c[3] > fr.w)
+        return fail(HYDRO_EINVAL, "crop " + std::to_string(i) + " is not a non-empty box inside its frame");
+    }
+  }
   if (host_mode && fr.where != HYDRO_MEM_HOST && !fr.host_data)
     return fail(HYDRO_EUNSUPPORTED, "a session with HOST predicates takes frames in host memory (or host_data)");
   int rc = ensure_dtype(s, fr.dtype);
@@ -1958,6 +2040,11 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
     s->theta_cap = n_seg * s->K;
   }
   s->theta_host.emplace_back(thresholds, thresholds + (size_t)n_seg * s->K);
+  if (!s->crop_preds.empty() && fr.n > 0) {
+    s->crops_host.emplace_back(fr.crops, fr.crops + 4 * fr.n);
+    HIP_TRY(hipMemcpyAsync(s->crops_dev, s->crops_host.back().data(), (size_t)fr.n * 4 * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipMemcpyAsync(s->theta, s->theta_host.back().data(), (size_t)n_seg * s->K * sizeof(float),
                          hipMemcpyHostToDevice, st));
 
@@ -2260,6 +2347,7 @@ static int finish_query(hydro_session* s, int64_t** alloc_out, int64_t* dst, int
   if (alloc_out) *alloc_out = ids;
   *out_n = nres;
   s->theta_host.clear();
+  s->crops_host.clear();
   s->in_query = false;
   return HYDRO_OK;
 }
@@ -2304,6 +2392,7 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   if (pred < 0 || pred >= s->K) return fail(HYDRO_EINVAL, "predicate index out of range");
   if (tier < 0 || tier > 3) return fail(HYDRO_EINVAL, "tier must be 0, 1, 2 or 3");
   if (s->models[pred].m.arch == HYDRO_ARCH_HOST) return fail(HYDRO_EUNSUPPORTED, "a HOST predicate has no logits");
+  if (s->models[pred].m.on_crop) return fail(HYDRO_EUNSUPPORTED, "an on_crop predicate takes crops: no whole-frame logits");
   if (tier == 3 && s->pol.precision != HYDRO_PREC_FP8) tier = s->pol.precision == HYDRO_PREC_BF16 ? 0 : 1;
   if (s->in_query)
     return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): logits and "
@@ -2382,7 +2471,7 @@ static int measure_bands(hydro_session* s, const hydro_frames* frames, float saf
   std::vector<double> z0((size_t)blk * kClasses), zm((size_t)blk * kClasses), z1((size_t)blk * kClasses),
       z2((size_t)blk * kClasses);
   for (int k = 0; k < s->K; ++k) {
-    if (s->models[k].m.arch == HYDRO_ARCH_HOST) {    // decided exactly on the CPU: no band
+    if (s->models[k].m.arch == HYDRO_ARCH_HOST || s->models[k].m.on_crop) {   // exact decisions: no band
       tau[k] = tau16[k] = tau32[k] = 0.f;
       continue;
     }

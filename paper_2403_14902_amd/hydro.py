@@ -40,7 +40,8 @@ class HydroError(RuntimeError):
 
 class Frames(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("where", C.c_int32), ("n", C.c_int64),
-                ("h", C.c_int32), ("w", C.c_int32), ("id_base", C.c_int64), ("host_data", C.c_void_p)]
+                ("h", C.c_int32), ("w", C.c_int32), ("id_base", C.c_int64), ("host_data", C.c_void_p),
+                ("crops", C.c_void_p)]
 
 
 FP = C.POINTER(C.c_float)
@@ -52,7 +53,8 @@ class Model(C.Structure):
                 ("n_layers", C.c_int32), ("widths", C.c_int32 * MAX_LAYERS),
                 ("conv_w", FP * MAX_LAYERS), ("conv_b", FP * MAX_LAYERS),
                 ("fc_w", FP), ("fc_b", FP), ("class_mask", C.c_uint32),
-                ("color_lo", C.c_float * 3), ("color_hi", C.c_float * 3), ("color_stride", C.c_int32)]
+                ("color_lo", C.c_float * 3), ("color_hi", C.c_float * 3), ("color_stride", C.c_int32),
+                ("on_crop", C.c_int32)]
 
 
 class Policy(C.Structure):
@@ -62,7 +64,7 @@ class Policy(C.Structure):
                 ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
                 ("time_kernels", C.c_int32), ("autotune", C.c_int32),
                 ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p), ("tau16", C.c_float),
-                ("reuse", C.c_int32), ("cache_log2", C.c_int32)]
+                ("reuse", C.c_int32), ("cache_log2", C.c_int32), ("balance", C.c_int32), ("pad2_", C.c_int32)]
 
 
 class PredStats(C.Structure):
@@ -163,8 +165,9 @@ class ModelSpec:
     """A predicate model held as contiguous fp32 numpy arrays (kept alive by this object)."""
 
     def __init__(self, arch: str, in_hw: int, class_mask: int, tensors: dict, hidden: int = 0,
-                 widths: Sequence[int] = ()):
+                 widths: Sequence[int] = (), on_crop: bool = False):
         self.arch, self.in_hw, self.class_mask = arch, in_hw, int(class_mask)
+        self.on_crop = bool(on_crop)
         self.hidden, self.widths = hidden, tuple(widths)
         f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
         if arch == "host":
@@ -183,9 +186,12 @@ class ModelSpec:
         return cls("host", in_hw, 0, {"lo": lo, "hi": hi, "stride": stride})
 
     @classmethod
-    def from_weights(cls, weights, class_mask: int) -> "ModelSpec":
-        """From a ``hydro_synth.ModelWeights``."""
+    def from_weights(cls, weights, class_mask: int, on_crop: bool = False, in_hw: int = 0) -> "ModelSpec":
+        """From a ``hydro_synth.ModelWeights`` (on_crop: a CNN on each tuple's crop of frames of
+        side in_hw)."""
         d = weights.desc
+        if on_crop:
+            return cls("cnn", in_hw or d.in_hw, class_mask, weights.tensors, widths=d.widths, on_crop=True)
         if d.arch == "mlp":
             hw = int(round((d.d_in / 3) ** 0.5))
             return cls("mlp", hw, class_mask, weights.tensors, hidden=d.hidden)
@@ -206,6 +212,7 @@ class ModelSpec:
             m.w1, m.b1, m.w2, m.b2 = (_fp(self.t[k]) for k in ("W1", "b1", "W2", "b2"))
         else:
             m.arch = ARCH_CNN
+            m.on_crop = int(self.on_crop)
             m.n_layers = len(self.widths)
             for i, w in enumerate(self.widths):
                 m.widths[i] = w
@@ -272,13 +279,19 @@ class Session:
         self._keep = []
         _check(lib().hydro_session_reset(self._h))
 
-    def push(self, frames, dtype: str, thresholds: np.ndarray, seg_len: int, id_base: int = 0, host_copy=None):
+    def push(self, frames, dtype: str, thresholds: np.ndarray, seg_len: int, id_base: int = 0, host_copy=None,
+             crops=None):
         """host_copy: the same frames in host memory (numpy or CPU tensor) for HOST predicates when
-        `frames` is on the device."""
+        `frames` is on the device.  crops: int32 [n][4] (y0, x0, h, w) per tuple for on_crop
+        predicates."""
         th = np.ascontiguousarray(thresholds, dtype=np.float32)
         if th.ndim == 1:
             th = th[None, :]
         fr = _frames_struct(frames, dtype, id_base)
+        if crops is not None:
+            cr = np.ascontiguousarray(crops, dtype=np.int32)
+            fr.crops = cr.ctypes.data
+            self._keep.append(cr)
         if host_copy is not None:
             hc = host_copy if hasattr(host_copy, "data_ptr") else np.ascontiguousarray(host_copy)
             fr.host_data = hc.data_ptr() if hasattr(hc, "data_ptr") else hc.ctypes.data

@@ -526,3 +526,24 @@ def test_ab_sweep_cost_policy_never_worse():
                 tot[pol] += ms[pol]
             assert ms[ho.POLICY_COST] <= min(ms[ho.POLICY_SCORE], ms[ho.POLICY_SEL]) + max(cost)
     assert tot[ho.POLICY_SEL] >= tot[ho.POLICY_SCORE] >= tot[ho.POLICY_COST]
+
+
+def test_crop_logits_whole_frame_and_torch():
+    """A crop covering the whole frame gives the frame's logits; a smaller crop equals torch
+    float64 conv2d (stride 2, padding 1) on the cropped, normalised image."""
+    torch = pytest.importorskip("torch")
+    cfg = hs.workload(2)
+    fr = hs.make_frames(cfg, 0, 3)
+    m = hs.make_model(cfg.models[0])
+    full = np.array([[0, 0, 64, 64]] * 3)
+    assert np.allclose(ho.crop_logits(m, fr, "bf16", full), ho.model_logits(m, fr, "bf16"), rtol=0, atol=1e-12)
+    crops = np.array([[5, 7, 19, 33], [0, 60, 64, 4], [30, 2, 1, 1]])
+    z = ho.crop_logits(m, fr, "bf16", crops)
+    for i, (y0, x0, h, w) in enumerate(crops):
+        x = torch.from_numpy(ho.normalize(ho.frames_to_f64(fr[i:i + 1, y0:y0 + h, x0:x0 + w], "bf16"))).permute(0, 3, 1, 2)
+        for wt, b in m.tensors["convs"]:
+            x = torch.relu(torch.nn.functional.conv2d(x, torch.from_numpy(wt.astype(np.float64)),
+                                                      torch.from_numpy(b.astype(np.float64)), stride=2, padding=1))
+        g = x.mean(dim=(2, 3))
+        zt = (g @ torch.from_numpy(m.tensors["Wfc"].astype(np.float64)) + torch.from_numpy(m.tensors["bfc"].astype(np.float64)))
+        assert np.allclose(z[i], zt.numpy()[0], rtol=0, atol=1e-12)
