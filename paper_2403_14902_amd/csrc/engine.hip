@@ -1622,6 +1622,9 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
 static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const Forward& f, hipStream_t st) {
   Queues q;
   if (tier == TIER_FIRST) q = Queues{s->q1, s->st->qcount, s->cap};
+  else if (tier == TIER_F32) q = Queues{s->q2, s->st->bcount, s->cap};
+  else if (tier == TIER_MID) q = Queues{s->qm, s->st->mcount, s->cap};
+  else q = Queues{s->q3, s->st->ecount, s->cap};
   if (tier == TIER_FIRST && s->crop.n_preds) {     // FP64 on crops: final decisions, first tier only
     CropArgs a = s->crop;
     a.q = q;
@@ -1629,9 +1632,6 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
     a.st = s->st;
     launch_crop_pass(a, f, s->crop_grid, st);
   }
-  else if (tier == TIER_F32) q = Queues{s->q2, s->st->bcount, s->cap};
-  else if (tier == TIER_MID) q = Queues{s->qm, s->st->mcount, s->cap};
-  else q = Queues{s->q3, s->st->ecount, s->cap};
   // grouped: one launch covers every predicate of an architecture; otherwise one launch per
   // predicate (the plain form)
   if (s->mlp.n_preds) {
