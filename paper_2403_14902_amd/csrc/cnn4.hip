@@ -520,12 +520,155 @@ template <int P> struct GemmShape<P, 3> {
   static constexpr int CIN = 128, COUT = 256, HIN = 16, HOUT = 8, BM = 128, BN = 256;
 };
 
+// Output channel held by row R of the BF16 third-convolution weight image.  In a 16x16 MFMA
+// tile, lane group g holds rows 4 g .. 4 g + 3 of the tile; with this order the four tiles of a
+// wave's 64 channels give lane group g channels 8 g .. 8 g + 7 (tiles 0, 1) and 32 + 8 g .. + 7
+// (tiles 2, 3), so each lane stores 16 contiguous bytes and a position's 64 channels are two
+// 64-byte runs per store instruction.
+__host__ __device__ inline int c4_l3_channel(int row) {
+  const int blk = row / 64, w = row % 64, nt = w / 16, i = w % 16;
+  return 64 * blk + (nt / 2) * 32 + 8 * (i / 4) + (nt % 2) * 4 + i % 4;
+}
+
 __host__ __device__ inline int c4_nkb(int prec, int layer) {
   const int cin = layer == 2 ? 64 : 128;
   const int bke = prec == C4_FP8 ? 128 : prec == C4_BF16 ? 64 : 32;   // FP32 and S3: 32
   return (9 * cin + bke - 1) / bke;
 }
 
+
+// Epilogue of one GEMM tile (acc: the 64 x 64 block of wave (wm, wn) of the tile).  Layer 3: bias +
+// ReLU, stored as the next layer's activations.  Layer 4: bias + ReLU, mean over each frame's 64
+// positions, this wave's share of the FC, then the margin and decision (or the logits).
+// PERM: the tile's channels follow c4_l3_channel (BF16 third convolution).
+template <int P, int LAYER, bool PERM = false>
+__device__ inline void c4_gemm_epilogue(const GcnnArgs& a, const Forward& f, const floatx4 (&acc)[4][4], int slot,
+                                        int k, int cb, int ebase, int64_t row0, int64_t rows, const float* ep_bias,
+                                        const float* ep_scale, const float* fcw_s, float (*zpart)[kClasses]) {
+  typedef typename C4T<P>::T T;
+  typedef GemmShape<P, LAYER> S;
+  constexpr int COUT = S::COUT, HOUT = S::HOUT, PP = HOUT * HOUT, BM = S::BM, BN = S::BN, WM = 64, WN = 64;
+  constexpr int MT = WM / 16, NT = WN / 16, WGM = BM / WM;
+  constexpr bool HEAD = LAYER == 3;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave % WGM, wn = wave / WGM;
+  if constexpr (PERM) {
+    static_assert(P == C4_BF16 && !HEAD, "permuted channels: BF16 third convolution");
+    __bf16* out = reinterpret_cast<__bf16*>(a.c4_act3);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int64_t row = row0 + wm * WM + mt * 16 + l16;
+      const bool valid = row < rows && ebase + row / PP < a.act_cap;
+      const int64_t e = valid ? row / PP : 0;
+      const int p = (int)(row % PP);
+      __bf16* o = out + ((int64_t)ebase + e) * (PP * COUT) + (int64_t)p * COUT + cb * BN;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {              // tiles 2h, 2h + 1: channels 32 h + 8 g .. + 7
+        const int cl = wn * WN + 32 * h + 8 * g;
+        const floatx4 b0 = *reinterpret_cast<const floatx4*>(ep_bias + cl);
+        const floatx4 b1 = *reinterpret_cast<const floatx4*>(ep_bias + cl + 4);
+        alignas(16) __bf16 v[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = static_cast<__bf16>(fmaxf(acc[2 * h][mt][r] + b0[r], 0.f));
+          v[4 + r] = static_cast<__bf16>(fmaxf(acc[2 * h + 1][mt][r] + b1[r], 0.f));
+        }
+        if (valid) *reinterpret_cast<uint4*>(o + cl) = *reinterpret_cast<const uint4*>(v);
+      }
+    }
+  } else if constexpr (!HEAD) {
+    T* out = reinterpret_cast<T*>(a.c4_act3);
+    const float inv_out = P == C4_FP8 ? 1.f / a.c4_ascale[slot][2] : 1.f;
+    unsigned* amax = a.c4_act_max ? a.c4_act_max + k * 4 + 2 : nullptr;
+    float m = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int64_t row = row0 + wm * WM + mt * 16 + l16;
+      const bool valid = row < rows && ebase + row / PP < a.act_cap;
+      const int64_t e = valid ? row / PP : 0;
+      const int p = (int)(row % PP);
+      T* o = out + ((int64_t)ebase + e) * (PP * COUT) + (int64_t)p * COUT;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int cl = wn * WN + nt * 16 + 4 * g;    // channel within the tile
+        const int ch = cb * BN + cl;
+        const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + cl);
+        floatx4 sc = {1.f, 1.f, 1.f, 1.f};
+        if constexpr (P == C4_FP8) sc = *reinterpret_cast<const floatx4*>(ep_scale + cl);
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float x = acc[nt][mt][r];
+          if constexpr (P == C4_FP8) x *= sc[r];
+          v[r] = fmaxf(x + bb[r], 0.f);
+          m = fmaxf(m, valid ? v[r] : 0.f);
+          v[r] *= inv_out;
+        }
+        if (valid) c4_store4<P>(o + ch, v[0], v[1], v[2], v[3]);
+      }
+    }
+    if constexpr (P == C4_F32 || P == C4_S3) c4_track_max(amax, m);
+  } else {
+    // wave (wm, wn): frame wm of the tile, channels wn*WN .. +WN-1.  Pool over the frame's 64
+    // positions, then this wave's share of FC.
+    const int64_t frow = row0 + wm * WM;             // first row of the frame
+    const bool fvalid = frow < rows;
+    float zc = 0.f;                                   // lane l16 < 10: class l16
+    const int cls = l16 < kClasses ? l16 : 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int chb = wn * WN + nt * 16 + 4 * g;
+      const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + chb);
+      floatx4 sc = {1.f, 1.f, 1.f, 1.f};
+      if constexpr (P == C4_FP8) sc = *reinterpret_cast<const floatx4*>(ep_scale + chb);
+      float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float x = acc[nt][mt][r];
+          if constexpr (P == C4_FP8) x *= sc[r];
+          s[r] += fmaxf(x + bb[r], 0.f);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float gch = row_sum16(s[r]) * (1.f / PP);
+        zc += gch * fcw_s[(chb + r) * kClasses + cls];
+      }
+    }
+    if (l16 >= kClasses) zc = 0.f;
+    // rows g = 0..3 hold different channel groups: add them
+    zc = (__shfl(zc, l16) + __shfl(zc, 16 + l16)) + (__shfl(zc, 32 + l16) + __shfl(zc, 48 + l16));
+    if (lane < kClasses) zpart[wave][lane] = zc;
+    __syncthreads();
+    if (wn == 0) {
+      bool pass = false, defer = false, active = false;
+      uint32_t e = 0;
+      if (fvalid) {
+        const int64_t ei = frow / PP;
+        e = a.q.entries[(int64_t)k * a.q.cap + ei];
+        if (lane == 0) {
+          active = true;
+          float z[kClasses];
+#pragma unroll
+          for (int c = 0; c < kClasses; ++c) {
+            float sum = 0.f;
+            for (int w2 = 0; w2 < BN / WN; ++w2) sum += zpart[wm + WGM * w2][c];
+            z[c] = sum + a.fc_b[slot][c];
+          }
+          const uint32_t idx = entry_idx(e);
+          if (f.logits != nullptr)
+            for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)z[c];
+          const float d = class_margin(z, a.class_mask[slot]);
+          const float th = theta_of(f, k, idx);
+          pass = d > th;
+          defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau[k];
+        }
+      }
+      if (f.logits == nullptr) forward_decision(f, k, e, active, defer, pass);
+    }
+  }
+}
 
 template <int P, int LAYER>
 __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
@@ -766,102 +909,238 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
       compute(kb % NS);
     }
 
-    // ---- epilogue
-    if constexpr (!HEAD) {
-      T* out = reinterpret_cast<T*>(a.c4_act3);
-      const float inv_out = P == C4_FP8 ? 1.f / a.c4_ascale[slot][2] : 1.f;
-      unsigned* amax = a.c4_act_max ? a.c4_act_max + k * 4 + 2 : nullptr;
-      float m = 0.f;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int64_t row = row0 + wm * WM + mt * 16 + l16;
-        const bool valid = row < rows && ebase + row / PP < a.act_cap;
-        const int64_t e = valid ? row / PP : 0;
-        const int p = (int)(row % PP);
-        T* o = out + ((int64_t)ebase + e) * (PP * COUT) + (int64_t)p * COUT;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int cl = wn * WN + nt * 16 + 4 * g;    // channel within the tile
-          const int ch = cb * BN + cl;
-          const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + cl);
-          floatx4 sc = {1.f, 1.f, 1.f, 1.f};
-          if constexpr (P == C4_FP8) sc = *reinterpret_cast<const floatx4*>(ep_scale + cl);
-          float v[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float x = acc[nt][mt][r];
-            if constexpr (P == C4_FP8) x *= sc[r];
-            v[r] = fmaxf(x + bb[r], 0.f);
-            m = fmaxf(m, valid ? v[r] : 0.f);
-            v[r] *= inv_out;
-          }
-          if (valid) c4_store4<P>(o + ch, v[0], v[1], v[2], v[3]);
-        }
-      }
-      if constexpr (P == C4_F32 || P == C4_S3) c4_track_max(amax, m);
-    } else {
-      // wave (wm, wn): frame wm of the tile, channels wn*WN .. +WN-1.  Pool over the frame's 64
-      // positions, then this wave's share of FC.
-      const int64_t frow = row0 + wm * WM;             // first row of the frame
-      const bool fvalid = frow < rows;
-      float zc = 0.f;                                   // lane l16 < 10: class l16
-      const int cls = l16 < kClasses ? l16 : 0;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int chb = wn * WN + nt * 16 + 4 * g;
-        const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + chb);
-        floatx4 sc = {1.f, 1.f, 1.f, 1.f};
-        if constexpr (P == C4_FP8) sc = *reinterpret_cast<const floatx4*>(ep_scale + chb);
-        float s[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float x = acc[nt][mt][r];
-            if constexpr (P == C4_FP8) x *= sc[r];
-            s[r] += fmaxf(x + bb[r], 0.f);
-          }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float gch = row_sum16(s[r]) * (1.f / PP);
-          zc += gch * fcw_s[(chb + r) * kClasses + cls];
-        }
-      }
-      if (l16 >= kClasses) zc = 0.f;
-      // rows g = 0..3 hold different channel groups: add them
-      zc = (__shfl(zc, l16) + __shfl(zc, 16 + l16)) + (__shfl(zc, 32 + l16) + __shfl(zc, 48 + l16));
-      if (lane < kClasses) zpart[wave][lane] = zc;
-      __syncthreads();
-      if (wn == 0) {
-        bool pass = false, defer = false, active = false;
-        uint32_t e = 0;
-        if (fvalid) {
-          const int64_t ei = frow / PP;
-          e = a.q.entries[(int64_t)k * a.q.cap + ei];
-          if (lane == 0) {
-            active = true;
-            float z[kClasses];
-#pragma unroll
-            for (int c = 0; c < kClasses; ++c) {
-              float sum = 0.f;
-              for (int w2 = 0; w2 < BN / WN; ++w2) sum += zpart[wm + WGM * w2][c];
-              z[c] = sum + a.fc_b[slot][c];
-            }
-            const uint32_t idx = entry_idx(e);
-            if (f.logits != nullptr)
-              for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)z[c];
-            const float d = class_margin(z, a.class_mask[slot]);
-            const float th = theta_of(f, k, idx);
-            pass = d > th;
-            defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau[k];
-          }
-        }
-        if (f.logits == nullptr) forward_decision(f, k, e, active, defer, pass);
-      }
-    }
+    c4_gemm_epilogue<P, LAYER>(a, f, acc, slot, k, cb, ebase, row0, rows, ep_bias, ep_scale, fcw_s, zpart);
     if (tid == 0) ticks_s[k] += wall_clock64() - t0;
     __syncthreads();   // the next tile's prologue rewrites LDS (stages, constants, zpart)
   }
+  if (tid < kMaxK && ticks_s[tid] && a.count_ticks) atomicAdd(&a.st->r_ticks[tid], ticks_s[tid]);
+}
+
+// BF16 layers 3 and 4 (the first pass): the implicit GEMM of c4_gemm_kernel with its pipeline
+// restructured so that the matrix cores are not left waiting on LDS or memory latency:
+//  - one stream of k-blocks over all of a workgroup's tiles: the first stages of the next tile are
+//    loaded during the current tile's last k-blocks and its epilogue;
+//  - each k-block's fragments are read into registers one MFMA step ahead (two register sets), and
+//    the barrier that publishes the next k-block and frees the oldest buffer sits between the two
+//    MFMA steps of a k-block, so that every wave arrives at it with MFMAs in its pipe and issues
+//    its next fragment reads before the MFMAs that follow.
+// The arithmetic (operands, products and the order in which they are added) is the generic
+// kernel's.
+struct C4Tile {
+  int slot, k, cb, ebase;
+  int64_t row0, rows;
+  bool valid;
+};
+
+template <int LAYER>
+__global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f) {
+  constexpr int P = C4_BF16;
+  typedef __bf16 T;
+  typedef GemmCfg<P> G;
+  typedef GemmShape<P, LAYER> S;
+  constexpr int UPR = G::UPR, CE = G::CE, BKE = G::ROWB / 2;
+  constexpr int CIN = S::CIN, COUT = S::COUT, HIN = S::HIN, HOUT = S::HOUT, PP = HOUT * HOUT;
+  constexpr int BM = S::BM, BN = S::BN, WM = 64, WN = 64, MT = WM / 16, NT = WN / 16, WGM = BM / WM;
+  constexpr int NKB = 9 * CIN / BKE;
+  constexpr int AUNITS = BN * UPR, UNITS = AUNITS + BM * UPR, NI = UNITS / 512, NIA = AUNITS / 512, NB = NI - NIA;
+  constexpr int STAGE = UNITS * 16, NS = 3;
+  constexpr bool HEAD = LAYER == 3;
+  static_assert(9 * CIN % BKE == 0 && NKB >= NS, "whole k-blocks, at least one per stage");
+  static_assert(UNITS % 512 == 0 && AUNITS % 512 == 0 && WGM * (BN / WN) == 8, "tile layout");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[NS * STAGE];
+  __shared__ float zpart[8][kClasses];
+  __shared__ __attribute__((aligned(16))) float ep_bias[BN];
+  __shared__ float fcw_s[HEAD ? COUT * kClasses : 1];
+  __shared__ unsigned long long ticks_s[kMaxK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave % WGM, wn = wave / WGM;
+  if (tid < kMaxK) ticks_s[tid] = 0;
+  const T* act_in = reinterpret_cast<const T*>(LAYER == 2 ? a.c4_act2 : a.c4_act3);
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)lds);
+  int total = 0;
+  for (int i = 0; i < a.n_preds; ++i)
+    if (a.c4[i]) total += (int)(((int64_t)a.q.counts[a.pred[i]] * PP + BM - 1) / BM) * (COUT / BN);
+  const int u_slot = lane % UPR;
+
+  auto decode = [&](int t) {
+    C4Tile r{};                       // past the last tile: slot 0, no rows (the loads read the
+    r.valid = t < total;              // zero page and slot 0's weights; nothing uses them)
+    if (!r.valid) return r;
+    int off = t;
+    for (int i = 0; i < a.n_preds; ++i) {
+      const int c = a.c4[i] ? (int)(((int64_t)a.q.counts[a.pred[i]] * PP + BM - 1) / BM) * (COUT / BN) : 0;
+      if (off < c) { r.slot = i; break; }
+      off -= c;
+      r.ebase += a.q.counts[a.pred[i]];
+    }
+    r.k = a.pred[r.slot];
+    r.cb = off % (COUT / BN);
+    r.row0 = (int64_t)(off / (COUT / BN)) * BM;
+    r.rows = (int64_t)a.q.counts[r.k] * PP;
+    return r;
+  };
+  // B rows this lane gathers for a tile, per load: the element offset of its chunk at tap (0, 0)
+  // (input position (2i - 1, 2j - 1) of output (i, j)) and 3 flag bits: output row 0 (tap row 0
+  // reads padding), output column 0 (tap column 0 reads padding), no row (past the queue).  A
+  // stride-2 3x3 convolution with HIN = 2 HOUT reads padding nowhere else.
+  struct Gather { int64_t off[NB]; uint32_t flags; };
+  auto gather = [&](const C4Tile& tl, Gather& q) {
+    q.flags = 0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int U = (wave + 8 * (NIA + i)) * 64 + lane - AUNITS;
+      const int rb = U / UPR;
+      const int64_t row = tl.row0 + rb;
+      const bool valid = tl.valid && row < tl.rows && tl.ebase + row / PP < a.act_cap;
+      const int64_t e = valid ? row / PP : 0;
+      const int p = valid ? (int)(row % PP) : 0;
+      const int oi = p / HOUT, oj = p % HOUT;
+      q.off[i] = ((int64_t)(valid ? tl.ebase : 0) + e) * (HIN * HIN * CIN) +
+                 ((int64_t)(2 * oi - 1) * HIN + (2 * oj - 1)) * CIN + (u_slot ^ c4_swz<UPR>(rb)) * CE;
+      q.flags |= ((oi == 0 ? 1u : 0u) | (oj == 0 ? 2u : 0u) | (valid ? 0u : 4u)) << (3 * i);
+    }
+  };
+  // source addresses of k-block kb of a tile: A (packed weight image, a straight copy), B (im2col:
+  // k-block kb is tap kb * BKE / CIN, channels from kb * BKE % CIN)
+  // (img: the tile's weight image, from tile_img)
+  auto tile_img = [&](const C4Tile& tl) {
+    return static_cast<const unsigned char*>(a.c4_img[tl.slot][LAYER - 2][P]) + (size_t)tl.cb * BN * G::ROWB;
+  };
+  auto addrs = [&](const unsigned char* img0, const Gather& q, int kb, const void* (&src)[NI]) {
+    const unsigned char* img = img0 + (size_t)kb * COUT * G::ROWB;
+    const int tap = kb * BKE / CIN, dy = tap / 3, dx = tap % 3;
+    const int64_t toff = (int64_t)(dy * HIN + dx) * CIN + kb * BKE % CIN;
+    const uint32_t bad = 4u | (dy == 0 ? 1u : 0u) | (dx == 0 ? 2u : 0u);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      if (i < NIA) {
+        src[i] = img + (size_t)((wave + 8 * i) * 64 + lane) * 16;
+      } else {
+        const bool ok = ((q.flags >> (3 * (i - NIA))) & bad) == 0;
+        src[i] = ok ? static_cast<const void*>(act_in + q.off[i - NIA] + toff) : a.zero_page;
+      }
+    }
+  };
+  auto dma = [&](const void* const (&src)[NI], int buf) {
+    const uint32_t base = lds0 + buf * STAGE;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) lds_dma16(src[i], __builtin_amdgcn_readfirstlane(base + (wave + 8 * i) * 1024));
+  };
+  struct Frag { bf16x8 a[NT], b[MT]; };
+  // MFMA step ks (k = 32 ks .. 32 ks + 31 of the k-block) of buffer buf: lane group g reads chunk
+  // 4 ks + g of each row
+  auto frags = [&](int buf, int ks, Frag& F) {
+    const unsigned char* A = lds + buf * STAGE;
+    const unsigned char* B = A + AUNITS * 16;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int r = wn * WN + nt * 16 + l16;
+      F.a[nt] = *reinterpret_cast<const bf16x8*>(A + (r * UPR + ((4 * ks + g) ^ c4_swz<UPR>(r))) * 16);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int r = wm * WM + mt * 16 + l16;
+      F.b[mt] = *reinterpret_cast<const bf16x8*>(B + (r * UPR + ((4 * ks + g) ^ c4_swz<UPR>(r))) * 16);
+    }
+  };
+  floatx4 acc[NT][MT];
+  auto mma = [&](const Frag& F) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = c4_mfma(F.a[nt], F.b[mt], acc[nt][mt]);
+  };
+
+  // The compute side walks this workgroup's tiles; the issue side walks the same stream of
+  // k-blocks NS k-blocks ahead (its tile changes once per tile, after a k-block's MFMAs).
+  int t = blockIdx.x;
+  C4Tile cur = decode(t);
+  if (cur.valid) {
+    int it = t, ikb = 0;
+    C4Tile itl = cur;
+    Gather ig;
+    gather(itl, ig);
+    const unsigned char* iimg = tile_img(itl);
+    auto advance = [&]() {
+      if (++ikb == NKB) {
+        ikb = 0;
+        it += gridDim.x;
+        itl = decode(it);
+        gather(itl, ig);
+        iimg = tile_img(itl);
+      }
+    };
+    // prologue: the stream's first NS k-blocks
+#pragma unroll
+    for (int s0 = 0; s0 < NS; ++s0) {
+      const void* src[NI];
+      addrs(iimg, ig, ikb, src);
+      dma(src, s0);
+      advance();
+    }
+    wait_vmcnt<(NS - 1) * NI>();
+    __syncthreads();
+    Frag F0, F1;
+    frags(0, 0, F0);
+    int buf = 0;                      // buffer of the current k-block
+    for (;;) {
+      const unsigned long long t0 = wall_clock64();
+      // epilogue constants of this tile (the previous tile's closing barrier ordered every read)
+      for (int i = tid; i < BN; i += 512) ep_bias[i] = a.bias[cur.slot][LAYER][cur.cb * BN + i];
+      if constexpr (HEAD)
+        for (int i = tid; i < COUT * kClasses; i += 512) fcw_s[i] = a.fc_w[cur.slot][i];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+      for (int kb = 0; kb < NKB; ++kb) {
+        // the next k-block of the issue stream goes into this buffer once every wave has read
+        // it; its addresses are formed while the MFMAs run (one MFMA, then one LDS read and two
+        // VALU, ...)
+        const void* src[NI];
+        addrs(iimg, ig, ikb, src);
+        frags(buf, 1, F1);
+        mma(F0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);    // VALU
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+        }
+        // publish k-block kb + 1 (issued NS - 1 k-blocks ago; the one after it may stay in
+        // flight) and free this buffer
+        wait_vmcnt<NI>();
+        __syncthreads();
+        dma(src, buf);
+        buf = buf + 1 == NS ? 0 : buf + 1;
+        frags(buf, 0, F0);            // the next k-block's first step (unused after the last)
+        mma(F1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        advance();
+      }
+      c4_gemm_epilogue<P, LAYER, !HEAD>(a, f, acc, cur.slot, cur.k, cur.cb, cur.ebase, cur.row0, cur.rows, ep_bias,
+                                        nullptr, fcw_s, zpart);
+      if (tid == 0) ticks_s[cur.k] += wall_clock64() - t0;
+      __syncthreads();                // epilogue constants and zpart are rewritten next
+      t += gridDim.x;
+      cur = decode(t);
+      if (!cur.valid) break;
+    }
+    wait_vmcnt<0>();                  // the loads issued past the last tile
+  }
+  __syncthreads();
   if (tid < kMaxK && ticks_s[tid] && a.count_ticks) atomicAdd(&a.st->r_ticks[tid], ticks_s[tid]);
 }
 
@@ -880,8 +1159,8 @@ void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hip
     hipLaunchKernelGGL((c4_gemm_kernel<C4_FP8, 3>), dim3(grid), dim3(512), 0, s, a, f);
   } else if (prec == C4_BF16) {
     launch_front<C4_BF16>(a, g1, s);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 2>), dim3(grid), dim3(512), 0, s, a, f);
-    hipLaunchKernelGGL((c4_gemm_kernel<C4_BF16, 3>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_bf16_kernel<2>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_bf16_kernel<3>), dim3(grid), dim3(512), 0, s, a, f);
   } else {
     // FP32 arithmetic: the front in fp32, layers 3 and 4 as three-term bf16 products
     launch_front<C4_F32>(a, g1, s);
@@ -1049,10 +1328,12 @@ void c4_pack_img(int prec, int layer, const float* w, const float* scale, unsign
   const int rowb = 128, upr = rowb / 16, ce = 16 / es, bke = rowb / es;
   const int nkb = c4_nkb(prec, layer);
   for (int kb = 0; kb < nkb; ++kb)
-    for (int oc = 0; oc < cout; ++oc)
+    for (int row = 0; row < cout; ++row)
       for (int s = 0; s < upr; ++s) {
-        const int c = s ^ (upr == 4 ? c4_swz<4>(oc) : c4_swz<8>(oc));
-        unsigned char* dst = out + (((size_t)kb * cout + oc) * upr + s) * 16;
+        // BF16 layer 3 (the third convolution): image row R holds channel c4_l3_channel(R)
+        const int oc = prec == C4_BF16 && layer == 2 ? c4_l3_channel(row) : row;
+        const int c = s ^ (upr == 4 ? c4_swz<4>(row) : c4_swz<8>(row));
+        unsigned char* dst = out + (((size_t)kb * cout + row) * upr + s) * 16;
         for (int e = 0; e < ce; ++e) {
           const int kk = kb * bke + c * ce + e;
           const float v = kk < 9 * cin ? c4_w(w, cin, oc, kk) : 0.f;
