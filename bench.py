@@ -50,10 +50,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs plain; MFMA util"
-# HBM bytes per first-pass round (reads + writes), from FETCH_SIZE / WRITE_SIZE runs of this script
-# scaled by the same counters on a 1 GiB device copy (the byte-counter summary in profiles/).  Valid
-# only for the kernel build those runs measured: None for a workload without such a run.
-FIRST_PASS_TRAFFIC = {"cnn3_drift64": 407.60e6 + 5.27e6}
+# HBM bytes of the first pass come from FETCH_SIZE / WRITE_SIZE runs of this script, scaled by the
+# same counters on a 1 GiB device copy (the byte-counter summaries in profiles/), and are reported
+# only while the kernel sources hash to the build those runs measured (None otherwise).
 # The 4-layer CNN first pass (front + layer-3 + layer-4 launches, bf16): HBM bytes per evaluated
 # frame from the same counters (profiles/cnn4_u8_128_first_pass.md), valid while the kernel
 # sources hash to the recorded value; the figure per launch is this times the launch's frames.
@@ -121,8 +120,6 @@ def parse():
 
 def first_pass_traffic(cfg, n, ev, launches):
     """HBM bytes per first-pass launch from the byte-counter runs of this kernel build, else None."""
-    if n == cfg.n and cfg.name in FIRST_PASS_TRAFFIC:
-        return FIRST_PASS_TRAFFIC[cfg.name]
     if cfg.name in FIRST_PASS_BYTES_PER_EVAL:
         sha, per_eval = FIRST_PASS_BYTES_PER_EVAL[cfg.name]
         if sources_hash(FIRST_PASS_SOURCES) == sha:
