@@ -48,6 +48,30 @@ __device__ inline typename Mf<T>::frag ld_frag(const T* p) {
   else return *p;
 }
 
+// FP32 arithmetic from bf16 MFMAs: fp32 activations split into three bf16 terms (x = h + m + l
+// exactly), weights held as three terms likewise; the six products down to 2^-24 relative, summed
+// smallest first.
+__device__ inline void split3(const float4& p0, const float4& p1, bf16x8 (&x)[3]) {
+  const float xv[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = static_cast<__bf16>(xv[e]);
+    const float r1 = xv[e] - static_cast<float>(h);
+    const __bf16 m = static_cast<__bf16>(r1);
+    x[0][e] = h;
+    x[1][e] = m;
+    x[2][e] = static_cast<__bf16>(r1 - static_cast<float>(m));
+  }
+}
+__device__ inline floatx4 mfma_s3(const bf16x8 (&w)[3], const bf16x8 (&x)[3], floatx4 c) {
+  c = mfma(w[0], x[2], c);
+  c = mfma(w[1], x[1], c);
+  c = mfma(w[0], x[1], c);
+  c = mfma(w[2], x[0], c);
+  c = mfma(w[1], x[0], c);
+  return mfma(w[0], x[0], c);
+}
+
 // geometry
 constexpr int H0 = 64, H1 = 32, H2 = 16, H3 = 8;
 constexpr int NTHR = 512;           // 8 wave64s per workgroup (the narrowest class: 4, two per CU)
@@ -60,7 +84,7 @@ constexpr int CB1 = 16;             // layer-1 channels per slab
 // Pixel strides (elements) of the layer-1 slab and the layer-2 output are padded so that the 16
 // lanes of an MFMA row group, which read 16 different pixels, spread over the LDS banks.
 template <typename T> struct Pad {
-  static constexpr int S1P = CB1 + (sizeof(T) == 4 ? 1 : 0);
+  static constexpr int S1P = CB1 + (sizeof(T) == 4 ? 4 : 0);   // fp32: 16-byte aligned pixels
   static constexpr int L2E = 16 / (int)sizeof(T);      // extra elements per layer-2 pixel
 };
 
@@ -264,30 +288,37 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   constexpr int NT = NWV * 64;                       // threads
   constexpr int C2 = 32 * M, C3 = 64 * M;
   constexpr int S1P = Pad<T>::S1P, C2P = C2 + Pad<T>::L2E;
-  constexpr int KSTEP = Mf<T>::KSTEP, KPL = Mf<T>::KPL;
+  // FP32 tier (T = float): fp32 activations, bf16 MFMAs on three-term operands, in the bf16
+  // fragment layout (k-steps of 32, 8 per lane)
+  constexpr bool S3 = sizeof(T) == 4;
+  typedef typename std::conditional<S3, __bf16, T>::type KT;
+  constexpr int KSTEP = Mf<KT>::KSTEP, KPL = Mf<KT>::KPL;
   typedef typename Mf<T>::frag frag;
+  // term t of the FP32 tier's packed layer l: fragments [slab][k-step][n-tile][lane]
+  auto s3w = [&](int l, int t) {
+    const size_t per_term = (size_t)cnn_slabs(l, M) * cnn_ksteps<__bf16>(l, M) * cnn_ntiles(l, M) * 64;
+    return reinterpret_cast<const bf16x8*>(a.w_s3[slot][l]) + t * per_term;
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
 
   const __bf16* FR = reinterpret_cast<const __bf16*>(region);
   T* S1 = reinterpret_cast<T*>(region + CnnLds<T>::S1_OFF);
   T* L2 = reinterpret_cast<T*>(region);
 
-  const T* const* wpk;
-  if constexpr (sizeof(T) == 2) wpk = reinterpret_cast<const T* const*>(a.w_bf[slot]);
-  else wpk = reinterpret_cast<const T* const*>(a.w_f32[slot]);
+  const T* const* wpk = reinterpret_cast<const T* const*>(a.w_bf[slot]);   // (bf16 tier)
   const float* b1 = sh.cb;
   const float* b2 = sh.cb + CB_L2;
   const float* b3 = sh.cb + CB_L3;
   // The narrow classes fetch the next frame now: their layer 3 is too short to cover the HBM
   // latency before the frame is stored (not the four-wave m = 2 form: no registers to spare).
   constexpr bool kEarlyFetch = M == 1 || (M == 2 && NWV == 8);
-  constexpr int KS1 = cnn_ksteps<T>(0, M), KS2 = cnn_ksteps<T>(1, M);
+  constexpr int KS1 = cnn_ksteps<KT>(0, M), KS2 = cnn_ksteps<KT>(1, M);
   constexpr int NT2 = 2 * M;
   // layer-2 wave tile: MT2 position tiles x NW2 channel tiles (the waves cover 16 x NT2)
   constexpr int MT2 = (M == 1 && NWV == 8) ? 2 : (M == 4 && sizeof(T) == 2) ? 8 : 4, NW2 = NT2 * (16 / MT2) / NWV;
   constexpr int NG2 = NT2 / NW2;                       // channel groups
   // weight prefetch depth (k-steps); the widest bf16 class has no registers to spare in layer 2
-  constexpr int PD2 = sizeof(T) == 4 ? 4 : ((M == 4 || (M == 2 && NWV == 4)) ? 2 : 3);
+  constexpr int PD2 = S3 ? 1 : ((M == 4 || (M == 2 && NWV == 4)) ? 2 : 3);
   const int mg2 = wave / NG2, ng2 = wave % NG2;
   static_assert((16 / MT2) * NG2 == NWV, "layer-2 wave tiling must cover the waves");
   // With the early fetch, slab 0's layer-1 weights and its first PD2 layer-2 weight k-steps are
@@ -326,6 +357,17 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   constexpr int MPW = 64 / NWV;                      // layer-1 m-tiles per wave
   constexpr bool kCacheA1 = sizeof(T) == 2 && M > 1 && NWV == 8;
   frag a1[kCacheA1 ? MPW : 1][KS1];
+  auto gather1b = [&](int mt) -> bf16x8 {
+    const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
+    const __bf16* rowp = FR + 2 * i * FRS + 5 + 6 * j;
+    alignas(16) __bf16 t8[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = min(8 * g + e, 26);
+      t8[e] = rowp[(k / 9) * FRS + k % 9];
+    }
+    return *reinterpret_cast<const bf16x8*>(t8);
+  };
   auto gather1 = [&](int mt, int ks) -> frag {
     const int px = mt * 16 + l16, i = px >> 5, j = px & 31;
     // im2col row of output (i, j): FR row 2i+u, elements 5 + 6j + (3v + c), k = 9u + 3v + c
@@ -361,14 +403,19 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   for (int slab = 0; slab < M; ++slab) {
     // layer 1: 64 m-tiles (16 positions each) x 16 channels; wave w owns m-tiles 8w..8w+7
     const frag* w1p = reinterpret_cast<const frag*>(wpk[0]) + (size_t)slab * KS1 * 64;
-    frag w1f[KS1];
-    if (kPreW && slab == 0) {
+    frag w1f[S3 ? 1 : KS1];
+    bf16x8 w1t[3];
+    if constexpr (S3) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) w1t[t] = s3w(0, t)[slab * 64 + lane];
+    } else if (kPreW && slab == 0) {
 #pragma unroll
       for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1_0[ks];
     } else {
 #pragma unroll
       for (int ks = 0; ks < KS1; ++ks) w1f[ks] = w1p[ks * 64 + lane];
     }
+    (void)w1t;
     float bb1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) bb1[r] = b1[slab * CB1 + 4 * g + r];
@@ -393,17 +440,18 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
         l1_store(mt, acc0);
         l1_store(mt + 1, acc1);
       }
-    } else if constexpr (!kCacheA1) {
-      // FP32 (7 k-steps): tiles in pairs as well, two independent accumulation chains
-#pragma unroll 1
+    } else if constexpr (S3) {
+      // FP32 tier: the raw frame values are exact in bf16, so the three weight terms give every
+      // product exactly (smallest term first); tiles in pairs
+#pragma unroll 2
       for (int q = 0; q < MPW; q += 2) {
         const int mt = wave * MPW + q;
+        const bf16x8 av0 = gather1b(mt), av1 = gather1b(mt + 1);
         floatx4 acc0 = (floatx4){0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
 #pragma unroll
-        for (int ks = 0; ks < KS1; ++ks) {
-          const frag av0 = gather1(mt, ks), av1 = gather1(mt + 1, ks);
-          acc0 = mfma(w1f[ks], av0, acc0);
-          acc1 = mfma(w1f[ks], av1, acc1);
+        for (int t = 2; t >= 0; --t) {
+          acc0 = mfma(w1t[t], av0, acc0);
+          acc1 = mfma(w1t[t], av1, acc1);
         }
         l1_store(mt, acc0);
         l1_store(mt + 1, acc1);
@@ -424,56 +472,85 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
       }
     }
     __syncthreads();
-    // layer 2 partial: K = 9 taps x 16 channels of this slab.  The weight fragments run PD2
-    // k-steps ahead of the MFMAs (they come from L2 cache; one k-step of MFMAs is far shorter
-    // than that latency).
-    const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64 + ng2 * NW2 * 64 + lane;
-    frag bw2[PD2][NW2];
-    if (kPreW && slab == 0) {
-#pragma unroll
-      for (int d = 0; d < PD2; ++d)
+    if constexpr (S3) {
+      // FP32 tier, layer 2 partial of this slab: K = 9 taps x 16 channels in k-steps of 32 (lane
+      // group g: tap (32 ks + 8 g) / 16, channels from 8 (g % 2)); a k-step's weights are
+      // requested before its activation reads and splits
+      const bf16x8* w2t[3] = {s3w(1, 0), s3w(1, 1), s3w(1, 2)};
+#pragma unroll 1
+      for (int ks = 0; ks < KS2; ++ks) {
+        bf16x8 w[NW2][3];
 #pragma unroll
         for (int n = 0; n < NW2; ++n)
-          if (d < KS2) bw2[d][n] = bw2_0[d][n];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) w[n][t] = w2t[t][((slab * KS2 + ks) * NT2 + ng2 * NW2 + n) * 64 + lane];
+        const int k0 = ks * 32 + 8 * g;
+        const int tp = min(k0 / CB1, 8);        // padded k (zero weights) reads a valid tap
+        const int c0 = k0 % CB1;
+        const int u = tp / 3, v = tp % 3;
+#pragma unroll
+        for (int q = 0; q < MT2; ++q) {
+          const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
+          const float4* src = reinterpret_cast<const float4*>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
+          bf16x8 x[3];
+          split3(src[0], src[1], x);
+#pragma unroll
+          for (int n = 0; n < NW2; ++n) acc2[q][n] = mfma_s3(w[n], x, acc2[q][n]);
+          __builtin_amdgcn_sched_barrier(0);    // one position tile's operands live at a time
+        }
+      }
     } else {
-#pragma unroll
-      for (int d = 0; d < PD2; ++d)
-#pragma unroll
-        for (int n = 0; n < NW2; ++n)
-          if (d < KS2) bw2[d][n] = w2p[(d * NT2 + n) * 64];
-    }
-#pragma unroll (kPreW && M == 1 ? 4 : 1)
-    for (int ks0 = 0; ks0 < KS2; ks0 += PD2) {
-#pragma unroll
-      for (int d = 0; d < PD2; ++d) {
-        const int ks = ks0 + d;
-        // (when PD2 divides KS2 the guard folds away and the loop body has no branches)
-        if (KS2 % PD2 == 0 || ks < KS2) {
-          const int k0 = ks * KSTEP + KPL * g;
-          int t = k0 / CB1;
-          const int c0 = k0 % CB1;
-          if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
-          const int u = t / 3, v = t % 3;
-          frag av[MT2];
-#pragma unroll
-          for (int q = 0; q < MT2; ++q) {
-            const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
-            av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
-          }
-#pragma unroll
+      // layer 2 partial: K = 9 taps x 16 channels of this slab.  The weight fragments run PD2
+      // k-steps ahead of the MFMAs (they come from L2 cache; one k-step of MFMAs is far shorter
+      // than that latency).
+      const frag* w2p = reinterpret_cast<const frag*>(wpk[1]) + (size_t)slab * KS2 * NT2 * 64 + ng2 * NW2 * 64 + lane;
+      frag bw2[PD2][NW2];
+      if (kPreW && slab == 0) {
+  #pragma unroll
+        for (int d = 0; d < PD2; ++d)
+  #pragma unroll
           for (int n = 0; n < NW2; ++n)
-#pragma unroll
-            for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bw2[d][n], av[q], acc2[q][n]);
-          if constexpr (KS2 % PD2 == 0) {
-            // unconditional refill; the last PD2 k-steps re-read the last fragment (unused).  The
-            // scheduling barrier keeps the loads here: sunk to the end of the iteration (to
-            // shorten register lifetimes) they would be waited on right after being issued.
-#pragma unroll
-            for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[(min(ks + PD2, KS2 - 1) * NT2 + n) * 64];
-            __builtin_amdgcn_sched_barrier(0);
-          } else if (ks + PD2 < KS2) {
-#pragma unroll
-            for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[((ks + PD2) * NT2 + n) * 64];
+            if (d < KS2) bw2[d][n] = bw2_0[d][n];
+      } else {
+  #pragma unroll
+        for (int d = 0; d < PD2; ++d)
+  #pragma unroll
+          for (int n = 0; n < NW2; ++n)
+            if (d < KS2) bw2[d][n] = w2p[(d * NT2 + n) * 64];
+      }
+  #pragma unroll (kPreW && M == 1 ? 4 : 1)
+      for (int ks0 = 0; ks0 < KS2; ks0 += PD2) {
+  #pragma unroll
+        for (int d = 0; d < PD2; ++d) {
+          const int ks = ks0 + d;
+          // (when PD2 divides KS2 the guard folds away and the loop body has no branches)
+          if (KS2 % PD2 == 0 || ks < KS2) {
+            const int k0 = ks * KSTEP + KPL * g;
+            int t = k0 / CB1;
+            const int c0 = k0 % CB1;
+            if (t > 8) t = 8;                       // padded k (zero weights) reads a valid tap
+            const int u = t / 3, v = t % 3;
+            frag av[MT2];
+  #pragma unroll
+            for (int q = 0; q < MT2; ++q) {
+              const int px = (mg2 * MT2 + q) * 16 + l16, i = px >> 4, j = px & 15;
+              av[q] = ld_frag<T>(S1 + ((2 * i + u) * S1_W + 2 * j + v) * S1P + c0);
+            }
+  #pragma unroll
+            for (int n = 0; n < NW2; ++n)
+  #pragma unroll
+              for (int q = 0; q < MT2; ++q) acc2[q][n] = mfma(bw2[d][n], av[q], acc2[q][n]);
+            if constexpr (KS2 % PD2 == 0) {
+              // unconditional refill; the last PD2 k-steps re-read the last fragment (unused).  The
+              // scheduling barrier keeps the loads here: sunk to the end of the iteration (to
+              // shorten register lifetimes) they would be waited on right after being issued.
+  #pragma unroll
+              for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[(min(ks + PD2, KS2 - 1) * NT2 + n) * 64];
+              __builtin_amdgcn_sched_barrier(0);
+            } else if (ks + PD2 < KS2) {
+  #pragma unroll
+              for (int n = 0; n < NW2; ++n) bw2[d][n] = w2p[((ks + PD2) * NT2 + n) * 64];
+            }
           }
         }
       }
@@ -501,10 +578,10 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   __syncthreads();
 
   // ---- layer 3: 4 position tiles (64 positions) x 4M channel tiles; wave tile MT3 x NW3
-  constexpr int KS3 = cnn_ksteps<T>(2, M), NT3 = 4 * M;
+  constexpr int KS3 = cnn_ksteps<KT>(2, M), NT3 = 4 * M;
   constexpr int MT3 = (M == 1 && NWV == 8) ? 2 : 4, NW3 = NT3 * (4 / MT3) / NWV;
   constexpr int MG3 = 4 / MT3;                         // position groups (1 or 2)
-  constexpr int PD3 = sizeof(T) == 4 ? 4 : ((M == 2 && NWV == 4) ? 2 : 3);
+  constexpr int PD3 = S3 ? 1 : ((M == 2 && NWV == 4) ? 2 : 3);
   static_assert(MG3 * (NT3 / NW3) == NWV, "layer-3 wave tiling must cover the waves");
   const int mh = wave % MG3, ng = wave / MG3;
   floatx4 acc3[MT3][NW3];
@@ -515,10 +592,12 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
   const frag* w3p = reinterpret_cast<const frag*>(wpk[2]) + (size_t)(ng * NW3) * 64 + lane;
   static_assert(KS3 % PD3 == 0, "layer-3 k-steps must be a multiple of the prefetch depth");
   frag bw3[PD3][NW3];
+  if constexpr (!S3) {
 #pragma unroll
-  for (int d = 0; d < PD3; ++d)
+    for (int d = 0; d < PD3; ++d)
 #pragma unroll
-    for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(d * NT3 + n) * 64];
+      for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(d * NT3 + n) * 64];
+  }
   auto l3_step = [&](int ks, const frag (&b)[NW3]) {
     const int k0 = ks * KSTEP + KPL * g;
     const int t = k0 / C2, c0 = k0 % C2;
@@ -554,20 +633,31 @@ __device__ void cnn_frame(const CnnArgs& a, int slot, unsigned char* region, Cnn
 #pragma unroll
     for (int d = 0; d < PD3; ++d) l3_step(KS3 - PD3 + d, bw3[d]);
   } else {
-    // FP32: the split loop above costs spills; the frame is requested before layer 3
+    // FP32 tier: the frame is requested before layer 3 (its wait falls on the first k-step only);
+    // per k-step the weight terms are requested before the activation reads and splits
     if (!kEarlyFetch) frame_issue<NT>(a, next_idx, pf);
     if (!kEarlyFetch && feat_dst != nullptr && wave == 0 && lane < 24)
       reinterpret_cast<uint4*>(feat_dst)[lane] = reinterpret_cast<const uint4*>(sh.feat)[lane];
+    (void)bw3;
+    const bf16x8* w3t[3] = {s3w(2, 0), s3w(2, 1), s3w(2, 2)};
 #pragma unroll 1
-    for (int ks0 = 0; ks0 < KS3; ks0 += PD3) {
+    for (int ks = 0; ks < KS3; ++ks) {
+      bf16x8 w[NW3][3];
 #pragma unroll
-      for (int d = 0; d < PD3; ++d) {
-        const int ks = ks0 + d;
-        l3_step(ks, bw3[d]);
-        // unconditional refill; the last PD3 k-steps re-read the last fragment (unused); kept in
-        // place by the scheduling barrier as in layer 2
+      for (int n = 0; n < NW3; ++n)
 #pragma unroll
-        for (int n = 0; n < NW3; ++n) bw3[d][n] = w3p[(min(ks + PD3, KS3 - 1) * NT3 + n) * 64];
+        for (int t = 0; t < 3; ++t) w[n][t] = w3t[t][(ks * NT3 + ng * NW3 + n) * 64 + lane];
+      const int k0 = ks * 32 + 8 * g;
+      const int tp = k0 / C2, c0 = k0 % C2;
+      const int u = tp / 3, v = tp % 3;
+#pragma unroll
+      for (int q = 0; q < MT3; ++q) {
+        const int px = (mh * MT3 + q) * 16 + l16, i = px >> 3, j = px & 7;
+        const float4* src = reinterpret_cast<const float4*>(L2 + ((2 * i + u) * L2_W + 2 * j + v) * C2P + c0);
+        bf16x8 x[3];
+        split3(src[0], src[1], x);
+#pragma unroll
+        for (int n = 0; n < NW3; ++n) acc3[q][n] = mfma_s3(w[n], x, acc3[q][n]);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -1031,7 +1121,7 @@ void launch_cnn_pass(const CnnArgs& a, const Forward& f, int tier, int grid, hip
       const int j = b.n_preds++;
       b.pred[j] = a.pred[i]; b.variant[j] = a.variant[i]; b.class_mask[j] = a.class_mask[i];
       for (int l = 0; l < 3; ++l) {
-        b.w_bf[j][l] = a.w_bf[i][l]; b.w_f32[j][l] = a.w_f32[i][l]; b.bias[j][l] = a.bias[i][l];
+        b.w_bf[j][l] = a.w_bf[i][l]; b.w_s3[j][l] = a.w_s3[i][l]; b.bias[j][l] = a.bias[i][l];
         b.w_canon[j][l] = a.w_canon[i][l]; b.b_canon[j][l] = a.b_canon[i][l]; b.wt_canon[j][l] = a.wt_canon[i][l];
       }
       b.fc_w[j] = a.fc_w[i]; b.fc_b[j] = a.fc_b[i]; b.esc_act[j] = a.esc_act[i];

@@ -50,7 +50,8 @@ struct CnnArgs {
   int variant[kMaxK];
   uint32_t class_mask[kMaxK];
   const __bf16* w_bf[kMaxK][3];     // packed per layer (bf16 fragments)
-  const float* w_f32[kMaxK][3];     // packed per layer (fp32 fragments)
+  const __bf16* w_s3[kMaxK][3];     // FP32 tier: the same fragments as three bf16 terms (hi, mid,
+                                    // lo; w = hi + mid + lo exactly), [term][fragment image]
   const float* bias[kMaxK][3];      // fp32, layer 1 folded
   const float* fc_w[kMaxK];         // [c_last][10]
   const float* fc_b[kMaxK];

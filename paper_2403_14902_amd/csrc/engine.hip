@@ -1143,13 +1143,6 @@ static int pack_models(hydro_session* s) {
         float* dp;
         uint16_t* bp;
         {
-          size_t n = cnn_packed_elems(hm.variant, l, HYDRO_PREC_FP32);
-          std::vector<float> pf(n);
-          cnn_pack_layer(hm.variant, l, HYDRO_PREC_FP32, hm.cw[l].data(), (float)sc, pf.data());
-          if ((rc = upload(s, pf.data(), n, &dp))) return rc;
-          ca.w_f32[i][l] = dp;
-        }
-        {
           size_t n = cnn_packed_elems(hm.variant, l, HYDRO_PREC_BF16);
           std::vector<float> pf(n);
           cnn_pack_layer(hm.variant, l, HYDRO_PREC_BF16, hm.cw[l].data(), (float)sc, pf.data());
@@ -1157,6 +1150,19 @@ static int pack_models(hydro_session* s) {
           for (size_t t = 0; t < n; ++t) pb[t] = f32_to_bf16_bits(pf[t]);
           if ((rc = upload(s, pb.data(), n, &bp))) return rc;
           ca.w_bf[i][l] = reinterpret_cast<const __bf16*>(bp);
+          // FP32 tier: each packed weight as hi + mid + lo in bf16 (exact for fp32 values), the
+          // three images one after the other
+          std::vector<uint16_t> p3(3 * n);
+          for (size_t t = 0; t < n; ++t) {
+            float v = pf[t];
+            for (int term = 0; term < 3; ++term) {
+              const uint16_t h = f32_to_bf16_bits(v);
+              p3[term * n + t] = h;
+              v -= bf16_bits_to_f32(h);
+            }
+          }
+          if ((rc = upload(s, p3.data(), 3 * n, &bp))) return rc;
+          ca.w_s3[i][l] = reinterpret_cast<const __bf16*>(bp);
         }
         if ((rc = upload(s, bias.data(), bias.size(), &dp))) return rc;
         ca.bias[i][l] = dp;
@@ -1688,7 +1694,7 @@ static void enqueue_tier(hydro_session* s, int tier, const FrameSrc& fr, const F
         b.n_preds = 1;
         b.pred[0] = a.pred[i]; b.variant[0] = a.variant[i]; b.class_mask[0] = a.class_mask[i];
         for (int l = 0; l < 3; ++l) {
-          b.w_bf[0][l] = a.w_bf[i][l]; b.w_f32[0][l] = a.w_f32[i][l]; b.bias[0][l] = a.bias[i][l];
+          b.w_bf[0][l] = a.w_bf[i][l]; b.w_s3[0][l] = a.w_s3[i][l]; b.bias[0][l] = a.bias[i][l];
           b.w_canon[0][l] = a.w_canon[i][l]; b.b_canon[0][l] = a.b_canon[i][l];
         }
         b.fc_w[0] = a.fc_w[i]; b.fc_b[0] = a.fc_b[i];
