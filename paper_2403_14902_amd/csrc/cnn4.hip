@@ -91,6 +91,12 @@ constexpr int F_SLOTS = 65;        // layer-1 columns of a row: even 0..62, then
 constexpr int F_FROWS = 17;        // frame rows a band reads
 constexpr int F_FPITCH = 388;      // bf16 elements per staged frame row: [0] unused, [1..3] the left
                                    // pad column, [4 + 3x + c] column x channel c
+// Layer 1's K slot (lane group g, element e of a 16x16x32 fragment) -> k = 9u + 3v + c: lane
+// groups 0..2 hold the first 8 of the 9 (pixel, channel) values of input row g, lane group 3 the
+// ninth of rows 0..2; slots 27.. (k >= 27) have zero weights.  Each lane then reads five aligned
+// dwords of one staged row (or the ninth element of each row) instead of eight 2-byte elements.
+__host__ __device__ inline int c4_l1_k(int g, int e) { return g < 3 ? 9 * g + e : e < 3 ? 9 * e + 8 : 27; }
+
 template <int P> struct FrontCfg;
 // bytes per layer-1 column slot (32 channels + padding: the slot pitch in 16-byte units is odd so
 // that eight consecutive slots fall on distinct bank groups)
@@ -284,15 +290,22 @@ void c4_front_kernel(GcnnArgs a) {
       for (int pt = 0; pt < 8; ++pt) {
         const int il = 2 * wave + (pt >> 2), j = (pt & 3) * 16 + l16;
         floatx4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-        const __bf16* fr = fb + (2 * il) * F_FPITCH + 1 + 6 * j;
-        bf16x8 xb;
+        // the 9 values of input row u for output column j (pixels 2j-1 .. 2j+1) are elements
+        // 6j+1 .. 6j+9 of the staged row; dwords from element 6j hold them in pairs
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(fb + (2 * il) * F_FPITCH + 6 * j);
+        constexpr int RP = F_FPITCH / 2;      // dwords per staged row
+        uint32_t d[5];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          int kk = 8 * g + e;
-          kk = kk > 26 ? 26 : kk;   // k = 27..31: zero weights (any finite element)
-          const int u = kk / 9, tt = kk % 9;
-          xb[e] = fr[u * F_FPITCH + tt];
+        for (int i = 0; i < 5; ++i) d[i] = rw[g < 3 ? g * RP + i : (i < 3 ? i * RP + 4 : 4)];
+        uint32_t xw[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t row = __builtin_amdgcn_alignbit(d[i + 1], d[i], 16);   // elements 2i+1, 2i+2
+          const uint32_t ninth = i == 0 ? (d[0] >> 16) | (d[1] & 0xFFFF0000u) : i == 1 ? d[2] >> 16 : 0u;
+          xw[i] = g < 3 ? row : ninth;
         }
+        bf16x8 xb;
+        __builtin_memcpy(&xb, xw, sizeof(xb));
         if constexpr (P == C4_F32) {
           // raw frame values are exact in bf16 and the weights are the sum of their three terms:
           // every product exact, fp32 sums (smallest term first)
@@ -1226,7 +1239,7 @@ static inline float c4_w(const float* w, int cin, int oc, int k) {
 }
 
 void c4_pack_front(const float* w1, float scale1, const float* w2, const float* s2, C4FrontPack* out) {
-  // layer 1: k = 9u + 3v + c (27 real)
+  // layer 1: k = 9u + 3v + c (27 real), K slots per c4_l1_k
   auto w1k = [&](int oc, int kk) -> float {
     if (kk >= 27) return 0.f;
     const int u = kk / 9, t = kk % 9, v = t / 3, c = t % 3;
@@ -1235,23 +1248,19 @@ void c4_pack_front(const float* w1, float scale1, const float* w2, const float* 
   out->w1b.assign(2 * 64 * 8, 0.f);
   for (int ct = 0; ct < 2; ++ct)
     for (int l = 0; l < 64; ++l)
-      for (int e = 0; e < 8; ++e) out->w1b[(ct * 64 + l) * 8 + e] = w1k(ct * 16 + (l & 15), 8 * (l >> 4) + e);
+      for (int e = 0; e < 8; ++e) out->w1b[(ct * 64 + l) * 8 + e] = w1k(ct * 16 + (l & 15), c4_l1_k(l >> 4, e));
   // FP32 arithmetic: the bf16 fragments' values split into three bf16 terms [term][ct][lane][8]
   out->w1s3.assign(3 * 2 * 64 * 8, 0);
   for (int ct = 0; ct < 2; ++ct)
     for (int l = 0; l < 64; ++l)
       for (int e = 0; e < 8; ++e) {
-        float v = w1k(ct * 16 + (l & 15), 8 * (l >> 4) + e);
+        float v = w1k(ct * 16 + (l & 15), c4_l1_k(l >> 4, e));
         for (int t = 0; t < 3; ++t) {
           const uint16_t h = c4_bf16_bits(v);
           out->w1s3[(((size_t)t * 2 + ct) * 64 + l) * 8 + e] = h;
           v -= c4_bf16_value(h);
         }
       }
-  out->w1f.assign(7 * 2 * 64, 0.f);
-  for (int s = 0; s < 7; ++s)
-    for (int ct = 0; ct < 2; ++ct)
-      for (int l = 0; l < 64; ++l) out->w1f[(s * 2 + ct) * 64 + l] = w1k(ct * 16 + (l & 15), 4 * s + (l >> 4));
   // layer 2 (cin 32), bf16 32x32x16 fragments [tap][h][c2][lane][8]: output channel
   // 32 c2 + lane % 32, input channel 16 h + 8 (lane / 32) + e
   out->w2b.assign(9 * 2 * 2 * 64 * 8, 0.f);

@@ -147,7 +147,7 @@ void launch_crop_pass(const CropArgs& a, const Forward& f, int grid, hipStream_t
 // three bf16 terms on the fly, weights packed as three bf16 terms; see cnn4.hip).
 enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2, C4_S3 = 3 };
 struct C4FrontPack {
-  std::vector<float> w1b, w1f;        // layer 1 (bf16 / fp32 fragment order)
+  std::vector<float> w1b;             // layer 1 (bf16 fragment order)
   std::vector<float> w2b, w2f;        // layer 2 (bf16 / fp32 fragment order, fp32 values)
   std::vector<uint16_t> w1s3, w2s3;   // layers 1 and 2 for FP32 arithmetic from three bf16 terms
   std::vector<uint8_t> w2q;           // layer 2 e4m3
