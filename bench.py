@@ -208,8 +208,8 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
     elif cfg.hw == 64 and all(len(d.widths) == 3 for d in cfg.models):
         kernel_label = "cnn_fused_kernel<bf16, *> (first pass: one launch per width class)"
     elif cfg.hw == 128 and all(tuple(d.widths) == (32, 64, 128, 256) for d in cfg.models):
-        kernel_label = ("c4_front_kernel<bf16> (layers 1-2) + c4_gemm_kernel<bf16, 2> (layer 3) + "
-                        "c4_gemm_kernel<bf16, 3> (layer 4, pool, FC, decision): the first pass of a round")
+        kernel_label = ("c4_front_kernel<bf16> (layers 1-2) + c4_gemm_bf16_kernel<2> (layer 3) + "
+                        "c4_gemm_bf16_kernel<3> (layer 4, pool, FC, decision): the first pass of a round")
     else:
         kernel_label = "gconv_* layer kernels + gcnn_head_kernel (first pass, grouped over predicates)"
     prec = args.precision
