@@ -976,10 +976,17 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
     if (a.c4[i]) total += (int)(((int64_t)a.q.counts[a.pred[i]] * PP + BM - 1) / BM) * (COUT / BN);
   const int u_slot = lane % UPR;
 
+  // past the last tile: no rows (the B loads read the zero page) and the weight image of the
+  // launch's first 4-layer slot (a valid image whatever the other slots hold; nothing uses them)
+  int first_c4 = 0;
+  for (int i = a.n_preds - 1; i >= 0; --i)
+    if (a.c4[i]) first_c4 = i;
   auto decode = [&](int t) {
-    C4Tile r{};                       // past the last tile: slot 0, no rows (the loads read the
-    r.valid = t < total;              // zero page and slot 0's weights; nothing uses them)
+    C4Tile r{};
+    r.slot = first_c4;
+    r.valid = t < total;
     if (!r.valid) return r;
+    r.slot = 0;
     int off = t;
     for (int i = 0; i < a.n_preds; ++i) {
       const int c = a.c4[i] ? (int)(((int64_t)a.q.counts[a.pred[i]] * PP + BM - 1) / BM) * (COUT / BN) : 0;

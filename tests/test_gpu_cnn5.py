@@ -152,3 +152,39 @@ def test_c5_fp64_fallback_path(c5, monkeypatch):
     assert sum(st["escalated"] for st in stats) > 20
     assert np.array_equal(ids, c.expect)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_c5_grouped_with_a_generic_cnn_in_slot_0(prec):
+    """A 4-layer CNN predicate grouped with a 3-layer CNN on the same 128x128 frames (the generic
+    layer-wise path), the 3-layer one first, so slot 0 of the grouped launch is not a 4-layer
+    CNN (the BF16 layer-3/4 kernel keeps loading past each workgroup's last tile, from a 4-layer
+    slot's weights): ids and written-order counts against the oracle."""
+    cfg = hs.workload(5)
+    n = 1024
+    frames = hs.make_frames_parallel(cfg, 0, n)
+    pt = hs.load_predicates(cfg)
+    gen = hs.make_model(hs.ModelDesc(arch="cnn", seed=4242, in_hw=128, widths=(16, 32, 64)))
+    c4m = hs.make_model(cfg.models[0])
+    masks = [pt.class_masks[1], pt.class_masks[0]]
+    D = np.stack([ho.predicate_margin(ho.model_logits(w, frames, cfg.dtype), m) for w, m in zip([gen, c4m], masks)],
+                 axis=1)
+    th = np.zeros((1, 2), dtype=np.float32)
+    for j in range(2):                     # between two distinct margins near the 40th percentile
+        u = np.unique(D[:, j])
+        m = np.searchsorted(u, np.quantile(D[:, j], 0.4))
+        th[0, j] = np.float32((u[m - 1] + u[m]) / 2.0)
+    seg_len = cfg.n // cfg.n_seg
+    theta = ho.tuple_thresholds(th, seg_len, np.arange(n))
+    assert np.abs(D - theta).min() > 1e-9
+    P = ho.decide(D, theta)
+    specs = [hydro.ModelSpec.from_weights(gen, masks[0]), hydro.ModelSpec.from_weights(c4m, masks[1])]
+    log(f"[gpu] c5 + generic CNN in slot 0, {prec}: pass rates {P.mean(axis=0).round(3).tolist()}")
+    s = hydro.Session(specs, hydro.make_policy("fixed", order=[0, 1], precision=prec, wave=512), 128, n)
+    s.push(torch.from_numpy(frames).cuda(), cfg.dtype, th, seg_len)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, ho.result_ids(P))
+    _, ev, ps = ho.short_circuit_eval(P, [0, 1])
+    assert [st["evaluated"] for st in stats] == list(ev)
+    assert [st["passed"] for st in stats] == list(ps)
+    s.close()
