@@ -1117,23 +1117,12 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
 #pragma unroll 1
       for (int kb = 0; kb < NKB; ++kb) {
         // the next k-block of the issue stream goes into this buffer once every wave has read
-        // it; its addresses are formed while the MFMAs run (one MFMA, then one LDS read and two
-        // VALU, ...)
+        // it; its addresses are formed while the MFMAs run (no branch in the loop body, so the
+        // compiler can interleave them)
         const void* src[NI];
         addrs(iimg, ig, ikb, src);
         frags(buf, 1, F1);
         mma(F0);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
-          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);    // VALU
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-        }
         // publish k-block kb + 1 (issued NS - 1 k-blocks ago; the one after it may stay in
         // flight) and free this buffer
         wait_vmcnt<NI>();
@@ -1142,12 +1131,6 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
         buf = buf + 1 == NS ? 0 : buf + 1;
         frags(buf, 0, F0);            // the next k-block's first step (unused after the last)
         mma(F1);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
         advance();
       }
       c4_gemm_epilogue<P, LAYER, !HEAD>(a, f, acc, cur.slot, cur.k, cur.cb, cur.ebase, cur.row0, cur.rows, ep_bias,
