@@ -633,45 +633,58 @@ __global__ __launch_bounds__(512) void mlp_gemm_dma_kernel(MlpArgs a) {
     for (int i = 0; i < MT; ++i)
 #pragma unroll
       for (int j = 0; j < NT; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-    auto compute = [&](int buf) {
+    // k-step ks (chunk 4 ks + g of each row) of buffer buf, read into registers
+    struct Frag { bf16x8 a[MT], b[NT]; };
+    auto frags = [&](int buf, int ks, Frag& fr) {
       const unsigned char* F = lds + buf * STAGE;
       const unsigned char* W = F + MD_BM * ROWB;
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {      // k-step ks reads chunk 4 ks + g of each row
-        bf16x8 af[MT], bfr[NT];
-#pragma unroll
-        for (int i = 0; i < MT; ++i) {
-          const int r = wm * WM + i * 16 + l16;
-          af[i] = *reinterpret_cast<const bf16x8*>(F + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
-        }
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const int r = wn * WN + j * 16 + l16;
-          bfr[j] = *reinterpret_cast<const bf16x8*>(W + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
-        }
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-#pragma unroll
-          for (int j = 0; j < NT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < MT; ++i) {
+        const int r = wm * WM + i * 16 + l16;
+        fr.a[i] = *reinterpret_cast<const bf16x8*>(F + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
       }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int r = wn * WN + j * 16 + l16;
+        fr.b[j] = *reinterpret_cast<const bf16x8*>(W + (r * UPR + ((4 * ks + g) ^ (r & 7))) * 16);
+      }
+    };
+    auto mma = [&](const Frag& fr) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.a[i], fr.b[j], acc[i][j], 0, 0, 0);
     };
 
     const int nk_all = D / BKE;
     const int kt0 = (int)((int64_t)nk_all * sp / S), kt1 = (int)((int64_t)nk_all * (sp + 1) / S);
     const int nkb = kt1 - kt0;
-    // (the previous tile's last barrier ordered every read of the ring)
+    // Ring of MD_NS k-blocks (k-block kb in buffer kb % MD_NS).  Fragments are read one MFMA step
+    // ahead, and the barrier that publishes k-block kb + 1 and frees buffer kb sits between a
+    // k-block's two steps: every wave reaches it with MFMAs in its pipe.  (The previous tile's last
+    // barrier ordered every read of the ring.)
 #pragma unroll
-    for (int s0 = 0; s0 < MD_NS - 1; ++s0)
+    for (int s0 = 0; s0 < MD_NS; ++s0)
       if (s0 < nkb) issue(kt0 + s0, s0);
+    if (nkb >= 3) wait_vmcnt<2 * NI>();
+    else if (nkb == 2) wait_vmcnt<NI>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    Frag F0, F1;
+    frags(0, 0, F0);
+    int buf = 0;
 #pragma unroll 1
     for (int kb = 0; kb < nkb; ++kb) {
-      const int ahead = min(MD_NS - 2, nkb - 1 - kb);
-      if (ahead >= 1) wait_vmcnt<NI>();
+      frags(buf, 1, F1);
+      mma(F0);
+      if (kb + 2 < nkb) wait_vmcnt<NI>();   // k-block kb + 1 landed; kb + 2 may stay in flight
       else wait_vmcnt<0>();
       __syncthreads();
-      if (kb + MD_NS - 1 < nkb) issue(kt0 + kb + MD_NS - 1, (kb + MD_NS - 1) % MD_NS);
-      compute(kb % MD_NS);
+      if (kb + MD_NS < nkb) issue(kt0 + kb + MD_NS, buf);
+      buf = buf + 1 == MD_NS ? 0 : buf + 1;
+      frags(buf, 0, F0);                     // the next k-block's first step (unused after the last)
+      mma(F1);
     }
 
     if (S > 1) {
