@@ -5,6 +5,7 @@ import itertools
 import numpy as np
 import pytest
 
+import hydro_synth as hs
 from tests.gpu_util import case, check_stats, log
 
 pytestmark = pytest.mark.gpu
@@ -228,4 +229,36 @@ def test_mlp_split_k_forced(c1, monkeypatch, prec):
     ids, stats = s.finish()
     assert np.array_equal(ids, c1.expect)
     check_stats(stats, c1.n, ids.size)
+    s.close()
+
+
+@pytest.mark.parametrize("hidden", [128, 384])
+def test_bf16_mlp_three_k_blocks(hidden):
+    """Two bf16 MLPs on 8x8x3 bf16 frames (192 inputs: the direct-to-LDS GEMM's smallest k
+    extent, three 64-element k-blocks, the whole ring filled by its prologue), grouped in one
+    launch: ids and written-order counts against the oracle, bands measured by the session."""
+    rng = np.random.default_rng(hidden)
+    n = 3000
+    frames = hs.f64_to_bf16_bits(rng.random((n, 8, 8, 3)))
+    models = [hs.make_model(hs.ModelDesc(arch="mlp", seed=900 + hidden, d_in=192, hidden=hidden)),
+              hs.make_model(hs.ModelDesc(arch="mlp", seed=901, d_in=192, hidden=128))]
+    masks = [0b0000011111, 0b1111100000]
+    D = np.stack([ho.predicate_margin(ho.model_logits(m, frames, "bf16"), k) for m, k in zip(models, masks)], axis=1)
+    th = np.zeros((1, 2), dtype=np.float32)
+    for j in range(2):                     # between two distinct margins near the median
+        u = np.unique(D[:, j])
+        m = np.searchsorted(u, np.median(D[:, j]))
+        th[0, j] = np.float32((u[m - 1] + u[m]) / 2.0)
+    theta = ho.tuple_thresholds(th, n, np.arange(n))
+    assert np.abs(D - theta).min() > 1e-9
+    P = ho.decide(D, theta)
+    specs = [hydro.ModelSpec.from_weights(m, k) for m, k in zip(models, masks)]
+    log(f"[gpu] bf16 MLP 192-{hidden}-10 and 192-128-10 on 8x8 frames: pass rates {P.mean(axis=0).round(3).tolist()}")
+    s = hydro.Session(specs, hydro.make_policy("fixed", order=[0, 1], precision="bf16", wave=1024), 8, n)
+    s.push(torch.from_numpy(frames).cuda(), "bf16", th, n)
+    ids, stats = s.finish()
+    assert np.array_equal(ids, ho.result_ids(P))
+    _, ev, ps = ho.short_circuit_eval(P, [0, 1])
+    assert [st["evaluated"] for st in stats] == list(ev)
+    assert [st["passed"] for st in stats] == list(ps)
     s.close()
