@@ -939,6 +939,73 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
 //    its next fragment reads before the MFMAs that follow.
 // The arithmetic (operands, products and the order in which they are added) is the generic
 // kernel's.
+// Epilogue of a four-frame layer-4 tile: wave (wm, wn) holds frames 2 wm and 2 wm + 1 of the tile
+// (rows 64 h .. 64 h + 63 of its 128, h = 0, 1) x channels 64 wn .. 64 wn + 63.  Bias + ReLU, mean
+// over each frame's 64 positions, this wave's share of the FC; then per frame the sum over the
+// four channel quarters, margin and decision (or the logits).  Same arithmetic, in the same
+// order, as the two-frame epilogue of c4_gemm_epilogue.
+__device__ inline void c4_head4_epilogue(const GcnnArgs& a, const Forward& f, const floatx4 (&acc)[4][8], int slot,
+                                         int k, int64_t row0, int64_t rows, const float* ep_bias, const float* fcw_s,
+                                         float (*zp)[2][kClasses]) {
+  constexpr int PP = 64, WN = 64, NT = 4, WGM = 2, NWN = 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int cls = l16 < kClasses ? l16 : 0;
+  float zc[2] = {0.f, 0.f};                         // lane l16 < 10: class l16 of frame h
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int chb = wn * WN + nt * 16 + 4 * g;
+    const floatx4 bb = *reinterpret_cast<const floatx4*>(ep_bias + chb);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float s4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int mt = 4 * h; mt < 4 * h + 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s4[r] += fmaxf(acc[nt][mt][r] + bb[r], 0.f);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float gch = row_sum16(s4[r]) * (1.f / PP);
+        zc[h] += gch * fcw_s[(chb + r) * kClasses + cls];
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float z = l16 < kClasses ? zc[h] : 0.f;
+    // rows g = 0..3 hold different channel groups: add them
+    z = (__shfl(z, l16) + __shfl(z, 16 + l16)) + (__shfl(z, 32 + l16) + __shfl(z, 48 + l16));
+    if (lane < kClasses) zp[wave][h][lane] = z;
+  }
+  __syncthreads();
+  if (wn == 0) {
+    // lane h < 2: frame 2 wm + h of the tile
+    const int h = lane & 1;
+    const int64_t frow = row0 + (int64_t)(2 * wm + h) * PP;
+    bool pass = false, defer = false, active = false;
+    uint32_t e = 0;
+    if (lane < 2 && frow < rows) {
+      e = a.q.entries[(int64_t)k * a.q.cap + frow / PP];
+      active = true;
+      float z[kClasses];
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) {
+        float sum = 0.f;
+        for (int w2 = 0; w2 < NWN; ++w2) sum += zp[wm + WGM * w2][h][c];
+        z[c] = sum + a.fc_b[slot][c];
+      }
+      const uint32_t idx = entry_idx(e);
+      if (f.logits != nullptr)
+        for (int c = 0; c < kClasses; ++c) f.logits[(int64_t)idx * kClasses + c] = (double)z[c];
+      const float d = class_margin(z, a.class_mask[slot]);
+      const float th = theta_of(f, k, idx);
+      pass = d > th;
+      defer = f.defer.entries != nullptr && fabsf(d - th) < f.tau[k];
+    }
+    if (f.logits == nullptr) forward_decision(f, k, e, active, defer, pass);
+  }
+}
+
 struct C4Tile {
   int slot, k, cb, ebase;
   int64_t row0, rows;
@@ -953,15 +1020,20 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
   typedef GemmShape<P, LAYER> S;
   constexpr int UPR = G::UPR, CE = G::CE, BKE = G::ROWB / 2;
   constexpr int CIN = S::CIN, COUT = S::COUT, HIN = S::HIN, HOUT = S::HOUT, PP = HOUT * HOUT;
-  constexpr int BM = S::BM, BN = S::BN, WM = 64, WN = 64, MT = WM / 16, NT = WN / 16, WGM = BM / WM;
+  // layer 3: one frame per tile (a wave: 64 positions x 64 channels), three 48 KB stages; layer 4:
+  // four frames per tile (a wave: two frames x 64 channels), two 64 KB stages, so the weight image
+  // is read once per four frames
+  constexpr bool HEAD = LAYER == 3;
+  constexpr int BM = HEAD ? 4 * PP : S::BM, BN = S::BN, WM = HEAD ? 2 * PP : 64, WN = 64;
+  constexpr int MT = WM / 16, NT = WN / 16, WGM = BM / WM;
   constexpr int NKB = 9 * CIN / BKE;
   constexpr int AUNITS = BN * UPR, UNITS = AUNITS + BM * UPR, NI = UNITS / 512, NIA = AUNITS / 512, NB = NI - NIA;
-  constexpr int STAGE = UNITS * 16, NS = 3;
-  constexpr bool HEAD = LAYER == 3;
+  constexpr int STAGE = UNITS * 16, NS = HEAD ? 2 : 3;
   static_assert(9 * CIN % BKE == 0 && NKB >= NS, "whole k-blocks, at least one per stage");
   static_assert(UNITS % 512 == 0 && AUNITS % 512 == 0 && WGM * (BN / WN) == 8, "tile layout");
+  static_assert(!HEAD || (BN == COUT && MT == 8 && NT == 4), "layer 4: whole frames, all channels");
   __shared__ __attribute__((aligned(1024))) unsigned char lds[NS * STAGE];
-  __shared__ float zpart[8][kClasses];
+  __shared__ float zpart[8][2][kClasses];
   __shared__ __attribute__((aligned(16))) float ep_bias[BN];
   __shared__ float fcw_s[HEAD ? COUT * kClasses : 1];
   __shared__ unsigned long long ticks_s[kMaxK];
@@ -1123,9 +1195,9 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
         addrs(iimg, ig, ikb, src);
         frags(buf, 1, F1);
         mma(F0);
-        // publish k-block kb + 1 (issued NS - 1 k-blocks ago; the one after it may stay in
+        // publish k-block kb + 1 (issued NS - 1 k-blocks ago; the NS - 2 after it may stay in
         // flight) and free this buffer
-        wait_vmcnt<NI>();
+        wait_vmcnt<(NS - 2) * NI>();
         __syncthreads();
         dma(src, buf);
         buf = buf + 1 == NS ? 0 : buf + 1;
@@ -1133,8 +1205,11 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
         mma(F1);
         advance();
       }
-      c4_gemm_epilogue<P, LAYER, !HEAD>(a, f, acc, cur.slot, cur.k, cur.cb, cur.ebase, cur.row0, cur.rows, ep_bias,
-                                        nullptr, fcw_s, zpart);
+      if constexpr (HEAD)
+        c4_head4_epilogue(a, f, acc, cur.slot, cur.k, cur.row0, cur.rows, ep_bias, fcw_s, zpart);
+      else
+        c4_gemm_epilogue<P, LAYER, true>(a, f, acc, cur.slot, cur.k, cur.cb, cur.ebase, cur.row0, cur.rows, ep_bias,
+                                         nullptr, fcw_s, zpart[0]);
       if (tid == 0) ticks_s[cur.k] += wall_clock64() - t0;
       __syncthreads();                // epilogue constants and zpart are rewritten next
       t += gridDim.x;
