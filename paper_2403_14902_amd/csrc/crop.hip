@@ -98,11 +98,11 @@ __global__ __launch_bounds__(kCropThreads) void k_crop_cnn(CropArgs a, Forward f
           for (int v = 0; v < 3; ++v) {
             const int y = 2 * i + u - 1, x = 2 * j + v - 1;
             if (y < 0 || x < 0 || y >= hin || x >= win) continue;
-            const float* wr = W + ((int64_t)oc * 9 + u * 3 + v) * cin;
+            const float* wr = W + (int64_t)(u * 3 + v) * cin * co + oc;
             for (int ch = 0; ch < cin; ++ch) {
               const double xv = l == 0 ? crop_in(a, idx, y0, x0, hin, win, y, x, ch)
                                        : in[((int64_t)y * win + x) * cin + ch];
-              s = fma((double)wr[ch], xv, s);
+              s = fma((double)wr[(int64_t)ch * co], xv, s);
             }
           }
         s += (double)B[oc];

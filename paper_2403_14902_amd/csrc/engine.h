@@ -125,7 +125,7 @@ struct CropArgs {
   uint32_t class_mask[kMaxK];
   int n_layers[kMaxK];
   int widths[kMaxK][HYDRO_MAX_LAYERS];
-  const float* wt[kMaxK][HYDRO_MAX_LAYERS];   // [co][3][3][ci] (channels last per tap), fp32
+  const float* wt[kMaxK][HYDRO_MAX_LAYERS];   // [3][3][ci][co] (output channels last), fp32
   const float* bias[kMaxK][HYDRO_MAX_LAYERS];
   const float* fc_w[kMaxK];                    // [c_last][10]
   const float* fc_b[kMaxK];

@@ -958,10 +958,12 @@ static int pack_models(hydro_session* s) {
       for (int l = 0; l < m.n_layers; ++l) {
         const int co = m.widths[l];
         cr.widths[i][l] = co;
+        // [tap][ci][co]: the lanes of a wave, which hold consecutive output channels, read
+        // consecutive weights
         std::vector<float> wt(hm.cw[l].size());
         for (int o = 0; o < co; ++o)
           for (int c = 0; c < cin; ++c)
-            for (int t = 0; t < 9; ++t) wt[((size_t)o * 9 + t) * cin + c] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
+            for (int t = 0; t < 9; ++t) wt[((size_t)t * cin + c) * co + o] = hm.cw[l][((size_t)o * cin + c) * 9 + t];
         float* dp;
         if ((rc = upload(s, wt.data(), wt.size(), &dp))) return rc;
         cr.wt[i][l] = dp;
