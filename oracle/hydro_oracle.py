@@ -32,11 +32,11 @@ function follows:
   estimated cost of a predicate for a routing batch is (1 - cache hit rate)
   times the cost of computing it (cache access taken as free).  A cached
   decision taken at one threshold answers another threshold only where the
-  comparison is implied (this build's reading: its cache holds decisions, not
+  comparison is implied (the reading taken here: its cache holds decisions, not
   raw UDF outputs).
 * ``color_fraction``: a cheap CPU predicate beside the GPU UDFs (section 4.1:
   the colour classifier runs on the CPU concurrently with the breed model on
-  the GPU); this build's reading is a channel box, the fraction of pixels whose
+  the GPU); the reading taken here is a channel box, the fraction of pixels whose
   three values all lie inside it, compared with theta like the UDF margins.
 * ``crop_logits``: a CNN on each tuple's crop of its frame, the variable-size
   inputs of section 5.3 (UDF composition, a classifier on Crop(frame, bbox)).
@@ -348,7 +348,7 @@ def smoothed_selectivity(passed, evaluated) -> np.ndarray:
     """(passed + 1) / (evaluated + 2): the pass fraction with a uniform prior.
 
     The paper estimates selectivity from counts of filtered rows; the +1/+2
-    prior is this build's reading for predicates that have seen few tuples.
+    prior is the reading taken here for predicates that have seen few tuples.
     """
     return (np.asarray(passed, dtype=np.float64) + 1.0) / (np.asarray(evaluated, dtype=np.float64) + 2.0)
 

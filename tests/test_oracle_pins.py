@@ -483,7 +483,7 @@ def test_color_fraction_hand_pin():
 def test_concurrent_makespan_paper_example():
     """Section 4.1's example: colour classifier (CPU, cost 1, selectivity 0.6) and breed classifier
     (GPU, cost 2, selectivity 0.1) running concurrently on 10 tuples: breed first takes 20 time
-    units, colour first 14.  The pass patterns are this build's reading of the figure (the one
+    units, colour first 14.  The pass patterns are the reading taken here of the figure (the one
     breed pass is not the last tuple; the six colour passes are tuples 2, 3, 5, 6, 8, 10)."""
     P = np.zeros((10, 2), dtype=bool)           # column 0: colour, column 1: breed
     P[[1, 2, 4, 5, 7, 9], 0] = True
