@@ -1492,7 +1492,10 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
         act = std::max<int64_t>(act, (int64_t)h * w * m.widths[l]);
       }
     }
-    s->crop_grid = s->n_cu * 2;
+    // four workgroups per CU (a quarter of what the kernel's registers allow): more hides the
+    // latency of the serial FP64 chains when a round holds many crops, fewer shortens the tail
+    // of the largest crop, which alone bounds a round that holds few
+    s->crop_grid = s->n_cu * 4;
     CropArgs& ca = s->crop;
     ca.act_doubles = (act + 31) / 32 * 32;
     ca.fh = frame_h;
