@@ -297,6 +297,10 @@ __device__ inline int choose_pred(const RouteArgs& a, uint32_t e, const int* ord
 // predicate per round, with a second pass to write, measured slower: its longer dependent chains
 // cost more than the atomics it saved.)
 constexpr int kRouteThreads = 256, kRouteItems = 8, kRouteChunk = kRouteThreads * kRouteItems;
+// Workgroups per CU: the register count allows 4 waves per SIMD, i.e. 4 workgroups; fewer leave
+// each chunk's reservation round trip exposed (2 per CU: 17 % slower at 2^22-tuple waves), and
+// halving the chunk (4 entries per thread, 8 workgroups per CU) nearly doubled the time.
+constexpr int kRouteBlocksPerCu = 4;
 
 __global__ __launch_bounds__(kRouteThreads) void k_route(RouteArgs a) {
   __shared__ int order[kMaxK];
@@ -2194,9 +2198,9 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
           router_nn_keys(s->rnn, s->st, s->pend[in_slot], in_slot, ra.adm_lo, ra.adm_hi, s->n_cu, st);
         }
       }
-      // enough workgroups for the round's live tuples (at most act_cap), up to 2 per CU
+      // enough workgroups for the round's live tuples (at most act_cap), up to kRouteBlocksPerCu per CU
       const int64_t live_bound = std::min<int64_t>(s->act_cap, n);
-      const int route_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * 2,
+      const int route_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->n_cu * kRouteBlocksPerCu,
                                                                           (live_bound + kRouteChunk - 1) / kRouteChunk));
       hipLaunchKernelGGL(k_route, dim3(route_grid), dim3(kRouteThreads), 0, st, ra);
       if (host_mode && !host_rc) host_rc = host_round_copy(s, st);
@@ -2805,7 +2809,7 @@ int hydro_compaction_debug(int32_t k, int64_t n, const uint32_t* pass_bits, int3
       ra.routing_batch = 64;
       ra.k = k;
       ra.q = Queues{q, st->qcount, block};
-      hipLaunchKernelGGL(k_route, dim3(n_cu * 2), dim3(kRouteThreads), 0, s, ra);
+      hipLaunchKernelGGL(k_route, dim3(n_cu * kRouteBlocksPerCu), dim3(kRouteThreads), 0, s, ra);
       if ((rc = mark(&b))) return rc;
       spans.push_back({{a, b}, 0});
       Forward f{};
