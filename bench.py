@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--route", default="learned")
     ap.add_argument("--precision", default="bf16", help="first pass of the full form: bf16 or fp8")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 first-pass form")
+    ap.add_argument("--no-rescore3", action="store_true",
+                    help="no three-product re-score tier in the bf16 forms of the 4-layer CNN workload")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
@@ -139,6 +141,7 @@ def run_form(hydro, torch, specs, frames_dev, dtype, pt, seg_len, policy, steps,
     blk = push_batch if push_batch > 0 else n
     sess = hydro.Session(specs, policy, frames_dev.shape[1], blk)
     bands = sess.calibrate(cal, dtype, safety) if cal is not None else None
+    run_form.tau16 = sess.bands()[1] if cal is not None else None
     res = None
 
     def one_query():
@@ -213,12 +216,16 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
     else:
         kernel_label = "gconv_* layer kernels + gcnn_head_kernel (first pass, grouped over predicates)"
     prec = args.precision
+    c4 = cfg.hw == 128 and all(d.arch == "cnn" and tuple(d.widths) == (32, 64, 128, 256) for d in cfg.models)
+    # the three-product re-score tier between the bf16 first pass and fp32 (4-layer CNN predicates)
+    mid = {"rescore3": 1} if prec == "bf16" and c4 and not args.no_rescore3 else {}
     full_pol = hydro.make_policy(args.route, precision=prec, wave=args.wave, grouped=1, autotune=1, time_kernels=1,
-                                 **extra)
+                                 **extra, **mid)
     log(f"[bench] eager full form ({args.route} routing)")
     ids, stats_all, infos, dt = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, full_pol,
                                          abl_steps, 1, n, cal, args.safety)
     bands = run_form.bands
+    tau16_full = run_form.tau16
     eager_value = n * abl_steps / dt
 
     # dominant kernels: the first-pass launches of every round
@@ -228,14 +235,17 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
     launches = sum(i["timed_rounds"] for i in infos)
     achieved = first_flops / (first_ms * 1e-3) / 1e12 if first_ms > 0 else 0.0
     resc = np.array([[s["rescored"] for s in st] for st in stats_all], dtype=np.float64)
-    f32_flops = float((resc * flops).sum())
+    resc16 = np.array([[s["rescored16"] for s in st] for st in stats_all], dtype=np.float64)
+    f32_in = resc16 if mid else resc                   # the frames the fp32 tier re-scored
+    f32_flops = float((f32_in * flops).sum())
     f32_ms = sum(i["f32_pass_ms"] for i in infos)
+    mid_ms = sum(i["mid_pass_ms"] for i in infos)
     last = stats_all[-1]
 
     # headline: the full form as deployed, each push replayed from its captured HIP graph
     log(f"[bench] full form, graph replay: {warmup} warmup + {steps} timed steps")
     gpol = hydro.make_policy(args.route, precision=prec, wave=args.wave, grouped=1, autotune=1, use_graph=1,
-                             **extra)
+                             **extra, **mid)
     ids_g, _, _, dtg = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, gpol, steps, warmup, n,
                                 cal, args.safety)
     assert np.array_equal(ids_g, ids), "graph replay and eager runs disagree"
@@ -256,7 +266,8 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         "config": {"workload": f"{cfg.name}: {n} frames {cfg.hw}x{cfg.hw}x3 {cfg.dtype}, "
                                f"{cfg.k} predicates, {cfg.n_seg} threshold segments"
                                + (f" (first {n} of {cfg.n} tuples)" if n < cfg.n else ""),
-                   "form": f"full: {prec} first pass + " + ("bf16/" if prec == "fp8" else "") + "fp32/fp64 re-score, "
+                   "form": f"full: {prec} first pass + " + ("bf16/" if prec == "fp8" else "")
+                           + ("three-product bf16/" if mid else "") + "fp32/fp64 re-score, "
                            + args.route + " routing, grouped, each push replayed from a captured HIP graph",
                    "frames_in": "HBM (generated on the device before timing)",
                    "wave": args.wave, "tuples_per_step": n, "ablation_steps": abl_steps},
@@ -276,19 +287,24 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         "phases_ms_per_step": {
             "route": sum(i["route_ms"] for i in infos) / abl_steps,
             "first_pass": first_ms / abl_steps,
+            **({"three_product_rescore": mid_ms / abl_steps} if mid else {}),
             "fp32_rescore": f32_ms / abl_steps,
             "fp64_escalate": sum(i["f64_pass_ms"] for i in infos) / abl_steps,
         },
         "fp32_rescore_tflops": f32_flops / (f32_ms * 1e-3) / 1e12 if f32_ms > 0 else 0.0,
+        **({"three_product_rescore_tflops": float((resc * flops).sum()) / (mid_ms * 1e-3) / 1e12 if mid_ms > 0
+            else 0.0} if mid else {}),
         "per_predicate": [{"evaluated": s["evaluated"], "passed": s["passed"], "rescored": s["rescored"],
                            "rescored16": s["rescored16"], "escalated": s["escalated"],
                            "selectivity": round(s["selectivity"], 4)} for s in last],
         "band_fraction": {"first_pass": float(resc.sum() / max(1.0, ev.sum())),
+                          **({"three_product": float(resc16.sum() / max(1.0, resc.sum()))} if mid else {}),
                           "fp32": float(sum(x["escalated"] for st in stats_all for x in st)
-                                        / max(1.0, float(resc.sum())))},
+                                        / max(1.0, float(f32_in.sum())))},
         "n_result": int(ids.size),
         "bands": ({"calibrated_on": f"{cal.shape[0]} separate frames", "safety": args.safety,
                    "tau": [round(float(x), 6) for x in bands[0]],
+                   **({"tau16": [float(x) for x in tau16_full]} if mid else {}),
                    "tau32": [float(x) for x in bands[1]]} if bands is not None else
                   {"tau": float(full_pol.tau), "tau32": float(full_pol.tau32)}),
         "rounds": infos[-1]["rounds"],
@@ -306,7 +322,7 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
     if args.route != "score":
         log("[bench] score form")
         spol = hydro.make_policy("score", precision="bf16", wave=args.wave, grouped=1, autotune=1, time_kernels=1,
-                                 **extra)
+                                 **extra, **mid)
         ids_s, st_s, inf_s, dts = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, spol,
                                            abl_steps, 1, n, cal, args.safety)
         assert np.array_equal(ids_s, ids), "score and learned routing disagree"
@@ -314,6 +330,20 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         out["score"] = {"value": n * abl_steps / dts, "unit": "tuples/s",
                         "udf_gflop_per_step": float((ev_s * flops).sum()) / abl_steps / 1e9,
                         "first_pass_ms_per_step": sum(i["first_pass_ms"] for i in inf_s) / abl_steps}
+
+    if mid:
+        # the same eager full form without the three-product tier (bf16 -> fp32 -> fp64)
+        log("[bench] full form without the three-product tier")
+        npol = hydro.make_policy(args.route, precision=prec, wave=args.wave, grouped=1, autotune=1, time_kernels=1,
+                                 **extra)
+        ids_n, st_n, inf_n, dtn = run_form(hydro, torch, specs, frames_dev, cfg.dtype, pt, seg_len, npol,
+                                           abl_steps, 1, n, cal, args.safety)
+        assert np.array_equal(ids_n, ids), "the forms with and without the three-product tier disagree"
+        out["without_three_product_tier"] = {
+            "value": n * abl_steps / dtn, "unit": "tuples/s", "form": "eager",
+            "phases_ms_per_step": {"first_pass": sum(i["first_pass_ms"] for i in inf_n) / abl_steps,
+                                   "fp32_rescore": sum(i["f32_pass_ms"] for i in inf_n) / abl_steps,
+                                   "fp64_escalate": sum(i["f64_pass_ms"] for i in inf_n) / abl_steps}}
 
     if primary and not args.no_fp8 and prec != "fp8" and all(
             d.arch == "cnn" and d.in_hw == 128 and tuple(d.widths) == (32, 64, 128, 256) for d in cfg.models):
@@ -346,7 +376,7 @@ def measure(args, wl, n_req, steps, warmup, abl_steps, hydro, torch, hs, primary
         log(f"[bench] full form pushed from pinned host memory: {nh} tuples in blocks of {blk}")
         frames_host = torch.empty(tuple(frames_dev[:nh].shape), dtype=frames_dev.dtype, pin_memory=True)
         frames_host.copy_(frames_dev[:nh])
-        hpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, **extra)
+        hpol = hydro.make_policy(args.route, precision="bf16", wave=args.wave, grouped=1, autotune=1, **extra, **mid)
         ids_h, _, _, dth = run_form(hydro, torch, specs, frames_host, cfg.dtype, pt, seg_len, hpol,
                                     abl_steps, 1, nh, cal, args.safety, push_batch=blk)
         assert np.array_equal(ids_h, ids[ids < nh]), "host-pushed and device-resident runs disagree"

@@ -139,7 +139,9 @@ typedef enum {
  * within tau of the threshold are re-scored in FP32.  FP8: OCP e4m3 operands with per-output-channel
  * weight scales and per-layer activation scales, fp32 accumulation (4-layer 128x128 CNN predicates
  * conv 32-64-128-256 only; layer 1 runs bf16, exact for raw frame values); margins within tau are
- * re-scored in BF16, BF16 margins within tau16 in FP32.  Every chain ends with FP32 margins within
+ * re-scored in BF16, BF16 margins within tau16 in FP32 (BF16 with policy.rescore3 likewise: first-pass
+ * margins within tau to a three-product tier, its margins within tau16 to FP32).  Every chain ends
+ * with FP32 margins within
  * tau32 re-scored in FP64, which decides.  The answer never depends on the precision. */
 typedef enum { HYDRO_PREC_FP32 = 0, HYDRO_PREC_BF16 = 1, HYDRO_PREC_FP8 = 2 } hydro_precision;
 typedef enum { HYDRO_COST_MEASURED = 0, HYDRO_COST_STATIC = 1 } hydro_cost_source;
@@ -179,7 +181,8 @@ typedef struct {
   uint64_t seed;                         /* LEARNED: router init / exploration seed              */
   void* stream;                          /* hipStream_t to run on; NULL: the session's own       */
   float tau16;                           /* FP8 first pass: |d - theta| < tau16 of the BF16
-                                            re-score goes on to FP32.  <= 0 (default): automatic */
+                                            re-score goes on to FP32 (rescore3: of the three-
+                                            product re-score).  <= 0 (default): automatic        */
   int32_t reuse;                         /* UDF result reuse (section 4.3, "Reuse-aware Routing"):
                                             0 (default): none.  1: the session keeps a device
                                             cache per predicate of every decision it takes (tuple
@@ -201,7 +204,13 @@ typedef struct {
                                             1 = data-aware: ordered by estimated work (the crop's
                                             area, the input-size heuristic), largest first, each
                                             workgroup taking the next from a shared counter      */
-  int32_t pad2_;
+  int32_t rescore3;                      /* BF16 first pass, every predicate a 4-layer 128x128
+                                            CNN (32-64-128-256): 1 = first-pass margins within tau
+                                            go to a re-score tier of three bf16 products per
+                                            product (hi x hi + hi x mid + mid x hi of the operands
+                                            split into bf16 terms, fp32 sums: about 2^-16
+                                            relative), its margins within tau16 on to FP32.  tau16
+                                            <= 0: automatic, floor 3e-4.  0 (default): none      */
 } hydro_policy;
 
 /* Per-predicate statistics of one query. */
@@ -213,7 +222,8 @@ typedef struct {
   double device_us;            /* summed device time of this predicate's first-pass tiles       */
   double cost_us_per_tuple;    /* final running cost estimate                                   */
   double selectivity;          /* passed / evaluated: conditional on the tuples it saw          */
-  uint64_t rescored16;         /* FP8 first pass: BF16 decisions deferred to the FP32 pass      */
+  uint64_t rescored16;         /* FP8 first pass: BF16 decisions deferred to the FP32 pass;
+                                  rescore3: three-product decisions deferred to the FP32 pass    */
   uint64_t cache_hits;         /* policy.reuse: decisions taken from the result cache (not
                                   counted in evaluated / passed)                                */
 } hydro_pred_stats;
@@ -341,7 +351,8 @@ int hydro_session_round_log(const hydro_session* s, int32_t first, int32_t n, hy
 
 /* Evaluate predicate `pred`'s model on every given tuple at one arithmetic tier
  * (0 = the first-pass precision of the session, 1 = FP32, 2 = FP64, 3 = the BF16 re-score tier of
- * an FP8 session; sessions of other precisions map 3 to their first pass) and return its logits as
+ * an FP8 session or the three-product tier of a rescore3 session; other sessions map 3 to their
+ * first pass) and return its logits as
  * fp64 [n][10] in host memory.  Used for logit-error reports and kernel parity tests.  Runs between
  * queries only: ESTATE while a query is open (a push since the last reset or finish); it leaves
  * the session reset. */
@@ -363,7 +374,8 @@ int hydro_session_calibrate(hydro_session* s, const hydro_frames* frames, float 
                             float* out_tau32);
 
 /* The per-predicate bands the next push uses (policy values, automatic or calibrated): caller
- * arrays [K], each may be NULL.  tau: first pass; tau16: BF16 re-score of an FP8 first pass;
+ * arrays [K], each may be NULL.  tau: first pass; tau16: BF16 re-score of an FP8 first pass (the
+ * three-product re-score of a rescore3 session);
  * tau32: FP32 pass. */
 int hydro_session_bands(const hydro_session* s, float* tau, float* tau16, float* tau32);
 

@@ -115,7 +115,8 @@ template <int P> constexpr int front_lds_bytes() { return F_FRAME_B<P> + F_RING 
 // Layer-1 column j -> its slot in a ring row.
 __device__ inline int f_slot(int j) { return (j & 1) ? 32 + ((j + 1) >> 1) : (j >> 1); }
 
-template <int P, bool U8>
+// X3 (with P = C4_F32 only): the three-product arithmetic of the C4_X3 tier
+template <int P, bool U8, bool X3 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == C4_F32 ? 1 : 2)))
 void c4_front_kernel(GcnnArgs a) {
   typedef typename C4T<P>::T T;
@@ -308,10 +309,10 @@ void c4_front_kernel(GcnnArgs a) {
         __builtin_memcpy(&xb, xw, sizeof(xb));
         if constexpr (P == C4_F32) {
           // raw frame values are exact in bf16 and the weights are the sum of their three terms:
-          // every product exact, fp32 sums (smallest term first)
+          // every product exact, fp32 sums (smallest term first); X3 drops the lowest term
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) {
-            acc[ct] = c4_mfma(w1t[2][ct], xb, acc[ct]);
+            if constexpr (!X3) acc[ct] = c4_mfma(w1t[2][ct], xb, acc[ct]);
             acc[ct] = c4_mfma(w1t[1][ct], xb, acc[ct]);
             acc[ct] = c4_mfma(w1t[0][ct], xb, acc[ct]);
           }
@@ -433,11 +434,16 @@ void c4_front_kernel(GcnnArgs a) {
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
               floatx4 c = acc[0][ct][mt];
-              c = c4_mfma(wh, xs[mt][2], c);
-              c = c4_mfma(wm, xs[mt][1], c);
-              c = c4_mfma(wh, xs[mt][1], c);
-              c = c4_mfma(wl, xs[mt][0], c);
-              c = c4_mfma(wm, xs[mt][0], c);
+              if constexpr (X3) {       // hi x hi + hi x mid + mid x hi (about 2^-16 relative)
+                c = c4_mfma(wh, xs[mt][1], c);
+                c = c4_mfma(wm, xs[mt][0], c);
+              } else {
+                c = c4_mfma(wh, xs[mt][2], c);
+                c = c4_mfma(wm, xs[mt][1], c);
+                c = c4_mfma(wh, xs[mt][1], c);
+                c = c4_mfma(wl, xs[mt][0], c);
+                c = c4_mfma(wm, xs[mt][0], c);
+              }
               acc[0][ct][mt] = c4_mfma(wh, xs[mt][0], c);
             }
           }
@@ -683,7 +689,8 @@ __device__ inline void c4_gemm_epilogue(const GcnnArgs& a, const Forward& f, con
   }
 }
 
-template <int P, int LAYER>
+// X3 (with P = C4_S3 only): the three-product arithmetic of the C4_X3 tier
+template <int P, int LAYER, bool X3 = false>
 __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
   typedef typename C4T<P>::T T;
   typedef GemmCfg<P> G;
@@ -832,11 +839,16 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
             floatx4 c = acc[nt][mt];
-            c = c4_mfma(aw[0][nt], xl, c);
-            c = c4_mfma(aw[1][nt], xm, c);
-            c = c4_mfma(aw[0][nt], xm, c);
-            c = c4_mfma(aw[2][nt], xh, c);
-            c = c4_mfma(aw[1][nt], xh, c);
+            if constexpr (X3) {         // hi x hi + hi x mid + mid x hi (about 2^-16 relative)
+              c = c4_mfma(aw[0][nt], xm, c);
+              c = c4_mfma(aw[1][nt], xh, c);
+            } else {
+              c = c4_mfma(aw[0][nt], xl, c);
+              c = c4_mfma(aw[1][nt], xm, c);
+              c = c4_mfma(aw[0][nt], xm, c);
+              c = c4_mfma(aw[2][nt], xh, c);
+              c = c4_mfma(aw[1][nt], xh, c);
+            }
             acc[nt][mt] = c4_mfma(aw[0][nt], xh, c);
           }
         }
@@ -1223,14 +1235,14 @@ __global__ __launch_bounds__(512) void c4_gemm_bf16_kernel(GcnnArgs a, Forward f
 }
 
 // ---------------------------------------------------------------- launch
-template <int P>
+template <int P, bool X3 = false>
 static void launch_front(const GcnnArgs& a, int grid, hipStream_t s) {
-  if (a.fr.dtype == HYDRO_DTYPE_U8) hipLaunchKernelGGL((c4_front_kernel<P, true>), dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((c4_front_kernel<P, false>), dim3(grid), dim3(256), 0, s, a);
+  if (a.fr.dtype == HYDRO_DTYPE_U8) hipLaunchKernelGGL((c4_front_kernel<P, true, X3>), dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((c4_front_kernel<P, false, X3>), dim3(grid), dim3(256), 0, s, a);
 }
 
 void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hipStream_t s) {
-  const int g1 = grid * (prec == C4_F32 ? 1 : 2);
+  const int g1 = grid * (prec == C4_F32 || prec == C4_X3 ? 1 : 2);
   if (prec == C4_FP8) {
     launch_front<C4_FP8>(a, g1, s);
     hipLaunchKernelGGL((c4_gemm_kernel<C4_FP8, 2>), dim3(grid), dim3(512), 0, s, a, f);
@@ -1239,6 +1251,11 @@ void launch_c4_pass(const GcnnArgs& a, const Forward& f, int prec, int grid, hip
     launch_front<C4_BF16>(a, g1, s);
     hipLaunchKernelGGL((c4_gemm_bf16_kernel<2>), dim3(grid), dim3(512), 0, s, a, f);
     hipLaunchKernelGGL((c4_gemm_bf16_kernel<3>), dim3(grid), dim3(512), 0, s, a, f);
+  } else if (prec == C4_X3) {
+    // the FP32 tier's kernels and images with the three leading products only
+    launch_front<C4_F32, true>(a, g1, s);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_S3, 2, true>), dim3(grid), dim3(512), 0, s, a, f);
+    hipLaunchKernelGGL((c4_gemm_kernel<C4_S3, 3, true>), dim3(grid), dim3(512), 0, s, a, f);
   } else {
     // FP32 arithmetic: the front in fp32, layers 3 and 4 as three-term bf16 products
     launch_front<C4_F32>(a, g1, s);

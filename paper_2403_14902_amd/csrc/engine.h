@@ -145,7 +145,10 @@ void launch_crop_pass(const CropArgs& a, const Forward& f, int grid, hipStream_t
 // Arithmetic tiers of the dedicated 4-layer CNN kernels.
 // C4_S3: FP32 arithmetic of the layer-3/4 GEMMs from bf16 MFMAs (fp32 activations split into
 // three bf16 terms on the fly, weights packed as three bf16 terms; see cnn4.hip).
-enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2, C4_S3 = 3 };
+// C4_X3: the C4_S3 kernels and images with the three leading products only (hi x hi, hi x mid,
+// mid x hi; layer 1 the two leading weight terms): about 2^-16 relative, the re-score tier between
+// a BF16 first pass and the FP32 tier (policy rescore3).
+enum { C4_F32 = 0, C4_BF16 = 1, C4_FP8 = 2, C4_S3 = 3, C4_X3 = 4 };
 struct C4FrontPack {
   std::vector<float> w1b;             // layer 1 (bf16 fragment order)
   std::vector<float> w2b, w2f;        // layer 2 (bf16 / fp32 fragment order, fp32 values)

@@ -618,6 +618,9 @@ struct GraphKey {
 constexpr int kEvPerRound = 6;               // start, routed, first pass, BF16 mid, FP32, FP64
 constexpr float kAutoTauFloor = 0.015f;     // automatic bands never go below these
 constexpr float kAutoTau32Floor = 1e-5f;
+// the three-product tier drops products below about 3 x 2^-18 of |w x| each: some 30x the FP32
+// tier's error, so its floor is 30x the FP32 floor
+constexpr float kAutoTauX3Floor = 3e-4f;
 
 // Persistent CPU threads for HOST predicates: run(n, fn) calls fn(t) for t = 0..n-1, the caller
 // taking t = 0, and returns when all have finished (no thread is created per round).
@@ -1339,6 +1342,9 @@ static int validate_policy(const hydro_policy* p, int K) {
   if (p->reuse && p->route == HYDRO_ROUTE_LEARNED)
     return fail(HYDRO_EUNSUPPORTED, "result reuse is not combined with the learned router");
   if (p->cache_log2 < 0 || p->cache_log2 > 28) return fail(HYDRO_EINVAL, "cache_log2 must be in 0 .. 28");
+  if (p->rescore3 != 0 && p->rescore3 != 1) return fail(HYDRO_EINVAL, "rescore3 must be 0 or 1");
+  if (p->rescore3 && p->precision != HYDRO_PREC_BF16)
+    return fail(HYDRO_EUNSUPPORTED, "the three-product re-score tier follows a BF16 first pass");
   return HYDRO_OK;
 }
 
@@ -1367,6 +1373,12 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
     for (int i = 0; i < k; ++i)
       if (models[i].arch != HYDRO_ARCH_CNN || !c4_shape_ok(models[i].in_h, models[i].n_layers, models[i].widths))
         return fail(HYDRO_EUNSUPPORTED, "the FP8 first pass is built for 4-layer 128x128 CNN predicates (32-64-128-256)");
+  if (policy->rescore3)
+    for (int i = 0; i < k; ++i)
+      if (models[i].arch != HYDRO_ARCH_CNN || models[i].on_crop ||
+          !c4_shape_ok(models[i].in_h, models[i].n_layers, models[i].widths))
+        return fail(HYDRO_EUNSUPPORTED, "the three-product re-score tier is built for 4-layer 128x128 CNN predicates "
+                                        "(32-64-128-256) on whole frames");
 
   g_alloc_counter = 0;
   hydro_session* s = new hydro_session();
@@ -1375,10 +1387,10 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
   s->pol = *policy;
   s->auto_tau = s->pol.tau <= 0.f;
   s->auto_tau32 = s->pol.tau32 <= 0.f;
-  s->auto_tau16 = s->pol.precision == HYDRO_PREC_FP8 && s->pol.tau16 <= 0.f;
+  s->auto_tau16 = (s->pol.precision == HYDRO_PREC_FP8 || s->pol.rescore3) && s->pol.tau16 <= 0.f;
   if (s->auto_tau) s->pol.tau = kAutoTauFloor;
   if (s->auto_tau32) s->pol.tau32 = kAutoTau32Floor;
-  if (s->pol.tau16 <= 0.f) s->pol.tau16 = kAutoTauFloor;
+  if (s->pol.tau16 <= 0.f) s->pol.tau16 = s->pol.rescore3 ? kAutoTauX3Floor : kAutoTauFloor;
   for (int i = 0; i < kMaxK; ++i) {
     s->tau_k[i] = s->pol.tau;
     s->tau32_k[i] = s->pol.tau32;
@@ -1455,7 +1467,8 @@ static int session_create(const hydro_model* models, int32_t k, const hydro_poli
   if ((rc = sess_alloc(s, (void**)&s->q1, cap * 4 * k))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->q2, cap * 4 * k))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->q3, cap * 4 * k))) return bail(rc);
-  if (s->pol.precision == HYDRO_PREC_FP8 && (rc = sess_alloc(s, (void**)&s->qm, cap * 4 * k))) return bail(rc);
+  if ((s->pol.precision == HYDRO_PREC_FP8 || s->pol.rescore3) && (rc = sess_alloc(s, (void**)&s->qm, cap * 4 * k)))
+    return bail(rc);
   const int64_t nwords = (cap + 31) / 32;
   if ((rc = sess_alloc(s, (void**)&s->result_bits, nwords * 4 + 1024))) return bail(rc);
   if ((rc = sess_alloc(s, (void**)&s->res_blocks, ((nwords + 255) / 256 + 1) * 4))) return bail(rc);
@@ -1604,7 +1617,7 @@ static Forward make_forward(hydro_session* s, int tier, int out_slot, const Fram
   f.cache = s->cache;
   const bool bf = s->pol.precision == HYDRO_PREC_BF16;
   const bool f8 = s->pol.precision == HYDRO_PREC_FP8;
-  if (tier == TIER_FIRST && f8) {
+  if (tier == TIER_FIRST && (f8 || s->pol.rescore3)) {     // on to the middle tier
     f.count_eval = 1;
     f.defer = Queues{s->qm, s->st->mcount, s->cap};
     f.defer_stat = s->st->r_rescored;
@@ -1901,7 +1914,7 @@ static int auto_bands(hydro_session* s, const hydro_frames& fr) {
   const bool low = s->pol.precision != HYDRO_PREC_FP32;
   for (int k = 0; k < s->K; ++k) {
     if (s->auto_tau) s->tau_k[k] = low ? std::max(tau[k], kAutoTauFloor) : std::max(tau32[k], kAutoTau32Floor);
-    if (s->auto_tau16) s->tau16_k[k] = std::max(tau16[k], kAutoTauFloor);
+    if (s->auto_tau16) s->tau16_k[k] = std::max(tau16[k], s->pol.rescore3 ? kAutoTauX3Floor : kAutoTauFloor);
     if (s->auto_tau32) s->tau32_k[k] = std::max(tau32[k], kAutoTau32Floor);
   }
   s->auto_tau = s->auto_tau32 = s->auto_tau16 = false;
@@ -2206,14 +2219,15 @@ int hydro_session_push(hydro_session* s, const hydro_frames* frames, const float
       if (host_mode && !host_rc) host_rc = host_round_copy(s, st);
       if (timed && ev[1]) hipEventRecord(ev[1], st);
 
-      // tier chain: first pass, [BF16 re-score of an FP8 first pass], [FP32 re-score of a
+      // tier chain: first pass, [BF16 re-score of an FP8 first pass, or the three-product
+      // re-score of a BF16 one (rescore3)], [FP32 re-score of a
       // low-precision first pass], FP64; events: after first, mid, FP32, FP64 (skipped tiers
       // record their event right after the previous one)
       const int chain[4] = {TIER_FIRST, TIER_MID, TIER_F32, TIER_F64};
       for (int ci = 0; ci < 4; ++ci) {
         const int tier = chain[ci];
         const bool run = tier == TIER_FIRST || tier == TIER_F64 ||
-                         (tier == TIER_MID && s->pol.precision == HYDRO_PREC_FP8) ||
+                         (tier == TIER_MID && (s->pol.precision == HYDRO_PREC_FP8 || s->pol.rescore3)) ||
                          (tier == TIER_F32 && s->pol.precision != HYDRO_PREC_FP32);
         if (run) {
           Forward f = make_forward(s, tier, out_slot, src, n_seg, seg_len, fr.id_base);
@@ -2408,7 +2422,8 @@ int hydro_session_logits(hydro_session* s, int32_t pred, int32_t tier, const hyd
   if (tier < 0 || tier > 3) return fail(HYDRO_EINVAL, "tier must be 0, 1, 2 or 3");
   if (s->models[pred].m.arch == HYDRO_ARCH_HOST) return fail(HYDRO_EUNSUPPORTED, "a HOST predicate has no logits");
   if (s->models[pred].m.on_crop) return fail(HYDRO_EUNSUPPORTED, "an on_crop predicate takes crops: no whole-frame logits");
-  if (tier == 3 && s->pol.precision != HYDRO_PREC_FP8) tier = s->pol.precision == HYDRO_PREC_BF16 ? 0 : 1;
+  if (tier == 3 && s->pol.precision != HYDRO_PREC_FP8 && !s->pol.rescore3)
+    tier = s->pol.precision == HYDRO_PREC_BF16 ? 0 : 1;
   if (s->in_query)
     return fail(HYDRO_ESTATE, "a query is in progress (pushes since the last reset / finish): logits and "
                               "calibration run between queries");
@@ -2482,7 +2497,7 @@ static int measure_bands(hydro_session* s, const hydro_frames* frames, float saf
   const int64_t blk = std::min<int64_t>(n, s->cap);
   const int esize = frames->dtype == HYDRO_DTYPE_F32 ? 4 : frames->dtype == HYDRO_DTYPE_BF16 ? 2 : 1;
   const int64_t fbytes = (int64_t)frames->h * frames->w * 3 * esize;
-  const bool f8 = s->pol.precision == HYDRO_PREC_FP8;
+  const bool f8 = s->pol.precision == HYDRO_PREC_FP8 || s->pol.rescore3;   // a middle tier
   std::vector<double> z0((size_t)blk * kClasses), zm((size_t)blk * kClasses), z1((size_t)blk * kClasses),
       z2((size_t)blk * kClasses);
   for (int k = 0; k < s->K; ++k) {

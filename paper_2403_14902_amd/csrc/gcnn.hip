@@ -724,7 +724,7 @@ void launch_gcnn_pass(const GcnnArgs& a0, const Forward& f, int tier, int grid, 
       else gcnn_copy_slot(gen, gen.n_preds++, a0, i);
     }
     if (c4a.n_preds > 0) {
-      const int p = tier == TIER_MID ? C4_BF16
+      const int p = tier == TIER_MID ? (a0.prec == HYDRO_PREC_FP8 ? C4_BF16 : C4_X3)
                     : tier != TIER_FIRST ? C4_F32
                     : a0.prec == HYDRO_PREC_FP8 ? C4_FP8 : a0.prec == HYDRO_PREC_BF16 ? C4_BF16 : C4_F32;
       launch_c4_pass(c4a, f, p, grid, s);

@@ -64,7 +64,7 @@ class Policy(C.Structure):
                 ("grouped", C.c_int32), ("use_graph", C.c_int32), ("log_routes", C.c_int32),
                 ("time_kernels", C.c_int32), ("autotune", C.c_int32),
                 ("explore", C.c_float), ("seed", C.c_uint64), ("stream", C.c_void_p), ("tau16", C.c_float),
-                ("reuse", C.c_int32), ("cache_log2", C.c_int32), ("balance", C.c_int32), ("pad2_", C.c_int32)]
+                ("reuse", C.c_int32), ("cache_log2", C.c_int32), ("balance", C.c_int32), ("rescore3", C.c_int32)]
 
 
 class PredStats(C.Structure):
