@@ -702,12 +702,13 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
   constexpr int WGM = BM / WM;                        // waves along M (8 waves in all)
   constexpr int NKB = (9 * CIN + BKE - 1) / BKE;
   constexpr bool S3 = P == C4_S3;
-  constexpr int AUNITS = S3 ? 3 * BN * 4 : BN * UPR;   // A: S3 holds three 64-byte rows per channel
+  constexpr int ATERMS = X3 ? 2 : 3;                  // weight terms staged (X3 reads hi and mid)
+  constexpr int AUNITS = S3 ? ATERMS * BN * 4 : BN * UPR;   // A: S3 holds a 64-byte row per channel and term
   constexpr int UNITS = AUNITS + BM * UPR;            // 16-byte units of one stage
   constexpr int NI = UNITS / 64 / 8;                  // load instructions per wave and stage
   constexpr int NIA = AUNITS / 64 / 8;                // ... of them for A (the rest gather B)
   constexpr int STAGE = UNITS * 16;
-  constexpr int NS = S3 ? 2 : 3;                      // stages in flight
+  constexpr int NS = S3 && !X3 ? 2 : 3;               // stages in flight (what LDS holds)
   constexpr bool HEAD = LAYER == 3;
   static_assert(UNITS % 512 == 0 && AUNITS % 512 == 0, "stage rows must fill the waves' load units");
   static_assert(WGM * (BN / WN) == 8, "eight waves per tile");
@@ -814,7 +815,7 @@ __global__ __launch_bounds__(512) void c4_gemm_kernel(GcnnArgs a, Forward f) {
         // smallest first
         bf16x8 aw[3][NT];
 #pragma unroll
-        for (int term = 0; term < 3; ++term)
+        for (int term = 0; term < ATERMS; ++term)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
             const int r = wn * WN + nt * 16 + l16;
