@@ -56,7 +56,7 @@ METRIC = "tuples/sec through ML-UDF conjunction at 1 GPU, learned+batched vs pla
 # The 4-layer CNN first pass (front + layer-3 + layer-4 launches, bf16): HBM bytes per evaluated
 # frame from the same counters (profiles/cnn4_u8_128_first_pass.md), valid while the kernel
 # sources hash to the recorded value; the figure per launch is this times the launch's frames.
-FIRST_PASS_BYTES_PER_EVAL = {"cnn4_u8_128": ('abc034d3ba5f195a', 10.145e9 / 18265.3)}
+FIRST_PASS_BYTES_PER_EVAL = {"cnn4_u8_128": ('abc034d3ba5f195a', 10.150e9 / 18280.8)}
 FIRST_PASS_SOURCES = ("paper_2403_14902_amd/csrc/cnn4.hip", "paper_2403_14902_amd/csrc/common.h")
 
 
