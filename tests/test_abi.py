@@ -103,3 +103,15 @@ def test_null_arguments_elsewhere():
 def test_valid_create_without_device_reports_device_error():
     rc, msg = _create([_mlp_spec()], hydro.make_policy())
     assert rc == hydro.EDEVICE and msg
+
+
+def test_rescore3_rules():
+    """The three-product re-score tier is opt-in, follows a BF16 first pass only, and only for
+    4-layer 128x128 CNN predicates (checked before any device work)."""
+    assert hydro.make_policy().rescore3 == 0
+    m = _mlp_spec()
+    assert _create([m], hydro.make_policy(rescore3=2))[0] == hydro.EINVAL
+    for prec in ("fp32", "fp8"):
+        assert _create([m], hydro.make_policy(precision=prec, rescore3=1))[0] == hydro.EUNSUPPORTED
+    rc, msg = _create([m], hydro.make_policy(precision="bf16", rescore3=1))
+    assert rc == hydro.EUNSUPPORTED and "three-product" in msg
