@@ -618,8 +618,8 @@ struct GraphKey {
 constexpr int kEvPerRound = 6;               // start, routed, first pass, BF16 mid, FP32, FP64
 constexpr float kAutoTauFloor = 0.015f;     // automatic bands never go below these
 constexpr float kAutoTau32Floor = 1e-5f;
-// the three-product tier drops products below about 3 x 2^-18 of |w x| each: some 30x the FP32
-// tier's error, so its floor is 30x the FP32 floor
+// the three-product tier drops three products of at most about 2^-16 of |w x| each; its logit
+// error is some 16x the FP32 tier's, and its floor 30x the FP32 floor
 constexpr float kAutoTauX3Floor = 3e-4f;
 
 // Persistent CPU threads for HOST predicates: run(n, fn) calls fn(t) for t = 0..n-1, the caller

@@ -30,7 +30,7 @@ def _cal(cfg):
 
 def test_rescore3_tier_logits(c5z):
     """Tier 3 of a rescore3 session is the three-product arithmetic: within 1e-4 of the FP64
-    logits (products below about 3 x 2^-18 of |w x| dropped), not the FP32 tier's values, and
+    logits (three products of at most about 2^-16 of |w x| dropped), not the FP32 tier's values, and
     between the FP32 and BF16 tiers' errors."""
     s = hydro.Session(c5z.specs(), hydro.make_policy("score", precision="bf16", rescore3=1), 128, 256)
     s.calibrate(_cal(c5z.cfg), "u8", safety=2.0)

@@ -31,3 +31,31 @@ def test_three_bf16_terms_carry_an_fp32_weight_exactly():
     for t in (hi, mid, lo):
         p32 = (x * t).astype(np.float32).astype(np.float64)
         assert np.array_equal(p32, x.astype(np.float64) * t.astype(np.float64))
+
+
+def test_three_leading_products_bound():
+    """The three-product tier keeps hi x hi + hi x mid + mid x hi of operands split as above
+    (weights and fp32 activations alike) and drops the rest.  Since |w - hi| <= 2^-8 |w| and
+    |w - hi - mid| <= 2^-16 |w| (bf16 keeps 8 significant bits), each dropped product is at most
+    about 2^-16 |w x|: the kept sum is within 3 x 2^-16 (1 + 2^-7) |w x| of the exact product,
+    and on typical operands far closer."""
+    rng = np.random.default_rng(11)
+    n = 400_000
+    w = (rng.normal(0, 1, n) * 10.0 ** rng.uniform(-3, 1, n)).astype(np.float32)
+    x = np.abs(rng.normal(0, 1, n) * 10.0 ** rng.uniform(-2, 2, n)).astype(np.float32)   # ReLU outputs
+
+    def split(v):
+        hi = _bf16(v)
+        mid = _bf16((v - hi).astype(np.float32))
+        return hi.astype(np.float64), mid.astype(np.float64)
+
+    wh, wm = split(w)
+    xh, xm = split(x)
+    kept = wh * xh + wh * xm + wm * xh
+    exact = w.astype(np.float64) * x.astype(np.float64)
+    rel = np.abs(kept - exact) / np.abs(exact)
+    assert rel.max() <= 3 * 2.0 ** -16 * (1 + 2.0 ** -7)
+    assert np.median(rel) < 2.0 ** -18
+    # and the residues are as stated
+    assert np.all(np.abs(w - wh) <= 2.0 ** -8 * np.abs(w))
+    assert np.all(np.abs(w - wh - wm) <= 2.0 ** -16 * np.abs(w))
