@@ -302,7 +302,7 @@ int hydro_query(const hydro_frames* frames, const hydro_model* models, int32_t k
  *     with *out_n set to the number needed;
  *   - a query whose buffers do not fit the array returns ECAPACITY (the message names the size):
  *     e.g. two MLP 3072-256 predicates fit up to about 100k tuples, three 64x64 CNNs of the
- *     16-32-64 family up to about 1M;
+ *     16-32-64 family up to about 1M; 4-layer 128x128 CNN predicates do not fit;
  *   - the FP64 tier evaluates at most 8 escalated tuples per predicate and round layer-parallel,
  *     the rest one per block on 16 blocks (same decisions, slower when many escalate).
  * Calls on one GPU share its array and keep nothing from the previous call (everything a call

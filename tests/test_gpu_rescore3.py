@@ -104,3 +104,21 @@ def test_rescore3_rules(c5):
     with pytest.raises(hydro.HydroError) as e:
         hydro.Session(c5.specs(), hydro.make_policy("score", precision="bf16", rescore3=2), 128, 16)
     assert e.value.code == hydro.EINVAL
+
+
+
+def test_rescore3_noalloc_capacity(c5):
+    """The 4-layer CNNs' buffers (weight images of every tier, fp32 activations) exceed the
+    allocation-free entry point's fixed array: with the middle tier as without it,
+    hydro_query_noalloc returns ECAPACITY naming the size, and hydro_query answers."""
+    n = 96
+    dev = c5.device_frames()[:n]
+    exp = ho.result_ids(c5.P[:n])
+    for mid in (0, 1):
+        pol = hydro.make_policy("score", precision="bf16", rescore3=mid, wave=64, tau=0.02, tau16=3e-4, tau32=1e-5)
+        ids, stats = hydro.query(dev, "u8", c5.specs(), c5.pt.thresholds, c5.seg_len, pol)
+        assert np.array_equal(ids, exp)
+        check_stats(stats, n, ids.size)
+        with pytest.raises(hydro.HydroError) as e:
+            hydro.query_noalloc(dev, "u8", c5.specs(), c5.pt.thresholds, c5.seg_len, pol, out_cap=n)
+        assert e.value.code == hydro.ECAPACITY and "bytes" in str(e.value)
